@@ -1,0 +1,389 @@
+"""Pins of the FP64 oracle against closed forms, invariants and finite differences.
+
+Each test fixes the oracle to something other than itself: exact solutions of
+hydrogenic problems (Sec. II.B), the Kato cusp behaviour of exponential
+envelopes, the antisymmetry and equivariance requirements (Sec. II.A, II.C),
+invariances of a distance-only embedding, an independent numpy forward, and
+central finite differences of that numpy forward.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import qmc_inputs as qi
+from oracle.layout import unpack
+from oracle.slater import hydrogenic, slater_local_energy
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+SMALL = qi.Ansatz(n_rbf=6, rbf_dmax=6.0, init_layers=1, width=12, mp_layers=2, n_det=3, n_env=2)
+
+
+def _closed_form_count(system, ans):
+    """Parameter count of the pinned blob, written as one closed formula."""
+    M, K, D, L0, L = system.n_nuc, ans.n_rbf, ans.width, ans.init_layers, ans.mp_layers
+    per_layer = 3 * (K * D + D + D * D + D) + D * D + D + M * D + 3 * D * D + D
+    orb = sum(D * ans.n_det * n + ans.n_det * n + 2 * ans.n_det * n * M * ans.n_env
+              for n in (system.n_up, system.n_down) if n > 0)
+    return (M + 2) * K * D + D + (L0 - 1) * (D * D + D) + L * per_layer + orb + ans.n_det
+
+
+def test_param_count_formula():
+    expected = {0: 3235, 1: 532848, 2: 532848, 3: 2286752}
+    for k, n in expected.items():
+        wl = qi.workload(k)
+        s = wl.systems[0]
+        assert oracle.param_count(s, wl.ansatz) == n
+        assert _closed_form_count(s, wl.ansatz) == n
+        assert qi.param_count(s, wl.ansatz) == n
+    for s in qi.workload(4).systems:
+        a = qi.BATCH_ANSATZ
+        assert oracle.param_count(s, a) == _closed_form_count(s, a) == qi.param_count(s, a)
+
+
+def test_batched_molecules_are_neutral_and_spread():
+    mols = qi.workload(4).systems
+    assert [m.n_elec for m in mols] == qi.BATCH_TARGETS
+    for m in mols:
+        assert 2 <= m.n_nuc <= 6
+        assert sum(m.charges) == m.n_elec
+        assert set(m.charges) <= {1.0, 3.0, 6.0, 7.0, 8.0}
+        assert m.n_up == (m.n_elec + 1) // 2
+        R = m.R()
+        for I in range(m.n_nuc):
+            for J in range(I):
+                assert np.linalg.norm(R[I] - R[J]) >= 1.5 - 1e-12
+
+
+def _one_center_params(system, ans, sigma, rng=None):
+    """Embedding weights arbitrary, orbital map zero, bias 1: psi = prod of envelopes."""
+    n = oracle.param_count(system, ans)
+    p = rng.standard_normal(n) * 0.3 if rng is not None else np.zeros(n)
+    P = unpack(p, system, ans)
+    for s, nel in (("up", system.n_up), ("down", system.n_down)):
+        if nel == 0:
+            continue
+        P[f"orb.{s}.W"][:] = 0.0
+        P[f"orb.{s}.b"][:] = 1.0
+        P[f"orb.{s}.pi"][:] = 0.0
+        P[f"orb.{s}.pi"][:, :, 0, 0] = 1.0
+        P[f"orb.{s}.sigma"][:] = 1.0
+        P[f"orb.{s}.sigma"][:, :, 0, 0] = sigma
+    P["c"][:] = 0.0
+    P["c"][0] = 1.0
+    return p
+
+
+def _random_points(n, N, seed, scale=1.5):
+    return np.random.default_rng(seed).standard_normal((n, N, 3)) * scale
+
+
+def test_hydrogen_atom_exact():
+    """psi = exp(-r) is the hydrogen ground state: E_L = -1/2 for every r."""
+    H = qi.System((1.0,), ((0.0, 0.0, 0.0),), 1, 0)
+    p = _one_center_params(H, SMALL, 1.0, np.random.default_rng(1))
+    r = _random_points(12, 1, 2)
+    res = oracle.local_energy(r, p, H, SMALL)
+    np.testing.assert_allclose(res["e_loc"], -0.5, rtol=0, atol=1e-12)
+
+
+@pytest.mark.parametrize("Z,sigma", [(1.0, 0.7), (1.0, 1.6), (2.0, 1.3), (3.0, 3.0)])
+def test_kato_cusp_closed_form(Z, sigma):
+    """exp(-sigma r) around charge Z: E_L = -sigma^2/2 + (sigma - Z)/r exactly; the
+    1/r divergence cancels only at sigma = Z (Kato's electron-nucleus cusp)."""
+    sys1 = qi.System((Z,), ((0.3, -0.2, 0.1),), 1, 0)
+    p = _one_center_params(sys1, SMALL, sigma, np.random.default_rng(3))
+    r = _random_points(10, 1, 4) + np.array([0.3, -0.2, 0.1])
+    rad = np.linalg.norm(r[:, 0] - np.array([0.3, -0.2, 0.1]), axis=-1)
+    res = oracle.local_energy(r, p, sys1, SMALL)
+    exact = -sigma ** 2 / 2 + (sigma - Z) / rad
+    np.testing.assert_allclose(res["e_loc"], exact, rtol=1e-12, atol=1e-12)
+    # separately: grad log psi = -sigma * unit vector, Laplacian = -2 sigma / r
+    np.testing.assert_allclose(res["lap"], -2 * sigma / rad, rtol=1e-12)
+    np.testing.assert_allclose((res["grad"] ** 2).sum((1, 2)), sigma ** 2, rtol=1e-12)
+
+
+@pytest.mark.parametrize("Z", [2.0, 3.0])
+def test_helium_like_product_state(Z):
+    """1s^2 with exponent Z: E_L = -Z^2 + 1/r12 exactly (electron repulsion on)."""
+    He = qi.System((Z,), ((0.0, 0.0, 0.0),), 1, 1)
+    p = _one_center_params(He, SMALL, Z, np.random.default_rng(5))
+    r = _random_points(10, 2, 6)
+    res = oracle.local_energy(r, p, He, SMALL)
+    r12 = np.linalg.norm(r[:, 0] - r[:, 1], axis=-1)
+    np.testing.assert_allclose(res["e_loc"], -Z ** 2 + 1 / r12, rtol=1e-12)
+
+
+def _golden_hydrogenic():
+    rows = []
+    with open(os.path.join(GOLDEN, "hydrogenic_energies.txt")) as fh:
+        for line in fh:
+            if line.strip() and not line.startswith("#"):
+                Z, up, dn, e = line.split()
+                rows.append((float(Z), up.split(","), dn.split(","), float(e)))
+    return rows
+
+
+@pytest.mark.parametrize("Z,up,dn,energy", _golden_hydrogenic())
+def test_noninteracting_hydrogenic_slater(Z, up, dn, energy):
+    """Slater determinants of hydrogenic orbitals: kinetic + e-n energy is the
+    constant sum of -Z^2/(2n^2); pins the determinant-Laplacian route."""
+    ou = [hydrogenic(o, Z) for o in up]
+    od = [hydrogenic(o, Z) for o in dn]
+    r = _random_points(6, len(up) + len(dn), 7, scale=1.0 / Z)
+    e, _, _ = slater_local_energy(r, ou, od, Z)
+    np.testing.assert_allclose(e, energy, rtol=1e-10)
+
+
+def _golden_potential():
+    rows = []
+    with open(os.path.join(GOLDEN, "potential_points.txt")) as fh:
+        for line in fh:
+            if line.strip() and not line.startswith("#"):
+                name, nuc, el, vnn, v = [x.strip() for x in line.split("|")]
+                nuc = [list(map(float, x.split())) for x in nuc.split(";")]
+                el = [list(map(float, x.split())) for x in el.split(";")]
+                rows.append((name, nuc, el, int(vnn), float(v)))
+    return rows
+
+
+@pytest.mark.parametrize("name,nuc,el,vnn,v", _golden_potential())
+def test_potential_hand_values(name, nuc, el, vnn, v):
+    N = len(el)
+    s = qi.System(tuple(n[0] for n in nuc), tuple(tuple(n[1:]) for n in nuc), N, 0)
+    got = oracle.potential(np.array([el]), s, vnn)
+    assert abs(got[0] - v) < 1e-14 * max(1.0, abs(v))
+
+
+def test_nuclear_repulsion_constants():
+    from oracle.energy import nuclear_repulsion
+    assert abs(nuclear_repulsion(qi.H2) - 1 / 1.4) < 1e-15
+    assert abs(nuclear_repulsion(qi.N2) - 49 / 2.068) < 1e-13
+
+
+def _small_system():
+    return qi.System((3.0, 1.0, 2.0), ((0.0, 0.0, 0.0), (1.6, 0.2, -0.3), (-0.5, 1.4, 0.9)), 3, 2)
+
+
+def test_torch_and_numpy_forwards_agree():
+    for k in (0, 1):
+        s, a, p, r = qi.workload_inputs(k, 6)
+        st, lt = oracle.logpsi(torch.as_tensor(r), torch.as_tensor(p), s, a)
+        sn, ln = oracle.logpsi_np(r, p, s, a)
+        np.testing.assert_allclose(lt.numpy(), ln, rtol=1e-12, atol=1e-12)
+        assert np.all(st.numpy() == sn)
+    s = _small_system()
+    p = qi.make_params(s, SMALL, 11)
+    r = qi.make_walkers(s, 7, 12)
+    st, lt = oracle.logpsi(torch.as_tensor(r), torch.as_tensor(p), s, SMALL)
+    sn, ln = oracle.logpsi_np(r, p, s, SMALL)
+    np.testing.assert_allclose(lt.numpy(), ln, rtol=1e-12, atol=1e-12)
+
+
+def test_single_determinant_matches_numpy_slogdet():
+    """One determinant per spin with c = 1: log|psi| = sum of numpy slogdets."""
+    from oracle.ansatz import orbital_matrices
+    s = _small_system()
+    a = qi.Ansatz(n_rbf=6, rbf_dmax=6.0, init_layers=1, width=12, mp_layers=1, n_det=1, n_env=2)
+    p = qi.make_params(s, a, 13)
+    r = qi.make_walkers(s, 5, 14)
+    mats = orbital_matrices(torch.as_tensor(r), unpack(torch.as_tensor(p), s, a), s, a)
+    ref = sum(np.linalg.slogdet(A.numpy()[:, 0])[1] for A in mats)
+    sgn = np.prod([np.linalg.slogdet(A.numpy()[:, 0])[0] for A in mats], axis=0)
+    st, lt = oracle.logpsi(torch.as_tensor(r), torch.as_tensor(p), s, a)
+    np.testing.assert_allclose(lt.numpy(), ref, rtol=1e-13)
+    assert np.all(st.numpy() == sgn)
+
+
+def test_cancelling_determinants_give_zero_psi():
+    """c = (1, -1) on two identical determinants: psi = 0 -> sign 0, log|psi| = -inf."""
+    s = _small_system()
+    a = qi.Ansatz(n_rbf=6, rbf_dmax=6.0, init_layers=1, width=12, mp_layers=1, n_det=2, n_env=2)
+    p = qi.make_params(s, a, 15)
+    P = unpack(p, s, a)
+    for sp, n in (("up", s.n_up), ("down", s.n_down)):
+        Wo = P[f"orb.{sp}.W"]
+        Wo[:, n:2 * n] = Wo[:, 0:n]
+        P[f"orb.{sp}.b"][n:2 * n] = P[f"orb.{sp}.b"][0:n]
+        P[f"orb.{sp}.pi"][1] = P[f"orb.{sp}.pi"][0]
+        P[f"orb.{sp}.sigma"][1] = P[f"orb.{sp}.sigma"][0]
+    P["c"][:] = [1.0, -1.0]
+    r = qi.make_walkers(s, 4, 16)
+    st, lt = oracle.logpsi(torch.as_tensor(r), torch.as_tensor(p), s, a)
+    assert np.all(st.numpy() == 0) and np.all(np.isneginf(lt.numpy()))
+    res = oracle.local_energy(r, p, s, a)
+    assert np.all(np.isnan(res["e_loc"]))
+
+
+def test_same_spin_exchange_antisymmetry():
+    s = _small_system()
+    p = qi.make_params(s, SMALL, 17)
+    r = qi.make_walkers(s, 5, 18)
+    base = oracle.local_energy(r, p, s, SMALL)
+    for (i, j) in ((0, 2), (3, 4)):
+        rs = r.copy()
+        rs[:, [i, j]] = rs[:, [j, i]]
+        sw = oracle.local_energy(rs, p, s, SMALL)
+        assert np.all(sw["sign"] == -base["sign"])
+        np.testing.assert_allclose(sw["logpsi"], base["logpsi"], rtol=1e-13, atol=1e-13)
+        np.testing.assert_allclose(sw["e_loc"], base["e_loc"], rtol=1e-11, atol=1e-11)
+        g = base["grad"].copy()
+        g[:, [i, j]] = g[:, [j, i]]
+        np.testing.assert_allclose(sw["grad"], g, rtol=1e-11, atol=1e-12)
+
+
+def test_translation_and_rotation_invariance():
+    s = _small_system()
+    p = qi.make_params(s, SMALL, 19)
+    r = qi.make_walkers(s, 4, 20)
+    base = oracle.local_energy(r, p, s, SMALL)
+    q, _ = np.linalg.qr(np.random.default_rng(21).standard_normal((3, 3)))
+    shift = np.array([0.7, -1.1, 2.3])
+    R2 = tuple(tuple(float(x) for x in (q @ np.array(c) + shift)) for c in s.coords)
+    s2 = qi.System(s.charges, R2, s.n_up, s.n_down)
+    r2 = r @ q.T + shift
+    moved = oracle.local_energy(r2, p, s2, SMALL)
+    np.testing.assert_allclose(moved["logpsi"], base["logpsi"], rtol=1e-12, atol=1e-12)
+    np.testing.assert_allclose(moved["e_loc"], base["e_loc"], rtol=1e-10, atol=1e-10)
+    np.testing.assert_allclose(moved["lap"], base["lap"], rtol=1e-10, atol=1e-10)
+
+
+def _fd_grad_lap(r, p, s, a, h):
+    """Central differences of the numpy forward: gradient and Laplacian."""
+    W, N, _ = r.shape
+    l0 = oracle.logpsi_np(r, p, s, a)[1]
+    g = np.zeros((W, N, 3))
+    lap = np.zeros(W)
+    for i in range(N):
+        for x in range(3):
+            rp = r.copy(); rp[:, i, x] += h
+            rm = r.copy(); rm[:, i, x] -= h
+            lpp = oracle.logpsi_np(rp, p, s, a)[1]
+            lmm = oracle.logpsi_np(rm, p, s, a)[1]
+            g[:, i, x] = (lpp - lmm) / (2 * h)
+            lap += (lpp - 2 * l0 + lmm) / h ** 2
+    return g, lap
+
+
+def test_gradient_and_laplacian_vs_finite_differences():
+    s = _small_system()
+    p = qi.make_params(s, SMALL, 23)
+    r = qi.make_walkers(s, 4, 24)
+    res = oracle.local_energy(r, p, s, SMALL)
+    h = 2e-3
+    g1, l1 = _fd_grad_lap(r, p, s, SMALL, h)
+    g2, l2 = _fd_grad_lap(r, p, s, SMALL, h / 2)
+    g = (4 * g2 - g1) / 3          # Richardson extrapolation of O(h^2) schemes
+    lap = (4 * l2 - l1) / 3
+    scale = np.abs(res["grad"]).max()
+    assert np.abs(g - res["grad"]).max() < 1e-7 * max(scale, 1.0)
+    np.testing.assert_allclose(lap, res["lap"], rtol=2e-6, atol=2e-6 * np.abs(res["lap"]).max())
+
+
+def test_loss_gradient_vs_finite_differences_of_surrogate():
+    """FD (h = 1e-5, float64) of S(theta) = sum_w g_w log|psi_w(theta)| with the
+    weights frozen, on sampled parameters, against the autograd estimator."""
+    s = _small_system()
+    p = qi.make_params(s, SMALL, 25)
+    r = qi.make_walkers(s, 6, 26)
+    e = oracle.local_energy(r, p, s, SMALL)["e_loc"]
+    G, e_mean, nf = oracle.loss_grad(r, e, p, s, SMALL)
+    assert nf == 6 and abs(e_mean - e.mean()) < 1e-14 * abs(e_mean) + 1e-14
+    wts = 2 * (e - e.mean()) / len(e)
+    idx = np.random.default_rng(27).choice(len(p), 64, replace=False)
+    h = 1e-5
+    for k in idx:
+        pp = p.copy(); pp[k] += h
+        pm = p.copy(); pm[k] -= h
+        fd = (np.sum(wts * oracle.logpsi_np(r, pp, s, SMALL)[1]) -
+              np.sum(wts * oracle.logpsi_np(r, pm, s, SMALL)[1])) / (2 * h)
+        assert abs(fd - G[k]) < 1e-7 * max(1.0, np.abs(G).max())
+
+
+def test_loss_gradient_zero_variance_hydrogen():
+    """For the exact H-atom state every local energy equals -1/2, so G = 0."""
+    H = qi.System((1.0,), ((0.0, 0.0, 0.0),), 1, 0)
+    p = _one_center_params(H, SMALL, 1.0, np.random.default_rng(28))
+    r = _random_points(16, 1, 29)
+    e = oracle.local_energy(r, p, H, SMALL)["e_loc"]
+    G, _, _ = oracle.loss_grad(r, e, p, H, SMALL)
+    assert np.abs(G).max() < 1e-12
+
+
+@pytest.mark.slow
+def test_loss_gradient_unbiased_hydrogen_closed_form():
+    """H atom with psi = exp(-sigma r), exact samples r ~ |psi|^2 (radius Gamma(3, 1/(2 sigma)),
+    uniform direction): E[G_sigma] = sigma - 1 = d/dsigma (sigma^2/2 - sigma)."""
+    H = qi.System((1.0,), ((0.0, 0.0, 0.0),), 1, 0)
+    a = qi.Ansatz(n_rbf=4, rbf_dmax=6.0, init_layers=1, width=4, mp_layers=0, n_det=1, n_env=1)
+    sigma = 1.4
+    p = _one_center_params(H, a, sigma)
+    names = list(oracle.param_shapes(H, a).keys())
+    off = 0
+    for nm, shp in oracle.param_shapes(H, a).items():
+        if nm == "orb.up.sigma":
+            break
+        off += int(np.prod(shp))
+    rng = np.random.default_rng(30)
+    nb, per = 20, 2000
+    ests = []
+    for b in range(nb):
+        rad = rng.gamma(3.0, 1.0 / (2 * sigma), per)
+        v = rng.standard_normal((per, 3))
+        v /= np.linalg.norm(v, axis=1, keepdims=True)
+        r = (rad[:, None] * v)[:, None, :]
+        e = -sigma ** 2 / 2 + (sigma - 1.0) / rad
+        G, _, _ = oracle.loss_grad(r, e, p, H, a, chunk=per)
+        ests.append(G[off])
+    ests = np.array(ests)
+    mean = ests.mean()
+    err = ests.std(ddof=1) / math.sqrt(nb)     # non-overlapping batch means (Sec. V.A)
+    assert abs(mean - (sigma - 1.0)) < 4 * err + 0.01 * (1.0 / per)
+    assert "orb.up.sigma" in names
+
+
+def test_metropolis_zero_step_accepts_everything():
+    s, a, p, r = qi.workload_inputs(0, 8)
+    lp = oracle.logpsi_np(r, p, s, a)[1]
+    noise = qi.make_noise(1, 8, s.n_elec, 2)[0]
+    u = qi.make_uniforms(1, 8, 3)[0]
+    r2, lp2, acc, _ = oracle.metropolis_step(r, lp, noise, u, 0.0, p, s, a)
+    assert np.all(acc == 1) and np.all(r2 == r)
+    np.testing.assert_allclose(lp2, lp, rtol=1e-13)
+
+
+def test_metropolis_rejects_nan_and_accepts_u_zero():
+    s, a, p, r = qi.workload_inputs(0, 4)
+    lp = oracle.logpsi_np(r, p, s, a)[1]
+    noise = qi.make_noise(1, 4, s.n_elec, 2)[0]
+    u = np.array([0.0, 0.0, 0.999999, 0.5])
+    lp_in = lp.copy()
+    lp_in[1] = np.inf            # current state infinitely likely -> proposal rejected unless u = 0
+    r2, lp2, acc, prop = oracle.metropolis_step(r, lp_in, noise, u, 0.5, p, s, a)
+    assert acc[0] == 1           # log 0 = -inf < anything finite
+    assert acc[1] == 0           # -inf < -inf is false
+
+
+@pytest.mark.slow
+def test_metropolis_hydrogen_mean_radius():
+    """Sampling |exp(-r)|^2 with the random-walk Metropolis step gives <r> = 3/2."""
+    H = qi.System((1.0,), ((0.0, 0.0, 0.0),), 1, 0)
+    a = qi.Ansatz(n_rbf=4, rbf_dmax=6.0, init_layers=1, width=4, mp_layers=0, n_det=1, n_env=1)
+    p = _one_center_params(H, a, 1.0)
+    W = 1000
+    r = _random_points(W, 1, 31, scale=1.0)
+    lp = oracle.logpsi_np(r, p, H, a)[1]
+    rng = np.random.default_rng(32)
+    rs = []
+    for t in range(400):
+        r, lp, acc, _ = oracle.metropolis_step(r, lp, rng.standard_normal((W, 1, 3)), rng.random(W), 0.6, p, H, a, chunk=W)
+        if t >= 100:
+            rs.append(np.linalg.norm(r[:, 0], axis=-1))
+    rs = np.array(rs)                    # [steps, W]
+    per_walker = rs.mean(0)
+    mean = per_walker.mean()
+    err = per_walker.std(ddof=1) / math.sqrt(W)
+    assert abs(mean - 1.5) < 4 * err
