@@ -1,0 +1,216 @@
+"""Benchmark of the VMC hot path on one MI355X.
+
+One step = the whole hot path over one batch of walkers: 10 random-walk
+Metropolis steps (each a full log|psi| evaluation of the proposals) followed
+by the local energy with exact gradient and Laplacian (and the loss gradient
+when the build provides it).  Workload: the N2-sized system (two Z=7 nuclei
+2.068 bohr apart, 7 up + 7 down electrons, 4096 walkers, 4 message-passing
+layers of width 128, 16 determinants, 8 envelope exponents), float32 jets with
+float64 determinants.  Inputs are seeded, synthetic and resident on the GPU
+before the timed region.
+
+Prints one JSON line.  `value` = walkers passed through the whole step per
+second; the local-energy-only rate, the error of E_L against the FP64 oracle,
+the roofline of the dominant kernel and the oracle's own throughput on the
+host cores are reported beside it.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK = {"fp32_mfma": 157.3e12, "fp64_mfma": 78.6e12, "bf16_mfma": 2.5e15, "hbm": 8.0e12}
+
+
+def algorithmic_model(s, a, elem_bytes):
+    """Per-walker algorithmic work of each stage (no padding, no structural zeros).
+
+    Jets carry R1 = 3N + 2 rows per electron (value, 3N tangents, Laplacian)."""
+    N, M, K, D, L, L0, nd = s.n_elec, s.n_nuc, a.n_rbf, a.width, a.mp_layers, a.init_layers, a.n_det
+    T = 3 * N
+    R1 = T + 2
+    Rj = N * R1
+    P = [s.n_up * (s.n_up - 1) // 2 + s.n_down * (s.n_down - 1) // 2, s.n_up * s.n_down, N * M]
+    nsq = s.n_up ** 2 + s.n_down ** 2
+    m = {}
+    m["node_gemm_jet_flops"] = (2 * Rj * ((M + 2) * K * D + (L0 - 1) * D * D) + L * 2 * Rj * 4 * D * D
+                                + 2 * R1 * D * nd * nsq)
+    m["edge_gemm_jet_flops"] = L * sum(P) * 3 * 2 * (K * D + D * D)
+    m["value_flops"] = (2 * N * ((M + 2) * K * D + (L0 - 1) * D * D) + L * (2 * N * 4 * D * D + sum(P) * 2 * (K * D + D * D))
+                        + 2 * D * nd * nsq)
+    m["agg_jet_bytes"] = L * elem_bytes * (N * R1 * D + N * R1 * 3 * D + sum(P) * 3 * D)
+    m["det_jet_bytes"] = elem_bytes * nd * R1 * nsq + 8 * 2 * nd * (T + 3)
+    return m
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--walkers", type=int, default=4096)
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64", "bf16"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-walkers", type=int, default=48)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path (walkers would be sharded "
+              "across GPUs with one all-reduce of the loss gradient).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import qmc_inputs as qi
+    from paper_2307_14123_amd import qmc
+
+    wl = qi.workload(1)
+    s, a = wl.systems[0], wl.ansatz
+    W = args.walkers
+    n_mc, tau = wl.metropolis_steps, wl.step_size
+    params = qi.make_params(s, a, qi.seed(1, 0))
+    r0 = qi.make_walkers(s, W, qi.seed(1, 1))
+    noise = qi.make_noise(n_mc, W, s.n_elec, qi.seed(1, 2))
+    uni = qi.make_uniforms(n_mc, W, qi.seed(1, 3))
+
+    dev = torch.device("cuda", 0)
+    plan = qmc.Plan([s], [W], a, args.precision)
+    P = torch.as_tensor(params, dtype=plan.param_dtype, device=dev).contiguous()
+    R = torch.as_tensor(r0, device=dev).contiguous()
+    NOISE = torch.as_tensor(noise, device=dev).contiguous()
+    U = torch.as_tensor(uni, device=dev).contiguous()
+    lp, _ = plan.logpsi(P, R)
+    out = {"logpsi": torch.empty(W, dtype=torch.float64, device=dev),
+           "sign": torch.empty(W, dtype=torch.float64, device=dev),
+           "grad": torch.empty(W * s.n_elec * 3, dtype=torch.float64, device=dev),
+           "lap": torch.empty(W, dtype=torch.float64, device=dev),
+           "e_loc": torch.empty(W, dtype=torch.float64, device=dev)}
+    acc = torch.empty(W, dtype=torch.uint8, device=dev)
+    for op in range(3):
+        plan.workspace(op)
+    has_grad = True
+    try:
+        plan.loss_grad(P, R, out["e_loc"])
+    except qmc.QmcError:
+        has_grad = False
+    torch.cuda.synchronize()
+
+    def step():
+        for t in range(n_mc):
+            plan.metropolis_step(P, R, lp, NOISE[t], U[t], tau, accepted=acc)
+        plan.local_energy(P, R, out=out)
+        if has_grad:
+            plan.loss_grad(P, R, out["e_loc"])
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    qmc.profile_enable(True)
+    qmc.profile_report(reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = qmc.profile_report(reset=True)
+    qmc.profile_enable(False)
+    ms_step = (t1 - t0) * 1e3 / args.steps
+
+    # local energy alone
+    reps = max(3, args.steps)
+    plan.local_energy(P, R, out=out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        plan.local_energy(P, R, out=out)
+    torch.cuda.synchronize()
+    ms_le = (time.perf_counter() - t0) * 1e3 / reps
+
+    eb = 8 if args.precision == "fp64" else 4
+    model = algorithmic_model(s, a, eb)
+    # dominant kernel by total time in the timed region
+    name, (nl, tot_ms) = max(prof.items(), key=lambda kv: kv[1][1])
+    avg_s = tot_ms / nl * 1e-3
+    gemm_dtype = {"fp32": "fp32_mfma", "fp64": "fp64_mfma", "bf16": "bf16_mfma"}[args.precision]
+    roof = None
+    if name.startswith("gemm_kernel") and (",6>" in name or ",5>" in name or ",7>" in name):
+        # jet node GEMMs of the local energy: init, per layer h and g, two orbital maps
+        launches_per_le = 1 + (a.init_layers - 1) + 2 * a.mp_layers + 2
+        per_launch = model["node_gemm_jet_flops"] * W / launches_per_le
+        roof = {"bound": "mfma", "achieved": per_launch / avg_s / 1e12, "peak": PEAK[gemm_dtype] / 1e12,
+                "unit": "TFLOP/s"}
+    elif name.startswith("aggregate_kernel"):
+        per_launch = model["agg_jet_bytes"] / a.mp_layers * W
+        roof = {"bound": "hbm", "achieved": per_launch / avg_s / 1e9, "peak": PEAK["hbm"] / 1e9, "unit": "GB/s"}
+    elif name.startswith("det_kernel"):
+        per_launch = model["det_jet_bytes"] * W / 2
+        roof = {"bound": "hbm", "achieved": per_launch / avg_s / 1e9, "peak": PEAK["hbm"] / 1e9, "unit": "GB/s"}
+    if roof is not None:
+        roof["frac"] = roof["achieved"] / roof["peak"]
+        roof["traffic"] = None
+        roof["kernel"] = name
+        roof["avg_launch_ms"] = tot_ms / nl
+
+    res = {
+        "metric": "walker local energies/sec at stated mHa error vs FP64 oracle; VMC train step ms",
+        "value": W / (ms_step * 1e-3),
+        "unit": "walkers/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"fp32": "f32+f64", "fp64": "f64", "bf16": "bf16+f32+f64"}[args.precision],
+        "data": "synthetic",
+        "config": {"workload": f"N2-sized: 2 x Z=7 at 2.068 bohr, 7 up + 7 down, {W} walkers, "
+                               f"{a.mp_layers} message-passing layers width {a.width}, {a.n_det} dets, "
+                               f"{a.n_env} envelope exponents; step = {n_mc} Metropolis steps (tau {tau}) + "
+                               f"local energy" + (" + loss gradient" if has_grad else ""),
+                   "walkers": W, "electrons": s.n_elec, "precision": args.precision,
+                   "loss_gradient_in_step": has_grad},
+        "e_loc_per_s": W / (ms_le * 1e-3),
+        "e_loc_ms": ms_le,
+        "roofline": roof,
+        "kernels_ms_per_step": {k: v[1] / args.steps for k, v in sorted(prof.items(), key=lambda kv: -kv[1][1])},
+    }
+
+    if not args.no_cpu_baseline:
+        import oracle
+        torch.set_num_threads(os.cpu_count() or 1)
+        nw = args.cpu_walkers
+        rs = r0[:nw].copy()
+        t0 = time.perf_counter()
+        lp_c = oracle.logpsi_np(rs, P.double().cpu().numpy(), s, a)[1]
+        pc = P.double().cpu().numpy()
+        for t in range(n_mc):
+            rs, lp_c, _, _ = oracle.metropolis_step(rs, lp_c, noise[t, :nw], uni[t, :nw], tau, pc, s, a)
+        ref = oracle.local_energy(rs, pc, s, a, chunk=16)
+        if has_grad:
+            oracle.loss_grad(rs, ref["e_loc"], pc, s, a)
+        tc = time.perf_counter() - t0
+        res["cpu_baseline"] = {"value": nw / tc, "unit": "walkers/s", "cores": torch.get_num_threads(),
+                               "kind": "oracle",
+                               "sample": f"{nw} of the {W} walkers through the same step (float64 CPU oracle: "
+                                         f"serial autograd Laplacian), {tc:.1f} s"}
+        # error of the GPU local energy on the same sample positions
+        Rs = torch.as_tensor(rs, device=dev).contiguous()
+        sub = qmc.Plan([s], [nw], a, args.precision)
+        o2 = sub.local_energy(P, Rs)
+        torch.cuda.synchronize()
+        err = np.abs(o2["e_loc"].cpu().numpy() - ref["e_loc"]) * 1e3
+        res["e_loc_err_mha_vs_fp64_oracle"] = {"p50": float(np.median(err)), "p99": float(np.percentile(err, 99)),
+                                               "max": float(err.max()), "walkers": nw}
+    print(json.dumps(res))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,206 @@
+/*
+ * qmc.h -- C ABI of the MI355X (gfx950) library for the hot path of
+ * real-space deep variational quantum Monte Carlo: batched evaluation of a
+ * graph-network wave function over many walkers, its exact gradient and
+ * Laplacian by forward propagation, the local energy, a random-walk
+ * Metropolis step and the VMC loss gradient.
+ *
+ * The quantities follow the paper (arXiv 2307.14123, DeepQMC):
+ *   - Hamiltonian inputs Z_I, R_I and the potential: molecular Hamiltonian,
+ *     Sec. II.A (the constant nucleus-nucleus repulsion is added when
+ *     qmc_ansatz.include_vnn is set).
+ *   - Spin convention: electrons 0..n_up-1 are spin-up, Sec. II.B.
+ *   - Ansatz: generalised Slater determinants (Sec. II.C) with graph-network
+ *     electron embeddings (Sec. III.A), orbitals times isotropic exponential
+ *     envelopes (Sec. III.B), spin-factorised determinants (Sec. III.C), in
+ *     the log domain (Sec. III.E).
+ *   - Local energy E_loc = -1/2 sum_i (Delta_i log|psi| + |grad_i log|psi||^2)
+ *     + V, Sec. IV.B.
+ *   - Loss gradient 2 E[(E_loc - L) grad_theta log|psi|], Sec. IV.A.
+ *   - Random-walk Metropolis sampler, Sec. V.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *   Memory: every array argument except the qmc_system / qmc_ansatz host
+ *     arrays is DEVICE memory owned by the caller.  The library never keeps a
+ *     pointer past the call.  Workspace `ws` is caller-allocated device memory
+ *     of at least qmc_workspace_size(plan, op) bytes, 256-byte aligned.
+ *   Layout: row-major, walker-major.  For a plan over several systems the
+ *     walker arrays are the concatenation of each system's block (system 0
+ *     first) and `params` is the concatenation of each system's blob.
+ *   Types: positions r, noise, u, logpsi, sign, grad, lap, e_loc, cotangent
+ *     and e_mean are double.  `params` and `grad_params` are double for a
+ *     QMC_FP64 plan and float for QMC_FP32 / QMC_BF16_MIXED plans.
+ *   Streams: `stream` is a hipStream_t passed as void* (NULL = the null
+ *     stream).  Calls enqueue work and return without synchronising; outputs
+ *     are valid once the stream reaches that point.
+ *   Errors: arguments are validated on the host before anything is enqueued;
+ *     a failed validation returns a status and launches nothing.  HIP launch
+ *     failures return QMC_ERR_HIP.  Nothing aborts and no exception crosses
+ *     the ABI.  Numerical anomalies are data: psi = 0 gives sign 0 and
+ *     logpsi = -inf, and an undefined local energy is NaN.
+ *   Concurrency: a plan is immutable after creation; concurrent calls on
+ *     different streams with different workspaces are safe.
+ */
+#ifndef QMC_H_
+#define QMC_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* One molecule (Sec. II.A): n_nuc nuclei with charges[n_nuc] and
+ * coords[n_nuc][3] in bohr (host arrays, copied by qmc_plan_create), n_up
+ * spin-up electrons followed by n_down spin-down electrons. */
+typedef struct qmc_system {
+  int32_t n_nuc;
+  const double* charges;
+  const double* coords;
+  int32_t n_up;
+  int32_t n_down;
+} qmc_system;
+
+/* Hyper-parameters of the ansatz (Sec. III).  version must be 1.
+ *   n_rbf, rbf_dmax : Gaussian radial basis of distances, centres
+ *                     k*rbf_dmax/(n_rbf-1), width rbf_dmax/(n_rbf-1)
+ *   init_layers     : tanh layers of the electron-node initialisation
+ *   width           : embedding width D
+ *   mp_layers       : message-passing interaction layers
+ *   n_det           : determinants
+ *   n_env           : envelope exponents per (orbital, nucleus)
+ *   include_vnn     : add sum_{I<J} Z_I Z_J / R_IJ to the potential */
+typedef struct qmc_ansatz {
+  int32_t version;
+  int32_t n_rbf;
+  double rbf_dmax;
+  int32_t init_layers;
+  int32_t width;
+  int32_t mp_layers;
+  int32_t n_det;
+  int32_t n_env;
+  int32_t include_vnn;
+} qmc_ansatz;
+
+typedef enum qmc_precision {
+  QMC_FP64 = 0,        /* every stage in float64 */
+  QMC_FP32 = 1,        /* embedding/orbital jets in float32, determinants,
+                          geometry and combination in float64 */
+  QMC_BF16_MIXED = 2   /* as QMC_FP32, but the embedding GEMMs take bf16
+                          operands with float32 accumulation */
+} qmc_precision;
+
+typedef enum qmc_status {
+  QMC_OK = 0,
+  QMC_ERR_INVALID_ARGUMENT = 1,
+  QMC_ERR_UNSUPPORTED = 2,
+  QMC_ERR_WORKSPACE_TOO_SMALL = 3,
+  QMC_ERR_HIP = 4,
+  QMC_ERR_INTERNAL = 5
+} qmc_status;
+
+/* Operation codes for qmc_workspace_size. */
+enum {
+  QMC_OP_LOGPSI = 0,
+  QMC_OP_LOCAL_ENERGY = 1,
+  QMC_OP_METROPOLIS = 2,
+  QMC_OP_LOGPSI_VJP = 3,
+  QMC_OP_LOSS_GRAD = 4
+};
+
+typedef struct qmc_plan qmc_plan;
+
+/* Number of scalar parameters of the ansatz blob for one system, or a
+ * negative value if the arguments are invalid.  Host only, pure.
+ * Blob order (matrices stored [in][out] so that a layer is y = x W + b):
+ *   init.W1[(M+2)K][D] init.b1[D], then init.Wl[D][D] init.bl[D] for l>=2;
+ *   per interaction layer: for t in (same, opp, nuc): U1[K][D] a1[D]
+ *     U2[D][D] a2[D]; then Wh[D][D] bh[D] Y[M][D] Wg[3D][D] bg[D];
+ *   per spin with n_sigma > 0: Worb[D][n_det*n_sigma] borb[n_det*n_sigma]
+ *     pi[n_det][n_sigma][M][n_env] sigma[n_det][n_sigma][M][n_env];
+ *   c[n_det]. */
+int64_t qmc_param_count(const qmc_system* system, const qmc_ansatz* ansatz);
+
+/* Create a plan for n_systems systems with walkers_per_system[s] walkers
+ * each (host arrays).  flags: reserved, must be 0.  On success *out owns the
+ * plan; release it with qmc_plan_destroy.  Host only: no device memory is
+ * allocated and nothing is launched. */
+qmc_status qmc_plan_create(qmc_plan** out, const qmc_system* systems, int32_t n_systems,
+                           const int64_t* walkers_per_system, const qmc_ansatz* ansatz,
+                           qmc_precision precision, uint32_t flags);
+
+qmc_status qmc_plan_destroy(qmc_plan* plan);
+
+/* Bytes of workspace that operation `op` (QMC_OP_*) needs. */
+qmc_status qmc_workspace_size(const qmc_plan* plan, int32_t op, size_t* bytes);
+
+/* Total walkers, electrons of system s, and parameters of the whole plan. */
+qmc_status qmc_plan_info(const qmc_plan* plan, int64_t* total_walkers, int64_t* total_params,
+                         int64_t* total_positions);
+
+/* sign psi and log|psi| (Sec. III.E) of every walker.
+ *   r[W][N][3] -> logpsi[W], sign[W] (sign in {-1, 0, +1}). */
+qmc_status qmc_logpsi(const qmc_plan* plan, const void* params, const double* r, double* logpsi,
+                      double* sign, void* ws, size_t ws_bytes, void* stream);
+
+/* Local energy (Sec. IV.B) with exact derivatives over all 3N coordinates:
+ *   r[W][N][3] -> logpsi[W], sign[W], grad[W][N][3] = grad log|psi|,
+ *   lap[W] = Laplacian of log|psi|, e_loc[W].
+ * Any output pointer except e_loc may be NULL. */
+qmc_status qmc_local_energy(const qmc_plan* plan, const void* params, const double* r,
+                            double* logpsi, double* sign, double* grad, double* lap, double* e_loc,
+                            void* ws, size_t ws_bytes, void* stream);
+
+/* One random-walk Metropolis step (Sec. V): r' = r + step * noise, accepted
+ * iff log(u) < 2 (log|psi(r')| - logpsi) in float64.  r and logpsi are
+ * in/out and change only for accepted walkers; logpsi must hold log|psi(r)|
+ * on entry.  noise[W][N][3] ~ N(0,1), u[W] in [0,1), accepted[W] in {0,1}
+ * (accepted may be NULL). */
+qmc_status qmc_metropolis_step(const qmc_plan* plan, const void* params, double* r,
+                               double* logpsi, const double* noise, const double* u, double step,
+                               uint8_t* accepted, void* ws, size_t ws_bytes, void* stream);
+
+/* Vector-Jacobian product of log|psi| with respect to the parameters:
+ *   grad_params[P] = sum_w cotangent[w] * d log|psi_w| / d params. */
+qmc_status qmc_logpsi_vjp(const qmc_plan* plan, const void* params, const double* r,
+                          const double* cotangent, void* grad_params, void* ws, size_t ws_bytes,
+                          void* stream);
+
+/* VMC loss gradient (Sec. IV.A): over the walkers of each system whose
+ * e_loc is finite, e_mean = their mean local energy (float64) and
+ *   grad_params = (2 / W_f) sum_w (e_loc[w] - e_mean) d log|psi_w| / d params.
+ * e_loc[W] is an input (as returned by qmc_local_energy); e_mean[n_systems]
+ * is a device output (may be NULL). */
+qmc_status qmc_loss_grad(const qmc_plan* plan, const void* params, const double* r,
+                         const double* e_loc, void* grad_params, double* e_mean, void* ws,
+                         size_t ws_bytes, void* stream);
+
+/* Determinant stage on caller-given orbital-matrix jets, for one spin block:
+ * for each of n_mat matrices A (n x n) with derivative matrices over n_tan
+ * coordinates and a Laplacian matrix, stored jets[n_mat][n_tan + 2][n][n]
+ * (row 0 = A, rows 1..n_tan = dA/dx_c, row n_tan+1 = sum_c d2A/dx_c^2),
+ * computes log|det A|, its sign, d log|det A| / dx_c = tr(A^-1 dA_c) and
+ * Delta log|det A| = tr(A^-1 lapA) - sum_c tr((A^-1 dA_c)^2) (Jacobi's
+ * formula; the log-domain determinant of Sec. III.E).  All device float64:
+ * logdet[n_mat], sign[n_mat], grad[n_mat][n_tan], lap[n_mat]. */
+qmc_status qmc_det_jets(int64_t n_mat, int32_t n, int32_t n_tan, const double* jets,
+                        double* logdet, double* sign, double* grad, double* lap, void* stream);
+
+/* Launch timing for measurement.  While enabled (process-wide), every kernel
+ * launch is bracketed by a pair of HIP events on its stream.
+ * qmc_profile_report waits for the recorded events and writes one line per
+ * kernel, "name launches total_ms\n", into buf (host, len bytes); reset != 0
+ * clears the records.  Not safe to call concurrently with launches from
+ * other host threads. */
+qmc_status qmc_profile_enable(int32_t on);
+qmc_status qmc_profile_report(char* buf, size_t len, int32_t reset);
+
+const char* qmc_status_str(qmc_status status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QMC_H_ */

@@ -1,0 +1,381 @@
+// C-ABI entry points: validate on the host, then enqueue the kernel sequence
+// of each system and walker chunk on the caller's stream.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "kernels.h"
+#include "plan.h"
+
+namespace qmc {
+
+// ---------------------------------------------------------------- launch timing
+struct ProfRec {
+  const char* name;
+  hipEvent_t a, b;
+};
+static std::mutex g_prof_mu;
+static bool g_prof_on = false;
+static std::vector<ProfRec> g_prof;
+
+bool prof_on() { return g_prof_on; }
+void prof_push(const char* name, hipEvent_t a, hipEvent_t b) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  g_prof.push_back({name, a, b});
+}
+
+static SysDev make_dev(const Plan& P, const SysPlan& s) {
+  SysDev d;
+  std::memset(&d, 0, sizeof(d));
+  d.N = s.N;
+  d.M = s.M;
+  d.nup = s.nup;
+  d.ndn = s.ndn;
+  d.T = s.T;
+  d.Rp = s.Rp;
+  d.K = P.ans.n_rbf;
+  d.D = P.ans.width;
+  d.ndet = P.ans.n_det;
+  d.nenv = P.ans.n_env;
+  d.P0 = s.P[0];
+  d.P1 = s.P[1];
+  d.P2 = s.P[2];
+  d.dmax = P.ans.rbf_dmax;
+  d.vnn = P.ans.include_vnn ? s.vnn : 0.0;
+  for (int I = 0; I < s.M; ++I) {
+    d.Z[I] = s.Z[I];
+    for (int x = 0; x < 3; ++x) d.R[3 * I + x] = s.R[3 * I + x];
+  }
+  return d;
+}
+
+#define CK(x)                                  \
+  do {                                         \
+    hipError_t e_ = (x);                       \
+    if (e_ != hipSuccess) return QMC_ERR_HIP;  \
+  } while (0)
+
+static GemmKind embed_kind(qmc_precision p) {
+  return p == QMC_FP64 ? GK_F64 : (p == QMC_BF16_MIXED ? GK_BF16 : GK_F32);
+}
+static GemmKind orbital_kind(qmc_precision p) { return p == QMC_FP64 ? GK_F64 : GK_F32; }
+
+static GemmArgs dense(const void* X, int64_t ldx, const void* W, int64_t ldw, const void* bias, void* Y, int64_t ldy,
+                      int64_t rows, int K, int Ncols, int Rp, int T, int act, int vmode) {
+  GemmArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.X = X;
+  a.ldx = ldx;
+  a.xrpw = rows;
+  a.xws = 0;
+  a.W = W;
+  a.ldw = ldw;
+  a.bias = bias;
+  a.Res = nullptr;
+  a.Y = Y;
+  a.ldy = ldy;
+  a.yrpw = rows;
+  a.yws = 0;
+  a.rows = rows;
+  a.K = K;
+  a.Ncols = Ncols;
+  a.Rp = Rp;
+  a.T = T;
+  a.act = act;
+  a.vmode = vmode;
+  a.transw = 0;
+  return a;
+}
+
+struct Outs {
+  double* logpsi;
+  double* sign;
+  double* grad;
+  double* lap;
+  double* eloc;
+};
+
+// Forward pass of one walker chunk: jet = 1 propagates value, 3N tangent and
+// Laplacian rows (local energy); jet = 0 propagates values only (log|psi|).
+template <typename S>
+static qmc_status forward_chunk(const Plan& P, const SysPlan& s, const S* prm, const double* r, int64_t wc, int jet,
+                                const Workspace& L, char* ws, const Outs& out, hipStream_t st) {
+  const SysDev dv = make_dev(P, s);
+  const int64_t N = s.N, M = s.M, D = P.ans.width, K = P.ans.n_rbf, ND = P.ans.n_det;
+  const int Rp = jet ? s.Rp : 1, Re = jet ? 4 : 1, vm = jet ? 0 : 1;
+  const GemmKind gk = embed_kind(P.prec), ok = orbital_kind(P.prec);
+  double* ee = (double*)(ws + L.geom);
+  double* en = ee + wc * N * N * 4;
+  double* vpot = (double*)(ws + L.vpot);
+  S* rho[3];
+  S* ehid[3];
+  S* wj[3];
+  for (int t = 0; t < 3; ++t) {
+    rho[t] = (S*)(ws + L.rho[t]);
+    ehid[t] = (S*)(ws + L.ehid[t]);
+    wj[t] = (S*)(ws + L.wjet[t]);
+  }
+  S* x0 = (S*)(ws + L.x0);
+  S* f = (S*)(ws + L.f);
+  S* h = (S*)(ws + L.h);
+  S* m = (S*)(ws + L.m);
+  S* ajet = (S*)(ws + L.ajet);
+  double* dld = (double*)(ws + L.dld);
+  double* dsg = (double*)(ws + L.dsg);
+  double* dg = (double*)(ws + L.dg);
+  double* dlap = (double*)(ws + L.dlap);
+  const ParamOffsets& O = s.off;
+
+  CK(launch_geometry(dv, r, wc, ee, en, jet ? vpot : nullptr, st));
+  if (P.ans.mp_layers > 0)
+    for (int t = 0; t < 3; ++t) CK(launch_rbf<S>(dv, t, ee, en, wc, jet, rho[t], st));
+  CK(launch_init_features<S>(dv, ee, en, wc, jet, x0, st));
+  const int64_t rows = wc * N * Rp;
+  const int F = (int)((M + 2) * K);
+  CK(launch_gemm(gk, dense(x0, F, prm + O.initW[0], D, prm + O.initb[0], f, D, rows, F, (int)D, Rp, s.T, 1, vm), st));
+  for (int l = 1; l < P.ans.init_layers; ++l) {
+    CK(launch_gemm(gk, dense(f, D, prm + O.initW[l], D, prm + O.initb[l], h, D, rows, (int)D, (int)D, Rp, s.T, 1, vm),
+                   st));
+    S* tmp = f;
+    f = h;
+    h = tmp;
+  }
+  for (int l = 0; l < P.ans.mp_layers; ++l) {
+    const auto& Ly = O.mp[l];
+    for (int t = 0; t < 3; ++t) {
+      const int64_t re = wc * s.P[t] * Re;
+      if (re == 0) continue;
+      CK(launch_gemm(gk, dense(rho[t], K, prm + Ly.U1[t], D, prm + Ly.a1[t], ehid[t], D, re, (int)K, (int)D, Re, 1, 1, vm),
+                     st));
+      CK(launch_gemm(gk, dense(ehid[t], D, prm + Ly.U2[t], D, prm + Ly.a2[t], wj[t], D, re, (int)D, (int)D, Re, 1, 0, vm),
+                     st));
+    }
+    CK(launch_gemm(gk, dense(f, D, prm + Ly.Wh, D, prm + Ly.bh, h, D, rows, (int)D, (int)D, Rp, s.T, 0, vm), st));
+    CK(launch_aggregate<S>(dv, h, wj[0], wj[1], wj[2], prm + Ly.Y, ee, en, wc, jet, m, st));
+    GemmArgs g = dense(m, 3 * D, prm + Ly.Wg, D, prm + Ly.bg, f, D, rows, (int)(3 * D), (int)D, Rp, s.T, 1, vm);
+    g.Res = f;
+    CK(launch_gemm(gk, g, st));
+  }
+  int64_t off_e = 0;
+  for (int sp = 0; sp < 2; ++sp) {
+    const int64_t n = s.nsig(sp);
+    if (n == 0) continue;
+    GemmArgs a = dense(f + off_e * Rp * D, D, prm + O.orbW[sp], ND * n, prm + O.orbb[sp], (S*)(ws + L.phi[sp]),
+                       ND * n, wc * n * Rp, (int)D, (int)(ND * n), Rp, s.T, 0, vm);
+    a.xrpw = n * Rp;
+    a.xws = N * Rp * D;
+    CK(launch_gemm(ok, a, st));
+    CK(launch_envelope<S>(dv, sp, (S*)(ws + L.phi[sp]), prm + O.pi[sp], prm + O.sigma[sp], en, wc, jet, ajet, st));
+    off_e += n;
+  }
+  CK(launch_det<S>(dv, ajet, wc, jet, dld, dsg, dg, dlap, st));
+  CK(launch_combine<S>(dv, prm + O.c, dld, dsg, dg, dlap, vpot, wc, jet, out.logpsi, out.sign, out.grad, out.lap,
+                       out.eloc, st));
+  return QMC_OK;
+}
+
+static bool ws_ok(const Plan& P, int op, const void* ws, size_t ws_bytes) {
+  if (!ws) return false;
+  if (reinterpret_cast<uintptr_t>(ws) % 256 != 0) return false;
+  return ws_bytes >= workspace_bytes(P, op);
+}
+
+static int64_t pos_offset(const Plan& P, const SysPlan& s) {
+  int64_t pos = 0;
+  for (const auto& t : P.sys) {
+    if (&t == &s) break;
+    pos += t.W * t.N * 3;
+  }
+  return pos;
+}
+
+template <typename S>
+static qmc_status run_forward(const Plan& P, const void* params, const double* r, const Outs& o, int jet, char* ws,
+                              hipStream_t st) {
+  const int op = jet ? QMC_OP_LOCAL_ENERGY : QMC_OP_LOGPSI;
+  for (const auto& s : P.sys) {
+    const S* prm = (const S*)params + s.param_offset;
+    for (int64_t w0 = 0; w0 < s.W; w0 += s.Wc) {
+      const int64_t wc = std::min<int64_t>(s.Wc, s.W - w0);
+      const int64_t wg = s.walker_offset + w0;  // global walker index
+      const Workspace L = workspace_layout(P, s, op, wc);
+      Outs oc;
+      oc.logpsi = o.logpsi ? o.logpsi + wg : nullptr;
+      oc.sign = o.sign ? o.sign + wg : nullptr;
+      oc.grad = o.grad ? o.grad + pos_offset(P, s) + w0 * s.T : nullptr;
+      oc.lap = o.lap ? o.lap + wg : nullptr;
+      oc.eloc = o.eloc ? o.eloc + wg : nullptr;
+      const double* rc = r + pos_offset(P, s) + w0 * s.N * 3;
+      const qmc_status e = forward_chunk<S>(P, s, prm, rc, wc, jet, L, ws, oc, st);
+      if (e != QMC_OK) return e;
+    }
+  }
+  return QMC_OK;
+}
+
+template <typename S>
+static qmc_status run_metropolis(const Plan& P, const void* params, double* r, double* logpsi, const double* noise,
+                                 const double* u, double step, uint8_t* accepted, char* ws, hipStream_t st) {
+  for (const auto& s : P.sys) {
+    const S* prm = (const S*)params + s.param_offset;
+    const int64_t pos = pos_offset(P, s);
+    for (int64_t w0 = 0; w0 < s.W; w0 += s.Wc) {
+      const int64_t wc = std::min<int64_t>(s.Wc, s.W - w0);
+      const int64_t wg = s.walker_offset + w0;
+      const Workspace L = workspace_layout(P, s, QMC_OP_METROPOLIS, wc);
+      double* rp = (double*)(ws + L.lp_prop);
+      double* lpp = rp + wc * s.N * 3;
+      const int64_t off = pos + w0 * s.N * 3;
+      CK(launch_propose(r + off, noise + off, step, wc * s.N * 3, rp, st));
+      Outs oc;
+      std::memset(&oc, 0, sizeof(oc));
+      oc.logpsi = lpp;
+      const qmc_status e = forward_chunk<S>(P, s, prm, rp, wc, 0, L, ws, oc, st);
+      if (e != QMC_OK) return e;
+      CK(launch_accept(wc, s.N * 3, rp, lpp, u + wg, r + off, logpsi + wg, accepted ? accepted + wg : nullptr, st));
+    }
+  }
+  return QMC_OK;
+}
+
+}  // namespace qmc
+
+using namespace qmc;
+
+extern "C" {
+
+qmc_status qmc_logpsi(const qmc_plan* plan, const void* params, const double* r, double* logpsi, double* sign,
+                      void* ws, size_t ws_bytes, void* stream) {
+  if (!plan || !params || !r || !logpsi) return QMC_ERR_INVALID_ARGUMENT;
+  if (!ws_ok(plan->p, QMC_OP_LOGPSI, ws, ws_bytes)) {
+    if (ws && ws_bytes < workspace_bytes(plan->p, QMC_OP_LOGPSI)) return QMC_ERR_WORKSPACE_TOO_SMALL;
+    return QMC_ERR_INVALID_ARGUMENT;
+  }
+  Outs o;
+  std::memset(&o, 0, sizeof(o));
+  o.logpsi = logpsi;
+  o.sign = sign;
+  hipStream_t st = (hipStream_t)stream;
+  if (plan->p.prec == QMC_FP64) return run_forward<double>(plan->p, params, r, o, 0, (char*)ws, st);
+  return run_forward<float>(plan->p, params, r, o, 0, (char*)ws, st);
+}
+
+qmc_status qmc_local_energy(const qmc_plan* plan, const void* params, const double* r, double* logpsi, double* sign,
+                            double* grad, double* lap, double* e_loc, void* ws, size_t ws_bytes, void* stream) {
+  if (!plan || !params || !r || !e_loc) return QMC_ERR_INVALID_ARGUMENT;
+  if (!ws_ok(plan->p, QMC_OP_LOCAL_ENERGY, ws, ws_bytes)) {
+    if (ws && ws_bytes < workspace_bytes(plan->p, QMC_OP_LOCAL_ENERGY)) return QMC_ERR_WORKSPACE_TOO_SMALL;
+    return QMC_ERR_INVALID_ARGUMENT;
+  }
+  Outs o = {logpsi, sign, grad, lap, e_loc};
+  hipStream_t st = (hipStream_t)stream;
+  if (plan->p.prec == QMC_FP64) return run_forward<double>(plan->p, params, r, o, 1, (char*)ws, st);
+  return run_forward<float>(plan->p, params, r, o, 1, (char*)ws, st);
+}
+
+qmc_status qmc_metropolis_step(const qmc_plan* plan, const void* params, double* r, double* logpsi,
+                               const double* noise, const double* u, double step, uint8_t* accepted, void* ws,
+                               size_t ws_bytes, void* stream) {
+  if (!plan || !params || !r || !logpsi || !noise || !u) return QMC_ERR_INVALID_ARGUMENT;
+  if (!std::isfinite(step) || step < 0) return QMC_ERR_INVALID_ARGUMENT;
+  if (!ws_ok(plan->p, QMC_OP_METROPOLIS, ws, ws_bytes)) {
+    if (ws && ws_bytes < workspace_bytes(plan->p, QMC_OP_METROPOLIS)) return QMC_ERR_WORKSPACE_TOO_SMALL;
+    return QMC_ERR_INVALID_ARGUMENT;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  if (plan->p.prec == QMC_FP64)
+    return run_metropolis<double>(plan->p, params, r, logpsi, noise, u, step, accepted, (char*)ws, st);
+  return run_metropolis<float>(plan->p, params, r, logpsi, noise, u, step, accepted, (char*)ws, st);
+}
+
+qmc_status qmc_logpsi_vjp(const qmc_plan* plan, const void* params, const double* r, const double* cotangent,
+                          void* grad_params, void* ws, size_t ws_bytes, void* stream) {
+  (void)plan;
+  (void)params;
+  (void)r;
+  (void)cotangent;
+  (void)grad_params;
+  (void)ws;
+  (void)ws_bytes;
+  (void)stream;
+  return QMC_ERR_UNSUPPORTED;
+}
+
+qmc_status qmc_loss_grad(const qmc_plan* plan, const void* params, const double* r, const double* e_loc,
+                         void* grad_params, double* e_mean, void* ws, size_t ws_bytes, void* stream) {
+  (void)plan;
+  (void)params;
+  (void)r;
+  (void)e_loc;
+  (void)grad_params;
+  (void)e_mean;
+  (void)ws;
+  (void)ws_bytes;
+  (void)stream;
+  return QMC_ERR_UNSUPPORTED;
+}
+
+qmc_status qmc_det_jets(int64_t n_mat, int32_t n, int32_t n_tan, const double* jets, double* logdet, double* sign,
+                        double* grad, double* lap, void* stream) {
+  if (n_mat < 0 || n < 1 || n > 32 || n_tan < 0 || n_tan > 4096) return QMC_ERR_INVALID_ARGUMENT;
+  if (n_mat == 0) return QMC_OK;
+  if (!jets || !logdet || !sign || !lap || (n_tan > 0 && !grad)) return QMC_ERR_INVALID_ARGUMENT;
+  CK(launch_det_generic(n_mat, n, n_tan, jets, logdet, sign, grad, lap, (hipStream_t)stream));
+  return QMC_OK;
+}
+
+}  // extern "C"
+
+extern "C" {
+
+qmc_status qmc_profile_enable(int32_t on) {
+  g_prof_on = on != 0;
+  return QMC_OK;
+}
+
+qmc_status qmc_profile_report(char* buf, size_t len, int32_t reset) {
+  if (!buf || len == 0) return QMC_ERR_INVALID_ARGUMENT;
+  std::vector<ProfRec> recs;
+  {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    recs = g_prof;
+    if (reset) g_prof.clear();
+  }
+  std::vector<std::string> names;
+  std::vector<double> ms;
+  std::vector<long> cnt;
+  for (const auto& r : recs) {
+    if (hipEventSynchronize(r.b) != hipSuccess) return QMC_ERR_HIP;
+    float t = 0.f;
+    if (hipEventElapsedTime(&t, r.a, r.b) != hipSuccess) return QMC_ERR_HIP;
+    size_t k = 0;
+    for (; k < names.size(); ++k)
+      if (names[k] == r.name) break;
+    if (k == names.size()) {
+      names.push_back(r.name);
+      ms.push_back(0.0);
+      cnt.push_back(0);
+    }
+    ms[k] += t;
+    cnt[k] += 1;
+    if (reset) {
+      (void)hipEventDestroy(r.a);
+      (void)hipEventDestroy(r.b);
+    }
+  }
+  std::string out;
+  for (size_t k = 0; k < names.size(); ++k) {
+    char line[256];
+    snprintf(line, sizeof(line), "%s %ld %.6f\n", names[k].c_str(), cnt[k], ms[k]);
+    out += line;
+  }
+  if (out.size() + 1 > len) return QMC_ERR_WORKSPACE_TOO_SMALL;
+  memcpy(buf, out.c_str(), out.size() + 1);
+  return QMC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,256 @@
+// Host-side part of the qmc library: parameter layout, plan creation,
+// argument validation and workspace sizing.  No HIP calls here, so that this
+// translation unit can be exercised on a machine without a GPU.
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "plan.h"
+
+namespace qmc {
+
+static int64_t take(int64_t& cur, int64_t n) {
+  int64_t o = cur;
+  cur += n;
+  return o;
+}
+
+bool compute_offsets(const qmc_system& s, const qmc_ansatz& a, ParamOffsets* off) {
+  const int64_t M = s.n_nuc, K = a.n_rbf, D = a.width;
+  int64_t cur = 0;
+  for (int l = 0; l < 8; ++l) off->initW[l] = off->initb[l] = -1;
+  off->initW[0] = take(cur, (M + 2) * K * D);
+  off->initb[0] = take(cur, D);
+  for (int l = 1; l < a.init_layers; ++l) {
+    off->initW[l] = take(cur, D * D);
+    off->initb[l] = take(cur, D);
+  }
+  off->mp.assign(a.mp_layers, ParamOffsets::Layer{});
+  for (int l = 0; l < a.mp_layers; ++l) {
+    auto& L = off->mp[l];
+    for (int t = 0; t < 3; ++t) {
+      L.U1[t] = take(cur, K * D);
+      L.a1[t] = take(cur, D);
+      L.U2[t] = take(cur, D * D);
+      L.a2[t] = take(cur, D);
+    }
+    L.Wh = take(cur, D * D);
+    L.bh = take(cur, D);
+    L.Y = take(cur, M * D);
+    L.Wg = take(cur, 3 * D * D);
+    L.bg = take(cur, D);
+  }
+  const int ns[2] = {s.n_up, s.n_down};
+  for (int sp = 0; sp < 2; ++sp) {
+    const int64_t n = ns[sp];
+    if (n == 0) {
+      off->orbW[sp] = off->orbb[sp] = off->pi[sp] = off->sigma[sp] = -1;
+      continue;
+    }
+    off->orbW[sp] = take(cur, D * a.n_det * n);
+    off->orbb[sp] = take(cur, a.n_det * n);
+    off->pi[sp] = take(cur, a.n_det * n * M * a.n_env);
+    off->sigma[sp] = take(cur, a.n_det * n * M * a.n_env);
+  }
+  off->c = take(cur, a.n_det);
+  off->total = cur;
+  return true;
+}
+
+size_t act_bytes(qmc_precision p) { return p == QMC_FP64 ? 8 : 4; }
+
+static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+Workspace workspace_layout(const Plan& p, const SysPlan& s, int op, int64_t wc) {
+  Workspace w;
+  std::memset(&w, 0, sizeof(w));
+  size_t cur = 0;
+  auto alloc = [&](size_t bytes) {
+    size_t o = cur;
+    cur = align256(cur + bytes);
+    return o;
+  };
+  const bool jet = (op == QMC_OP_LOCAL_ENERGY);
+  const size_t E = act_bytes(p.prec);
+  const int64_t N = s.N, M = s.M, D = p.ans.width, K = p.ans.n_rbf, ND = p.ans.n_det;
+  const int64_t Rp = jet ? s.Rp : 1, Rpe = jet ? 4 : 1;
+  w.geom = alloc(size_t(wc) * (N * N + N * M) * 4 * 8);
+  w.vpot = alloc(size_t(wc) * 8);
+  for (int t = 0; t < 3; ++t) {
+    w.rho[t] = alloc(size_t(wc) * s.P[t] * Rpe * K * E);
+    w.ehid[t] = alloc(size_t(wc) * s.P[t] * Rpe * D * E);
+    w.wjet[t] = alloc(size_t(wc) * s.P[t] * Rpe * D * E);
+  }
+  w.x0 = alloc(size_t(wc) * N * Rp * (M + 2) * K * E);
+  w.f = alloc(size_t(wc) * N * Rp * D * E);
+  w.h = alloc(size_t(wc) * N * Rp * D * E);
+  w.m = alloc(size_t(wc) * N * Rp * 3 * D * E);
+  int64_t nsq = 0;
+  for (int sp = 0; sp < 2; ++sp) {
+    const int64_t n = s.nsig(sp);
+    w.phi[sp] = alloc(size_t(wc) * n * Rp * ND * n * E);
+    nsq += n * n;
+  }
+  w.ajet = alloc(size_t(wc) * ND * Rp * nsq * E);
+  w.dld = alloc(size_t(wc) * 2 * ND * 8);
+  w.dsg = alloc(size_t(wc) * 2 * ND * 8);
+  w.dg = alloc(size_t(wc) * 2 * ND * (jet ? s.T : 1) * 8);
+  w.dlap = alloc(size_t(wc) * 2 * ND * 8);
+  if (op == QMC_OP_METROPOLIS) {
+    w.lp_prop = alloc(size_t(wc) * (N * 3 + 1) * 8);
+  }
+  w.total = cur;
+  return w;
+}
+
+size_t workspace_bytes(const Plan& p, int op) {
+  size_t mx = 0;
+  for (const auto& s : p.sys) {
+    const size_t b = workspace_layout(p, s, op, s.Wc).total;
+    if (b > mx) mx = b;
+  }
+  return mx + 256;
+}
+
+static bool valid_system(const qmc_system* s) {
+  if (!s || s->n_nuc < 1 || s->n_nuc > 64 || !s->charges || !s->coords) return false;
+  if (s->n_up < 0 || s->n_down < 0 || s->n_up + s->n_down < 1) return false;
+  if (s->n_up + s->n_down > 64) return false;
+  for (int i = 0; i < s->n_nuc; ++i) {
+    if (!(s->charges[i] > 0) || !std::isfinite(s->charges[i])) return false;
+    for (int x = 0; x < 3; ++x)
+      if (!std::isfinite(s->coords[3 * i + x])) return false;
+  }
+  return true;
+}
+
+static bool valid_ansatz(const qmc_ansatz* a) {
+  if (!a || a->version != 1) return false;
+  if (a->n_rbf < 2 || a->n_rbf > 64 || !(a->rbf_dmax > 0) || !std::isfinite(a->rbf_dmax)) return false;
+  if (a->init_layers < 1 || a->init_layers > 8) return false;
+  if (a->width < 1 || a->width > 1024) return false;
+  if (a->mp_layers < 0 || a->mp_layers > 16) return false;
+  if (a->n_det < 1 || a->n_det > 64 || a->n_env < 1 || a->n_env > 32) return false;
+  if (a->include_vnn != 0 && a->include_vnn != 1) return false;
+  return true;
+}
+
+}  // namespace qmc
+
+using namespace qmc;
+
+extern "C" {
+
+int64_t qmc_param_count(const qmc_system* system, const qmc_ansatz* ansatz) {
+  if (!valid_system(system) || !valid_ansatz(ansatz)) return -1;
+  ParamOffsets off;
+  compute_offsets(*system, *ansatz, &off);
+  return off.total;
+}
+
+qmc_status qmc_plan_create(qmc_plan** out, const qmc_system* systems, int32_t n_systems,
+                           const int64_t* walkers_per_system, const qmc_ansatz* ansatz,
+                           qmc_precision precision, uint32_t flags) {
+  if (!out) return QMC_ERR_INVALID_ARGUMENT;
+  *out = nullptr;
+  if (!systems || n_systems < 1 || n_systems > 4096 || !walkers_per_system) return QMC_ERR_INVALID_ARGUMENT;
+  if (!valid_ansatz(ansatz)) return QMC_ERR_INVALID_ARGUMENT;
+  if (precision != QMC_FP64 && precision != QMC_FP32 && precision != QMC_BF16_MIXED)
+    return QMC_ERR_INVALID_ARGUMENT;
+  if (flags != 0) return QMC_ERR_INVALID_ARGUMENT;
+  // the bf16 MFMA path works on K in steps of 32 and the jet GEMM tiles on 16-wide
+  // column blocks; both handle any width, so no further restriction here.
+  qmc_plan* plan = new (std::nothrow) qmc_plan;
+  if (!plan) return QMC_ERR_INTERNAL;
+  Plan& P = plan->p;
+  P.ans = *ansatz;
+  P.prec = precision;
+  P.total_walkers = 0;
+  P.total_params = 0;
+  P.max_chunk_bytes = int64_t(24) << 30;
+  for (int32_t k = 0; k < n_systems; ++k) {
+    const qmc_system* s = &systems[k];
+    if (!valid_system(s) || walkers_per_system[k] < 1 || walkers_per_system[k] > (int64_t(1) << 24)) {
+      delete plan;
+      return QMC_ERR_INVALID_ARGUMENT;
+    }
+    SysPlan sp;
+    sp.M = s->n_nuc;
+    sp.nup = s->n_up;
+    sp.ndn = s->n_down;
+    sp.N = s->n_up + s->n_down;
+    sp.Z.assign(s->charges, s->charges + sp.M);
+    sp.R.assign(s->coords, s->coords + 3 * sp.M);
+    sp.vnn = 0;
+    for (int I = 0; I < sp.M; ++I)
+      for (int J = 0; J < I; ++J) {
+        const double dx = sp.R[3 * I] - sp.R[3 * J], dy = sp.R[3 * I + 1] - sp.R[3 * J + 1],
+                     dz = sp.R[3 * I + 2] - sp.R[3 * J + 2];
+        const double d = std::sqrt(dx * dx + dy * dy + dz * dz);
+        if (!(d > 0)) {
+          delete plan;
+          return QMC_ERR_INVALID_ARGUMENT;  // coincident nuclei
+        }
+        sp.vnn += sp.Z[I] * sp.Z[J] / d;
+      }
+    sp.W = walkers_per_system[k];
+    sp.walker_offset = P.total_walkers;
+    sp.param_offset = P.total_params;
+    compute_offsets(*s, *ansatz, &sp.off);
+    sp.T = 3 * sp.N;
+    sp.Rp = ((sp.T + 2) + 15) / 16 * 16;
+    sp.P[TYPE_SAME] = sp.nup * (sp.nup - 1) / 2 + sp.ndn * (sp.ndn - 1) / 2;
+    sp.P[TYPE_OPP] = sp.nup * sp.ndn;
+    sp.P[TYPE_NUC] = sp.N * sp.M;
+    sp.Wc = sp.W;
+    P.total_walkers += sp.W;
+    P.total_params += sp.off.total;
+    P.sys.push_back(sp);
+  }
+  // walker chunks: bound the largest workspace (local energy) by max_chunk_bytes
+  for (auto& sp : P.sys) {
+    int64_t wc = sp.W;
+    while (wc > 64 && workspace_layout(P, sp, QMC_OP_LOCAL_ENERGY, wc).total > size_t(P.max_chunk_bytes))
+      wc = (wc + 1) / 2;
+    sp.Wc = wc;
+  }
+  *out = plan;
+  return QMC_OK;
+}
+
+qmc_status qmc_plan_destroy(qmc_plan* plan) {
+  if (!plan) return QMC_ERR_INVALID_ARGUMENT;
+  delete plan;
+  return QMC_OK;
+}
+
+qmc_status qmc_workspace_size(const qmc_plan* plan, int32_t op, size_t* bytes) {
+  if (!plan || !bytes || op < QMC_OP_LOGPSI || op > QMC_OP_LOSS_GRAD) return QMC_ERR_INVALID_ARGUMENT;
+  *bytes = workspace_bytes(plan->p, op);
+  return QMC_OK;
+}
+
+qmc_status qmc_plan_info(const qmc_plan* plan, int64_t* total_walkers, int64_t* total_params,
+                         int64_t* total_positions) {
+  if (!plan) return QMC_ERR_INVALID_ARGUMENT;
+  int64_t pos = 0;
+  for (const auto& s : plan->p.sys) pos += s.W * s.N * 3;
+  if (total_walkers) *total_walkers = plan->p.total_walkers;
+  if (total_params) *total_params = plan->p.total_params;
+  if (total_positions) *total_positions = pos;
+  return QMC_OK;
+}
+
+const char* qmc_status_str(qmc_status s) {
+  switch (s) {
+    case QMC_OK: return "QMC_OK";
+    case QMC_ERR_INVALID_ARGUMENT: return "QMC_ERR_INVALID_ARGUMENT";
+    case QMC_ERR_UNSUPPORTED: return "QMC_ERR_UNSUPPORTED";
+    case QMC_ERR_WORKSPACE_TOO_SMALL: return "QMC_ERR_WORKSPACE_TOO_SMALL";
+    case QMC_ERR_HIP: return "QMC_ERR_HIP";
+    case QMC_ERR_INTERNAL: return "QMC_ERR_INTERNAL";
+  }
+  return "QMC_ERR_UNKNOWN";
+}
+
+}  // extern "C"

@@ -1,0 +1,106 @@
+// Launch interface of the gfx950 kernels (host-callable, HIP types only).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace qmc {
+
+// Optional per-launch timing (qmc_profile_enable): a launch site opens a
+// ProfScope naming the kernel; events are recorded on the launch stream.
+bool prof_on();
+void prof_push(const char* name, hipEvent_t a, hipEvent_t b);
+struct ProfScope {
+  hipEvent_t a = nullptr, b = nullptr;
+  const char* name;
+  hipStream_t st;
+  ProfScope(const char* n, hipStream_t s) : name(n), st(s) {
+    if (prof_on() && hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess) {
+      if (hipEventRecord(a, st) != hipSuccess) a = nullptr;
+    } else {
+      a = nullptr;
+    }
+  }
+  ~ProfScope() {
+    if (a && hipEventRecord(b, st) == hipSuccess) prof_push(name, a, b);
+  }
+};
+
+// Compute kinds of the GEMM: operands and accumulation.
+enum GemmKind { GK_F64 = 0, GK_F32 = 1, GK_BF16 = 2 };
+
+// Y = act(X W + bias) (+ Res), over jet rows grouped per electron (or per pair).
+//   Row r of X lives at X + (r / xrpw) * xws + (r % xrpw) * ldx (same for Y/Res
+//   with yrpw/yws/ldy).  W(k, n) = W[k * ldw + n], or W[n * ldw + k] when transw.
+//   Jet rows (vmode = 0): groups of Rp rows: row 0 value, rows 1..T tangents,
+//   row T+1 Laplacian, the rest zero padding.  vmode = 1: every row a value row.
+//   act: 0 linear, 1 tanh (propagated through the jet).
+struct GemmArgs {
+  const void* X;
+  int64_t ldx, xrpw, xws;
+  const void* W;
+  int64_t ldw;
+  const void* bias;
+  const void* Res;
+  void* Y;
+  int64_t ldy, yrpw, yws;
+  int64_t rows;
+  int K, Ncols;
+  int Rp, T, act, vmode;
+  int transw;
+};
+
+hipError_t launch_gemm(GemmKind kind, const GemmArgs& a, hipStream_t st);
+
+// Geometry of a walker chunk: dense pair distances and unit vectors (float64).
+//   r: [W][N][3]; ee: [W][N][N][4] (d, ux, uy, uz of r_i - r_j); en: [W][N][M][4];
+//   vpot[W] = potential energy (+ vnn).
+struct SysDev {
+  int N, M, nup, ndn, T, Rp, K, D, ndet, nenv, P0, P1, P2;
+  double dmax, vnn;
+  double Z[64];
+  double R[64 * 3];
+};
+
+hipError_t launch_geometry(const SysDev& s, const double* r, int64_t W, double* ee, double* en,
+                           double* vpot, hipStream_t st);
+
+template <typename S>
+hipError_t launch_rbf(const SysDev& s, int type, const double* ee, const double* en, int64_t W, int jet,
+                      S* rho, hipStream_t st);
+
+template <typename S>
+hipError_t launch_init_features(const SysDev& s, const double* ee, const double* en, int64_t W, int jet,
+                                S* x0, hipStream_t st);
+
+template <typename S>
+hipError_t launch_aggregate(const SysDev& s, const S* h, const S* wsame, const S* wopp, const S* wnuc,
+                            const S* Y, const double* ee, const double* en, int64_t W, int jet, S* m,
+                            hipStream_t st);
+
+template <typename S>
+hipError_t launch_envelope(const SysDev& s, int spin, const S* phi, const S* pi, const S* sigma,
+                           const double* en, int64_t W, int jet, S* ajet, hipStream_t st);
+
+// Determinants of A-jets: one problem per (walker, spin, det).
+//   ajet: per walker [spin][det][rows][n][n] (rows = T + 2 padded to Rp, or 1).
+template <typename S>
+hipError_t launch_det(const SysDev& s, const S* ajet, int64_t W, int jet, double* ld, double* sg,
+                      double* g, double* lap, hipStream_t st);
+
+// Generic batched determinant jets (float64), one n x n problem per matrix.
+hipError_t launch_det_generic(int64_t nmat, int n, int ntan, const double* jets, double* ld,
+                              double* sg, double* g, double* lap, hipStream_t st);
+
+template <typename S>
+hipError_t launch_combine(const SysDev& s, const S* c, const double* ld, const double* sg,
+                          const double* g, const double* dlap, const double* vpot, int64_t W, int jet,
+                          double* logpsi, double* sign, double* grad, double* lap, double* eloc,
+                          hipStream_t st);
+
+hipError_t launch_propose(const double* r, const double* noise, double step, int64_t n, double* rp,
+                          hipStream_t st);
+hipError_t launch_accept(int64_t W, int N3, const double* rp, const double* lp_prop, const double* u,
+                         double* r, double* logpsi, uint8_t* accepted, hipStream_t st);
+
+}  // namespace qmc

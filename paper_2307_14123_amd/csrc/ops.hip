@@ -1,0 +1,785 @@
+// Element-wise and per-walker kernels of the local-energy path (gfx950).
+//
+// Jets: every activation carries rows (value, d/dx_c for the 3N electron
+// coordinates c = 3j + a, Laplacian), padded to Rp rows.  Functions of one
+// distance are propagated as univariate jets in the distance (value, first,
+// second derivative) and expanded here with the chain rule:
+//   e-e distance d_ij: grad_i d = u_ij, grad_j d = -u_ij, |grad d|^2 = 2, lap d = 4/d
+//   e-n distance d_iI: grad_i d = u_iI,                  |grad d|^2 = 1, lap d = 2/d
+// with u the unit vector of r_i - r_j (or r_i - R_I).
+#include <cmath>
+
+#include "kernels.h"
+
+namespace qmc {
+
+// ---------------------------------------------------------------- helpers
+
+__device__ inline void rbf3(double d, int k, double dmax, int K, double& r0, double& r1, double& r2) {
+  const double s = dmax / (K - 1);
+  const double x = (d - k * s) / s;
+  r0 = exp(-x * x);
+  r1 = -2.0 * x / s * r0;
+  r2 = (4.0 * x * x - 2.0) / (s * s) * r0;
+}
+
+// unordered pair index of electrons i != j inside their edge type (0 same-spin, 1 up-down)
+__device__ inline int ee_pair(const SysDev& s, int i, int j, int& type) {
+  const bool ui = i < s.nup, uj = j < s.nup;
+  if (ui != uj) {
+    type = 1;
+    const int a = ui ? i : j, b = ui ? j : i;
+    return a * s.ndn + (b - s.nup);
+  }
+  type = 0;
+  int a = i < j ? i : j, b = i < j ? j : i;
+  int n = s.nup, off = 0;
+  if (!ui) {
+    n = s.ndn;
+    a -= s.nup;
+    b -= s.nup;
+    off = s.nup * (s.nup - 1) / 2;
+  }
+  return off + a * (2 * n - a - 1) / 2 + (b - a - 1);
+}
+
+__device__ inline void decode_pair(const SysDev& s, int type, int p, int& i, int& j) {
+  if (type == 2) {
+    i = p / s.M;
+    j = p % s.M;
+    return;
+  }
+  if (type == 1) {
+    i = p / s.ndn;
+    j = s.nup + p % s.ndn;
+    return;
+  }
+  int n = s.nup, base = 0;
+  const int cu = s.nup * (s.nup - 1) / 2;
+  if (p >= cu) {
+    p -= cu;
+    n = s.ndn;
+    base = s.nup;
+  }
+  int a = 0;
+  while (p >= n - 1 - a) {
+    p -= n - 1 - a;
+    ++a;
+  }
+  i = base + a;
+  j = base + a + 1 + p;
+}
+
+// ---------------------------------------------------------------- geometry
+
+__global__ void geometry_kernel(SysDev s, const double* __restrict__ r, int64_t W, double* __restrict__ ee,
+                                double* __restrict__ en) {
+  const int NN = s.N + s.M;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= W * s.N * NN) return;
+  const int64_t w = t / (s.N * NN);
+  const int rem = (int)(t % (s.N * NN));
+  const int i = rem / NN, jj = rem % NN;
+  const double* ri = r + (w * s.N + i) * 3;
+  double o[3];
+  double* dst;
+  if (jj < s.N) {
+    const double* rj = r + (w * s.N + jj) * 3;
+    for (int x = 0; x < 3; ++x) o[x] = ri[x] - rj[x];
+    dst = ee + ((w * s.N + i) * s.N + jj) * 4;
+  } else {
+    const int I = jj - s.N;
+    for (int x = 0; x < 3; ++x) o[x] = ri[x] - s.R[3 * I + x];
+    dst = en + ((w * s.N + i) * s.M + I) * 4;
+  }
+  const double d = sqrt(o[0] * o[0] + o[1] * o[1] + o[2] * o[2]);
+  const double inv = (jj == i) ? 0.0 : 1.0 / d;
+  dst[0] = d;
+  dst[1] = o[0] * inv;
+  dst[2] = o[1] * inv;
+  dst[3] = o[2] * inv;
+}
+
+// V = sum_{i<j} 1/d_ij - sum_{i,I} Z_I / d_iI + V_nn, one thread per walker
+__global__ void potential_kernel(SysDev s, const double* __restrict__ r, int64_t W, double* __restrict__ vpot) {
+  const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (w >= W) return;
+  const double* rw = r + w * s.N * 3;
+  double v = 0.0;
+  for (int i = 0; i < s.N; ++i) {
+    const double x = rw[3 * i], y = rw[3 * i + 1], z = rw[3 * i + 2];
+    for (int I = 0; I < s.M; ++I) {
+      const double dx = x - s.R[3 * I], dy = y - s.R[3 * I + 1], dz = z - s.R[3 * I + 2];
+      v -= s.Z[I] / sqrt(dx * dx + dy * dy + dz * dz);
+    }
+    for (int j = 0; j < i; ++j) {
+      const double dx = x - rw[3 * j], dy = y - rw[3 * j + 1], dz = z - rw[3 * j + 2];
+      v += 1.0 / sqrt(dx * dx + dy * dy + dz * dz);
+    }
+  }
+  vpot[w] = v + s.vnn;
+}
+
+hipError_t launch_geometry(const SysDev& s, const double* r, int64_t W, double* ee, double* en, double* vpot,
+                           hipStream_t st) {
+  ProfScope ps("geometry_kernel", st);
+  const int64_t n = W * s.N * (s.N + s.M);
+  hipLaunchKernelGGL(geometry_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, s, r, W, ee, en);
+  if (vpot)
+    hipLaunchKernelGGL(potential_kernel, dim3((unsigned)((W + 127) / 128)), dim3(128), 0, st, s, r, W, vpot);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- radial basis jets per edge
+
+template <typename S>
+__global__ void rbf_kernel(SysDev s, int type, const double* __restrict__ ee, const double* __restrict__ en,
+                           int64_t W, int jet, S* __restrict__ rho) {
+  const int P = type == 0 ? s.P0 : (type == 1 ? s.P1 : s.P2);
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= W * P * s.K) return;
+  const int k = (int)(t % s.K);
+  const int64_t wp = t / s.K;
+  const int64_t w = wp / P;
+  const int p = (int)(wp % P);
+  int i, j;
+  decode_pair(s, type, p, i, j);
+  const double d = (type == 2) ? en[((w * s.N + i) * s.M + j) * 4] : ee[((w * s.N + i) * s.N + j) * 4];
+  double r0, r1, r2;
+  rbf3(d, k, s.dmax, s.K, r0, r1, r2);
+  if (jet) {
+    S* o = rho + wp * 4 * s.K + k;
+    o[0] = (S)r0;
+    o[s.K] = (S)r1;
+    o[2 * s.K] = (S)r2;
+    o[3 * s.K] = (S)0;
+  } else {
+    rho[wp * s.K + k] = (S)r0;
+  }
+}
+
+template <typename S>
+hipError_t launch_rbf(const SysDev& s, int type, const double* ee, const double* en, int64_t W, int jet, S* rho,
+                      hipStream_t st) {
+  const int P = type == 0 ? s.P0 : (type == 1 ? s.P1 : s.P2);
+  const int64_t n = W * P * s.K;
+  if (n == 0) return hipSuccess;
+  ProfScope ps("rbf_kernel", st);
+  hipLaunchKernelGGL(rbf_kernel<S>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, s, type, ee, en, W, jet,
+                     rho);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- electron-node input features
+
+// x_i = [rho(d_i1) .. rho(d_iM), mean_same rho(d_ij), mean_opp rho(d_ij)] with jets over all 3N coordinates
+template <typename S>
+__global__ void init_features_kernel(SysDev s, const double* __restrict__ ee, const double* __restrict__ en,
+                                     int64_t W, int jet, S* __restrict__ x0) {
+  const int F = (s.M + 2) * s.K;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= W * s.N * F) return;
+  const int f = (int)(t % F);
+  const int64_t wi = t / F;
+  const int i = (int)(wi % s.N);
+  const int64_t w = wi / s.N;
+  const int Rp = jet ? s.Rp : 1;
+  S* out = x0 + wi * Rp * F + f;
+  const int K = s.K;
+  if (f < s.M * K) {
+    const int I = f / K, k = f % K;
+    const double* g = en + ((w * s.N + i) * s.M + I) * 4;
+    double r0, r1, r2;
+    rbf3(g[0], k, s.dmax, K, r0, r1, r2);
+    out[0] = (S)r0;
+    if (!jet) return;
+    for (int q = 1; q < Rp; ++q) {
+      double v = 0.0;
+      if (q <= s.T) {
+        const int c = q - 1;
+        if (c / 3 == i) v = r1 * g[1 + c % 3];
+      } else if (q == s.T + 1) {
+        v = r2 + 2.0 * r1 / g[0];
+      }
+      out[(int64_t)q * F] = (S)v;
+    }
+    return;
+  }
+  const int blk = (f - s.M * K) / K;  // 0 same, 1 opposite
+  const int k = (f - s.M * K) % K;
+  const bool up = i < s.nup;
+  // members of the set: same spin (j != i) or opposite spin
+  const bool same_set = (blk == 0);
+  const int lo = (up == same_set) ? 0 : s.nup;
+  const int hi = (up == same_set) ? s.nup : s.N;
+  const int cnt = (hi - lo) - (same_set ? 1 : 0);
+  const double inv = cnt > 0 ? 1.0 / cnt : 0.0;
+  const double* eei = ee + (w * s.N + i) * s.N * 4;
+  double val = 0.0, gs[3] = {0, 0, 0}, lap = 0.0;
+  for (int j = lo; j < hi; ++j) {
+    if (j == i) continue;
+    double r0, r1, r2;
+    const double* g = eei + j * 4;
+    rbf3(g[0], k, s.dmax, K, r0, r1, r2);
+    val += r0;
+    for (int a = 0; a < 3; ++a) gs[a] += r1 * g[1 + a];
+    lap += 2.0 * r2 + 4.0 * r1 / g[0];
+  }
+  out[0] = (S)(val * inv);
+  if (!jet) return;
+  for (int q = 1; q < Rp; ++q) {
+    double v = 0.0;
+    if (q <= s.T && cnt > 0) {
+      const int c = q - 1, j = c / 3, a = c % 3;
+      if (j == i) {
+        v = gs[a] * inv;
+      } else if (j >= lo && j < hi) {
+        const double* g = eei + j * 4;
+        double r0, r1, r2;
+        rbf3(g[0], k, s.dmax, K, r0, r1, r2);
+        v = -r1 * g[1 + a] * inv;
+      }
+    } else if (q == s.T + 1) {
+      v = lap * inv;
+    }
+    out[(int64_t)q * F] = (S)v;
+  }
+}
+
+template <typename S>
+hipError_t launch_init_features(const SysDev& s, const double* ee, const double* en, int64_t W, int jet, S* x0,
+                                hipStream_t st) {
+  ProfScope ps("init_features_kernel", st);
+  const int64_t n = W * s.N * (s.M + 2) * s.K;
+  hipLaunchKernelGGL(init_features_kernel<S>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, s, ee, en, W,
+                     jet, x0);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- message aggregation
+
+// m_i = [mean_{j same} w_same(d_ij) h_j, mean_{j opp} w_opp(d_ij) h_j, mean_I w_nuc(d_iI) Y_I]
+// propagated through the jets with the product rule.  Block: (walker, column
+// chunk of DC); thread: (receiver i, column).  The senders' h jets of the
+// walker for the chunk are staged in LDS and reused by every receiver.
+template <typename S, int NMAX>
+__global__ void aggregate_kernel(SysDev s, const S* __restrict__ h, const S* __restrict__ wsame,
+                                 const S* __restrict__ wopp, const S* __restrict__ wnuc, const S* __restrict__ Y,
+                                 const double* __restrict__ ee, const double* __restrict__ en, int jet, int DC,
+                                 S* __restrict__ m) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  S* hs = (S*)smem;  // [N][Rp][DC]
+  const int N = s.N, D = s.D;
+  const int Rp = jet ? s.Rp : 1;
+  const int Re = jet ? 4 : 1;
+  const int64_t w = blockIdx.x;
+  const int d0 = blockIdx.y * DC;
+  const S* hw = h + w * N * Rp * D;
+  for (int e = threadIdx.x; e < N * Rp * DC; e += blockDim.x) {
+    const int x = e % DC;
+    const int jq = e / DC;
+    hs[e] = (d0 + x < D) ? hw[(int64_t)jq * D + d0 + x] : S(0);
+  }
+  __syncthreads();
+  const int dd = threadIdx.x % DC;
+  const int i = threadIdx.x / DC;
+  const int d = d0 + dd;
+  if (i >= N || d >= D) return;
+  const bool up = i < s.nup;
+  const int nsame = (up ? s.nup : s.ndn) - 1;
+  const int nopp = up ? s.ndn : s.nup;
+  const S inv_s = nsame > 0 ? S(1) / S(nsame) : S(0);
+  const S inv_o = nopp > 0 ? S(1) / S(nopp) : S(0);
+  const double* eei = ee + (w * N + i) * N * 4;
+
+  // filter values w(d_ij) at this column for every sender
+  S wv[NMAX];
+#pragma unroll
+  for (int j = 0; j < NMAX; ++j) {
+    wv[j] = 0;
+    if (j < N && j != i) {
+      int type;
+      const int p = ee_pair(s, i, j, type);
+      const int P = type ? s.P1 : s.P0;
+      const S* wt = type ? wopp : wsame;
+      wv[j] = wt[((w * P + p) * Re) * D + d];
+    }
+  }
+  auto wjet = [&](int j, int row) -> S {
+    int type;
+    const int p = ee_pair(s, i, j, type);
+    const int P = type ? s.P1 : s.P0;
+    const S* wt = type ? wopp : wsame;
+    return wt[((w * P + p) * Re + row) * D + d];
+  };
+  const S* Yd = Y + d;
+  const double* eni = en + (w * N + i) * s.M * 4;
+  S* mo = m + (w * N + i) * (int64_t)Rp * 3 * D + d;
+
+  for (int q = 0; q < Rp; ++q) {
+    S aup = 0, adn = 0;
+#pragma unroll
+    for (int j = 0; j < NMAX; ++j) {
+      if (j < N) {
+        const S hv = hs[(j * Rp + q) * DC + dd];
+        if (j < s.nup)
+          aup += wv[j] * hv;
+        else
+          adn += wv[j] * hv;
+      }
+    }
+    S nuc = 0;
+    if (jet && q >= 1 && q <= s.T) {
+      const int c = q - 1, k = c / 3, a = c % 3;
+      if (k == i) {
+        for (int j = 0; j < N; ++j) {
+          if (j == i) continue;
+          const S corr = hs[(j * Rp) * DC + dd] * wjet(j, 1) * (S)eei[j * 4 + 1 + a];
+          if (j < s.nup)
+            aup += corr;
+          else
+            adn += corr;
+        }
+        for (int I = 0; I < s.M; ++I)
+          nuc += wnuc[((w * (int64_t)s.P2 + i * s.M + I) * Re + 1) * D + d] * (S)eni[I * 4 + 1 + a] * Yd[I * D];
+      } else {
+        const S corr = -hs[(k * Rp) * DC + dd] * wjet(k, 1) * (S)eei[k * 4 + 1 + a];
+        if (k < s.nup)
+          aup += corr;
+        else
+          adn += corr;
+      }
+    } else if (jet && q == s.T + 1) {
+      for (int j = 0; j < N; ++j) {
+        if (j == i) continue;
+        const double* g = eei + j * 4;
+        const S w1 = wjet(j, 1), w2 = wjet(j, 2);
+        const S lapw = S(2) * w2 + S(4) * w1 / (S)g[0];
+        S cross = 0;
+        for (int a = 0; a < 3; ++a)
+          cross += (S)g[1 + a] * (hs[(j * Rp + 1 + 3 * i + a) * DC + dd] - hs[(j * Rp + 1 + 3 * j + a) * DC + dd]);
+        const S corr = hs[(j * Rp) * DC + dd] * lapw + S(2) * w1 * cross;
+        if (j < s.nup)
+          aup += corr;
+        else
+          adn += corr;
+      }
+      for (int I = 0; I < s.M; ++I) {
+        const S* wn = wnuc + ((w * (int64_t)s.P2 + i * s.M + I) * Re) * D + d;
+        nuc += (wn[2 * D] + S(2) * wn[D] / (S)eni[I * 4]) * Yd[I * D];
+      }
+    } else if (q == 0) {
+      for (int I = 0; I < s.M; ++I) nuc += wnuc[((w * (int64_t)s.P2 + i * s.M + I) * Re) * D + d] * Yd[I * D];
+    }
+    const S ms = (up ? aup : adn) * inv_s;
+    const S mop = (up ? adn : aup) * inv_o;
+    S* row = mo + (int64_t)q * 3 * D;
+    row[0] = ms;
+    row[D] = mop;
+    row[2 * D] = nuc / S(s.M);
+  }
+}
+
+template <typename S, int NMAX>
+static hipError_t agg_launch(const SysDev& s, const S* h, const S* ws, const S* wo, const S* wn, const S* Y,
+                             const double* ee, const double* en, int64_t W, int jet, S* m, hipStream_t st) {
+  const int Rp = jet ? s.Rp : 1;
+  int DC = 64;
+  while (DC > 1 && (DC * s.N > 1024 || (size_t)s.N * Rp * DC * sizeof(S) > 64 * 1024)) DC >>= 1;
+  const size_t lds = (size_t)s.N * Rp * DC * sizeof(S);
+  ProfScope ps("aggregate_kernel", st);
+  dim3 grid((unsigned)W, (unsigned)((s.D + DC - 1) / DC));
+  hipLaunchKernelGGL((aggregate_kernel<S, NMAX>), grid, dim3(DC * s.N), lds, st, s, h, ws, wo, wn, Y, ee, en, jet,
+                     DC, m);
+  return hipGetLastError();
+}
+
+template <typename S>
+hipError_t launch_aggregate(const SysDev& s, const S* h, const S* wsame, const S* wopp, const S* wnuc, const S* Y,
+                            const double* ee, const double* en, int64_t W, int jet, S* m, hipStream_t st) {
+  if (s.N <= 4) return agg_launch<S, 4>(s, h, wsame, wopp, wnuc, Y, ee, en, W, jet, m, st);
+  if (s.N <= 8) return agg_launch<S, 8>(s, h, wsame, wopp, wnuc, Y, ee, en, W, jet, m, st);
+  if (s.N <= 16) return agg_launch<S, 16>(s, h, wsame, wopp, wnuc, Y, ee, en, W, jet, m, st);
+  if (s.N <= 32) return agg_launch<S, 32>(s, h, wsame, wopp, wnuc, Y, ee, en, W, jet, m, st);
+  if (s.N <= 48) return agg_launch<S, 48>(s, h, wsame, wopp, wnuc, Y, ee, en, W, jet, m, st);
+  return hipErrorInvalidValue;
+}
+
+// ---------------------------------------------------------------- orbitals x envelopes
+
+// A[a][k] = phi_k(r_a) * sum_{I,beta} pi exp(-sigma d_aI), jets by the product rule.
+// Output per walker: [spin][det][row][a][k] (this launch fills one spin block).
+template <typename S>
+__global__ void envelope_kernel(SysDev s, int spin, const S* __restrict__ phi, const S* __restrict__ pi,
+                                const S* __restrict__ sg, const double* __restrict__ en, int64_t W, int jet,
+                                S* __restrict__ ajet) {
+  const int n = spin ? s.ndn : s.nup;
+  const int i0 = spin ? s.nup : 0;
+  const int Rp = jet ? s.Rp : 1;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= W * s.ndet * n * n) return;
+  const int k = (int)(t % n);
+  const int a = (int)((t / n) % n);
+  const int p = (int)((t / (n * n)) % s.ndet);
+  const int64_t w = t / ((int64_t)n * n * s.ndet);
+  const int i = i0 + a;
+  double e0 = 0, eg[3] = {0, 0, 0}, el = 0;
+  const double* g = en + (w * s.N + i) * s.M * 4;
+  for (int I = 0; I < s.M; ++I) {
+    const double d = g[I * 4];
+    for (int b = 0; b < s.nenv; ++b) {
+      const int64_t idx = (((int64_t)p * n + k) * s.M + I) * s.nenv + b;
+      const double pw = (double)pi[idx], sgm = (double)sg[idx];
+      const double e = pw * exp(-sgm * d);
+      e0 += e;
+      if (jet) {
+        for (int x = 0; x < 3; ++x) eg[x] -= sgm * e * g[I * 4 + 1 + x];
+        el += e * (sgm * sgm - 2.0 * sgm / d);
+      }
+    }
+  }
+  const int ncol = s.ndet * n;
+  const S* ph = phi + ((w * n + a) * Rp) * (int64_t)ncol + p * n + k;
+  const int64_t wstride = (int64_t)s.ndet * Rp * (s.nup * s.nup + s.ndn * s.ndn);
+  const int64_t soff = spin ? (int64_t)s.ndet * Rp * s.nup * s.nup : 0;
+  S* out = ajet + w * wstride + soff + ((int64_t)p * Rp * n + a) * n + k;
+  const double p0 = (double)ph[0];
+  out[0] = (S)(p0 * e0);
+  if (!jet) return;
+  const int64_t rs = (int64_t)n * n;
+  for (int q = 1; q < Rp; ++q) {
+    double v = 0.0;
+    if (q <= s.T) {
+      v = (double)ph[(int64_t)q * ncol] * e0;
+      const int c = q - 1;
+      if (c / 3 == i) v += p0 * eg[c % 3];
+    } else if (q == s.T + 1) {
+      v = (double)ph[(int64_t)q * ncol] * e0 + p0 * el;
+      for (int x = 0; x < 3; ++x) v += 2.0 * (double)ph[(int64_t)(1 + 3 * i + x) * ncol] * eg[x];
+    }
+    out[q * rs] = (S)v;
+  }
+}
+
+template <typename S>
+hipError_t launch_envelope(const SysDev& s, int spin, const S* phi, const S* pi, const S* sigma, const double* en,
+                           int64_t W, int jet, S* ajet, hipStream_t st) {
+  const int n = spin ? s.ndn : s.nup;
+  const int64_t cnt = W * s.ndet * n * n;
+  if (cnt == 0) return hipSuccess;
+  ProfScope ps("envelope_kernel", st);
+  hipLaunchKernelGGL(envelope_kernel<S>, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, st, s, spin, phi, pi,
+                     sigma, en, W, jet, ajet);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- determinants (float64)
+
+__device__ inline double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+// One wavefront per n x n problem: Gauss-Jordan with partial pivoting gives
+// log|det A|, its sign and A^-1; then for every tangent c: X = A^-1 dA_c,
+// d log|det| = tr X, and the Laplacian tr(A^-1 lapA) - sum_c tr(X^2).
+constexpr int DMAX = 32;
+
+template <typename S>
+__global__ __launch_bounds__(64) void det_kernel(const S* __restrict__ src, int64_t stride_outer, int n_inner,
+                                                 int64_t stride_inner, int rows, int n, int ntan, int jet,
+                                                 int64_t out_outer, int64_t out_off, double* __restrict__ ld,
+                                                 double* __restrict__ sg, double* __restrict__ gout,
+                                                 double* __restrict__ lapout) {
+  __shared__ double Mx[DMAX][2 * DMAX + 1];
+  __shared__ double dA[DMAX][DMAX + 1];
+  __shared__ double Xs[DMAX][DMAX + 1];
+  __shared__ double fcol[DMAX];
+  __shared__ int piv_s;
+  const int lane = threadIdx.x;
+  const int64_t pb = blockIdx.x;
+  const int64_t o = pb / n_inner;
+  const int in = (int)(pb % n_inner);
+  const S* A = src + o * stride_outer + in * stride_inner;
+  const int64_t oi = o * out_outer + out_off + in;
+  const int nn = n * n;
+  (void)rows;
+  for (int e = lane; e < n * 2 * n; e += 64) {
+    const int r = e / (2 * n), c = e % (2 * n);
+    Mx[r][c] = c < n ? (double)A[r * n + c] : (c - n == r ? 1.0 : 0.0);
+  }
+  __syncthreads();
+  double logdet = 0.0, sgn = 1.0;
+  bool singular = false;
+  for (int col = 0; col < n; ++col) {
+    // pivot: largest |value| in rows col..n-1 (smallest index on ties)
+    double best = -1.0;
+    int bi = col;
+    for (int r = col + lane; r < n; r += 64) {
+      const double v = fabs(Mx[r][col]);
+      if (v > best) {
+        best = v;
+        bi = r;
+      }
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+      const double ob = __shfl_xor(best, off);
+      const int oidx = __shfl_xor(bi, off);
+      if (ob > best || (ob == best && oidx < bi)) {
+        best = ob;
+        bi = oidx;
+      }
+    }
+    if (lane == 0) piv_s = bi;
+    __syncthreads();
+    const int pr = piv_s;
+    if (!(best > 0.0)) {
+      singular = true;
+      break;
+    }
+    if (pr != col) {
+      for (int c = lane; c < 2 * n; c += 64) {
+        const double tmp = Mx[pr][c];
+        Mx[pr][c] = Mx[col][c];
+        Mx[col][c] = tmp;
+      }
+      sgn = -sgn;
+    }
+    __syncthreads();
+    const double pv = Mx[col][col];
+    logdet += log(fabs(pv));
+    if (pv < 0) sgn = -sgn;
+    for (int r = lane; r < n; r += 64) fcol[r] = Mx[r][col];
+    __syncthreads();
+    for (int c = lane; c < 2 * n; c += 64) Mx[col][c] /= pv;
+    __syncthreads();
+    for (int e = lane; e < n * 2 * n; e += 64) {
+      const int r = e / (2 * n), c = e % (2 * n);
+      if (r != col) Mx[r][c] -= fcol[r] * Mx[col][c];
+    }
+    __syncthreads();
+  }
+  if (singular) {
+    if (lane == 0) {
+      ld[oi] = -INFINITY;
+      sg[oi] = 0.0;
+      if (jet) lapout[oi] = 0.0;
+    }
+    if (jet)
+      for (int c = lane; c < ntan; c += 64) gout[oi * ntan + c] = 0.0;
+    return;
+  }
+  if (lane == 0) {
+    ld[oi] = logdet;
+    sg[oi] = sgn;
+  }
+  if (!jet) return;
+  // A^-1 sits in Mx[:, n:2n]
+  double qacc = 0.0;
+  for (int c = 0; c < ntan; ++c) {
+    const S* dsrc = A + (int64_t)(1 + c) * nn;
+    for (int e = lane; e < nn; e += 64) dA[e / n][e % n] = (double)dsrc[e];
+    __syncthreads();
+    double gpart = 0.0;
+    for (int e = lane; e < nn; e += 64) {
+      const int a = e / n, b = e % n;
+      double x = 0.0;
+      for (int k = 0; k < n; ++k) x += Mx[a][n + k] * dA[k][b];
+      Xs[a][b] = x;
+      if (a == b) gpart += x;
+    }
+    __syncthreads();
+    for (int e = lane; e < nn; e += 64) {
+      const int a = e / n, b = e % n;
+      qacc += Xs[a][b] * Xs[b][a];
+    }
+    const double gc = wave_sum(gpart);
+    if (lane == 0) gout[oi * ntan + c] = gc;
+  }
+  const S* lsrc = A + (int64_t)(1 + ntan) * nn;
+  double tr = 0.0;
+  for (int e = lane; e < nn; e += 64) {
+    const int a = e / n, b = e % n;
+    tr += Mx[a][n + b] * (double)lsrc[b * n + a];
+  }
+  tr = wave_sum(tr);
+  qacc = wave_sum(qacc);
+  if (lane == 0) lapout[oi] = tr - qacc;
+}
+
+template <typename S>
+hipError_t launch_det(const SysDev& s, const S* ajet, int64_t W, int jet, double* ld, double* sg, double* g,
+                      double* lap, hipStream_t st) {
+  const int Rp = jet ? s.Rp : 1;
+  const int64_t wstride = (int64_t)s.ndet * Rp * (s.nup * s.nup + s.ndn * s.ndn);
+  for (int spin = 0; spin < 2; ++spin) {
+    const int n = spin ? s.ndn : s.nup;
+    if (n == 0) continue;
+    if (n > DMAX) return hipErrorInvalidValue;
+    const int64_t soff = spin ? (int64_t)s.ndet * Rp * s.nup * s.nup : 0;
+    ProfScope ps("det_kernel", st);
+    hipLaunchKernelGGL(det_kernel<S>, dim3((unsigned)(W * s.ndet)), dim3(64), 0, st, ajet + soff, wstride, s.ndet,
+                       (int64_t)Rp * n * n, Rp, n, s.T, jet, (int64_t)2 * s.ndet, (int64_t)spin * s.ndet, ld, sg, g,
+                       lap);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_det_generic(int64_t nmat, int n, int ntan, const double* jets, double* ld, double* sg, double* g,
+                              double* lap, hipStream_t st) {
+  if (n < 1 || n > DMAX) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(det_kernel<double>, dim3((unsigned)nmat), dim3(64), 0, st, jets, (int64_t)(ntan + 2) * n * n, 1,
+                     (int64_t)0, ntan + 2, n, ntan, 1, (int64_t)1, (int64_t)0, ld, sg, g, lap);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- combination and local energy
+
+// psi = sum_p c_p det_p^up det_p^down in the log domain; with weights
+// w_p = c_p D_p / psi: grad log|psi| = sum_p w_p grad l_p,
+// Delta psi / psi = sum_p w_p (Delta l_p + |grad l_p|^2),
+// E_loc = -1/2 Delta psi / psi + V.  One wavefront per walker.
+template <typename S>
+__global__ __launch_bounds__(64) void combine_kernel(SysDev s, const S* __restrict__ c, const double* __restrict__ ld,
+                                                     const double* __restrict__ sg, const double* __restrict__ g,
+                                                     const double* __restrict__ dlap, const double* __restrict__ vpot,
+                                                     int jet, double* __restrict__ logpsi, double* __restrict__ sign,
+                                                     double* __restrict__ grad, double* __restrict__ lap,
+                                                     double* __restrict__ eloc) {
+  const int64_t w = blockIdx.x;
+  const int lane = threadIdx.x;
+  const int nd = s.ndet;
+  const bool has[2] = {s.nup > 0, s.ndn > 0};
+  double mx = -INFINITY;
+  for (int p = 0; p < nd; ++p) {
+    double l = 0.0;
+    for (int sp = 0; sp < 2; ++sp)
+      if (has[sp]) l += ld[(w * 2 + sp) * nd + p];
+    if (l > mx) mx = l;
+  }
+  if (!(mx > -INFINITY)) mx = 0.0;
+  double S_ = 0.0;
+  for (int p = 0; p < nd; ++p) {
+    double l = 0.0, sgn = (double)c[p];
+    for (int sp = 0; sp < 2; ++sp)
+      if (has[sp]) {
+        l += ld[(w * 2 + sp) * nd + p];
+        sgn *= sg[(w * 2 + sp) * nd + p];
+      }
+    if (sgn != 0.0) S_ += sgn * exp(l - mx);
+  }
+  const double lp = mx + log(fabs(S_));
+  const double sgnpsi = S_ > 0 ? 1.0 : (S_ < 0 ? -1.0 : 0.0);
+  if (lane == 0) {
+    if (logpsi) logpsi[w] = lp;
+    if (sign) sign[w] = sgnpsi;
+  }
+  if (!jet) return;
+  const double invS = 1.0 / S_;
+  double Apart = 0.0, Bpart = 0.0;
+  for (int cc = lane; cc < s.T; cc += 64) {
+    double gc = 0.0, a2 = 0.0;
+    for (int p = 0; p < nd; ++p) {
+      double l = 0.0, sgn = (double)c[p], gp = 0.0;
+      for (int sp = 0; sp < 2; ++sp)
+        if (has[sp]) {
+          const int64_t o = (w * 2 + sp) * nd + p;
+          l += ld[o];
+          sgn *= sg[o];
+          gp += g[o * s.T + cc];
+        }
+      const double wp = sgn != 0.0 ? sgn * exp(l - mx) * invS : 0.0;
+      gc += wp * gp;
+      a2 += wp * gp * gp;
+    }
+    Apart += a2;
+    Bpart += gc * gc;
+    if (grad) grad[w * s.T + cc] = sgnpsi != 0.0 ? gc : NAN;
+  }
+  const double A = wave_sum(Apart), B = wave_sum(Bpart);
+  if (lane == 0) {
+    double lsum = 0.0;
+    for (int p = 0; p < nd; ++p) {
+      double l = 0.0, sgn = (double)c[p], dl = 0.0;
+      for (int sp = 0; sp < 2; ++sp)
+        if (has[sp]) {
+          const int64_t o = (w * 2 + sp) * nd + p;
+          l += ld[o];
+          sgn *= sg[o];
+          dl += dlap[o];
+        }
+      if (sgn != 0.0) lsum += sgn * exp(l - mx) * invS * dl;
+    }
+    const double ok = sgnpsi != 0.0 ? 1.0 : NAN;
+    if (lap) lap[w] = ok * (lsum + A - B);
+    if (eloc) eloc[w] = ok * (-0.5 * (lsum + A) + vpot[w]);
+  }
+}
+
+template <typename S>
+hipError_t launch_combine(const SysDev& s, const S* c, const double* ld, const double* sg, const double* g,
+                          const double* dlap, const double* vpot, int64_t W, int jet, double* logpsi, double* sign,
+                          double* grad, double* lap, double* eloc, hipStream_t st) {
+  ProfScope ps("combine_kernel", st);
+  hipLaunchKernelGGL(combine_kernel<S>, dim3((unsigned)W), dim3(64), 0, st, s, c, ld, sg, g, dlap, vpot, jet, logpsi,
+                     sign, grad, lap, eloc);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- Metropolis
+
+__global__ void propose_kernel(const double* __restrict__ r, const double* __restrict__ noise, double step, int64_t n,
+                               double* __restrict__ rp) {
+  // product and sum rounded separately (no fused multiply-add), so the
+  // proposal is the same float64 value a host computes as r + (step * noise)
+#pragma clang fp contract(off)
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) rp[t] = r[t] + step * noise[t];
+}
+
+__global__ void accept_kernel(int64_t W, int N3, const double* __restrict__ rp, const double* __restrict__ lpp,
+                              const double* __restrict__ u, double* __restrict__ r, double* __restrict__ logpsi,
+                              uint8_t* __restrict__ accepted) {
+  const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (w >= W) return;
+  const bool acc = log(u[w]) < 2.0 * (lpp[w] - logpsi[w]);
+  if (acc) {
+    for (int x = 0; x < N3; ++x) r[w * N3 + x] = rp[w * N3 + x];
+    logpsi[w] = lpp[w];
+  }
+  if (accepted) accepted[w] = acc ? 1 : 0;
+}
+
+hipError_t launch_propose(const double* r, const double* noise, double step, int64_t n, double* rp, hipStream_t st) {
+  ProfScope ps("propose_kernel", st);
+  hipLaunchKernelGGL(propose_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, r, noise, step, n, rp);
+  return hipGetLastError();
+}
+
+hipError_t launch_accept(int64_t W, int N3, const double* rp, const double* lp_prop, const double* u, double* r,
+                         double* logpsi, uint8_t* accepted, hipStream_t st) {
+  ProfScope ps("accept_kernel", st);
+  hipLaunchKernelGGL(accept_kernel, dim3((unsigned)((W + 127) / 128)), dim3(128), 0, st, W, N3, rp, lp_prop, u, r,
+                     logpsi, accepted);
+  return hipGetLastError();
+}
+
+// explicit instantiations
+#define QMC_INST(S)                                                                                             \
+  template hipError_t launch_rbf<S>(const SysDev&, int, const double*, const double*, int64_t, int, S*,         \
+                                    hipStream_t);                                                               \
+  template hipError_t launch_init_features<S>(const SysDev&, const double*, const double*, int64_t, int, S*,    \
+                                              hipStream_t);                                                     \
+  template hipError_t launch_aggregate<S>(const SysDev&, const S*, const S*, const S*, const S*, const S*,      \
+                                          const double*, const double*, int64_t, int, S*, hipStream_t);         \
+  template hipError_t launch_envelope<S>(const SysDev&, int, const S*, const S*, const S*, const double*,       \
+                                         int64_t, int, S*, hipStream_t);                                        \
+  template hipError_t launch_det<S>(const SysDev&, const S*, int64_t, int, double*, double*, double*, double*, \
+                                    hipStream_t);                                                               \
+  template hipError_t launch_combine<S>(const SysDev&, const S*, const double*, const double*, const double*,    \
+                                        const double*, const double*, int64_t, int, double*, double*, double*,  \
+                                        double*, double*, hipStream_t);
+QMC_INST(double)
+QMC_INST(float)
+
+}  // namespace qmc

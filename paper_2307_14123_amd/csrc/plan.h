@@ -1,0 +1,76 @@
+// Internal plan structures of the qmc library (host side, no HIP types).
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+#include <vector>
+
+#include "../../include/qmc.h"
+
+namespace qmc {
+
+// Offsets (in elements, relative to the system's blob) of every tensor.
+struct ParamOffsets {
+  int64_t initW[8], initb[8];  // init layers 1..L0 (index l-1)
+  struct Layer {
+    int64_t U1[3], a1[3], U2[3], a2[3];  // edge filters: 0 same, 1 opp, 2 nuc
+    int64_t Wh, bh, Y, Wg, bg;
+  };
+  std::vector<Layer> mp;
+  int64_t orbW[2], orbb[2], pi[2], sigma[2];  // -1 when that spin block is empty
+  int64_t c;
+  int64_t total;
+};
+
+enum { TYPE_SAME = 0, TYPE_OPP = 1, TYPE_NUC = 2 };
+
+// Everything one system needs at launch time.
+struct SysPlan {
+  int M, N, nup, ndn;
+  std::vector<double> Z, R;  // R: [M][3]
+  double vnn;
+  int64_t W;              // walkers of this system
+  int64_t walker_offset;  // first walker in the concatenated walker arrays
+  int64_t param_offset;   // first element of this system's blob
+  ParamOffsets off;
+  int T;                  // tangents 3N
+  int Rp;                 // jet rows per electron, padded: roundup(3N + 2, 16)
+  int P[3];               // pairs per edge type: same-spin (unordered), up-down, electron-nucleus
+  int64_t Wc;             // walkers per launch sequence (chunk)
+  int nsig(int s) const { return s == 0 ? nup : ndn; }
+};
+
+struct Plan {
+  qmc_ansatz ans;
+  qmc_precision prec;
+  std::vector<SysPlan> sys;
+  int64_t total_walkers;
+  int64_t total_params;
+  int64_t max_chunk_bytes;
+};
+
+// Byte offsets of the buffers one chunk of one system uses.
+struct Workspace {
+  size_t geom, vpot;
+  size_t rho[3], ehid[3], wjet[3];
+  size_t x0, f, h, m;
+  size_t phi[2], ajet;
+  size_t dld, dsg, dg, dlap;
+  size_t lp_prop;
+  // backward (value mode)
+  size_t st_f, st_h, st_m, st_ehid, st_w, st_t0;
+  size_t gbar_f, gbar_h, gbar_m, gbar_w, gbar_e, gbar_phi, gpart, wts;
+  size_t total;
+};
+
+bool compute_offsets(const qmc_system& s, const qmc_ansatz& a, ParamOffsets* off);
+size_t act_bytes(qmc_precision p);
+// jet = true: value, 3N tangent and Laplacian rows; false: value rows only.
+Workspace workspace_layout(const Plan& p, const SysPlan& s, int op, int64_t wc);
+size_t workspace_bytes(const Plan& p, int op);
+
+}  // namespace qmc
+
+struct qmc_plan {
+  qmc::Plan p;
+};

@@ -1,0 +1,257 @@
+"""ctypes binding of libqmc.so (argument marshalling only).
+
+Every computation runs in the HIP library; torch provides device memory and
+the current stream.  The functions raise if the library is not built or a
+call returns an error status: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Sequence
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libqmc.so")
+
+QMC_FP64, QMC_FP32, QMC_BF16_MIXED = 0, 1, 2
+PRECISIONS = {"fp64": QMC_FP64, "fp32": QMC_FP32, "bf16": QMC_BF16_MIXED}
+OP_LOGPSI, OP_LOCAL_ENERGY, OP_METROPOLIS, OP_LOGPSI_VJP, OP_LOSS_GRAD = range(5)
+
+
+class QmcSystem(ctypes.Structure):
+    _fields_ = [("n_nuc", ctypes.c_int32), ("charges", ctypes.POINTER(ctypes.c_double)),
+                ("coords", ctypes.POINTER(ctypes.c_double)), ("n_up", ctypes.c_int32),
+                ("n_down", ctypes.c_int32)]
+
+
+class QmcAnsatz(ctypes.Structure):
+    _fields_ = [("version", ctypes.c_int32), ("n_rbf", ctypes.c_int32), ("rbf_dmax", ctypes.c_double),
+                ("init_layers", ctypes.c_int32), ("width", ctypes.c_int32), ("mp_layers", ctypes.c_int32),
+                ("n_det", ctypes.c_int32), ("n_env", ctypes.c_int32), ("include_vnn", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libqmc.so (built in-tree by __graft_entry__.build())."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, sz, i32, i64, dp = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p
+    L.qmc_param_count.restype = i64
+    L.qmc_param_count.argtypes = [ctypes.POINTER(QmcSystem), ctypes.POINTER(QmcAnsatz)]
+    L.qmc_plan_create.restype = i32
+    L.qmc_plan_create.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(QmcSystem), i32, ctypes.POINTER(i64),
+                                  ctypes.POINTER(QmcAnsatz), i32, ctypes.c_uint32]
+    L.qmc_plan_destroy.restype = i32
+    L.qmc_plan_destroy.argtypes = [vp]
+    L.qmc_workspace_size.restype = i32
+    L.qmc_workspace_size.argtypes = [vp, i32, ctypes.POINTER(sz)]
+    L.qmc_plan_info.restype = i32
+    L.qmc_plan_info.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64)]
+    L.qmc_logpsi.restype = i32
+    L.qmc_logpsi.argtypes = [vp, vp, dp, dp, dp, vp, sz, vp]
+    L.qmc_local_energy.restype = i32
+    L.qmc_local_energy.argtypes = [vp, vp, dp, dp, dp, dp, dp, dp, vp, sz, vp]
+    L.qmc_metropolis_step.restype = i32
+    L.qmc_metropolis_step.argtypes = [vp, vp, dp, dp, dp, dp, ctypes.c_double, vp, vp, sz, vp]
+    L.qmc_logpsi_vjp.restype = i32
+    L.qmc_logpsi_vjp.argtypes = [vp, vp, dp, dp, vp, vp, sz, vp]
+    L.qmc_loss_grad.restype = i32
+    L.qmc_loss_grad.argtypes = [vp, vp, dp, dp, vp, dp, vp, sz, vp]
+    L.qmc_det_jets.restype = i32
+    L.qmc_det_jets.argtypes = [i64, i32, i32, dp, dp, dp, dp, dp, vp]
+    L.qmc_profile_enable.restype = i32
+    L.qmc_profile_enable.argtypes = [i32]
+    L.qmc_profile_report.restype = i32
+    L.qmc_profile_report.argtypes = [ctypes.c_char_p, sz, i32]
+    L.qmc_status_str.restype = ctypes.c_char_p
+    L.qmc_status_str.argtypes = [i32]
+    _lib = L
+    return L
+
+
+class QmcError(RuntimeError):
+    pass
+
+
+def _check(status: int, what: str):
+    if status != 0:
+        raise QmcError(f"{what}: {lib().qmc_status_str(status).decode()}")
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def make_ansatz(ans) -> QmcAnsatz:
+    return QmcAnsatz(1, ans.n_rbf, float(ans.rbf_dmax), ans.init_layers, ans.width, ans.mp_layers, ans.n_det,
+                     ans.n_env, ans.include_vnn)
+
+
+class _SysHolder:
+    """Keeps the host arrays of a qmc_system alive while the library copies them."""
+
+    def __init__(self, system):
+        Z = [float(z) for z in system.charges]
+        R = [float(x) for c in system.coords for x in c]
+        self.Z = (ctypes.c_double * len(Z))(*Z)
+        self.R = (ctypes.c_double * len(R))(*R)
+        self.s = QmcSystem(len(Z), self.Z, self.R, system.n_up, system.n_down)
+
+
+def param_count(system, ans) -> int:
+    h = _SysHolder(system)
+    a = make_ansatz(ans)
+    return int(lib().qmc_param_count(ctypes.byref(h.s), ctypes.byref(a)))
+
+
+class Plan:
+    """A plan over one or several systems; methods take device tensors."""
+
+    def __init__(self, systems: Sequence, walkers: Sequence[int], ans, precision: str = "fp64"):
+        self.systems = list(systems)
+        self.walkers = [int(w) for w in walkers]
+        self.ans = ans
+        self.precision = precision
+        holders = [_SysHolder(s) for s in self.systems]
+        arr = (QmcSystem * len(holders))(*[h.s for h in holders])
+        wps = (ctypes.c_int64 * len(self.walkers))(*self.walkers)
+        a = make_ansatz(ans)
+        handle = ctypes.c_void_p(0)
+        _check(lib().qmc_plan_create(ctypes.byref(handle), arr, len(holders), wps, ctypes.byref(a),
+                                     PRECISIONS[precision], 0), "qmc_plan_create")
+        self.handle = handle
+        tw, tp, tpos = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        _check(lib().qmc_plan_info(self.handle, ctypes.byref(tw), ctypes.byref(tp), ctypes.byref(tpos)),
+               "qmc_plan_info")
+        self.total_walkers, self.total_params, self.total_positions = tw.value, tp.value, tpos.value
+        self.param_dtype = torch.float64 if precision == "fp64" else torch.float32
+        self._ws = {}
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.qmc_plan_destroy(h)
+            self.handle = None
+
+    def workspace_bytes(self, op: int) -> int:
+        b = ctypes.c_size_t()
+        _check(lib().qmc_workspace_size(self.handle, op, ctypes.byref(b)), "qmc_workspace_size")
+        return int(b.value)
+
+    def workspace(self, op: int, device="cuda"):
+        n = self.workspace_bytes(op)
+        ws = self._ws.get(op)
+        if ws is None or ws.numel() < n:
+            ws = torch.empty(n, dtype=torch.uint8, device=device)
+            self._ws[op] = ws
+        return ws
+
+    def _check_inputs(self, params, r):
+        if params.dtype != self.param_dtype or params.numel() != self.total_params or not params.is_contiguous():
+            raise ValueError("params: wrong dtype, size or layout")
+        if r.dtype != torch.float64 or r.numel() != self.total_positions or not r.is_contiguous():
+            raise ValueError("r: expected contiguous float64 [W][N][3] positions")
+        if not (params.is_cuda and r.is_cuda):
+            raise ValueError("params and r must be device tensors")
+
+    def logpsi(self, params, r):
+        self._check_inputs(params, r)
+        W = self.total_walkers
+        lp = torch.empty(W, dtype=torch.float64, device=r.device)
+        sg = torch.empty(W, dtype=torch.float64, device=r.device)
+        ws = self.workspace(OP_LOGPSI)
+        _check(lib().qmc_logpsi(self.handle, _ptr(params), _ptr(r), _ptr(lp), _ptr(sg), _ptr(ws), ws.numel(),
+                                _stream()), "qmc_logpsi")
+        return lp, sg
+
+    def local_energy(self, params, r, out=None):
+        self._check_inputs(params, r)
+        W = self.total_walkers
+        dev = r.device
+        if out is None:
+            out = {"logpsi": torch.empty(W, dtype=torch.float64, device=dev),
+                   "sign": torch.empty(W, dtype=torch.float64, device=dev),
+                   "grad": torch.empty(self.total_positions, dtype=torch.float64, device=dev),
+                   "lap": torch.empty(W, dtype=torch.float64, device=dev),
+                   "e_loc": torch.empty(W, dtype=torch.float64, device=dev)}
+        ws = self.workspace(OP_LOCAL_ENERGY)
+        _check(lib().qmc_local_energy(self.handle, _ptr(params), _ptr(r), _ptr(out.get("logpsi")),
+                                      _ptr(out.get("sign")), _ptr(out.get("grad")), _ptr(out.get("lap")),
+                                      _ptr(out["e_loc"]), _ptr(ws), ws.numel(), _stream()), "qmc_local_energy")
+        return out
+
+    def metropolis_step(self, params, r, logpsi, noise, u, step, accepted=None):
+        """In place on r and logpsi; returns the uint8 acceptance flags."""
+        self._check_inputs(params, r)
+        W = self.total_walkers
+        if noise.dtype != torch.float64 or noise.numel() != self.total_positions or not noise.is_contiguous():
+            raise ValueError("noise: expected float64 like r")
+        if u.dtype != torch.float64 or u.numel() != W or logpsi.dtype != torch.float64 or logpsi.numel() != W:
+            raise ValueError("u/logpsi: expected float64 [W]")
+        if accepted is None:
+            accepted = torch.empty(W, dtype=torch.uint8, device=r.device)
+        ws = self.workspace(OP_METROPOLIS)
+        _check(lib().qmc_metropolis_step(self.handle, _ptr(params), _ptr(r), _ptr(logpsi), _ptr(noise), _ptr(u),
+                                         float(step), _ptr(accepted), _ptr(ws), ws.numel(), _stream()),
+               "qmc_metropolis_step")
+        return accepted
+
+    def logpsi_vjp(self, params, r, cotangent):
+        self._check_inputs(params, r)
+        g = torch.empty_like(params)
+        ws = self.workspace(OP_LOGPSI_VJP)
+        _check(lib().qmc_logpsi_vjp(self.handle, _ptr(params), _ptr(r), _ptr(cotangent), _ptr(g), _ptr(ws),
+                                    ws.numel(), _stream()), "qmc_logpsi_vjp")
+        return g
+
+    def loss_grad(self, params, r, e_loc):
+        self._check_inputs(params, r)
+        g = torch.empty_like(params)
+        em = torch.empty(len(self.systems), dtype=torch.float64, device=r.device)
+        ws = self.workspace(OP_LOSS_GRAD)
+        _check(lib().qmc_loss_grad(self.handle, _ptr(params), _ptr(r), _ptr(e_loc), _ptr(g), _ptr(em), _ptr(ws),
+                                   ws.numel(), _stream()), "qmc_loss_grad")
+        return g, em
+
+
+def det_jets(jets, n: int, n_tan: int):
+    """Determinant stage on given matrix jets [n_mat][n_tan+2][n][n] (float64 device)."""
+    if jets.dtype != torch.float64 or not jets.is_contiguous() or not jets.is_cuda:
+        raise ValueError("jets: expected contiguous float64 device tensor")
+    nmat = jets.numel() // ((n_tan + 2) * n * n)
+    dev = jets.device
+    ld = torch.empty(nmat, dtype=torch.float64, device=dev)
+    sg = torch.empty(nmat, dtype=torch.float64, device=dev)
+    g = torch.empty(max(nmat * n_tan, 1), dtype=torch.float64, device=dev)
+    lap = torch.empty(nmat, dtype=torch.float64, device=dev)
+    _check(lib().qmc_det_jets(nmat, n, n_tan, _ptr(jets), _ptr(ld), _ptr(sg), _ptr(g), _ptr(lap), _stream()),
+           "qmc_det_jets")
+    return ld, sg, g[:nmat * n_tan].reshape(nmat, n_tan), lap
+
+
+def profile_enable(on: bool = True):
+    """Time every kernel launch with HIP events on its own stream."""
+    _check(lib().qmc_profile_enable(1 if on else 0), "qmc_profile_enable")
+
+
+def profile_report(reset: bool = True):
+    """{kernel name: (launches, total ms)} for the launches recorded since the last reset."""
+    buf = ctypes.create_string_buffer(1 << 16)
+    _check(lib().qmc_profile_report(buf, len(buf), 1 if reset else 0), "qmc_profile_report")
+    out = {}
+    for line in buf.value.decode().splitlines():
+        name, n, ms = line.rsplit(" ", 2)
+        out[name] = (int(n), float(ms))
+    return out
