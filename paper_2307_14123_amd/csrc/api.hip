@@ -172,7 +172,7 @@ static qmc_status forward_chunk(const Plan& P, const SysPlan& s, const S* prm, c
     CK(launch_envelope<S>(dv, sp, (S*)(ws + L.phi[sp]), prm + O.pi[sp], prm + O.sigma[sp], en, wc, jet, ajet, st));
     off_e += n;
   }
-  CK(launch_det<S>(dv, ajet, wc, jet, dld, dsg, dg, dlap, st));
+  CK(launch_det<S>(dv, ajet, wc, jet, dld, dsg, dg, dlap, nullptr, st));
   CK(launch_combine<S>(dv, prm + O.c, dld, dsg, dg, dlap, vpot, wc, jet, out.logpsi, out.sign, out.grad, out.lap,
                        out.eloc, st));
   return QMC_OK;
@@ -242,6 +242,231 @@ static qmc_status run_metropolis(const Plan& P, const void* params, double* r, d
   return QMC_OK;
 }
 
+
+// ---------------------------------------------------------------- parameter backward
+
+static WgradArgs wg(const void* X, int64_t ldx, const void* G, int64_t ldg, int64_t rows, int Kin, int Nout,
+                    const BwdWorkspace& B, char* ws) {
+  WgradArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.X = X;
+  a.ldx = ldx;
+  a.xrpw = rows;
+  a.xws = 0;
+  a.G = G;
+  a.ldg = ldg;
+  a.grpw = rows;
+  a.gws = 0;
+  a.rows = rows;
+  a.Kin = Kin;
+  a.Nout = Nout;
+  a.ones = 1;
+  a.part = (double*)(ws + B.wpart);
+  a.rows_per_split = B.rows_per_split;
+  a.max_split = B.max_split;
+  return a;
+}
+
+// Value-only forward of one chunk that keeps every layer's activations.
+template <typename S>
+static qmc_status forward_stash(const Plan& P, const SysPlan& s, const S* prm, const double* r, int64_t wc,
+                                const BwdWorkspace& B, char* ws, hipStream_t st) {
+  const SysDev dv = make_dev(P, s);
+  const int64_t N = s.N, M = s.M, D = P.ans.width, K = P.ans.n_rbf, ND = P.ans.n_det;
+  const int L = P.ans.mp_layers, L0 = P.ans.init_layers;
+  const GemmKind gk = embed_kind(P.prec), ok = orbital_kind(P.prec);
+  const ParamOffsets& O = s.off;
+  double* ee = (double*)(ws + B.geom);
+  double* en = ee + wc * N * N * 4;
+  auto F_ = [&](size_t base, int64_t blk, int l) { return (S*)(ws + base + size_t(blk) * l); };
+  CK(launch_geometry(dv, r, wc, ee, en, nullptr, st));
+  if (L > 0)
+    for (int t = 0; t < 3; ++t) CK(launch_rbf<S>(dv, t, ee, en, wc, 0, (S*)(ws + B.rho[t]), st));
+  S* x0 = (S*)(ws + B.x0);
+  CK(launch_init_features<S>(dv, ee, en, wc, 0, x0, st));
+  const int64_t rows = wc * N;
+  const int Fd = (int)((M + 2) * K);
+  CK(launch_gemm(gk, dense(x0, Fd, prm + O.initW[0], D, prm + O.initb[0], F_(B.finit, B.blk_f, 0), D, rows, Fd,
+                           (int)D, 1, 0, 1, 1), st));
+  for (int l = 1; l < L0; ++l)
+    CK(launch_gemm(gk, dense(F_(B.finit, B.blk_f, l - 1), D, prm + O.initW[l], D, prm + O.initb[l],
+                             F_(B.finit, B.blk_f, l), D, rows, (int)D, (int)D, 1, 0, 1, 1), st));
+  S* fprev = F_(B.finit, B.blk_f, L0 - 1);
+  for (int l = 0; l < L; ++l) {
+    const auto& Ly = O.mp[l];
+    for (int t = 0; t < 3; ++t) {
+      const int64_t re = wc * s.P[t];
+      if (re == 0) continue;
+      S* eh = F_(B.ehid[t], B.blk_e[t], l);
+      S* wv = F_(B.wv[t], B.blk_e[t], l);
+      CK(launch_gemm(gk, dense((S*)(ws + B.rho[t]), K, prm + Ly.U1[t], D, prm + Ly.a1[t], eh, D, re, (int)K, (int)D, 1,
+                               0, 1, 1), st));
+      CK(launch_gemm(gk, dense(eh, D, prm + Ly.U2[t], D, prm + Ly.a2[t], wv, D, re, (int)D, (int)D, 1, 0, 0, 1), st));
+    }
+    S* h = F_(B.hst, B.blk_f, l);
+    S* m = F_(B.mst, B.blk_m, l);
+    S* t = F_(B.tst, B.blk_f, l);
+    S* fo = F_(B.fst, B.blk_f, l);
+    CK(launch_gemm(gk, dense(fprev, D, prm + Ly.Wh, D, prm + Ly.bh, h, D, rows, (int)D, (int)D, 1, 0, 0, 1), st));
+    CK(launch_aggregate<S>(dv, h, F_(B.wv[0], B.blk_e[0], l), F_(B.wv[1], B.blk_e[1], l), F_(B.wv[2], B.blk_e[2], l),
+                           prm + Ly.Y, ee, en, wc, 0, m, st));
+    CK(launch_gemm(gk, dense(m, 3 * D, prm + Ly.Wg, D, prm + Ly.bg, t, D, rows, (int)(3 * D), (int)D, 1, 0, 1, 1), st));
+    CK(launch_add<S>(rows * D, fprev, t, fo, st));
+    fprev = fo;
+  }
+  int64_t off_e = 0;
+  for (int sp = 0; sp < 2; ++sp) {
+    const int64_t n = s.nsig(sp);
+    if (n == 0) continue;
+    GemmArgs a = dense(fprev + off_e * D, D, prm + O.orbW[sp], ND * n, prm + O.orbb[sp], (S*)(ws + B.phi[sp]), ND * n,
+                       wc * n, (int)D, (int)(ND * n), 1, 0, 0, 1);
+    a.xrpw = n;
+    a.xws = N * D;
+    CK(launch_gemm(ok, a, st));
+    CK(launch_envelope<S>(dv, sp, (S*)(ws + B.phi[sp]), prm + O.pi[sp], prm + O.sigma[sp], en, wc, 0,
+                          (S*)(ws + B.aval), st));
+    off_e += n;
+  }
+  CK(launch_det<S>(dv, (S*)(ws + B.aval), wc, 0, (double*)(ws + B.dld), (double*)(ws + B.dsg), nullptr, nullptr,
+                   (double*)(ws + B.ainv), st));
+  return QMC_OK;
+}
+
+// Cotangent gbar[wc] on log|psi| of the chunk -> accumulate parameter gradients into gacc (float64).
+template <typename S>
+static qmc_status backward_chunk(const Plan& P, const SysPlan& s, const S* prm, const double* gbar, int64_t wc,
+                                 const BwdWorkspace& B, char* ws, hipStream_t st) {
+  const SysDev dv = make_dev(P, s);
+  const int64_t N = s.N, M = s.M, D = P.ans.width, K = P.ans.n_rbf, ND = P.ans.n_det;
+  const int L = P.ans.mp_layers, L0 = P.ans.init_layers;
+  const GemmKind bk = P.prec == QMC_FP64 ? GK_F64 : GK_F32;
+  const ParamOffsets& O = s.off;
+  double* gacc = (double*)(ws + B.gacc);
+  double* en = (double*)(ws + B.geom) + wc * N * N * 4;
+  auto F_ = [&](size_t base, int64_t blk, int l) { return (S*)(ws + base + size_t(blk) * l); };
+  const int64_t rows = wc * N;
+  double* lbar = (double*)(ws + B.lbar);
+  double* cpart = (double*)(ws + B.cpart);
+  CK(launch_combine_bwd<S>(dv, prm + O.c, (double*)(ws + B.dld), (double*)(ws + B.dsg), gbar, wc, lbar, cpart, st));
+  CK(launch_rowsum(cpart, wc, ND, ND, gacc + O.c, st));
+  S* fL = L > 0 ? F_(B.fst, B.blk_f, L - 1) : F_(B.finit, B.blk_f, L0 - 1);
+  S* fbar = (S*)(ws + B.fbar);
+  S* fbar2 = (S*)(ws + B.fbar2);
+  int64_t off_e = 0;
+  const double* ainv = (double*)(ws + B.ainv);
+  for (int sp = 0; sp < 2; ++sp) {
+    const int64_t n = s.nsig(sp);
+    if (n == 0) continue;
+    const int64_t ncol = ND * n;
+    S* phib = (S*)(ws + B.phibar[sp]);
+    double* pip = (double*)(ws + B.pipart);
+    double* sgp = (double*)(ws + B.sgpart);
+    const double* ai = ainv + (sp ? wc * ND * s.nup * s.nup : 0);
+    CK(launch_orb_bwd<S>(dv, sp, lbar, ai, (S*)(ws + B.phi[sp]), prm + O.pi[sp], prm + O.sigma[sp], en, wc, phib, pip,
+                         sgp, st));
+    const int64_t ne = ncol * M * P.ans.n_env;
+    CK(launch_rowsum(pip, wc, ne, ne, gacc + O.pi[sp], st));
+    CK(launch_rowsum(sgp, wc, ne, ne, gacc + O.sigma[sp], st));
+    WgradArgs a = wg(fL + off_e * D, D, phib, ncol, wc * n, (int)D, (int)ncol, B, ws);
+    a.xrpw = n;
+    a.xws = N * D;
+    CK(launch_wgrad(bk, a, gacc + O.orbW[sp], ncol, gacc + O.orbb[sp], st));
+    GemmArgs g = dense(phib, ncol, prm + O.orbW[sp], ncol, nullptr, fbar + off_e * D, D, wc * n, (int)ncol, (int)D, 1, 0,
+                       0, 1);
+    g.transw = 1;
+    g.yrpw = n;
+    g.yws = N * D;
+    CK(launch_gemm(bk, g, st));
+    off_e += n;
+  }
+  S* zbar = (S*)(ws + B.zbar);
+  S* hbar = (S*)(ws + B.hbar);
+  S* mbar = (S*)(ws + B.mbar);
+  S* ebar = (S*)(ws + B.ebar);
+  for (int l = L - 1; l >= 0; --l) {
+    const auto& Ly = O.mp[l];
+    S* fin = l == 0 ? F_(B.finit, B.blk_f, L0 - 1) : F_(B.fst, B.blk_f, l - 1);
+    CK(launch_tanh_bwd<S>(rows * D, fbar, F_(B.tst, B.blk_f, l), zbar, st));
+    CK(launch_wgrad(bk, wg(F_(B.mst, B.blk_m, l), 3 * D, zbar, D, rows, (int)(3 * D), (int)D, B, ws), gacc + Ly.Wg, D,
+                    gacc + Ly.bg, st));
+    GemmArgs gm = dense(zbar, D, prm + Ly.Wg, D, nullptr, mbar, 3 * D, rows, (int)D, (int)(3 * D), 1, 0, 0, 1);
+    gm.transw = 1;
+    CK(launch_gemm(bk, gm, st));
+    S* wb[3] = {(S*)(ws + B.wbar[0]), (S*)(ws + B.wbar[1]), (S*)(ws + B.wbar[2])};
+    double* yp = (double*)(ws + B.ypart);
+    CK(launch_agg_bwd<S>(dv, mbar, F_(B.hst, B.blk_f, l), F_(B.wv[0], B.blk_e[0], l), F_(B.wv[1], B.blk_e[1], l),
+                         F_(B.wv[2], B.blk_e[2], l), prm + Ly.Y, wc, hbar, wb[0], wb[1], wb[2], yp, st));
+    CK(launch_rowsum(yp, wc, M * D, M * D, gacc + Ly.Y, st));
+    CK(launch_wgrad(bk, wg(fin, D, hbar, D, rows, (int)D, (int)D, B, ws), gacc + Ly.Wh, D, gacc + Ly.bh, st));
+    GemmArgs gh = dense(hbar, D, prm + Ly.Wh, D, nullptr, fbar2, D, rows, (int)D, (int)D, 1, 0, 0, 1);
+    gh.transw = 1;
+    gh.Res = fbar;
+    CK(launch_gemm(bk, gh, st));
+    std::swap(fbar, fbar2);
+    for (int t = 0; t < 3; ++t) {
+      const int64_t re = wc * s.P[t];
+      if (re == 0) continue;
+      S* eh = F_(B.ehid[t], B.blk_e[t], l);
+      CK(launch_wgrad(bk, wg(eh, D, wb[t], D, re, (int)D, (int)D, B, ws), gacc + Ly.U2[t], D, gacc + Ly.a2[t], st));
+      GemmArgs ge = dense(wb[t], D, prm + Ly.U2[t], D, nullptr, ebar, D, re, (int)D, (int)D, 1, 0, 2, 1);
+      ge.transw = 1;
+      ge.aux = eh;
+      CK(launch_gemm(bk, ge, st));
+      CK(launch_wgrad(bk, wg((S*)(ws + B.rho[t]), K, ebar, D, re, (int)K, (int)D, B, ws), gacc + Ly.U1[t], D,
+                      gacc + Ly.a1[t], st));
+    }
+  }
+  for (int l = L0 - 1; l >= 0; --l) {
+    S* out = F_(B.finit, B.blk_f, l);
+    CK(launch_tanh_bwd<S>(rows * D, fbar, out, zbar, st));
+    const int Fd = (int)((M + 2) * K);
+    if (l == 0) {
+      CK(launch_wgrad(bk, wg((S*)(ws + B.x0), Fd, zbar, D, rows, Fd, (int)D, B, ws), gacc + O.initW[0], D,
+                      gacc + O.initb[0], st));
+    } else {
+      CK(launch_wgrad(bk, wg(F_(B.finit, B.blk_f, l - 1), D, zbar, D, rows, (int)D, (int)D, B, ws), gacc + O.initW[l],
+                      D, gacc + O.initb[l], st));
+      GemmArgs gi = dense(zbar, D, prm + O.initW[l], D, nullptr, fbar2, D, rows, (int)D, (int)D, 1, 0, 0, 1);
+      gi.transw = 1;
+      CK(launch_gemm(bk, gi, st));
+      std::swap(fbar, fbar2);
+    }
+  }
+  return QMC_OK;
+}
+
+// cot: per-walker cotangent (VJP) or nullptr with e_loc given (loss gradient).
+template <typename S>
+static qmc_status run_backward(const Plan& P, const void* params, const double* r, const double* cot,
+                               const double* e_loc, void* grad, double* e_mean, char* ws, hipStream_t st) {
+  for (size_t si = 0; si < P.sys.size(); ++si) {
+    const SysPlan& s = P.sys[si];
+    const S* prm = (const S*)params + s.param_offset;
+    const BwdWorkspace B0 = bwd_layout(P, s, s.Wc);
+    double* gacc = (double*)(ws + B0.gacc);
+    CK(launch_fill(s.off.total, 0.0, gacc, st));
+    const double* gall;
+    if (cot) {
+      gall = cot + s.walker_offset;
+    } else {
+      double* gb = (double*)(ws + B0.gbar);
+      CK(launch_loss_weights(e_loc + s.walker_offset, s.W, (double*)(ws + B0.stats), gb, e_mean ? e_mean + si : nullptr,
+                             st));
+      gall = gb;
+    }
+    for (int64_t w0 = 0; w0 < s.W; w0 += s.Wc) {
+      const int64_t wc = std::min<int64_t>(s.Wc, s.W - w0);
+      // the layout depends only on the chunk size through sizes; keep the full-chunk offsets so
+      // that gacc / gbar / stats stay at fixed places
+      const qmc_status e1 = forward_stash<S>(P, s, prm, r + pos_offset(P, s) + w0 * s.N * 3, wc, B0, ws, st);
+      if (e1 != QMC_OK) return e1;
+      const qmc_status e2 = backward_chunk<S>(P, s, prm, gall + w0, wc, B0, ws, st);
+      if (e2 != QMC_OK) return e2;
+    }
+    CK(launch_cast<S>(s.off.total, gacc, (S*)grad + s.param_offset, st));
+  }
+  return QMC_OK;
+}
 }  // namespace qmc
 
 using namespace qmc;
@@ -294,29 +519,28 @@ qmc_status qmc_metropolis_step(const qmc_plan* plan, const void* params, double*
 
 qmc_status qmc_logpsi_vjp(const qmc_plan* plan, const void* params, const double* r, const double* cotangent,
                           void* grad_params, void* ws, size_t ws_bytes, void* stream) {
-  (void)plan;
-  (void)params;
-  (void)r;
-  (void)cotangent;
-  (void)grad_params;
-  (void)ws;
-  (void)ws_bytes;
-  (void)stream;
-  return QMC_ERR_UNSUPPORTED;
+  if (!plan || !params || !r || !cotangent || !grad_params) return QMC_ERR_INVALID_ARGUMENT;
+  if (!ws_ok(plan->p, QMC_OP_LOGPSI_VJP, ws, ws_bytes)) {
+    if (ws && ws_bytes < workspace_bytes(plan->p, QMC_OP_LOGPSI_VJP)) return QMC_ERR_WORKSPACE_TOO_SMALL;
+    return QMC_ERR_INVALID_ARGUMENT;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  if (plan->p.prec == QMC_FP64)
+    return run_backward<double>(plan->p, params, r, cotangent, nullptr, grad_params, nullptr, (char*)ws, st);
+  return run_backward<float>(plan->p, params, r, cotangent, nullptr, grad_params, nullptr, (char*)ws, st);
 }
 
 qmc_status qmc_loss_grad(const qmc_plan* plan, const void* params, const double* r, const double* e_loc,
                          void* grad_params, double* e_mean, void* ws, size_t ws_bytes, void* stream) {
-  (void)plan;
-  (void)params;
-  (void)r;
-  (void)e_loc;
-  (void)grad_params;
-  (void)e_mean;
-  (void)ws;
-  (void)ws_bytes;
-  (void)stream;
-  return QMC_ERR_UNSUPPORTED;
+  if (!plan || !params || !r || !e_loc || !grad_params) return QMC_ERR_INVALID_ARGUMENT;
+  if (!ws_ok(plan->p, QMC_OP_LOSS_GRAD, ws, ws_bytes)) {
+    if (ws && ws_bytes < workspace_bytes(plan->p, QMC_OP_LOSS_GRAD)) return QMC_ERR_WORKSPACE_TOO_SMALL;
+    return QMC_ERR_INVALID_ARGUMENT;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  if (plan->p.prec == QMC_FP64)
+    return run_backward<double>(plan->p, params, r, nullptr, e_loc, grad_params, e_mean, (char*)ws, st);
+  return run_backward<float>(plan->p, params, r, nullptr, e_loc, grad_params, e_mean, (char*)ws, st);
 }
 
 qmc_status qmc_det_jets(int64_t n_mat, int32_t n, int32_t n_tan, const double* jets, double* logdet, double* sign,

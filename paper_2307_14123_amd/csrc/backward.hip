@@ -1,0 +1,479 @@
+// Backward (vector-Jacobian product of log|psi| with respect to the
+// parameters) and the loss-gradient helpers, gfx950.
+//
+// With cotangent g_w on log|psi_w|: through the log-sum-exp over determinants
+// (Sec. III.E) each determinant log gets g_w * w_p with w_p = c_p D_p / psi,
+// and c_p gets g_w D_p / psi; d log|det A| / dA = A^-T (Jacobi's formula), so
+// the orbital matrix cotangent is g_w w_p A^-T; A = phi * env splits into
+// phi_bar = A_bar * env and env_bar = A_bar * phi; linear layers give
+// W_bar = x^T y_bar, b_bar = sum y_bar, x_bar = y_bar W^T; tanh gives
+// z_bar = t_bar (1 - t^2).  Parameter gradients are sums over walkers and
+// electrons: they are formed as split-row MFMA reductions whose partial sums
+// are added in float64 in a fixed order (deterministic).
+#include <cmath>
+#include <type_traits>
+
+#include "kernels.h"
+
+namespace qmc {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+// ---------------------------------------------------------------- weight gradients
+
+// part[split][m][n] = sum over this split's rows r of X[r][m] * G[r][n]
+// (m = Kin is a virtual column of ones when a.ones: the bias gradient).
+template <int KIND>
+__global__ __launch_bounds__(256) void wgrad_kernel(WgradArgs a) {
+  using S = typename std::conditional<KIND == GK_F64, double, float>::type;
+  using Acc = typename std::conditional<KIND == GK_F64, d4, f4>::type;
+  constexpr int BM = 64, BN = 64, BR = 16;
+  __shared__ S Xs[BR][BM + 4];
+  __shared__ S Gs[BR][BN + 4];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
+  const int split = blockIdx.z;
+  const int64_t r0 = (int64_t)split * a.rows_per_split;
+  const int64_t r1 = r0 + a.rows_per_split < a.rows ? r0 + a.rows_per_split : a.rows;
+  const S* X = (const S*)a.X;
+  const S* G = (const S*)a.G;
+  const int Mtot = a.Kin + (a.ones ? 1 : 0);
+  Acc acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) acc[i][j][e] = 0;
+  const int lr = tid / 16, lc = (tid % 16) * 4;  // loader: row lr, 4 columns from lc
+  for (int64_t rb = r0; rb < r1; rb += BR) {
+    const int64_t r = rb + lr;
+    const bool rv = r < r1;
+    const S* xr = X + (rv ? (r / a.xrpw) * a.xws + (r % a.xrpw) * a.ldx : 0);
+    const S* gr = G + (rv ? (r / a.grpw) * a.gws + (r % a.grpw) * a.ldg : 0);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int m = m0 + lc + e, n = n0 + lc + e;
+      S xv = 0, gv = 0;
+      if (rv) {
+        if (m < a.Kin)
+          xv = xr[m];
+        else if (m == a.Kin && a.ones)
+          xv = 1;
+        if (n < a.Nout) gv = gr[n];
+      }
+      Xs[lr][lc + e] = xv;
+      Gs[lr][lc + e] = gv;
+    }
+    __syncthreads();
+    const int g = lane >> 4, c = lane & 15;
+#pragma unroll
+    for (int kq = 0; kq < BR / 4; ++kq) {
+      S av[2], bv[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) av[i] = Xs[kq * 4 + g][wm * 32 + i * 16 + c];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) bv[j] = Gs[kq * 4 + g][wn * 32 + j * 16 + c];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          if constexpr (KIND == GK_F64)
+            acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], bv[j], acc[i][j], 0, 0, 0);
+          else
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i], bv[j], acc[i][j], 0, 0, 0);
+        }
+    }
+    __syncthreads();
+  }
+  const int g = lane >> 4, c = lane & 15;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int row = (KIND == GK_F64) ? g + 4 * e : 4 * g + e;
+        const int m = m0 + wm * 32 + i * 16 + row;
+        const int n = n0 + wn * 32 + j * 16 + c;
+        if (m < Mtot && n < a.Nout) a.part[((int64_t)split * Mtot + m) * a.Nout + n] = (double)acc[i][j][e];
+      }
+}
+
+// gW[m][n] += sum_split part (m < Kin), gb[n] += row Kin (bias), in split order
+__global__ void wgrad_reduce_kernel(const double* __restrict__ part, int nsplit, int Kin, int ones, int Nout,
+                                    double* __restrict__ gW, int64_t ldgw, double* __restrict__ gb) {
+  const int Mtot = Kin + (ones ? 1 : 0);
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)Mtot * Nout) return;
+  const int m = (int)(t / Nout), n = (int)(t % Nout);
+  double s = 0.0;
+  for (int k = 0; k < nsplit; ++k) s += part[((int64_t)k * Mtot + m) * Nout + n];
+  if (m < Kin)
+    gW[(int64_t)m * ldgw + n] += s;
+  else
+    gb[n] += s;
+}
+
+hipError_t launch_wgrad(GemmKind kind, const WgradArgs& a, double* gW, int64_t ldgw, double* gb, hipStream_t st) {
+  if (a.rows <= 0) return hipSuccess;
+  const int Mtot = a.Kin + (a.ones ? 1 : 0);
+  const int nsplit = (int)((a.rows + a.rows_per_split - 1) / a.rows_per_split);
+  if (nsplit > a.max_split) return hipErrorInvalidValue;
+  dim3 grid((unsigned)((Mtot + 63) / 64), (unsigned)((a.Nout + 63) / 64), (unsigned)nsplit);
+  {
+    ProfScope ps(kind == GK_F64 ? "wgrad_kernel<f64>" : "wgrad_kernel<f32>", st);
+    if (kind == GK_F64)
+      hipLaunchKernelGGL(wgrad_kernel<GK_F64>, grid, dim3(256), 0, st, a);
+    else
+      hipLaunchKernelGGL(wgrad_kernel<GK_F32>, grid, dim3(256), 0, st, a);
+  }
+  const int64_t n = (int64_t)Mtot * a.Nout;
+  ProfScope ps("wgrad_reduce_kernel", st);
+  hipLaunchKernelGGL(wgrad_reduce_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a.part, nsplit, a.Kin,
+                     a.ones, a.Nout, gW, ldgw, gb);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- small element-wise kernels
+
+template <typename S>
+__global__ void tanh_bwd_kernel(int64_t n, const S* __restrict__ ybar, const S* __restrict__ t, S* __restrict__ z) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) z[i] = ybar[i] * (S(1) - t[i] * t[i]);
+}
+
+template <typename S>
+__global__ void add_kernel(int64_t n, const S* __restrict__ a, const S* __restrict__ b, S* __restrict__ o) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) o[i] = a[i] + b[i];
+}
+
+__global__ void fill_kernel(int64_t n, double v, double* __restrict__ p) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+template <typename S>
+__global__ void cast_kernel(int64_t n, const double* __restrict__ src, S* __restrict__ dst) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = (S)src[i];
+}
+
+// dst[c] += sum_r src[r * ld + c], r in order (one thread per column)
+__global__ void rowsum_kernel(const double* __restrict__ src, int64_t R, int64_t C, int64_t ld,
+                              double* __restrict__ dst) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= C) return;
+  double s = 0.0;
+  for (int64_t r = 0; r < R; ++r) s += src[r * ld + c];
+  dst[c] += s;
+}
+
+template <typename S>
+hipError_t launch_tanh_bwd(int64_t n, const S* ybar, const S* t, S* z, hipStream_t st) {
+  ProfScope ps("tanh_bwd_kernel", st);
+  hipLaunchKernelGGL(tanh_bwd_kernel<S>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, ybar, t, z);
+  return hipGetLastError();
+}
+template <typename S>
+hipError_t launch_add(int64_t n, const S* a, const S* b, S* o, hipStream_t st) {
+  ProfScope ps("add_kernel", st);
+  hipLaunchKernelGGL(add_kernel<S>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, a, b, o);
+  return hipGetLastError();
+}
+hipError_t launch_fill(int64_t n, double v, double* p, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  ProfScope ps("fill_kernel", st);
+  hipLaunchKernelGGL(fill_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, v, p);
+  return hipGetLastError();
+}
+template <typename S>
+hipError_t launch_cast(int64_t n, const double* src, S* dst, hipStream_t st) {
+  ProfScope ps("cast_kernel", st);
+  hipLaunchKernelGGL(cast_kernel<S>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, src, dst);
+  return hipGetLastError();
+}
+hipError_t launch_rowsum(const double* src, int64_t R, int64_t C, int64_t ld, double* dst, hipStream_t st) {
+  if (R <= 0 || C <= 0) return hipSuccess;
+  ProfScope ps("rowsum_kernel", st);
+  hipLaunchKernelGGL(rowsum_kernel, dim3((unsigned)((C + 127) / 128)), dim3(128), 0, st, src, R, C, ld, dst);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- loss-gradient weights
+
+// stats[0] = mean of the finite e_loc, stats[1] = their count.  One block,
+// fixed per-thread order and tree reduction: deterministic.
+__global__ __launch_bounds__(1024) void emean_kernel(const double* __restrict__ e, int64_t W, double* __restrict__ stats) {
+  __shared__ double ss[1024];
+  __shared__ double sc[1024];
+  double s = 0.0, c = 0.0;
+  for (int64_t w = threadIdx.x; w < W; w += 1024) {
+    const double v = e[w];
+    if (isfinite(v)) {
+      s += v;
+      c += 1.0;
+    }
+  }
+  ss[threadIdx.x] = s;
+  sc[threadIdx.x] = c;
+  __syncthreads();
+  for (int o = 512; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) {
+      ss[threadIdx.x] += ss[threadIdx.x + o];
+      sc[threadIdx.x] += sc[threadIdx.x + o];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    stats[0] = sc[0] > 0 ? ss[0] / sc[0] : NAN;
+    stats[1] = sc[0];
+  }
+}
+
+// g_w = 2 (e_w - mean) / count for finite e_w, else 0
+__global__ void gbar_kernel(const double* __restrict__ e, const double* __restrict__ stats, int64_t W,
+                            double* __restrict__ g) {
+  const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (w >= W) return;
+  const double v = e[w];
+  g[w] = (isfinite(v) && stats[1] > 0) ? 2.0 * (v - stats[0]) / stats[1] : 0.0;
+}
+
+hipError_t launch_loss_weights(const double* e, int64_t W, double* stats, double* g, double* e_mean,
+                               hipStream_t st) {
+  {
+    ProfScope ps("emean_kernel", st);
+    hipLaunchKernelGGL(emean_kernel, dim3(1), dim3(1024), 0, st, e, W, stats);
+  }
+  if (e_mean) {
+    if (hipMemcpyAsync(e_mean, stats, sizeof(double), hipMemcpyDeviceToDevice, st) != hipSuccess)
+      return hipErrorUnknown;
+  }
+  ProfScope ps("gbar_kernel", st);
+  hipLaunchKernelGGL(gbar_kernel, dim3((unsigned)((W + 255) / 256)), dim3(256), 0, st, e, stats, W, g);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- combination backward
+
+// lbar[w][p] = g_w * w_p (cotangent of each determinant log, both spins);
+// cpart[w][p] = g_w * D_p / psi (cotangent of c_p, summed over walkers later).
+template <typename S>
+__global__ void combine_bwd_kernel(SysDev s, const S* __restrict__ c, const double* __restrict__ ld,
+                                   const double* __restrict__ sg, const double* __restrict__ gbar, int64_t W,
+                                   double* __restrict__ lbar, double* __restrict__ cpart) {
+  const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (w >= W) return;
+  const int nd = s.ndet;
+  const bool has[2] = {s.nup > 0, s.ndn > 0};
+  double mx = -INFINITY;
+  for (int p = 0; p < nd; ++p) {
+    double l = 0.0;
+    for (int sp = 0; sp < 2; ++sp)
+      if (has[sp]) l += ld[(w * 2 + sp) * nd + p];
+    if (l > mx) mx = l;
+  }
+  if (!(mx > -INFINITY)) mx = 0.0;
+  double S_ = 0.0;
+  for (int p = 0; p < nd; ++p) {
+    double l = 0.0, sgn = (double)c[p];
+    for (int sp = 0; sp < 2; ++sp)
+      if (has[sp]) {
+        l += ld[(w * 2 + sp) * nd + p];
+        sgn *= sg[(w * 2 + sp) * nd + p];
+      }
+    if (sgn != 0.0) S_ += sgn * exp(l - mx);
+  }
+  const double gw = gbar[w];
+  for (int p = 0; p < nd; ++p) {
+    double l = 0.0, sd = 1.0;
+    for (int sp = 0; sp < 2; ++sp)
+      if (has[sp]) {
+        l += ld[(w * 2 + sp) * nd + p];
+        sd *= sg[(w * 2 + sp) * nd + p];
+      }
+    const double dpsi = (sd != 0.0 && S_ != 0.0 && gw != 0.0) ? sd * exp(l - mx) / S_ : 0.0;  // D_p / psi
+    lbar[w * nd + p] = gw * (double)c[p] * dpsi;
+    cpart[w * nd + p] = gw * dpsi;
+  }
+}
+
+template <typename S>
+hipError_t launch_combine_bwd(const SysDev& s, const S* c, const double* ld, const double* sg, const double* gbar,
+                              int64_t W, double* lbar, double* cpart, hipStream_t st) {
+  ProfScope ps("combine_bwd_kernel", st);
+  hipLaunchKernelGGL(combine_bwd_kernel<S>, dim3((unsigned)((W + 127) / 128)), dim3(128), 0, st, s, c, ld, sg, gbar,
+                     W, lbar, cpart);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- orbitals x envelopes backward
+
+// One thread per (walker, det, orbital k) of spin block `spin`: loops over the
+// electrons a of the block.  A_bar[a][k] = lbar_p * (A^-1)[k][a];
+// phi_bar = A_bar * env (written per electron row), and the envelope weights
+// and exponents collect env_bar * exp(-sigma d) and -env_bar * pi * d * exp(-sigma d).
+template <typename S>
+__global__ void orb_bwd_kernel(SysDev s, int spin, const double* __restrict__ lbar, const double* __restrict__ ainv,
+                               const S* __restrict__ phi, const S* __restrict__ pi, const S* __restrict__ sg,
+                               const double* __restrict__ en, int64_t W, S* __restrict__ phibar,
+                               double* __restrict__ pipart, double* __restrict__ sgpart) {
+  const int n = spin ? s.ndn : s.nup;
+  const int i0 = spin ? s.nup : 0;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= W * s.ndet * n) return;
+  const int k = (int)(t % n);
+  const int p = (int)((t / n) % s.ndet);
+  const int64_t w = t / ((int64_t)n * s.ndet);
+  const int ncol = s.ndet * n;
+  const int nenvM = s.M * s.nenv;
+  const double lb = lbar[w * s.ndet + p];
+  const double* Ai = ainv + ((w * s.ndet + p) * n) * (int64_t)n;  // [n][n]
+  double* pp = pipart + t * nenvM;
+  double* sp = sgpart + t * nenvM;
+  for (int e = 0; e < nenvM; ++e) {
+    pp[e] = 0.0;
+    sp[e] = 0.0;
+  }
+  for (int a = 0; a < n; ++a) {
+    const int i = i0 + a;
+    const double Ab = lb * Ai[k * n + a];
+    const double* g = en + (w * s.N + i) * s.M * 4;
+    double env = 0.0;
+    for (int I = 0; I < s.M; ++I)
+      for (int b = 0; b < s.nenv; ++b) {
+        const int64_t idx = (((int64_t)p * n + k) * s.M + I) * s.nenv + b;
+        env += (double)pi[idx] * exp(-(double)sg[idx] * g[I * 4]);
+      }
+    const double ph = (double)phi[(w * n + a) * (int64_t)ncol + p * n + k];
+    phibar[(w * n + a) * (int64_t)ncol + p * n + k] = (S)(Ab * env);
+    const double eb = Ab * ph;
+    for (int I = 0; I < s.M; ++I)
+      for (int b = 0; b < s.nenv; ++b) {
+        const int64_t idx = (((int64_t)p * n + k) * s.M + I) * s.nenv + b;
+        const double d = g[I * 4];
+        const double ex = exp(-(double)sg[idx] * d);
+        pp[I * s.nenv + b] += eb * ex;
+        sp[I * s.nenv + b] -= eb * (double)pi[idx] * d * ex;
+      }
+  }
+}
+
+template <typename S>
+hipError_t launch_orb_bwd(const SysDev& s, int spin, const double* lbar, const double* ainv, const S* phi,
+                          const S* pi, const S* sg, const double* en, int64_t W, S* phibar, double* pipart,
+                          double* sgpart, hipStream_t st) {
+  const int n = spin ? s.ndn : s.nup;
+  const int64_t cnt = W * s.ndet * n;
+  if (cnt == 0) return hipSuccess;
+  ProfScope ps("orb_bwd_kernel", st);
+  hipLaunchKernelGGL(orb_bwd_kernel<S>, dim3((unsigned)((cnt + 127) / 128)), dim3(128), 0, st, s, spin, lbar, ainv,
+                     phi, pi, sg, en, W, phibar, pipart, sgpart);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- message aggregation backward
+
+__device__ inline int ee_pair_b(const SysDev& s, int i, int j, int& type) {
+  const bool ui = i < s.nup, uj = j < s.nup;
+  if (ui != uj) {
+    type = 1;
+    const int a = ui ? i : j, b = ui ? j : i;
+    return a * s.ndn + (b - s.nup);
+  }
+  type = 0;
+  int a = i < j ? i : j, b = i < j ? j : i;
+  int n = s.nup, off = 0;
+  if (!ui) {
+    n = s.ndn;
+    a -= s.nup;
+    b -= s.nup;
+    off = s.nup * (s.nup - 1) / 2;
+  }
+  return off + a * (2 * n - a - 1) / 2 + (b - a - 1);
+}
+
+// Block per walker, thread per column d.  With mbar = [m_same, m_opp, m_nuc] cotangents:
+//   h_bar_j   = sum_i (1/n(i)) w(d_ij) m_bar_type(i,j),_i
+//   w_bar_ij  = (1/n(i)) m_bar_i h_j + (1/n(j)) m_bar_j h_i      (unordered e-e pair)
+//   w_bar_iI  = m_bar_nuc_i Y_I / M,   Y_bar_I += sum_i w_iI m_bar_nuc_i / M
+template <typename S>
+__global__ void agg_bwd_kernel(SysDev s, const S* __restrict__ mbar, const S* __restrict__ h,
+                               const S* __restrict__ wsame, const S* __restrict__ wopp, const S* __restrict__ wnuc,
+                               const S* __restrict__ Y, S* __restrict__ hbar, S* __restrict__ wbs,
+                               S* __restrict__ wbo, S* __restrict__ wbn, double* __restrict__ ypart) {
+  const int64_t w = blockIdx.x;
+  const int N = s.N, D = s.D, M = s.M;
+  const S* mb = mbar + w * N * 3 * (int64_t)D;
+  const S* hw = h + w * N * (int64_t)D;
+  auto inv_n = [&](int i, int type) -> S {
+    const bool up = i < s.nup;
+    const int n = type == 0 ? (up ? s.nup : s.ndn) - 1 : (up ? s.ndn : s.nup);
+    return n > 0 ? S(1) / S(n) : S(0);
+  };
+  for (int d = threadIdx.x; d < D; d += blockDim.x) {
+    for (int j = 0; j < N; ++j) {
+      S acc = 0;
+      for (int i = 0; i < N; ++i) {
+        if (i == j) continue;
+        int type;
+        const int p = ee_pair_b(s, i, j, type);
+        const S wv = type ? wopp[(w * s.P1 + p) * D + d] : wsame[(w * s.P0 + p) * D + d];
+        acc += inv_n(i, type) * wv * mb[(int64_t)i * 3 * D + type * D + d];
+      }
+      hbar[(w * N + j) * D + d] = acc;
+    }
+    for (int i = 0; i < N; ++i)
+      for (int j = i + 1; j < N; ++j) {
+        int type;
+        const int p = ee_pair_b(s, i, j, type);
+        const S v = inv_n(i, type) * mb[(int64_t)i * 3 * D + type * D + d] * hw[(int64_t)j * D + d] +
+                    inv_n(j, type) * mb[(int64_t)j * 3 * D + type * D + d] * hw[(int64_t)i * D + d];
+        if (type)
+          wbo[(w * s.P1 + p) * D + d] = v;
+        else
+          wbs[(w * s.P0 + p) * D + d] = v;
+      }
+    const S invM = S(1) / S(M);
+    for (int I = 0; I < M; ++I) {
+      double yp = 0.0;
+      const S yv = Y[I * D + d];
+      for (int i = 0; i < N; ++i) {
+        const S mn = mb[(int64_t)i * 3 * D + 2 * D + d];
+        const int64_t pe = (w * s.P2 + i * M + I) * D + d;
+        wbn[pe] = mn * yv * invM;
+        yp += (double)(wnuc[pe] * mn * invM);
+      }
+      ypart[(w * M + I) * D + d] = yp;
+    }
+  }
+}
+
+template <typename S>
+hipError_t launch_agg_bwd(const SysDev& s, const S* mbar, const S* h, const S* wsame, const S* wopp, const S* wnuc,
+                          const S* Y, int64_t W, S* hbar, S* wbs, S* wbo, S* wbn, double* ypart, hipStream_t st) {
+  ProfScope ps("agg_bwd_kernel", st);
+  const int threads = s.D < 256 ? ((s.D + 63) / 64) * 64 : 256;
+  hipLaunchKernelGGL(agg_bwd_kernel<S>, dim3((unsigned)W), dim3(threads), 0, st, s, mbar, h, wsame, wopp, wnuc, Y,
+                     hbar, wbs, wbo, wbn, ypart);
+  return hipGetLastError();
+}
+
+#define QMC_BWD_INST(S)                                                                                           \
+  template hipError_t launch_tanh_bwd<S>(int64_t, const S*, const S*, S*, hipStream_t);                          \
+  template hipError_t launch_add<S>(int64_t, const S*, const S*, S*, hipStream_t);                               \
+  template hipError_t launch_cast<S>(int64_t, const double*, S*, hipStream_t);                                   \
+  template hipError_t launch_combine_bwd<S>(const SysDev&, const S*, const double*, const double*, const double*, \
+                                            int64_t, double*, double*, hipStream_t);                              \
+  template hipError_t launch_orb_bwd<S>(const SysDev&, int, const double*, const double*, const S*, const S*,     \
+                                        const S*, const double*, int64_t, S*, double*, double*, hipStream_t);     \
+  template hipError_t launch_agg_bwd<S>(const SysDev&, const S*, const S*, const S*, const S*, const S*,          \
+                                        const S*, int64_t, S*, S*, S*, S*, double*, hipStream_t);
+QMC_BWD_INST(double)
+QMC_BWD_INST(float)
+
+}  // namespace qmc

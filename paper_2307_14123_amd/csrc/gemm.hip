@@ -174,7 +174,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs a) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           const S z = acc[mb][nb][i] + b;
-          out[mb][i] = a.act ? dtanh(z) : z;
+          out[mb][i] = a.act == 1 ? dtanh(z) : z;
         }
     } else if (a.Rp == 4) {
       // univariate jets: groups of 4 rows (value, first, second derivative, pad)
@@ -268,6 +268,10 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs a) {
           if (r < a.rows) {
             const int64_t off = (r / a.yrpw) * a.yws + (r % a.yrpw) * a.ldy + col;
             S o = out[mb][i];
+            if (a.act == 2) {
+              const S t = ((const S*)a.aux)[off];
+              o *= S(1) - t * t;
+            }
             if (Res) o += Res[off];
             Y[off] = o;
           }
@@ -314,6 +318,7 @@ static hipError_t launch_kind(const GemmArgs& a, hipStream_t st) {
 hipError_t launch_gemm(GemmKind kind, const GemmArgs& a, hipStream_t st) {
   if (a.rows <= 0 || a.Ncols <= 0) return hipSuccess;
   if (!a.vmode && a.Rp == 4 && a.T != 1) return hipErrorInvalidValue;
+  if (a.act == 2 && (!a.vmode || !a.aux)) return hipErrorInvalidValue;
   switch (kind) {
     case GK_F64: return launch_kind<GK_F64>(a, st);
     case GK_F32: return launch_kind<GK_F32>(a, st);

@@ -103,10 +103,78 @@ Workspace workspace_layout(const Plan& p, const SysPlan& s, int op, int64_t wc) 
   return w;
 }
 
+BwdWorkspace bwd_layout(const Plan& p, const SysPlan& s, int64_t wc) {
+  BwdWorkspace b;
+  std::memset(&b, 0, sizeof(b));
+  size_t cur = 0;
+  auto alloc = [&](size_t bytes) {
+    size_t o = cur;
+    cur = align256(cur + bytes);
+    return o;
+  };
+  const size_t E = act_bytes(p.prec);
+  const int64_t N = s.N, M = s.M, D = p.ans.width, K = p.ans.n_rbf, ND = p.ans.n_det;
+  const int64_t L = p.ans.mp_layers, L0 = p.ans.init_layers, F = (M + 2) * K;
+  int64_t nsq = 0, nmax = 0, pmax = 0;
+  for (int sp = 0; sp < 2; ++sp) {
+    nsq += int64_t(s.nsig(sp)) * s.nsig(sp);
+    if (s.nsig(sp) > nmax) nmax = s.nsig(sp);
+  }
+  for (int t = 0; t < 3; ++t)
+    if (s.P[t] > pmax) pmax = s.P[t];
+  b.geom = alloc(size_t(wc) * (N * N + N * M) * 4 * 8);
+  for (int t = 0; t < 3; ++t) {
+    b.blk_e[t] = int64_t(align256(size_t(wc) * s.P[t] * D * E));
+    b.rho[t] = alloc(size_t(wc) * s.P[t] * K * E);
+    b.ehid[t] = alloc(size_t(b.blk_e[t]) * (L > 0 ? L : 1));
+    b.wv[t] = alloc(size_t(b.blk_e[t]) * (L > 0 ? L : 1));
+  }
+  b.blk_f = int64_t(align256(size_t(wc) * N * D * E));
+  b.blk_m = int64_t(align256(size_t(wc) * N * 3 * D * E));
+  b.x0 = alloc(size_t(wc) * N * F * E);
+  b.finit = alloc(size_t(b.blk_f) * L0);
+  b.fst = alloc(size_t(b.blk_f) * (L > 0 ? L : 1));
+  b.hst = alloc(size_t(b.blk_f) * (L > 0 ? L : 1));
+  b.mst = alloc(size_t(b.blk_m) * (L > 0 ? L : 1));
+  b.tst = alloc(size_t(b.blk_f) * (L > 0 ? L : 1));
+  for (int sp = 0; sp < 2; ++sp) b.phi[sp] = alloc(size_t(wc) * s.nsig(sp) * ND * s.nsig(sp) * E);
+  b.aval = alloc(size_t(wc) * ND * nsq * E);
+  b.dld = alloc(size_t(wc) * 2 * ND * 8);
+  b.dsg = alloc(size_t(wc) * 2 * ND * 8);
+  b.ainv = alloc(size_t(wc) * ND * nsq * 8);
+  b.gbar = alloc(size_t(s.W) * 8);
+  b.stats = alloc(2 * 8);
+  b.lbar = alloc(size_t(wc) * ND * 8);
+  b.cpart = alloc(size_t(wc) * ND * 8);
+  for (int sp = 0; sp < 2; ++sp) b.phibar[sp] = alloc(size_t(wc) * s.nsig(sp) * ND * s.nsig(sp) * E);
+  b.pipart = alloc(size_t(wc) * ND * nmax * M * p.ans.n_env * 8);
+  b.sgpart = alloc(size_t(wc) * ND * nmax * M * p.ans.n_env * 8);
+  b.fbar = alloc(size_t(b.blk_f));
+  b.fbar2 = alloc(size_t(b.blk_f));
+  b.zbar = alloc(size_t(b.blk_f));
+  b.hbar = alloc(size_t(b.blk_f));
+  b.mbar = alloc(size_t(b.blk_m));
+  for (int t = 0; t < 3; ++t) b.wbar[t] = alloc(size_t(wc) * s.P[t] * D * E);
+  b.ebar = alloc(size_t(wc) * pmax * D * E);
+  b.ypart = alloc(size_t(wc) * M * D * 8);
+  b.rows_per_split = 1024;
+  const int64_t rmax = wc * (N > pmax ? N : pmax);
+  b.max_split = int((rmax + b.rows_per_split - 1) / b.rows_per_split);
+  int64_t kin = 3 * D;
+  if (F > kin) kin = F;
+  int64_t nout = D;
+  if (ND * nmax > nout) nout = ND * nmax;
+  b.wpart = alloc(size_t(b.max_split) * (kin + 1) * nout * 8);
+  b.gacc = alloc(size_t(s.off.total) * 8);
+  b.total = cur;
+  return b;
+}
+
 size_t workspace_bytes(const Plan& p, int op) {
   size_t mx = 0;
   for (const auto& s : p.sys) {
-    const size_t b = workspace_layout(p, s, op, s.Wc).total;
+    const size_t b = (op == QMC_OP_LOGPSI_VJP || op == QMC_OP_LOSS_GRAD) ? bwd_layout(p, s, s.Wc).total
+                                                                          : workspace_layout(p, s, op, s.Wc).total;
     if (b > mx) mx = b;
   }
   return mx + 256;

@@ -48,6 +48,7 @@ struct GemmArgs {
   int K, Ncols;
   int Rp, T, act, vmode;
   int transw;
+  const void* aux;  // act == 2: out = acc * (1 - aux^2), aux addressed like Y (tanh backward)
 };
 
 hipError_t launch_gemm(GemmKind kind, const GemmArgs& a, hipStream_t st);
@@ -84,9 +85,10 @@ hipError_t launch_envelope(const SysDev& s, int spin, const S* phi, const S* pi,
 
 // Determinants of A-jets: one problem per (walker, spin, det).
 //   ajet: per walker [spin][det][rows][n][n] (rows = T + 2 padded to Rp, or 1).
+//   ainv (optional): A^-1 per spin block, [spin][W][det][n][n] (spin 1 after all of spin 0).
 template <typename S>
 hipError_t launch_det(const SysDev& s, const S* ajet, int64_t W, int jet, double* ld, double* sg,
-                      double* g, double* lap, hipStream_t st);
+                      double* g, double* lap, double* ainv, hipStream_t st);
 
 // Generic batched determinant jets (float64), one n x n problem per matrix.
 hipError_t launch_det_generic(int64_t nmat, int n, int ntan, const double* jets, double* ld,
@@ -102,5 +104,43 @@ hipError_t launch_propose(const double* r, const double* noise, double step, int
                           hipStream_t st);
 hipError_t launch_accept(int64_t W, int N3, const double* rp, const double* lp_prop, const double* u,
                          double* r, double* logpsi, uint8_t* accepted, hipStream_t st);
+
+// ---------------------------------------------------------------- backward
+
+// part[split][m][n] = sum_{rows r of the split} X[r][m] G[r][n] (m = Kin: ones, bias)
+// then gW[m][n] += sum_split (m < Kin), gb[n] += bias row.  Rows addressed like GemmArgs.
+struct WgradArgs {
+  const void* X;
+  int64_t ldx, xrpw, xws;
+  const void* G;
+  int64_t ldg, grpw, gws;
+  int64_t rows;
+  int Kin, Nout, ones;
+  double* part;
+  int64_t rows_per_split;
+  int max_split;
+};
+hipError_t launch_wgrad(GemmKind kind, const WgradArgs& a, double* gW, int64_t ldgw, double* gb, hipStream_t st);
+
+template <typename S>
+hipError_t launch_tanh_bwd(int64_t n, const S* ybar, const S* t, S* z, hipStream_t st);
+template <typename S>
+hipError_t launch_add(int64_t n, const S* a, const S* b, S* o, hipStream_t st);
+hipError_t launch_fill(int64_t n, double v, double* p, hipStream_t st);
+template <typename S>
+hipError_t launch_cast(int64_t n, const double* src, S* dst, hipStream_t st);
+hipError_t launch_rowsum(const double* src, int64_t R, int64_t C, int64_t ld, double* dst, hipStream_t st);
+hipError_t launch_loss_weights(const double* e, int64_t W, double* stats, double* g, double* e_mean,
+                               hipStream_t st);
+template <typename S>
+hipError_t launch_combine_bwd(const SysDev& s, const S* c, const double* ld, const double* sg, const double* gbar,
+                              int64_t W, double* lbar, double* cpart, hipStream_t st);
+template <typename S>
+hipError_t launch_orb_bwd(const SysDev& s, int spin, const double* lbar, const double* ainv, const S* phi,
+                          const S* pi, const S* sg, const double* en, int64_t W, S* phibar, double* pipart,
+                          double* sgpart, hipStream_t st);
+template <typename S>
+hipError_t launch_agg_bwd(const SysDev& s, const S* mbar, const S* h, const S* wsame, const S* wopp, const S* wnuc,
+                          const S* Y, int64_t W, S* hbar, S* wbs, S* wbo, S* wbn, double* ypart, hipStream_t st);
 
 }  // namespace qmc

@@ -490,7 +490,7 @@ __global__ __launch_bounds__(64) void det_kernel(const S* __restrict__ src, int6
                                                  int64_t stride_inner, int rows, int n, int ntan, int jet,
                                                  int64_t out_outer, int64_t out_off, double* __restrict__ ld,
                                                  double* __restrict__ sg, double* __restrict__ gout,
-                                                 double* __restrict__ lapout) {
+                                                 double* __restrict__ lapout, double* __restrict__ ainv) {
   __shared__ double Mx[DMAX][2 * DMAX + 1];
   __shared__ double dA[DMAX][DMAX + 1];
   __shared__ double Xs[DMAX][DMAX + 1];
@@ -565,6 +565,8 @@ __global__ __launch_bounds__(64) void det_kernel(const S* __restrict__ src, int6
       sg[oi] = 0.0;
       if (jet) lapout[oi] = 0.0;
     }
+    if (ainv)
+      for (int e = lane; e < nn; e += 64) ainv[pb * nn + e] = 0.0;
     if (jet)
       for (int c = lane; c < ntan; c += 64) gout[oi * ntan + c] = 0.0;
     return;
@@ -573,6 +575,8 @@ __global__ __launch_bounds__(64) void det_kernel(const S* __restrict__ src, int6
     ld[oi] = logdet;
     sg[oi] = sgn;
   }
+  if (ainv)
+    for (int e = lane; e < nn; e += 64) ainv[pb * nn + e] = Mx[e / n][n + e % n];
   if (!jet) return;
   // A^-1 sits in Mx[:, n:2n]
   double qacc = 0.0;
@@ -609,7 +613,7 @@ __global__ __launch_bounds__(64) void det_kernel(const S* __restrict__ src, int6
 
 template <typename S>
 hipError_t launch_det(const SysDev& s, const S* ajet, int64_t W, int jet, double* ld, double* sg, double* g,
-                      double* lap, hipStream_t st) {
+                      double* lap, double* ainv, hipStream_t st) {
   const int Rp = jet ? s.Rp : 1;
   const int64_t wstride = (int64_t)s.ndet * Rp * (s.nup * s.nup + s.ndn * s.ndn);
   for (int spin = 0; spin < 2; ++spin) {
@@ -620,7 +624,7 @@ hipError_t launch_det(const SysDev& s, const S* ajet, int64_t W, int jet, double
     ProfScope ps("det_kernel", st);
     hipLaunchKernelGGL(det_kernel<S>, dim3((unsigned)(W * s.ndet)), dim3(64), 0, st, ajet + soff, wstride, s.ndet,
                        (int64_t)Rp * n * n, Rp, n, s.T, jet, (int64_t)2 * s.ndet, (int64_t)spin * s.ndet, ld, sg, g,
-                       lap);
+                       lap, ainv ? ainv + (spin ? (int64_t)W * s.ndet * s.nup * s.nup : 0) : nullptr);
   }
   return hipGetLastError();
 }
@@ -629,7 +633,7 @@ hipError_t launch_det_generic(int64_t nmat, int n, int ntan, const double* jets,
                               double* lap, hipStream_t st) {
   if (n < 1 || n > DMAX) return hipErrorInvalidValue;
   hipLaunchKernelGGL(det_kernel<double>, dim3((unsigned)nmat), dim3(64), 0, st, jets, (int64_t)(ntan + 2) * n * n, 1,
-                     (int64_t)0, ntan + 2, n, ntan, 1, (int64_t)1, (int64_t)0, ld, sg, g, lap);
+                     (int64_t)0, ntan + 2, n, ntan, 1, (int64_t)1, (int64_t)0, ld, sg, g, lap, nullptr);
   return hipGetLastError();
 }
 
@@ -775,7 +779,7 @@ hipError_t launch_accept(int64_t W, int N3, const double* rp, const double* lp_p
   template hipError_t launch_envelope<S>(const SysDev&, int, const S*, const S*, const S*, const double*,       \
                                          int64_t, int, S*, hipStream_t);                                        \
   template hipError_t launch_det<S>(const SysDev&, const S*, int64_t, int, double*, double*, double*, double*, \
-                                    hipStream_t);                                                               \
+                                    double*, hipStream_t);                                                             \
   template hipError_t launch_combine<S>(const SysDev&, const S*, const double*, const double*, const double*,    \
                                         const double*, const double*, int64_t, int, double*, double*, double*,  \
                                         double*, double*, hipStream_t);

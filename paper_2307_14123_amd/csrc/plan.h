@@ -49,7 +49,7 @@ struct Plan {
   int64_t max_chunk_bytes;
 };
 
-// Byte offsets of the buffers one chunk of one system uses.
+// Byte offsets of the buffers one chunk of one system uses (forward ops).
 struct Workspace {
   size_t geom, vpot;
   size_t rho[3], ehid[3], wjet[3];
@@ -57,9 +57,21 @@ struct Workspace {
   size_t phi[2], ajet;
   size_t dld, dsg, dg, dlap;
   size_t lp_prop;
-  // backward (value mode)
-  size_t st_f, st_h, st_m, st_ehid, st_w, st_t0;
-  size_t gbar_f, gbar_h, gbar_m, gbar_w, gbar_e, gbar_phi, gpart, wts;
+  size_t total;
+};
+
+// Buffers of the parameter backward: a value-only forward that keeps every
+// layer's activations (stash), then the cotangents.  Per-layer arrays hold L
+// consecutive blocks.
+struct BwdWorkspace {
+  // stash
+  size_t geom, rho[3], ehid[3], wv[3], x0, finit, fst, hst, mst, tst, phi[2], aval, dld, dsg, ainv;
+  int64_t blk_e[3], blk_f, blk_m;  // bytes of one layer block (edges per type, node rows, messages)
+  // cotangents
+  size_t gbar, stats, lbar, cpart, phibar[2], pipart, sgpart, fbar, fbar2, zbar, hbar, mbar, wbar[3], ebar, ypart;
+  size_t wpart, gacc;
+  int64_t rows_per_split;
+  int max_split;
   size_t total;
 };
 
@@ -67,6 +79,7 @@ bool compute_offsets(const qmc_system& s, const qmc_ansatz& a, ParamOffsets* off
 size_t act_bytes(qmc_precision p);
 // jet = true: value, 3N tangent and Laplacian rows; false: value rows only.
 Workspace workspace_layout(const Plan& p, const SysPlan& s, int op, int64_t wc);
+BwdWorkspace bwd_layout(const Plan& p, const SysPlan& s, int64_t wc);
 size_t workspace_bytes(const Plan& p, int op);
 
 }  // namespace qmc

@@ -255,3 +255,27 @@ def profile_report(reset: bool = True):
         name, n, ms = line.rsplit(" ", 2)
         out[name] = (int(n), float(ms))
     return out
+
+
+class LogPsi(torch.autograd.Function):
+    """log|psi| of every walker as a differentiable function of the parameters.
+
+    Forward: qmc_logpsi.  Backward: the hand-written vector-Jacobian product
+    qmc_logpsi_vjp (positions get no gradient)."""
+
+    @staticmethod
+    def forward(ctx, params, r, plan):
+        lp, _ = plan.logpsi(params, r)
+        ctx.plan = plan
+        ctx.save_for_backward(params, r)
+        return lp
+
+    @staticmethod
+    def backward(ctx, g):
+        params, r = ctx.saved_tensors
+        grad = ctx.plan.logpsi_vjp(params, r, g.to(torch.float64).contiguous())
+        return grad, None, None
+
+
+def logpsi_autograd(plan, params, r):
+    return LogPsi.apply(params, r, plan)
