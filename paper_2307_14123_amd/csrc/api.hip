@@ -348,7 +348,7 @@ static qmc_status backward_chunk(const Plan& P, const SysPlan& s, const S* prm, 
   double* lbar = (double*)(ws + B.lbar);
   double* cpart = (double*)(ws + B.cpart);
   CK(launch_combine_bwd<S>(dv, prm + O.c, (double*)(ws + B.dld), (double*)(ws + B.dsg), gbar, wc, lbar, cpart, st));
-  CK(launch_rowsum(cpart, wc, ND, ND, gacc + O.c, st));
+  CK(launch_rowsum(cpart, wc, ND, ND, gacc + O.c, (double*)(ws + B.wpart), B.wpart_elems, st));
   S* fL = L > 0 ? F_(B.fst, B.blk_f, L - 1) : F_(B.finit, B.blk_f, L0 - 1);
   S* fbar = (S*)(ws + B.fbar);
   S* fbar2 = (S*)(ws + B.fbar2);
@@ -365,8 +365,8 @@ static qmc_status backward_chunk(const Plan& P, const SysPlan& s, const S* prm, 
     CK(launch_orb_bwd<S>(dv, sp, lbar, ai, (S*)(ws + B.phi[sp]), prm + O.pi[sp], prm + O.sigma[sp], en, wc, phib, pip,
                          sgp, st));
     const int64_t ne = ncol * M * P.ans.n_env;
-    CK(launch_rowsum(pip, wc, ne, ne, gacc + O.pi[sp], st));
-    CK(launch_rowsum(sgp, wc, ne, ne, gacc + O.sigma[sp], st));
+    CK(launch_rowsum(pip, wc, ne, ne, gacc + O.pi[sp], (double*)(ws + B.wpart), B.wpart_elems, st));
+    CK(launch_rowsum(sgp, wc, ne, ne, gacc + O.sigma[sp], (double*)(ws + B.wpart), B.wpart_elems, st));
     WgradArgs a = wg(fL + off_e * D, D, phib, ncol, wc * n, (int)D, (int)ncol, B, ws);
     a.xrpw = n;
     a.xws = N * D;
@@ -396,7 +396,7 @@ static qmc_status backward_chunk(const Plan& P, const SysPlan& s, const S* prm, 
     double* yp = (double*)(ws + B.ypart);
     CK(launch_agg_bwd<S>(dv, mbar, F_(B.hst, B.blk_f, l), F_(B.wv[0], B.blk_e[0], l), F_(B.wv[1], B.blk_e[1], l),
                          F_(B.wv[2], B.blk_e[2], l), prm + Ly.Y, wc, hbar, wb[0], wb[1], wb[2], yp, st));
-    CK(launch_rowsum(yp, wc, M * D, M * D, gacc + Ly.Y, st));
+    CK(launch_rowsum(yp, wc, M * D, M * D, gacc + Ly.Y, (double*)(ws + B.wpart), B.wpart_elems, st));
     CK(launch_wgrad(bk, wg(fin, D, hbar, D, rows, (int)D, (int)D, B, ws), gacc + Ly.Wh, D, gacc + Ly.bh, st));
     GemmArgs gh = dense(hbar, D, prm + Ly.Wh, D, nullptr, fbar2, D, rows, (int)D, (int)D, 1, 0, 0, 1);
     gh.transw = 1;

@@ -162,13 +162,25 @@ __global__ void cast_kernel(int64_t n, const double* __restrict__ src, S* __rest
   if (i < n) dst[i] = (S)src[i];
 }
 
-// dst[c] += sum_r src[r * ld + c], r in order (one thread per column)
-__global__ void rowsum_kernel(const double* __restrict__ src, int64_t R, int64_t C, int64_t ld,
-                              double* __restrict__ dst) {
+// dst[c] += sum_r src[r * ld + c]: rows split in chunks of 64 (one thread per
+// (chunk, column)), then the chunk sums are added in chunk order.
+__global__ void rowsum_partial_kernel(const double* __restrict__ src, int64_t R, int64_t C, int64_t ld,
+                                      double* __restrict__ part) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t k = blockIdx.y;
+  if (c >= C) return;
+  const int64_t r0 = k * 64, r1 = r0 + 64 < R ? r0 + 64 : R;
+  double s = 0.0;
+  for (int64_t r = r0; r < r1; ++r) s += src[r * ld + c];
+  part[k * C + c] = s;
+}
+
+__global__ void rowsum_final_kernel(const double* __restrict__ part, int64_t nchunk, int64_t C,
+                                    double* __restrict__ dst) {
   const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= C) return;
   double s = 0.0;
-  for (int64_t r = 0; r < R; ++r) s += src[r * ld + c];
+  for (int64_t k = 0; k < nchunk; ++k) s += part[k * C + c];
   dst[c] += s;
 }
 
@@ -196,10 +208,15 @@ hipError_t launch_cast(int64_t n, const double* src, S* dst, hipStream_t st) {
   hipLaunchKernelGGL(cast_kernel<S>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, src, dst);
   return hipGetLastError();
 }
-hipError_t launch_rowsum(const double* src, int64_t R, int64_t C, int64_t ld, double* dst, hipStream_t st) {
+hipError_t launch_rowsum(const double* src, int64_t R, int64_t C, int64_t ld, double* dst, double* scratch,
+                         int64_t scratch_elems, hipStream_t st) {
   if (R <= 0 || C <= 0) return hipSuccess;
+  const int64_t nchunk = (R + 63) / 64;
+  if (nchunk * C > scratch_elems || nchunk > 65535) return hipErrorInvalidValue;
   ProfScope ps("rowsum_kernel", st);
-  hipLaunchKernelGGL(rowsum_kernel, dim3((unsigned)((C + 127) / 128)), dim3(128), 0, st, src, R, C, ld, dst);
+  hipLaunchKernelGGL(rowsum_partial_kernel, dim3((unsigned)((C + 127) / 128), (unsigned)nchunk), dim3(128), 0, st, src,
+                     R, C, ld, scratch);
+  hipLaunchKernelGGL(rowsum_final_kernel, dim3((unsigned)((C + 127) / 128)), dim3(128), 0, st, scratch, nchunk, C, dst);
   return hipGetLastError();
 }
 

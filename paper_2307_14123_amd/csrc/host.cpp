@@ -164,7 +164,13 @@ BwdWorkspace bwd_layout(const Plan& p, const SysPlan& s, int64_t wc) {
   if (F > kin) kin = F;
   int64_t nout = D;
   if (ND * nmax > nout) nout = ND * nmax;
-  b.wpart = alloc(size_t(b.max_split) * (kin + 1) * nout * 8);
+  b.wpart_elems = int64_t(b.max_split) * (kin + 1) * nout;
+  {
+    // the same scratch serves the row sums: chunks of 64 walkers x one walker's columns
+    const int64_t rs = ((wc + 63) / 64) * (ND * nmax * M * p.ans.n_env + M * D + ND);
+    if (rs > b.wpart_elems) b.wpart_elems = rs;
+  }
+  b.wpart = alloc(size_t(b.wpart_elems) * 8);
   b.gacc = alloc(size_t(s.off.total) * 8);
   b.total = cur;
   return b;

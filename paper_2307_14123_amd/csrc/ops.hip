@@ -259,138 +259,192 @@ hipError_t launch_init_features(const SysDev& s, const double* ee, const double*
 // ---------------------------------------------------------------- message aggregation
 
 // m_i = [mean_{j same} w_same(d_ij) h_j, mean_{j opp} w_opp(d_ij) h_j, mean_I w_nuc(d_iI) Y_I]
-// propagated through the jets with the product rule.  Block: (walker, column
-// chunk of DC); thread: (receiver i, column).  The senders' h jets of the
-// walker for the chunk are staged in LDS and reused by every receiver.
+// propagated through the jets with the product rule.
+//
+// Block: (walker, column chunk of DC).  Thread: (receiver i, column d).  Each
+// thread keeps, for every sender j, the filter value w(d_ij), its derivative
+// w'(d_ij), the filter Laplacian and the sender's value row in registers, so
+// the row loop only touches registers and LDS.  The senders' jet rows are
+// streamed through LDS in chunks of RC rows (all receivers of the walker
+// reuse them).  Tangent row c = 3k + a gets, besides sum_j w_ij dh_j/dx_c,
+//   k == i:  sum_j h_j w'_ij u_ij[a]          (dd_ij/dr_i = u_ij)
+//   k != i:  -h_k w'_ik u_ik[a]               (dd_ik/dr_k = -u_ik)
+// and the Laplacian row adds sum_j h_j (2 w'' + 4 w'/d) + 2 sum_c dw/dx_c dh_j/dx_c,
+// whose cross term is accumulated while the tangent rows stream past.
 template <typename S, int NMAX>
-__global__ void aggregate_kernel(SysDev s, const S* __restrict__ h, const S* __restrict__ wsame,
-                                 const S* __restrict__ wopp, const S* __restrict__ wnuc, const S* __restrict__ Y,
-                                 const double* __restrict__ ee, const double* __restrict__ en, int jet, int DC,
-                                 S* __restrict__ m) {
+__global__ __launch_bounds__(NMAX >= 32 ? 256 : 512) void aggregate_kernel(SysDev s, const S* __restrict__ h, const S* __restrict__ wsame,
+                                                        const S* __restrict__ wopp, const S* __restrict__ wnuc,
+                                                        const S* __restrict__ Y, const double* __restrict__ ee,
+                                                        const double* __restrict__ en, int jet, int DC, int RC,
+                                                        S* __restrict__ m) {
   extern __shared__ __align__(16) unsigned char smem[];
-  S* hs = (S*)smem;  // [N][Rp][DC]
-  const int N = s.N, D = s.D;
+  const int N = s.N, M = s.M, D = s.D;
   const int Rp = jet ? s.Rp : 1;
   const int Re = jet ? 4 : 1;
   const int64_t w = blockIdx.x;
   const int d0 = blockIdx.y * DC;
-  const S* hw = h + w * N * Rp * D;
-  for (int e = threadIdx.x; e < N * Rp * DC; e += blockDim.x) {
-    const int x = e % DC;
-    const int jq = e / DC;
-    hs[e] = (d0 + x < D) ? hw[(int64_t)jq * D + d0 + x] : S(0);
+  S* hs = (S*)smem;               // [N][RC][DC]
+  S* gu = hs + N * RC * DC;       // [N][N][4]: d_ij, unit vector of r_i - r_j
+  S* gn = gu + N * N * 4;         // [N][M][4]
+  S* wns = gn + N * M * 4;        // [N][M][3][DC]: nuclear filter jets
+  S* ys = wns + N * M * 3 * DC;   // [M][DC]
+  const int nt = blockDim.x;
+  for (int e = threadIdx.x; e < N * N * 4; e += nt) gu[e] = (S)ee[w * N * N * 4 + e];
+  for (int e = threadIdx.x; e < N * M * 4; e += nt) gn[e] = (S)en[w * N * M * 4 + e];
+  for (int e = threadIdx.x; e < N * M * 3 * DC; e += nt) {
+    const int x = e % DC, r3 = (e / DC) % 3, iI = e / (3 * DC);
+    wns[e] = (d0 + x < D && (jet || r3 == 0)) ? wnuc[((w * s.P2 + iI) * Re + r3) * D + d0 + x] : S(0);
   }
-  __syncthreads();
+  for (int e = threadIdx.x; e < M * DC; e += nt) {
+    const int x = e % DC, I = e / DC;
+    ys[e] = (d0 + x < D) ? Y[I * D + d0 + x] : S(0);
+  }
   const int dd = threadIdx.x % DC;
   const int i = threadIdx.x / DC;
   const int d = d0 + dd;
-  if (i >= N || d >= D) return;
+  const bool active = (i < N) && (d < D);
   const bool up = i < s.nup;
   const int nsame = (up ? s.nup : s.ndn) - 1;
   const int nopp = up ? s.ndn : s.nup;
   const S inv_s = nsame > 0 ? S(1) / S(nsame) : S(0);
   const S inv_o = nopp > 0 ? S(1) / S(nopp) : S(0);
-  const double* eei = ee + (w * N + i) * N * 4;
-
-  // filter values w(d_ij) at this column for every sender
-  S wv[NMAX];
+  S wv[NMAX], wd[NMAX], lw[NMAX], h0[NMAX];
 #pragma unroll
   for (int j = 0; j < NMAX; ++j) {
     wv[j] = 0;
-    if (j < N && j != i) {
+    wd[j] = 0;
+    lw[j] = 0;
+    h0[j] = 0;
+    if (active && j < N && j != i) {
       int type;
       const int p = ee_pair(s, i, j, type);
       const int P = type ? s.P1 : s.P0;
-      const S* wt = type ? wopp : wsame;
-      wv[j] = wt[((w * P + p) * Re) * D + d];
+      const S* wt = (type ? wopp : wsame) + ((w * P + p) * Re) * D + d;
+      wv[j] = wt[0];
+      if (jet) {
+        wd[j] = wt[D];
+        lw[j] = wt[2 * D];  // w'' for now; combined with w' / d below
+      }
     }
   }
-  auto wjet = [&](int j, int row) -> S {
-    int type;
-    const int p = ee_pair(s, i, j, type);
-    const int P = type ? s.P1 : s.P0;
-    const S* wt = type ? wopp : wsame;
-    return wt[((w * P + p) * Re + row) * D + d];
-  };
-  const S* Yd = Y + d;
-  const double* eni = en + (w * N + i) * s.M * 4;
-  S* mo = m + (w * N + i) * (int64_t)Rp * 3 * D + d;
-
-  for (int q = 0; q < Rp; ++q) {
-    S aup = 0, adn = 0;
+  __syncthreads();
+  if (jet) {
 #pragma unroll
-    for (int j = 0; j < NMAX; ++j) {
-      if (j < N) {
-        const S hv = hs[(j * Rp + q) * DC + dd];
-        if (j < s.nup)
-          aup += wv[j] * hv;
-        else
-          adn += wv[j] * hv;
-      }
+    for (int j = 0; j < NMAX; ++j)
+      if (active && j < N && j != i) lw[j] = S(2) * lw[j] + S(4) * wd[j] / gu[(i * N + j) * 4];
+  }
+  S lx_up = 0, lx_dn = 0;  // Laplacian-row terms gathered while the tangent rows stream past
+  S* mrow = m + ((w * N + i) * (int64_t)Rp) * 3 * D + d;
+  const S invM = S(1) / S(M);
+  for (int q0 = 0; q0 < Rp; q0 += RC) {
+    __syncthreads();
+    for (int e = threadIdx.x; e < N * RC * DC; e += nt) {
+      const int x = e % DC, qq = (e / DC) % RC, j = e / (RC * DC);
+      const int q = q0 + qq;
+      hs[e] = (q < Rp && d0 + x < D) ? h[((w * N + j) * Rp + q) * (int64_t)D + d0 + x] : S(0);
     }
-    S nuc = 0;
-    if (jet && q >= 1 && q <= s.T) {
-      const int c = q - 1, k = c / 3, a = c % 3;
-      if (k == i) {
-        for (int j = 0; j < N; ++j) {
-          if (j == i) continue;
-          const S corr = hs[(j * Rp) * DC + dd] * wjet(j, 1) * (S)eei[j * 4 + 1 + a];
+    __syncthreads();
+    if (!active) continue;
+    if (q0 == 0) {
+#pragma unroll
+      for (int j = 0; j < NMAX; ++j)
+        if (j < N) h0[j] = hs[(j * RC) * DC + dd];
+    }
+    const int qe = (q0 + RC < Rp) ? q0 + RC : Rp;
+    for (int q = q0; q < qe; ++q) {
+      const int qq = q - q0;
+      S aup = 0, adn = 0;
+#pragma unroll
+      for (int j = 0; j < NMAX; ++j) {
+        if (j < N) {
+          const S hv = hs[(j * RC + qq) * DC + dd];
           if (j < s.nup)
-            aup += corr;
+            aup += wv[j] * hv;
           else
-            adn += corr;
+            adn += wv[j] * hv;
         }
-        for (int I = 0; I < s.M; ++I)
-          nuc += wnuc[((w * (int64_t)s.P2 + i * s.M + I) * Re + 1) * D + d] * (S)eni[I * 4 + 1 + a] * Yd[I * D];
-      } else {
-        const S corr = -hs[(k * Rp) * DC + dd] * wjet(k, 1) * (S)eei[k * 4 + 1 + a];
-        if (k < s.nup)
-          aup += corr;
-        else
-          adn += corr;
       }
-    } else if (jet && q == s.T + 1) {
-      for (int j = 0; j < N; ++j) {
-        if (j == i) continue;
-        const double* g = eei + j * 4;
-        const S w1 = wjet(j, 1), w2 = wjet(j, 2);
-        const S lapw = S(2) * w2 + S(4) * w1 / (S)g[0];
-        S cross = 0;
-        for (int a = 0; a < 3; ++a)
-          cross += (S)g[1 + a] * (hs[(j * Rp + 1 + 3 * i + a) * DC + dd] - hs[(j * Rp + 1 + 3 * j + a) * DC + dd]);
-        const S corr = hs[(j * Rp) * DC + dd] * lapw + S(2) * w1 * cross;
-        if (j < s.nup)
-          aup += corr;
-        else
-          adn += corr;
+      S nuc = 0;
+      if (jet && q >= 1 && q <= s.T) {
+        const int c = q - 1, k = c / 3, a = c % 3;
+        if (k == i) {
+#pragma unroll
+          for (int j = 0; j < NMAX; ++j) {
+            if (j < N && j != i) {
+              const S cw = wd[j] * gu[(i * N + j) * 4 + 1 + a];
+              const S hq = hs[(j * RC + qq) * DC + dd];
+              if (j < s.nup) {
+                aup += h0[j] * cw;
+                lx_up += S(2) * cw * hq;
+              } else {
+                adn += h0[j] * cw;
+                lx_dn += S(2) * cw * hq;
+              }
+            }
+          }
+          for (int I = 0; I < M; ++I)
+            nuc += wns[((i * M + I) * 3 + 1) * DC + dd] * gn[(i * M + I) * 4 + 1 + a] * ys[I * DC + dd];
+        } else {
+          S wdk = 0, h0k = 0;
+#pragma unroll
+          for (int j = 0; j < NMAX; ++j)
+            if (j == k) {
+              wdk = wd[j];
+              h0k = h0[j];
+            }
+          const S cw = wdk * gu[(i * N + k) * 4 + 1 + a];
+          const S corr = -h0k * cw;
+          const S lx = S(-2) * cw * hs[(k * RC + qq) * DC + dd];
+          if (k < s.nup) {
+            aup += corr;
+            lx_up += lx;
+          } else {
+            adn += corr;
+            lx_dn += lx;
+          }
+        }
+      } else if (jet && q == s.T + 1) {
+#pragma unroll
+        for (int j = 0; j < NMAX; ++j) {
+          if (j < N && j != i) {
+            if (j < s.nup)
+              aup += h0[j] * lw[j];
+            else
+              adn += h0[j] * lw[j];
+          }
+        }
+        aup += lx_up;
+        adn += lx_dn;
+        for (int I = 0; I < M; ++I) {
+          const S* wn = wns + ((i * M + I) * 3) * DC + dd;
+          nuc += (wn[2 * DC] + S(2) * wn[DC] / gn[(i * M + I) * 4]) * ys[I * DC + dd];
+        }
+      } else if (q == 0) {
+        for (int I = 0; I < M; ++I) nuc += wns[((i * M + I) * 3) * DC + dd] * ys[I * DC + dd];
       }
-      for (int I = 0; I < s.M; ++I) {
-        const S* wn = wnuc + ((w * (int64_t)s.P2 + i * s.M + I) * Re) * D + d;
-        nuc += (wn[2 * D] + S(2) * wn[D] / (S)eni[I * 4]) * Yd[I * D];
-      }
-    } else if (q == 0) {
-      for (int I = 0; I < s.M; ++I) nuc += wnuc[((w * (int64_t)s.P2 + i * s.M + I) * Re) * D + d] * Yd[I * D];
+      S* row = mrow + (int64_t)q * 3 * D;
+      row[0] = (up ? aup : adn) * inv_s;
+      row[D] = (up ? adn : aup) * inv_o;
+      row[2 * D] = nuc * invM;
     }
-    const S ms = (up ? aup : adn) * inv_s;
-    const S mop = (up ? adn : aup) * inv_o;
-    S* row = mo + (int64_t)q * 3 * D;
-    row[0] = ms;
-    row[D] = mop;
-    row[2 * D] = nuc / S(s.M);
   }
 }
 
 template <typename S, int NMAX>
 static hipError_t agg_launch(const SysDev& s, const S* h, const S* ws, const S* wo, const S* wn, const S* Y,
                              const double* ee, const double* en, int64_t W, int jet, S* m, hipStream_t st) {
-  const int Rp = jet ? s.Rp : 1;
-  int DC = 64;
-  while (DC > 1 && (DC * s.N > 1024 || (size_t)s.N * Rp * DC * sizeof(S) > 64 * 1024)) DC >>= 1;
-  const size_t lds = (size_t)s.N * Rp * DC * sizeof(S);
+  const int RC = jet ? 16 : 1;
+  int DC = 1;
+  while (DC < s.D && DC < 64) DC <<= 1;
+  auto lds = [&](int dc) {
+    return (size_t)(s.N * RC * dc + s.N * s.N * 4 + s.N * s.M * 4 + s.N * s.M * 3 * dc + s.M * dc) * sizeof(S);
+  };
+  const int max_threads = NMAX >= 32 ? 256 : 512;
+  while (DC > 1 && (DC * s.N > max_threads || lds(DC) > 64 * 1024)) DC >>= 1;
   ProfScope ps("aggregate_kernel", st);
   dim3 grid((unsigned)W, (unsigned)((s.D + DC - 1) / DC));
-  hipLaunchKernelGGL((aggregate_kernel<S, NMAX>), grid, dim3(DC * s.N), lds, st, s, h, ws, wo, wn, Y, ee, en, jet,
-                     DC, m);
+  hipLaunchKernelGGL((aggregate_kernel<S, NMAX>), grid, dim3(DC * s.N), lds(DC), st, s, h, ws, wo, wn, Y, ee, en, jet,
+                     DC, RC, m);
   return hipGetLastError();
 }
 
@@ -491,11 +545,16 @@ __global__ __launch_bounds__(64) void det_kernel(const S* __restrict__ src, int6
                                                  int64_t out_outer, int64_t out_off, double* __restrict__ ld,
                                                  double* __restrict__ sg, double* __restrict__ gout,
                                                  double* __restrict__ lapout, double* __restrict__ ainv) {
-  __shared__ double Mx[DMAX][2 * DMAX + 1];
-  __shared__ double dA[DMAX][DMAX + 1];
-  __shared__ double Xs[DMAX][DMAX + 1];
-  __shared__ double fcol[DMAX];
-  __shared__ int piv_s;
+  // LDS sized for this n: augmented [n][2n+1], dA [n][n+1], X [n][n+1], pivot column [n]
+  extern __shared__ __align__(16) unsigned char dsm[];
+  double* Mx_ = (double*)dsm;
+  double* dA_ = Mx_ + n * (2 * n + 1);
+  double* Xs_ = dA_ + n * (n + 1);
+  double* fcol = Xs_ + n * (n + 1);
+  int* piv_p = (int*)(fcol + n);
+#define Mx(r, c) Mx_[(r) * (2 * n + 1) + (c)]
+#define dA(r, c) dA_[(r) * (n + 1) + (c)]
+#define Xs(r, c) Xs_[(r) * (n + 1) + (c)]
   const int lane = threadIdx.x;
   const int64_t pb = blockIdx.x;
   const int64_t o = pb / n_inner;
@@ -506,7 +565,7 @@ __global__ __launch_bounds__(64) void det_kernel(const S* __restrict__ src, int6
   (void)rows;
   for (int e = lane; e < n * 2 * n; e += 64) {
     const int r = e / (2 * n), c = e % (2 * n);
-    Mx[r][c] = c < n ? (double)A[r * n + c] : (c - n == r ? 1.0 : 0.0);
+    Mx(r, c) = c < n ? (double)A[r * n + c] : (c - n == r ? 1.0 : 0.0);
   }
   __syncthreads();
   double logdet = 0.0, sgn = 1.0;
@@ -516,7 +575,7 @@ __global__ __launch_bounds__(64) void det_kernel(const S* __restrict__ src, int6
     double best = -1.0;
     int bi = col;
     for (int r = col + lane; r < n; r += 64) {
-      const double v = fabs(Mx[r][col]);
+      const double v = fabs(Mx(r, col));
       if (v > best) {
         best = v;
         bi = r;
@@ -530,32 +589,32 @@ __global__ __launch_bounds__(64) void det_kernel(const S* __restrict__ src, int6
         bi = oidx;
       }
     }
-    if (lane == 0) piv_s = bi;
+    if (lane == 0) *piv_p = bi;
     __syncthreads();
-    const int pr = piv_s;
+    const int pr = *piv_p;
     if (!(best > 0.0)) {
       singular = true;
       break;
     }
     if (pr != col) {
       for (int c = lane; c < 2 * n; c += 64) {
-        const double tmp = Mx[pr][c];
-        Mx[pr][c] = Mx[col][c];
-        Mx[col][c] = tmp;
+        const double tmp = Mx(pr, c);
+        Mx(pr, c) = Mx(col, c);
+        Mx(col, c) = tmp;
       }
       sgn = -sgn;
     }
     __syncthreads();
-    const double pv = Mx[col][col];
+    const double pv = Mx(col, col);
     logdet += log(fabs(pv));
     if (pv < 0) sgn = -sgn;
-    for (int r = lane; r < n; r += 64) fcol[r] = Mx[r][col];
+    for (int r = lane; r < n; r += 64) fcol[r] = Mx(r, col);
     __syncthreads();
-    for (int c = lane; c < 2 * n; c += 64) Mx[col][c] /= pv;
+    for (int c = lane; c < 2 * n; c += 64) Mx(col, c) /= pv;
     __syncthreads();
     for (int e = lane; e < n * 2 * n; e += 64) {
       const int r = e / (2 * n), c = e % (2 * n);
-      if (r != col) Mx[r][c] -= fcol[r] * Mx[col][c];
+      if (r != col) Mx(r, c) -= fcol[r] * Mx(col, c);
     }
     __syncthreads();
   }
@@ -576,26 +635,26 @@ __global__ __launch_bounds__(64) void det_kernel(const S* __restrict__ src, int6
     sg[oi] = sgn;
   }
   if (ainv)
-    for (int e = lane; e < nn; e += 64) ainv[pb * nn + e] = Mx[e / n][n + e % n];
+    for (int e = lane; e < nn; e += 64) ainv[pb * nn + e] = Mx(e / n, n + e % n);
   if (!jet) return;
   // A^-1 sits in Mx[:, n:2n]
   double qacc = 0.0;
   for (int c = 0; c < ntan; ++c) {
     const S* dsrc = A + (int64_t)(1 + c) * nn;
-    for (int e = lane; e < nn; e += 64) dA[e / n][e % n] = (double)dsrc[e];
+    for (int e = lane; e < nn; e += 64) dA(e / n, e % n) = (double)dsrc[e];
     __syncthreads();
     double gpart = 0.0;
     for (int e = lane; e < nn; e += 64) {
       const int a = e / n, b = e % n;
       double x = 0.0;
-      for (int k = 0; k < n; ++k) x += Mx[a][n + k] * dA[k][b];
-      Xs[a][b] = x;
+      for (int k = 0; k < n; ++k) x += Mx(a, n + k) * dA(k, b);
+      Xs(a, b) = x;
       if (a == b) gpart += x;
     }
     __syncthreads();
     for (int e = lane; e < nn; e += 64) {
       const int a = e / n, b = e % n;
-      qacc += Xs[a][b] * Xs[b][a];
+      qacc += Xs(a, b) * Xs(b, a);
     }
     const double gc = wave_sum(gpart);
     if (lane == 0) gout[oi * ntan + c] = gc;
@@ -604,12 +663,17 @@ __global__ __launch_bounds__(64) void det_kernel(const S* __restrict__ src, int6
   double tr = 0.0;
   for (int e = lane; e < nn; e += 64) {
     const int a = e / n, b = e % n;
-    tr += Mx[a][n + b] * (double)lsrc[b * n + a];
+    tr += Mx(a, n + b) * (double)lsrc[b * n + a];
   }
   tr = wave_sum(tr);
   qacc = wave_sum(qacc);
   if (lane == 0) lapout[oi] = tr - qacc;
 }
+#undef Mx
+#undef dA
+#undef Xs
+
+static size_t det_lds(int n) { return (size_t)(n * (2 * n + 1) + 2 * n * (n + 1) + n) * 8 + 16; }
 
 template <typename S>
 hipError_t launch_det(const SysDev& s, const S* ajet, int64_t W, int jet, double* ld, double* sg, double* g,
@@ -622,7 +686,7 @@ hipError_t launch_det(const SysDev& s, const S* ajet, int64_t W, int jet, double
     if (n > DMAX) return hipErrorInvalidValue;
     const int64_t soff = spin ? (int64_t)s.ndet * Rp * s.nup * s.nup : 0;
     ProfScope ps("det_kernel", st);
-    hipLaunchKernelGGL(det_kernel<S>, dim3((unsigned)(W * s.ndet)), dim3(64), 0, st, ajet + soff, wstride, s.ndet,
+    hipLaunchKernelGGL(det_kernel<S>, dim3((unsigned)(W * s.ndet)), dim3(64), det_lds(n), st, ajet + soff, wstride, s.ndet,
                        (int64_t)Rp * n * n, Rp, n, s.T, jet, (int64_t)2 * s.ndet, (int64_t)spin * s.ndet, ld, sg, g,
                        lap, ainv ? ainv + (spin ? (int64_t)W * s.ndet * s.nup * s.nup : 0) : nullptr);
   }
@@ -632,7 +696,7 @@ hipError_t launch_det(const SysDev& s, const S* ajet, int64_t W, int jet, double
 hipError_t launch_det_generic(int64_t nmat, int n, int ntan, const double* jets, double* ld, double* sg, double* g,
                               double* lap, hipStream_t st) {
   if (n < 1 || n > DMAX) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(det_kernel<double>, dim3((unsigned)nmat), dim3(64), 0, st, jets, (int64_t)(ntan + 2) * n * n, 1,
+  hipLaunchKernelGGL(det_kernel<double>, dim3((unsigned)nmat), dim3(64), det_lds(n), st, jets, (int64_t)(ntan + 2) * n * n, 1,
                      (int64_t)0, ntan + 2, n, ntan, 1, (int64_t)1, (int64_t)0, ld, sg, g, lap, nullptr);
   return hipGetLastError();
 }

@@ -70,6 +70,7 @@ struct BwdWorkspace {
   // cotangents
   size_t gbar, stats, lbar, cpart, phibar[2], pipart, sgpart, fbar, fbar2, zbar, hbar, mbar, wbar[3], ebar, ypart;
   size_t wpart, gacc;
+  int64_t wpart_elems;
   int64_t rows_per_split;
   int max_split;
   size_t total;
