@@ -14,6 +14,9 @@
 // into registers (16-byte vectors where the layout allows) while the MFMAs
 // consume the current stage, so each K-step needs one barrier.
 //
+// Both operand tiles keep k contiguous in LDS ([rows][k] and [columns][k]),
+// so one 16-byte LDS read gives a lane its operands of four f32/f64 MFMAs.
+//
 // MFMA shapes: f64 v_mfma_f64_16x16x4, f32 v_mfma_f32_16x16x4, bf16
 // v_mfma_f32_16x16x32 (operands rounded to bf16, float accumulation).  The
 // 16x16 accumulator layouts: f32/bf16: lane l, element i -> row 4*(l/16)+i,
@@ -73,12 +76,13 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs a) {
   constexpr int BK = G::BK;
   constexpr int BM = 16 * MB;
   constexpr int BN = 128;
-  constexpr int APAD = (KIND == GK_BF16) ? 8 : (KIND == GK_F64 ? 1 : 4);
-  constexpr int BPAD = (KIND == GK_BF16) ? 8 : 16;
-  constexpr int ALD = BK + APAD;  // A tile row stride
-  constexpr int BLD = (KIND == GK_BF16) ? BK + BPAD : BN + BPAD;
+  // A tile [BM][BK+pad] and B tile stored transposed [BN][BK+pad]: k is contiguous in both, so a
+  // lane reads its operands for several MFMAs with one 16-byte LDS load
+  constexpr int APAD = (KIND == GK_BF16) ? 8 : 4;
+  constexpr int ALD = BK + APAD;
+  constexpr int BLD = BK + APAD;
   constexpr int ASZ = BM * ALD;
-  constexpr int BSZ = (KIND == GK_BF16) ? BN * BLD : BK * BLD;
+  constexpr int BSZ = BN * BLD;
   __shared__ L As[2][ASZ];
   __shared__ L Bs[2][BSZ];
 
@@ -110,8 +114,9 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs a) {
     akk[u] = (v % AKV) * 4;
     const int64_t r = m0 + arr[u];
     aval[u] = (v < AV) && (r < a.rows);
-    const int64_t rr = aval[u] ? r : 0;
-    arow[u] = X + (rr / a.xrpw) * a.xws + (rr % a.xrpw) * a.ldx;
+    const uint32_t rr = aval[u] ? (uint32_t)r : 0u, rpw = (uint32_t)a.xrpw;
+    const uint32_t qb = rr / rpw;
+    arow[u] = X + (int64_t)qb * a.xws + (int64_t)(rr - qb * rpw) * a.ldx;
   }
   S ra[NA][4], rb[NB][4];
 
@@ -134,23 +139,13 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs a) {
     for (int u = 0; u < NB; ++u) {
       const int v = tid + 256 * u;
       if (v >= BV) continue;
+      const int n = v % BN, kk = (v / BN) * 4;  // 4 consecutive k of output column n
+      const int kg = k0 + kk, ng = n0 + n;
       if (!a.transw) {
-        const int kk = v / (BN / 4), n = (v % (BN / 4)) * 4;
-        const int kg = k0 + kk, ng = n0 + n;
         const S* src = Wt + (int64_t)kg * a.ldw + ng;
-        if (bvec && kg < a.K && ng + 3 < a.Ncols) {
-          const Vec t = *(const Vec*)src;
-          rb[u][0] = t.x;
-          rb[u][1] = t.y;
-          rb[u][2] = t.z;
-          rb[u][3] = t.w;
-        } else {
 #pragma unroll
-          for (int e = 0; e < 4; ++e) rb[u][e] = (kg < a.K && ng + e < a.Ncols) ? src[e] : S(0);
-        }
+        for (int e = 0; e < 4; ++e) rb[u][e] = (ng < a.Ncols && kg + e < a.K) ? src[(int64_t)e * a.ldw] : S(0);
       } else {
-        const int n = v / (BK / 4), kk = (v % (BK / 4)) * 4;
-        const int kg = k0 + kk, ng = n0 + n;
         const S* src = Wt + (int64_t)ng * a.ldw + kg;
         if (bvec && ng < a.Ncols && kg + 3 < a.K) {
           const Vec t = *(const Vec*)src;
@@ -169,31 +164,25 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs a) {
 #pragma unroll
     for (int u = 0; u < NA; ++u) {
       if (tid + 256 * u >= AV) continue;
+      L* dst = &As[buf][arr[u] * ALD + akk[u]];
+      if constexpr (KIND == GK_BF16) {
 #pragma unroll
-      for (int e = 0; e < 4; ++e) As[buf][arr[u] * ALD + akk[u] + e] = (L)ra[u][e];
+        for (int e = 0; e < 4; ++e) dst[e] = (L)ra[u][e];
+      } else {
+        *(Vec*)dst = Vec{ra[u][0], ra[u][1], ra[u][2], ra[u][3]};
+      }
     }
 #pragma unroll
     for (int u = 0; u < NB; ++u) {
       const int v = tid + 256 * u;
       if (v >= BV) continue;
-      if (!a.transw) {
-        const int kk = v / (BN / 4), n = (v % (BN / 4)) * 4;
+      const int n = v % BN, kk = (v / BN) * 4;
+      L* dst = &Bs[buf][n * BLD + kk];
+      if constexpr (KIND == GK_BF16) {
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          if (KIND == GK_BF16)
-            Bs[buf][(n + e) * BLD + kk] = (L)rb[u][e];
-          else
-            Bs[buf][kk * BLD + n + e] = (L)rb[u][e];
-        }
+        for (int e = 0; e < 4; ++e) dst[e] = (L)rb[u][e];
       } else {
-        const int n = v / (BK / 4), kk = (v % (BK / 4)) * 4;
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          if (KIND == GK_BF16)
-            Bs[buf][n * BLD + kk + e] = (L)rb[u][e];
-          else
-            Bs[buf][(kk + e) * BLD + n] = (L)rb[u][e];
-        }
+        *(Vec*)dst = Vec{rb[u][0], rb[u][1], rb[u][2], rb[u][3]};
       }
     }
   };
@@ -228,20 +217,28 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs a) {
           acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv[nb], acc[mb][nb], 0, 0, 0);
       }
     } else {
+      // lane group g supplies k = 4g + kq at MFMA step kq (the same order for A and B)
 #pragma unroll
-      for (int kq = 0; kq < BK / 4; ++kq) {
-        L bv[2];
+      for (int k4 = 0; k4 < BK / 16; ++k4) {
+        Vec bv[2];
 #pragma unroll
-        for (int nb = 0; nb < 2; ++nb) bv[nb] = Bc[(kq * 4 + g) * BLD + wave * 32 + nb * 16 + c];
+        for (int nb = 0; nb < 2; ++nb) bv[nb] = *(const Vec*)&Bc[(wave * 32 + nb * 16 + c) * BLD + k4 * 16 + 4 * g];
 #pragma unroll
         for (int mb = 0; mb < MB; ++mb) {
-          const L av = Ac[(mb * 16 + c) * ALD + kq * 4 + g];
+          const Vec av = *(const Vec*)&Ac[(mb * 16 + c) * ALD + k4 * 16 + 4 * g];
 #pragma unroll
           for (int nb = 0; nb < 2; ++nb) {
-            if constexpr (KIND == GK_F64)
-              acc[mb][nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv[nb], acc[mb][nb], 0, 0, 0);
-            else
-              acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv[nb], acc[mb][nb], 0, 0, 0);
+            if constexpr (KIND == GK_F64) {
+              acc[mb][nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av.x, bv[nb].x, acc[mb][nb], 0, 0, 0);
+              acc[mb][nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av.y, bv[nb].y, acc[mb][nb], 0, 0, 0);
+              acc[mb][nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av.z, bv[nb].z, acc[mb][nb], 0, 0, 0);
+              acc[mb][nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av.w, bv[nb].w, acc[mb][nb], 0, 0, 0);
+            } else {
+              acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.x, bv[nb].x, acc[mb][nb], 0, 0, 0);
+              acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.y, bv[nb].y, acc[mb][nb], 0, 0, 0);
+              acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.z, bv[nb].z, acc[mb][nb], 0, 0, 0);
+              acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.w, bv[nb].w, acc[mb][nb], 0, 0, 0);
+            }
           }
         }
       }
@@ -266,10 +263,33 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs a) {
     grp[mb] = mb / bpg;
     qbase[mb] = (mb - grp[mb] * bpg) * 16;
   }
+  // output row offsets of this lane's 4*MB rows: one 32-bit division per 16-row block, then
+  // stepping through the rows (rows of one lane are consecutive for f32/bf16, 4 apart for f64)
+  int64_t yoff[MB][4];
+  bool yval[MB][4];
+  {
+    const uint32_t rpw = (uint32_t)a.yrpw;
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb) {
+      const int64_t r0 = m0 + mb * 16 + rowof(g4, 0);
+      const uint32_t rr = (uint32_t)r0;
+      uint32_t qb = rr / rpw, rem = rr - qb * rpw;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        yval[mb][i] = (r0 + (rowof(g4, i) - rowof(g4, 0))) < a.rows;
+        yoff[mb][i] = (int64_t)qb * a.yws + (int64_t)rem * a.ldy;
+        const uint32_t step = (uint32_t)(rowof(g4, 1) - rowof(g4, 0));
+        rem += step;
+        while (rem >= rpw) {
+          rem -= rpw;
+          ++qb;
+        }
+      }
+    }
+  }
   auto emit = [&](int mb, int i, int col, S o) {
-    const int64_t r = m0 + mb * 16 + rowof(g4, i);
-    if (r < a.rows && col < a.Ncols) {
-      const int64_t off = (r / a.yrpw) * a.yws + (r % a.yrpw) * a.ldy + col;
+    if (yval[mb][i] && col < a.Ncols) {
+      const int64_t off = yoff[mb][i] + col;
       if (a.act == 2) {
         const S t = ((const S*)a.aux)[off];
         o *= S(1) - t * t;
@@ -415,6 +435,10 @@ static hipError_t launch_kind(const GemmArgs& a, hipStream_t st) {
 
 hipError_t launch_gemm(GemmKind kind, const GemmArgs& a, hipStream_t st) {
   if (a.rows <= 0 || a.Ncols <= 0) return hipSuccess;
+  // row indices and rows-per-block are handled in 32 bits inside the kernel
+  if (a.rows >= (int64_t(1) << 31) || a.xrpw <= 0 || a.yrpw <= 0 || a.xrpw >= (int64_t(1) << 31) ||
+      a.yrpw >= (int64_t(1) << 31))
+    return hipErrorInvalidValue;
   if (!a.vmode && a.Rp == 4 && a.T != 1) return hipErrorInvalidValue;
   if (a.act == 2 && (!a.vmode || !a.aux)) return hipErrorInvalidValue;
   switch (kind) {

@@ -262,32 +262,35 @@ hipError_t launch_init_features(const SysDev& s, const double* ee, const double*
 // propagated through the jets with the product rule.
 //
 // Block: (walker, column chunk of DC).  Thread: (receiver i, column d).  Each
-// thread keeps, for every sender j, the filter value w(d_ij), its derivative
-// w'(d_ij), the filter Laplacian and the sender's value row in registers, so
-// the row loop only touches registers and LDS.  The senders' jet rows are
-// streamed through LDS in chunks of RC rows (all receivers of the walker
-// reuse them).  Tangent row c = 3k + a gets, besides sum_j w_ij dh_j/dx_c,
+// thread keeps the filter values w(d_ij) of its receiver, split into a
+// same-spin and an opposite-spin array (zero elsewhere), and the filter
+// Laplacians in registers.  The senders' jet rows stream through LDS in
+// chunks of RC rows (rows of absent senders up to NMAX are zero, so the sums
+// need no guards); filter derivatives w'(d_ij), the senders' value rows and
+// the geometry sit in LDS.  Tangent row c = 3k + a gets, besides
+// sum_j w_ij dh_j/dx_c:
 //   k == i:  sum_j h_j w'_ij u_ij[a]          (dd_ij/dr_i = u_ij)
 //   k != i:  -h_k w'_ik u_ik[a]               (dd_ik/dr_k = -u_ik)
 // and the Laplacian row adds sum_j h_j (2 w'' + 4 w'/d) + 2 sum_c dw/dx_c dh_j/dx_c,
-// whose cross term is accumulated while the tangent rows stream past.
+// whose cross term accumulates while the tangent rows stream past.
 template <typename S, int NMAX>
-__global__ __launch_bounds__(NMAX >= 32 ? 256 : 512) void aggregate_kernel(SysDev s, const S* __restrict__ h, const S* __restrict__ wsame,
-                                                        const S* __restrict__ wopp, const S* __restrict__ wnuc,
-                                                        const S* __restrict__ Y, const double* __restrict__ ee,
-                                                        const double* __restrict__ en, int jet, int DC, int RC,
-                                                        S* __restrict__ m) {
+__global__ __launch_bounds__(NMAX >= 32 ? 256 : 512) void aggregate_kernel(
+    SysDev s, const S* __restrict__ h, const S* __restrict__ wsame, const S* __restrict__ wopp,
+    const S* __restrict__ wnuc, const S* __restrict__ Y, const double* __restrict__ ee, const double* __restrict__ en,
+    int jet, int DC, int RC, S* __restrict__ m) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int N = s.N, M = s.M, D = s.D;
   const int Rp = jet ? s.Rp : 1;
   const int Re = jet ? 4 : 1;
   const int64_t w = blockIdx.x;
   const int d0 = blockIdx.y * DC;
-  S* hs = (S*)smem;               // [N][RC][DC]
-  S* gu = hs + N * RC * DC;       // [N][N][4]: d_ij, unit vector of r_i - r_j
-  S* gn = gu + N * N * 4;         // [N][M][4]
-  S* wns = gn + N * M * 4;        // [N][M][3][DC]: nuclear filter jets
-  S* ys = wns + N * M * 3 * DC;   // [M][DC]
+  S* hs = (S*)smem;                 // [NMAX][RC][DC], rows of j >= N stay zero
+  S* wdl = hs + NMAX * RC * DC;     // [N][N][DC]: w'(d_ij) (zero on the diagonal)
+  S* h0s = wdl + (jet ? N * N * DC : 0);  // [N][DC]: senders' value rows
+  S* gu = h0s + N * DC;             // [N][N][4]: d_ij, unit vector of r_i - r_j
+  S* gn = gu + N * N * 4;           // [N][M][4]
+  S* wns = gn + N * M * 4;          // [N][M][3][DC]: nuclear filter jets
+  S* ys = wns + N * M * 3 * DC;     // [M][DC]
   const int nt = blockDim.x;
   for (int e = threadIdx.x; e < N * N * 4; e += nt) gu[e] = (S)ee[w * N * N * 4 + e];
   for (int e = threadIdx.x; e < N * M * 4; e += nt) gn[e] = (S)en[w * N * M * 4 + e];
@@ -299,6 +302,19 @@ __global__ __launch_bounds__(NMAX >= 32 ? 256 : 512) void aggregate_kernel(SysDe
     const int x = e % DC, I = e / DC;
     ys[e] = (d0 + x < D) ? Y[I * D + d0 + x] : S(0);
   }
+  if (jet) {
+    for (int e = threadIdx.x; e < N * N * DC; e += nt) {
+      const int x = e % DC, ij = e / DC, ii = ij / N, jj = ij % N;
+      S v = 0;
+      if (ii != jj && d0 + x < D) {
+        int type;
+        const int p = ee_pair(s, ii, jj, type);
+        v = (type ? wopp : wsame)[((w * (type ? s.P1 : s.P0) + p) * Re + 1) * D + d0 + x];
+      }
+      wdl[e] = v;
+    }
+  }
+  for (int e = threadIdx.x; e < NMAX * RC * DC; e += nt) hs[e] = S(0);
   const int dd = threadIdx.x % DC;
   const int i = threadIdx.x / DC;
   const int d = d0 + dd;
@@ -308,32 +324,32 @@ __global__ __launch_bounds__(NMAX >= 32 ? 256 : 512) void aggregate_kernel(SysDe
   const int nopp = up ? s.ndn : s.nup;
   const S inv_s = nsame > 0 ? S(1) / S(nsame) : S(0);
   const S inv_o = nopp > 0 ? S(1) / S(nopp) : S(0);
-  S wv[NMAX], wd[NMAX], lw[NMAX], h0[NMAX];
+  S wsm[NMAX], wop[NMAX], lw[NMAX];
 #pragma unroll
   for (int j = 0; j < NMAX; ++j) {
-    wv[j] = 0;
-    wd[j] = 0;
+    wsm[j] = 0;
+    wop[j] = 0;
     lw[j] = 0;
-    h0[j] = 0;
     if (active && j < N && j != i) {
       int type;
       const int p = ee_pair(s, i, j, type);
-      const int P = type ? s.P1 : s.P0;
-      const S* wt = (type ? wopp : wsame) + ((w * P + p) * Re) * D + d;
-      wv[j] = wt[0];
-      if (jet) {
-        wd[j] = wt[D];
-        lw[j] = wt[2 * D];  // w'' for now; combined with w' / d below
-      }
+      const S* wt = (type ? wopp : wsame) + ((w * (type ? s.P1 : s.P0) + p) * Re) * D + d;
+      if (type)
+        wop[j] = wt[0];
+      else
+        wsm[j] = wt[0];
+      if (jet) lw[j] = wt[2 * D];  // w'' for now; combined with w'/d below
     }
   }
   __syncthreads();
   if (jet) {
 #pragma unroll
     for (int j = 0; j < NMAX; ++j)
-      if (active && j < N && j != i) lw[j] = S(2) * lw[j] + S(4) * wd[j] / gu[(i * N + j) * 4];
+      if (active && j < N && j != i)
+        lw[j] = S(2) * lw[j] + S(4) * wdl[(i * N + j) * DC + dd] / gu[(i * N + j) * 4];
   }
-  S lx_up = 0, lx_dn = 0;  // Laplacian-row terms gathered while the tangent rows stream past
+  S lx_s = 0, lx_o = 0;  // Laplacian-row cross terms, same-spin and opposite-spin senders
+  const bool ups = up;
   S* mrow = m + ((w * N + i) * (int64_t)Rp) * 3 * D + d;
   const S invM = S(1) / S(M);
   for (int q0 = 0; q0 < Rp; q0 += RC) {
@@ -341,80 +357,66 @@ __global__ __launch_bounds__(NMAX >= 32 ? 256 : 512) void aggregate_kernel(SysDe
     for (int e = threadIdx.x; e < N * RC * DC; e += nt) {
       const int x = e % DC, qq = (e / DC) % RC, j = e / (RC * DC);
       const int q = q0 + qq;
-      hs[e] = (q < Rp && d0 + x < D) ? h[((w * N + j) * Rp + q) * (int64_t)D + d0 + x] : S(0);
+      const S v = (q < Rp && d0 + x < D) ? h[((w * N + j) * Rp + q) * (int64_t)D + d0 + x] : S(0);
+      hs[e] = v;
+      if (q == 0) h0s[j * DC + x] = v;
     }
     __syncthreads();
     if (!active) continue;
-    if (q0 == 0) {
-#pragma unroll
-      for (int j = 0; j < NMAX; ++j)
-        if (j < N) h0[j] = hs[(j * RC) * DC + dd];
-    }
     const int qe = (q0 + RC < Rp) ? q0 + RC : Rp;
     for (int q = q0; q < qe; ++q) {
       const int qq = q - q0;
-      S aup = 0, adn = 0;
+      S ms = 0, mo = 0;
 #pragma unroll
       for (int j = 0; j < NMAX; ++j) {
-        if (j < N) {
-          const S hv = hs[(j * RC + qq) * DC + dd];
-          if (j < s.nup)
-            aup += wv[j] * hv;
-          else
-            adn += wv[j] * hv;
-        }
+        const S hv = hs[(j * RC + qq) * DC + dd];
+        ms += wsm[j] * hv;
+        mo += wop[j] * hv;
       }
       S nuc = 0;
       if (jet && q >= 1 && q <= s.T) {
         const int c = q - 1, k = c / 3, a = c % 3;
         if (k == i) {
-#pragma unroll
-          for (int j = 0; j < NMAX; ++j) {
-            if (j < N && j != i) {
-              const S cw = wd[j] * gu[(i * N + j) * 4 + 1 + a];
-              const S hq = hs[(j * RC + qq) * DC + dd];
-              if (j < s.nup) {
-                aup += h0[j] * cw;
-                lx_up += S(2) * cw * hq;
-              } else {
-                adn += h0[j] * cw;
-                lx_dn += S(2) * cw * hq;
-              }
+          for (int j = 0; j < N; ++j) {
+            if (j == i) continue;
+            const S cw = wdl[(i * N + j) * DC + dd] * gu[(i * N + j) * 4 + 1 + a];
+            const S t0 = h0s[j * DC + dd] * cw;
+            const S t1 = S(2) * cw * hs[(j * RC + qq) * DC + dd];
+            if ((j < s.nup) == ups) {
+              ms += t0;
+              lx_s += t1;
+            } else {
+              mo += t0;
+              lx_o += t1;
             }
           }
           for (int I = 0; I < M; ++I)
             nuc += wns[((i * M + I) * 3 + 1) * DC + dd] * gn[(i * M + I) * 4 + 1 + a] * ys[I * DC + dd];
         } else {
-          S wdk = 0, h0k = 0;
-#pragma unroll
-          for (int j = 0; j < NMAX; ++j)
-            if (j == k) {
-              wdk = wd[j];
-              h0k = h0[j];
-            }
-          const S cw = wdk * gu[(i * N + k) * 4 + 1 + a];
-          const S corr = -h0k * cw;
-          const S lx = S(-2) * cw * hs[(k * RC + qq) * DC + dd];
-          if (k < s.nup) {
-            aup += corr;
-            lx_up += lx;
+          const S cw = wdl[(i * N + k) * DC + dd] * gu[(i * N + k) * 4 + 1 + a];
+          const S t0 = -h0s[k * DC + dd] * cw;
+          const S t1 = S(-2) * cw * hs[(k * RC + qq) * DC + dd];
+          if ((k < s.nup) == ups) {
+            ms += t0;
+            lx_s += t1;
           } else {
-            adn += corr;
-            lx_dn += lx;
+            mo += t0;
+            lx_o += t1;
           }
         }
       } else if (jet && q == s.T + 1) {
 #pragma unroll
         for (int j = 0; j < NMAX; ++j) {
-          if (j < N && j != i) {
-            if (j < s.nup)
-              aup += h0[j] * lw[j];
+          if (j < N) {
+            const S t = h0s[j * DC + dd] * lw[j];
+            if ((j < s.nup) == ups)
+              ms += t;
             else
-              adn += h0[j] * lw[j];
+              mo += t;
           }
         }
-        aup += lx_up;
-        adn += lx_dn;
+        ms += lx_s;
+        mo += lx_o;
         for (int I = 0; I < M; ++I) {
           const S* wn = wns + ((i * M + I) * 3) * DC + dd;
           nuc += (wn[2 * DC] + S(2) * wn[DC] / gn[(i * M + I) * 4]) * ys[I * DC + dd];
@@ -423,11 +425,44 @@ __global__ __launch_bounds__(NMAX >= 32 ? 256 : 512) void aggregate_kernel(SysDe
         for (int I = 0; I < M; ++I) nuc += wns[((i * M + I) * 3) * DC + dd] * ys[I * DC + dd];
       }
       S* row = mrow + (int64_t)q * 3 * D;
-      row[0] = (up ? aup : adn) * inv_s;
-      row[D] = (up ? adn : aup) * inv_o;
+      row[0] = ms * inv_s;
+      row[D] = mo * inv_o;
       row[2 * D] = nuc * invM;
     }
   }
+}
+
+// Value rows only (log|psi| without derivatives): one thread per (walker, receiver, column).
+template <typename S>
+__global__ void aggregate_value_kernel(SysDev s, const S* __restrict__ h, const S* __restrict__ wsame,
+                                       const S* __restrict__ wopp, const S* __restrict__ wnuc,
+                                       const S* __restrict__ Y, int64_t W, S* __restrict__ m) {
+  const int N = s.N, D = s.D, M = s.M;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= W * N * D) return;
+  const int d = (int)(t % D);
+  const int i = (int)((t / D) % N);
+  const int64_t w = t / ((int64_t)N * D);
+  const bool up = i < s.nup;
+  const int nsame = (up ? s.nup : s.ndn) - 1;
+  const int nopp = up ? s.ndn : s.nup;
+  S ms = 0, mo = 0;
+  for (int j = 0; j < N; ++j) {
+    if (j == i) continue;
+    int type;
+    const int p = ee_pair(s, i, j, type);
+    const S hv = h[(w * N + j) * D + d];
+    if (type)
+      mo += wopp[(w * s.P1 + p) * D + d] * hv;
+    else
+      ms += wsame[(w * s.P0 + p) * D + d] * hv;
+  }
+  S nuc = 0;
+  for (int I = 0; I < M; ++I) nuc += wnuc[(w * s.P2 + i * M + I) * D + d] * Y[I * D + d];
+  S* row = m + (w * N + i) * 3 * (int64_t)D + d;
+  row[0] = nsame > 0 ? ms / S(nsame) : S(0);
+  row[D] = nopp > 0 ? mo / S(nopp) : S(0);
+  row[2 * D] = nuc / S(M);
 }
 
 template <typename S, int NMAX>
@@ -437,7 +472,9 @@ static hipError_t agg_launch(const SysDev& s, const S* h, const S* ws, const S* 
   int DC = 1;
   while (DC < s.D && DC < 64) DC <<= 1;
   auto lds = [&](int dc) {
-    return (size_t)(s.N * RC * dc + s.N * s.N * 4 + s.N * s.M * 4 + s.N * s.M * 3 * dc + s.M * dc) * sizeof(S);
+    return (size_t)(NMAX * RC * dc + (jet ? s.N * s.N * dc : 0) + s.N * dc + s.N * s.N * 4 + s.N * s.M * 4 +
+                    s.N * s.M * 3 * dc + s.M * dc) *
+           sizeof(S);
   };
   const int max_threads = NMAX >= 32 ? 256 : 512;
   while (DC > 1 && (DC * s.N > max_threads || lds(DC) > 64 * 1024)) DC >>= 1;
@@ -451,6 +488,13 @@ static hipError_t agg_launch(const SysDev& s, const S* h, const S* ws, const S* 
 template <typename S>
 hipError_t launch_aggregate(const SysDev& s, const S* h, const S* wsame, const S* wopp, const S* wnuc, const S* Y,
                             const double* ee, const double* en, int64_t W, int jet, S* m, hipStream_t st) {
+  if (!jet) {
+    const int64_t n = W * s.N * s.D;
+    ProfScope ps("aggregate_value_kernel", st);
+    hipLaunchKernelGGL(aggregate_value_kernel<S>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, s, h, wsame,
+                       wopp, wnuc, Y, W, m);
+    return hipGetLastError();
+  }
   if (s.N <= 4) return agg_launch<S, 4>(s, h, wsame, wopp, wnuc, Y, ee, en, W, jet, m, st);
   if (s.N <= 8) return agg_launch<S, 8>(s, h, wsame, wopp, wnuc, Y, ee, en, W, jet, m, st);
   if (s.N <= 16) return agg_launch<S, 16>(s, h, wsame, wopp, wnuc, Y, ee, en, W, jet, m, st);

@@ -100,14 +100,22 @@ def test_small_molecule_ragged_fp64():
 
 
 def test_n2_ansatz_fp32_subset_mha():
+    """float32 jets, float64 determinants.  Errors are reported in mHa; near an
+    electron-nucleus coalescence |Delta log|psi|| reaches 1e5 Ha, so the bound is
+    stated relative to the largest addend of E_L (as for float64) plus a median."""
     s, a, p, r = qi.workload_inputs(1, 64)
     ref = oracle.local_energy(r, p.astype(np.float32).astype(np.float64), s, a)
     got = _run_le(s, a, p, r, "fp32")
     ok = ~flagged(r, p, s, a)
     err = (got["e_loc"] - ref["e_loc"])[ok] * 1e3
     report("n2 fp32 64", err)
+    scale = np.maximum.reduce([np.abs(ref["e_loc"]), 0.5 * np.abs(ref["lap"]),
+                               0.5 * (ref["grad"] ** 2).sum((1, 2)), np.ones_like(ref["e_loc"])])[ok]
+    rel = np.abs(err) * 1e-3 / scale
+    print(f"[n2 fp32 64] max error relative to the largest addend {rel.max():.2e}", flush=True)
     assert np.all(got["sign"][ok] == ref["sign"][ok])
-    assert np.percentile(np.abs(err), 99) < 50.0
+    assert rel.max() < 2e-5
+    assert np.median(np.abs(err)) < 0.5
 
 
 def _one_center(system, a, sigma, rng):
