@@ -30,25 +30,52 @@ sys.path.insert(0, ROOT)
 PEAK = {"fp32_mfma": 157.3e12, "fp64_mfma": 78.6e12, "bf16_mfma": 2.5e15, "hbm": 8.0e12}
 
 
-def algorithmic_model(s, a, elem_bytes):
-    """Per-walker algorithmic work of each stage (no padding, no structural zeros).
+def algorithmic_model(s, a, elem_bytes, n_mc, with_grad):
+    """Algorithmic work of one bench step per kernel name (FLOP or bytes summed
+    over all launches of that kernel in the step), without padding rows or
+    structurally zero rows.
 
-    Jets carry R1 = 3N + 2 rows per electron (value, 3N tangents, Laplacian)."""
+    Jets carry R1 = 3N + 2 rows per electron (value, 3N tangents, Laplacian);
+    edge filters carry 3 rows per pair (value, first and second derivative)."""
     N, M, K, D, L, L0, nd = s.n_elec, s.n_nuc, a.n_rbf, a.width, a.mp_layers, a.init_layers, a.n_det
     T = 3 * N
     R1 = T + 2
     Rj = N * R1
     P = [s.n_up * (s.n_up - 1) // 2 + s.n_down * (s.n_down - 1) // 2, s.n_up * s.n_down, N * M]
     nsq = s.n_up ** 2 + s.n_down ** 2
-    m = {}
-    m["node_gemm_jet_flops"] = (2 * Rj * ((M + 2) * K * D + (L0 - 1) * D * D) + L * 2 * Rj * 4 * D * D
-                                + 2 * R1 * D * nd * nsq)
-    m["edge_gemm_jet_flops"] = L * sum(P) * 3 * 2 * (K * D + D * D)
-    m["value_flops"] = (2 * N * ((M + 2) * K * D + (L0 - 1) * D * D) + L * (2 * N * 4 * D * D + sum(P) * 2 * (K * D + D * D))
-                        + 2 * D * nd * nsq)
-    m["agg_jet_bytes"] = L * elem_bytes * (N * R1 * D + N * R1 * 3 * D + sum(P) * 3 * D)
-    m["det_jet_bytes"] = elem_bytes * nd * R1 * nsq + 8 * 2 * nd * (T + 3)
+    eb = elem_bytes
+    # forward with jets (local energy)
+    # h and the electron-message part of g over all jet rows; the nuclear message has 5 nonzero
+    # jet rows per electron (value, own coordinates, Laplacian)
+    node_jet = (2 * Rj * ((M + 2) * K * D + (L0 - 1) * D * D) + L * 2 * Rj * 3 * D * D + L * 2 * N * 5 * D * D
+                + 2 * R1 * D * nd * nsq)
+    edge_jet = L * sum(P) * 3 * 2 * (K * D + D * D)
+    # value rows: one log|psi| (Metropolis proposal, stashed forward of the backward)
+    val_fwd = (2 * N * ((M + 2) * K * D + (L0 - 1) * D * D) + L * (2 * N * 4 * D * D + sum(P) * 2 * (K * D + D * D))
+               + 2 * D * nd * nsq)
+    # data cotangents of the backward (x_bar = y_bar W^T), weight gradients (W_bar = x^T y_bar)
+    val_bwd = 2 * D * nd * nsq + L * (2 * N * 3 * D * D + 2 * N * D * D + sum(P) * 2 * D * D) + (L0 - 1) * 2 * N * D * D
+    wgrad = val_fwd
+    n_val = n_mc + (1 if with_grad else 0)
+    m = {
+        "gemm_kernel<jet>": ("mfma", node_jet),
+        "gemm_kernel<edge>": ("mfma", edge_jet),
+        "gemm_kernel<val>": ("mfma", n_val * val_fwd + (val_bwd if with_grad else 0)),
+        "wgrad_kernel": ("mfma", wgrad if with_grad else 0),
+        # HBM-bound kernels: bytes of jets read and written
+        "aggregate_kernel": ("hbm", L * eb * (N * R1 * D + N * R1 * 2 * D + (P[0] + P[1]) * 3 * D)),
+        "det_kernel": ("hbm", eb * nd * R1 * nsq + 8 * 2 * nd * (T + 3)),
+        "envelope_kernel": ("hbm", 2 * eb * nd * R1 * nsq),
+    }
     return m
+
+
+def kernel_family(name):
+    if name.startswith("gemm_kernel"):
+        return "gemm_kernel<" + name.rstrip(">").split(",")[-1] + ">"
+    if name.startswith("wgrad_kernel"):
+        return "wgrad_kernel"
+    return name
 
 
 def main():
@@ -56,10 +83,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--walkers", type=int, default=4096)
+    ap.add_argument("--workload", default="n2", choices=["n2", "c4h4", "h2"],
+                    help="n2: the headline workload; c4h4 / h2: the precision and small FP64 systems")
+    ap.add_argument("--walkers", type=int, default=None)
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64", "bf16"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-walkers", type=int, default=48)
+    ap.add_argument("--cpu-walkers", type=int, default=96)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (walkers would be sharded "
@@ -70,14 +99,15 @@ def main():
     import qmc_inputs as qi
     from paper_2307_14123_amd import qmc
 
-    wl = qi.workload(1)
+    k = {"n2": 1, "c4h4": 3, "h2": 0}[args.workload]
+    wl = qi.workload(k)
     s, a = wl.systems[0], wl.ansatz
-    W = args.walkers
-    n_mc, tau = wl.metropolis_steps, wl.step_size
-    params = qi.make_params(s, a, qi.seed(1, 0))
-    r0 = qi.make_walkers(s, W, qi.seed(1, 1))
-    noise = qi.make_noise(n_mc, W, s.n_elec, qi.seed(1, 2))
-    uni = qi.make_uniforms(n_mc, W, qi.seed(1, 3))
+    W = args.walkers or wl.walkers
+    n_mc, tau = 10, 0.2
+    params = qi.make_params(s, a, qi.seed(k, 0))
+    r0 = qi.make_walkers(s, W, qi.seed(k, 1))
+    noise = qi.make_noise(n_mc, W, s.n_elec, qi.seed(k, 2))
+    uni = qi.make_uniforms(n_mc, W, qi.seed(k, 3))
 
     dev = torch.device("cuda", 0)
     plan = qmc.Plan([s], [W], a, args.precision)
@@ -134,29 +164,38 @@ def main():
     ms_le = (time.perf_counter() - t0) * 1e3 / reps
 
     eb = 8 if args.precision == "fp64" else 4
-    model = algorithmic_model(s, a, eb)
-    # dominant kernel by total time in the timed region
-    name, (nl, tot_ms) = max(prof.items(), key=lambda kv: kv[1][1])
-    avg_s = tot_ms / nl * 1e-3
+    model = algorithmic_model(s, a, eb, n_mc, has_grad)
+    fam = {}
+    for k, (nl, ms) in prof.items():
+        f = kernel_family(k)
+        n0, m0 = fam.get(f, (0, 0.0))
+        fam[f] = (n0 + nl, m0 + ms)
+    # dominant kernel family by total time in the timed region
+    name, (nl, tot_ms) = max(fam.items(), key=lambda kv: kv[1][1])
     gemm_dtype = {"fp32": "fp32_mfma", "fp64": "fp64_mfma", "bf16": "bf16_mfma"}[args.precision]
     roof = None
-    if name.startswith("gemm_kernel") and (",6>" in name or ",5>" in name or ",7>" in name):
-        # jet node GEMMs of the local energy: init, per layer h and g, two orbital maps
-        launches_per_le = 1 + (a.init_layers - 1) + 2 * a.mp_layers + 2
-        per_launch = model["node_gemm_jet_flops"] * W / launches_per_le
-        roof = {"bound": "mfma", "achieved": per_launch / avg_s / 1e12, "peak": PEAK[gemm_dtype] / 1e12,
-                "unit": "TFLOP/s"}
-    elif name.startswith("aggregate_kernel"):
-        per_launch = model["agg_jet_bytes"] / a.mp_layers * W
-        roof = {"bound": "hbm", "achieved": per_launch / avg_s / 1e9, "peak": PEAK["hbm"] / 1e9, "unit": "GB/s"}
-    elif name.startswith("det_kernel"):
-        per_launch = model["det_jet_bytes"] * W / 2
-        roof = {"bound": "hbm", "achieved": per_launch / avg_s / 1e9, "peak": PEAK["hbm"] / 1e9, "unit": "GB/s"}
-    if roof is not None:
+    if name in model:
+        bound, work_per_walker = model[name]
+        per_launch = work_per_walker * W * args.steps / nl
+        avg_s = tot_ms / nl * 1e-3
+        if bound == "mfma":
+            pk = PEAK["fp32_mfma"] if (name == "gemm_kernel<val>" or name == "wgrad_kernel") and args.precision == "bf16" \
+                else PEAK[gemm_dtype]
+            roof = {"bound": "mfma", "achieved": per_launch / avg_s / 1e12, "peak": pk / 1e12, "unit": "TFLOP/s"}
+        else:
+            roof = {"bound": "hbm", "achieved": per_launch / avg_s / 1e9, "peak": PEAK["hbm"] / 1e9, "unit": "GB/s"}
         roof["frac"] = roof["achieved"] / roof["peak"]
         roof["traffic"] = None
         roof["kernel"] = name
+        roof["launches_per_step"] = nl / args.steps
         roof["avg_launch_ms"] = tot_ms / nl
+    others = {}
+    for f, (n1, ms1) in fam.items():
+        if f in model and model[f][1] > 0:
+            bound, wpw = model[f]
+            per = wpw * W * args.steps / (ms1 * 1e-3)
+            others[f] = {"bound": bound, "achieved": per / (1e12 if bound == "mfma" else 1e9),
+                         "unit": "TFLOP/s" if bound == "mfma" else "GB/s", "ms_per_step": ms1 / args.steps}
 
     res = {
         "metric": "walker local energies/sec at stated mHa error vs FP64 oracle; VMC train step ms",
@@ -171,7 +210,9 @@ def main():
         "vs_baseline": None,
         "dtype": {"fp32": "f32+f64", "fp64": "f64", "bf16": "bf16+f32+f64"}[args.precision],
         "data": "synthetic",
-        "config": {"workload": f"N2-sized: 2 x Z=7 at 2.068 bohr, 7 up + 7 down, {W} walkers, "
+        "config": {"workload": {"n2": "N2-sized: 2 x Z=7 at 2.068 bohr, 7 up + 7 down",
+                                "c4h4": "C4H4-sized: 4 C + 4 H, 14 up + 14 down",
+                                "h2": "H2: 2 x Z=1 at 1.4 bohr, 1 up + 1 down"}[args.workload] + f", {W} walkers, "
                                f"{a.mp_layers} message-passing layers width {a.width}, {a.n_det} dets, "
                                f"{a.n_env} envelope exponents; step = {n_mc} Metropolis steps (tau {tau}) + "
                                f"local energy" + (" + loss gradient" if has_grad else ""),
@@ -180,13 +221,14 @@ def main():
         "e_loc_per_s": W / (ms_le * 1e-3),
         "e_loc_ms": ms_le,
         "roofline": roof,
-        "kernels_ms_per_step": {k: v[1] / args.steps for k, v in sorted(prof.items(), key=lambda kv: -kv[1][1])},
+        "kernel_rooflines": others,
+        "kernels_ms_per_step": {k: round(v[1] / args.steps, 3) for k, v in sorted(prof.items(), key=lambda kv: -kv[1][1])},
     }
 
     if not args.no_cpu_baseline:
         import oracle
         torch.set_num_threads(os.cpu_count() or 1)
-        nw = args.cpu_walkers
+        nw = min(args.cpu_walkers, W) if args.workload == "n2" else min(8, W)
         rs = r0[:nw].copy()
         t0 = time.perf_counter()
         lp_c = oracle.logpsi_np(rs, P.double().cpu().numpy(), s, a)[1]

@@ -156,9 +156,24 @@ static qmc_status forward_chunk(const Plan& P, const SysPlan& s, const S* prm, c
     }
     CK(launch_gemm(gk, dense(f, D, prm + Ly.Wh, D, prm + Ly.bh, h, D, rows, (int)D, (int)D, Rp, s.T, 0, vm), st));
     CK(launch_aggregate<S>(dv, h, wj[0], wj[1], wj[2], prm + Ly.Y, ee, en, wc, jet, m, st));
-    GemmArgs g = dense(m, 3 * D, prm + Ly.Wg, D, prm + Ly.bg, f, D, rows, (int)(3 * D), (int)D, Rp, s.T, 1, vm);
-    g.Res = f;
-    CK(launch_gemm(gk, g, st));
+    if (jet) {
+      // electron messages [W][N][Rp][2D]; the nuclear message has 5 nonzero jet rows per electron:
+      // its product with the nuclear block of W_g is formed on those rows and added before the tanh
+      S* mn5 = (S*)(ws + L.mn5);
+      S* zn5 = (S*)(ws + L.zn5);
+      CK(launch_nuc_message<S>(dv, wj[2], prm + Ly.Y, en, wc, mn5, st));
+      CK(launch_gemm(gk, dense(mn5, D, prm + Ly.Wg + 2 * D * D, D, nullptr, zn5, D, wc * N * 5, (int)D, (int)D, 1, 0, 0,
+                               1), st));
+      GemmArgs g = dense(m, 2 * D, prm + Ly.Wg, D, prm + Ly.bg, f, D, rows, (int)(2 * D), (int)D, Rp, s.T, 1, vm);
+      g.Res = f;
+      g.add5 = zn5;
+      g.nel = (int)N;
+      CK(launch_gemm(gk, g, st));
+    } else {
+      GemmArgs g = dense(m, 3 * D, prm + Ly.Wg, D, prm + Ly.bg, f, D, rows, (int)(3 * D), (int)D, Rp, s.T, 1, vm);
+      g.Res = f;
+      CK(launch_gemm(gk, g, st));
+    }
   }
   int64_t off_e = 0;
   for (int sp = 0; sp < 2; ++sp) {

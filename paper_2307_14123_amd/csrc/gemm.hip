@@ -25,6 +25,8 @@
 // B use the same k assignment, so the contraction does not depend on how the
 // hardware orders k inside a lane.
 #include <cstdio>
+#include <cstdlib>
+#include <cstring>
 
 #include "kernels.h"
 
@@ -66,14 +68,14 @@ __device__ inline double dtanh(double x) { return tanh(x); }
 __device__ inline float dtanh(float x) { return tanhf(x); }
 
 // EPI: 0 value rows, 1 univariate edge jets (groups of 4 rows), 2 electron jets (groups of Rp = 16*bpg rows)
-template <int KIND, int MB, int EPI>
+template <int KIND, int MB, int EPI, int BKT>
 __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs a) {
   using G = GT<KIND>;
   using S = typename G::S;
   using Acc = typename G::Acc;
   using L = typename G::L;
   using Vec = typename V4<S>::T;
-  constexpr int BK = G::BK;
+  constexpr int BK = BKT;
   constexpr int BM = 16 * MB;
   constexpr int BN = 128;
   // A tile [BM][BK+pad] and B tile stored transposed [BN][BK+pad]: k is contiguous in both, so a
@@ -263,6 +265,23 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs a) {
     grp[mb] = mb / bpg;
     qbase[mb] = (mb - grp[mb] * bpg) * 16;
   }
+  // global row group and electron (group mod nel) of each 16-row block, for add5
+  int64_t gidx[MB];
+  int gel[MB];
+  if (EPI == 2 && a.add5) {
+    const uint32_t g0 = (uint32_t)m0 / (uint32_t)a.Rp;
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb) {
+      gidx[mb] = (int64_t)g0 + grp[mb];
+      gel[mb] = (int)((g0 + (uint32_t)grp[mb]) % (uint32_t)a.nel);
+    }
+  } else {
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb) {
+      gidx[mb] = 0;
+      gel[mb] = 0;
+    }
+  }
   // output row offsets of this lane's 4*MB rows: one 32-bit division per 16-row block, then
   // stepping through the rows (rows of one lane are consecutive for f32/bf16, 4 apart for f64)
   int64_t yoff[MB][4];
@@ -348,6 +367,26 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs a) {
       }
     } else {
       // EPI == 2: groups of Rp = 16*bpg rows spanning whole 16-row blocks
+      if (a.add5 && cvalid) {
+        // the 5 nonzero rows of a term that depends on the electron's own position only
+        const S* A5 = (const S*)a.add5;
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb) {
+          const int e = gel[mb];
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int q = qbase[mb] + rowof(g4, i);
+            int k5 = -1;
+            if (q == 0)
+              k5 = 0;
+            else if (q == a.T + 1)
+              k5 = 4;
+            else if (q >= 1 && q <= a.T && (q - 1) / 3 == e)
+              k5 = 1 + (q - 1) % 3;
+            if (k5 >= 0 && yval[mb][i]) acc[mb][nb][i] += A5[(gidx[mb] * 5 + k5) * a.Ncols + col];
+          }
+        }
+      }
       S ssq[MB], z0b[MB];
 #pragma unroll
       for (int mb = 0; mb < MB; ++mb) {
@@ -398,39 +437,93 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs a) {
 static const char* gemm_name(int kind, int mb, int epi) {
   static const char* kn[3] = {"f64", "f32", "bf16"};
   static const char* en[3] = {"val", "edge", "jet"};
-  static char names[3][9][3][40];
+  static char names[3][17][3][40];
   static bool init = false;
   if (!init) {
     for (int k = 0; k < 3; ++k)
-      for (int m = 0; m < 9; ++m)
+      for (int m = 0; m < 17; ++m)
         for (int e = 0; e < 3; ++e) snprintf(names[k][m][e], 40, "gemm_kernel<%s,%d,%s>", kn[k], m, en[e]);
     init = true;
   }
   return names[kind][mb][epi];
 }
 
-template <int KIND, int MB, int EPI>
+template <int KIND, int MB, int EPI, int BKT>
 static hipError_t launch_mb(const GemmArgs& a, hipStream_t st) {
   ProfScope ps(gemm_name(KIND, MB, EPI), st);
   constexpr int BM = 16 * MB;
   dim3 grid((unsigned)((a.rows + BM - 1) / BM), (unsigned)((a.Ncols + 127) / 128));
-  hipLaunchKernelGGL((gemm_kernel<KIND, MB, EPI>), grid, dim3(256), 0, st, a);
+  hipLaunchKernelGGL((gemm_kernel<KIND, MB, EPI, BKT>), grid, dim3(256), 0, st, a);
   return hipGetLastError();
+}
+
+// Tile choice: rows per tile (MB blocks of 16) and K per pipeline stage.
+// QMC_GEMM_TILE=<mbmul>,<bk> overrides it for tuning runs: mbmul doubles the
+// row blocks of jet tiles (and of value/edge tiles), bk in {16, 32}.
+static int tile_mul() {
+  static int v = -1;
+  if (v < 0) {
+    v = 1;
+    if (const char* e = getenv("QMC_GEMM_TILE")) v = atoi(e) == 2 ? 2 : 1;
+  }
+  return v;
+}
+static int tile_bk(int def) {
+  static int v = -1;
+  if (v < 0) {
+    v = 0;
+    if (const char* e = getenv("QMC_GEMM_TILE"))
+      if (const char* c = strchr(e, ',')) v = atoi(c + 1) == 32 ? 32 : (atoi(c + 1) == 16 ? 16 : 0);
+  }
+  return v ? v : def;
+}
+
+template <int KIND, int BKT>
+static hipError_t launch_kind_bk(const GemmArgs& a, hipStream_t st) {
+  constexpr bool WIDE = (KIND == GK_F32);  // larger tiles are only instantiated for float32
+  const int mul = WIDE ? tile_mul() : 1;
+  if (a.vmode) {
+    if constexpr (WIDE)
+      if (mul == 2) return launch_mb<KIND, 16, 0, BKT>(a, st);
+    return launch_mb<KIND, 8, 0, BKT>(a, st);
+  }
+  if (a.Rp == 4) {
+    if constexpr (WIDE)
+      if (mul == 2) return launch_mb<KIND, 16, 1, BKT>(a, st);
+    return launch_mb<KIND, 8, 1, BKT>(a, st);
+  }
+  if (a.Rp % 16 != 0 || a.Rp > 128) return hipErrorInvalidValue;
+  const int bpg = a.Rp / 16;
+  int mb = bpg * (8 / bpg);
+  if constexpr (WIDE) {
+    if (mul == 2) {
+      switch (mb) {
+        case 5: return launch_mb<KIND, 10, 2, BKT>(a, st);
+        case 6: return launch_mb<KIND, 12, 2, BKT>(a, st);
+        case 7: return launch_mb<KIND, 14, 2, BKT>(a, st);
+        case 8: return launch_mb<KIND, 16, 2, BKT>(a, st);
+      }
+    }
+  }
+  switch (mb) {
+    case 5: return launch_mb<KIND, 5, 2, BKT>(a, st);
+    case 6: return launch_mb<KIND, 6, 2, BKT>(a, st);
+    case 7: return launch_mb<KIND, 7, 2, BKT>(a, st);
+    case 8: return launch_mb<KIND, 8, 2, BKT>(a, st);
+  }
+  return hipErrorInvalidValue;
 }
 
 template <int KIND>
 static hipError_t launch_kind(const GemmArgs& a, hipStream_t st) {
-  if (a.vmode) return launch_mb<KIND, 8, 0>(a, st);
-  if (a.Rp == 4) return launch_mb<KIND, 8, 1>(a, st);
-  if (a.Rp % 16 != 0 || a.Rp > 128) return hipErrorInvalidValue;
-  const int bpg = a.Rp / 16;
-  switch (bpg * (8 / bpg)) {
-    case 5: return launch_mb<KIND, 5, 2>(a, st);
-    case 6: return launch_mb<KIND, 6, 2>(a, st);
-    case 7: return launch_mb<KIND, 7, 2>(a, st);
-    case 8: return launch_mb<KIND, 8, 2>(a, st);
+  if constexpr (KIND == GK_F32) {
+    if (tile_bk(16) == 32) return launch_kind_bk<KIND, 32>(a, st);
+    return launch_kind_bk<KIND, 16>(a, st);
+  } else if constexpr (KIND == GK_BF16) {
+    return launch_kind_bk<KIND, 32>(a, st);
+  } else {
+    return launch_kind_bk<KIND, 16>(a, st);
   }
-  return hipErrorInvalidValue;
 }
 
 hipError_t launch_gemm(GemmKind kind, const GemmArgs& a, hipStream_t st) {
@@ -441,6 +534,8 @@ hipError_t launch_gemm(GemmKind kind, const GemmArgs& a, hipStream_t st) {
     return hipErrorInvalidValue;
   if (!a.vmode && a.Rp == 4 && a.T != 1) return hipErrorInvalidValue;
   if (a.act == 2 && (!a.vmode || !a.aux)) return hipErrorInvalidValue;
+  if (a.add5 && (a.vmode || a.Rp < 16 || a.nel < 1 || a.xrpw != a.rows || a.yrpw != a.rows))
+    return hipErrorInvalidValue;
   switch (kind) {
     case GK_F64: return launch_kind<GK_F64>(a, st);
     case GK_F32: return launch_kind<GK_F32>(a, st);

@@ -84,7 +84,9 @@ Workspace workspace_layout(const Plan& p, const SysPlan& s, int op, int64_t wc) 
   w.x0 = alloc(size_t(wc) * N * Rp * (M + 2) * K * E);
   w.f = alloc(size_t(wc) * N * Rp * D * E);
   w.h = alloc(size_t(wc) * N * Rp * D * E);
-  w.m = alloc(size_t(wc) * N * Rp * 3 * D * E);
+  w.m = alloc(size_t(wc) * N * Rp * (jet ? 2 : 3) * D * E);
+  w.mn5 = alloc(jet ? size_t(wc) * N * 5 * D * E : 0);
+  w.zn5 = alloc(jet ? size_t(wc) * N * 5 * D * E : 0);
   int64_t nsq = 0;
   for (int sp = 0; sp < 2; ++sp) {
     const int64_t n = s.nsig(sp);

@@ -49,6 +49,10 @@ struct GemmArgs {
   int Rp, T, act, vmode;
   int transw;
   const void* aux;  // act == 2: out = acc * (1 - aux^2), aux addressed like Y (tanh backward)
+  // electron jets: rows [W][N][Rp] also receive add5 [W][N][5][Ncols] before the activation, at
+  // the value row, the 3 rows of the electron's own coordinates and the Laplacian row (N = nel)
+  const void* add5;
+  int nel;
 };
 
 hipError_t launch_gemm(GemmKind kind, const GemmArgs& a, hipStream_t st);
@@ -78,6 +82,12 @@ template <typename S>
 hipError_t launch_aggregate(const SysDev& s, const S* h, const S* wsame, const S* wopp, const S* wnuc,
                             const S* Y, const double* ee, const double* en, int64_t W, int jet, S* m,
                             hipStream_t st);
+
+// Jet mode writes [W][N][Rp][2D] (same-spin, opposite-spin messages); value mode writes [W][N][3D]
+// including the nuclear message.  launch_nuc_message: nuclear messages with jets, [W][N][5][D].
+template <typename S>
+hipError_t launch_nuc_message(const SysDev& s, const S* wnuc, const S* Y, const double* en, int64_t W, S* out,
+                              hipStream_t st);
 
 template <typename S>
 hipError_t launch_envelope(const SysDev& s, int spin, const S* phi, const S* pi, const S* sigma,

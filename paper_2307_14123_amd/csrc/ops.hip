@@ -258,8 +258,9 @@ hipError_t launch_init_features(const SysDev& s, const double* ee, const double*
 
 // ---------------------------------------------------------------- message aggregation
 
-// m_i = [mean_{j same} w_same(d_ij) h_j, mean_{j opp} w_opp(d_ij) h_j, mean_I w_nuc(d_iI) Y_I]
-// propagated through the jets with the product rule.
+// Electron messages with jets: m_i = [mean_{j same} w_same(d_ij) h_j, mean_{j opp} w_opp(d_ij) h_j]
+// propagated with the product rule, written as [W][N][Rp][2D].  (The nuclear
+// message is nonzero in 5 jet rows only and is handled by nuc_message_kernel.)
 //
 // Block: (walker, column chunk of DC).  Thread: (receiver i, column d).  Each
 // thread keeps the filter values w(d_ij) of its receiver, split into a
@@ -276,43 +277,28 @@ hipError_t launch_init_features(const SysDev& s, const double* ee, const double*
 template <typename S, int NMAX>
 __global__ __launch_bounds__(NMAX >= 32 ? 256 : 512) void aggregate_kernel(
     SysDev s, const S* __restrict__ h, const S* __restrict__ wsame, const S* __restrict__ wopp,
-    const S* __restrict__ wnuc, const S* __restrict__ Y, const double* __restrict__ ee, const double* __restrict__ en,
-    int jet, int DC, int RC, S* __restrict__ m) {
+    const double* __restrict__ ee, int DC, int RC, S* __restrict__ m) {
   extern __shared__ __align__(16) unsigned char smem[];
-  const int N = s.N, M = s.M, D = s.D;
-  const int Rp = jet ? s.Rp : 1;
-  const int Re = jet ? 4 : 1;
+  const int N = s.N, D = s.D;
+  const int Rp = s.Rp;
+  constexpr int Re = 4;
   const int64_t w = blockIdx.x;
   const int d0 = blockIdx.y * DC;
   S* hs = (S*)smem;                 // [NMAX][RC][DC], rows of j >= N stay zero
   S* wdl = hs + NMAX * RC * DC;     // [N][N][DC]: w'(d_ij) (zero on the diagonal)
-  S* h0s = wdl + (jet ? N * N * DC : 0);  // [N][DC]: senders' value rows
+  S* h0s = wdl + N * N * DC;        // [N][DC]: senders' value rows
   S* gu = h0s + N * DC;             // [N][N][4]: d_ij, unit vector of r_i - r_j
-  S* gn = gu + N * N * 4;           // [N][M][4]
-  S* wns = gn + N * M * 4;          // [N][M][3][DC]: nuclear filter jets
-  S* ys = wns + N * M * 3 * DC;     // [M][DC]
   const int nt = blockDim.x;
   for (int e = threadIdx.x; e < N * N * 4; e += nt) gu[e] = (S)ee[w * N * N * 4 + e];
-  for (int e = threadIdx.x; e < N * M * 4; e += nt) gn[e] = (S)en[w * N * M * 4 + e];
-  for (int e = threadIdx.x; e < N * M * 3 * DC; e += nt) {
-    const int x = e % DC, r3 = (e / DC) % 3, iI = e / (3 * DC);
-    wns[e] = (d0 + x < D && (jet || r3 == 0)) ? wnuc[((w * s.P2 + iI) * Re + r3) * D + d0 + x] : S(0);
-  }
-  for (int e = threadIdx.x; e < M * DC; e += nt) {
-    const int x = e % DC, I = e / DC;
-    ys[e] = (d0 + x < D) ? Y[I * D + d0 + x] : S(0);
-  }
-  if (jet) {
-    for (int e = threadIdx.x; e < N * N * DC; e += nt) {
-      const int x = e % DC, ij = e / DC, ii = ij / N, jj = ij % N;
-      S v = 0;
-      if (ii != jj && d0 + x < D) {
-        int type;
-        const int p = ee_pair(s, ii, jj, type);
-        v = (type ? wopp : wsame)[((w * (type ? s.P1 : s.P0) + p) * Re + 1) * D + d0 + x];
-      }
-      wdl[e] = v;
+  for (int e = threadIdx.x; e < N * N * DC; e += nt) {
+    const int x = e % DC, ij = e / DC, ii = ij / N, jj = ij % N;
+    S v = 0;
+    if (ii != jj && d0 + x < D) {
+      int type;
+      const int p = ee_pair(s, ii, jj, type);
+      v = (type ? wopp : wsame)[((w * (type ? s.P1 : s.P0) + p) * Re + 1) * D + d0 + x];
     }
+    wdl[e] = v;
   }
   for (int e = threadIdx.x; e < NMAX * RC * DC; e += nt) hs[e] = S(0);
   const int dd = threadIdx.x % DC;
@@ -338,20 +324,16 @@ __global__ __launch_bounds__(NMAX >= 32 ? 256 : 512) void aggregate_kernel(
         wop[j] = wt[0];
       else
         wsm[j] = wt[0];
-      if (jet) lw[j] = wt[2 * D];  // w'' for now; combined with w'/d below
+      lw[j] = wt[2 * D];  // w'' for now; combined with w'/d below
     }
   }
   __syncthreads();
-  if (jet) {
 #pragma unroll
-    for (int j = 0; j < NMAX; ++j)
-      if (active && j < N && j != i)
-        lw[j] = S(2) * lw[j] + S(4) * wdl[(i * N + j) * DC + dd] / gu[(i * N + j) * 4];
-  }
+  for (int j = 0; j < NMAX; ++j)
+    if (active && j < N && j != i) lw[j] = S(2) * lw[j] + S(4) * wdl[(i * N + j) * DC + dd] / gu[(i * N + j) * 4];
   S lx_s = 0, lx_o = 0;  // Laplacian-row cross terms, same-spin and opposite-spin senders
   const bool ups = up;
-  S* mrow = m + ((w * N + i) * (int64_t)Rp) * 3 * D + d;
-  const S invM = S(1) / S(M);
+  S* mrow = m + ((w * N + i) * (int64_t)Rp) * 2 * D + d;
   for (int q0 = 0; q0 < Rp; q0 += RC) {
     __syncthreads();
     for (int e = threadIdx.x; e < N * RC * DC; e += nt) {
@@ -373,8 +355,7 @@ __global__ __launch_bounds__(NMAX >= 32 ? 256 : 512) void aggregate_kernel(
         ms += wsm[j] * hv;
         mo += wop[j] * hv;
       }
-      S nuc = 0;
-      if (jet && q >= 1 && q <= s.T) {
+      if (q >= 1 && q <= s.T) {
         const int c = q - 1, k = c / 3, a = c % 3;
         if (k == i) {
           for (int j = 0; j < N; ++j) {
@@ -390,8 +371,6 @@ __global__ __launch_bounds__(NMAX >= 32 ? 256 : 512) void aggregate_kernel(
               lx_o += t1;
             }
           }
-          for (int I = 0; I < M; ++I)
-            nuc += wns[((i * M + I) * 3 + 1) * DC + dd] * gn[(i * M + I) * 4 + 1 + a] * ys[I * DC + dd];
         } else {
           const S cw = wdl[(i * N + k) * DC + dd] * gu[(i * N + k) * 4 + 1 + a];
           const S t0 = -h0s[k * DC + dd] * cw;
@@ -404,7 +383,7 @@ __global__ __launch_bounds__(NMAX >= 32 ? 256 : 512) void aggregate_kernel(
             lx_o += t1;
           }
         }
-      } else if (jet && q == s.T + 1) {
+      } else if (q == s.T + 1) {
 #pragma unroll
         for (int j = 0; j < NMAX; ++j) {
           if (j < N) {
@@ -417,19 +396,52 @@ __global__ __launch_bounds__(NMAX >= 32 ? 256 : 512) void aggregate_kernel(
         }
         ms += lx_s;
         mo += lx_o;
-        for (int I = 0; I < M; ++I) {
-          const S* wn = wns + ((i * M + I) * 3) * DC + dd;
-          nuc += (wn[2 * DC] + S(2) * wn[DC] / gn[(i * M + I) * 4]) * ys[I * DC + dd];
-        }
-      } else if (q == 0) {
-        for (int I = 0; I < M; ++I) nuc += wns[((i * M + I) * 3) * DC + dd] * ys[I * DC + dd];
       }
-      S* row = mrow + (int64_t)q * 3 * D;
+      S* row = mrow + (int64_t)q * 2 * D;
       row[0] = ms * inv_s;
       row[D] = mo * inv_o;
-      row[2 * D] = nuc * invM;
     }
   }
+}
+
+// Nuclear messages with jets.  m_nuc_i = mean_I w_nuc(d_iI) Y_I depends on r_i
+// only, so its jet is nonzero in 5 rows: value, the 3 coordinates of electron
+// i, Laplacian (e-n distance: |grad d|^2 = 1, lap d = 2/d).  Output
+// [W][N][5][D], one thread per (walker, electron, column).
+template <typename S>
+__global__ void nuc_message_kernel(SysDev s, const S* __restrict__ wnuc, const S* __restrict__ Y,
+                                   const double* __restrict__ en, int64_t W, S* __restrict__ out) {
+  const int N = s.N, D = s.D, M = s.M;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= W * N * D) return;
+  const int d = (int)(t % D);
+  const int64_t wi = t / D;
+  S v = 0, g[3] = {0, 0, 0}, l = 0;
+  for (int I = 0; I < M; ++I) {
+    const S* wn = wnuc + ((wi * M + I) * 4) * (int64_t)D + d;  // pair (i, I) of walker w: index wi*M + I
+    const double* ge = en + (wi * M + I) * 4;
+    const S y = Y[I * D + d];
+    v += wn[0] * y;
+    for (int a = 0; a < 3; ++a) g[a] += wn[D] * (S)ge[1 + a] * y;
+    l += (wn[2 * D] + S(2) * wn[D] / (S)ge[0]) * y;
+  }
+  const S invM = S(1) / S(M);
+  S* o = out + wi * 5 * (int64_t)D + d;
+  o[0] = v * invM;
+  o[D] = g[0] * invM;
+  o[2 * D] = g[1] * invM;
+  o[3 * D] = g[2] * invM;
+  o[4 * D] = l * invM;
+}
+
+template <typename S>
+hipError_t launch_nuc_message(const SysDev& s, const S* wnuc, const S* Y, const double* en, int64_t W, S* out,
+                              hipStream_t st) {
+  const int64_t n = W * s.N * s.D;
+  ProfScope ps("nuc_message_kernel", st);
+  hipLaunchKernelGGL(nuc_message_kernel<S>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, s, wnuc, Y, en, W,
+                     out);
+  return hipGetLastError();
 }
 
 // Value rows only (log|psi| without derivatives): one thread per (walker, receiver, column).
@@ -466,22 +478,19 @@ __global__ void aggregate_value_kernel(SysDev s, const S* __restrict__ h, const 
 }
 
 template <typename S, int NMAX>
-static hipError_t agg_launch(const SysDev& s, const S* h, const S* ws, const S* wo, const S* wn, const S* Y,
-                             const double* ee, const double* en, int64_t W, int jet, S* m, hipStream_t st) {
-  const int RC = jet ? 16 : 1;
+static hipError_t agg_launch(const SysDev& s, const S* h, const S* ws, const S* wo, const double* ee, int64_t W, S* m,
+                             hipStream_t st) {
+  const int RC = 16;
   int DC = 1;
   while (DC < s.D && DC < 64) DC <<= 1;
   auto lds = [&](int dc) {
-    return (size_t)(NMAX * RC * dc + (jet ? s.N * s.N * dc : 0) + s.N * dc + s.N * s.N * 4 + s.N * s.M * 4 +
-                    s.N * s.M * 3 * dc + s.M * dc) *
-           sizeof(S);
+    return (size_t)(NMAX * RC * dc + s.N * s.N * dc + s.N * dc + s.N * s.N * 4) * sizeof(S);
   };
   const int max_threads = NMAX >= 32 ? 256 : 512;
   while (DC > 1 && (DC * s.N > max_threads || lds(DC) > 64 * 1024)) DC >>= 1;
   ProfScope ps("aggregate_kernel", st);
   dim3 grid((unsigned)W, (unsigned)((s.D + DC - 1) / DC));
-  hipLaunchKernelGGL((aggregate_kernel<S, NMAX>), grid, dim3(DC * s.N), lds(DC), st, s, h, ws, wo, wn, Y, ee, en, jet,
-                     DC, RC, m);
+  hipLaunchKernelGGL((aggregate_kernel<S, NMAX>), grid, dim3(DC * s.N), lds(DC), st, s, h, ws, wo, ee, DC, RC, m);
   return hipGetLastError();
 }
 
@@ -495,11 +504,11 @@ hipError_t launch_aggregate(const SysDev& s, const S* h, const S* wsame, const S
                        wopp, wnuc, Y, W, m);
     return hipGetLastError();
   }
-  if (s.N <= 4) return agg_launch<S, 4>(s, h, wsame, wopp, wnuc, Y, ee, en, W, jet, m, st);
-  if (s.N <= 8) return agg_launch<S, 8>(s, h, wsame, wopp, wnuc, Y, ee, en, W, jet, m, st);
-  if (s.N <= 16) return agg_launch<S, 16>(s, h, wsame, wopp, wnuc, Y, ee, en, W, jet, m, st);
-  if (s.N <= 32) return agg_launch<S, 32>(s, h, wsame, wopp, wnuc, Y, ee, en, W, jet, m, st);
-  if (s.N <= 48) return agg_launch<S, 48>(s, h, wsame, wopp, wnuc, Y, ee, en, W, jet, m, st);
+  if (s.N <= 4) return agg_launch<S, 4>(s, h, wsame, wopp, ee, W, m, st);
+  if (s.N <= 8) return agg_launch<S, 8>(s, h, wsame, wopp, ee, W, m, st);
+  if (s.N <= 16) return agg_launch<S, 16>(s, h, wsame, wopp, ee, W, m, st);
+  if (s.N <= 32) return agg_launch<S, 32>(s, h, wsame, wopp, ee, W, m, st);
+  if (s.N <= 48) return agg_launch<S, 48>(s, h, wsame, wopp, ee, W, m, st);
   return hipErrorInvalidValue;
 }
 
@@ -884,6 +893,8 @@ hipError_t launch_accept(int64_t W, int N3, const double* rp, const double* lp_p
                                               hipStream_t);                                                     \
   template hipError_t launch_aggregate<S>(const SysDev&, const S*, const S*, const S*, const S*, const S*,      \
                                           const double*, const double*, int64_t, int, S*, hipStream_t);         \
+  template hipError_t launch_nuc_message<S>(const SysDev&, const S*, const S*, const double*, int64_t, S*,      \
+                                            hipStream_t);                                                       \
   template hipError_t launch_envelope<S>(const SysDev&, int, const S*, const S*, const S*, const double*,       \
                                          int64_t, int, S*, hipStream_t);                                        \
   template hipError_t launch_det<S>(const SysDev&, const S*, int64_t, int, double*, double*, double*, double*, \

@@ -53,7 +53,7 @@ struct Plan {
 struct Workspace {
   size_t geom, vpot;
   size_t rho[3], ehid[3], wjet[3];
-  size_t x0, f, h, m;
+  size_t x0, f, h, m, mn5, zn5;
   size_t phi[2], ajet;
   size_t dld, dsg, dg, dlap;
   size_t lp_prop;
