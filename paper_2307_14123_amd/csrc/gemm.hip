@@ -5,17 +5,27 @@
 // follows needs, per (electron, column), the sum over gradient rows of the
 // squared pre-activation: t = tanh(z0), grad t = t' grad z,
 // lap t = t' lap z + t'' |grad z|^2 with t' = 1 - t^2, t'' = -2 t t'.
-// Tiles therefore hold whole row groups (BM is a multiple of the group
-// size) so that this reduction stays inside one wavefront: each wave owns all
-// BM rows of its 32 output columns, reduces its own accumulator rows and
-// finishes with two cross-lane shuffles.
+// Tiles therefore hold whole row groups (BM is a multiple of the group size).
 //
-// Pipeline: two LDS stages; the next K-slice is fetched from global memory
-// into registers (16-byte vectors where the layout allows) while the MFMAs
-// consume the current stage, so each K-step needs one barrier.
+// Main loop: 256 threads, block tile BM x 128, each of the 4 waves owns all
+// BM rows of 32 output columns.  Two LDS stages; the next K-slice is fetched
+// into registers while the MFMAs consume the current stage (one barrier per
+// K-step).  Operand loads are branch-free 16-byte loads whenever K is a
+// multiple of the K-step and the operands are 16-byte aligned; otherwise a
+// bounds-checked path is taken.
 //
-// Both operand tiles keep k contiguous in LDS ([rows][k] and [columns][k]),
-// so one 16-byte LDS read gives a lane its operands of four f32/f64 MFMAs.
+// LDS layouts: A [BM][BK+4] (k contiguous: one 16-byte read gives a lane the
+// operands of four f32/f64 MFMAs); B [BK][128+4] (columns contiguous, written
+// straight from coalesced row loads of W; a lane reads its four k values with
+// four scalar reads).  For bf16 both tiles are k-contiguous ([rows][k],
+// [columns][k]) so that a lane's eight k values are one 16-byte read.
+//
+// Epilogue: each wave stages its accumulator tile in LDS transposed
+// ([column][row]), then every lane takes one output column and a run of whole
+// row groups (or a part of one group, with the |grad z|^2 partial sums
+// combined by cross-lane shuffles).  Rows are walked in order, so the bias,
+// the five-row nuclear term, the residual and the output are read and written
+// as row segments shared by 32 (16 for f64) lanes.
 //
 // MFMA shapes: f64 v_mfma_f64_16x16x4, f32 v_mfma_f32_16x16x4, bf16
 // v_mfma_f32_16x16x32 (operands rounded to bf16, float accumulation).  The
@@ -27,6 +37,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <type_traits>
 
 #include "kernels.h"
 
@@ -41,19 +52,16 @@ template <> struct GT<GK_F64> {
   using S = double;
   using Acc = d4;
   using L = double;  // LDS element
-  static constexpr int BK = 16;
 };
 template <> struct GT<GK_F32> {
   using S = float;
   using Acc = f4;
   using L = float;
-  static constexpr int BK = 16;
 };
 template <> struct GT<GK_BF16> {
   using S = float;
   using Acc = f4;
   using L = __bf16;
-  static constexpr int BK = 32;
 };
 
 template <typename S> struct V4;
@@ -67,6 +75,8 @@ template <> struct V4<double> {
 __device__ inline double dtanh(double x) { return tanh(x); }
 __device__ inline float dtanh(float x) { return tanhf(x); }
 
+constexpr int cmax(int a, int b) { return a > b ? a : b; }
+
 // EPI: 0 value rows, 1 univariate edge jets (groups of 4 rows), 2 electron jets (groups of Rp = 16*bpg rows)
 template <int KIND, int MB, int EPI, int BKT>
 __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs a) {
@@ -78,17 +88,23 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs a) {
   constexpr int BK = BKT;
   constexpr int BM = 16 * MB;
   constexpr int BN = 128;
-  // A tile [BM][BK+pad] and B tile stored transposed [BN][BK+pad]: k is contiguous in both, so a
-  // lane reads its operands for several MFMAs with one 16-byte LDS load
-  constexpr int APAD = (KIND == GK_BF16) ? 8 : 4;
+  constexpr bool BF = (KIND == GK_BF16);
+  constexpr int APAD = BF ? 8 : 4;
   constexpr int ALD = BK + APAD;
-  constexpr int BLD = BK + APAD;
+  constexpr int BLD = BF ? BK + 8 : BN + 4;
   constexpr int ASZ = BM * ALD;
-  constexpr int BSZ = BN * BLD;
-  __shared__ L As[2][ASZ];
-  __shared__ L Bs[2][BSZ];
+  constexpr int BSZ = BF ? BN * BLD : BK * BLD;
+  // epilogue staging: per wave NCP columns x CLD rows per pass
+  constexpr int NPASS = (KIND == GK_F64) ? 2 : 1;
+  constexpr int NCP = 32 / NPASS;  // columns staged per pass
+  constexpr int LPC = 64 / NCP;    // lanes sharing one column
+  constexpr int CLD = BM + 4;
+  constexpr int STAGE_BYTES = 2 * (ASZ + BSZ) * (int)sizeof(L);
+  constexpr int C_BYTES = 4 * NCP * CLD * (int)sizeof(S);
+  __shared__ __attribute__((aligned(16))) char smem[cmax(STAGE_BYTES, C_BYTES)];
+  L* const As = (L*)smem;
+  L* const Bs = As + 2 * ASZ;
 
-  // global -> register slots: A has BM*BK/4 vectors, B has BK*BN/4
   constexpr int AV = BM * BK / 4, BV = BK * BN / 4;
   constexpr int NA = (AV + 255) / 256, NB = (BV + 255) / 256;
   constexpr int AKV = BK / 4;  // vectors per A row
@@ -100,10 +116,14 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs a) {
   const int n0 = blockIdx.y * BN;
   const S* __restrict__ X = (const S*)a.X;
   const S* __restrict__ Wt = (const S*)a.W;
-  const bool avec = (a.ldx % 4 == 0) && (a.K % 4 == 0) && ((a.xws % 4) == 0) &&
+  const bool kfull = (a.K % BK) == 0;
+  const bool avec = (a.ldx % 4 == 0) && ((a.xws % 4) == 0) &&
                     ((reinterpret_cast<uintptr_t>(X) % (4 * sizeof(S))) == 0);
-  const bool bvec = (a.ldw % 4 == 0) && (reinterpret_cast<uintptr_t>(Wt) % (4 * sizeof(S)) == 0) &&
-                    (a.transw ? (a.K % 4 == 0) : (a.Ncols % 4 == 0));
+  const bool bvec = (a.ldw % 4 == 0) && (reinterpret_cast<uintptr_t>(Wt) % (4 * sizeof(S)) == 0);
+  // Fast path: every operand load is an unconditional 16-byte load.  Rows past the end and
+  // columns past Ncols are clamped to the last valid ones; their products land only in outputs
+  // that the epilogue does not store (rows are checked per row, jet groups are whole).
+  const bool fast = kfull && avec && bvec && (a.Ncols % 4 == 0) && (a.K % 4 == 0);
 
   // fixed row pointers of this thread's A slots
   const S* arow[NA];
@@ -116,17 +136,33 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs a) {
     akk[u] = (v % AKV) * 4;
     const int64_t r = m0 + arr[u];
     aval[u] = (v < AV) && (r < a.rows);
-    const uint32_t rr = aval[u] ? (uint32_t)r : 0u, rpw = (uint32_t)a.xrpw;
+    const uint32_t rr = (uint32_t)(r < a.rows ? r : a.rows - 1), rpw = (uint32_t)a.xrpw;
     const uint32_t qb = rr / rpw;
     arow[u] = X + (int64_t)qb * a.xws + (int64_t)(rr - qb * rpw) * a.ldx;
   }
   S ra[NA][4], rb[NB][4];
 
-  auto load_tiles = [&](int k0) {
+  // B slot v: float32/float64 with W row-major (k, n): 4 consecutive columns of row k;
+  // transposed W and bf16: 4 consecutive k of column n
+  int bkk[NB], bnn[NB];
+  {
+    const bool tr = BF || a.transw;
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+      const int v = tid + 256 * u;
+      bkk[u] = tr ? (v / BN) * 4 : v / (BN / 4);
+      bnn[u] = tr ? v % BN : (v % (BN / 4)) * 4;
+    }
+  }
+
+  // MODE 0: bounds-checked loads; 1: fast, W row-major; 2: fast, W transposed
+  auto load_tiles = [&](int k0, auto mode_tag) {
+    constexpr int MODE = decltype(mode_tag)::value;
 #pragma unroll
     for (int u = 0; u < NA; ++u) {
+      if (tid + 256 * u >= AV) continue;
       const int k = k0 + akk[u];
-      if (aval[u] && avec && k + 3 < a.K) {
+      if (MODE != 0 || (aval[u] && avec && k + 3 < a.K)) {
         const Vec t = *(const Vec*)(arow[u] + k);
         ra[u][0] = t.x;
         ra[u][1] = t.y;
@@ -141,15 +177,36 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs a) {
     for (int u = 0; u < NB; ++u) {
       const int v = tid + 256 * u;
       if (v >= BV) continue;
-      const int n = v % BN, kk = (v / BN) * 4;  // 4 consecutive k of output column n
-      const int kg = k0 + kk, ng = n0 + n;
-      if (!a.transw) {
-        const S* src = Wt + (int64_t)kg * a.ldw + ng;
+      const int kg = k0 + bkk[u];
+      int ng = n0 + bnn[u];
+      if (MODE == 1 || (MODE == 0 && !a.transw)) {
+        if constexpr (!BF) {
+          // 4 consecutive columns of W row kg
+          if (MODE == 1) ng = ng < a.Ncols ? ng : a.Ncols - 4;
+          const S* src = Wt + (int64_t)kg * a.ldw + ng;
+          if (MODE == 1 || (bvec && kg < a.K && ng + 3 < a.Ncols)) {
+            const Vec t = *(const Vec*)src;
+            rb[u][0] = t.x;
+            rb[u][1] = t.y;
+            rb[u][2] = t.z;
+            rb[u][3] = t.w;
+          } else {
 #pragma unroll
-        for (int e = 0; e < 4; ++e) rb[u][e] = (ng < a.Ncols && kg + e < a.K) ? src[(int64_t)e * a.ldw] : S(0);
+            for (int e = 0; e < 4; ++e) rb[u][e] = (kg < a.K && ng + e < a.Ncols) ? src[e] : S(0);
+          }
+        } else {
+          // 4 consecutive k of column ng (strided by ldw)
+          if (MODE == 1) ng = ng < a.Ncols ? ng : a.Ncols - 1;
+          const S* src = Wt + (int64_t)kg * a.ldw + ng;
+#pragma unroll
+          for (int e = 0; e < 4; ++e)
+            rb[u][e] = (MODE == 1 || (ng < a.Ncols && kg + e < a.K)) ? src[(int64_t)e * a.ldw] : S(0);
+        }
       } else {
+        // 4 consecutive k of W^T column ng
+        if (MODE == 2) ng = ng < a.Ncols ? ng : a.Ncols - 1;
         const S* src = Wt + (int64_t)ng * a.ldw + kg;
-        if (bvec && ng < a.Ncols && kg + 3 < a.K) {
+        if (MODE == 2 || (bvec && ng < a.Ncols && kg + 3 < a.K)) {
           const Vec t = *(const Vec*)src;
           rb[u][0] = t.x;
           rb[u][1] = t.y;
@@ -166,8 +223,8 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs a) {
 #pragma unroll
     for (int u = 0; u < NA; ++u) {
       if (tid + 256 * u >= AV) continue;
-      L* dst = &As[buf][arr[u] * ALD + akk[u]];
-      if constexpr (KIND == GK_BF16) {
+      L* dst = &As[buf * ASZ + arr[u] * ALD + akk[u]];
+      if constexpr (BF) {
 #pragma unroll
         for (int e = 0; e < 4; ++e) dst[e] = (L)ra[u][e];
       } else {
@@ -178,13 +235,18 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs a) {
     for (int u = 0; u < NB; ++u) {
       const int v = tid + 256 * u;
       if (v >= BV) continue;
-      const int n = v % BN, kk = (v / BN) * 4;
-      L* dst = &Bs[buf][n * BLD + kk];
-      if constexpr (KIND == GK_BF16) {
+      const int kk = bkk[u], nn = bnn[u];
+      if constexpr (BF) {
+        L* dst = &Bs[buf * BSZ + nn * BLD + kk];
 #pragma unroll
         for (int e = 0; e < 4; ++e) dst[e] = (L)rb[u][e];
       } else {
-        *(Vec*)dst = Vec{rb[u][0], rb[u][1], rb[u][2], rb[u][3]};
+        if (!a.transw) {
+          *(Vec*)&Bs[buf * BSZ + kk * BLD + nn] = Vec{rb[u][0], rb[u][1], rb[u][2], rb[u][3]};
+        } else {
+#pragma unroll
+          for (int e = 0; e < 4; ++e) Bs[buf * BSZ + (kk + e) * BLD + nn] = rb[u][e];
+        }
       }
     }
   };
@@ -199,235 +261,217 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs a) {
 
   const int g = lane >> 4, c = lane & 15;
   const int nk = (a.K + BK - 1) / BK;
-  load_tiles(0);
-  store_tiles(0);
-  __syncthreads();
-  for (int kt = 0; kt < nk; ++kt) {
-    const int cur = kt & 1;
-    if (kt + 1 < nk) load_tiles((kt + 1) * BK);
-    const L* Ac = As[cur];
-    const L* Bc = Bs[cur];
-    if constexpr (KIND == GK_BF16) {
-      bf16x8 bv[2];
+
+  auto mainloop = [&](auto mode_tag) {
+    load_tiles(0, mode_tag);
+    store_tiles(0);
+    __syncthreads();
+    for (int kt = 0; kt < nk; ++kt) {
+      const int cur = kt & 1;
+      if (kt + 1 < nk) load_tiles((kt + 1) * BK, mode_tag);
+      const L* Ac = As + cur * ASZ;
+      const L* Bc = Bs + cur * BSZ;
+      if constexpr (BF) {
+        bf16x8 bv[2];
 #pragma unroll
-      for (int nb = 0; nb < 2; ++nb) bv[nb] = *(const bf16x8*)&Bc[(wave * 32 + nb * 16 + c) * BLD + 8 * g];
-#pragma unroll
-      for (int mb = 0; mb < MB; ++mb) {
-        const bf16x8 av = *(const bf16x8*)&Ac[(mb * 16 + c) * ALD + 8 * g];
-#pragma unroll
-        for (int nb = 0; nb < 2; ++nb)
-          acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv[nb], acc[mb][nb], 0, 0, 0);
-      }
-    } else {
-      // lane group g supplies k = 4g + kq at MFMA step kq (the same order for A and B)
-#pragma unroll
-      for (int k4 = 0; k4 < BK / 16; ++k4) {
-        Vec bv[2];
-#pragma unroll
-        for (int nb = 0; nb < 2; ++nb) bv[nb] = *(const Vec*)&Bc[(wave * 32 + nb * 16 + c) * BLD + k4 * 16 + 4 * g];
+        for (int nb = 0; nb < 2; ++nb) bv[nb] = *(const bf16x8*)&Bc[(wave * 32 + nb * 16 + c) * BLD + 8 * g];
 #pragma unroll
         for (int mb = 0; mb < MB; ++mb) {
-          const Vec av = *(const Vec*)&Ac[(mb * 16 + c) * ALD + k4 * 16 + 4 * g];
+          const bf16x8 av = *(const bf16x8*)&Ac[(mb * 16 + c) * ALD + 8 * g];
 #pragma unroll
-          for (int nb = 0; nb < 2; ++nb) {
-            if constexpr (KIND == GK_F64) {
-              acc[mb][nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av.x, bv[nb].x, acc[mb][nb], 0, 0, 0);
-              acc[mb][nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av.y, bv[nb].y, acc[mb][nb], 0, 0, 0);
-              acc[mb][nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av.z, bv[nb].z, acc[mb][nb], 0, 0, 0);
-              acc[mb][nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av.w, bv[nb].w, acc[mb][nb], 0, 0, 0);
-            } else {
-              acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.x, bv[nb].x, acc[mb][nb], 0, 0, 0);
-              acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.y, bv[nb].y, acc[mb][nb], 0, 0, 0);
-              acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.z, bv[nb].z, acc[mb][nb], 0, 0, 0);
-              acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.w, bv[nb].w, acc[mb][nb], 0, 0, 0);
+          for (int nb = 0; nb < 2; ++nb)
+            acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv[nb], acc[mb][nb], 0, 0, 0);
+        }
+      } else {
+        // lane group g supplies k = 4g + kq at MFMA step kq (the same order for A and B)
+#pragma unroll
+        for (int k4 = 0; k4 < BK / 16; ++k4) {
+          S bq[2][4];
+#pragma unroll
+          for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+            for (int kq = 0; kq < 4; ++kq) bq[nb][kq] = Bc[(k4 * 16 + 4 * g + kq) * BLD + wave * 32 + nb * 16 + c];
+#pragma unroll
+          for (int mb = 0; mb < MB; ++mb) {
+            const Vec av = *(const Vec*)&Ac[(mb * 16 + c) * ALD + k4 * 16 + 4 * g];
+#pragma unroll
+            for (int nb = 0; nb < 2; ++nb) {
+              if constexpr (KIND == GK_F64) {
+                acc[mb][nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av.x, bq[nb][0], acc[mb][nb], 0, 0, 0);
+                acc[mb][nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av.y, bq[nb][1], acc[mb][nb], 0, 0, 0);
+                acc[mb][nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av.z, bq[nb][2], acc[mb][nb], 0, 0, 0);
+                acc[mb][nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av.w, bq[nb][3], acc[mb][nb], 0, 0, 0);
+              } else {
+                acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.x, bq[nb][0], acc[mb][nb], 0, 0, 0);
+                acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.y, bq[nb][1], acc[mb][nb], 0, 0, 0);
+                acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.z, bq[nb][2], acc[mb][nb], 0, 0, 0);
+                acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.w, bq[nb][3], acc[mb][nb], 0, 0, 0);
+              }
             }
           }
         }
       }
-    }
-    if (kt + 1 < nk) store_tiles(cur ^ 1);
-    __syncthreads();
-  }
-
-  // ---------------- epilogue ----------------
-  // row (inside a 16-row block) of accumulator element i of this lane
-  auto rowof = [&](int gg, int i) -> int { return KIND == GK_F64 ? gg + 4 * i : 4 * gg + i; };
-  const S* __restrict__ bias = (const S*)a.bias;
-  const S* __restrict__ Res = (const S*)a.Res;
-  S* __restrict__ Y = (S*)a.Y;
-  const int g4 = g;
-  const int c16 = c;
-  // jet groups spanning whole 16-row blocks: block mb is block (mb % bpg) of group mb / bpg
-  int qbase[MB], grp[MB];
-  const int bpg = (EPI == 2) ? (a.Rp >> 4) : 1;
-#pragma unroll
-  for (int mb = 0; mb < MB; ++mb) {
-    grp[mb] = mb / bpg;
-    qbase[mb] = (mb - grp[mb] * bpg) * 16;
-  }
-  // global row group and electron (group mod nel) of each 16-row block, for add5
-  int64_t gidx[MB];
-  int gel[MB];
-  if (EPI == 2 && a.add5) {
-    const uint32_t g0 = (uint32_t)m0 / (uint32_t)a.Rp;
-#pragma unroll
-    for (int mb = 0; mb < MB; ++mb) {
-      gidx[mb] = (int64_t)g0 + grp[mb];
-      gel[mb] = (int)((g0 + (uint32_t)grp[mb]) % (uint32_t)a.nel);
-    }
-  } else {
-#pragma unroll
-    for (int mb = 0; mb < MB; ++mb) {
-      gidx[mb] = 0;
-      gel[mb] = 0;
-    }
-  }
-  // output row offsets of this lane's 4*MB rows: one 32-bit division per 16-row block, then
-  // stepping through the rows (rows of one lane are consecutive for f32/bf16, 4 apart for f64)
-  int64_t yoff[MB][4];
-  bool yval[MB][4];
-  {
-    const uint32_t rpw = (uint32_t)a.yrpw;
-#pragma unroll
-    for (int mb = 0; mb < MB; ++mb) {
-      const int64_t r0 = m0 + mb * 16 + rowof(g4, 0);
-      const uint32_t rr = (uint32_t)r0;
-      uint32_t qb = rr / rpw, rem = rr - qb * rpw;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        yval[mb][i] = (r0 + (rowof(g4, i) - rowof(g4, 0))) < a.rows;
-        yoff[mb][i] = (int64_t)qb * a.yws + (int64_t)rem * a.ldy;
-        const uint32_t step = (uint32_t)(rowof(g4, 1) - rowof(g4, 0));
-        rem += step;
-        while (rem >= rpw) {
-          rem -= rpw;
-          ++qb;
-        }
-      }
-    }
-  }
-  auto emit = [&](int mb, int i, int col, S o) {
-    if (yval[mb][i] && col < a.Ncols) {
-      const int64_t off = yoff[mb][i] + col;
-      if (a.act == 2) {
-        const S t = ((const S*)a.aux)[off];
-        o *= S(1) - t * t;
-      }
-      if (Res) o += Res[off];
-      Y[off] = o;
+      if (kt + 1 < nk) store_tiles(cur ^ 1);
+      __syncthreads();
     }
   };
+  if (fast && !a.transw)
+    mainloop(std::integral_constant<int, 1>{});
+  else if (fast)
+    mainloop(std::integral_constant<int, 2>{});
+  else
+    mainloop(std::integral_constant<int, 0>{});
+
+  // ---------------- epilogue ----------------
+  // The loop ended with a barrier after the last LDS reads, so the stage buffers can be reused.
+  const S* __restrict__ bias = (const S*)a.bias;
+  const S* __restrict__ Res = (const S*)a.Res;
+  const S* __restrict__ Aux = (const S*)a.aux;
+  S* __restrict__ Y = (S*)a.Y;
+  S* const Cw = (S*)smem + wave * NCP * CLD;
+  const int cl = lane % NCP, sub = lane / NCP;
+
 #pragma unroll
-  for (int nb = 0; nb < 2; ++nb) {
-    const int col = n0 + wave * 32 + nb * 16 + c16;
-    const bool cvalid = col < a.Ncols;
-    const S b = (bias && cvalid) ? bias[col] : S(0);
-    if constexpr (EPI == 0) {
+  for (int pass = 0; pass < NPASS; ++pass) {
+    if (pass > 0) __syncthreads();  // the previous pass's reads are done
 #pragma unroll
-      for (int mb = 0; mb < MB; ++mb)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const S z = acc[mb][nb][i] + b;
-          emit(mb, i, col, a.act == 1 ? dtanh(z) : z);
-        }
-    } else if constexpr (EPI == 1) {
-      // univariate jets: groups of 4 rows (value, first, second derivative, pad)
+    for (int nb = 0; nb < 2; ++nb) {
+      if (NPASS == 2 && nb != pass) continue;
+      const int ccol = (NPASS == 1 ? nb * 16 : 0) + c;
 #pragma unroll
       for (int mb = 0; mb < MB; ++mb) {
         if constexpr (KIND == GK_F64) {
-          // element i of lane group g4 holds row 4*i + g4: the group is spread over the 4 lane groups
 #pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            const S z0 = __shfl(acc[mb][nb][i], c16) + b, z1 = __shfl(acc[mb][nb][i], c16 + 16),
-                    z2 = __shfl(acc[mb][nb][i], c16 + 32);
-            S o0 = z0, o1 = z1, o2 = z2;
-            if (a.act) {
-              const S t = dtanh(z0), t1 = S(1) - t * t, t2 = S(-2) * t * t1;
-              o0 = t;
-              o1 = t1 * z1;
-              o2 = t1 * z2 + t2 * z1 * z1;
+          for (int i = 0; i < 4; ++i) Cw[ccol * CLD + mb * 16 + g + 4 * i] = acc[mb][nb][i];
+        } else {
+          *(f4*)&Cw[ccol * CLD + mb * 16 + 4 * g] = acc[mb][nb];
+        }
+      }
+    }
+    __syncthreads();
+
+    const int col = n0 + wave * 32 + pass * NCP + cl;
+    const bool cvalid = col < a.Ncols;
+    const S b = (bias && cvalid) ? bias[col] : S(0);
+    const S* Cc = Cw + cl * CLD;
+
+    if constexpr (EPI == 0 || EPI == 1) {
+      // a run of R0 consecutive rows per lane
+      constexpr int R0 = BM / LPC;
+      const int64_t rs = m0 + sub * R0;
+      const uint32_t rpw = (uint32_t)a.yrpw;
+      uint32_t qb = (uint32_t)rs / rpw, rem = (uint32_t)rs - qb * rpw;
+      auto next_off = [&]() {
+        const int64_t off = (int64_t)qb * a.yws + (int64_t)rem * a.ldy + col;
+        if (++rem == rpw) {
+          rem = 0;
+          ++qb;
+        }
+        return off;
+      };
+      if (cvalid) {
+        if constexpr (EPI == 0) {
+#pragma unroll 4
+          for (int r = 0; r < R0; ++r) {
+            if (rs + r >= a.rows) break;
+            const int64_t off = next_off();
+            const S z = Cc[sub * R0 + r] + b;
+            S o = a.act == 1 ? dtanh(z) : z;
+            if (a.act == 2) {
+              const S t = Aux[off];
+              o *= S(1) - t * t;
             }
-            emit(mb, i, col, g4 == 0 ? o0 : (g4 == 1 ? o1 : (g4 == 2 ? o2 : S(0))));
+            if (Res) o += Res[off];
+            Y[off] = o;
           }
         } else {
-          // one lane holds a whole group
-          const S z0 = acc[mb][nb][0] + b, z1 = acc[mb][nb][1], z2 = acc[mb][nb][2];
-          S o0 = z0, o1 = z1, o2 = z2;
-          if (a.act) {
-            const S t = dtanh(z0), t1 = S(1) - t * t, t2 = S(-2) * t * t1;
-            o0 = t;
-            o1 = t1 * z1;
-            o2 = t1 * z2 + t2 * z1 * z1;
+          // univariate jets: groups of 4 rows (value, first, second derivative, pad)
+          for (int r = 0; r < R0; r += 4) {
+            if (rs + r >= a.rows) break;
+            const S z0 = Cc[sub * R0 + r] + b, z1 = Cc[sub * R0 + r + 1], z2 = Cc[sub * R0 + r + 2];
+            S o[4] = {z0, z1, z2, S(0)};
+            if (a.act) {
+              const S t = dtanh(z0), t1 = S(1) - t * t, t2 = S(-2) * t * t1;
+              o[0] = t;
+              o[1] = t1 * z1;
+              o[2] = t1 * z2 + t2 * z1 * z1;
+            }
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+              const int64_t off = next_off();
+              Y[off] = Res ? o[e] + Res[off] : o[e];
+            }
           }
-          emit(mb, 0, col, o0);
-          emit(mb, 1, col, o1);
-          emit(mb, 2, col, o2);
-          emit(mb, 3, col, S(0));
         }
       }
     } else {
-      // EPI == 2: groups of Rp = 16*bpg rows spanning whole 16-row blocks
-      if (a.add5 && cvalid) {
-        // the 5 nonzero rows of a term that depends on the electron's own position only
-        const S* A5 = (const S*)a.add5;
-#pragma unroll
-        for (int mb = 0; mb < MB; ++mb) {
-          const int e = gel[mb];
-#pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            const int q = qbase[mb] + rowof(g4, i);
+      // EPI == 2: groups of Rp rows; a lane takes whole groups, or one part of a group when the
+      // tile has fewer groups than lanes per column
+      const int Rp = a.Rp, T = a.T;
+      const int Gt = BM / Rp;                    // groups in the tile (1, 2, 4 or 8)
+      const int PPG = Gt >= LPC ? 1 : LPC / Gt;  // lanes per group
+      const int GPL = Gt >= LPC ? Gt / LPC : 1;  // groups per lane
+      const int rpp = Rp / PPG;
+      const S* __restrict__ A5 = (const S*)a.add5;
+      for (int j = 0; j < GPL; ++j) {
+        const int grp = PPG == 1 ? sub + LPC * j : sub / PPG;
+        const int part = PPG == 1 ? 0 : sub % PPG;
+        const int qlo = part * rpp;
+        const int64_t rg = m0 + (int64_t)grp * Rp;  // first row of the group
+        const bool gvalid = cvalid && rg < a.rows;
+        const int64_t gidx = rg / Rp;
+        const int el = A5 ? (int)(gidx % a.nel) : -1;
+        const S* Cg = Cc + grp * Rp;
+        // pre-activation of row q, including the bias and the five-row term
+        auto zrow = [&](int q) -> S {
+          S z = Cg[q];
+          if (q == 0) z += b;
+          if (A5) {
             int k5 = -1;
             if (q == 0)
               k5 = 0;
-            else if (q == a.T + 1)
+            else if (q == T + 1)
               k5 = 4;
-            else if (q >= 1 && q <= a.T && (q - 1) / 3 == e)
-              k5 = 1 + (q - 1) % 3;
-            if (k5 >= 0 && yval[mb][i]) acc[mb][nb][i] += A5[(gidx[mb] * 5 + k5) * a.Ncols + col];
+            else if (q >= 1 + 3 * el && q <= 3 + 3 * el)
+              k5 = q - 3 * el;
+            if (k5 >= 0) z += A5[(gidx * 5 + k5) * a.Ncols + col];
+          }
+          return z;
+        };
+        S ssq = 0, z0 = 0;
+        if (gvalid) {
+          z0 = zrow(0);
+          const int q1 = qlo < 1 ? 1 : qlo, q2 = qlo + rpp - 1 < T ? qlo + rpp - 1 : T;
+          for (int q = q1; q <= q2; ++q) {
+            const S z = zrow(q);
+            ssq += z * z;
           }
         }
-      }
-      S ssq[MB], z0b[MB];
-#pragma unroll
-      for (int mb = 0; mb < MB; ++mb) {
-        S sq = 0;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const int q = qbase[mb] + rowof(g4, i);
-          if (q >= 1 && q <= a.T) sq += acc[mb][nb][i] * acc[mb][nb][i];
-        }
-        sq += __shfl_xor(sq, 16);
-        sq += __shfl_xor(sq, 32);
-        ssq[mb] = sq;
-        z0b[mb] = __shfl(acc[mb][nb][0], c16) + b;  // row 0 of this block (the value row when it starts a group)
-      }
-#pragma unroll
-      for (int mb = 0; mb < MB; ++mb) {
-        S S2 = 0, z0 = 0;
-#pragma unroll
-        for (int mq = 0; mq < MB; ++mq) {
-          if (grp[mq] == grp[mb]) S2 += ssq[mq];
-          if (grp[mq] == grp[mb] && qbase[mq] == 0) z0 = z0b[mq];
-        }
-        S t = z0, t1 = 1, t2 = 0;
-        if (a.act) {
-          t = dtanh(z0);
-          t1 = S(1) - t * t;
-          t2 = S(-2) * t * t1;
-        }
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const int q = qbase[mb] + rowof(g4, i);
-          S o;
-          if (q == 0)
-            o = t;
-          else if (q <= a.T)
-            o = t1 * acc[mb][nb][i];
-          else if (q == a.T + 1)
-            o = t1 * acc[mb][nb][i] + t2 * S2;
-          else
-            o = 0;
-          emit(mb, i, col, o);
+        for (int o = 1; o < PPG; o <<= 1) ssq += __shfl_xor(ssq, NCP * o);
+        if (gvalid) {
+          S t = z0, t1 = 1, t2 = 0;
+          if (a.act) {
+            t = dtanh(z0);
+            t1 = S(1) - t * t;
+            t2 = S(-2) * t * t1;
+          }
+          const uint32_t rpw = (uint32_t)a.yrpw;
+          const uint32_t qb = (uint32_t)rg / rpw;
+          const int64_t base = (int64_t)qb * a.yws + (int64_t)((uint32_t)rg - qb * rpw) * a.ldy + col;
+          for (int q = qlo; q < qlo + rpp; ++q) {
+            S o;
+            if (q == 0)
+              o = t;
+            else if (q <= T)
+              o = t1 * zrow(q);
+            else if (q == T + 1)
+              o = t1 * zrow(q) + t2 * ssq;
+            else
+              o = 0;
+            const int64_t off = base + (int64_t)q * a.ldy;
+            if (Res) o += Res[off];
+            Y[off] = o;
+          }
         }
       }
     }
@@ -457,55 +501,25 @@ static hipError_t launch_mb(const GemmArgs& a, hipStream_t st) {
   return hipGetLastError();
 }
 
-// Tile choice: rows per tile (MB blocks of 16) and K per pipeline stage.
-// QMC_GEMM_TILE=<mbmul>,<bk> overrides it for tuning runs: mbmul doubles the
-// row blocks of jet tiles (and of value/edge tiles), bk in {16, 32}.
-static int tile_mul() {
-  static int v = -1;
-  if (v < 0) {
-    v = 1;
-    if (const char* e = getenv("QMC_GEMM_TILE")) v = atoi(e) == 2 ? 2 : 1;
+// Tile choice (GemmArgs::tile, or QMC_GEMM_TILE=<bits> for tuning runs): bit 0 selects 32-wide K
+// stages for float32, bit 1 half-height (64-row) value and edge tiles.
+static int tile_bits(const GemmArgs& a) {
+  static int env = -2;
+  if (env == -2) {
+    env = -1;
+    if (const char* e = getenv("QMC_GEMM_TILE")) env = atoi(e) & 3;
   }
-  return v;
-}
-static int tile_bk(int def) {
-  static int v = -1;
-  if (v < 0) {
-    v = 0;
-    if (const char* e = getenv("QMC_GEMM_TILE"))
-      if (const char* c = strchr(e, ',')) v = atoi(c + 1) == 32 ? 32 : (atoi(c + 1) == 16 ? 16 : 0);
-  }
-  return v ? v : def;
+  return env >= 0 ? env : (a.tile & 3);
 }
 
 template <int KIND, int BKT>
-static hipError_t launch_kind_bk(const GemmArgs& a, hipStream_t st) {
-  constexpr bool WIDE = (KIND == GK_F32);  // larger tiles are only instantiated for float32
-  const int mul = WIDE ? tile_mul() : 1;
-  if (a.vmode) {
-    if constexpr (WIDE)
-      if (mul == 2) return launch_mb<KIND, 16, 0, BKT>(a, st);
-    return launch_mb<KIND, 8, 0, BKT>(a, st);
-  }
-  if (a.Rp == 4) {
-    if constexpr (WIDE)
-      if (mul == 2) return launch_mb<KIND, 16, 1, BKT>(a, st);
-    return launch_mb<KIND, 8, 1, BKT>(a, st);
-  }
+static hipError_t launch_kind_bk(const GemmArgs& a, int bits, hipStream_t st) {
+  const bool half = (bits & 2) != 0;
+  if (a.vmode) return half ? launch_mb<KIND, 4, 0, BKT>(a, st) : launch_mb<KIND, 8, 0, BKT>(a, st);
+  if (a.Rp == 4) return half ? launch_mb<KIND, 4, 1, BKT>(a, st) : launch_mb<KIND, 8, 1, BKT>(a, st);
   if (a.Rp % 16 != 0 || a.Rp > 128) return hipErrorInvalidValue;
   const int bpg = a.Rp / 16;
-  int mb = bpg * (8 / bpg);
-  if constexpr (WIDE) {
-    if (mul == 2) {
-      switch (mb) {
-        case 5: return launch_mb<KIND, 10, 2, BKT>(a, st);
-        case 6: return launch_mb<KIND, 12, 2, BKT>(a, st);
-        case 7: return launch_mb<KIND, 14, 2, BKT>(a, st);
-        case 8: return launch_mb<KIND, 16, 2, BKT>(a, st);
-      }
-    }
-  }
-  switch (mb) {
+  switch (bpg * (8 / bpg)) {
     case 5: return launch_mb<KIND, 5, 2, BKT>(a, st);
     case 6: return launch_mb<KIND, 6, 2, BKT>(a, st);
     case 7: return launch_mb<KIND, 7, 2, BKT>(a, st);
@@ -514,32 +528,24 @@ static hipError_t launch_kind_bk(const GemmArgs& a, hipStream_t st) {
   return hipErrorInvalidValue;
 }
 
-template <int KIND>
-static hipError_t launch_kind(const GemmArgs& a, hipStream_t st) {
-  if constexpr (KIND == GK_F32) {
-    if (tile_bk(16) == 32) return launch_kind_bk<KIND, 32>(a, st);
-    return launch_kind_bk<KIND, 16>(a, st);
-  } else if constexpr (KIND == GK_BF16) {
-    return launch_kind_bk<KIND, 32>(a, st);
-  } else {
-    return launch_kind_bk<KIND, 16>(a, st);
-  }
-}
-
 hipError_t launch_gemm(GemmKind kind, const GemmArgs& a, hipStream_t st) {
   if (a.rows <= 0 || a.Ncols <= 0) return hipSuccess;
   // row indices and rows-per-block are handled in 32 bits inside the kernel
   if (a.rows >= (int64_t(1) << 31) || a.xrpw <= 0 || a.yrpw <= 0 || a.xrpw >= (int64_t(1) << 31) ||
       a.yrpw >= (int64_t(1) << 31))
     return hipErrorInvalidValue;
-  if (!a.vmode && a.Rp == 4 && a.T != 1) return hipErrorInvalidValue;
+  if (!a.vmode && a.Rp == 4 && (a.T != 1 || a.rows % 4 != 0 || a.yrpw % 4 != 0)) return hipErrorInvalidValue;
+  // electron jets: whole groups of Rp rows, none straddling an output row block
+  if (!a.vmode && a.Rp != 4 && (a.Rp < 16 || a.rows % a.Rp != 0 || a.yrpw % a.Rp != 0)) return hipErrorInvalidValue;
   if (a.act == 2 && (!a.vmode || !a.aux)) return hipErrorInvalidValue;
   if (a.add5 && (a.vmode || a.Rp < 16 || a.nel < 1 || a.xrpw != a.rows || a.yrpw != a.rows))
     return hipErrorInvalidValue;
+  const int bits = tile_bits(a);
   switch (kind) {
-    case GK_F64: return launch_kind<GK_F64>(a, st);
-    case GK_F32: return launch_kind<GK_F32>(a, st);
-    case GK_BF16: return launch_kind<GK_BF16>(a, st);
+    case GK_F64: return launch_kind_bk<GK_F64, 16>(a, bits, st);
+    case GK_F32:
+      return (bits & 1) ? launch_kind_bk<GK_F32, 32>(a, bits, st) : launch_kind_bk<GK_F32, 16>(a, bits, st);
+    case GK_BF16: return launch_kind_bk<GK_BF16, 32>(a, bits, st);
   }
   return hipErrorInvalidValue;
 }
