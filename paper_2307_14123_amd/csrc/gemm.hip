@@ -501,15 +501,19 @@ static hipError_t launch_mb(const GemmArgs& a, hipStream_t st) {
   return hipGetLastError();
 }
 
-// Tile choice (GemmArgs::tile, or QMC_GEMM_TILE=<bits> for tuning runs): bit 0 selects 32-wide K
-// stages for float32, bit 1 half-height (64-row) value and edge tiles.
+// Tile choice (GemmArgs::tile - 1 when nonzero, or QMC_GEMM_TILE=<bits> for tuning runs): bit 0
+// selects 32-wide K stages for float32, bit 1 half-height (64-row) value and edge tiles.  The
+// default takes half-height tiles when full ones would give fewer than 4 blocks per compute unit.
 static int tile_bits(const GemmArgs& a) {
   static int env = -2;
   if (env == -2) {
     env = -1;
     if (const char* e = getenv("QMC_GEMM_TILE")) env = atoi(e) & 3;
   }
-  return env >= 0 ? env : (a.tile & 3);
+  if (env >= 0) return env;
+  if (a.tile > 0) return (a.tile - 1) & 3;
+  const int64_t blocks = ((a.rows + 127) / 128) * ((a.Ncols + 127) / 128);
+  return (a.vmode || a.Rp == 4) && blocks < 4 * 256 ? 2 : 0;
 }
 
 template <int KIND, int BKT>

@@ -53,7 +53,8 @@ struct GemmArgs {
   // the value row, the 3 rows of the electron's own coordinates and the Laplacian row (N = nel)
   const void* add5;
   int nel;
-  // tile choice (0 = default): bit 0 selects 32-wide K stages (float32), bit 1 half-height value tiles
+  // tile choice: 0 = default, else 1 + bits (bit 0: 32-wide K stages for float32, bit 1: half-height
+  // value and edge tiles)
   int tile;
 };
 

@@ -444,37 +444,63 @@ hipError_t launch_nuc_message(const SysDev& s, const S* wnuc, const S* Y, const 
   return hipGetLastError();
 }
 
-// Value rows only (log|psi| without derivatives): one thread per (walker, receiver, column).
+// Value rows only (log|psi| without derivatives).  Block: one walker.  The
+// senders' features are staged in LDS (when they fit) with a table of pair
+// indices and types; each thread produces (receiver, column) outputs, so the
+// filter values are read once per ordered pair with consecutive columns.
 template <typename S>
-__global__ void aggregate_value_kernel(SysDev s, const S* __restrict__ h, const S* __restrict__ wsame,
-                                       const S* __restrict__ wopp, const S* __restrict__ wnuc,
-                                       const S* __restrict__ Y, int64_t W, S* __restrict__ m) {
+__global__ __launch_bounds__(256) void aggregate_value_kernel(SysDev s, const S* __restrict__ h,
+                                                              const S* __restrict__ wsame,
+                                                              const S* __restrict__ wopp,
+                                                              const S* __restrict__ wnuc,
+                                                              const S* __restrict__ Y, int stage,
+                                                              S* __restrict__ m) {
+  extern __shared__ __align__(16) unsigned char smem[];
   const int N = s.N, D = s.D, M = s.M;
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= W * N * D) return;
-  const int d = (int)(t % D);
-  const int i = (int)((t / D) % N);
-  const int64_t w = t / ((int64_t)N * D);
-  const bool up = i < s.nup;
-  const int nsame = (up ? s.nup : s.ndn) - 1;
-  const int nopp = up ? s.ndn : s.nup;
-  S ms = 0, mo = 0;
-  for (int j = 0; j < N; ++j) {
-    if (j == i) continue;
-    int type;
-    const int p = ee_pair(s, i, j, type);
-    const S hv = h[(w * N + j) * D + d];
-    if (type)
-      mo += wopp[(w * s.P1 + p) * D + d] * hv;
-    else
-      ms += wsame[(w * s.P0 + p) * D + d] * hv;
+  const int64_t w = blockIdx.x;
+  constexpr int OPP = 1 << 30;
+  int* po = (int*)smem;               // [N][N]: pair index, | OPP for an up-down pair
+  S* hs = (S*)(smem + ((N * N * sizeof(int) + 15) / 16) * 16);  // [N][D] when staged
+  for (int e = threadIdx.x; e < N * N; e += blockDim.x) {
+    const int i = e / N, j = e - (e / N) * N;
+    int v = 0;
+    if (i != j) {
+      int type;
+      const int p = ee_pair(s, i, j, type);
+      v = type ? (p | OPP) : p;
+    }
+    po[e] = v;
   }
-  S nuc = 0;
-  for (int I = 0; I < M; ++I) nuc += wnuc[(w * s.P2 + i * M + I) * D + d] * Y[I * D + d];
-  S* row = m + (w * N + i) * 3 * (int64_t)D + d;
-  row[0] = nsame > 0 ? ms / S(nsame) : S(0);
-  row[D] = nopp > 0 ? mo / S(nopp) : S(0);
-  row[2 * D] = nuc / S(M);
+  const S* hw = h + w * N * (int64_t)D;
+  if (stage)
+    for (int e = threadIdx.x; e < N * D; e += blockDim.x) hs[e] = hw[e];
+  __syncthreads();
+  const S* hsrc = stage ? hs : hw;
+  const S* wsw = wsame + w * s.P0 * (int64_t)D;
+  const S* wow = wopp + w * s.P1 * (int64_t)D;
+  const S* wnw = wnuc + w * s.P2 * (int64_t)D;
+  for (int o = threadIdx.x; o < N * D; o += blockDim.x) {
+    const int i = o / D, d = o - (o / D) * D;
+    const bool up = i < s.nup;
+    const int nsame = (up ? s.nup : s.ndn) - 1;
+    const int nopp = up ? s.ndn : s.nup;
+    S ms = 0, mo = 0;
+    for (int j = 0; j < N; ++j) {
+      if (j == i) continue;
+      const int v = po[i * N + j];
+      const S hv = hsrc[j * D + d];
+      if (v & OPP)
+        mo += wow[(int64_t)(v & (OPP - 1)) * D + d] * hv;
+      else
+        ms += wsw[(int64_t)v * D + d] * hv;
+    }
+    S nuc = 0;
+    for (int I = 0; I < M; ++I) nuc += wnw[(int64_t)(i * M + I) * D + d] * Y[I * D + d];
+    S* row = m + (w * N + i) * 3 * (int64_t)D + d;
+    row[0] = nsame > 0 ? ms / S(nsame) : S(0);
+    row[D] = nopp > 0 ? mo / S(nopp) : S(0);
+    row[2 * D] = nuc / S(M);
+  }
 }
 
 template <typename S, int NMAX>
@@ -497,11 +523,14 @@ static hipError_t agg_launch(const SysDev& s, const S* h, const S* ws, const S* 
 template <typename S>
 hipError_t launch_aggregate(const SysDev& s, const S* h, const S* wsame, const S* wopp, const S* wnuc, const S* Y,
                             const double* ee, const double* en, int64_t W, int jet, S* m, hipStream_t st) {
+  if (W <= 0) return hipSuccess;
   if (!jet) {
-    const int64_t n = W * s.N * s.D;
+    const size_t tab = ((size_t)s.N * s.N * sizeof(int) + 15) / 16 * 16;
+    const size_t hb = (size_t)s.N * s.D * sizeof(S);
+    const int stage = tab + hb <= 64 * 1024;
     ProfScope ps("aggregate_value_kernel", st);
-    hipLaunchKernelGGL(aggregate_value_kernel<S>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, s, h, wsame,
-                       wopp, wnuc, Y, W, m);
+    hipLaunchKernelGGL(aggregate_value_kernel<S>, dim3((unsigned)W), dim3(256), tab + (stage ? hb : 0), st, s, h,
+                       wsame, wopp, wnuc, Y, stage, m);
     return hipGetLastError();
   }
   if (s.N <= 4) return agg_launch<S, 4>(s, h, wsame, wopp, ee, W, m, st);
