@@ -40,7 +40,9 @@
  *     the ABI.  Numerical anomalies are data: psi = 0 gives sign 0 and
  *     logpsi = -inf, and an undefined local energy is NaN.
  *   Concurrency: a plan is immutable after creation; concurrent calls on
- *     different streams with different workspaces are safe.
+ *     different streams with different workspaces are safe, except on a
+ *     plan created with QMC_PLAN_CONCURRENT_SYSTEMS (its internal streams
+ *     are shared by all calls).
  */
 #ifndef QMC_H_
 #define QMC_H_
@@ -123,15 +125,38 @@ typedef struct qmc_plan qmc_plan;
  *   c[n_det]. */
 int64_t qmc_param_count(const qmc_system* system, const qmc_ansatz* ansatz);
 
+/* Plan flags.
+ * QMC_PLAN_CONCURRENT_SYSTEMS: a multi-system plan runs the kernel sequence
+ *   of every system on its own stream owned by the plan, forked from and
+ *   joined back to the caller's stream with events, so that the systems
+ *   (molecules of different sizes) share the device; captured into a graph,
+ *   the whole batch is one graph launch.  Each system then has its own
+ *   workspace region (the workspace is the sum over systems instead of the
+ *   maximum).  Calls on such a plan must not overlap (one caller stream at a
+ *   time, in host order).
+ * QMC_PLAN_AUTOTUNE: qmc_plan_create times the candidate GEMM tiles (K-step,
+ *   tile height, persistent grid) on the current device for every system's
+ *   jet, value, edge and backward GEMM shapes and keeps the fastest.  This
+ *   allocates device memory transiently and synchronises the device. */
+enum { QMC_PLAN_CONCURRENT_SYSTEMS = 1u, QMC_PLAN_AUTOTUNE = 2u };
+
 /* Create a plan for n_systems systems with walkers_per_system[s] walkers
- * each (host arrays).  flags: reserved, must be 0.  On success *out owns the
- * plan; release it with qmc_plan_destroy.  Host only: no device memory is
- * allocated and nothing is launched. */
+ * each (host arrays).  flags: a combination of QMC_PLAN_* (0 for none);
+ * unknown bits are an invalid argument.  On success *out owns the plan;
+ * release it with qmc_plan_destroy.  Without flags this is host only: no
+ * device memory is allocated and nothing is launched.  With flags it creates
+ * streams and events on the current device (QMC_ERR_HIP if that fails). */
 qmc_status qmc_plan_create(qmc_plan** out, const qmc_system* systems, int32_t n_systems,
                            const int64_t* walkers_per_system, const qmc_ansatz* ansatz,
                            qmc_precision precision, uint32_t flags);
 
 qmc_status qmc_plan_destroy(qmc_plan* plan);
+
+/* GEMM tile choice of system s, one entry per GEMM class (electron jets,
+ * value rows, edge jets, backward value rows): 0 = built-in default, else
+ * 1 + bits (bit 0: 32-wide K steps, bit 1: 64-row tiles, bit 2: persistent
+ * grid).  Host only. */
+qmc_status qmc_plan_tiles(const qmc_plan* plan, int32_t s, int32_t tiles[4]);
 
 /* Bytes of workspace that operation `op` (QMC_OP_*) needs. */
 qmc_status qmc_workspace_size(const qmc_plan* plan, int32_t op, size_t* bytes);

@@ -64,6 +64,13 @@ static GemmKind embed_kind(qmc_precision p) {
 }
 static GemmKind orbital_kind(qmc_precision p) { return p == QMC_FP64 ? GK_F64 : GK_F32; }
 
+// GEMM with the plan's tile choice for its class (electron jets, edge jets, value rows, backward).
+static hipError_t gemm(const SysPlan& s, GemmKind kind, GemmArgs a, hipStream_t st) {
+  const int cls = !a.vmode ? (a.Rp == 4 ? TILE_EDGE : TILE_JET) : (a.transw ? TILE_BWD : TILE_VAL);
+  if (a.tile == 0) a.tile = s.tile[cls];
+  return launch_gemm(kind, a, st);
+}
+
 static GemmArgs dense(const void* X, int64_t ldx, const void* W, int64_t ldw, const void* bias, void* Y, int64_t ldy,
                       int64_t rows, int K, int Ncols, int Rp, int T, int act, int vmode) {
   GemmArgs a;
@@ -136,9 +143,9 @@ static qmc_status forward_chunk(const Plan& P, const SysPlan& s, const S* prm, c
   CK(launch_init_features<S>(dv, ee, en, wc, jet, x0, st));
   const int64_t rows = wc * N * Rp;
   const int F = (int)((M + 2) * K);
-  CK(launch_gemm(gk, dense(x0, F, prm + O.initW[0], D, prm + O.initb[0], f, D, rows, F, (int)D, Rp, s.T, 1, vm), st));
+  CK(gemm(s, gk, dense(x0, F, prm + O.initW[0], D, prm + O.initb[0], f, D, rows, F, (int)D, Rp, s.T, 1, vm), st));
   for (int l = 1; l < P.ans.init_layers; ++l) {
-    CK(launch_gemm(gk, dense(f, D, prm + O.initW[l], D, prm + O.initb[l], h, D, rows, (int)D, (int)D, Rp, s.T, 1, vm),
+    CK(gemm(s, gk, dense(f, D, prm + O.initW[l], D, prm + O.initb[l], h, D, rows, (int)D, (int)D, Rp, s.T, 1, vm),
                    st));
     S* tmp = f;
     f = h;
@@ -149,12 +156,12 @@ static qmc_status forward_chunk(const Plan& P, const SysPlan& s, const S* prm, c
     for (int t = 0; t < 3; ++t) {
       const int64_t re = wc * s.P[t] * Re;
       if (re == 0) continue;
-      CK(launch_gemm(gk, dense(rho[t], K, prm + Ly.U1[t], D, prm + Ly.a1[t], ehid[t], D, re, (int)K, (int)D, Re, 1, 1, vm),
+      CK(gemm(s, gk, dense(rho[t], K, prm + Ly.U1[t], D, prm + Ly.a1[t], ehid[t], D, re, (int)K, (int)D, Re, 1, 1, vm),
                      st));
-      CK(launch_gemm(gk, dense(ehid[t], D, prm + Ly.U2[t], D, prm + Ly.a2[t], wj[t], D, re, (int)D, (int)D, Re, 1, 0, vm),
+      CK(gemm(s, gk, dense(ehid[t], D, prm + Ly.U2[t], D, prm + Ly.a2[t], wj[t], D, re, (int)D, (int)D, Re, 1, 0, vm),
                      st));
     }
-    CK(launch_gemm(gk, dense(f, D, prm + Ly.Wh, D, prm + Ly.bh, h, D, rows, (int)D, (int)D, Rp, s.T, 0, vm), st));
+    CK(gemm(s, gk, dense(f, D, prm + Ly.Wh, D, prm + Ly.bh, h, D, rows, (int)D, (int)D, Rp, s.T, 0, vm), st));
     CK(launch_aggregate<S>(dv, h, wj[0], wj[1], wj[2], prm + Ly.Y, ee, en, wc, jet, m, st));
     if (jet) {
       // electron messages [W][N][Rp][2D]; the nuclear message has 5 nonzero jet rows per electron:
@@ -162,17 +169,17 @@ static qmc_status forward_chunk(const Plan& P, const SysPlan& s, const S* prm, c
       S* mn5 = (S*)(ws + L.mn5);
       S* zn5 = (S*)(ws + L.zn5);
       CK(launch_nuc_message<S>(dv, wj[2], prm + Ly.Y, en, wc, mn5, st));
-      CK(launch_gemm(gk, dense(mn5, D, prm + Ly.Wg + 2 * D * D, D, nullptr, zn5, D, wc * N * 5, (int)D, (int)D, 1, 0, 0,
+      CK(gemm(s, gk, dense(mn5, D, prm + Ly.Wg + 2 * D * D, D, nullptr, zn5, D, wc * N * 5, (int)D, (int)D, 1, 0, 0,
                                1), st));
       GemmArgs g = dense(m, 2 * D, prm + Ly.Wg, D, prm + Ly.bg, f, D, rows, (int)(2 * D), (int)D, Rp, s.T, 1, vm);
       g.Res = f;
       g.add5 = zn5;
       g.nel = (int)N;
-      CK(launch_gemm(gk, g, st));
+      CK(gemm(s, gk, g, st));
     } else {
       GemmArgs g = dense(m, 3 * D, prm + Ly.Wg, D, prm + Ly.bg, f, D, rows, (int)(3 * D), (int)D, Rp, s.T, 1, vm);
       g.Res = f;
-      CK(launch_gemm(gk, g, st));
+      CK(gemm(s, gk, g, st));
     }
   }
   int64_t off_e = 0;
@@ -183,7 +190,7 @@ static qmc_status forward_chunk(const Plan& P, const SysPlan& s, const S* prm, c
                        ND * n, wc * n * Rp, (int)D, (int)(ND * n), Rp, s.T, 0, vm);
     a.xrpw = n * Rp;
     a.xws = N * Rp * D;
-    CK(launch_gemm(ok, a, st));
+    CK(gemm(s, ok, a, st));
     CK(launch_envelope<S>(dv, sp, (S*)(ws + L.phi[sp]), prm + O.pi[sp], prm + O.sigma[sp], en, wc, jet, ajet, st));
     off_e += n;
   }
@@ -208,11 +215,38 @@ static int64_t pos_offset(const Plan& P, const SysPlan& s) {
   return pos;
 }
 
+// Runs f(si, stream, workspace) for every system: in order on the caller's stream, or, for a plan
+// with concurrent systems, each on the plan's stream of that system (with its own workspace
+// region) between a fork event recorded on the caller's stream and a join event it waits for.
+template <class F>
+static qmc_status for_systems(const Plan& P, int op, char* ws, hipStream_t st, F f) {
+  if (!P.concurrent()) {
+    for (size_t si = 0; si < P.sys.size(); ++si) {
+      const qmc_status e = f(si, st, ws);
+      if (e != QMC_OK) return e;
+    }
+    return QMC_OK;
+  }
+  CK(hipEventRecord((hipEvent_t)P.fork, st));
+  qmc_status err = QMC_OK;
+  for (size_t si = 0; si < P.sys.size(); ++si) {
+    hipStream_t ss = (hipStream_t)P.streams[si];
+    if (err == QMC_OK && hipStreamWaitEvent(ss, (hipEvent_t)P.fork, 0) != hipSuccess) err = QMC_ERR_HIP;
+    if (err == QMC_OK) err = f(si, ss, ws + sys_ws_offset(P, op, si));
+    // every side stream joins back, also after an error, so that a stream capture stays well formed
+    if (hipEventRecord((hipEvent_t)P.joins[si], ss) != hipSuccess ||
+        hipStreamWaitEvent(st, (hipEvent_t)P.joins[si], 0) != hipSuccess)
+      err = QMC_ERR_HIP;
+  }
+  return err;
+}
+
 template <typename S>
 static qmc_status run_forward(const Plan& P, const void* params, const double* r, const Outs& o, int jet, char* ws,
                               hipStream_t st) {
   const int op = jet ? QMC_OP_LOCAL_ENERGY : QMC_OP_LOGPSI;
-  for (const auto& s : P.sys) {
+  return for_systems(P, op, ws, st, [&](size_t si, hipStream_t ss, char* wsb) -> qmc_status {
+    const SysPlan& s = P.sys[si];
     const S* prm = (const S*)params + s.param_offset;
     for (int64_t w0 = 0; w0 < s.W; w0 += s.Wc) {
       const int64_t wc = std::min<int64_t>(s.Wc, s.W - w0);
@@ -225,36 +259,37 @@ static qmc_status run_forward(const Plan& P, const void* params, const double* r
       oc.lap = o.lap ? o.lap + wg : nullptr;
       oc.eloc = o.eloc ? o.eloc + wg : nullptr;
       const double* rc = r + pos_offset(P, s) + w0 * s.N * 3;
-      const qmc_status e = forward_chunk<S>(P, s, prm, rc, wc, jet, L, ws, oc, st);
+      const qmc_status e = forward_chunk<S>(P, s, prm, rc, wc, jet, L, wsb, oc, ss);
       if (e != QMC_OK) return e;
     }
-  }
-  return QMC_OK;
+    return QMC_OK;
+  });
 }
 
 template <typename S>
 static qmc_status run_metropolis(const Plan& P, const void* params, double* r, double* logpsi, const double* noise,
                                  const double* u, double step, uint8_t* accepted, char* ws, hipStream_t st) {
-  for (const auto& s : P.sys) {
+  return for_systems(P, QMC_OP_METROPOLIS, ws, st, [&](size_t si, hipStream_t ss, char* wsb) -> qmc_status {
+    const SysPlan& s = P.sys[si];
     const S* prm = (const S*)params + s.param_offset;
     const int64_t pos = pos_offset(P, s);
     for (int64_t w0 = 0; w0 < s.W; w0 += s.Wc) {
       const int64_t wc = std::min<int64_t>(s.Wc, s.W - w0);
       const int64_t wg = s.walker_offset + w0;
       const Workspace L = workspace_layout(P, s, QMC_OP_METROPOLIS, wc);
-      double* rp = (double*)(ws + L.lp_prop);
+      double* rp = (double*)(wsb + L.lp_prop);
       double* lpp = rp + wc * s.N * 3;
       const int64_t off = pos + w0 * s.N * 3;
-      CK(launch_propose(r + off, noise + off, step, wc * s.N * 3, rp, st));
+      CK(launch_propose(r + off, noise + off, step, wc * s.N * 3, rp, ss));
       Outs oc;
       std::memset(&oc, 0, sizeof(oc));
       oc.logpsi = lpp;
-      const qmc_status e = forward_chunk<S>(P, s, prm, rp, wc, 0, L, ws, oc, st);
+      const qmc_status e = forward_chunk<S>(P, s, prm, rp, wc, 0, L, wsb, oc, ss);
       if (e != QMC_OK) return e;
-      CK(launch_accept(wc, s.N * 3, rp, lpp, u + wg, r + off, logpsi + wg, accepted ? accepted + wg : nullptr, st));
+      CK(launch_accept(wc, s.N * 3, rp, lpp, u + wg, r + off, logpsi + wg, accepted ? accepted + wg : nullptr, ss));
     }
-  }
-  return QMC_OK;
+    return QMC_OK;
+  });
 }
 
 
@@ -301,10 +336,10 @@ static qmc_status forward_stash(const Plan& P, const SysPlan& s, const S* prm, c
   CK(launch_init_features<S>(dv, ee, en, wc, 0, x0, st));
   const int64_t rows = wc * N;
   const int Fd = (int)((M + 2) * K);
-  CK(launch_gemm(gk, dense(x0, Fd, prm + O.initW[0], D, prm + O.initb[0], F_(B.finit, B.blk_f, 0), D, rows, Fd,
+  CK(gemm(s, gk, dense(x0, Fd, prm + O.initW[0], D, prm + O.initb[0], F_(B.finit, B.blk_f, 0), D, rows, Fd,
                            (int)D, 1, 0, 1, 1), st));
   for (int l = 1; l < L0; ++l)
-    CK(launch_gemm(gk, dense(F_(B.finit, B.blk_f, l - 1), D, prm + O.initW[l], D, prm + O.initb[l],
+    CK(gemm(s, gk, dense(F_(B.finit, B.blk_f, l - 1), D, prm + O.initW[l], D, prm + O.initb[l],
                              F_(B.finit, B.blk_f, l), D, rows, (int)D, (int)D, 1, 0, 1, 1), st));
   S* fprev = F_(B.finit, B.blk_f, L0 - 1);
   for (int l = 0; l < L; ++l) {
@@ -314,18 +349,18 @@ static qmc_status forward_stash(const Plan& P, const SysPlan& s, const S* prm, c
       if (re == 0) continue;
       S* eh = F_(B.ehid[t], B.blk_e[t], l);
       S* wv = F_(B.wv[t], B.blk_e[t], l);
-      CK(launch_gemm(gk, dense((S*)(ws + B.rho[t]), K, prm + Ly.U1[t], D, prm + Ly.a1[t], eh, D, re, (int)K, (int)D, 1,
+      CK(gemm(s, gk, dense((S*)(ws + B.rho[t]), K, prm + Ly.U1[t], D, prm + Ly.a1[t], eh, D, re, (int)K, (int)D, 1,
                                0, 1, 1), st));
-      CK(launch_gemm(gk, dense(eh, D, prm + Ly.U2[t], D, prm + Ly.a2[t], wv, D, re, (int)D, (int)D, 1, 0, 0, 1), st));
+      CK(gemm(s, gk, dense(eh, D, prm + Ly.U2[t], D, prm + Ly.a2[t], wv, D, re, (int)D, (int)D, 1, 0, 0, 1), st));
     }
     S* h = F_(B.hst, B.blk_f, l);
     S* m = F_(B.mst, B.blk_m, l);
     S* t = F_(B.tst, B.blk_f, l);
     S* fo = F_(B.fst, B.blk_f, l);
-    CK(launch_gemm(gk, dense(fprev, D, prm + Ly.Wh, D, prm + Ly.bh, h, D, rows, (int)D, (int)D, 1, 0, 0, 1), st));
+    CK(gemm(s, gk, dense(fprev, D, prm + Ly.Wh, D, prm + Ly.bh, h, D, rows, (int)D, (int)D, 1, 0, 0, 1), st));
     CK(launch_aggregate<S>(dv, h, F_(B.wv[0], B.blk_e[0], l), F_(B.wv[1], B.blk_e[1], l), F_(B.wv[2], B.blk_e[2], l),
                            prm + Ly.Y, ee, en, wc, 0, m, st));
-    CK(launch_gemm(gk, dense(m, 3 * D, prm + Ly.Wg, D, prm + Ly.bg, t, D, rows, (int)(3 * D), (int)D, 1, 0, 1, 1), st));
+    CK(gemm(s, gk, dense(m, 3 * D, prm + Ly.Wg, D, prm + Ly.bg, t, D, rows, (int)(3 * D), (int)D, 1, 0, 1, 1), st));
     CK(launch_add<S>(rows * D, fprev, t, fo, st));
     fprev = fo;
   }
@@ -337,7 +372,7 @@ static qmc_status forward_stash(const Plan& P, const SysPlan& s, const S* prm, c
                        wc * n, (int)D, (int)(ND * n), 1, 0, 0, 1);
     a.xrpw = n;
     a.xws = N * D;
-    CK(launch_gemm(ok, a, st));
+    CK(gemm(s, ok, a, st));
     CK(launch_envelope<S>(dv, sp, (S*)(ws + B.phi[sp]), prm + O.pi[sp], prm + O.sigma[sp], en, wc, 0,
                           (S*)(ws + B.aval), st));
     off_e += n;
@@ -391,7 +426,7 @@ static qmc_status backward_chunk(const Plan& P, const SysPlan& s, const S* prm, 
     g.transw = 1;
     g.yrpw = n;
     g.yws = N * D;
-    CK(launch_gemm(bk, g, st));
+    CK(gemm(s, bk, g, st));
     off_e += n;
   }
   S* zbar = (S*)(ws + B.zbar);
@@ -406,7 +441,7 @@ static qmc_status backward_chunk(const Plan& P, const SysPlan& s, const S* prm, 
                     gacc + Ly.bg, st));
     GemmArgs gm = dense(zbar, D, prm + Ly.Wg, D, nullptr, mbar, 3 * D, rows, (int)D, (int)(3 * D), 1, 0, 0, 1);
     gm.transw = 1;
-    CK(launch_gemm(bk, gm, st));
+    CK(gemm(s, bk, gm, st));
     S* wb[3] = {(S*)(ws + B.wbar[0]), (S*)(ws + B.wbar[1]), (S*)(ws + B.wbar[2])};
     double* yp = (double*)(ws + B.ypart);
     CK(launch_agg_bwd<S>(dv, mbar, F_(B.hst, B.blk_f, l), F_(B.wv[0], B.blk_e[0], l), F_(B.wv[1], B.blk_e[1], l),
@@ -416,7 +451,7 @@ static qmc_status backward_chunk(const Plan& P, const SysPlan& s, const S* prm, 
     GemmArgs gh = dense(hbar, D, prm + Ly.Wh, D, nullptr, fbar2, D, rows, (int)D, (int)D, 1, 0, 0, 1);
     gh.transw = 1;
     gh.Res = fbar;
-    CK(launch_gemm(bk, gh, st));
+    CK(gemm(s, bk, gh, st));
     std::swap(fbar, fbar2);
     for (int t = 0; t < 3; ++t) {
       const int64_t re = wc * s.P[t];
@@ -426,7 +461,7 @@ static qmc_status backward_chunk(const Plan& P, const SysPlan& s, const S* prm, 
       GemmArgs ge = dense(wb[t], D, prm + Ly.U2[t], D, nullptr, ebar, D, re, (int)D, (int)D, 1, 0, 2, 1);
       ge.transw = 1;
       ge.aux = eh;
-      CK(launch_gemm(bk, ge, st));
+      CK(gemm(s, bk, ge, st));
       CK(launch_wgrad(bk, wg((S*)(ws + B.rho[t]), K, ebar, D, re, (int)K, (int)D, B, ws), gacc + Ly.U1[t], D,
                       gacc + Ly.a1[t], st));
     }
@@ -443,7 +478,7 @@ static qmc_status backward_chunk(const Plan& P, const SysPlan& s, const S* prm, 
                       D, gacc + O.initb[l], st));
       GemmArgs gi = dense(zbar, D, prm + O.initW[l], D, nullptr, fbar2, D, rows, (int)D, (int)D, 1, 0, 0, 1);
       gi.transw = 1;
-      CK(launch_gemm(bk, gi, st));
+      CK(gemm(s, bk, gi, st));
       std::swap(fbar, fbar2);
     }
   }
@@ -454,34 +489,141 @@ static qmc_status backward_chunk(const Plan& P, const SysPlan& s, const S* prm, 
 template <typename S>
 static qmc_status run_backward(const Plan& P, const void* params, const double* r, const double* cot,
                                const double* e_loc, void* grad, double* e_mean, char* ws, hipStream_t st) {
-  for (size_t si = 0; si < P.sys.size(); ++si) {
+  const int op = cot ? QMC_OP_LOGPSI_VJP : QMC_OP_LOSS_GRAD;
+  return for_systems(P, op, ws, st, [&](size_t si, hipStream_t ss, char* wsb) -> qmc_status {
     const SysPlan& s = P.sys[si];
     const S* prm = (const S*)params + s.param_offset;
     const BwdWorkspace B0 = bwd_layout(P, s, s.Wc);
-    double* gacc = (double*)(ws + B0.gacc);
-    CK(launch_fill(s.off.total, 0.0, gacc, st));
+    double* gacc = (double*)(wsb + B0.gacc);
+    CK(launch_fill(s.off.total, 0.0, gacc, ss));
     const double* gall;
     if (cot) {
       gall = cot + s.walker_offset;
     } else {
-      double* gb = (double*)(ws + B0.gbar);
-      CK(launch_loss_weights(e_loc + s.walker_offset, s.W, (double*)(ws + B0.stats), gb, e_mean ? e_mean + si : nullptr,
-                             st));
+      double* gb = (double*)(wsb + B0.gbar);
+      CK(launch_loss_weights(e_loc + s.walker_offset, s.W, (double*)(wsb + B0.stats), gb,
+                             e_mean ? e_mean + si : nullptr, ss));
       gall = gb;
     }
     for (int64_t w0 = 0; w0 < s.W; w0 += s.Wc) {
       const int64_t wc = std::min<int64_t>(s.Wc, s.W - w0);
       // the layout depends only on the chunk size through sizes; keep the full-chunk offsets so
       // that gacc / gbar / stats stay at fixed places
-      const qmc_status e1 = forward_stash<S>(P, s, prm, r + pos_offset(P, s) + w0 * s.N * 3, wc, B0, ws, st);
+      const qmc_status e1 = forward_stash<S>(P, s, prm, r + pos_offset(P, s) + w0 * s.N * 3, wc, B0, wsb, ss);
       if (e1 != QMC_OK) return e1;
-      const qmc_status e2 = backward_chunk<S>(P, s, prm, gall + w0, wc, B0, ws, st);
+      const qmc_status e2 = backward_chunk<S>(P, s, prm, gall + w0, wc, B0, wsb, ss);
       if (e2 != QMC_OK) return e2;
     }
-    CK(launch_cast<S>(s.off.total, gacc, (S*)grad + s.param_offset, st));
+    CK(launch_cast<S>(s.off.total, gacc, (S*)grad + s.param_offset, ss));
+    return QMC_OK;
+  });
+}
+
+// ---------------------------------------------------------------- plan device set-up
+
+// Mean time of 3 launches after one warm-up launch (ms), or a negative value if the launch fails.
+static float time_gemm(GemmKind kind, const GemmArgs& a, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+  if (launch_gemm(kind, a, st) != hipSuccess) return -1.f;
+  if (hipEventRecord(e0, st) != hipSuccess) return -1.f;
+  for (int i = 0; i < 3; ++i)
+    if (launch_gemm(kind, a, st) != hipSuccess) return -1.f;
+  float ms = 0.f;
+  if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+      hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+    return -1.f;
+  return ms / 3.f;
+}
+
+// Times the tile candidates of every system's four GEMM classes on representative shapes (at most
+// 2^20 rows each, zero operands) and keeps the fastest in SysPlan::tile.
+static qmc_status autotune(Plan& P) {
+  const GemmKind gk = embed_kind(P.prec);
+  const size_t E = act_bytes(P.prec);
+  const int64_t D = P.ans.width, cap = int64_t(1) << 20;
+  const size_t xb = size_t(cap) * 2 * D * E, wb = size_t(2 * D) * D * E, yb = size_t(cap) * D * E;
+  void *X = nullptr, *Wm = nullptr, *B = nullptr, *Y = nullptr;
+  hipStream_t st = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  qmc_status err = QMC_OK;
+  if (hipMalloc(&X, xb) != hipSuccess || hipMalloc(&Wm, wb) != hipSuccess || hipMalloc(&B, D * E) != hipSuccess ||
+      hipMalloc(&Y, yb) != hipSuccess || hipMemset(X, 0, xb) != hipSuccess || hipMemset(Wm, 0, wb) != hipSuccess ||
+      hipMemset(B, 0, D * E) != hipSuccess || hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    err = QMC_ERR_HIP;
+  const bool f32 = P.prec == QMC_FP32;
+  // K-step (bit 0) and persistent grids (bit 2) are float32 options
+  const std::vector<int> jet_bits = f32 ? std::vector<int>{0, 1, 4, 5} : std::vector<int>{0};
+  const std::vector<int> row_bits = f32 ? std::vector<int>{0, 1, 2, 3, 4, 6} : std::vector<int>{0, 2};
+  for (auto& s : P.sys) {
+    if (err != QMC_OK) break;
+    const int64_t pmax = std::max<int64_t>(1, std::max(s.P[0], std::max(s.P[1], s.P[2])));
+    for (int cls = 0; cls < 4 && err == QMC_OK; ++cls) {
+      GemmArgs a = dense(X, D, Wm, D, B, Y, D, 1, (int)D, (int)D, 1, 0, 0, 1);
+      if (cls == TILE_JET) {
+        a = dense(X, 2 * D, Wm, D, B, Y, D, std::min(cap, s.Wc * s.N * s.Rp) / s.Rp * s.Rp, (int)(2 * D), (int)D,
+                  s.Rp, s.T, 1, 0);
+      } else if (cls == TILE_EDGE) {
+        a = dense(X, D, Wm, D, B, Y, D, std::min(cap, s.Wc * pmax * 4) / 4 * 4, (int)D, (int)D, 4, 1, 1, 0);
+      } else {
+        a = dense(X, D, Wm, D, B, Y, D, std::min(cap, s.Wc * pmax), (int)D, (int)D, 1, 0, 0, 1);
+        a.transw = cls == TILE_BWD;
+      }
+      if (a.rows <= 0) continue;
+      float best = 1e30f;
+      int pick = 0;
+      for (int bits : (cls == TILE_JET ? jet_bits : row_bits)) {
+        a.tile = bits + 1;
+        const float t = time_gemm(gk, a, st, e0, e1);
+        if (t < 0.f) {
+          err = QMC_ERR_HIP;
+          break;
+        }
+        if (t < best) {
+          best = t;
+          pick = bits + 1;
+        }
+      }
+      s.tile[cls] = pick;
+    }
   }
+  if (st) (void)hipStreamSynchronize(st);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (st) (void)hipStreamDestroy(st);
+  if (X) (void)hipFree(X);
+  if (Wm) (void)hipFree(Wm);
+  if (B) (void)hipFree(B);
+  if (Y) (void)hipFree(Y);
+  return err;
+}
+
+qmc_status plan_device_init(Plan& P) {
+  if (P.concurrent()) {
+    hipEvent_t f = nullptr;
+    if (hipEventCreateWithFlags(&f, hipEventDisableTiming) != hipSuccess) return QMC_ERR_HIP;
+    P.fork = f;
+    for (size_t si = 0; si < P.sys.size(); ++si) {
+      hipStream_t s = nullptr;
+      hipEvent_t j = nullptr;
+      if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return QMC_ERR_HIP;
+      P.streams.push_back(s);
+      if (hipEventCreateWithFlags(&j, hipEventDisableTiming) != hipSuccess) return QMC_ERR_HIP;
+      P.joins.push_back(j);
+    }
+  }
+  if (P.flags & QMC_PLAN_AUTOTUNE) return autotune(P);
   return QMC_OK;
 }
+
+void plan_device_release(Plan& P) {
+  for (void* s : P.streams) (void)hipStreamDestroy((hipStream_t)s);
+  for (void* e : P.joins) (void)hipEventDestroy((hipEvent_t)e);
+  if (P.fork) (void)hipEventDestroy((hipEvent_t)P.fork);
+  P.streams.clear();
+  P.joins.clear();
+  P.fork = nullptr;
+}
+
 }  // namespace qmc
 
 using namespace qmc;

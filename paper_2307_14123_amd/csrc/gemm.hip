@@ -36,6 +36,7 @@
 // hardware orders k inside a lane.
 #include <cstdio>
 #include <cstdlib>
+#include <algorithm>
 #include <cstring>
 #include <type_traits>
 
@@ -78,7 +79,7 @@ __device__ inline float dtanh(float x) { return tanhf(x); }
 constexpr int cmax(int a, int b) { return a > b ? a : b; }
 
 // EPI: 0 value rows, 1 univariate edge jets (groups of 4 rows), 2 electron jets (groups of Rp = 16*bpg rows)
-template <int KIND, int MB, int EPI, int BKT>
+template <int KIND, int MB, int EPI, int BKT, bool PERSIST>
 __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs a) {
   using G = GT<KIND>;
   using S = typename G::S;
@@ -112,369 +113,381 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs a) {
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
-  const int64_t m0 = (int64_t)blockIdx.x * BM;
-  const int n0 = blockIdx.y * BN;
-  const S* __restrict__ X = (const S*)a.X;
-  const S* __restrict__ Wt = (const S*)a.W;
-  const bool kfull = (a.K % BK) == 0;
-  const bool avec = (a.ldx % 4 == 0) && ((a.xws % 4) == 0) &&
-                    ((reinterpret_cast<uintptr_t>(X) % (4 * sizeof(S))) == 0);
-  const bool bvec = (a.ldw % 4 == 0) && (reinterpret_cast<uintptr_t>(Wt) % (4 * sizeof(S)) == 0);
-  // Fast path: every operand load is an unconditional 16-byte load.  Rows past the end and
-  // columns past Ncols are clamped to the last valid ones; their products land only in outputs
-  // that the epilogue does not store (rows are checked per row, jet groups are whole).
-  const bool fast = kfull && avec && bvec && (a.Ncols % 4 == 0) && (a.K % 4 == 0);
+  // one row tile; a persistent launch walks the row tiles with a grid stride
+  auto row_tile = [&](int64_t bx) {
+    const int64_t m0 = bx * BM;
+    const int n0 = blockIdx.y * BN;
+    const S* __restrict__ X = (const S*)a.X;
+    const S* __restrict__ Wt = (const S*)a.W;
+    const bool kfull = (a.K % BK) == 0;
+    const bool avec = (a.ldx % 4 == 0) && ((a.xws % 4) == 0) &&
+                      ((reinterpret_cast<uintptr_t>(X) % (4 * sizeof(S))) == 0);
+    const bool bvec = (a.ldw % 4 == 0) && (reinterpret_cast<uintptr_t>(Wt) % (4 * sizeof(S)) == 0);
+    // Fast path: every operand load is an unconditional 16-byte load.  Rows past the end and
+    // columns past Ncols are clamped to the last valid ones; their products land only in outputs
+    // that the epilogue does not store (rows are checked per row, jet groups are whole).
+    const bool fast = kfull && avec && bvec && (a.Ncols % 4 == 0) && (a.K % 4 == 0);
 
-  // fixed row pointers of this thread's A slots
-  const S* arow[NA];
-  bool aval[NA];
-  int arr[NA], akk[NA];
-#pragma unroll
-  for (int u = 0; u < NA; ++u) {
-    const int v = tid + 256 * u;
-    arr[u] = v / AKV;
-    akk[u] = (v % AKV) * 4;
-    const int64_t r = m0 + arr[u];
-    aval[u] = (v < AV) && (r < a.rows);
-    const uint32_t rr = (uint32_t)(r < a.rows ? r : a.rows - 1), rpw = (uint32_t)a.xrpw;
-    const uint32_t qb = rr / rpw;
-    arow[u] = X + (int64_t)qb * a.xws + (int64_t)(rr - qb * rpw) * a.ldx;
-  }
-  S ra[NA][4], rb[NB][4];
-
-  // B slot v: float32/float64 with W row-major (k, n): 4 consecutive columns of row k;
-  // transposed W and bf16: 4 consecutive k of column n
-  int bkk[NB], bnn[NB];
-  {
-    const bool tr = BF || a.transw;
-#pragma unroll
-    for (int u = 0; u < NB; ++u) {
-      const int v = tid + 256 * u;
-      bkk[u] = tr ? (v / BN) * 4 : v / (BN / 4);
-      bnn[u] = tr ? v % BN : (v % (BN / 4)) * 4;
-    }
-  }
-
-  // MODE 0: bounds-checked loads; 1: fast, W row-major; 2: fast, W transposed
-  auto load_tiles = [&](int k0, auto mode_tag) {
-    constexpr int MODE = decltype(mode_tag)::value;
-#pragma unroll
+    // fixed row pointers of this thread's A slots
+    const S* arow[NA];
+    bool aval[NA];
+    int arr[NA], akk[NA];
+  #pragma unroll
     for (int u = 0; u < NA; ++u) {
-      if (tid + 256 * u >= AV) continue;
-      const int k = k0 + akk[u];
-      if (MODE != 0 || (aval[u] && avec && k + 3 < a.K)) {
-        const Vec t = *(const Vec*)(arow[u] + k);
-        ra[u][0] = t.x;
-        ra[u][1] = t.y;
-        ra[u][2] = t.z;
-        ra[u][3] = t.w;
-      } else {
-#pragma unroll
-        for (int e = 0; e < 4; ++e) ra[u][e] = (aval[u] && k + e < a.K) ? arow[u][k + e] : S(0);
+      const int v = tid + 256 * u;
+      arr[u] = v / AKV;
+      akk[u] = (v % AKV) * 4;
+      const int64_t r = m0 + arr[u];
+      aval[u] = (v < AV) && (r < a.rows);
+      const uint32_t rr = (uint32_t)(r < a.rows ? r : a.rows - 1), rpw = (uint32_t)a.xrpw;
+      const uint32_t qb = rr / rpw;
+      arow[u] = X + (int64_t)qb * a.xws + (int64_t)(rr - qb * rpw) * a.ldx;
+    }
+    S ra[NA][4], rb[NB][4];
+
+    // B slot v: float32/float64 with W row-major (k, n): 4 consecutive columns of row k;
+    // transposed W and bf16: 4 consecutive k of column n
+    int bkk[NB], bnn[NB];
+    {
+      const bool tr = BF || a.transw;
+  #pragma unroll
+      for (int u = 0; u < NB; ++u) {
+        const int v = tid + 256 * u;
+        bkk[u] = tr ? (v / BN) * 4 : v / (BN / 4);
+        bnn[u] = tr ? v % BN : (v % (BN / 4)) * 4;
       }
     }
-#pragma unroll
-    for (int u = 0; u < NB; ++u) {
-      const int v = tid + 256 * u;
-      if (v >= BV) continue;
-      const int kg = k0 + bkk[u];
-      int ng = n0 + bnn[u];
-      if (MODE == 1 || (MODE == 0 && !a.transw)) {
-        if constexpr (!BF) {
-          // 4 consecutive columns of W row kg
-          if (MODE == 1) ng = ng < a.Ncols ? ng : a.Ncols - 4;
-          const S* src = Wt + (int64_t)kg * a.ldw + ng;
-          if (MODE == 1 || (bvec && kg < a.K && ng + 3 < a.Ncols)) {
+
+    // MODE 0: bounds-checked loads; 1: fast, W row-major; 2: fast, W transposed
+    auto load_tiles = [&](int k0, auto mode_tag) {
+      constexpr int MODE = decltype(mode_tag)::value;
+  #pragma unroll
+      for (int u = 0; u < NA; ++u) {
+        if (tid + 256 * u >= AV) continue;
+        const int k = k0 + akk[u];
+        if (MODE != 0 || (aval[u] && avec && k + 3 < a.K)) {
+          const Vec t = *(const Vec*)(arow[u] + k);
+          ra[u][0] = t.x;
+          ra[u][1] = t.y;
+          ra[u][2] = t.z;
+          ra[u][3] = t.w;
+        } else {
+  #pragma unroll
+          for (int e = 0; e < 4; ++e) ra[u][e] = (aval[u] && k + e < a.K) ? arow[u][k + e] : S(0);
+        }
+      }
+  #pragma unroll
+      for (int u = 0; u < NB; ++u) {
+        const int v = tid + 256 * u;
+        if (v >= BV) continue;
+        const int kg = k0 + bkk[u];
+        int ng = n0 + bnn[u];
+        if (MODE == 1 || (MODE == 0 && !a.transw)) {
+          if constexpr (!BF) {
+            // 4 consecutive columns of W row kg
+            if (MODE == 1) ng = ng < a.Ncols ? ng : a.Ncols - 4;
+            const S* src = Wt + (int64_t)kg * a.ldw + ng;
+            if (MODE == 1 || (bvec && kg < a.K && ng + 3 < a.Ncols)) {
+              const Vec t = *(const Vec*)src;
+              rb[u][0] = t.x;
+              rb[u][1] = t.y;
+              rb[u][2] = t.z;
+              rb[u][3] = t.w;
+            } else {
+  #pragma unroll
+              for (int e = 0; e < 4; ++e) rb[u][e] = (kg < a.K && ng + e < a.Ncols) ? src[e] : S(0);
+            }
+          } else {
+            // 4 consecutive k of column ng (strided by ldw)
+            if (MODE == 1) ng = ng < a.Ncols ? ng : a.Ncols - 1;
+            const S* src = Wt + (int64_t)kg * a.ldw + ng;
+  #pragma unroll
+            for (int e = 0; e < 4; ++e)
+              rb[u][e] = (MODE == 1 || (ng < a.Ncols && kg + e < a.K)) ? src[(int64_t)e * a.ldw] : S(0);
+          }
+        } else {
+          // 4 consecutive k of W^T column ng
+          if (MODE == 2) ng = ng < a.Ncols ? ng : a.Ncols - 1;
+          const S* src = Wt + (int64_t)ng * a.ldw + kg;
+          if (MODE == 2 || (bvec && ng < a.Ncols && kg + 3 < a.K)) {
             const Vec t = *(const Vec*)src;
             rb[u][0] = t.x;
             rb[u][1] = t.y;
             rb[u][2] = t.z;
             rb[u][3] = t.w;
           } else {
-#pragma unroll
-            for (int e = 0; e < 4; ++e) rb[u][e] = (kg < a.K && ng + e < a.Ncols) ? src[e] : S(0);
+  #pragma unroll
+            for (int e = 0; e < 4; ++e) rb[u][e] = (ng < a.Ncols && kg + e < a.K) ? src[e] : S(0);
+          }
+        }
+      }
+    };
+    auto store_tiles = [&](int buf) {
+  #pragma unroll
+      for (int u = 0; u < NA; ++u) {
+        if (tid + 256 * u >= AV) continue;
+        L* dst = &As[buf * ASZ + arr[u] * ALD + akk[u]];
+        if constexpr (BF) {
+  #pragma unroll
+          for (int e = 0; e < 4; ++e) dst[e] = (L)ra[u][e];
+        } else {
+          *(Vec*)dst = Vec{ra[u][0], ra[u][1], ra[u][2], ra[u][3]};
+        }
+      }
+  #pragma unroll
+      for (int u = 0; u < NB; ++u) {
+        const int v = tid + 256 * u;
+        if (v >= BV) continue;
+        const int kk = bkk[u], nn = bnn[u];
+        if constexpr (BF) {
+          L* dst = &Bs[buf * BSZ + nn * BLD + kk];
+  #pragma unroll
+          for (int e = 0; e < 4; ++e) dst[e] = (L)rb[u][e];
+        } else {
+          if (!a.transw) {
+            *(Vec*)&Bs[buf * BSZ + kk * BLD + nn] = Vec{rb[u][0], rb[u][1], rb[u][2], rb[u][3]};
+          } else {
+  #pragma unroll
+            for (int e = 0; e < 4; ++e) Bs[buf * BSZ + (kk + e) * BLD + nn] = rb[u][e];
+          }
+        }
+      }
+    };
+
+    Acc acc[MB][2];
+  #pragma unroll
+    for (int i = 0; i < MB; ++i)
+  #pragma unroll
+      for (int j = 0; j < 2; ++j)
+  #pragma unroll
+        for (int e = 0; e < 4; ++e) acc[i][j][e] = 0;
+
+    const int g = lane >> 4, c = lane & 15;
+    const int nk = (a.K + BK - 1) / BK;
+
+    auto mainloop = [&](auto mode_tag) {
+      load_tiles(0, mode_tag);
+      store_tiles(0);
+      __syncthreads();
+      for (int kt = 0; kt < nk; ++kt) {
+        const int cur = kt & 1;
+        if (kt + 1 < nk) load_tiles((kt + 1) * BK, mode_tag);
+        const L* Ac = As + cur * ASZ;
+        const L* Bc = Bs + cur * BSZ;
+        if constexpr (BF) {
+          bf16x8 bv[2];
+  #pragma unroll
+          for (int nb = 0; nb < 2; ++nb) bv[nb] = *(const bf16x8*)&Bc[(wave * 32 + nb * 16 + c) * BLD + 8 * g];
+  #pragma unroll
+          for (int mb = 0; mb < MB; ++mb) {
+            const bf16x8 av = *(const bf16x8*)&Ac[(mb * 16 + c) * ALD + 8 * g];
+  #pragma unroll
+            for (int nb = 0; nb < 2; ++nb)
+              acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv[nb], acc[mb][nb], 0, 0, 0);
           }
         } else {
-          // 4 consecutive k of column ng (strided by ldw)
-          if (MODE == 1) ng = ng < a.Ncols ? ng : a.Ncols - 1;
-          const S* src = Wt + (int64_t)kg * a.ldw + ng;
-#pragma unroll
-          for (int e = 0; e < 4; ++e)
-            rb[u][e] = (MODE == 1 || (ng < a.Ncols && kg + e < a.K)) ? src[(int64_t)e * a.ldw] : S(0);
-        }
-      } else {
-        // 4 consecutive k of W^T column ng
-        if (MODE == 2) ng = ng < a.Ncols ? ng : a.Ncols - 1;
-        const S* src = Wt + (int64_t)ng * a.ldw + kg;
-        if (MODE == 2 || (bvec && ng < a.Ncols && kg + 3 < a.K)) {
-          const Vec t = *(const Vec*)src;
-          rb[u][0] = t.x;
-          rb[u][1] = t.y;
-          rb[u][2] = t.z;
-          rb[u][3] = t.w;
-        } else {
-#pragma unroll
-          for (int e = 0; e < 4; ++e) rb[u][e] = (ng < a.Ncols && kg + e < a.K) ? src[e] : S(0);
-        }
-      }
-    }
-  };
-  auto store_tiles = [&](int buf) {
-#pragma unroll
-    for (int u = 0; u < NA; ++u) {
-      if (tid + 256 * u >= AV) continue;
-      L* dst = &As[buf * ASZ + arr[u] * ALD + akk[u]];
-      if constexpr (BF) {
-#pragma unroll
-        for (int e = 0; e < 4; ++e) dst[e] = (L)ra[u][e];
-      } else {
-        *(Vec*)dst = Vec{ra[u][0], ra[u][1], ra[u][2], ra[u][3]};
-      }
-    }
-#pragma unroll
-    for (int u = 0; u < NB; ++u) {
-      const int v = tid + 256 * u;
-      if (v >= BV) continue;
-      const int kk = bkk[u], nn = bnn[u];
-      if constexpr (BF) {
-        L* dst = &Bs[buf * BSZ + nn * BLD + kk];
-#pragma unroll
-        for (int e = 0; e < 4; ++e) dst[e] = (L)rb[u][e];
-      } else {
-        if (!a.transw) {
-          *(Vec*)&Bs[buf * BSZ + kk * BLD + nn] = Vec{rb[u][0], rb[u][1], rb[u][2], rb[u][3]};
-        } else {
-#pragma unroll
-          for (int e = 0; e < 4; ++e) Bs[buf * BSZ + (kk + e) * BLD + nn] = rb[u][e];
-        }
-      }
-    }
-  };
-
-  Acc acc[MB][2];
-#pragma unroll
-  for (int i = 0; i < MB; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j)
-#pragma unroll
-      for (int e = 0; e < 4; ++e) acc[i][j][e] = 0;
-
-  const int g = lane >> 4, c = lane & 15;
-  const int nk = (a.K + BK - 1) / BK;
-
-  auto mainloop = [&](auto mode_tag) {
-    load_tiles(0, mode_tag);
-    store_tiles(0);
-    __syncthreads();
-    for (int kt = 0; kt < nk; ++kt) {
-      const int cur = kt & 1;
-      if (kt + 1 < nk) load_tiles((kt + 1) * BK, mode_tag);
-      const L* Ac = As + cur * ASZ;
-      const L* Bc = Bs + cur * BSZ;
-      if constexpr (BF) {
-        bf16x8 bv[2];
-#pragma unroll
-        for (int nb = 0; nb < 2; ++nb) bv[nb] = *(const bf16x8*)&Bc[(wave * 32 + nb * 16 + c) * BLD + 8 * g];
-#pragma unroll
-        for (int mb = 0; mb < MB; ++mb) {
-          const bf16x8 av = *(const bf16x8*)&Ac[(mb * 16 + c) * ALD + 8 * g];
-#pragma unroll
-          for (int nb = 0; nb < 2; ++nb)
-            acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv[nb], acc[mb][nb], 0, 0, 0);
-        }
-      } else {
-        // lane group g supplies k = 4g + kq at MFMA step kq (the same order for A and B)
-#pragma unroll
-        for (int k4 = 0; k4 < BK / 16; ++k4) {
-          S bq[2][4];
-#pragma unroll
-          for (int nb = 0; nb < 2; ++nb)
-#pragma unroll
-            for (int kq = 0; kq < 4; ++kq) bq[nb][kq] = Bc[(k4 * 16 + 4 * g + kq) * BLD + wave * 32 + nb * 16 + c];
-#pragma unroll
-          for (int mb = 0; mb < MB; ++mb) {
-            const Vec av = *(const Vec*)&Ac[(mb * 16 + c) * ALD + k4 * 16 + 4 * g];
-#pragma unroll
-            for (int nb = 0; nb < 2; ++nb) {
-              if constexpr (KIND == GK_F64) {
-                acc[mb][nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av.x, bq[nb][0], acc[mb][nb], 0, 0, 0);
-                acc[mb][nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av.y, bq[nb][1], acc[mb][nb], 0, 0, 0);
-                acc[mb][nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av.z, bq[nb][2], acc[mb][nb], 0, 0, 0);
-                acc[mb][nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av.w, bq[nb][3], acc[mb][nb], 0, 0, 0);
-              } else {
-                acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.x, bq[nb][0], acc[mb][nb], 0, 0, 0);
-                acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.y, bq[nb][1], acc[mb][nb], 0, 0, 0);
-                acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.z, bq[nb][2], acc[mb][nb], 0, 0, 0);
-                acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.w, bq[nb][3], acc[mb][nb], 0, 0, 0);
+          // lane group g supplies k = 4g + kq at MFMA step kq (the same order for A and B)
+  #pragma unroll
+          for (int k4 = 0; k4 < BK / 16; ++k4) {
+            S bq[2][4];
+  #pragma unroll
+            for (int nb = 0; nb < 2; ++nb)
+  #pragma unroll
+              for (int kq = 0; kq < 4; ++kq) bq[nb][kq] = Bc[(k4 * 16 + 4 * g + kq) * BLD + wave * 32 + nb * 16 + c];
+  #pragma unroll
+            for (int mb = 0; mb < MB; ++mb) {
+              const Vec av = *(const Vec*)&Ac[(mb * 16 + c) * ALD + k4 * 16 + 4 * g];
+  #pragma unroll
+              for (int nb = 0; nb < 2; ++nb) {
+                if constexpr (KIND == GK_F64) {
+                  acc[mb][nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av.x, bq[nb][0], acc[mb][nb], 0, 0, 0);
+                  acc[mb][nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av.y, bq[nb][1], acc[mb][nb], 0, 0, 0);
+                  acc[mb][nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av.z, bq[nb][2], acc[mb][nb], 0, 0, 0);
+                  acc[mb][nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av.w, bq[nb][3], acc[mb][nb], 0, 0, 0);
+                } else {
+                  acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.x, bq[nb][0], acc[mb][nb], 0, 0, 0);
+                  acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.y, bq[nb][1], acc[mb][nb], 0, 0, 0);
+                  acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.z, bq[nb][2], acc[mb][nb], 0, 0, 0);
+                  acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.w, bq[nb][3], acc[mb][nb], 0, 0, 0);
+                }
               }
             }
           }
         }
+        if (kt + 1 < nk) store_tiles(cur ^ 1);
+        __syncthreads();
       }
-      if (kt + 1 < nk) store_tiles(cur ^ 1);
+    };
+    if (fast && !a.transw)
+      mainloop(std::integral_constant<int, 1>{});
+    else if (fast)
+      mainloop(std::integral_constant<int, 2>{});
+    else
+      mainloop(std::integral_constant<int, 0>{});
+
+    // ---------------- epilogue ----------------
+    // The loop ended with a barrier after the last LDS reads, so the stage buffers can be reused.
+    const S* __restrict__ bias = (const S*)a.bias;
+    const S* __restrict__ Res = (const S*)a.Res;
+    const S* __restrict__ Aux = (const S*)a.aux;
+    S* __restrict__ Y = (S*)a.Y;
+    S* const Cw = (S*)smem + wave * NCP * CLD;
+    const int cl = lane % NCP, sub = lane / NCP;
+
+  #pragma unroll
+    for (int pass = 0; pass < NPASS; ++pass) {
+      if (pass > 0) __syncthreads();  // the previous pass's reads are done
+  #pragma unroll
+      for (int nb = 0; nb < 2; ++nb) {
+        if (NPASS == 2 && nb != pass) continue;
+        const int ccol = (NPASS == 1 ? nb * 16 : 0) + c;
+  #pragma unroll
+        for (int mb = 0; mb < MB; ++mb) {
+          if constexpr (KIND == GK_F64) {
+  #pragma unroll
+            for (int i = 0; i < 4; ++i) Cw[ccol * CLD + mb * 16 + g + 4 * i] = acc[mb][nb][i];
+          } else {
+            *(f4*)&Cw[ccol * CLD + mb * 16 + 4 * g] = acc[mb][nb];
+          }
+        }
+      }
       __syncthreads();
+
+      const int col = n0 + wave * 32 + pass * NCP + cl;
+      const bool cvalid = col < a.Ncols;
+      const S b = (bias && cvalid) ? bias[col] : S(0);
+      const S* Cc = Cw + cl * CLD;
+
+      if constexpr (EPI == 0 || EPI == 1) {
+        // a run of R0 consecutive rows per lane
+        constexpr int R0 = BM / LPC;
+        const int64_t rs = m0 + sub * R0;
+        const uint32_t rpw = (uint32_t)a.yrpw;
+        uint32_t qb = (uint32_t)rs / rpw, rem = (uint32_t)rs - qb * rpw;
+        auto next_off = [&]() {
+          const int64_t off = (int64_t)qb * a.yws + (int64_t)rem * a.ldy + col;
+          if (++rem == rpw) {
+            rem = 0;
+            ++qb;
+          }
+          return off;
+        };
+        if (cvalid) {
+          if constexpr (EPI == 0) {
+  #pragma unroll 4
+            for (int r = 0; r < R0; ++r) {
+              if (rs + r >= a.rows) break;
+              const int64_t off = next_off();
+              const S z = Cc[sub * R0 + r] + b;
+              S o = a.act == 1 ? dtanh(z) : z;
+              if (a.act == 2) {
+                const S t = Aux[off];
+                o *= S(1) - t * t;
+              }
+              if (Res) o += Res[off];
+              Y[off] = o;
+            }
+          } else {
+            // univariate jets: groups of 4 rows (value, first, second derivative, pad)
+            for (int r = 0; r < R0; r += 4) {
+              if (rs + r >= a.rows) break;
+              const S z0 = Cc[sub * R0 + r] + b, z1 = Cc[sub * R0 + r + 1], z2 = Cc[sub * R0 + r + 2];
+              S o[4] = {z0, z1, z2, S(0)};
+              if (a.act) {
+                const S t = dtanh(z0), t1 = S(1) - t * t, t2 = S(-2) * t * t1;
+                o[0] = t;
+                o[1] = t1 * z1;
+                o[2] = t1 * z2 + t2 * z1 * z1;
+              }
+  #pragma unroll
+              for (int e = 0; e < 4; ++e) {
+                const int64_t off = next_off();
+                Y[off] = Res ? o[e] + Res[off] : o[e];
+              }
+            }
+          }
+        }
+      } else {
+        // EPI == 2: groups of Rp rows; a lane takes whole groups, or one part of a group when the
+        // tile has fewer groups than lanes per column
+        const int Rp = a.Rp, T = a.T;
+        const int Gt = BM / Rp;                    // groups in the tile (1, 2, 4 or 8)
+        const int PPG = Gt >= LPC ? 1 : LPC / Gt;  // lanes per group
+        const int GPL = Gt >= LPC ? Gt / LPC : 1;  // groups per lane
+        const int rpp = Rp / PPG;
+        const S* __restrict__ A5 = (const S*)a.add5;
+        for (int j = 0; j < GPL; ++j) {
+          const int grp = PPG == 1 ? sub + LPC * j : sub / PPG;
+          const int part = PPG == 1 ? 0 : sub % PPG;
+          const int qlo = part * rpp;
+          const int64_t rg = m0 + (int64_t)grp * Rp;  // first row of the group
+          const bool gvalid = cvalid && rg < a.rows;
+          const int64_t gidx = rg / Rp;
+          const int el = A5 ? (int)(gidx % a.nel) : -1;
+          const S* Cg = Cc + grp * Rp;
+          // pre-activation of row q, including the bias and the five-row term
+          auto zrow = [&](int q) -> S {
+            S z = Cg[q];
+            if (q == 0) z += b;
+            if (A5) {
+              int k5 = -1;
+              if (q == 0)
+                k5 = 0;
+              else if (q == T + 1)
+                k5 = 4;
+              else if (q >= 1 + 3 * el && q <= 3 + 3 * el)
+                k5 = q - 3 * el;
+              if (k5 >= 0) z += A5[(gidx * 5 + k5) * a.Ncols + col];
+            }
+            return z;
+          };
+          S ssq = 0, z0 = 0;
+          if (gvalid) {
+            z0 = zrow(0);
+            const int q1 = qlo < 1 ? 1 : qlo, q2 = qlo + rpp - 1 < T ? qlo + rpp - 1 : T;
+            for (int q = q1; q <= q2; ++q) {
+              const S z = zrow(q);
+              ssq += z * z;
+            }
+          }
+          for (int o = 1; o < PPG; o <<= 1) ssq += __shfl_xor(ssq, NCP * o);
+          if (gvalid) {
+            S t = z0, t1 = 1, t2 = 0;
+            if (a.act) {
+              t = dtanh(z0);
+              t1 = S(1) - t * t;
+              t2 = S(-2) * t * t1;
+            }
+            const uint32_t rpw = (uint32_t)a.yrpw;
+            const uint32_t qb = (uint32_t)rg / rpw;
+            const int64_t base = (int64_t)qb * a.yws + (int64_t)((uint32_t)rg - qb * rpw) * a.ldy + col;
+            for (int q = qlo; q < qlo + rpp; ++q) {
+              S o;
+              if (q == 0)
+                o = t;
+              else if (q <= T)
+                o = t1 * zrow(q);
+              else if (q == T + 1)
+                o = t1 * zrow(q) + t2 * ssq;
+              else
+                o = 0;
+              const int64_t off = base + (int64_t)q * a.ldy;
+              if (Res) o += Res[off];
+              Y[off] = o;
+            }
+          }
+        }
+      }
     }
   };
-  if (fast && !a.transw)
-    mainloop(std::integral_constant<int, 1>{});
-  else if (fast)
-    mainloop(std::integral_constant<int, 2>{});
-  else
-    mainloop(std::integral_constant<int, 0>{});
-
-  // ---------------- epilogue ----------------
-  // The loop ended with a barrier after the last LDS reads, so the stage buffers can be reused.
-  const S* __restrict__ bias = (const S*)a.bias;
-  const S* __restrict__ Res = (const S*)a.Res;
-  const S* __restrict__ Aux = (const S*)a.aux;
-  S* __restrict__ Y = (S*)a.Y;
-  S* const Cw = (S*)smem + wave * NCP * CLD;
-  const int cl = lane % NCP, sub = lane / NCP;
-
-#pragma unroll
-  for (int pass = 0; pass < NPASS; ++pass) {
-    if (pass > 0) __syncthreads();  // the previous pass's reads are done
-#pragma unroll
-    for (int nb = 0; nb < 2; ++nb) {
-      if (NPASS == 2 && nb != pass) continue;
-      const int ccol = (NPASS == 1 ? nb * 16 : 0) + c;
-#pragma unroll
-      for (int mb = 0; mb < MB; ++mb) {
-        if constexpr (KIND == GK_F64) {
-#pragma unroll
-          for (int i = 0; i < 4; ++i) Cw[ccol * CLD + mb * 16 + g + 4 * i] = acc[mb][nb][i];
-        } else {
-          *(f4*)&Cw[ccol * CLD + mb * 16 + 4 * g] = acc[mb][nb];
-        }
-      }
+  if constexpr (PERSIST) {
+    const int64_t nbx = (a.rows + BM - 1) / BM;
+    for (int64_t bx = blockIdx.x; bx < nbx; bx += gridDim.x) {
+      if (bx != (int64_t)blockIdx.x) __syncthreads();  // the previous tile's epilogue reads are done
+      row_tile(bx);
     }
-    __syncthreads();
-
-    const int col = n0 + wave * 32 + pass * NCP + cl;
-    const bool cvalid = col < a.Ncols;
-    const S b = (bias && cvalid) ? bias[col] : S(0);
-    const S* Cc = Cw + cl * CLD;
-
-    if constexpr (EPI == 0 || EPI == 1) {
-      // a run of R0 consecutive rows per lane
-      constexpr int R0 = BM / LPC;
-      const int64_t rs = m0 + sub * R0;
-      const uint32_t rpw = (uint32_t)a.yrpw;
-      uint32_t qb = (uint32_t)rs / rpw, rem = (uint32_t)rs - qb * rpw;
-      auto next_off = [&]() {
-        const int64_t off = (int64_t)qb * a.yws + (int64_t)rem * a.ldy + col;
-        if (++rem == rpw) {
-          rem = 0;
-          ++qb;
-        }
-        return off;
-      };
-      if (cvalid) {
-        if constexpr (EPI == 0) {
-#pragma unroll 4
-          for (int r = 0; r < R0; ++r) {
-            if (rs + r >= a.rows) break;
-            const int64_t off = next_off();
-            const S z = Cc[sub * R0 + r] + b;
-            S o = a.act == 1 ? dtanh(z) : z;
-            if (a.act == 2) {
-              const S t = Aux[off];
-              o *= S(1) - t * t;
-            }
-            if (Res) o += Res[off];
-            Y[off] = o;
-          }
-        } else {
-          // univariate jets: groups of 4 rows (value, first, second derivative, pad)
-          for (int r = 0; r < R0; r += 4) {
-            if (rs + r >= a.rows) break;
-            const S z0 = Cc[sub * R0 + r] + b, z1 = Cc[sub * R0 + r + 1], z2 = Cc[sub * R0 + r + 2];
-            S o[4] = {z0, z1, z2, S(0)};
-            if (a.act) {
-              const S t = dtanh(z0), t1 = S(1) - t * t, t2 = S(-2) * t * t1;
-              o[0] = t;
-              o[1] = t1 * z1;
-              o[2] = t1 * z2 + t2 * z1 * z1;
-            }
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-              const int64_t off = next_off();
-              Y[off] = Res ? o[e] + Res[off] : o[e];
-            }
-          }
-        }
-      }
-    } else {
-      // EPI == 2: groups of Rp rows; a lane takes whole groups, or one part of a group when the
-      // tile has fewer groups than lanes per column
-      const int Rp = a.Rp, T = a.T;
-      const int Gt = BM / Rp;                    // groups in the tile (1, 2, 4 or 8)
-      const int PPG = Gt >= LPC ? 1 : LPC / Gt;  // lanes per group
-      const int GPL = Gt >= LPC ? Gt / LPC : 1;  // groups per lane
-      const int rpp = Rp / PPG;
-      const S* __restrict__ A5 = (const S*)a.add5;
-      for (int j = 0; j < GPL; ++j) {
-        const int grp = PPG == 1 ? sub + LPC * j : sub / PPG;
-        const int part = PPG == 1 ? 0 : sub % PPG;
-        const int qlo = part * rpp;
-        const int64_t rg = m0 + (int64_t)grp * Rp;  // first row of the group
-        const bool gvalid = cvalid && rg < a.rows;
-        const int64_t gidx = rg / Rp;
-        const int el = A5 ? (int)(gidx % a.nel) : -1;
-        const S* Cg = Cc + grp * Rp;
-        // pre-activation of row q, including the bias and the five-row term
-        auto zrow = [&](int q) -> S {
-          S z = Cg[q];
-          if (q == 0) z += b;
-          if (A5) {
-            int k5 = -1;
-            if (q == 0)
-              k5 = 0;
-            else if (q == T + 1)
-              k5 = 4;
-            else if (q >= 1 + 3 * el && q <= 3 + 3 * el)
-              k5 = q - 3 * el;
-            if (k5 >= 0) z += A5[(gidx * 5 + k5) * a.Ncols + col];
-          }
-          return z;
-        };
-        S ssq = 0, z0 = 0;
-        if (gvalid) {
-          z0 = zrow(0);
-          const int q1 = qlo < 1 ? 1 : qlo, q2 = qlo + rpp - 1 < T ? qlo + rpp - 1 : T;
-          for (int q = q1; q <= q2; ++q) {
-            const S z = zrow(q);
-            ssq += z * z;
-          }
-        }
-        for (int o = 1; o < PPG; o <<= 1) ssq += __shfl_xor(ssq, NCP * o);
-        if (gvalid) {
-          S t = z0, t1 = 1, t2 = 0;
-          if (a.act) {
-            t = dtanh(z0);
-            t1 = S(1) - t * t;
-            t2 = S(-2) * t * t1;
-          }
-          const uint32_t rpw = (uint32_t)a.yrpw;
-          const uint32_t qb = (uint32_t)rg / rpw;
-          const int64_t base = (int64_t)qb * a.yws + (int64_t)((uint32_t)rg - qb * rpw) * a.ldy + col;
-          for (int q = qlo; q < qlo + rpp; ++q) {
-            S o;
-            if (q == 0)
-              o = t;
-            else if (q <= T)
-              o = t1 * zrow(q);
-            else if (q == T + 1)
-              o = t1 * zrow(q) + t2 * ssq;
-            else
-              o = 0;
-            const int64_t off = base + (int64_t)q * a.ldy;
-            if (Res) o += Res[off];
-            Y[off] = o;
-          }
-        }
-      }
-    }
+  } else {
+    row_tile(blockIdx.x);
   }
 }
 
@@ -492,42 +505,82 @@ static const char* gemm_name(int kind, int mb, int epi) {
   return names[kind][mb][epi];
 }
 
-template <int KIND, int MB, int EPI, int BKT>
-static hipError_t launch_mb(const GemmArgs& a, hipStream_t st) {
+static int device_cus() {
+  static int cus = 0;
+  if (cus == 0) {
+    int dev = 0, n = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && n > 0)
+      cus = n;
+    else
+      cus = 256;
+  }
+  return cus;
+}
+
+template <int KIND, int MB, int EPI, int BKT, bool PERSIST>
+static hipError_t launch_grid(const GemmArgs& a, hipStream_t st) {
   ProfScope ps(gemm_name(KIND, MB, EPI), st);
   constexpr int BM = 16 * MB;
-  dim3 grid((unsigned)((a.rows + BM - 1) / BM), (unsigned)((a.Ncols + 127) / 128));
-  hipLaunchKernelGGL((gemm_kernel<KIND, MB, EPI, BKT>), grid, dim3(256), 0, st, a);
+  const int64_t nbx = (a.rows + BM - 1) / BM;
+  const unsigned gy = (unsigned)((a.Ncols + 127) / 128);
+  int64_t gx = nbx;
+  if constexpr (PERSIST) {
+    // as many blocks as fit on the device at once, each walking row tiles with a grid stride
+    static int occ = 0;
+    if (occ == 0) {
+      int o = 0;
+      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, gemm_kernel<KIND, MB, EPI, BKT, true>, 256, 0) !=
+              hipSuccess ||
+          o < 1)
+        o = 1;
+      occ = o;
+    }
+    const int64_t slots = (int64_t)occ * device_cus() / gy;
+    gx = std::max<int64_t>(1, std::min<int64_t>(nbx, slots));
+  }
+  hipLaunchKernelGGL((gemm_kernel<KIND, MB, EPI, BKT, PERSIST>), dim3((unsigned)gx, gy), dim3(256), 0, st, a);
   return hipGetLastError();
 }
 
+// Persistent variants are instantiated for float32 only (the other kinds ignore the bit).
+template <int KIND, int MB, int EPI, int BKT>
+static hipError_t launch_mb(const GemmArgs& a, bool persist, hipStream_t st) {
+  if constexpr (KIND == GK_F32)
+    if (persist) return launch_grid<KIND, MB, EPI, BKT, true>(a, st);
+  return launch_grid<KIND, MB, EPI, BKT, false>(a, st);
+}
+
 // Tile choice (GemmArgs::tile - 1 when nonzero, or QMC_GEMM_TILE=<bits> for tuning runs): bit 0
-// selects 32-wide K stages for float32, bit 1 half-height (64-row) value and edge tiles.  The
-// default takes half-height tiles when full ones would give fewer than 4 blocks per compute unit.
+// selects 32-wide K stages for float32, bit 1 half-height (64-row) value and edge tiles, bit 2 a
+// persistent grid (float32).  The default takes half-height tiles when full ones would give fewer than 4
+// blocks per compute unit.
 static int tile_bits(const GemmArgs& a) {
   static int env = -2;
   if (env == -2) {
     env = -1;
-    if (const char* e = getenv("QMC_GEMM_TILE")) env = atoi(e) & 3;
+    if (const char* e = getenv("QMC_GEMM_TILE")) env = atoi(e) & 7;
   }
   if (env >= 0) return env;
-  if (a.tile > 0) return (a.tile - 1) & 3;
+  if (a.tile > 0) return (a.tile - 1) & 7;
   const int64_t blocks = ((a.rows + 127) / 128) * ((a.Ncols + 127) / 128);
   return (a.vmode || a.Rp == 4) && blocks < 4 * 256 ? 2 : 0;
 }
 
 template <int KIND, int BKT>
 static hipError_t launch_kind_bk(const GemmArgs& a, int bits, hipStream_t st) {
-  const bool half = (bits & 2) != 0;
-  if (a.vmode) return half ? launch_mb<KIND, 4, 0, BKT>(a, st) : launch_mb<KIND, 8, 0, BKT>(a, st);
-  if (a.Rp == 4) return half ? launch_mb<KIND, 4, 1, BKT>(a, st) : launch_mb<KIND, 8, 1, BKT>(a, st);
+  const bool half = (bits & 2) != 0, persist = (bits & 4) != 0;
+  if (a.vmode)
+    return half ? launch_mb<KIND, 4, 0, BKT>(a, persist, st) : launch_mb<KIND, 8, 0, BKT>(a, persist, st);
+  if (a.Rp == 4)
+    return half ? launch_mb<KIND, 4, 1, BKT>(a, persist, st) : launch_mb<KIND, 8, 1, BKT>(a, persist, st);
   if (a.Rp % 16 != 0 || a.Rp > 128) return hipErrorInvalidValue;
   const int bpg = a.Rp / 16;
   switch (bpg * (8 / bpg)) {
-    case 5: return launch_mb<KIND, 5, 2, BKT>(a, st);
-    case 6: return launch_mb<KIND, 6, 2, BKT>(a, st);
-    case 7: return launch_mb<KIND, 7, 2, BKT>(a, st);
-    case 8: return launch_mb<KIND, 8, 2, BKT>(a, st);
+    case 5: return launch_mb<KIND, 5, 2, BKT>(a, persist, st);
+    case 6: return launch_mb<KIND, 6, 2, BKT>(a, persist, st);
+    case 7: return launch_mb<KIND, 7, 2, BKT>(a, persist, st);
+    case 8: return launch_mb<KIND, 8, 2, BKT>(a, persist, st);
   }
   return hipErrorInvalidValue;
 }

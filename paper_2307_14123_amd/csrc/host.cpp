@@ -1,5 +1,6 @@
 // Host-side part of the qmc library: parameter layout, plan creation,
-// argument validation and workspace sizing.  No HIP calls here, so that this
+// argument validation and workspace sizing.  No HIP calls here (the device set-up of plans created
+// with flags lives in the HIP part: plan_device_init), so that this
 // translation unit can be exercised on a machine without a GPU.
 #include <cmath>
 #include <cstring>
@@ -178,14 +179,26 @@ BwdWorkspace bwd_layout(const Plan& p, const SysPlan& s, int64_t wc) {
   return b;
 }
 
+static size_t sys_bytes(const Plan& p, int op, const SysPlan& s) {
+  return (op == QMC_OP_LOGPSI_VJP || op == QMC_OP_LOSS_GRAD) ? bwd_layout(p, s, s.Wc).total
+                                                              : workspace_layout(p, s, op, s.Wc).total;
+}
+
+size_t sys_ws_offset(const Plan& p, int op, size_t si) {
+  if (!p.concurrent()) return 0;
+  size_t off = 0;
+  for (size_t k = 0; k < si; ++k) off += align256(sys_bytes(p, op, p.sys[k]));
+  return off;
+}
+
 size_t workspace_bytes(const Plan& p, int op) {
-  size_t mx = 0;
+  size_t mx = 0, sum = 0;
   for (const auto& s : p.sys) {
-    const size_t b = (op == QMC_OP_LOGPSI_VJP || op == QMC_OP_LOSS_GRAD) ? bwd_layout(p, s, s.Wc).total
-                                                                          : workspace_layout(p, s, op, s.Wc).total;
+    const size_t b = sys_bytes(p, op, s);
     if (b > mx) mx = b;
+    sum += align256(b);
   }
-  return mx + 256;
+  return (p.concurrent() ? sum : mx) + 256;
 }
 
 static bool valid_system(const qmc_system* s) {
@@ -233,7 +246,7 @@ qmc_status qmc_plan_create(qmc_plan** out, const qmc_system* systems, int32_t n_
   if (!valid_ansatz(ansatz)) return QMC_ERR_INVALID_ARGUMENT;
   if (precision != QMC_FP64 && precision != QMC_FP32 && precision != QMC_BF16_MIXED)
     return QMC_ERR_INVALID_ARGUMENT;
-  if (flags != 0) return QMC_ERR_INVALID_ARGUMENT;
+  if (flags & ~uint32_t(QMC_PLAN_CONCURRENT_SYSTEMS | QMC_PLAN_AUTOTUNE)) return QMC_ERR_INVALID_ARGUMENT;
   // the bf16 MFMA path works on K in steps of 32 and the jet GEMM tiles on 16-wide
   // column blocks; both handle any width, so no further restriction here.
   qmc_plan* plan = new (std::nothrow) qmc_plan;
@@ -241,6 +254,7 @@ qmc_status qmc_plan_create(qmc_plan** out, const qmc_system* systems, int32_t n_
   Plan& P = plan->p;
   P.ans = *ansatz;
   P.prec = precision;
+  P.flags = flags;
   P.total_walkers = 0;
   P.total_params = 0;
   P.max_chunk_bytes = int64_t(24) << 30;
@@ -279,6 +293,7 @@ qmc_status qmc_plan_create(qmc_plan** out, const qmc_system* systems, int32_t n_
     sp.P[TYPE_OPP] = sp.nup * sp.ndn;
     sp.P[TYPE_NUC] = sp.N * sp.M;
     sp.Wc = sp.W;
+    for (int c = 0; c < 4; ++c) sp.tile[c] = 0;
     P.total_walkers += sp.W;
     P.total_params += sp.off.total;
     P.sys.push_back(sp);
@@ -290,13 +305,28 @@ qmc_status qmc_plan_create(qmc_plan** out, const qmc_system* systems, int32_t n_
       wc = (wc + 1) / 2;
     sp.Wc = wc;
   }
+  if (flags) {
+    const qmc_status e = plan_device_init(P);
+    if (e != QMC_OK) {
+      plan_device_release(P);
+      delete plan;
+      return e;
+    }
+  }
   *out = plan;
   return QMC_OK;
 }
 
 qmc_status qmc_plan_destroy(qmc_plan* plan) {
   if (!plan) return QMC_ERR_INVALID_ARGUMENT;
+  plan_device_release(plan->p);
   delete plan;
+  return QMC_OK;
+}
+
+qmc_status qmc_plan_tiles(const qmc_plan* plan, int32_t s, int32_t tiles[4]) {
+  if (!plan || !tiles || s < 0 || s >= (int32_t)plan->p.sys.size()) return QMC_ERR_INVALID_ARGUMENT;
+  for (int c = 0; c < 4; ++c) tiles[c] = plan->p.sys[s].tile[c];
   return QMC_OK;
 }
 

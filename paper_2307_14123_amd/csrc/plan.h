@@ -37,16 +37,25 @@ struct SysPlan {
   int Rp;                 // jet rows per electron, padded: roundup(3N + 2, 16)
   int P[3];               // pairs per edge type: same-spin (unordered), up-down, electron-nucleus
   int64_t Wc;             // walkers per launch sequence (chunk)
+  int tile[4];            // GEMM tile choice per class (TILE_*): 0 default, else 1 + tile bits
   int nsig(int s) const { return s == 0 ? nup : ndn; }
 };
+
+enum { TILE_JET = 0, TILE_VAL = 1, TILE_EDGE = 2, TILE_BWD = 3 };
 
 struct Plan {
   qmc_ansatz ans;
   qmc_precision prec;
+  uint32_t flags;
   std::vector<SysPlan> sys;
   int64_t total_walkers;
   int64_t total_params;
   int64_t max_chunk_bytes;
+  // QMC_PLAN_CONCURRENT_SYSTEMS: one stream per system, a fork event and one join event per system
+  // (HIP handles, created and destroyed by plan_device_init / plan_device_release)
+  std::vector<void*> streams, joins;
+  void* fork = nullptr;
+  bool concurrent() const { return (flags & QMC_PLAN_CONCURRENT_SYSTEMS) && sys.size() > 1; }
 };
 
 // Byte offsets of the buffers one chunk of one system uses (forward ops).
@@ -82,6 +91,11 @@ size_t act_bytes(qmc_precision p);
 Workspace workspace_layout(const Plan& p, const SysPlan& s, int op, int64_t wc);
 BwdWorkspace bwd_layout(const Plan& p, const SysPlan& s, int64_t wc);
 size_t workspace_bytes(const Plan& p, int op);
+// Byte offset of system si's workspace region (0 unless the plan runs systems concurrently).
+size_t sys_ws_offset(const Plan& p, int op, size_t si);
+// Streams, events and autotuning of a plan created with flags (device code, in the HIP part).
+qmc_status plan_device_init(Plan& p);
+void plan_device_release(Plan& p);
 
 }  // namespace qmc
 

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libqmc.so")
 QMC_FP64, QMC_FP32, QMC_BF16_MIXED = 0, 1, 2
 PRECISIONS = {"fp64": QMC_FP64, "fp32": QMC_FP32, "bf16": QMC_BF16_MIXED}
 OP_LOGPSI, OP_LOCAL_ENERGY, OP_METROPOLIS, OP_LOGPSI_VJP, OP_LOSS_GRAD = range(5)
+PLAN_CONCURRENT_SYSTEMS, PLAN_AUTOTUNE = 1, 2
 
 
 class QmcSystem(ctypes.Structure):
@@ -71,6 +72,8 @@ def lib():
     L.qmc_profile_enable.argtypes = [i32]
     L.qmc_profile_report.restype = i32
     L.qmc_profile_report.argtypes = [ctypes.c_char_p, sz, i32]
+    L.qmc_plan_tiles.restype = i32
+    L.qmc_plan_tiles.argtypes = [vp, i32, ctypes.POINTER(i32)]
     L.qmc_status_str.restype = ctypes.c_char_p
     L.qmc_status_str.argtypes = [i32]
     _lib = L
@@ -117,9 +120,15 @@ def param_count(system, ans) -> int:
 
 
 class Plan:
-    """A plan over one or several systems; methods take device tensors."""
+    """A plan over one or several systems; methods take device tensors.
 
-    def __init__(self, systems: Sequence, walkers: Sequence[int], ans, precision: str = "fp64"):
+    concurrent: run every system on its own stream of the plan (fork/join with
+    the current stream), so that a multi-system batch shares the device and
+    captures into one graph.  autotune: time the GEMM tile candidates of every
+    system at creation and keep the fastest."""
+
+    def __init__(self, systems: Sequence, walkers: Sequence[int], ans, precision: str = "fp64",
+                 concurrent: bool = False, autotune: bool = False):
         self.systems = list(systems)
         self.walkers = [int(w) for w in walkers]
         self.ans = ans
@@ -129,8 +138,9 @@ class Plan:
         wps = (ctypes.c_int64 * len(self.walkers))(*self.walkers)
         a = make_ansatz(ans)
         handle = ctypes.c_void_p(0)
+        flags = (PLAN_CONCURRENT_SYSTEMS if concurrent else 0) | (PLAN_AUTOTUNE if autotune else 0)
         _check(lib().qmc_plan_create(ctypes.byref(handle), arr, len(holders), wps, ctypes.byref(a),
-                                     PRECISIONS[precision], 0), "qmc_plan_create")
+                                     PRECISIONS[precision], flags), "qmc_plan_create")
         self.handle = handle
         tw, tp, tpos = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
         _check(lib().qmc_plan_info(self.handle, ctypes.byref(tw), ctypes.byref(tp), ctypes.byref(tpos)),
@@ -145,17 +155,28 @@ class Plan:
             _lib.qmc_plan_destroy(h)
             self.handle = None
 
+    def tiles(self):
+        """Per system: GEMM tile choice of the (jet, value, edge, backward) classes (0 = default)."""
+        out = []
+        for k in range(len(self.systems)):
+            t = (ctypes.c_int32 * 4)()
+            _check(lib().qmc_plan_tiles(self.handle, k, t), "qmc_plan_tiles")
+            out.append(tuple(int(x) for x in t))
+        return out
+
     def workspace_bytes(self, op: int) -> int:
         b = ctypes.c_size_t()
         _check(lib().qmc_workspace_size(self.handle, op, ctypes.byref(b)), "qmc_workspace_size")
         return int(b.value)
 
     def workspace(self, op: int, device="cuda"):
+        """One workspace shared by all operations (calls are ordered on the stream), grown on demand."""
         n = self.workspace_bytes(op)
-        ws = self._ws.get(op)
+        ws = self._ws.get("shared")
         if ws is None or ws.numel() < n:
+            self._ws.pop("shared", None)
             ws = torch.empty(n, dtype=torch.uint8, device=device)
-            self._ws[op] = ws
+            self._ws["shared"] = ws
         return ws
 
     def _check_inputs(self, params, r):
@@ -216,14 +237,54 @@ class Plan:
                                     ws.numel(), _stream()), "qmc_logpsi_vjp")
         return g
 
-    def loss_grad(self, params, r, e_loc):
+    def loss_grad(self, params, r, e_loc, grad=None, e_mean=None):
         self._check_inputs(params, r)
-        g = torch.empty_like(params)
-        em = torch.empty(len(self.systems), dtype=torch.float64, device=r.device)
+        g = torch.empty_like(params) if grad is None else grad
+        em = torch.empty(len(self.systems), dtype=torch.float64, device=r.device) if e_mean is None else e_mean
+        if g.dtype != params.dtype or g.numel() != params.numel() or em.numel() != len(self.systems):
+            raise ValueError("grad / e_mean: wrong dtype or size")
         ws = self.workspace(OP_LOSS_GRAD)
         _check(lib().qmc_loss_grad(self.handle, _ptr(params), _ptr(r), _ptr(e_loc), _ptr(g), _ptr(em), _ptr(ws),
                                    ws.numel(), _stream()), "qmc_loss_grad")
         return g, em
+
+
+class GraphStep:
+    """Local energies and the loss gradient of a plan captured into one graph.
+
+    Inputs (params, r) and outputs (self.out: logpsi, sign, grad, lap, e_loc,
+    param_grad, e_mean) are static tensors; write new positions into r and call
+    replay().  With a concurrent plan the graph holds one branch per system."""
+
+    def __init__(self, plan: Plan, params, r, warmup: int = 1):
+        self.plan, self.params, self.r = plan, params, r
+        W, dev = plan.total_walkers, r.device
+        self.out = {"logpsi": torch.empty(W, dtype=torch.float64, device=dev),
+                    "sign": torch.empty(W, dtype=torch.float64, device=dev),
+                    "grad": torch.empty(plan.total_positions, dtype=torch.float64, device=dev),
+                    "lap": torch.empty(W, dtype=torch.float64, device=dev),
+                    "e_loc": torch.empty(W, dtype=torch.float64, device=dev),
+                    "param_grad": torch.empty_like(params),
+                    "e_mean": torch.empty(len(plan.systems), dtype=torch.float64, device=dev)}
+        # workspaces are allocated by the warm-up, outside the capture
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            for _ in range(warmup):
+                self._body()
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph):
+            self._body()
+
+    def _body(self):
+        o = self.out
+        self.plan.local_energy(self.params, self.r, out=o)
+        self.plan.loss_grad(self.params, self.r, o["e_loc"], grad=o["param_grad"], e_mean=o["e_mean"])
+
+    def replay(self):
+        self.graph.replay()
 
 
 def det_jets(jets, n: int, n_tan: int):

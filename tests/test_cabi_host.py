@@ -54,7 +54,7 @@ def test_invalid_arguments_rejected():
     W = (ctypes.c_int64 * 1)(16)
     arr = (qmc.QmcSystem * 1)(h.s)
     assert L.qmc_plan_create(ctypes.byref(handle), arr, 1, W, ctypes.byref(a), 7, 0) == 1      # precision
-    assert L.qmc_plan_create(ctypes.byref(handle), arr, 1, W, ctypes.byref(a), 1, 3) == 1      # flags
+    assert L.qmc_plan_create(ctypes.byref(handle), arr, 1, W, ctypes.byref(a), 1, 8) == 1      # unknown flag
     W0 = (ctypes.c_int64 * 1)(0)
     assert L.qmc_plan_create(ctypes.byref(handle), arr, 1, W0, ctypes.byref(a), 1, 0) == 1     # no walkers
     neg = qmc.QmcSystem(2, h.Z, h.R, -1, 7)
@@ -96,3 +96,32 @@ def test_walker_chunking_bounds_workspace():
     plan = qmc.Plan([qi.C4H4], [8192], qi.C4H4_ANSATZ, "bf16")
     assert plan.workspace_bytes(qmc.OP_LOCAL_ENERGY) < (25 << 30)
     assert plan.total_params == 2286752
+
+
+def test_plan_flags_and_tiles():
+    """Known flags are accepted (they need a device: without one the plan reports QMC_ERR_HIP);
+    a plain plan reports the built-in tile choice (0) for every GEMM class."""
+    qmc, L = _lib()
+    a = qmc.make_ansatz(qi.BATCH_ANSATZ)
+    mols = qi.workload(4).systems[:2]
+    hs = [qmc._SysHolder(m) for m in mols]
+    arr = (qmc.QmcSystem * 2)(*[h.s for h in hs])
+    W = (ctypes.c_int64 * 2)(8, 8)
+    for flags in (1, 2, 3):
+        handle = ctypes.c_void_p(0)
+        st = L.qmc_plan_create(ctypes.byref(handle), arr, 2, W, ctypes.byref(a), 1, flags)
+        assert st in (0, 4)
+        if st == 0:
+            assert L.qmc_plan_destroy(handle) == 0
+        else:
+            assert not handle.value
+    handle = ctypes.c_void_p(0)
+    assert L.qmc_plan_create(ctypes.byref(handle), arr, 2, W, ctypes.byref(a), 1, 0) == 0
+    try:
+        t = (ctypes.c_int32 * 4)()
+        assert L.qmc_plan_tiles(handle, 1, t) == 0 and list(t) == [0, 0, 0, 0]
+        assert L.qmc_plan_tiles(handle, 2, t) == 1
+        assert L.qmc_plan_tiles(handle, -1, t) == 1
+    finally:
+        L.qmc_plan_destroy(handle)
+
