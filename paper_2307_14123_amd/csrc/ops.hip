@@ -9,6 +9,8 @@
 // with u the unit vector of r_i - r_j (or r_i - R_I).
 #include <cmath>
 
+#include <algorithm>
+
 #include "kernels.h"
 
 namespace qmc {
@@ -262,146 +264,187 @@ hipError_t launch_init_features(const SysDev& s, const double* ee, const double*
 // propagated with the product rule, written as [W][N][Rp][2D].  (The nuclear
 // message is nonzero in 5 jet rows only and is handled by nuc_message_kernel.)
 //
-// Block: (walker, column chunk of DC).  Thread: (receiver i, column d).  Each
-// thread keeps the filter values w(d_ij) of its receiver, split into a
-// same-spin and an opposite-spin array (zero elsewhere), and the filter
-// Laplacians in registers.  The senders' jet rows stream through LDS in
-// chunks of RC rows (rows of absent senders up to NMAX are zero, so the sums
-// need no guards); filter derivatives w'(d_ij), the senders' value rows and
-// the geometry sit in LDS.  Tangent row c = 3k + a gets, besides
-// sum_j w_ij dh_j/dx_c:
+// Block: one walker and a chunk of DC columns.  Thread: one column d and one
+// group of up to RG receivers of the same spin.  The group's filter values
+// w(d_ij) for every sender stay in registers in fixed sender slots (up
+// electrons, then down electrons, NS slots each; empty slots hold weight 0 and
+// read a valid row, so the sums have no branches), and same/opposite follows
+// from the receivers' spin.  The senders' jet rows are read one row q at a
+// time, the next row (and the operands of its moving-sender correction)
+// fetched while the current one is used; every output row is written once.
+// Tangent row c = 3k + a gets, besides sum_j w_ij dh_j/dx_c:
 //   k == i:  sum_j h_j w'_ij u_ij[a]          (dd_ij/dr_i = u_ij)
 //   k != i:  -h_k w'_ik u_ik[a]               (dd_ik/dr_k = -u_ik)
 // and the Laplacian row adds sum_j h_j (2 w'' + 4 w'/d) + 2 sum_c dw/dx_c dh_j/dx_c,
 // whose cross term accumulates while the tangent rows stream past.
-template <typename S, int NMAX>
-__global__ __launch_bounds__(NMAX >= 32 ? 256 : 512) void aggregate_kernel(
-    SysDev s, const S* __restrict__ h, const S* __restrict__ wsame, const S* __restrict__ wopp,
-    const double* __restrict__ ee, int DC, int RC, S* __restrict__ m) {
+template <typename S, int NS, int RG>
+__global__ __launch_bounds__(512) void aggregate_kernel(SysDev s, const S* __restrict__ h,
+                                                        const S* __restrict__ wsame, const S* __restrict__ wopp,
+                                                        const double* __restrict__ ee, int DC, int nch,
+                                                        S* __restrict__ m) {
   extern __shared__ __align__(16) unsigned char smem[];
-  const int N = s.N, D = s.D;
-  const int Rp = s.Rp;
-  constexpr int Re = 4;
-  const int64_t w = blockIdx.x;
-  const int d0 = blockIdx.y * DC;
-  S* hs = (S*)smem;                 // [NMAX][RC][DC], rows of j >= N stay zero
-  S* wdl = hs + NMAX * RC * DC;     // [N][N][DC]: w'(d_ij) (zero on the diagonal)
-  S* h0s = wdl + N * N * DC;        // [N][DC]: senders' value rows
-  S* gu = h0s + N * DC;             // [N][N][4]: d_ij, unit vector of r_i - r_j
-  const int nt = blockDim.x;
-  for (int e = threadIdx.x; e < N * N * 4; e += nt) gu[e] = (S)ee[w * N * N * 4 + e];
-  for (int e = threadIdx.x; e < N * N * DC; e += nt) {
-    const int x = e % DC, ij = e / DC, ii = ij / N, jj = ij % N;
-    S v = 0;
-    if (ii != jj && d0 + x < D) {
-      int type;
-      const int p = ee_pair(s, ii, jj, type);
-      v = (type ? wopp : wsame)[((w * (type ? s.P1 : s.P0) + p) * Re + 1) * D + d0 + x];
-    }
-    wdl[e] = v;
-  }
-  for (int e = threadIdx.x; e < NMAX * RC * DC; e += nt) hs[e] = S(0);
-  const int dd = threadIdx.x % DC;
-  const int i = threadIdx.x / DC;
-  const int d = d0 + dd;
-  const bool active = (i < N) && (d < D);
-  const bool up = i < s.nup;
-  const int nsame = (up ? s.nup : s.ndn) - 1;
-  const int nopp = up ? s.ndn : s.nup;
-  const S inv_s = nsame > 0 ? S(1) / S(nsame) : S(0);
-  const S inv_o = nopp > 0 ? S(1) / S(nopp) : S(0);
-  S wsm[NMAX], wop[NMAX], lw[NMAX];
-#pragma unroll
-  for (int j = 0; j < NMAX; ++j) {
-    wsm[j] = 0;
-    wop[j] = 0;
-    lw[j] = 0;
-    if (active && j < N && j != i) {
+  constexpr int OPP = 1 << 30;
+  const int N = s.N, D = s.D, Rp = s.Rp, T = s.T, nup = s.nup, ndn = s.ndn;
+  const int64_t w = blockIdx.x / nch;
+  const int chunk = blockIdx.x - (int)(w * nch);
+  S* gu = (S*)smem;                  // [N][N][4]: d_ij, unit vector of r_i - r_j
+  int* pt = (int*)(gu + N * N * 4);  // [N][N]: pair index within its type, | OPP for an up-down pair
+  for (int e = threadIdx.x; e < N * N * 4; e += blockDim.x) gu[e] = (S)ee[w * N * N * 4 + e];
+  for (int e = threadIdx.x; e < N * N; e += blockDim.x) {
+    const int i = e / N, j = e - (e / N) * N;
+    int v = 0;
+    if (i != j) {
       int type;
       const int p = ee_pair(s, i, j, type);
-      const S* wt = (type ? wopp : wsame) + ((w * (type ? s.P1 : s.P0) + p) * Re) * D + d;
-      if (type)
-        wop[j] = wt[0];
-      else
-        wsm[j] = wt[0];
-      lw[j] = wt[2 * D];  // w'' for now; combined with w'/d below
+      v = type ? (p | OPP) : p;
     }
+    pt[e] = v;
   }
   __syncthreads();
+  const int d = chunk * DC + (int)(threadIdx.x % DC), g = threadIdx.x / DC;
+  const int ngu = (nup + RG - 1) / RG, ngd = (ndn + RG - 1) / RG;
+  if (d >= D || g >= ngu + ngd) return;  // no barriers below
+  const bool up = g < ngu;
+  const int i0 = up ? g * RG : nup + (g - ngu) * RG;
+  const int cnt = min(RG, (up ? nup : N) - i0);
+  const int nsame = (up ? nup : ndn) - 1, nopp = up ? ndn : nup;
+  const S inv_s = nsame > 0 ? S(1) / S(nsame) : S(0), inv_o = nopp > 0 ? S(1) / S(nopp) : S(0);
+  // row r (0 value, 1 first, 2 second derivative) of the filter jet of pair (i, j), column d
+  auto wrow = [&](int i, int j, int r) -> S {
+    const int v = pt[i * N + j];
+    return (v & OPP) ? wopp[((w * s.P1 + (v & (OPP - 1))) * 4 + r) * (int64_t)D + d]
+                     : wsame[((w * s.P0 + v) * 4 + r) * (int64_t)D + d];
+  };
+  // sender of slot sl, clamped to a valid electron for empty slots (their weights are zero)
+  auto sender = [&](int sl) { return sl < NS ? min(sl, N - 1) : min(nup + sl - NS, N - 1); };
+  S wv[RG][2 * NS];
 #pragma unroll
-  for (int j = 0; j < NMAX; ++j)
-    if (active && j < N && j != i) lw[j] = S(2) * lw[j] + S(4) * wdl[(i * N + j) * DC + dd] / gu[(i * N + j) * 4];
-  S lx_s = 0, lx_o = 0;  // Laplacian-row cross terms, same-spin and opposite-spin senders
-  const bool ups = up;
-  S* mrow = m + ((w * N + i) * (int64_t)Rp) * 2 * D + d;
-  for (int q0 = 0; q0 < Rp; q0 += RC) {
-    __syncthreads();
-    for (int e = threadIdx.x; e < N * RC * DC; e += nt) {
-      const int x = e % DC, qq = (e / DC) % RC, j = e / (RC * DC);
-      const int q = q0 + qq;
-      const S v = (q < Rp && d0 + x < D) ? h[((w * N + j) * Rp + q) * (int64_t)D + d0 + x] : S(0);
-      hs[e] = v;
-      if (q == 0) h0s[j * DC + x] = v;
+  for (int r = 0; r < RG; ++r)
+#pragma unroll
+    for (int sl = 0; sl < 2 * NS; ++sl) {
+      const int j = sender(sl);
+      const bool ok = r < cnt && (sl < NS ? sl < nup : sl - NS < ndn) && j != i0 + r;
+      wv[r][sl] = ok ? wrow(i0 + r, j, 0) : S(0);
     }
-    __syncthreads();
-    if (!active) continue;
-    const int qe = (q0 + RC < Rp) ? q0 + RC : Rp;
-    for (int q = q0; q < qe; ++q) {
-      const int qq = q - q0;
-      S ms = 0, mo = 0;
+  const S* hb = h + w * N * (int64_t)Rp * D + d;  // h_j row q: hb[(j * Rp + q) * D]
+  S* mb = m + w * N * (int64_t)Rp * 2 * D + d;    // m_i row q: mb[(i * Rp + q) * 2D], opposite at + D
+  S lxs[RG], lxo[RG];
 #pragma unroll
-      for (int j = 0; j < NMAX; ++j) {
-        const S hv = hs[(j * RC + qq) * DC + dd];
-        ms += wsm[j] * hv;
-        mo += wop[j] * hv;
+  for (int r = 0; r < RG; ++r) lxs[r] = lxo[r] = 0;
+  S hv[2 * NS];
+  auto fetch = [&](int q, S* dst) {
+#pragma unroll
+    for (int sl = 0; sl < 2 * NS; ++sl) dst[sl] = hb[((int64_t)sender(sl) * Rp + q) * D];
+  };
+  // operands of the moving-sender correction of a tangent row (sender kk): w'_ik of every receiver,
+  // h_k value row and h_k row q
+  S cwp[RG], ch0 = 0, chq = 0;
+  auto fetch_corr = [&](int q, int kk, S* wp, S& h0, S& hq) {
+#pragma unroll
+    for (int r = 0; r < RG; ++r) wp[r] = (r < cnt && i0 + r != kk) ? wrow(i0 + r, kk, 1) : S(0);
+    h0 = hb[(int64_t)kk * Rp * D];
+    hq = hb[((int64_t)kk * Rp + q) * D];
+  };
+#pragma unroll
+  for (int r = 0; r < RG; ++r) cwp[r] = 0;
+  fetch(0, hv);
+  int k = 0, a = 0;  // electron and coordinate of tangent row q (q >= 1)
+  for (int q = 0; q <= T + 1; ++q) {
+    S nv[2 * NS], nwp[RG], nh0 = 0, nhq = 0;
+    if (q <= T) fetch(q + 1, nv);
+    if (q + 1 <= T) fetch_corr(q + 1, q / 3, nwp, nh0, nhq);  // tangent row q + 1 moves electron q / 3
+    S ms[RG], mo[RG];
+#pragma unroll
+    for (int r = 0; r < RG; ++r) {
+      S au = 0, ad = 0;
+#pragma unroll
+      for (int sl = 0; sl < NS; ++sl) {
+        au += wv[r][sl] * hv[sl];
+        ad += wv[r][NS + sl] * hv[NS + sl];
       }
-      if (q >= 1 && q <= s.T) {
-        const int c = q - 1, k = c / 3, a = c % 3;
+      ms[r] = up ? au : ad;
+      mo[r] = up ? ad : au;
+    }
+    if (q >= 1 && q <= T) {
+#pragma unroll
+      for (int r = 0; r < RG; ++r) {
+        if (r >= cnt) continue;
+        const int i = i0 + r;
         if (k == i) {
+          // d(d_ij)/dr_i = u_ij for every sender j
+#pragma unroll 4
           for (int j = 0; j < N; ++j) {
             if (j == i) continue;
-            const S cw = wdl[(i * N + j) * DC + dd] * gu[(i * N + j) * 4 + 1 + a];
-            const S t0 = h0s[j * DC + dd] * cw;
-            const S t1 = S(2) * cw * hs[(j * RC + qq) * DC + dd];
-            if ((j < s.nup) == ups) {
-              ms += t0;
-              lx_s += t1;
+            const S cw = wrow(i, j, 1) * gu[(i * N + j) * 4 + 1 + a];
+            const S t0 = hb[(int64_t)j * Rp * D] * cw;
+            const S t1 = S(2) * cw * hb[((int64_t)j * Rp + q) * D];
+            if ((j < nup) == up) {
+              ms[r] += t0;
+              lxs[r] += t1;
             } else {
-              mo += t0;
-              lx_o += t1;
+              mo[r] += t0;
+              lxo[r] += t1;
             }
           }
         } else {
-          const S cw = wdl[(i * N + k) * DC + dd] * gu[(i * N + k) * 4 + 1 + a];
-          const S t0 = -h0s[k * DC + dd] * cw;
-          const S t1 = S(-2) * cw * hs[(k * RC + qq) * DC + dd];
-          if ((k < s.nup) == ups) {
-            ms += t0;
-            lx_s += t1;
+          // d(d_ik)/dr_k = -u_ik: only sender k moves with this coordinate
+          const S cw = cwp[r] * gu[(i * N + k) * 4 + 1 + a];
+          const S t0 = -ch0 * cw;
+          const S t1 = S(-2) * cw * chq;
+          if ((k < nup) == up) {
+            ms[r] += t0;
+            lxs[r] += t1;
           } else {
-            mo += t0;
-            lx_o += t1;
+            mo[r] += t0;
+            lxo[r] += t1;
           }
         }
-      } else if (q == s.T + 1) {
-#pragma unroll
-        for (int j = 0; j < NMAX; ++j) {
-          if (j < N) {
-            const S t = h0s[j * DC + dd] * lw[j];
-            if ((j < s.nup) == ups)
-              ms += t;
-            else
-              mo += t;
-          }
-        }
-        ms += lx_s;
-        mo += lx_o;
       }
-      S* row = mrow + (int64_t)q * 2 * D;
-      row[0] = ms * inv_s;
-      row[D] = mo * inv_o;
+      if (++a == 3) {
+        a = 0;
+        ++k;
+      }
+    } else if (q == T + 1) {
+#pragma unroll
+      for (int r = 0; r < RG; ++r) {
+        if (r >= cnt) continue;
+        const int i = i0 + r;
+#pragma unroll 4
+        for (int j = 0; j < N; ++j) {
+          if (j == i) continue;
+          const S t = hb[(int64_t)j * Rp * D] * (S(2) * wrow(i, j, 2) + S(4) * wrow(i, j, 1) / gu[(i * N + j) * 4]);
+          if ((j < nup) == up)
+            ms[r] += t;
+          else
+            mo[r] += t;
+        }
+        ms[r] += lxs[r];
+        mo[r] += lxo[r];
+      }
     }
+#pragma unroll
+    for (int r = 0; r < RG; ++r)
+      if (r < cnt) {
+        S* o = mb + ((int64_t)(i0 + r) * Rp + q) * 2 * D;
+        o[0] = ms[r] * inv_s;
+        o[D] = mo[r] * inv_o;
+      }
+#pragma unroll
+    for (int sl = 0; sl < 2 * NS; ++sl) hv[sl] = nv[sl];
+#pragma unroll
+    for (int r = 0; r < RG; ++r) cwp[r] = nwp[r];
+    ch0 = nh0;
+    chq = nhq;
   }
+  // padding rows
+  for (int q = T + 2; q < Rp; ++q)
+#pragma unroll
+    for (int r = 0; r < RG; ++r)
+      if (r < cnt) {
+        S* o = mb + ((int64_t)(i0 + r) * Rp + q) * 2 * D;
+        o[0] = 0;
+        o[D] = 0;
+      }
 }
 
 // Nuclear messages with jets.  m_nuc_i = mean_I w_nuc(d_iI) Y_I depends on r_i
@@ -503,20 +546,27 @@ __global__ __launch_bounds__(256) void aggregate_value_kernel(SysDev s, const S*
   }
 }
 
-template <typename S, int NMAX>
+template <typename S, int NS>
 static hipError_t agg_launch(const SysDev& s, const S* h, const S* ws, const S* wo, const double* ee, int64_t W, S* m,
                              hipStream_t st) {
-  const int RC = 16;
-  int DC = 1;
-  while (DC < s.D && DC < 64) DC <<= 1;
-  auto lds = [&](int dc) {
-    return (size_t)(NMAX * RC * dc + s.N * s.N * dc + s.N * dc + s.N * s.N * 4) * sizeof(S);
-  };
-  const int max_threads = NMAX >= 32 ? 256 : 512;
-  while (DC > 1 && (DC * s.N > max_threads || lds(DC) > 64 * 1024)) DC >>= 1;
+  constexpr int RG = (NS <= 8 && sizeof(S) == 4) ? 2 : 1;  // receivers per thread (register budget)
+  const int ngroups = (s.nup + RG - 1) / RG + (s.ndn + RG - 1) / RG;
+  // columns per block: the largest power of two up to 64 with all groups in at most 512 threads
+  int DC = 64;
+  while (DC > 1 && (DC >= 2 * s.D || DC * ngroups > 512)) DC >>= 1;
+  const int nch = (s.D + DC - 1) / DC;
+  const size_t lds = (size_t)s.N * s.N * 4 * sizeof(S) + (size_t)s.N * s.N * sizeof(int);
+  static size_t lds_set = 0;
+  if (lds > 64 * 1024 && lds > lds_set) {
+    if (hipFuncSetAttribute((const void*)aggregate_kernel<S, NS, RG>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)lds) != hipSuccess)
+      return hipErrorInvalidValue;
+    lds_set = lds;
+  }
   ProfScope ps("aggregate_kernel", st);
-  dim3 grid((unsigned)W, (unsigned)((s.D + DC - 1) / DC));
-  hipLaunchKernelGGL((aggregate_kernel<S, NMAX>), grid, dim3(DC * s.N), lds(DC), st, s, h, ws, wo, ee, DC, RC, m);
+  // blocks of one walker are adjacent, so they run together and share its rows in L2
+  hipLaunchKernelGGL((aggregate_kernel<S, NS, RG>), dim3((unsigned)(W * nch)), dim3(DC * ngroups), lds, st, s, h, ws,
+                     wo, ee, DC, nch, m);
   return hipGetLastError();
 }
 
@@ -533,11 +583,12 @@ hipError_t launch_aggregate(const SysDev& s, const S* h, const S* wsame, const S
                        wsame, wopp, wnuc, Y, stage, m);
     return hipGetLastError();
   }
-  if (s.N <= 4) return agg_launch<S, 4>(s, h, wsame, wopp, ee, W, m, st);
-  if (s.N <= 8) return agg_launch<S, 8>(s, h, wsame, wopp, ee, W, m, st);
-  if (s.N <= 16) return agg_launch<S, 16>(s, h, wsame, wopp, ee, W, m, st);
-  if (s.N <= 32) return agg_launch<S, 32>(s, h, wsame, wopp, ee, W, m, st);
-  if (s.N <= 48) return agg_launch<S, 48>(s, h, wsame, wopp, ee, W, m, st);
+  // template on the larger spin block
+  const int ns = std::max(s.nup, s.ndn);
+  if (ns <= 4) return agg_launch<S, 4>(s, h, wsame, wopp, ee, W, m, st);
+  if (ns <= 8) return agg_launch<S, 8>(s, h, wsame, wopp, ee, W, m, st);
+  if (ns <= 16) return agg_launch<S, 16>(s, h, wsame, wopp, ee, W, m, st);
+  if (ns <= 24) return agg_launch<S, 24>(s, h, wsame, wopp, ee, W, m, st);
   return hipErrorInvalidValue;
 }
 
