@@ -6,6 +6,7 @@
 
 #include <mutex>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "kernels.h"
@@ -138,7 +139,9 @@ static qmc_status forward_chunk(const Plan& P, const SysPlan& s, const S* prm, c
   const ParamOffsets& O = s.off;
 
   CK(launch_geometry(dv, r, wc, ee, en, jet ? vpot : nullptr, st));
-  if (P.ans.mp_layers > 0)
+  // float32 plans of width 128 evaluate each edge filter in one fused kernel from the distances
+  const bool fused = std::is_same<S, float>::value && P.prec == QMC_FP32 && edge_mlp_supported(dv);
+  if (P.ans.mp_layers > 0 && !fused)
     for (int t = 0; t < 3; ++t) CK(launch_rbf<S>(dv, t, ee, en, wc, jet, rho[t], st));
   CK(launch_init_features<S>(dv, ee, en, wc, jet, x0, st));
   const int64_t rows = wc * N * Rp;
@@ -156,6 +159,14 @@ static qmc_status forward_chunk(const Plan& P, const SysPlan& s, const S* prm, c
     for (int t = 0; t < 3; ++t) {
       const int64_t re = wc * s.P[t] * Re;
       if (re == 0) continue;
+      if constexpr (std::is_same<S, float>::value) {
+        if (fused) {
+          EdgeMlpArgs ea{prm + Ly.U1[t], prm + Ly.a1[t], prm + Ly.U2[t], prm + Ly.a2[t], ee, en, wj[t], nullptr,
+                         wc * s.P[t], t, jet};
+          CK(launch_edge_mlp(dv, ea, st));
+          continue;
+        }
+      }
       CK(gemm(s, gk, dense(rho[t], K, prm + Ly.U1[t], D, prm + Ly.a1[t], ehid[t], D, re, (int)K, (int)D, Re, 1, 1, vm),
                      st));
       CK(gemm(s, gk, dense(ehid[t], D, prm + Ly.U2[t], D, prm + Ly.a2[t], wj[t], D, re, (int)D, (int)D, Re, 1, 0, vm),
@@ -349,6 +360,14 @@ static qmc_status forward_stash(const Plan& P, const SysPlan& s, const S* prm, c
       if (re == 0) continue;
       S* eh = F_(B.ehid[t], B.blk_e[t], l);
       S* wv = F_(B.wv[t], B.blk_e[t], l);
+      if constexpr (std::is_same<S, float>::value) {
+        if (P.prec == QMC_FP32 && edge_mlp_supported(dv)) {
+          // the hidden layer is kept for the backward
+          EdgeMlpArgs ea{prm + Ly.U1[t], prm + Ly.a1[t], prm + Ly.U2[t], prm + Ly.a2[t], ee, en, wv, eh, re, t, 0};
+          CK(launch_edge_mlp(dv, ea, st));
+          continue;
+        }
+      }
       CK(gemm(s, gk, dense((S*)(ws + B.rho[t]), K, prm + Ly.U1[t], D, prm + Ly.a1[t], eh, D, re, (int)K, (int)D, 1,
                                0, 1, 1), st));
       CK(gemm(s, gk, dense(eh, D, prm + Ly.U2[t], D, prm + Ly.a2[t], wv, D, re, (int)D, (int)D, 1, 0, 0, 1), st));

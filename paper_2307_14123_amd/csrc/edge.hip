@@ -1,0 +1,170 @@
+// Fused edge filters on MFMA (float32, width 128, at most 16 radial basis
+// functions): for every pair of one edge type,
+//   w(d) = tanh(rho(d) U1 + a1) U2 + a2,
+// from the pair distance to the filter row in one kernel, as a value row or
+// as a univariate jet in d (rows value, first and second derivative, zero).
+//
+// The first layer is computed transposed, Z^T = U1^T rho^T (+ a1 through a
+// constant basis function on the value row), so that each lane's accumulator
+// (rows 4*(l/16)+i, column l%16 of the 16x16 tile) holds the hidden units
+// 16*hb + 4*(l/16) + i of pair row l%16: exactly the A-operand slice the
+// second layer's MFMA wants from that lane (row l%16, k = 4*(l/16) + step).
+// The hidden layer never leaves the registers.  For jets the tanh is
+// propagated across the four rows of a pair (lanes 4p'..4p'+3 of a 16-lane
+// group) with quad shuffles: t = tanh(z0), t' z1, t' z2 + t'' z1^2.
+//
+// A persistent grid keeps U2 (transposed, 16-byte chunks XOR-swizzled by row
+// against LDS bank conflicts) and U1, a1, a2 in LDS; each wave takes 16 pair
+// rows at a time.  The radial basis is evaluated in float64 and rounded, as
+// in the separate basis kernel.
+#include <algorithm>
+
+#include "kernels.h"
+#include "pairs.h"
+
+namespace qmc {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+constexpr int ED = 128;  // filter width handled here
+
+template <int JET>
+__global__ __launch_bounds__(256) void edge_mlp_kernel(SysDev s, EdgeMlpArgs a) {
+  __shared__ __attribute__((aligned(16))) float u2t[ED * ED];  // U2^T (n, k), chunk (k/4) ^ (n & 7)
+  __shared__ __attribute__((aligned(16))) float u1t[ED * 16];  // U1^T (k, r), r < 16
+  __shared__ float a1s[ED], a2s[ED];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int g = lane >> 4, c = lane & 15;
+  const int K = s.K;
+  for (int e = tid; e < ED * ED; e += 256) {
+    const int k = e / ED, n = e - k * ED;
+    u2t[n * ED + (((k >> 2) ^ (n & 7)) << 2) + (k & 3)] = a.U2[e];
+  }
+  for (int e = tid; e < ED * 16; e += 256) {
+    const int k = e >> 4, r = e & 15;
+    u1t[e] = r < K ? a.U1[r * ED + k] : 0.f;
+  }
+  for (int e = tid; e < ED; e += 256) {
+    a1s[e] = a.a1[e];
+    a2s[e] = a.a2[e];
+  }
+  __syncthreads();
+
+  const int P = a.type == 0 ? s.P0 : (a.type == 1 ? s.P1 : s.P2);
+  const int64_t rows = JET ? a.pairs * 4 : a.pairs;
+  const int64_t ntiles = (rows + 15) / 16;
+  for (int64_t tile = (int64_t)blockIdx.x * 4 + wave; tile < ntiles; tile += (int64_t)gridDim.x * 4) {
+    const int64_t row0 = tile * 16;
+    // ---- this lane's pair row (column c of the first layer)
+    const int64_t row = row0 + c;
+    const int e = JET ? (int)(row & 3) : 0;
+    float rb[4] = {0.f, 0.f, 0.f, 0.f};
+    if (row < rows && e < 3) {
+      const int64_t pr = JET ? row >> 2 : row;
+      const int64_t w = pr / P;
+      const int pi = (int)(pr - w * P);
+      int i, j;
+      decode_pair(s, a.type, pi, i, j);
+      const double d = a.type == 2 ? a.en[((w * s.N + i) * s.M + j) * 4] : a.ee[((w * s.N + i) * s.N + j) * 4];
+#pragma unroll
+      for (int kq = 0; kq < 4; ++kq) {
+        const int r = 4 * g + kq;
+        if (r < K) {
+          double r0, r1, r2;
+          rbf3(d, r, s.dmax, K, r0, r1, r2);
+          rb[kq] = (float)(e == 0 ? r0 : (e == 1 ? r1 : r2));
+        }
+      }
+    }
+    const float bias_in = (g == 0 && e == 0) ? 1.f : 0.f;  // constant basis function of the value row
+    // ---- first layer: z^T blocks of 16 hidden units
+    f4 z[ED / 16];
+#pragma unroll
+    for (int hb = 0; hb < ED / 16; ++hb) {
+      f4 acc = {0.f, 0.f, 0.f, 0.f};
+      const f4 ua = *(const f4*)&u1t[(16 * hb + c) * 16 + 4 * g];
+      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(ua.x, rb[0], acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(ua.y, rb[1], acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(ua.z, rb[2], acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(ua.w, rb[3], acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(g == 0 ? a1s[16 * hb + c] : 0.f, bias_in, acc, 0, 0, 0);
+      z[hb] = acc;
+    }
+    // ---- tanh (through the jet of a pair's four rows)
+    const int qbase = (lane & ~3);  // lane of row 0 of this lane's pair (same 16-lane group)
+#pragma unroll
+    for (int hb = 0; hb < ED / 16; ++hb)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const float zi = z[hb][i];
+        if constexpr (JET) {
+          const float z0 = __shfl(zi, qbase), z1 = __shfl(zi, qbase + 1), z2 = __shfl(zi, qbase + 2);
+          const float t = tanhf(z0), t1 = 1.f - t * t, t2 = -2.f * t * t1;
+          z[hb][i] = e == 0 ? t : (e == 1 ? t1 * z1 : (e == 2 ? t1 * z2 + t2 * z1 * z1 : 0.f));
+        } else {
+          z[hb][i] = tanhf(zi);
+        }
+      }
+    if (!JET && a.zout && row < rows) {
+#pragma unroll
+      for (int hb = 0; hb < ED / 16; ++hb) *(f4*)&a.zout[row * ED + 16 * hb + 4 * g] = z[hb];
+    }
+    // ---- second layer, two 16-column blocks at a time
+#pragma unroll 1
+    for (int nb = 0; nb < ED / 16; nb += 2) {
+      f4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+      const int n0 = 16 * nb + c, n1 = n0 + 16;
+#pragma unroll
+      for (int hb = 0; hb < ED / 16; ++hb) {
+        const int ch = 4 * hb + g;
+        const f4 b0 = *(const f4*)&u2t[n0 * ED + ((ch ^ (n0 & 7)) << 2)];
+        const f4 b1 = *(const f4*)&u2t[n1 * ED + ((ch ^ (n1 & 7)) << 2)];
+        acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(z[hb][0], b0.x, acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(z[hb][0], b1.x, acc1, 0, 0, 0);
+        acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(z[hb][1], b0.y, acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(z[hb][1], b1.y, acc1, 0, 0, 0);
+        acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(z[hb][2], b0.z, acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(z[hb][2], b1.z, acc1, 0, 0, 0);
+        acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(z[hb][3], b0.w, acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(z[hb][3], b1.w, acc1, 0, 0, 0);
+      }
+      // lane holds output rows row0 + 4g + i, columns n0 / n1; a2 goes to value rows only
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int64_t orow = row0 + 4 * g + i;
+        if (orow >= rows) continue;
+        const bool vrow = !JET || i == 0;  // row0 is a multiple of 4: row 4g + i of a jet is entry i
+        a.out[orow * ED + n0] = acc0[i] + (vrow ? a2s[n0] : 0.f);
+        a.out[orow * ED + n1] = acc1[i] + (vrow ? a2s[n1] : 0.f);
+      }
+    }
+  }
+}
+
+bool edge_mlp_supported(const SysDev& s) { return s.D == ED && s.K >= 2 && s.K <= 16; }
+
+hipError_t launch_edge_mlp(const SysDev& s, const EdgeMlpArgs& a, hipStream_t st) {
+  if (!edge_mlp_supported(s) || a.pairs < 0 || a.type < 0 || a.type > 2) return hipErrorInvalidValue;
+  if (a.pairs == 0) return hipSuccess;
+  if (a.jet && a.zout) return hipErrorInvalidValue;
+  static int cus = 0;
+  if (cus == 0) {
+    int dev = 0, n = 0;
+    cus = (hipGetDevice(&dev) == hipSuccess &&
+           hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && n > 0)
+              ? n
+              : 256;
+  }
+  const int64_t rows = a.jet ? a.pairs * 4 : a.pairs;
+  const int64_t tiles = (rows + 15) / 16;
+  // two blocks (73 KB of LDS each) per compute unit, each walking tiles with a grid stride
+  const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>((tiles + 3) / 4, 2 * (int64_t)cus));
+  ProfScope ps(a.jet ? "edge_mlp_kernel<jet>" : "edge_mlp_kernel<val>", st);
+  if (a.jet)
+    hipLaunchKernelGGL(edge_mlp_kernel<1>, dim3((unsigned)blocks), dim3(256), 0, st, s, a);
+  else
+    hipLaunchKernelGGL(edge_mlp_kernel<0>, dim3((unsigned)blocks), dim3(256), 0, st, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace qmc

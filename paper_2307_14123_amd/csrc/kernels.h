@@ -70,6 +70,20 @@ struct SysDev {
   double R[64 * 3];
 };
 
+// Fused edge filters w(d) = tanh(rho(d) U1 + a1) U2 + a2 on MFMA (float32, width 128, at most 16
+// basis functions) for every pair of one edge type, from the geometry to the filter rows.
+struct EdgeMlpArgs {
+  const float *U1, *a1, *U2, *a2;
+  const double *ee, *en;  // geometry of the walker chunk (layouts as launch_geometry writes them)
+  float* out;             // [pairs][D] value rows, or [pairs][4][D] univariate jets
+  float* zout;            // optional, value rows only: the hidden layer tanh(rho U1 + a1), [pairs][D]
+  int64_t pairs;          // walkers x pairs of this type
+  int type;               // 0 same-spin, 1 up-down, 2 electron-nucleus
+  int jet;
+};
+bool edge_mlp_supported(const SysDev& s);
+hipError_t launch_edge_mlp(const SysDev& s, const EdgeMlpArgs& a, hipStream_t st);
+
 hipError_t launch_geometry(const SysDev& s, const double* r, int64_t W, double* ee, double* en,
                            double* vpot, hipStream_t st);
 

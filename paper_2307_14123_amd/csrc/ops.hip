@@ -12,65 +12,11 @@
 #include <algorithm>
 
 #include "kernels.h"
+#include "pairs.h"
 
 namespace qmc {
 
-// ---------------------------------------------------------------- helpers
-
-__device__ inline void rbf3(double d, int k, double dmax, int K, double& r0, double& r1, double& r2) {
-  const double s = dmax / (K - 1);
-  const double x = (d - k * s) / s;
-  r0 = exp(-x * x);
-  r1 = -2.0 * x / s * r0;
-  r2 = (4.0 * x * x - 2.0) / (s * s) * r0;
-}
-
-// unordered pair index of electrons i != j inside their edge type (0 same-spin, 1 up-down)
-__device__ inline int ee_pair(const SysDev& s, int i, int j, int& type) {
-  const bool ui = i < s.nup, uj = j < s.nup;
-  if (ui != uj) {
-    type = 1;
-    const int a = ui ? i : j, b = ui ? j : i;
-    return a * s.ndn + (b - s.nup);
-  }
-  type = 0;
-  int a = i < j ? i : j, b = i < j ? j : i;
-  int n = s.nup, off = 0;
-  if (!ui) {
-    n = s.ndn;
-    a -= s.nup;
-    b -= s.nup;
-    off = s.nup * (s.nup - 1) / 2;
-  }
-  return off + a * (2 * n - a - 1) / 2 + (b - a - 1);
-}
-
-__device__ inline void decode_pair(const SysDev& s, int type, int p, int& i, int& j) {
-  if (type == 2) {
-    i = p / s.M;
-    j = p % s.M;
-    return;
-  }
-  if (type == 1) {
-    i = p / s.ndn;
-    j = s.nup + p % s.ndn;
-    return;
-  }
-  int n = s.nup, base = 0;
-  const int cu = s.nup * (s.nup - 1) / 2;
-  if (p >= cu) {
-    p -= cu;
-    n = s.ndn;
-    base = s.nup;
-  }
-  int a = 0;
-  while (p >= n - 1 - a) {
-    p -= n - 1 - a;
-    ++a;
-  }
-  i = base + a;
-  j = base + a + 1 + p;
-}
+// pair helpers (radial basis, pair indexing) live in pairs.h
 
 // ---------------------------------------------------------------- geometry
 

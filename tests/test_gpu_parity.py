@@ -182,6 +182,25 @@ def test_logpsi_value_mode_matches_jets():
     assert np.all(host(sg) == ref_s)
 
 
+def test_fp32_value_mode_logpsi():
+    """float32 value rows (fused edge filters, Metropolis proposals): log|psi| against the oracle on
+    the float32-rounded parameters, and against the float32 jet path's value row."""
+    s, a, p, r = qi.workload_inputs(1, 48)
+    q = _q()
+    plan = q.Plan([s], [48], a, "fp32")
+    P = dev(p, torch.float32)
+    lp, sg = plan.logpsi(P, dev(r))
+    le = plan.local_energy(P, dev(r))
+    torch.cuda.synchronize()
+    ref_s, ref_l = oracle.logpsi_np(r, p.astype(np.float32).astype(np.float64), s, a)
+    ok = ~flagged(r, p, s, a)
+    e_or = np.abs(host(lp) - ref_l)[ok]
+    e_jet = np.abs(host(lp) - host(le["logpsi"]))[ok]
+    print(f"[fp32 value logpsi] max |dlogpsi| vs oracle {e_or.max():.3e}, vs jet path {e_jet.max():.3e}", flush=True)
+    assert np.all(host(sg)[ok] == ref_s[ok])
+    assert e_or.max() < 2e-4 and e_jet.max() < 2e-4
+
+
 def test_det_stage_on_hydrogenic_jets():
     """Determinant kernel fed analytic orbital jets (oracle autograd): the
     non-interacting kinetic + e-n energy is the constant -sum Z^2/(2 n^2)."""
