@@ -30,13 +30,15 @@ sys.path.insert(0, ROOT)
 PEAK = {"fp32_mfma": 157.3e12, "fp64_mfma": 78.6e12, "bf16_mfma": 2.5e15, "hbm": 8.0e12}
 
 
-def algorithmic_model(s, a, elem_bytes, n_mc, with_grad):
-    """Algorithmic work of one bench step per kernel name (FLOP or bytes summed
-    over all launches of that kernel in the step), without padding rows or
+def algorithmic_model(s, a, elem_bytes, n_mc, with_grad, fused_edges):
+    """Algorithmic work of one bench step per kernel family (FLOP or bytes summed
+    over all launches of that family in the step), without padding rows or
     structurally zero rows.
 
     Jets carry R1 = 3N + 2 rows per electron (value, 3N tangents, Laplacian);
-    edge filters carry 3 rows per pair (value, first and second derivative)."""
+    edge filters carry 3 rows per pair (value, first and second derivative).
+    fused_edges: the edge filters run in edge_mlp_kernel (float32, width 128)
+    instead of two GEMM launches each."""
     N, M, K, D, L, L0, nd = s.n_elec, s.n_nuc, a.n_rbf, a.width, a.mp_layers, a.init_layers, a.n_det
     T = 3 * N
     R1 = T + 2
@@ -51,23 +53,57 @@ def algorithmic_model(s, a, elem_bytes, n_mc, with_grad):
                 + 2 * R1 * D * nd * nsq)
     edge_jet = L * sum(P) * 3 * 2 * (K * D + D * D)
     # value rows: one log|psi| (Metropolis proposal, stashed forward of the backward)
-    val_fwd = (2 * N * ((M + 2) * K * D + (L0 - 1) * D * D) + L * (2 * N * 4 * D * D + sum(P) * 2 * (K * D + D * D))
-               + 2 * D * nd * nsq)
+    node_val = 2 * N * ((M + 2) * K * D + (L0 - 1) * D * D) + L * 2 * N * 4 * D * D + 2 * D * nd * nsq
+    edge_val = L * sum(P) * 2 * (K * D + D * D)
     # data cotangents of the backward (x_bar = y_bar W^T), weight gradients (W_bar = x^T y_bar)
     val_bwd = 2 * D * nd * nsq + L * (2 * N * 3 * D * D + 2 * N * D * D + sum(P) * 2 * D * D) + (L0 - 1) * 2 * N * D * D
-    wgrad = val_fwd
+    wgrad = node_val + edge_val
     n_val = n_mc + (1 if with_grad else 0)
     m = {
         "gemm_kernel<jet>": ("mfma", node_jet),
-        "gemm_kernel<edge>": ("mfma", edge_jet),
-        "gemm_kernel<val>": ("mfma", n_val * val_fwd + (val_bwd if with_grad else 0)),
+        "gemm_kernel<val>": ("mfma", n_val * node_val + (0 if fused_edges else n_val * edge_val)
+                             + (val_bwd if with_grad else 0)),
         "wgrad_kernel": ("mfma", wgrad if with_grad else 0),
         # HBM-bound kernels: bytes of jets read and written
         "aggregate_kernel": ("hbm", L * eb * (N * R1 * D + N * R1 * 2 * D + (P[0] + P[1]) * 3 * D)),
         "det_kernel": ("hbm", eb * nd * R1 * nsq + 8 * 2 * nd * (T + 3)),
         "envelope_kernel": ("hbm", 2 * eb * nd * R1 * nsq),
     }
+    if fused_edges:
+        m["edge_mlp_kernel<jet>"] = ("mfma", edge_jet)
+        m["edge_mlp_kernel<val>"] = ("mfma", n_val * edge_val)
+    else:
+        m["gemm_kernel<edge>"] = ("mfma", edge_jet)
     return m
+
+
+# source file of each kernel family (a stored traffic measurement is used only while it is unchanged)
+FAMILY_SOURCE = {"gemm_kernel": "gemm.hip", "edge_mlp_kernel": "edge.hip", "aggregate_kernel": "ops.hip",
+                 "det_kernel": "ops.hip", "envelope_kernel": "ops.hip", "wgrad_kernel": "backward.hip"}
+
+
+def stored_traffic(family, workload, precision):
+    """HBM bytes per launch of a kernel family from a committed counter summary
+    (profiles/traffic_<family>_<workload>_<precision>.txt, FETCH_SIZE and
+    WRITE_SIZE scaled by a plain copy of known size), or None when there is none
+    or the family's source changed since the counters were taken."""
+    import hashlib
+    tag = family.replace("<", "_").replace(">", "")
+    path = os.path.join(ROOT, "profiles", f"traffic_{tag}_{workload}_{precision}.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if ":" in line:
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    src = os.path.join(ROOT, "paper_2307_14123_amd", "csrc", FAMILY_SOURCE.get(family.split("<")[0], ""))
+    if not os.path.isfile(src) or kv.get("source_sha256") != hashlib.sha256(open(src, "rb").read()).hexdigest():
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def kernel_family(name):
@@ -90,6 +126,8 @@ def main():
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64", "bf16"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-walkers", type=int, default=96)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="end with a plain 256 MiB device copy, the reference for traffic counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (walkers would be sharded "
@@ -167,7 +205,8 @@ def main():
     ms_le = (time.perf_counter() - t0) * 1e3 / reps
 
     eb = 8 if args.precision == "fp64" else 4
-    model = algorithmic_model(s, a, eb, n_mc, has_grad)
+    fused = args.precision == "fp32" and a.width == 128 and a.n_rbf <= 16
+    model = algorithmic_model(s, a, eb, n_mc, has_grad, fused)
     fam = {}
     for k, (nl, ms) in prof.items():
         f = kernel_family(k)
@@ -188,7 +227,7 @@ def main():
         else:
             roof = {"bound": "hbm", "achieved": per_launch / avg_s / 1e9, "peak": PEAK["hbm"] / 1e9, "unit": "GB/s"}
         roof["frac"] = roof["achieved"] / roof["peak"]
-        roof["traffic"] = None
+        roof["traffic"] = stored_traffic(name, args.workload, args.precision)
         roof["kernel"] = name
         roof["launches_per_step"] = nl / args.steps
         roof["avg_launch_ms"] = tot_ms / nl
@@ -254,6 +293,12 @@ def main():
         err = np.abs(o2["e_loc"].cpu().numpy() - ref["e_loc"]) * 1e3
         res["e_loc_err_mha_vs_fp64_oracle"] = {"p50": float(np.median(err)), "p99": float(np.percentile(err, 99)),
                                                "max": float(err.max()), "walkers": nw}
+    if args.copy_calibration:
+        x = torch.ones(64 << 20, dtype=torch.float32, device=dev)
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        y.copy_(x)
+        torch.cuda.synchronize()
     print(json.dumps(res))
 
 

@@ -1,0 +1,138 @@
+"""Summaries of rocprofv3 output for the kernels of this library.
+
+  python -m paper_2307_14123_amd.profiling stats <kernel_stats.csv> --command "<cmd>" --out <file.md>
+      per-kernel launch counts and durations (from --kernel-trace --stats, csv output),
+      grouped by the families bench.py reports
+  python -m paper_2307_14123_amd.profiling traffic <fetch dir> <write dir> --family "gemm_kernel<jet>"
+      --source <csrc file> --command "<cmd>" --out <file.txt>
+      HBM bytes per launch of one kernel family from a FETCH_SIZE run and a WRITE_SIZE run,
+      each scaled by what the same counter reads for the plain device copy in the same run
+      (bench.py --copy-calibration copies 256 MiB)
+
+Only reads CSV files; nothing here touches the GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import collections
+import csv
+import glob
+import hashlib
+import os
+import re
+
+COPY_BYTES = 256 << 20
+
+
+def family(kernel_name: str) -> str:
+    """bench.py's family of a demangled kernel name ('qmc::gemm_kernel<1, 6, 2, 16, false>(...)')."""
+    base = kernel_name.split("(")[0].replace("void ", "").strip()
+    base = base.split("::")[-1] if base.startswith("qmc::") else base
+    m = re.match(r"(\w+)<(.*)>$", base)
+    if not m:
+        return base
+    name, targs = m.group(1), [t.strip() for t in m.group(2).split(",")]
+    if name == "gemm_kernel" and len(targs) >= 3:
+        return "gemm_kernel<" + {"0": "val", "1": "edge", "2": "jet"}.get(targs[2], targs[2]) + ">"
+    if name == "edge_mlp_kernel":
+        return "edge_mlp_kernel<" + ("jet" if targs[0] == "1" else "val") + ">"
+    if name == "wgrad_kernel":
+        return "wgrad_kernel"
+    return name
+
+
+def stats(path: str, command: str) -> str:
+    rows = list(csv.DictReader(open(path)))
+    out = ["# Kernel time summary", "", "Command (run from the repository root):", "", "    " + command, "",
+           "| kernel | family | launches | total ms | average us | share |", "|---|---|---|---|---|---|"]
+    tot = sum(float(r["TotalDurationNs"]) for r in rows)
+    fam = collections.defaultdict(lambda: [0, 0.0])
+    for r in sorted(rows, key=lambda r: -float(r["TotalDurationNs"]))[:30]:
+        f = family(r["Name"])
+        n, t = int(r["Calls"]), float(r["TotalDurationNs"])
+        out.append(f"| `{r['Name'].split('(')[0][:70]}` | {f} | {n} | {t / 1e6:.3f} | {t / n / 1e3:.1f} | "
+                   f"{100 * t / tot:.1f}% |")
+    for r in rows:
+        f = family(r["Name"])
+        fam[f][0] += int(r["Calls"])
+        fam[f][1] += float(r["TotalDurationNs"])
+    out += ["", "| family | launches | total ms | average us |", "|---|---|---|---|"]
+    for f, (n, t) in sorted(fam.items(), key=lambda kv: -kv[1][1])[:15]:
+        out.append(f"| {f} | {n} | {t / 1e6:.3f} | {t / n / 1e3:.1f} |")
+    return "\n".join(out) + "\n"
+
+
+def _counter(d: str, counter: str):
+    per = collections.defaultdict(lambda: collections.defaultdict(float))
+    for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+        for r in csv.DictReader(open(f)):
+            if r["Counter_Name"] == counter:
+                per[r["Kernel_Name"]][r["Dispatch_Id"]] += float(r["Counter_Value"])
+    return per
+
+
+def traffic(fetch_dir: str, write_dir: str, fam: str, source: str, command: str) -> str:
+    fetch, write = _counter(fetch_dir, "FETCH_SIZE"), _counter(write_dir, "WRITE_SIZE")
+
+    def copy_kib(per):
+        vals = [v for k, d in per.items() if "copyBuffer" in k for v in d.values()]
+        if not vals:
+            raise SystemExit("no device copy in the counter run (use bench.py --copy-calibration)")
+        return max(vals)
+
+    def fam_kib(per):
+        vals = [v for k, d in per.items() if family(k) == fam for v in d.values()]
+        if not vals:
+            raise SystemExit(f"no launch of {fam} in the counter run")
+        return sum(vals) / len(vals), len(vals)
+
+    sf = COPY_BYTES / (copy_kib(fetch) * 1024.0)
+    sw = COPY_BYTES / (copy_kib(write) * 1024.0)
+    f_kib, nf = fam_kib(fetch)
+    w_kib, nw = fam_kib(write)
+    bytes_per_launch = f_kib * 1024.0 * sf + w_kib * 1024.0 * sw
+    sha = hashlib.sha256(open(source, "rb").read()).hexdigest()
+    lines = [
+        f"# HBM traffic of {fam}",
+        "command: " + command,
+        f"kernel_family: {fam}",
+        f"source: {os.path.relpath(source)}",
+        f"source_sha256: {sha}",
+        f"launches: {nf}",
+        f"fetch_kib_per_launch_raw: {f_kib:.1f}",
+        f"write_kib_per_launch_raw: {w_kib:.1f}",
+        f"copy_fetch_scale: {sf:.4f}",
+        f"copy_write_scale: {sw:.4f}",
+        f"read_bytes_per_launch: {f_kib * 1024.0 * sf:.6g}",
+        f"write_bytes_per_launch: {w_kib * 1024.0 * sw:.6g}",
+        f"hbm_bytes_per_launch: {bytes_per_launch:.6g}",
+    ]
+    return "\n".join(lines) + "\n"
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    a1 = sub.add_parser("stats")
+    a1.add_argument("csv")
+    a1.add_argument("--command", required=True)
+    a1.add_argument("--out", required=True)
+    a2 = sub.add_parser("traffic")
+    a2.add_argument("fetch_dir")
+    a2.add_argument("write_dir")
+    a2.add_argument("--family", required=True)
+    a2.add_argument("--source", required=True)
+    a2.add_argument("--command", required=True)
+    a2.add_argument("--out", required=True)
+    args = ap.parse_args()
+    if args.cmd == "stats":
+        text = stats(args.csv, args.command)
+    else:
+        text = traffic(args.fetch_dir, args.write_dir, args.family, args.source, args.command)
+    with open(args.out, "w") as f:
+        f.write(text)
+    print(text)
+
+
+if __name__ == "__main__":
+    main()
