@@ -339,6 +339,8 @@ __global__ void orb_bwd_kernel(SysDev s, int spin, const double* __restrict__ lb
                                const S* __restrict__ phi, const S* __restrict__ pi, const S* __restrict__ sg,
                                const double* __restrict__ en, int64_t W, S* __restrict__ phibar,
                                double* __restrict__ pipart, double* __restrict__ sgpart) {
+  // envelope values in the plan's activation type (as in the forward); sums in float64
+  using T = S;
   const int n = spin ? s.ndn : s.nup;
   const int i0 = spin ? s.nup : 0;
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -347,37 +349,39 @@ __global__ void orb_bwd_kernel(SysDev s, int spin, const double* __restrict__ lb
   const int p = (int)((t / n) % s.ndet);
   const int64_t w = t / ((int64_t)n * s.ndet);
   const int ncol = s.ndet * n;
-  const int nenvM = s.M * s.nenv;
   const double lb = lbar[w * s.ndet + p];
   const double* Ai = ainv + ((w * s.ndet + p) * n) * (int64_t)n;  // [n][n]
-  double* pp = pipart + t * nenvM;
-  double* sp = sgpart + t * nenvM;
-  for (int e = 0; e < nenvM; ++e) {
-    pp[e] = 0.0;
-    sp[e] = 0.0;
-  }
+  const double* gw = en + (w * s.N + i0) * s.M * 4;                // electron a of this spin: gw + a * M * 4
+  const S* phw = phi + (w * n) * (int64_t)ncol + p * n + k;        // row a: phw[a * ncol]
+  const S* pik = pi + ((int64_t)p * n + k) * s.M * s.nenv;
+  const S* sgk = sg + ((int64_t)p * n + k) * s.M * s.nenv;
+  // phi_bar = Abar * env, with Abar = lbar A^-T
   for (int a = 0; a < n; ++a) {
-    const int i = i0 + a;
-    const double Ab = lb * Ai[k * n + a];
-    const double* g = en + (w * s.N + i) * s.M * 4;
-    double env = 0.0;
-    for (int I = 0; I < s.M; ++I)
-      for (int b = 0; b < s.nenv; ++b) {
-        const int64_t idx = (((int64_t)p * n + k) * s.M + I) * s.nenv + b;
-        env += (double)pi[idx] * exp(-(double)sg[idx] * g[I * 4]);
-      }
-    const double ph = (double)phi[(w * n + a) * (int64_t)ncol + p * n + k];
-    phibar[(w * n + a) * (int64_t)ncol + p * n + k] = (S)(Ab * env);
-    const double eb = Ab * ph;
-    for (int I = 0; I < s.M; ++I)
-      for (int b = 0; b < s.nenv; ++b) {
-        const int64_t idx = (((int64_t)p * n + k) * s.M + I) * s.nenv + b;
-        const double d = g[I * 4];
-        const double ex = exp(-(double)sg[idx] * d);
-        pp[I * s.nenv + b] += eb * ex;
-        sp[I * s.nenv + b] -= eb * (double)pi[idx] * d * ex;
-      }
+    const double* g = gw + a * s.M * 4;
+    T env = 0;
+    for (int I = 0; I < s.M; ++I) {
+      const T d = (T)g[I * 4];
+      for (int b = 0; b < s.nenv; ++b) env += pik[I * s.nenv + b] * exp(-sgk[I * s.nenv + b] * d);
+    }
+    phibar[(w * n + a) * (int64_t)ncol + p * n + k] = (S)(lb * Ai[k * n + a] * (double)env);
   }
+  // pi_bar and sigma_bar of every (nucleus, exponent): sums over the electrons of the spin block
+  double* pp = pipart + t * (int64_t)(s.M * s.nenv);
+  double* sp = sgpart + t * (int64_t)(s.M * s.nenv);
+  for (int I = 0; I < s.M; ++I)
+    for (int b = 0; b < s.nenv; ++b) {
+      const T pw = pik[I * s.nenv + b], sgm = sgk[I * s.nenv + b];
+      double ap = 0.0, as = 0.0;
+      for (int a = 0; a < n; ++a) {
+        const T d = (T)gw[a * s.M * 4 + I * 4];
+        const double eb = lb * Ai[k * n + a] * (double)phw[(int64_t)a * ncol];
+        const double ex = (double)exp(-sgm * d);
+        ap += eb * ex;
+        as -= eb * (double)pw * (double)d * ex;
+      }
+      pp[I * s.nenv + b] = ap;
+      sp[I * s.nenv + b] = as;
+    }
 }
 
 template <typename S>

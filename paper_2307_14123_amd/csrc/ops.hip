@@ -546,6 +546,8 @@ template <typename S>
 __global__ void envelope_kernel(SysDev s, int spin, const S* __restrict__ phi, const S* __restrict__ pi,
                                 const S* __restrict__ sg, const double* __restrict__ en, int64_t W, int jet,
                                 S* __restrict__ ajet) {
+  // arithmetic in the plan's activation type (float64 only for the FP64 plan)
+  using T = S;
   const int n = spin ? s.ndn : s.nup;
   const int i0 = spin ? s.nup : 0;
   const int Rp = jet ? s.Rp : 1;
@@ -556,18 +558,19 @@ __global__ void envelope_kernel(SysDev s, int spin, const S* __restrict__ phi, c
   const int p = (int)((t / (n * n)) % s.ndet);
   const int64_t w = t / ((int64_t)n * n * s.ndet);
   const int i = i0 + a;
-  double e0 = 0, eg[3] = {0, 0, 0}, el = 0;
+  T e0 = 0, eg[3] = {0, 0, 0}, el = 0;
   const double* g = en + (w * s.N + i) * s.M * 4;
   for (int I = 0; I < s.M; ++I) {
-    const double d = g[I * 4];
+    const T d = (T)g[I * 4];
+    const T u[3] = {(T)g[I * 4 + 1], (T)g[I * 4 + 2], (T)g[I * 4 + 3]};
     for (int b = 0; b < s.nenv; ++b) {
       const int64_t idx = (((int64_t)p * n + k) * s.M + I) * s.nenv + b;
-      const double pw = (double)pi[idx], sgm = (double)sg[idx];
-      const double e = pw * exp(-sgm * d);
+      const T pw = pi[idx], sgm = sg[idx];
+      const T e = pw * exp(-sgm * d);
       e0 += e;
       if (jet) {
-        for (int x = 0; x < 3; ++x) eg[x] -= sgm * e * g[I * 4 + 1 + x];
-        el += e * (sgm * sgm - 2.0 * sgm / d);
+        for (int x = 0; x < 3; ++x) eg[x] -= sgm * e * u[x];
+        el += e * (sgm * sgm - T(2) * sgm / d);
       }
     }
   }
@@ -576,19 +579,19 @@ __global__ void envelope_kernel(SysDev s, int spin, const S* __restrict__ phi, c
   const int64_t wstride = (int64_t)s.ndet * Rp * (s.nup * s.nup + s.ndn * s.ndn);
   const int64_t soff = spin ? (int64_t)s.ndet * Rp * s.nup * s.nup : 0;
   S* out = ajet + w * wstride + soff + ((int64_t)p * Rp * n + a) * n + k;
-  const double p0 = (double)ph[0];
+  const T p0 = ph[0];
   out[0] = (S)(p0 * e0);
   if (!jet) return;
   const int64_t rs = (int64_t)n * n;
   for (int q = 1; q < Rp; ++q) {
-    double v = 0.0;
+    T v = 0;
     if (q <= s.T) {
-      v = (double)ph[(int64_t)q * ncol] * e0;
+      v = (T)ph[(int64_t)q * ncol] * e0;
       const int c = q - 1;
       if (c / 3 == i) v += p0 * eg[c % 3];
     } else if (q == s.T + 1) {
-      v = (double)ph[(int64_t)q * ncol] * e0 + p0 * el;
-      for (int x = 0; x < 3; ++x) v += 2.0 * (double)ph[(int64_t)(1 + 3 * i + x) * ncol] * eg[x];
+      v = (T)ph[(int64_t)q * ncol] * e0 + p0 * el;
+      for (int x = 0; x < 3; ++x) v += T(2) * (T)ph[(int64_t)(1 + 3 * i + x) * ncol] * eg[x];
     }
     out[q * rs] = (S)v;
   }
