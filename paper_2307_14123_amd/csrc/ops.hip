@@ -393,6 +393,150 @@ __global__ __launch_bounds__(512) void aggregate_kernel(SysDev s, const S* __res
       }
 }
 
+// The same messages for larger spin blocks (more than 8 electrons per spin):
+// one receiver per thread would fetch every sender row once per receiver, so
+// here the block stages RC rows of all senders (its column chunk) in LDS and
+// every receiver thread reads them from there.  Filter values stay in
+// registers in sender slots; the moving-sender correction of the next row is
+// fetched one row ahead.
+template <typename S, int NS, int RC>
+__global__ __launch_bounds__(512) void aggregate_lds_kernel(SysDev s, const S* __restrict__ h,
+                                                            const S* __restrict__ wsame, const S* __restrict__ wopp,
+                                                            const double* __restrict__ ee, int DC, int nch,
+                                                            S* __restrict__ m) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  constexpr int OPP = 1 << 30;
+  const int N = s.N, D = s.D, Rp = s.Rp, T = s.T, nup = s.nup, ndn = s.ndn;
+  const int64_t w = blockIdx.x / nch;
+  const int chunk = blockIdx.x - (int)(w * nch);
+  const int c0 = chunk * DC;
+  S* gu = (S*)smem;                     // [N][N][4]: d_ij, unit vector of r_i - r_j
+  S* hs = gu + N * N * 4;               // [RC][2NS][DC]: rows q0.. of every sender slot (zero if empty)
+  S* h0s = hs + RC * 2 * NS * DC;       // [2NS][DC]: value rows
+  int* pt = (int*)(h0s + 2 * NS * DC);  // [N][N]: pair index within its type, | OPP for an up-down pair
+  const int nt = blockDim.x;
+  const S* hw = h + w * N * (int64_t)Rp * D;  // h_j row q: hw[(j * Rp + q) * D + d]
+  auto sender = [&](int sl) { return sl < NS ? (sl < nup ? sl : -1) : (sl - NS < ndn ? nup + sl - NS : -1); };
+  auto slot_of = [&](int j) { return j < nup ? j : NS + (j - nup); };
+  for (int e = threadIdx.x; e < N * N * 4; e += nt) gu[e] = (S)ee[w * N * N * 4 + e];
+  for (int e = threadIdx.x; e < N * N; e += nt) {
+    const int i = e / N, j = e - (e / N) * N;
+    int v = 0;
+    if (i != j) {
+      int type;
+      const int p = ee_pair(s, i, j, type);
+      v = type ? (p | OPP) : p;
+    }
+    pt[e] = v;
+  }
+  for (int e = threadIdx.x; e < 2 * NS * DC; e += nt) {
+    const int sl = e / DC, x = e - (e / DC) * DC, j = sender(sl);
+    h0s[e] = (j >= 0 && c0 + x < D) ? hw[(int64_t)j * Rp * D + c0 + x] : S(0);
+  }
+  __syncthreads();
+  const int dd = threadIdx.x % DC, i = threadIdx.x / DC, d = min(c0 + dd, D - 1);
+  const bool active = c0 + dd < D && i < N;  // idle threads still stage rows and meet the barriers
+  const bool up = i < nup;
+  const int nsame = (up ? nup : ndn) - 1, nopp = up ? ndn : nup;
+  const S inv_s = nsame > 0 ? S(1) / S(nsame) : S(0), inv_o = nopp > 0 ? S(1) / S(nopp) : S(0);
+  auto wrow = [&](int ii, int j, int r) -> S {
+    const int v = pt[ii * N + j];
+    return (v & OPP) ? wopp[((w * s.P1 + (v & (OPP - 1))) * 4 + r) * (int64_t)D + d]
+                     : wsame[((w * s.P0 + v) * 4 + r) * (int64_t)D + d];
+  };
+  S wv[2 * NS];
+#pragma unroll
+  for (int sl = 0; sl < 2 * NS; ++sl) {
+    const int j = sender(sl);
+    wv[sl] = (active && j >= 0 && j != i) ? wrow(i, j, 0) : S(0);
+  }
+  S* mb = m + (w * N + min(i, N - 1)) * (int64_t)Rp * 2 * D + d;  // row q of receiver i: mb[q * 2D]
+  S lxs = 0, lxo = 0;
+  S cwp = 0;  // w'_ik of the moving sender of the current tangent row
+  int k = 0, a = 0;
+  for (int q0 = 0; q0 <= T + 1; q0 += RC) {
+    if (q0 > 0) __syncthreads();  // the previous rows are consumed
+    for (int e = threadIdx.x; e < RC * 2 * NS * DC; e += nt) {
+      const int x = e % DC, sq = e / DC, sl = sq % (2 * NS), qq = sq / (2 * NS), j = sender(sl);
+      hs[e] = (j >= 0 && q0 + qq <= T + 1 && c0 + x < D) ? hw[((int64_t)j * Rp + q0 + qq) * D + c0 + x] : S(0);
+    }
+    __syncthreads();
+    if (!active) continue;
+    const int qe = min(RC, T + 2 - q0);
+    for (int qq = 0; qq < qe; ++qq) {
+      const int q = q0 + qq;
+      // w'_ik for tangent row q + 1 (electron q / 3), fetched ahead
+      const int kn = q / 3;
+      const S nwp = (q + 1 <= T && kn != i) ? wrow(i, kn, 1) : S(0);
+      const S* hq = hs + qq * 2 * NS * DC + dd;  // sender slot sl of row q: hq[sl * DC]
+      S au = 0, ad = 0;
+#pragma unroll
+      for (int sl = 0; sl < NS; ++sl) {
+        au += wv[sl] * hq[sl * DC];
+        ad += wv[NS + sl] * hq[(NS + sl) * DC];
+      }
+      S ms = up ? au : ad, mo = up ? ad : au;
+      if (q >= 1 && q <= T) {
+        if (k == i) {
+          // d(d_ij)/dr_i = u_ij for every sender j
+#pragma unroll 4
+          for (int j = 0; j < N; ++j) {
+            if (j == i) continue;
+            const S cw = wrow(i, j, 1) * gu[(i * N + j) * 4 + 1 + a];
+            const S t0 = h0s[slot_of(j) * DC + dd] * cw;
+            const S t1 = S(2) * cw * hq[slot_of(j) * DC];
+            if ((j < nup) == up) {
+              ms += t0;
+              lxs += t1;
+            } else {
+              mo += t0;
+              lxo += t1;
+            }
+          }
+        } else {
+          // d(d_ik)/dr_k = -u_ik: only sender k moves with this coordinate
+          const S cw = cwp * gu[(i * N + k) * 4 + 1 + a];
+          const S t0 = -h0s[slot_of(k) * DC + dd] * cw;
+          const S t1 = S(-2) * cw * hq[slot_of(k) * DC];
+          if ((k < nup) == up) {
+            ms += t0;
+            lxs += t1;
+          } else {
+            mo += t0;
+            lxo += t1;
+          }
+        }
+        if (++a == 3) {
+          a = 0;
+          ++k;
+        }
+      } else if (q == T + 1) {
+#pragma unroll 4
+        for (int j = 0; j < N; ++j) {
+          if (j == i) continue;
+          const S t = h0s[slot_of(j) * DC + dd] * (S(2) * wrow(i, j, 2) + S(4) * wrow(i, j, 1) / gu[(i * N + j) * 4]);
+          if ((j < nup) == up)
+            ms += t;
+          else
+            mo += t;
+        }
+        ms += lxs;
+        mo += lxo;
+      }
+      S* o = mb + (int64_t)q * 2 * D;
+      o[0] = ms * inv_s;
+      o[D] = mo * inv_o;
+      cwp = nwp;
+    }
+  }
+  if (active)
+    for (int q = T + 2; q < Rp; ++q) {
+      S* o = mb + (int64_t)q * 2 * D;
+      o[0] = 0;
+      o[D] = 0;
+    }
+}
+
 // Nuclear messages with jets.  m_nuc_i = mean_I w_nuc(d_iI) Y_I depends on r_i
 // only, so its jet is nonzero in 5 rows: value, the 3 coordinates of electron
 // i, Laplacian (e-n distance: |grad d|^2 = 1, lap d = 2/d).  Output
@@ -516,6 +660,29 @@ static hipError_t agg_launch(const SysDev& s, const S* h, const S* ws, const S* 
   return hipGetLastError();
 }
 
+template <typename S, int NS>
+static hipError_t agg_lds_launch(const SysDev& s, const S* h, const S* ws, const S* wo, const double* ee, int64_t W,
+                                 S* m, hipStream_t st) {
+  constexpr int RC = 4;  // sender rows staged per step
+  // columns per block: the largest power of two up to 64 with one thread per receiver in at most 512 threads
+  int DC = 64;
+  while (DC > 1 && (DC >= 2 * s.D || DC * s.N > 512)) DC >>= 1;
+  const int nch = (s.D + DC - 1) / DC;
+  const size_t lds = ((size_t)s.N * s.N * 4 + (size_t)RC * 2 * NS * DC + (size_t)2 * NS * DC) * sizeof(S) +
+                     (size_t)s.N * s.N * sizeof(int);
+  static size_t lds_set = 0;
+  if (lds > 64 * 1024 && lds > lds_set) {
+    if (hipFuncSetAttribute((const void*)aggregate_lds_kernel<S, NS, RC>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+      return hipErrorInvalidValue;
+    lds_set = lds;
+  }
+  ProfScope ps("aggregate_kernel", st);
+  hipLaunchKernelGGL((aggregate_lds_kernel<S, NS, RC>), dim3((unsigned)(W * nch)), dim3(DC * s.N), lds, st, s, h,
+                     ws, wo, ee, DC, nch, m);
+  return hipGetLastError();
+}
+
 template <typename S>
 hipError_t launch_aggregate(const SysDev& s, const S* h, const S* wsame, const S* wopp, const S* wnuc, const S* Y,
                             const double* ee, const double* en, int64_t W, int jet, S* m, hipStream_t st) {
@@ -529,12 +696,12 @@ hipError_t launch_aggregate(const SysDev& s, const S* h, const S* wsame, const S
                        wsame, wopp, wnuc, Y, stage, m);
     return hipGetLastError();
   }
-  // template on the larger spin block
+  // template on the larger spin block; above 8 electrons per spin the sender rows go through LDS
   const int ns = std::max(s.nup, s.ndn);
   if (ns <= 4) return agg_launch<S, 4>(s, h, wsame, wopp, ee, W, m, st);
   if (ns <= 8) return agg_launch<S, 8>(s, h, wsame, wopp, ee, W, m, st);
-  if (ns <= 16) return agg_launch<S, 16>(s, h, wsame, wopp, ee, W, m, st);
-  if (ns <= 24) return agg_launch<S, 24>(s, h, wsame, wopp, ee, W, m, st);
+  if (ns <= 16) return agg_lds_launch<S, 16>(s, h, wsame, wopp, ee, W, m, st);
+  if (ns <= 24) return agg_lds_launch<S, 24>(s, h, wsame, wopp, ee, W, m, st);
   return hipErrorInvalidValue;
 }
 
