@@ -221,8 +221,11 @@ hipError_t launch_init_features(const SysDev& s, const double* ee, const double*
 // Tangent row c = 3k + a gets, besides sum_j w_ij dh_j/dx_c:
 //   k == i:  sum_j h_j w'_ij u_ij[a]          (dd_ij/dr_i = u_ij)
 //   k != i:  -h_k w'_ik u_ik[a]               (dd_ik/dr_k = -u_ik)
-// and the Laplacian row adds sum_j h_j (2 w'' + 4 w'/d) + 2 sum_c dw/dx_c dh_j/dx_c,
-// whose cross term accumulates while the tangent rows stream past.
+// and the Laplacian row adds sum_j h_j (2 w'' + 4 w'/d) + 2 sum_c dw/dx_c dh_j/dx_c.
+// Everything that involves the receiver's own coordinates (its own tangent
+// rows, the Laplacian row's h_j terms and the cross terms of its own rows) is
+// gathered once before the row loop; the cross terms of the moving senders
+// accumulate while the rows stream past.
 template <typename S, int NS, int RG>
 __global__ __launch_bounds__(512) void aggregate_kernel(SysDev s, const S* __restrict__ h,
                                                         const S* __restrict__ wsame, const S* __restrict__ wopp,
@@ -274,9 +277,42 @@ __global__ __launch_bounds__(512) void aggregate_kernel(SysDev s, const S* __res
     }
   const S* hb = h + w * N * (int64_t)Rp * D + d;  // h_j row q: hb[(j * Rp + q) * D]
   S* mb = m + w * N * (int64_t)Rp * 2 * D + d;    // m_i row q: mb[(i * Rp + q) * 2D], opposite at + D
-  S lxs[RG], lxo[RG];
+  // Terms that involve a receiver's own coordinates, gathered once per thread: the sender sums of
+  // its own tangent rows (ts, to: same-spin, opposite-spin senders), and the Laplacian row's
+  // sum_j h_j (2 w'' + 4 w'/d) plus the cross terms 2 w'_ij u_ij . dh_j/dr_i (in lxs, lxo; the
+  // cross terms of the other electrons' rows are added while the rows stream past).
+  S lxs[RG], lxo[RG], ts[RG][3], to[RG][3];
 #pragma unroll
-  for (int r = 0; r < RG; ++r) lxs[r] = lxo[r] = 0;
+  for (int r = 0; r < RG; ++r) {
+    lxs[r] = lxo[r] = 0;
+    ts[r][0] = ts[r][1] = ts[r][2] = to[r][0] = to[r][1] = to[r][2] = 0;
+    if (r >= cnt) continue;
+    const int i = i0 + r;
+#pragma unroll 2
+    for (int j = 0; j < N; ++j) {
+      if (j == i) continue;
+      const S w1 = wrow(i, j, 1), w2 = wrow(i, j, 2), h0 = hb[(int64_t)j * Rp * D];
+      const S* gij = gu + (i * N + j) * 4;
+      S lx = h0 * (S(2) * w2 + S(4) * w1 / gij[0]), t[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const S cw = w1 * gij[1 + c];
+        t[c] = h0 * cw;
+        lx += S(2) * cw * hb[((int64_t)j * Rp + 1 + 3 * i + c) * D];
+      }
+      if ((j < nup) == up) {
+        lxs[r] += lx;
+        ts[r][0] += t[0];
+        ts[r][1] += t[1];
+        ts[r][2] += t[2];
+      } else {
+        lxo[r] += lx;
+        to[r][0] += t[0];
+        to[r][1] += t[1];
+        to[r][2] += t[2];
+      }
+    }
+  }
   S hv[2 * NS];
   auto fetch = [&](int q, S* dst) {
 #pragma unroll
@@ -317,21 +353,9 @@ __global__ __launch_bounds__(512) void aggregate_kernel(SysDev s, const S* __res
         if (r >= cnt) continue;
         const int i = i0 + r;
         if (k == i) {
-          // d(d_ij)/dr_i = u_ij for every sender j
-#pragma unroll 4
-          for (int j = 0; j < N; ++j) {
-            if (j == i) continue;
-            const S cw = wrow(i, j, 1) * gu[(i * N + j) * 4 + 1 + a];
-            const S t0 = hb[(int64_t)j * Rp * D] * cw;
-            const S t1 = S(2) * cw * hb[((int64_t)j * Rp + q) * D];
-            if ((j < nup) == up) {
-              ms[r] += t0;
-              lxs[r] += t1;
-            } else {
-              mo[r] += t0;
-              lxo[r] += t1;
-            }
-          }
+          // d(d_ij)/dr_i = u_ij for every sender j: gathered before the rows
+          ms[r] += a == 0 ? ts[r][0] : (a == 1 ? ts[r][1] : ts[r][2]);
+          mo[r] += a == 0 ? to[r][0] : (a == 1 ? to[r][1] : to[r][2]);
         } else {
           // d(d_ik)/dr_k = -u_ik: only sender k moves with this coordinate
           const S cw = cwp[r] * gu[(i * N + k) * 4 + 1 + a];
@@ -353,17 +377,6 @@ __global__ __launch_bounds__(512) void aggregate_kernel(SysDev s, const S* __res
     } else if (q == T + 1) {
 #pragma unroll
       for (int r = 0; r < RG; ++r) {
-        if (r >= cnt) continue;
-        const int i = i0 + r;
-#pragma unroll 4
-        for (int j = 0; j < N; ++j) {
-          if (j == i) continue;
-          const S t = hb[(int64_t)j * Rp * D] * (S(2) * wrow(i, j, 2) + S(4) * wrow(i, j, 1) / gu[(i * N + j) * 4]);
-          if ((j < nup) == up)
-            ms[r] += t;
-          else
-            mo[r] += t;
-        }
         ms[r] += lxs[r];
         mo[r] += lxo[r];
       }
@@ -451,7 +464,34 @@ __global__ __launch_bounds__(512) void aggregate_lds_kernel(SysDev s, const S* _
     wv[sl] = (active && j >= 0 && j != i) ? wrow(i, j, 0) : S(0);
   }
   S* mb = m + (w * N + min(i, N - 1)) * (int64_t)Rp * 2 * D + d;  // row q of receiver i: mb[q * 2D]
-  S lxs = 0, lxo = 0;
+  // own-coordinate terms gathered once (as in aggregate_kernel)
+  S lxs = 0, lxo = 0, ts[3] = {0, 0, 0}, to[3] = {0, 0, 0};
+  if (active) {
+#pragma unroll 2
+    for (int j = 0; j < N; ++j) {
+      if (j == i) continue;
+      const S w1 = wrow(i, j, 1), w2 = wrow(i, j, 2), h0 = h0s[slot_of(j) * DC + dd];
+      const S* gij = gu + (i * N + j) * 4;
+      S lx = h0 * (S(2) * w2 + S(4) * w1 / gij[0]), t[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const S cw = w1 * gij[1 + c];
+        t[c] = h0 * cw;
+        lx += S(2) * cw * hw[((int64_t)j * Rp + 1 + 3 * i + c) * D + d];
+      }
+      if ((j < nup) == up) {
+        lxs += lx;
+        ts[0] += t[0];
+        ts[1] += t[1];
+        ts[2] += t[2];
+      } else {
+        lxo += lx;
+        to[0] += t[0];
+        to[1] += t[1];
+        to[2] += t[2];
+      }
+    }
+  }
   S cwp = 0;  // w'_ik of the moving sender of the current tangent row
   int k = 0, a = 0;
   for (int q0 = 0; q0 <= T + 1; q0 += RC) {
@@ -478,21 +518,9 @@ __global__ __launch_bounds__(512) void aggregate_lds_kernel(SysDev s, const S* _
       S ms = up ? au : ad, mo = up ? ad : au;
       if (q >= 1 && q <= T) {
         if (k == i) {
-          // d(d_ij)/dr_i = u_ij for every sender j
-#pragma unroll 4
-          for (int j = 0; j < N; ++j) {
-            if (j == i) continue;
-            const S cw = wrow(i, j, 1) * gu[(i * N + j) * 4 + 1 + a];
-            const S t0 = h0s[slot_of(j) * DC + dd] * cw;
-            const S t1 = S(2) * cw * hq[slot_of(j) * DC];
-            if ((j < nup) == up) {
-              ms += t0;
-              lxs += t1;
-            } else {
-              mo += t0;
-              lxo += t1;
-            }
-          }
+          // d(d_ij)/dr_i = u_ij for every sender j: gathered before the rows
+          ms += a == 0 ? ts[0] : (a == 1 ? ts[1] : ts[2]);
+          mo += a == 0 ? to[0] : (a == 1 ? to[1] : to[2]);
         } else {
           // d(d_ik)/dr_k = -u_ik: only sender k moves with this coordinate
           const S cw = cwp * gu[(i * N + k) * 4 + 1 + a];
@@ -511,15 +539,6 @@ __global__ __launch_bounds__(512) void aggregate_lds_kernel(SysDev s, const S* _
           ++k;
         }
       } else if (q == T + 1) {
-#pragma unroll 4
-        for (int j = 0; j < N; ++j) {
-          if (j == i) continue;
-          const S t = h0s[slot_of(j) * DC + dd] * (S(2) * wrow(i, j, 2) + S(4) * wrow(i, j, 1) / gu[(i * N + j) * 4]);
-          if ((j < nup) == up)
-            ms += t;
-          else
-            mo += t;
-        }
         ms += lxs;
         mo += lxo;
       }

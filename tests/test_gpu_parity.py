@@ -99,14 +99,15 @@ def test_small_molecule_ragged_fp64():
     _compare_fp64("ragged fp64 37", s, a, p, r)
 
 
-def test_large_spin_blocks_fp64():
-    """More than 8 electrons per spin (10 up, 9 down): the message aggregation stages the
-    senders' rows in LDS instead of holding one receiver group per thread."""
-    s = qi.System((8.0, 7.0, 4.0), ((0.0, 0.0, 0.0), (2.2, 0.3, -0.4), (-0.9, 1.9, 1.1)), 10, 9)
+@pytest.mark.parametrize("n_up,n_down", [(10, 9), (9, 2)])
+def test_large_spin_blocks_fp64(n_up, n_down):
+    """More than 8 electrons in a spin block (balanced and strongly polarised): the message
+    aggregation stages the senders' rows in LDS instead of holding one receiver group per thread."""
+    s = qi.System((8.0, 7.0, 4.0), ((0.0, 0.0, 0.0), (2.2, 0.3, -0.4), (-0.9, 1.9, 1.1)), n_up, n_down)
     a = qi.Ansatz(n_rbf=6, rbf_dmax=7.0, init_layers=1, width=12, mp_layers=2, n_det=2, n_env=2)
     p = qi.make_params(s, a, 43)
     r = qi.make_walkers(s, 7, 44)
-    _compare_fp64("19 electrons fp64 7", s, a, p, r)
+    _compare_fp64(f"{n_up}+{n_down} electrons fp64 7", s, a, p, r)
 
 
 def test_n2_ansatz_fp32_subset_mha():
