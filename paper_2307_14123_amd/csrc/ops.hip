@@ -636,16 +636,16 @@ __global__ __launch_bounds__(256) void aggregate_value_kernel(SysDev s, const S*
     const bool up = i < s.nup;
     const int nsame = (up ? s.nup : s.ndn) - 1;
     const int nopp = up ? s.ndn : s.nup;
+    // senders of each spin block in one branch-free loop (independent loads in flight)
+    const int ls = up ? 0 : s.nup, hs_ = up ? s.nup : N, lo = up ? s.nup : 0, ho = up ? N : s.nup;
     S ms = 0, mo = 0;
-    for (int j = 0; j < N; ++j) {
-      if (j == i) continue;
-      const int v = po[i * N + j];
-      const S hv = hsrc[j * D + d];
-      if (v & OPP)
-        mo += wow[(int64_t)(v & (OPP - 1)) * D + d] * hv;
-      else
-        ms += wsw[(int64_t)v * D + d] * hv;
+#pragma unroll 4
+    for (int j = ls; j < hs_; ++j) {
+      const S wgt = j == i ? S(0) : wsw[(int64_t)po[i * N + j] * D + d];
+      ms += wgt * hsrc[j * D + d];
     }
+#pragma unroll 4
+    for (int j = lo; j < ho; ++j) mo += wow[(int64_t)(po[i * N + j] & (OPP - 1)) * D + d] * hsrc[j * D + d];
     S nuc = 0;
     for (int I = 0; I < M; ++I) nuc += wnw[(int64_t)(i * M + I) * D + d] * Y[I * D + d];
     S* row = m + (w * N + i) * 3 * (int64_t)D + d;
