@@ -27,7 +27,9 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK = {"fp32_mfma": 157.3e12, "fp64_mfma": 78.6e12, "bf16_mfma": 2.5e15, "hbm": 8.0e12}
+PEAK = {"fp32_mfma": 157.3e12, "fp64_mfma": 78.6e12, "bf16_mfma": 2.5e15, "hbm": 8.0e12,
+        # float32 exponentials: 256 compute units x 4 SIMDs x 4 lanes per clock (quarter rate) x 2.4 GHz
+        "exp_f32": 256 * 4 * 4 * 2.4e9}
 
 
 def algorithmic_model(s, a, elem_bytes, n_mc, with_grad, fused_edges):
@@ -67,8 +69,11 @@ def algorithmic_model(s, a, elem_bytes, n_mc, with_grad, fused_edges):
         # HBM-bound kernels: bytes of jets read and written
         "aggregate_kernel": ("hbm", L * eb * (N * R1 * D + N * R1 * 2 * D + (P[0] + P[1]) * 3 * D)),
         "det_kernel": ("hbm", eb * nd * R1 * nsq + 8 * 2 * nd * (T + 3)),
-        "envelope_kernel": ("hbm", 2 * eb * nd * R1 * nsq),
+        "envelope_kernel<jet>": ("hbm", 2 * eb * nd * R1 * nsq),
     }
+    if eb == 4:
+        # value rows: one exponential per (electron, orbital, nucleus, exponent) and log|psi|
+        m["envelope_kernel<val>"] = ("alu", n_val * nd * nsq * M * a.n_env)
     if fused_edges:
         m["edge_mlp_kernel<jet>"] = ("mfma", edge_jet)
         m["edge_mlp_kernel<val>"] = ("mfma", n_val * edge_val)
@@ -224,6 +229,9 @@ def main():
             pk = PEAK["fp32_mfma"] if (name == "gemm_kernel<val>" or name == "wgrad_kernel") and args.precision == "bf16" \
                 else PEAK[gemm_dtype]
             roof = {"bound": "mfma", "achieved": per_launch / avg_s / 1e12, "peak": pk / 1e12, "unit": "TFLOP/s"}
+        elif bound == "alu":
+            roof = {"bound": "alu", "achieved": per_launch / avg_s / 1e9, "peak": PEAK["exp_f32"] / 1e9,
+                    "unit": "Gexp/s"}
         else:
             roof = {"bound": "hbm", "achieved": per_launch / avg_s / 1e9, "peak": PEAK["hbm"] / 1e9, "unit": "GB/s"}
         roof["frac"] = roof["achieved"] / roof["peak"]
@@ -237,7 +245,8 @@ def main():
             bound, wpw = model[f]
             per = wpw * W * args.steps / (ms1 * 1e-3)
             others[f] = {"bound": bound, "achieved": per / (1e12 if bound == "mfma" else 1e9),
-                         "unit": "TFLOP/s" if bound == "mfma" else "GB/s", "ms_per_step": ms1 / args.steps}
+                         "unit": {"mfma": "TFLOP/s", "alu": "Gexp/s"}.get(bound, "GB/s"),
+                         "ms_per_step": ms1 / args.steps}
 
     res = {
         "metric": "walker local energies/sec at stated mHa error vs FP64 oracle; VMC train step ms",

@@ -728,38 +728,63 @@ hipError_t launch_aggregate(const SysDev& s, const S* h, const S* wsame, const S
 
 // A[a][k] = phi_k(r_a) * sum_{I,beta} pi exp(-sigma d_aI), jets by the product rule.
 // Output per walker: [spin][det][row][a][k] (this launch fills one spin block).
+//
+// One determinant per grid row (blockIdx.y); a thread per (walker, electron a, orbital k).  The
+// envelope weights of the determinant go through LDS a chunk of nuclei at a time, laid out
+// [nucleus][exponent][orbital] as (pi, sigma) pairs, so that the lanes of a wave (consecutive
+// orbitals, then electrons) read consecutive or identical pairs.  For jets the exponentials of
+// one nucleus are summed as s1 = sum sigma e and s2 = sum sigma^2 e before they meet the
+// direction u of that nucleus: grad = -sum_I u_I s1_I, Laplacian term sum_I (s2_I - 2 s1_I / d_I).
 template <typename S>
-__global__ void envelope_kernel(SysDev s, int spin, const S* __restrict__ phi, const S* __restrict__ pi,
-                                const S* __restrict__ sg, const double* __restrict__ en, int64_t W, int jet,
-                                S* __restrict__ ajet) {
+__global__ __launch_bounds__(256) void envelope_kernel(SysDev s, int spin, const S* __restrict__ phi,
+                                                       const S* __restrict__ pi, const S* __restrict__ sg,
+                                                       const double* __restrict__ en, int64_t W, int jet, int ic,
+                                                       S* __restrict__ ajet) {
   // arithmetic in the plan's activation type (float64 only for the FP64 plan)
   using T = S;
+  typedef S S2 __attribute__((ext_vector_type(2)));
+  extern __shared__ __align__(16) unsigned char esm[];
+  S2* tab = (S2*)esm;
   const int n = spin ? s.ndn : s.nup;
   const int i0 = spin ? s.nup : 0;
   const int Rp = jet ? s.Rp : 1;
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= W * s.ndet * n * n) return;
-  const int k = (int)(t % n);
-  const int a = (int)((t / n) % n);
-  const int p = (int)((t / (n * n)) % s.ndet);
-  const int64_t w = t / ((int64_t)n * n * s.ndet);
+  const int nn = n * n, nb = s.nenv, M = s.M;
+  const int p = blockIdx.y;
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const bool live = t < W * nn;
+  const int64_t w = live ? t / nn : 0;
+  const int r = live ? (int)(t - w * nn) : 0;
+  const int a = r / n, k = r - a * n;
   const int i = i0 + a;
+  const double* g = en + (w * s.N + i) * M * 4;
   T e0 = 0, eg[3] = {0, 0, 0}, el = 0;
-  const double* g = en + (w * s.N + i) * s.M * 4;
-  for (int I = 0; I < s.M; ++I) {
-    const T d = (T)g[I * 4];
-    const T u[3] = {(T)g[I * 4 + 1], (T)g[I * 4 + 2], (T)g[I * 4 + 3]};
-    for (int b = 0; b < s.nenv; ++b) {
-      const int64_t idx = (((int64_t)p * n + k) * s.M + I) * s.nenv + b;
-      const T pw = pi[idx], sgm = sg[idx];
-      const T e = pw * exp(-sgm * d);
-      e0 += e;
+  for (int I0 = 0; I0 < M; I0 += ic) {
+    const int ni = min(ic, M - I0);
+    __syncthreads();  // the previous chunk has been read
+    for (int e = threadIdx.x; e < n * ni * nb; e += 256) {
+      const int kk = e / (ni * nb), j = e - kk * (ni * nb);
+      const int64_t src = ((int64_t)(p * n + kk) * M + I0) * nb + j;
+      tab[j * n + kk] = S2{pi[src], sg[src]};
+    }
+    __syncthreads();
+    if (!live) continue;
+    for (int I = 0; I < ni; ++I) {
+      const T d = (T)g[(I0 + I) * 4];
+      T s1 = 0, s2 = 0;
+      for (int b = 0; b < nb; ++b) {
+        const S2 ps = tab[(I * nb + b) * n + k];
+        const T e = ps.x * exp(-ps.y * d);
+        e0 += e;
+        s1 += ps.y * e;
+        s2 += ps.y * ps.y * e;
+      }
       if (jet) {
-        for (int x = 0; x < 3; ++x) eg[x] -= sgm * e * u[x];
-        el += e * (sgm * sgm - T(2) * sgm / d);
+        for (int x = 0; x < 3; ++x) eg[x] -= (T)g[(I0 + I) * 4 + 1 + x] * s1;
+        el += s2 - T(2) * s1 / d;
       }
     }
   }
+  if (!live) return;
   const int ncol = s.ndet * n;
   const S* ph = phi + ((w * n + a) * Rp) * (int64_t)ncol + p * n + k;
   const int64_t wstride = (int64_t)s.ndet * Rp * (s.nup * s.nup + s.ndn * s.ndn);
@@ -768,16 +793,16 @@ __global__ void envelope_kernel(SysDev s, int spin, const S* __restrict__ phi, c
   const T p0 = ph[0];
   out[0] = (S)(p0 * e0);
   if (!jet) return;
-  const int64_t rs = (int64_t)n * n;
+  const int64_t rs = (int64_t)nn;
+  const int own = 1 + 3 * i;  // tangent rows of this electron's own coordinates
   for (int q = 1; q < Rp; ++q) {
     T v = 0;
     if (q <= s.T) {
       v = (T)ph[(int64_t)q * ncol] * e0;
-      const int c = q - 1;
-      if (c / 3 == i) v += p0 * eg[c % 3];
+      if (q >= own && q < own + 3) v += p0 * eg[q - own];
     } else if (q == s.T + 1) {
       v = (T)ph[(int64_t)q * ncol] * e0 + p0 * el;
-      for (int x = 0; x < 3; ++x) v += T(2) * (T)ph[(int64_t)(1 + 3 * i + x) * ncol] * eg[x];
+      for (int x = 0; x < 3; ++x) v += T(2) * (T)ph[(int64_t)(own + x) * ncol] * eg[x];
     }
     out[q * rs] = (S)v;
   }
@@ -787,11 +812,16 @@ template <typename S>
 hipError_t launch_envelope(const SysDev& s, int spin, const S* phi, const S* pi, const S* sigma, const double* en,
                            int64_t W, int jet, S* ajet, hipStream_t st) {
   const int n = spin ? s.ndn : s.nup;
-  const int64_t cnt = W * s.ndet * n * n;
+  const int64_t cnt = W * n * n;
   if (cnt == 0) return hipSuccess;
-  ProfScope ps("envelope_kernel", st);
-  hipLaunchKernelGGL(envelope_kernel<S>, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, st, s, spin, phi, pi,
-                     sigma, en, W, jet, ajet);
+  // nuclei per LDS chunk: at most 32 KB of (pi, sigma) pairs
+  const size_t per = (size_t)n * s.nenv * 2 * sizeof(S);
+  const int ic = (int)std::max<size_t>(1, std::min<size_t>(s.M, 32768 / per));
+  const size_t lds = per * ic;
+  if (lds > 65536 || (cnt + 255) / 256 > INT32_MAX) return hipErrorInvalidValue;
+  ProfScope ps(jet ? "envelope_kernel<jet>" : "envelope_kernel<val>", st);
+  hipLaunchKernelGGL(envelope_kernel<S>, dim3((unsigned)((cnt + 255) / 256), (unsigned)s.ndet), dim3(256), lds, st,
+                     s, spin, phi, pi, sigma, en, W, jet, ic, ajet);
   return hipGetLastError();
 }
 
