@@ -832,146 +832,228 @@ __device__ inline double wave_sum(double v) {
   return v;
 }
 
-// One wavefront per n x n problem: Gauss-Jordan with partial pivoting gives
-// log|det A|, its sign and A^-1; then for every tangent c: X = A^-1 dA_c,
-// d log|det| = tr X, and the Laplacian tr(A^-1 lapA) - sum_c tr(X^2).
+// Determinants with G lanes per n x n problem (G = 8, 16 or 32, G >= n): lane r
+// holds row r of A (and of the growing inverse) in registers, so the
+// elimination needs no barrier: the pivot of each column is found with a
+// butterfly over the group, and the pivot row reaches the other lanes by
+// shuffles.  Rows are never swapped; a lane that has served as pivot for column
+// c is marked used and, in Gauss-Jordan form, ends up holding row c of A^-1.
+// log|det A| is the sum of log|pivot|, its sign the product of the pivot signs
+// and of the permutation's sign (parity of its inversions).
+//
+// Jets: for every tangent t the rows of dA_t go through LDS, lane r forms row
+// c(r) of X = A^-1 dA_t, d log|det| = tr X (group sum), and the Laplacian is
+// tr(A^-1 lapA) - sum_t tr(X^2), the product of X's rows and columns taken
+// through a second LDS tile.
 constexpr int DMAX = 32;
 
-template <typename S>
-__global__ __launch_bounds__(64) void det_kernel(const S* __restrict__ src, int64_t stride_outer, int n_inner,
-                                                 int64_t stride_inner, int rows, int n, int ntan, int jet,
-                                                 int64_t out_outer, int64_t out_off, double* __restrict__ ld,
-                                                 double* __restrict__ sg, double* __restrict__ gout,
-                                                 double* __restrict__ lapout, double* __restrict__ ainv) {
-  // LDS sized for this n: augmented [n][2n+1], dA [n][n+1], X [n][n+1], pivot column [n]
+template <int G>
+__device__ inline double group_sum(double v) {
+#pragma unroll
+  for (int o = 1; o < G; o <<= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+template <int G>
+__device__ inline int group_sum_int(int v) {
+#pragma unroll
+  for (int o = 1; o < G; o <<= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+template <typename S, int G, bool INV>
+__global__ __launch_bounds__(256) void det_kernel(const S* __restrict__ src, int64_t stride_outer, int n_inner,
+                                                  int64_t stride_inner, int64_t nprob, int n, int ntan, int jet,
+                                                  int64_t out_outer, int64_t out_off, double* __restrict__ ld,
+                                                  double* __restrict__ sg, double* __restrict__ gout,
+                                                  double* __restrict__ lapout, double* __restrict__ ainv) {
   extern __shared__ __align__(16) unsigned char dsm[];
-  double* Mx_ = (double*)dsm;
-  double* dA_ = Mx_ + n * (2 * n + 1);
-  double* Xs_ = dA_ + n * (n + 1);
-  double* fcol = Xs_ + n * (n + 1);
-  int* piv_p = (int*)(fcol + n);
-#define Mx(r, c) Mx_[(r) * (2 * n + 1) + (c)]
-#define dA(r, c) dA_[(r) * (n + 1) + (c)]
-#define Xs(r, c) Xs_[(r) * (n + 1) + (c)]
-  const int lane = threadIdx.x;
-  const int64_t pb = blockIdx.x;
-  const int64_t o = pb / n_inner;
-  const int in = (int)(pb % n_inner);
+  const int lane = threadIdx.x & 63;
+  const int r = lane & (G - 1);
+  const int base = lane - r;
+  const int slot = threadIdx.x / G;  // problem slot in the block
+  const int64_t pb = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
+  const bool live = pb < nprob;
+  const int64_t o = live ? pb / n_inner : 0;
+  const int in = live ? (int)(pb % n_inner) : 0;
   const S* A = src + o * stride_outer + in * stride_inner;
   const int64_t oi = o * out_outer + out_off + in;
   const int nn = n * n;
-  (void)rows;
-  for (int e = lane; e < n * 2 * n; e += 64) {
-    const int r = e / (2 * n), c = e % (2 * n);
-    Mx(r, c) = c < n ? (double)A[r * n + c] : (c - n == r ? 1.0 : 0.0);
+  const bool row = live && r < n;
+
+  double a[G], v[G];
+#pragma unroll
+  for (int c = 0; c < G; ++c) {
+    a[c] = (row && c < n) ? (double)A[r * n + c] : 0.0;
+    v[c] = (INV && row && c == r) ? 1.0 : 0.0;
   }
-  __syncthreads();
+  bool used = !row;  // padding lanes never serve as pivot
+  int cp = r;        // column this lane was pivot for
   double logdet = 0.0, sgn = 1.0;
   bool singular = false;
-  for (int col = 0; col < n; ++col) {
-    // pivot: largest |value| in rows col..n-1 (smallest index on ties)
-    double best = -1.0;
-    int bi = col;
-    for (int r = col + lane; r < n; r += 64) {
-      const double v = fabs(Mx(r, col));
-      if (v > best) {
-        best = v;
-        bi = r;
+#pragma unroll
+  for (int col = 0; col < G; ++col) {
+    if (col >= n) break;
+    // pivot: largest |a[col]| over the unused rows (NaN counts as largest; smallest row on ties)
+    double key = used ? -1.0 : (a[col] != a[col] ? INFINITY : fabs(a[col]));
+    int idx = r;
+#pragma unroll
+    for (int off = 1; off < G; off <<= 1) {
+      const double ok = __shfl_xor(key, off);
+      const int oid = __shfl_xor(idx, off);
+      if (ok > key || (ok == key && oid < idx)) {
+        key = ok;
+        idx = oid;
       }
     }
-    for (int off = 32; off > 0; off >>= 1) {
-      const double ob = __shfl_xor(best, off);
-      const int oidx = __shfl_xor(bi, off);
-      if (ob > best || (ob == best && oidx < bi)) {
-        best = ob;
-        bi = oidx;
-      }
-    }
-    if (lane == 0) *piv_p = bi;
-    __syncthreads();
-    const int pr = *piv_p;
-    if (!(best > 0.0)) {
-      singular = true;
-      break;
-    }
-    if (pr != col) {
-      for (int c = lane; c < 2 * n; c += 64) {
-        const double tmp = Mx(pr, c);
-        Mx(pr, c) = Mx(col, c);
-        Mx(col, c) = tmp;
-      }
-      sgn = -sgn;
-    }
-    __syncthreads();
-    const double pv = Mx(col, col);
+    if (!(key > 0.0)) singular = true;
+    const double pv = __shfl(a[col], base + idx);
+    const double pvs = key > 0.0 ? pv : 1.0;
     logdet += log(fabs(pv));
     if (pv < 0) sgn = -sgn;
-    for (int r = lane; r < n; r += 64) fcol[r] = Mx(r, col);
-    __syncthreads();
-    for (int c = lane; c < 2 * n; c += 64) Mx(col, c) /= pv;
-    __syncthreads();
-    for (int e = lane; e < n * 2 * n; e += 64) {
-      const int r = e / (2 * n), c = e % (2 * n);
-      if (r != col) Mx(r, c) -= fcol[r] * Mx(col, c);
+    const double rinv = 1.0 / pvs;
+    const bool me = r == idx;
+    double prow[G], pvrow[G];
+#pragma unroll
+    for (int c = col + 1; c < G; ++c) prow[c] = __shfl(a[c], base + idx);
+    if (INV) {
+#pragma unroll
+      for (int c = 0; c < G; ++c) pvrow[c] = __shfl(v[c], base + idx);
     }
-    __syncthreads();
-  }
-  if (singular) {
-    if (lane == 0) {
-      ld[oi] = -INFINITY;
-      sg[oi] = 0.0;
-      if (jet) lapout[oi] = 0.0;
+    if (me) {
+      used = true;
+      cp = col;
+      if (INV) {
+#pragma unroll
+        for (int c = col + 1; c < G; ++c) a[c] *= rinv;
+#pragma unroll
+        for (int c = 0; c < G; ++c) v[c] *= rinv;
+      }
+    } else if (INV || !used) {
+      // Gauss-Jordan eliminates every other row, LU only the rows below (the unused ones)
+      const double f = a[col] * rinv;
+#pragma unroll
+      for (int c = col + 1; c < G; ++c) a[c] -= f * prow[c];
+      if (INV) {
+#pragma unroll
+        for (int c = 0; c < G; ++c) v[c] -= f * pvrow[c];
+      }
     }
-    if (ainv)
-      for (int e = lane; e < nn; e += 64) ainv[pb * nn + e] = 0.0;
-    if (jet)
-      for (int c = lane; c < ntan; c += 64) gout[oi * ntan + c] = 0.0;
-    return;
   }
-  if (lane == 0) {
-    ld[oi] = logdet;
-    sg[oi] = sgn;
+  // sign of the permutation row -> column: parity of its inversions
+  int inv_cnt = 0;
+#pragma unroll
+  for (int j = 0; j < G; ++j) {
+    const int cj = __shfl(cp, base + j);
+    if (j > r && j < n && r < n && cj < cp) ++inv_cnt;
   }
-  if (ainv)
-    for (int e = lane; e < nn; e += 64) ainv[pb * nn + e] = Mx(e / n, n + e % n);
+  inv_cnt = group_sum_int<G>(inv_cnt);
+  if (inv_cnt & 1) sgn = -sgn;
+  if (live && r == 0) {
+    ld[oi] = singular ? -INFINITY : logdet;
+    sg[oi] = singular ? 0.0 : sgn;
+  }
+  if (!INV) return;
+  if (ainv && row) {
+    double* dst = ainv + pb * (int64_t)nn + (int64_t)cp * n;
+#pragma unroll
+    for (int c = 0; c < G; ++c)
+      if (c < n) dst[c] = singular ? 0.0 : v[c];
+  }
   if (!jet) return;
-  // A^-1 sits in Mx[:, n:2n]
+  // LDS per problem slot: dA tile [n][n+1] (type S), X tile [n][n+1] (double)
+  const int ld1 = n + 1;
+  S* dsl = (S*)dsm + (size_t)slot * n * ld1;
+  double* xsl = (double*)(dsm + (((size_t)(blockDim.x / G) * n * ld1 * sizeof(S) + 15) / 16) * 16) +
+                (size_t)slot * n * ld1;
   double qacc = 0.0;
-  for (int c = 0; c < ntan; ++c) {
-    const S* dsrc = A + (int64_t)(1 + c) * nn;
-    for (int e = lane; e < nn; e += 64) dA(e / n, e % n) = (double)dsrc[e];
-    __syncthreads();
-    double gpart = 0.0;
-    for (int e = lane; e < nn; e += 64) {
-      const int a = e / n, b = e % n;
-      double x = 0.0;
-      for (int k = 0; k < n; ++k) x += Mx(a, n + k) * dA(k, b);
-      Xs(a, b) = x;
-      if (a == b) gpart += x;
+  S nxt[G];
+#pragma unroll
+  for (int c = 0; c < G; ++c) nxt[c] = (row && c < n && ntan > 0) ? A[(int64_t)nn + r * n + c] : S(0);
+  for (int t = 0; t < ntan; ++t) {
+    if (row) {
+#pragma unroll
+      for (int c = 0; c < G; ++c)
+        if (c < n) dsl[r * ld1 + c] = nxt[c];
+    }
+    if (t + 1 < ntan) {
+      const S* q = A + (int64_t)(2 + t) * nn + r * n;
+#pragma unroll
+      for (int c = 0; c < G; ++c) nxt[c] = (row && c < n) ? q[c] : S(0);
     }
     __syncthreads();
-    for (int e = lane; e < nn; e += 64) {
-      const int a = e / n, b = e % n;
-      qacc += Xs(a, b) * Xs(b, a);
+    // row cp of X = A^-1 dA_t
+    double x[G];
+#pragma unroll
+    for (int b = 0; b < G; ++b) x[b] = 0.0;
+    if (row) {
+#pragma unroll
+      for (int k = 0; k < G; ++k) {
+        if (k >= n) break;
+        const double vk = v[k];
+#pragma unroll
+        for (int b = 0; b < G; ++b)
+          if (b < n) x[b] += vk * (double)dsl[k * ld1 + b];
+      }
+#pragma unroll
+      for (int b = 0; b < G; ++b)
+        if (b < n) xsl[cp * ld1 + b] = x[b];
     }
-    const double gc = wave_sum(gpart);
-    if (lane == 0) gout[oi * ntan + c] = gc;
+    double dg = 0.0;
+#pragma unroll
+    for (int b = 0; b < G; ++b)
+      if (b == cp) dg = x[b];
+    dg = group_sum<G>(row ? dg : 0.0);
+    if (live && r == 0) gout[oi * ntan + t] = singular ? 0.0 : dg;
+    __syncthreads();
+    if (row) {
+#pragma unroll
+      for (int b = 0; b < G; ++b)
+        if (b < n) qacc += x[b] * xsl[b * ld1 + cp];
+    }
   }
-  const S* lsrc = A + (int64_t)(1 + ntan) * nn;
+  // tr(A^-1 lapA): row cp of A^-1 against column cp of lapA
   double tr = 0.0;
-  for (int e = lane; e < nn; e += 64) {
-    const int a = e / n, b = e % n;
-    tr += Mx(a, n + b) * (double)lsrc[b * n + a];
+  if (row) {
+    const S* lsrc = A + (int64_t)(1 + ntan) * nn;
+#pragma unroll
+    for (int b = 0; b < G; ++b)
+      if (b < n) tr += v[b] * (double)lsrc[b * n + cp];
   }
-  tr = wave_sum(tr);
-  qacc = wave_sum(qacc);
-  if (lane == 0) lapout[oi] = tr - qacc;
+  const double lap = group_sum<G>(tr - qacc);
+  if (live && r == 0) lapout[oi] = singular ? 0.0 : lap;
 }
-#undef Mx
-#undef dA
-#undef Xs
 
-static size_t det_lds(int n) { return (size_t)(n * (2 * n + 1) + 2 * n * (n + 1) + n) * 8 + 16; }
+static int det_group(int n) { return n <= 8 ? 8 : (n <= 16 ? 16 : 32); }
+
+// Launches the variant for n; LDS: the dA and X tiles of every problem slot (jets only).
+template <typename S>
+static hipError_t det_dispatch(const S* src, int64_t stride_outer, int n_inner, int64_t stride_inner, int64_t nprob,
+                               int n, int ntan, int jet, int64_t out_outer, int64_t out_off, double* ld, double* sg,
+                               double* g, double* lap, double* ainv, hipStream_t st) {
+  if (n < 1 || n > DMAX) return hipErrorInvalidValue;
+  if (nprob <= 0) return hipSuccess;
+  const int G = det_group(n);
+  const int threads = G == 8 ? 256 : (G == 16 ? 128 : 64);
+  const int slots = threads / G;
+  const int64_t blocks = (nprob + slots - 1) / slots;
+  if (blocks > INT32_MAX) return hipErrorInvalidValue;
+  const bool inv = jet || ainv;
+  const size_t lds = jet ? ((size_t)slots * n * (n + 1) * sizeof(S) + 15) / 16 * 16 + (size_t)slots * n * (n + 1) * 8
+                         : 0;
+#define QMC_DET(GG, II)                                                                                       \
+  hipLaunchKernelGGL((det_kernel<S, GG, II>), dim3((unsigned)blocks), dim3(threads), lds, st, src, stride_outer, \
+                     n_inner, stride_inner, nprob, n, ntan, jet, out_outer, out_off, ld, sg, g, lap, ainv)
+  if (G == 8) {
+    if (inv) QMC_DET(8, true); else QMC_DET(8, false);
+  } else if (G == 16) {
+    if (inv) QMC_DET(16, true); else QMC_DET(16, false);
+  } else {
+    if (inv) QMC_DET(32, true); else QMC_DET(32, false);
+  }
+#undef QMC_DET
+  return hipGetLastError();
+}
 
 template <typename S>
 hipError_t launch_det(const SysDev& s, const S* ajet, int64_t W, int jet, double* ld, double* sg, double* g,
@@ -983,20 +1065,21 @@ hipError_t launch_det(const SysDev& s, const S* ajet, int64_t W, int jet, double
     if (n == 0) continue;
     if (n > DMAX) return hipErrorInvalidValue;
     const int64_t soff = spin ? (int64_t)s.ndet * Rp * s.nup * s.nup : 0;
-    ProfScope ps("det_kernel", st);
-    hipLaunchKernelGGL(det_kernel<S>, dim3((unsigned)(W * s.ndet)), dim3(64), det_lds(n), st, ajet + soff, wstride, s.ndet,
-                       (int64_t)Rp * n * n, Rp, n, s.T, jet, (int64_t)2 * s.ndet, (int64_t)spin * s.ndet, ld, sg, g,
-                       lap, ainv ? ainv + (spin ? (int64_t)W * s.ndet * s.nup * s.nup : 0) : nullptr);
+    ProfScope ps(jet ? "det_kernel<jet>" : "det_kernel<val>", st);
+    const hipError_t e =
+        det_dispatch<S>(ajet + soff, wstride, s.ndet, (int64_t)Rp * n * n, W * s.ndet, n, s.T, jet,
+                        (int64_t)2 * s.ndet, (int64_t)spin * s.ndet, ld, sg, g, lap,
+                        ainv ? ainv + (spin ? (int64_t)W * s.ndet * s.nup * s.nup : 0) : nullptr, st);
+    if (e != hipSuccess) return e;
   }
-  return hipGetLastError();
+  return hipSuccess;
 }
 
 hipError_t launch_det_generic(int64_t nmat, int n, int ntan, const double* jets, double* ld, double* sg, double* g,
                               double* lap, hipStream_t st) {
   if (n < 1 || n > DMAX) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(det_kernel<double>, dim3((unsigned)nmat), dim3(64), det_lds(n), st, jets, (int64_t)(ntan + 2) * n * n, 1,
-                     (int64_t)0, ntan + 2, n, ntan, 1, (int64_t)1, (int64_t)0, ld, sg, g, lap, nullptr);
-  return hipGetLastError();
+  return det_dispatch<double>(jets, (int64_t)(ntan + 2) * n * n, 1, (int64_t)0, nmat, n, ntan, 1, (int64_t)1,
+                              (int64_t)0, ld, sg, g, lap, nullptr, st);
 }
 
 // ---------------------------------------------------------------- combination and local energy

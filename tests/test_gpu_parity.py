@@ -99,15 +99,51 @@ def test_small_molecule_ragged_fp64():
     _compare_fp64("ragged fp64 37", s, a, p, r)
 
 
-@pytest.mark.parametrize("n_up,n_down", [(10, 9), (9, 2)])
+@pytest.mark.parametrize("n_up,n_down", [(10, 9), (9, 2), (17, 3)])
 def test_large_spin_blocks_fp64(n_up, n_down):
     """More than 8 electrons in a spin block (balanced and strongly polarised): the message
-    aggregation stages the senders' rows in LDS instead of holding one receiver group per thread."""
-    s = qi.System((8.0, 7.0, 4.0), ((0.0, 0.0, 0.0), (2.2, 0.3, -0.4), (-0.9, 1.9, 1.1)), n_up, n_down)
+    aggregation stages the senders' rows in LDS instead of holding one receiver group per thread,
+    and the determinants take 16 or 32 lanes per matrix (with jets, and value rows only)."""
+    s = qi.System((8.0, 7.0, 4.0, 1.0), ((0.0, 0.0, 0.0), (2.2, 0.3, -0.4), (-0.9, 1.9, 1.1), (1.0, -1.5, 0.7)),
+                  n_up, n_down)
     a = qi.Ansatz(n_rbf=6, rbf_dmax=7.0, init_layers=1, width=12, mp_layers=2, n_det=2, n_env=2)
     p = qi.make_params(s, a, 43)
     r = qi.make_walkers(s, 7, 44)
-    _compare_fp64(f"{n_up}+{n_down} electrons fp64 7", s, a, p, r)
+    got, ref = _compare_fp64(f"{n_up}+{n_down} electrons fp64 7", s, a, p, r)
+    plan = _q().Plan([s], [7], a, "fp64")
+    lp, sg = plan.logpsi(dev(p), dev(r))
+    torch.cuda.synchronize()
+    ok = ~flagged(r, p, s, a)
+    assert rel_err(host(lp)[ok], ref["logpsi"][ok]).max() < 1e-10
+    np.testing.assert_array_equal(host(sg)[ok], ref["sign"][ok])
+
+
+@pytest.mark.parametrize("n", [1, 5, 8, 9, 16, 17, 32])
+def test_det_jets_matrix_sizes(n):
+    """Determinant stage on random matrix jets at every lane-group size (8, 16, 32 lanes per matrix,
+    ragged tail of matrices): log|det|, sign, tr(A^-1 dA) and tr(A^-1 lapA) - sum tr((A^-1 dA)^2)
+    against numpy in float64; a matrix with a zero row is reported singular."""
+    rng = np.random.default_rng(100 + n)
+    nmat, T = 37, 5
+    J = rng.standard_normal((nmat, T + 2, n, n))
+    J[:, 0] += 2.0 * np.eye(n)
+    J[3, 0, n // 2] = 0.0
+    ld, sg, g, lap = _q().det_jets(dev(J), n, T)
+    torch.cuda.synchronize()
+    A, dA, L = J[:, 0], J[:, 1:T + 1], J[:, T + 1]
+    rs, rl = np.linalg.slogdet(A)
+    live = np.arange(nmat) != 3
+    X = np.linalg.solve(A[live][:, None], dA[live])
+    rg = np.trace(X, axis1=-2, axis2=-1)
+    rlap = np.trace(np.linalg.solve(A[live], L[live]), axis1=-2, axis2=-1) - np.einsum("mtab,mtba->m", X, X)
+    cond = np.linalg.cond(A[live])
+    print(f"[det n={n}] max cond {cond.max():.1e}", flush=True)
+    np.testing.assert_array_equal(host(sg)[live], rs[live])
+    assert np.abs(host(ld)[live] - rl[live]).max() < 1e-11 * max(1.0, np.abs(rl).max())
+    assert np.abs(host(g)[live] - rg).max() < 1e-10 * max(1.0, np.abs(rg).max())
+    assert np.abs(host(lap)[live] - rlap).max() < 1e-10 * max(1.0, np.abs(rlap).max())
+    assert host(ld)[3] == -np.inf and host(sg)[3] == 0.0
+    assert np.all(host(g)[3] == 0.0) and host(lap)[3] == 0.0
 
 
 def test_n2_ansatz_fp32_subset_mha():
