@@ -323,8 +323,7 @@ static WgradArgs wg(const void* X, int64_t ldx, const void* G, int64_t ldg, int6
   a.Nout = Nout;
   a.ones = 1;
   a.part = (double*)(ws + B.wpart);
-  a.rows_per_split = B.rows_per_split;
-  a.max_split = B.max_split;
+  a.part_elems = B.wpart_elems;
   return a;
 }
 

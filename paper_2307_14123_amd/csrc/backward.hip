@@ -10,7 +10,10 @@
 // z_bar = t_bar (1 - t^2).  Parameter gradients are sums over walkers and
 // electrons: they are formed as split-row MFMA reductions whose partial sums
 // are added in float64 in a fixed order (deterministic).
+#include <algorithm>
 #include <cmath>
+#include <cstdint>
+#include <cstdlib>
 #include <type_traits>
 
 #include "kernels.h"
@@ -102,38 +105,217 @@ __global__ __launch_bounds__(256) void wgrad_kernel(WgradArgs a) {
       }
 }
 
-// gW[m][n] += sum_split part (m < Kin), gb[n] += row Kin (bias), in split order
-__global__ void wgrad_reduce_kernel(const double* __restrict__ part, int nsplit, int Kin, int ones, int Nout,
-                                    double* __restrict__ gW, int64_t ldgw, double* __restrict__ gb) {
+// float32 weight gradients with whole-width tiles: a block owns a BM x 128 tile of W_bar for
+// one split of the rows, so every input row is read by one block per output tile (D = 128:
+// once).  Rows stream through LDS 32 at a time in two stages (the next rows are loaded into
+// registers while the current ones feed the MFMAs, one barrier per step); float4 loads.
+// The bias gradient (column sums of G) is accumulated by the first row of tiles from the
+// same LDS rows, so the output tile carries no extra row of ones.
+template <int BM>
+__global__ __launch_bounds__(256) void wgrad_f32_kernel(WgradArgs a) {
+  constexpr int BN = 128, BR = 32;
+  constexpr int WGM = BM == 128 ? 2 : 1, WGN = 4 / WGM;
+  constexpr int WTM = BM / WGM, WTN = BN / WGN;
+  constexpr int TM = WTM / 16, TN = WTN / 16;
+  constexpr int XL = BM + 4, GL = BN + 4;
+  constexpr int XV = BR * BM / 4 / 256, GV = BR * BN / 4 / 256;
+  __shared__ __attribute__((aligned(16))) float Xs[2][BR * XL];
+  __shared__ __attribute__((aligned(16))) float Gs[2][BR * GL];
+  __shared__ float bsum[2][BN];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave / WGN, wn = wave % WGN;
+  const int g = lane >> 4, c = lane & 15;
+  const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
+  const int split = blockIdx.z;
+  const int64_t r0 = (int64_t)split * a.rows_per_split;
+  const int64_t r1 = r0 + a.rows_per_split < a.rows ? r0 + a.rows_per_split : a.rows;
+  const float* X = (const float*)a.X;
+  const float* G = (const float*)a.G;
+  const bool bias = a.ones && blockIdx.x == 0;
+  const int Mtot = a.Kin + (a.ones ? 1 : 0);
+  float* part = (float*)a.part;  // float32 partial sums: each is a float32 MFMA accumulation, stored exactly
+
+  f4 xv[XV], gv[GV];
+  auto load = [&](int64_t rb) {
+#pragma unroll
+    for (int i = 0; i < XV; ++i) {
+      const int f = tid + 256 * i, row = f / (BM / 4), m = m0 + 4 * (f % (BM / 4));
+      const int64_t r = rb + row;
+      f4 v = {0.f, 0.f, 0.f, 0.f};
+      if (r < r1 && m < a.Kin) {
+        const uint32_t q = (uint32_t)r / (uint32_t)a.xrpw, rem = (uint32_t)r - q * (uint32_t)a.xrpw;
+        v = *(const f4*)(X + (int64_t)q * a.xws + (int64_t)rem * a.ldx + m);
+      }
+      xv[i] = v;
+    }
+#pragma unroll
+    for (int i = 0; i < GV; ++i) {
+      const int f = tid + 256 * i, row = f / (BN / 4), n = n0 + 4 * (f % (BN / 4));
+      const int64_t r = rb + row;
+      f4 v = {0.f, 0.f, 0.f, 0.f};
+      if (r < r1 && n < a.Nout) {
+        const uint32_t q = (uint32_t)r / (uint32_t)a.grpw, rem = (uint32_t)r - q * (uint32_t)a.grpw;
+        v = *(const f4*)(G + (int64_t)q * a.gws + (int64_t)rem * a.ldg + n);
+      }
+      gv[i] = v;
+    }
+  };
+  auto store = [&](int st) {
+#pragma unroll
+    for (int i = 0; i < XV; ++i) {
+      const int f = tid + 256 * i;
+      *(f4*)&Xs[st][(f / (BM / 4)) * XL + 4 * (f % (BM / 4))] = xv[i];
+    }
+#pragma unroll
+    for (int i = 0; i < GV; ++i) {
+      const int f = tid + 256 * i;
+      *(f4*)&Gs[st][(f / (BN / 4)) * GL + 4 * (f % (BN / 4))] = gv[i];
+    }
+  };
+
+  f4 acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+  float bs = 0.f;
+  const int bcol = tid & (BN - 1), bhalf = tid >> 7;
+  if (r0 < r1) {
+    load(r0);
+    store(0);
+  }
+  __syncthreads();
+  int st = 0;
+  for (int64_t rb = r0; rb < r1; rb += BR) {
+    const bool more = rb + BR < r1;
+    if (more) load(rb + BR);
+#pragma unroll
+    for (int kq = 0; kq < BR / 4; ++kq) {
+      float av[TM], bv[TN];
+#pragma unroll
+      for (int i = 0; i < TM; ++i) av[i] = Xs[st][(4 * kq + g) * XL + wm * WTM + 16 * i + c];
+#pragma unroll
+      for (int j = 0; j < TN; ++j) bv[j] = Gs[st][(4 * kq + g) * GL + wn * WTN + 16 * j + c];
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i], bv[j], acc[i][j], 0, 0, 0);
+    }
+    if (bias) {
+#pragma unroll
+      for (int rr = 0; rr < BR / 2; ++rr) bs += Gs[st][(bhalf * (BR / 2) + rr) * GL + bcol];
+    }
+    if (more) store(st ^ 1);
+    __syncthreads();
+    st ^= 1;
+  }
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int m = m0 + wm * WTM + 16 * i + 4 * g + e;
+        const int n = n0 + wn * WTN + 16 * j + c;
+        if (m < a.Kin && n < a.Nout) part[((int64_t)split * Mtot + m) * a.Nout + n] = acc[i][j][e];
+      }
+  if (bias) {
+    bsum[bhalf][bcol] = bs;
+    __syncthreads();
+    const int n = n0 + tid;
+    if (tid < BN && n < a.Nout) part[((int64_t)split * Mtot + a.Kin) * a.Nout + n] = bsum[0][tid] + bsum[1][tid];
+  }
+}
+
+// gW[m][n] += sum_split part (m < Kin), gb[n] += row Kin (bias).  Four waves per 64 outputs,
+// wave q summing splits q, q + 4, ...; the four sums are added in a fixed order (deterministic).
+template <typename P>
+__global__ __launch_bounds__(256) void wgrad_reduce_kernel(const P* __restrict__ part, int nsplit, int Kin, int ones,
+                                                           int Nout, double* __restrict__ gW, int64_t ldgw,
+                                                           double* __restrict__ gb) {
+  __shared__ double red[4][64];
   const int Mtot = Kin + (ones ? 1 : 0);
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= (int64_t)Mtot * Nout) return;
-  const int m = (int)(t / Nout), n = (int)(t % Nout);
+  const int64_t tot = (int64_t)Mtot * Nout;
+  const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
+  const int64_t t = (int64_t)blockIdx.x * 64 + lane;
   double s = 0.0;
-  for (int k = 0; k < nsplit; ++k) s += part[((int64_t)k * Mtot + m) * Nout + n];
+  if (t < tot) {
+#pragma unroll 4
+    for (int k = q; k < nsplit; k += 4) s += (double)part[(int64_t)k * tot + t];
+  }
+  red[q][lane] = s;
+  __syncthreads();
+  if (q != 0 || t >= tot) return;
+  s = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
+  const int m = (int)(t / Nout), n = (int)(t % Nout);
   if (m < Kin)
     gW[(int64_t)m * ldgw + n] += s;
   else
     gb[n] += s;
 }
 
-hipError_t launch_wgrad(GemmKind kind, const WgradArgs& a, double* gW, int64_t ldgw, double* gb, hipStream_t st) {
-  if (a.rows <= 0) return hipSuccess;
+static int backward_cus() {
+  static int cus = 0;
+  if (cus == 0) {
+    int dev = 0, n = 0;
+    cus = (hipGetDevice(&dev) == hipSuccess &&
+           hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && n > 0)
+              ? n
+              : 256;
+  }
+  return cus;
+}
+
+static bool wgrad_f32_tiles_ok(const WgradArgs& a) {
+  auto al = [](const void* p) { return ((uintptr_t)p & 15) == 0; };
+  return a.Kin % 4 == 0 && a.Nout % 4 == 0 && a.ldx % 4 == 0 && a.ldg % 4 == 0 && a.xws % 4 == 0 &&
+         a.gws % 4 == 0 && al(a.X) && al(a.G) && a.xrpw > 0 && a.grpw > 0 && a.xrpw <= INT32_MAX &&
+         a.grpw <= INT32_MAX && a.rows <= INT32_MAX;
+}
+
+hipError_t launch_wgrad(GemmKind kind, const WgradArgs& a0, double* gW, int64_t ldgw, double* gb, hipStream_t st) {
+  if (a0.rows <= 0) return hipSuccess;
+  WgradArgs a = a0;
   const int Mtot = a.Kin + (a.ones ? 1 : 0);
-  const int nsplit = (int)((a.rows + a.rows_per_split - 1) / a.rows_per_split);
-  if (nsplit > a.max_split) return hipErrorInvalidValue;
-  dim3 grid((unsigned)((Mtot + 63) / 64), (unsigned)((a.Nout + 63) / 64), (unsigned)nsplit);
+  const bool tiles = kind == GK_F32 && wgrad_f32_tiles_ok(a);
+  const int bm = !tiles ? 64 : (a.Kin <= 32 ? 32 : (a.Kin <= 64 ? 64 : 128));
+  const int mt = tiles ? (a.Kin + bm - 1) / bm : (Mtot + 63) / 64;
+  const int nt = tiles ? (a.Nout + 127) / 128 : (a.Nout + 63) / 64;
+  // splits: about two blocks per compute unit, at least 256 rows each, within the partial-sum buffer
+  // float32 tiles store float32 partials: twice as many fit
+  const int64_t cap = (tiles ? 2 * a.part_elems : a.part_elems) / ((int64_t)Mtot * a.Nout);
+  static const int per_cu = [] {
+    const char* e = std::getenv("QMC_WGRAD_BLOCKS_PER_CU");  // tuning knob, default 2
+    const int v = e ? std::atoi(e) : 2;
+    return v >= 1 && v <= 8 ? v : 2;
+  }();
+  int64_t nsplit = std::min<int64_t>((per_cu * backward_cus() + mt * nt - 1) / (mt * nt), (a.rows + 255) / 256);
+  nsplit = std::max<int64_t>(1, std::min<int64_t>(nsplit, cap));
+  a.rows_per_split = ((a.rows + nsplit - 1) / nsplit + 31) / 32 * 32;
+  nsplit = (a.rows + a.rows_per_split - 1) / a.rows_per_split;
+  if (cap < 1 || nsplit > cap || nsplit > 65535) return hipErrorInvalidValue;
+  dim3 grid((unsigned)mt, (unsigned)nt, (unsigned)nsplit);
   {
     ProfScope ps(kind == GK_F64 ? "wgrad_kernel<f64>" : "wgrad_kernel<f32>", st);
     if (kind == GK_F64)
       hipLaunchKernelGGL(wgrad_kernel<GK_F64>, grid, dim3(256), 0, st, a);
-    else
+    else if (!tiles)
       hipLaunchKernelGGL(wgrad_kernel<GK_F32>, grid, dim3(256), 0, st, a);
+    else if (bm == 32)
+      hipLaunchKernelGGL(wgrad_f32_kernel<32>, grid, dim3(256), 0, st, a);
+    else if (bm == 64)
+      hipLaunchKernelGGL(wgrad_f32_kernel<64>, grid, dim3(256), 0, st, a);
+    else
+      hipLaunchKernelGGL(wgrad_f32_kernel<128>, grid, dim3(256), 0, st, a);
   }
   const int64_t n = (int64_t)Mtot * a.Nout;
   ProfScope ps("wgrad_reduce_kernel", st);
-  hipLaunchKernelGGL(wgrad_reduce_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a.part, nsplit, a.Kin,
-                     a.ones, a.Nout, gW, ldgw, gb);
+  if (tiles)
+    hipLaunchKernelGGL(wgrad_reduce_kernel<float>, dim3((unsigned)((n + 63) / 64)), dim3(256), 0, st,
+                       (const float*)a.part, (int)nsplit, a.Kin, a.ones, a.Nout, gW, ldgw, gb);
+  else
+    hipLaunchKernelGGL(wgrad_reduce_kernel<double>, dim3((unsigned)((n + 63) / 64)), dim3(256), 0, st,
+                       (const double*)a.part, (int)nsplit, a.Kin, a.ones, a.Nout, gW, ldgw, gb);
   return hipGetLastError();
 }
 

@@ -143,9 +143,9 @@ struct WgradArgs {
   int64_t ldg, grpw, gws;
   int64_t rows;
   int Kin, Nout, ones;
-  double* part;
-  int64_t rows_per_split;
-  int max_split;
+  double* part;           // partial sums, [split][Kin + ones][Nout]
+  int64_t part_elems;     // capacity of part (elements); the launcher picks the splits within it
+  int64_t rows_per_split;  // set by launch_wgrad
 };
 hipError_t launch_wgrad(GemmKind kind, const WgradArgs& a, double* gW, int64_t ldgw, double* gb, hipStream_t st);
 
