@@ -16,9 +16,10 @@
 // A persistent grid keeps U2 (transposed, 16-byte chunks XOR-swizzled by row
 // against LDS bank conflicts) and U1, a1, a2 in LDS; each wave takes 16 pair
 // rows at a time.  The radial basis is evaluated in float64 and rounded, as
-// in the separate basis kernel.
+// in the separate basis kernel; tanh is the float32 form of act.h.
 #include <algorithm>
 
+#include "act.h"
 #include "kernels.h"
 #include "pairs.h"
 
@@ -36,6 +37,7 @@ __global__ __launch_bounds__(256) void edge_mlp_kernel(SysDev s, EdgeMlpArgs a) 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int g = lane >> 4, c = lane & 15;
   const int K = s.K;
+  const double rs = rbf_spacing(s.dmax, K), ris = (K - 1) / s.dmax;
   for (int e = tid; e < ED * ED; e += 256) {
     const int k = e / ED, n = e - k * ED;
     u2t[n * ED + (((k >> 2) ^ (n & 7)) << 2) + (k & 3)] = a.U2[e];
@@ -71,7 +73,7 @@ __global__ __launch_bounds__(256) void edge_mlp_kernel(SysDev s, EdgeMlpArgs a) 
         const int r = 4 * g + kq;
         if (r < K) {
           double r0, r1, r2;
-          rbf3(d, r, s.dmax, K, r0, r1, r2);
+          rbf3(d, r, rs, ris, r0, r1, r2);
           rb[kq] = (float)(e == 0 ? r0 : (e == 1 ? r1 : r2));
         }
       }
@@ -99,10 +101,10 @@ __global__ __launch_bounds__(256) void edge_mlp_kernel(SysDev s, EdgeMlpArgs a) 
         const float zi = z[hb][i];
         if constexpr (JET) {
           const float z0 = __shfl(zi, qbase), z1 = __shfl(zi, qbase + 1), z2 = __shfl(zi, qbase + 2);
-          const float t = tanhf(z0), t1 = 1.f - t * t, t2 = -2.f * t * t1;
+          const float t = tanh_f32(z0), t1 = 1.f - t * t, t2 = -2.f * t * t1;
           z[hb][i] = e == 0 ? t : (e == 1 ? t1 * z1 : (e == 2 ? t1 * z2 + t2 * z1 * z1 : 0.f));
         } else {
-          z[hb][i] = tanhf(zi);
+          z[hb][i] = tanh_f32(zi);
         }
       }
     if (!JET && a.zout && row < rows) {

@@ -40,6 +40,7 @@
 #include <cstring>
 #include <type_traits>
 
+#include "act.h"
 #include "kernels.h"
 
 namespace qmc {
@@ -74,7 +75,7 @@ template <> struct V4<double> {
 };
 
 __device__ inline double dtanh(double x) { return tanh(x); }
-__device__ inline float dtanh(float x) { return tanhf(x); }
+__device__ inline float dtanh(float x) { return tanh_f32(x); }
 
 constexpr int cmax(int a, int b) { return a > b ? a : b; }
 

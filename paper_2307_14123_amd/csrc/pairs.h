@@ -8,12 +8,14 @@
 
 namespace qmc {
 
-__device__ inline void rbf3(double d, int k, double dmax, int K, double& r0, double& r1, double& r2) {
-  const double s = dmax / (K - 1);
-  const double x = (d - k * s) / s;
+// s = dmax / (K - 1) is the spacing (and width) of the Gaussians, inv_s its reciprocal
+__device__ inline double rbf_spacing(double dmax, int K) { return dmax / (K - 1); }
+
+__device__ inline void rbf3(double d, int k, double s, double inv_s, double& r0, double& r1, double& r2) {
+  const double x = (d - k * s) * inv_s;
   r0 = exp(-x * x);
-  r1 = -2.0 * x / s * r0;
-  r2 = (4.0 * x * x - 2.0) / (s * s) * r0;
+  r1 = -2.0 * x * inv_s * r0;
+  r2 = (4.0 * x * x - 2.0) * (inv_s * inv_s) * r0;
 }
 
 // unordered pair index of electrons i != j inside their edge type (0 same-spin, 1 up-down)
