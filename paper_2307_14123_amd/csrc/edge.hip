@@ -14,10 +14,12 @@
 // group) with quad shuffles: t = tanh(z0), t' z1, t' z2 + t'' z1^2.
 //
 // A persistent grid keeps U2 (transposed, 16-byte chunks XOR-swizzled by row
-// against LDS bank conflicts) and U1, a1, a2 in LDS; each wave takes 16 pair
-// rows at a time.  The radial basis is evaluated in float64 and rounded, as
-// in the separate basis kernel; tanh is the float32 form of act.h.
+// against LDS bank conflicts) and U1, a1, a2 in LDS, one copy per block of 12
+// waves (three per SIMD); each wave takes 16 pair rows at a time.  The radial
+// basis is evaluated in float64 and rounded, as in the separate basis kernel;
+// tanh is the float32 form of act.h.
 #include <algorithm>
+#include <cstdlib>
 
 #include "act.h"
 #include "kernels.h"
@@ -29,8 +31,8 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 
 constexpr int ED = 128;  // filter width handled here
 
-template <int JET>
-__global__ __launch_bounds__(256) void edge_mlp_kernel(SysDev s, EdgeMlpArgs a) {
+template <int JET, int NW>
+__global__ __launch_bounds__(64 * NW) void edge_mlp_kernel(SysDev s, EdgeMlpArgs a) {
   __shared__ __attribute__((aligned(16))) float u2t[ED * ED];  // U2^T (n, k), chunk (k/4) ^ (n & 7)
   __shared__ __attribute__((aligned(16))) float u1t[ED * 16];  // U1^T (k, r), r < 16
   __shared__ float a1s[ED], a2s[ED];
@@ -38,15 +40,15 @@ __global__ __launch_bounds__(256) void edge_mlp_kernel(SysDev s, EdgeMlpArgs a) 
   const int g = lane >> 4, c = lane & 15;
   const int K = s.K;
   const double rs = rbf_spacing(s.dmax, K), ris = (K - 1) / s.dmax;
-  for (int e = tid; e < ED * ED; e += 256) {
+  for (int e = tid; e < ED * ED; e += 64 * NW) {
     const int k = e / ED, n = e - k * ED;
     u2t[n * ED + (((k >> 2) ^ (n & 7)) << 2) + (k & 3)] = a.U2[e];
   }
-  for (int e = tid; e < ED * 16; e += 256) {
+  for (int e = tid; e < ED * 16; e += 64 * NW) {
     const int k = e >> 4, r = e & 15;
     u1t[e] = r < K ? a.U1[r * ED + k] : 0.f;
   }
-  for (int e = tid; e < ED; e += 256) {
+  for (int e = tid; e < ED; e += 64 * NW) {
     a1s[e] = a.a1[e];
     a2s[e] = a.a2[e];
   }
@@ -55,7 +57,7 @@ __global__ __launch_bounds__(256) void edge_mlp_kernel(SysDev s, EdgeMlpArgs a) 
   const int P = a.type == 0 ? s.P0 : (a.type == 1 ? s.P1 : s.P2);
   const int64_t rows = JET ? a.pairs * 4 : a.pairs;
   const int64_t ntiles = (rows + 15) / 16;
-  for (int64_t tile = (int64_t)blockIdx.x * 4 + wave; tile < ntiles; tile += (int64_t)gridDim.x * 4) {
+  for (int64_t tile = (int64_t)blockIdx.x * NW + wave; tile < ntiles; tile += (int64_t)gridDim.x * NW) {
     const int64_t row0 = tile * 16;
     // ---- this lane's pair row (column c of the first layer)
     const int64_t row = row0 + c;
@@ -149,23 +151,40 @@ hipError_t launch_edge_mlp(const SysDev& s, const EdgeMlpArgs& a, hipStream_t st
   if (!edge_mlp_supported(s) || a.pairs < 0 || a.type < 0 || a.type > 2) return hipErrorInvalidValue;
   if (a.pairs == 0) return hipSuccess;
   if (a.jet && a.zout) return hipErrorInvalidValue;
-  static int cus = 0;
+  static int cus = 0, nw = 0;
   if (cus == 0) {
     int dev = 0, n = 0;
     cus = (hipGetDevice(&dev) == hipSuccess &&
            hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && n > 0)
               ? n
               : 256;
+    // waves per block: 12 (three per SIMD, one block per compute unit: the VGPR budget) by default;
+    // QMC_EDGE_WAVES=4 for two blocks of 4 (a tuning knob)
+    const char* e = std::getenv("QMC_EDGE_WAVES");
+    nw = e && std::atoi(e) == 4 ? 4 : 12;
   }
   const int64_t rows = a.jet ? a.pairs * 4 : a.pairs;
   const int64_t tiles = (rows + 15) / 16;
-  // two blocks (73 KB of LDS each) per compute unit, each walking tiles with a grid stride
-  const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>((tiles + 3) / 4, 2 * (int64_t)cus));
+  // blocks of nw waves share one copy of the weights in LDS (73 KB); as many blocks as fit per
+  // compute unit, each walking tiles with a grid stride
+  auto go = [&](auto kern, int w) {
+    int occ = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, 64 * w, 0) != hipSuccess || occ < 1) occ = 1;
+    const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>((tiles + w - 1) / w, (int64_t)occ * cus));
+    hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(64 * w), 0, st, s, a);
+  };
   ProfScope ps(a.jet ? "edge_mlp_kernel<jet>" : "edge_mlp_kernel<val>", st);
-  if (a.jet)
-    hipLaunchKernelGGL(edge_mlp_kernel<1>, dim3((unsigned)blocks), dim3(256), 0, st, s, a);
-  else
-    hipLaunchKernelGGL(edge_mlp_kernel<0>, dim3((unsigned)blocks), dim3(256), 0, st, s, a);
+  if (a.jet) {
+    if (nw == 4)
+      go(edge_mlp_kernel<1, 4>, 4);
+    else
+      go(edge_mlp_kernel<1, 12>, 12);
+  } else {
+    if (nw == 4)
+      go(edge_mlp_kernel<0, 4>, 4);
+    else
+      go(edge_mlp_kernel<0, 12>, 12);
+  }
   return hipGetLastError();
 }
 
