@@ -36,7 +36,7 @@ def family(kernel_name: str) -> str:
         return "gemm_kernel<" + {"0": "val", "1": "edge", "2": "jet"}.get(targs[2], targs[2]) + ">"
     if name == "edge_mlp_kernel":
         return "edge_mlp_kernel<" + ("jet" if targs[0] == "1" else "val") + ">"
-    if name == "wgrad_kernel":
+    if name in ("wgrad_kernel", "wgrad_f32_kernel"):
         return "wgrad_kernel"
     return name
 
