@@ -18,6 +18,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -111,6 +112,34 @@ def stored_traffic(family, workload, precision):
         return None
 
 
+def dist(ms):
+    """median, p10 and p90 of per-repetition times (ms) from HIP events on the launch stream"""
+    v = np.asarray(ms, dtype=np.float64)
+    return {"median": float(np.median(v)), "p10": float(np.percentile(v, 10)), "p90": float(np.percentile(v, 90)),
+            "n": int(v.size)}
+
+
+def environment():
+    """GPU name, ROCm and driver versions, and the clock / power state rocm-smi reports."""
+    import subprocess
+    import torch
+    env = {"gpu": torch.cuda.get_device_name(0), "torch": torch.__version__}
+    for key, path in (("rocm", "/opt/rocm/.info/version"), ("amdgpu_driver", "/sys/module/amdgpu/version")):
+        try:
+            with open(path) as f:
+                env[key] = f.read().strip()
+        except OSError:
+            pass
+    try:
+        res = subprocess.run(["rocm-smi", "--showclocks", "--showpower"], capture_output=True, text=True, timeout=30)
+        keep = [ln.strip() for ln in res.stdout.splitlines()
+                if any(t in ln for t in ("sclk", "mclk", "fclk", "Power", "power")) and "====" not in ln]
+        env["rocm_smi"] = keep[:12]
+    except (OSError, subprocess.SubprocessError):
+        pass
+    return env
+
+
 def kernel_family(name):
     if name.startswith("gemm_kernel"):
         return "gemm_kernel<" + name.rstrip(">").split(",")[-1] + ">"
@@ -190,24 +219,38 @@ def main():
     qmc.profile_enable(True)
     qmc.profile_report(reset=True)
     torch.cuda.synchronize()
+    # HIP events on the launch stream around every step (and, through the profile switch, every launch)
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    evs[0].record()
+    for i in range(args.steps):
         step()
+        evs[i + 1].record()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     prof = qmc.profile_report(reset=True)
     qmc.profile_enable(False)
     ms_step = (t1 - t0) * 1e3 / args.steps
+    step_ms = [evs[i].elapsed_time(evs[i + 1]) for i in range(args.steps)]
 
-    # local energy alone
-    reps = max(3, args.steps)
+    # local energy alone: at least 50 repetitions or 1 s (at most 60), each between two HIP events
     plan.local_energy(P, R, out=out)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(reps):
+    plan.local_energy(P, R, out=out)
+    torch.cuda.synchronize()
+    est = (time.perf_counter() - t0) * 1e3
+    reps = int(min(60, max(50 if est < 20 else 1, args.steps, math.ceil(1000.0 / max(est, 1e-3)))))
+    lev = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
+    t0 = time.perf_counter()
+    lev[0].record()
+    for i in range(reps):
         plan.local_energy(P, R, out=out)
+        lev[i + 1].record()
     torch.cuda.synchronize()
     ms_le = (time.perf_counter() - t0) * 1e3 / reps
+    le_ms = [lev[i].elapsed_time(lev[i + 1]) for i in range(reps)]
+    peaks = qmc.measure_peaks()
 
     eb = 8 if args.precision == "fp64" else 4
     fused = args.precision == "fp32" and a.width == 128 and a.n_rbf <= 16
@@ -236,6 +279,11 @@ def main():
             roof = {"bound": "hbm", "achieved": per_launch / avg_s / 1e9, "peak": PEAK["hbm"] / 1e9, "unit": "GB/s"}
         roof["frac"] = roof["achieved"] / roof["peak"]
         roof["traffic"] = stored_traffic(name, args.workload, args.precision)
+        mkey = {"mfma": gemm_dtype if roof["peak"] == PEAK[gemm_dtype] / 1e12 else "fp32_mfma", "hbm": "copy"}
+        pm = peaks.get(mkey.get(bound, ""))
+        if pm:
+            roof["peak_measured"] = pm
+            roof["frac_measured"] = roof["achieved"] / pm
         roof["kernel"] = name
         roof["launches_per_step"] = nl / args.steps
         roof["avg_launch_ms"] = tot_ms / nl
@@ -271,7 +319,12 @@ def main():
                    "loss_gradient_in_step": has_grad},
         "e_loc_per_s": W / (ms_le * 1e-3),
         "e_loc_ms": ms_le,
+        "step_ms_events": dist(step_ms),
+        "e_loc_ms_events": dist(le_ms),
         "roofline": roof,
+        "measured_peaks": {"fp32_mfma_tflops": peaks["fp32_mfma"], "bf16_mfma_tflops": peaks["bf16_mfma"],
+                           "fp64_mfma_tflops": peaks["fp64_mfma"], "copy_gbs": peaks["copy"]},
+        "env": environment(),
         "kernel_rooflines": others,
         "kernels_ms_per_step": {k: round(v[1] / args.steps, 3) for k, v in sorted(prof.items(), key=lambda kv: -kv[1][1])},
     }

@@ -213,6 +213,17 @@ qmc_status qmc_loss_grad(const qmc_plan* plan, const void* params, const double*
 qmc_status qmc_det_jets(int64_t n_mat, int32_t n, int32_t n_tan, const double* jets,
                         double* logdet, double* sign, double* grad, double* lap, void* stream);
 
+/* Achievable device peaks, the denominators of measured roofline fractions:
+ * peaks[0..2] = MFMA TFLOP/s of float32 16x16x4, bf16 16x16x32 and float64
+ * 16x16x4 instructions (register operands, independent accumulation chains,
+ * every compute unit busy), peaks[3] = GB/s of a plain device copy (bytes
+ * read + bytes written) between the two halves of scratch.  scratch: device
+ * buffer owned by the caller, 16-byte aligned, 64 MiB to 16 GiB (its contents
+ * are overwritten; 512 MiB or more measures HBM rather than cache); peaks:
+ * host double[4].  Synchronises the stream (it times itself with HIP events
+ * on it); a measurement utility, not part of the method. */
+qmc_status qmc_measure_peaks(void* scratch, size_t scratch_bytes, double* peaks, void* stream);
+
 /* Launch timing for measurement.  While enabled (process-wide), every kernel
  * launch is bracketed by a pair of HIP events on its stream.
  * qmc_profile_report waits for the recorded events and writes one line per

@@ -17,7 +17,7 @@ LIB = os.path.join(HERE, "libqmc.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["host.cpp", "api.hip", "gemm.hip", "ops.hip", "backward.hip", "edge.hip"]
+SOURCES = ["host.cpp", "api.hip", "gemm.hip", "ops.hip", "backward.hip", "edge.hip", "peaks.hip"]
 
 COMMON = ["-O3", "-fPIC", "-std=c++17", f"-I{INCLUDE}", f"-I{CSRC}"]
 DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

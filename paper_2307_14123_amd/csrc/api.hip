@@ -727,6 +727,14 @@ qmc_status qmc_det_jets(int64_t n_mat, int32_t n, int32_t n_tan, const double* j
   return QMC_OK;
 }
 
+qmc_status qmc_measure_peaks(void* scratch, size_t scratch_bytes, double* peaks, void* stream) {
+  if (!scratch || !peaks || scratch_bytes < (size_t(64) << 20) || scratch_bytes > (size_t(16) << 30) ||
+      (reinterpret_cast<uintptr_t>(scratch) & 15) != 0)
+    return QMC_ERR_INVALID_ARGUMENT;
+  CK(measure_peaks(scratch, scratch_bytes, peaks, (hipStream_t)stream));
+  return QMC_OK;
+}
+
 }  // extern "C"
 
 extern "C" {

@@ -118,6 +118,9 @@ hipError_t launch_det(const SysDev& s, const S* ajet, int64_t W, int jet, double
                       double* g, double* lap, double* ainv, hipStream_t st);
 
 // Generic batched determinant jets (float64), one n x n problem per matrix.
+// Achievable peaks (float32, bf16 and float64 MFMA TFLOP/s; copy GB/s read + written) measured on the
+// device with the caller's scratch buffer; synchronises the stream.
+hipError_t measure_peaks(void* scratch, size_t bytes, double* out, hipStream_t st);
 hipError_t launch_det_generic(int64_t nmat, int n, int ntan, const double* jets, double* ld,
                               double* sg, double* g, double* lap, hipStream_t st);
 

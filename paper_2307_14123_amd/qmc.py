@@ -68,6 +68,8 @@ def lib():
     L.qmc_loss_grad.argtypes = [vp, vp, dp, dp, vp, dp, vp, sz, vp]
     L.qmc_det_jets.restype = i32
     L.qmc_det_jets.argtypes = [i64, i32, i32, dp, dp, dp, dp, dp, vp]
+    L.qmc_measure_peaks.restype = i32
+    L.qmc_measure_peaks.argtypes = [vp, sz, ctypes.POINTER(ctypes.c_double), vp]
     L.qmc_profile_enable.restype = i32
     L.qmc_profile_enable.argtypes = [i32]
     L.qmc_profile_report.restype = i32
@@ -300,6 +302,16 @@ def det_jets(jets, n: int, n_tan: int):
     _check(lib().qmc_det_jets(nmat, n, n_tan, _ptr(jets), _ptr(ld), _ptr(sg), _ptr(g), _ptr(lap), _stream()),
            "qmc_det_jets")
     return ld, sg, g[:nmat * n_tan].reshape(nmat, n_tan), lap
+
+
+def measure_peaks(scratch_bytes: int = 1 << 30) -> dict:
+    """Achievable device peaks from qmc_measure_peaks, on a scratch tensor allocated here:
+    {"fp32_mfma", "bf16_mfma", "fp64_mfma"} in TFLOP/s and "copy" in GB/s (read + write)."""
+    buf = torch.empty(scratch_bytes // 4, dtype=torch.float32, device="cuda")
+    out = (ctypes.c_double * 4)()
+    _check(lib().qmc_measure_peaks(_ptr(buf), buf.numel() * 4, out, _stream()), "qmc_measure_peaks")
+    del buf
+    return {"fp32_mfma": out[0], "bf16_mfma": out[1], "fp64_mfma": out[2], "copy": out[3]}
 
 
 def profile_enable(on: bool = True):

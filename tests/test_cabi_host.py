@@ -125,3 +125,14 @@ def test_plan_flags_and_tiles():
     finally:
         L.qmc_plan_destroy(handle)
 
+
+
+def test_measure_peaks_rejects_bad_scratch():
+    """qmc_measure_peaks validates its scratch buffer on the host before touching the device."""
+    qmc, L = _lib()
+    out = (ctypes.c_double * 4)()
+    bad = [(None, 1 << 30), (ctypes.c_void_p(1 << 20), 1 << 10), (ctypes.c_void_p((1 << 20) + 4), 1 << 30),
+           (ctypes.c_void_p(1 << 20), 1 << 40)]
+    for ptr, n in bad:
+        assert L.qmc_measure_peaks(ptr, n, out, None) == 1  # QMC_ERR_INVALID_ARGUMENT
+    assert L.qmc_measure_peaks(ctypes.c_void_p(1 << 20), 1 << 30, None, None) == 1
