@@ -206,12 +206,19 @@ def main():
         has_grad = False
     torch.cuda.synchronize()
 
+    G = torch.empty_like(P)
+    EM = torch.empty(1, dtype=torch.float64, device=dev)
+    # plain gradient descent; its cost does not depend on lr, kept small so that the network stays near its
+    # seeded initialisation over the warm-up and timed steps
+    lr = 1e-8
+
     def step():
         for t in range(n_mc):
             plan.metropolis_step(P, R, lp, NOISE[t], U[t], tau, accepted=acc)
         plan.local_energy(P, R, out=out)
         if has_grad:
-            plan.loss_grad(P, R, out["e_loc"])
+            plan.loss_grad(P, R, out["e_loc"], grad=G, e_mean=EM)
+            plan.sgd_update(P, G, lr)
 
     for _ in range(args.warmup):
         step()
@@ -314,7 +321,8 @@ def main():
                                 "h2": "H2: 2 x Z=1 at 1.4 bohr, 1 up + 1 down"}[args.workload] + f", {W} walkers, "
                                f"{a.mp_layers} message-passing layers width {a.width}, {a.n_det} dets, "
                                f"{a.n_env} envelope exponents; step = {n_mc} Metropolis steps (tau {tau}) + "
-                               f"local energy" + (" + loss gradient" if has_grad else ""),
+                               f"local energy" + (" + loss gradient + gradient-descent update (lr 1e-8)"
+                                                  if has_grad else ""),
                    "walkers": W, "electrons": s.n_elec, "precision": args.precision,
                    "loss_gradient_in_step": has_grad},
         "e_loc_per_s": W / (ms_le * 1e-3),
@@ -341,7 +349,8 @@ def main():
             rs, lp_c, _, _ = oracle.metropolis_step(rs, lp_c, noise[t, :nw], uni[t, :nw], tau, pc, s, a)
         ref = oracle.local_energy(rs, pc, s, a, chunk=16)
         if has_grad:
-            oracle.loss_grad(rs, ref["e_loc"], pc, s, a)
+            gc = oracle.loss_grad(rs, ref["e_loc"], pc, s, a)[0]
+            pc_next = pc - lr * gc  # the gradient-descent update of the step
         tc = time.perf_counter() - t0
         res["cpu_baseline"] = {"value": nw / tc, "unit": "walkers/s", "cores": torch.get_num_threads(),
                                "kind": "oracle",

@@ -213,6 +213,17 @@ qmc_status qmc_loss_grad(const qmc_plan* plan, const void* params, const double*
 qmc_status qmc_det_jets(int64_t n_mat, int32_t n, int32_t n_tan, const double* jets,
                         double* logdet, double* sign, double* grad, double* lap, void* stream);
 
+/* Optimizer step of a training iteration (plain gradient descent on the
+ * parameter blob, Sec. IV.A): params[i] -= lr * grad[i] for i < n, computed
+ * in float64 (product and difference each rounded, no fused multiply-add)
+ * and rounded to the io dtype of the precision (float64 for
+ * QMC_FP64, float32 otherwise).  params, grad: device, n elements each
+ * (grad as written by qmc_loss_grad); enqueued on stream.  Invalid
+ * arguments (n < 0, null pointers with n > 0, non-finite lr, unknown
+ * precision) return QMC_ERR_INVALID_ARGUMENT and launch nothing. */
+qmc_status qmc_sgd_update(int32_t precision, void* params, const void* grad, int64_t n, double lr,
+                          void* stream);
+
 /* Achievable device peaks, the denominators of measured roofline fractions:
  * peaks[0..2] = MFMA TFLOP/s of float32 16x16x4, bf16 16x16x32 and float64
  * 16x16x4 instructions (register operands, independent accumulation chains,

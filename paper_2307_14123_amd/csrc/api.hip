@@ -727,6 +727,17 @@ qmc_status qmc_det_jets(int64_t n_mat, int32_t n, int32_t n_tan, const double* j
   return QMC_OK;
 }
 
+qmc_status qmc_sgd_update(int32_t precision, void* params, const void* grad, int64_t n, double lr, void* stream) {
+  if (n < 0 || (n > 0 && (!params || !grad)) || !std::isfinite(lr)) return QMC_ERR_INVALID_ARGUMENT;
+  if (precision != QMC_FP64 && precision != QMC_FP32 && precision != QMC_BF16_MIXED) return QMC_ERR_INVALID_ARGUMENT;
+  if (n == 0) return QMC_OK;
+  if (precision == QMC_FP64)
+    CK(launch_sgd<double>(n, lr, (const double*)grad, (double*)params, (hipStream_t)stream));
+  else
+    CK(launch_sgd<float>(n, lr, (const float*)grad, (float*)params, (hipStream_t)stream));
+  return QMC_OK;
+}
+
 qmc_status qmc_measure_peaks(void* scratch, size_t scratch_bytes, double* peaks, void* stream) {
   if (!scratch || !peaks || scratch_bytes < (size_t(64) << 20) || scratch_bytes > (size_t(16) << 30) ||
       (reinterpret_cast<uintptr_t>(scratch) & 15) != 0)

@@ -344,6 +344,27 @@ __global__ void cast_kernel(int64_t n, const double* __restrict__ src, S* __rest
   if (i < n) dst[i] = (S)src[i];
 }
 
+// params[i] -= lr * grad[i] (the optimizer step of a training iteration: plain gradient descent)
+template <typename S>
+__global__ void sgd_kernel(int64_t n, double lr, const S* __restrict__ grad, S* __restrict__ params) {
+#pragma clang fp contract(off)  // a product, then a difference, each rounded (no fused multiply-add)
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    const double step = lr * (double)grad[i];
+    params[i] = (S)((double)params[i] - step);
+  }
+}
+
+template <typename S>
+hipError_t launch_sgd(int64_t n, double lr, const S* grad, S* params, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  ProfScope ps("sgd_kernel", st);
+  hipLaunchKernelGGL(sgd_kernel<S>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, lr, grad, params);
+  return hipGetLastError();
+}
+template hipError_t launch_sgd<float>(int64_t, double, const float*, float*, hipStream_t);
+template hipError_t launch_sgd<double>(int64_t, double, const double*, double*, hipStream_t);
+
 // dst[c] += sum_r src[r * ld + c]: rows split in chunks of 64 (one thread per
 // (chunk, column)), then the chunk sums are added in chunk order.
 __global__ void rowsum_partial_kernel(const double* __restrict__ src, int64_t R, int64_t C, int64_t ld,

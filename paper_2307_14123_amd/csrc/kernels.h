@@ -158,6 +158,8 @@ template <typename S>
 hipError_t launch_add(int64_t n, const S* a, const S* b, S* o, hipStream_t st);
 hipError_t launch_fill(int64_t n, double v, double* p, hipStream_t st);
 template <typename S>
+hipError_t launch_sgd(int64_t n, double lr, const S* grad, S* params, hipStream_t st);
+template <typename S>
 hipError_t launch_cast(int64_t n, const double* src, S* dst, hipStream_t st);
 hipError_t launch_rowsum(const double* src, int64_t R, int64_t C, int64_t ld, double* dst, double* scratch,
                          int64_t scratch_elems, hipStream_t st);

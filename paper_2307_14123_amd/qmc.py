@@ -68,6 +68,8 @@ def lib():
     L.qmc_loss_grad.argtypes = [vp, vp, dp, dp, vp, dp, vp, sz, vp]
     L.qmc_det_jets.restype = i32
     L.qmc_det_jets.argtypes = [i64, i32, i32, dp, dp, dp, dp, dp, vp]
+    L.qmc_sgd_update.restype = i32
+    L.qmc_sgd_update.argtypes = [i32, vp, vp, i64, ctypes.c_double, vp]
     L.qmc_measure_peaks.restype = i32
     L.qmc_measure_peaks.argtypes = [vp, sz, ctypes.POINTER(ctypes.c_double), vp]
     L.qmc_profile_enable.restype = i32
@@ -249,6 +251,17 @@ class Plan:
         _check(lib().qmc_loss_grad(self.handle, _ptr(params), _ptr(r), _ptr(e_loc), _ptr(g), _ptr(em), _ptr(ws),
                                    ws.numel(), _stream()), "qmc_loss_grad")
         return g, em
+
+    def sgd_update(self, params, grad, lr: float):
+        """params -= lr * grad on the device (the optimizer step of a training iteration)."""
+        if params.dtype != self.param_dtype or params.numel() != self.total_params or not params.is_contiguous():
+            raise ValueError("params: wrong dtype, size or layout")
+        if grad.dtype != params.dtype or grad.numel() != params.numel() or not grad.is_contiguous():
+            raise ValueError("grad: wrong dtype or size")
+        if not (params.is_cuda and grad.is_cuda):
+            raise ValueError("params and grad must be device tensors")
+        _check(lib().qmc_sgd_update(PRECISIONS[self.precision], _ptr(params), _ptr(grad), params.numel(), float(lr),
+                                    _stream()), "qmc_sgd_update")
 
 
 class GraphStep:

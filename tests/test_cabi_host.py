@@ -136,3 +136,14 @@ def test_measure_peaks_rejects_bad_scratch():
     for ptr, n in bad:
         assert L.qmc_measure_peaks(ptr, n, out, None) == 1  # QMC_ERR_INVALID_ARGUMENT
     assert L.qmc_measure_peaks(ctypes.c_void_p(1 << 20), 1 << 30, None, None) == 1
+
+
+def test_sgd_update_rejects_bad_arguments():
+    """qmc_sgd_update validates on the host before launching."""
+    qmc, L = _lib()
+    p = ctypes.c_void_p(1 << 20)
+    assert L.qmc_sgd_update(1, p, p, -1, 1e-3, None) == 1
+    assert L.qmc_sgd_update(1, None, p, 10, 1e-3, None) == 1
+    assert L.qmc_sgd_update(1, p, p, 10, float("nan"), None) == 1
+    assert L.qmc_sgd_update(7, p, p, 10, 1e-3, None) == 1
+    assert L.qmc_sgd_update(1, None, None, 0, 1e-3, None) == 0
