@@ -250,12 +250,14 @@ __global__ __launch_bounds__(512) void aggregate_kernel(SysDev s, const S* __res
     pt[e] = v;
   }
   __syncthreads();
-  const int d = chunk * DC + (int)(threadIdx.x % DC), g = threadIdx.x / DC;
+  const int dr = chunk * DC + (int)(threadIdx.x % DC), g = threadIdx.x / DC;
   const int ngu = (nup + RG - 1) / RG, ngd = (ndn + RG - 1) / RG;
-  if (d >= D || g >= ngu + ngd) return;  // no barriers below
+  // threads past the last column or group compute nothing (cnt = 0) but meet the barriers
+  const bool live = dr < D && g < ngu + ngd;
+  const int d = min(dr, D - 1);
   const bool up = g < ngu;
   const int i0 = up ? g * RG : nup + (g - ngu) * RG;
-  const int cnt = min(RG, (up ? nup : N) - i0);
+  const int cnt = live ? min(RG, (up ? nup : N) - i0) : 0;
   const int nsame = (up ? nup : ndn) - 1, nopp = up ? ndn : nup;
   const S inv_s = nsame > 0 ? S(1) / S(nsame) : S(0), inv_o = nopp > 0 ? S(1) / S(nopp) : S(0);
   // row r (0 value, 1 first, 2 second derivative) of the filter jet of pair (i, j), column d
@@ -385,8 +387,10 @@ __global__ __launch_bounds__(512) void aggregate_kernel(SysDev s, const S* __res
     for (int r = 0; r < RG; ++r)
       if (r < cnt) {
         S* o = mb + ((int64_t)(i0 + r) * Rp + q) * 2 * D;
-        o[0] = ms[r] * inv_s;
-        o[D] = mo[r] * inv_o;
+        // streaming stores: the messages are not read again here, so they should not take L2 lines
+        // from the sender rows that the other receiver groups of the block are about to read
+        __builtin_nontemporal_store(ms[r] * inv_s, o);
+        __builtin_nontemporal_store(mo[r] * inv_o, o + D);
       }
 #pragma unroll
     for (int sl = 0; sl < 2 * NS; ++sl) hv[sl] = nv[sl];
@@ -394,6 +398,9 @@ __global__ __launch_bounds__(512) void aggregate_kernel(SysDev s, const S* __res
     for (int r = 0; r < RG; ++r) cwp[r] = nwp[r];
     ch0 = nh0;
     chq = nhq;
+    // the receiver groups of a block read the same sender rows: a barrier every 8 rows keeps them
+    // close enough for the rows to be found in L2 by the later groups
+    if ((q & 7) == 7) __syncthreads();
   }
   // padding rows
   for (int q = T + 2; q < Rp; ++q)
@@ -401,8 +408,8 @@ __global__ __launch_bounds__(512) void aggregate_kernel(SysDev s, const S* __res
     for (int r = 0; r < RG; ++r)
       if (r < cnt) {
         S* o = mb + ((int64_t)(i0 + r) * Rp + q) * 2 * D;
-        o[0] = 0;
-        o[D] = 0;
+        __builtin_nontemporal_store(S(0), o);
+        __builtin_nontemporal_store(S(0), o + D);
       }
 }
 
@@ -729,7 +736,7 @@ hipError_t launch_aggregate(const SysDev& s, const S* h, const S* wsame, const S
 // A[a][k] = phi_k(r_a) * sum_{I,beta} pi exp(-sigma d_aI), jets by the product rule.
 // Output per walker: [spin][det][row][a][k] (this launch fills one spin block).
 //
-// One determinant per grid row (blockIdx.y); a thread per (walker, electron a, orbital k).  The
+// One determinant per block; a thread per (walker, electron a, orbital k).  The
 // envelope weights of the determinant go through LDS a chunk of nuclei at a time, laid out
 // [nucleus][exponent][orbital] as (pi, sigma) pairs, so that the lanes of a wave (consecutive
 // orbitals, then electrons) read consecutive or identical pairs.  For jets the exponentials of
@@ -749,8 +756,15 @@ __global__ __launch_bounds__(256) void envelope_kernel(SysDev s, int spin, const
   const int i0 = spin ? s.nup : 0;
   const int Rp = jet ? s.Rp : 1;
   const int nn = n * n, nb = s.nenv, M = s.M;
-  const int p = blockIdx.y;
-  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  // block b runs on XCD b % 8 (round-robin dispatch): the determinants of one chunk of
+  // (walker, electron, orbital) triples are consecutive blocks of one XCD, so the orbital rows they
+  // share (every determinant's columns side by side) are read from HBM once and then from that XCD's L2
+  const int64_t nx = (W * nn + 255) / 256;
+  const int64_t b = blockIdx.x, rr = b >> 3;
+  const int p = (int)(rr % s.ndet);
+  const int64_t xc = (rr / s.ndet) * 8 + (b & 7);
+  if (xc >= nx) return;  // the whole block: before any barrier
+  const int64_t t = xc * 256 + threadIdx.x;
   const bool live = t < W * nn;
   const int64_t w = live ? t / nn : 0;
   const int r = live ? (int)(t - w * nn) : 0;
@@ -818,10 +832,11 @@ hipError_t launch_envelope(const SysDev& s, int spin, const S* phi, const S* pi,
   const size_t per = (size_t)n * s.nenv * 2 * sizeof(S);
   const int ic = (int)std::max<size_t>(1, std::min<size_t>(s.M, 32768 / per));
   const size_t lds = per * ic;
-  if (lds > 65536 || (cnt + 255) / 256 > INT32_MAX) return hipErrorInvalidValue;
+  const int64_t nx8 = ((cnt + 255) / 256 + 7) / 8 * 8;  // row chunks, rounded up to whole XCD rounds
+  if (lds > 65536 || nx8 * s.ndet > INT32_MAX) return hipErrorInvalidValue;
   ProfScope ps(jet ? "envelope_kernel<jet>" : "envelope_kernel<val>", st);
-  hipLaunchKernelGGL(envelope_kernel<S>, dim3((unsigned)((cnt + 255) / 256), (unsigned)s.ndet), dim3(256), lds, st,
-                     s, spin, phi, pi, sigma, en, W, jet, ic, ajet);
+  hipLaunchKernelGGL(envelope_kernel<S>, dim3((unsigned)(nx8 * s.ndet)), dim3(256), lds, st, s, spin, phi, pi, sigma,
+                     en, W, jet, ic, ajet);
   return hipGetLastError();
 }
 

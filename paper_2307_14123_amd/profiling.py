@@ -3,6 +3,10 @@
   python -m paper_2307_14123_amd.profiling stats <kernel_stats.csv> --command "<cmd>" --out <file.md>
       per-kernel launch counts and durations (from --kernel-trace --stats, csv output),
       grouped by the families bench.py reports
+  python -m paper_2307_14123_amd.profiling hbm <fetch dir> <write dir> <kernel_stats.csv> --command "<cmd>" --out <file.md>
+      achieved HBM bytes and GB/s of every kernel family of a program: bytes per launch from a FETCH_SIZE
+      run and a WRITE_SIZE run (scaled by the device copy in the same runs), average duration from a
+      --kernel-trace --stats run of the same program
   python -m paper_2307_14123_amd.profiling traffic <fetch dir> <write dir> --family "gemm_kernel<jet>"
       --source <csrc file> --command "<cmd>" --out <file.txt>
       HBM bytes per launch of one kernel family from a FETCH_SIZE run and a WRITE_SIZE run,
@@ -32,6 +36,8 @@ def family(kernel_name: str) -> str:
     if not m:
         return base
     name, targs = m.group(1), [t.strip() for t in m.group(2).split(",")]
+    if name == "det_kernel" and len(targs) >= 3:
+        return "det_kernel<" + ("inv" if targs[2] == "true" else "lu") + ">"
     if name == "gemm_kernel" and len(targs) >= 3:
         return "gemm_kernel<" + {"0": "val", "1": "edge", "2": "jet"}.get(targs[2], targs[2]) + ">"
     if name == "edge_mlp_kernel":
@@ -110,6 +116,48 @@ def traffic(fetch_dir: str, write_dir: str, fam: str, source: str, command: str)
     return "\n".join(lines) + "\n"
 
 
+def hbm(fetch_dir: str, write_dir: str, stats_csv: str, command: str, top: int = 12) -> str:
+    fetch, write = _counter(fetch_dir, "FETCH_SIZE"), _counter(write_dir, "WRITE_SIZE")
+
+    def copy_kib(per):
+        vals = [v for k, d in per.items() if "copyBuffer" in k for v in d.values()]
+        if not vals:
+            raise SystemExit("no device copy in the counter run")
+        return max(vals)
+
+    sf = COPY_BYTES / (copy_kib(fetch) * 1024.0)
+    sw = COPY_BYTES / (copy_kib(write) * 1024.0)
+    per_fam = collections.defaultdict(lambda: [0.0, 0.0, 0])  # read bytes, write bytes, launches
+    for per, scale, slot in ((fetch, sf, 0), (write, sw, 1)):
+        for k, d in per.items():
+            if "copyBuffer" in k or not k.startswith(("qmc::", "void qmc::")):
+                continue
+            f = family(k)
+            per_fam[f][slot] += sum(d.values()) * 1024.0 * scale
+            if slot == 0:
+                per_fam[f][2] += len(d)
+    dur = collections.defaultdict(lambda: [0, 0.0])
+    for r in csv.DictReader(open(stats_csv)):
+        f = family(r["Name"])
+        dur[f][0] += int(r["Calls"])
+        dur[f][1] += float(r["TotalDurationNs"])
+    out = ["# Achieved HBM traffic per kernel family", "", "Commands (run from the repository root):", "",
+           "    " + command, "",
+           f"Counter scaling from the device copy of {COPY_BYTES >> 20} MiB in the same runs: FETCH_SIZE x {sf:.4f}, "
+           f"WRITE_SIZE x {sw:.4f}.", "",
+           "| family | launches | MB read / launch | MB written / launch | average us | achieved GB/s |",
+           "|---|---|---|---|---|---|"]
+    rows = []
+    for f, (rd, wr, n) in per_fam.items():
+        if n == 0 or f not in dur or dur[f][0] == 0:
+            continue
+        avg_s = dur[f][1] / dur[f][0] * 1e-9
+        rows.append((dur[f][1], f, n, rd / n, wr / n, avg_s))
+    for _, f, n, rd, wr, avg_s in sorted(rows, reverse=True)[:top]:
+        out.append(f"| {f} | {n} | {rd / 1e6:.1f} | {wr / 1e6:.1f} | {avg_s * 1e6:.1f} | {(rd + wr) / avg_s / 1e9:.0f} |")
+    return "\n".join(out) + "\n"
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -124,8 +172,16 @@ def main():
     a2.add_argument("--source", required=True)
     a2.add_argument("--command", required=True)
     a2.add_argument("--out", required=True)
+    a3 = sub.add_parser("hbm")
+    a3.add_argument("fetch_dir")
+    a3.add_argument("write_dir")
+    a3.add_argument("stats_csv")
+    a3.add_argument("--command", required=True)
+    a3.add_argument("--out", required=True)
     args = ap.parse_args()
-    if args.cmd == "stats":
+    if args.cmd == "hbm":
+        text = hbm(args.fetch_dir, args.write_dir, args.stats_csv, args.command)
+    elif args.cmd == "stats":
         text = stats(args.csv, args.command)
     else:
         text = traffic(args.fetch_dir, args.write_dir, args.family, args.source, args.command)
