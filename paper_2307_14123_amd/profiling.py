@@ -130,7 +130,7 @@ def hbm(fetch_dir: str, write_dir: str, stats_csv: str, command: str, top: int =
     per_fam = collections.defaultdict(lambda: [0.0, 0.0, 0])  # read bytes, write bytes, launches
     for per, scale, slot in ((fetch, sf, 0), (write, sw, 1)):
         for k, d in per.items():
-            if "copyBuffer" in k or not k.startswith(("qmc::", "void qmc::")):
+            if "copyBuffer" in k or "_peak_kernel" in k or not k.startswith(("qmc::", "void qmc::")):
                 continue
             f = family(k)
             per_fam[f][slot] += sum(d.values()) * 1024.0 * scale
