@@ -1,18 +1,24 @@
 """Benchmark of the VMC hot path on one MI355X.
 
 One step = the whole hot path over one batch of walkers: 10 random-walk
-Metropolis steps (each a full log|psi| evaluation of the proposals) followed
-by the local energy with exact gradient and Laplacian (and the loss gradient
-when the build provides it).  Workload: the N2-sized system (two Z=7 nuclei
-2.068 bohr apart, 7 up + 7 down electrons, 4096 walkers, 4 message-passing
-layers of width 128, 16 determinants, 8 envelope exponents), float32 jets with
-float64 determinants.  Inputs are seeded, synthetic and resident on the GPU
-before the timed region.
+Metropolis steps (each a full log|psi| evaluation of the proposals), the local
+energy with exact gradient and Laplacian, the loss gradient and the
+gradient-descent update of the parameters.  Workload: the N2-sized system (two
+Z=7 nuclei 2.068 bohr apart, 7 up + 7 down electrons, 4096 walkers, 4
+message-passing layers of width 128, 16 determinants, 8 envelope exponents),
+float32 jets with float64 determinants.  Inputs are seeded, synthetic and
+resident on the GPU before the timed region.
+
+The step is captured into one HIP graph after the warm-up steps; the timed
+region replays it K times between HIP events on the launch stream.  An eager
+pass over the same K steps, with HIP events around every launch, gives the
+per-kernel times and the roofline of the dominant kernel.
 
 Prints one JSON line.  `value` = walkers passed through the whole step per
-second; the local-energy-only rate, the error of E_L against the FP64 oracle,
-the roofline of the dominant kernel and the oracle's own throughput on the
-host cores are reported beside it.
+second; the local-energy-only rate, the error of E_L against the FP64 oracle
+(on the seeded network, restored after the timed steps), the roofline of the
+dominant kernel, the measured device peaks and the oracle's own throughput on
+the host cores are reported beside it.
 """
 from __future__ import annotations
 
@@ -208,6 +214,7 @@ def main():
 
     G = torch.empty_like(P)
     EM = torch.empty(1, dtype=torch.float64, device=dev)
+    P_init = P.clone()  # the seeded network, restored after the timed steps have updated it
     # plain gradient descent; its cost does not depend on lr, kept small so that the network stays near its
     # seeded initialisation over the warm-up and timed steps
     lr = 1e-8
@@ -223,40 +230,68 @@ def main():
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
+
+    # The whole step captured into one HIP graph: the same kernels in the same order, without the
+    # gaps between launches.  Falls back to eager steps if capture fails.
+    graph, graph_err = None, None
+    try:
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            step()
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            step()
+        g.replay()  # untimed
+        torch.cuda.synchronize()
+        graph = g
+    except Exception as e:  # noqa: BLE001 - reported in the bench line
+        graph_err = repr(e)[:200]
+
+    def timed(run, n):
+        """n repetitions of run() between HIP events on the launch stream; (wall ms per rep, event ms list)"""
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(n + 1)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ev[0].record()
+        for i in range(n):
+            run()
+            ev[i + 1].record()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / n, [ev[i].elapsed_time(ev[i + 1]) for i in range(n)]
+
+    # timed region: K steps (graph replays when captured)
+    ms_step, step_ms = timed(graph.replay if graph is not None else step, args.steps)
+    # the same K steps eagerly with HIP events around every launch: per-kernel times and rooflines
     qmc.profile_enable(True)
     qmc.profile_report(reset=True)
-    torch.cuda.synchronize()
-    # HIP events on the launch stream around every step (and, through the profile switch, every launch)
-    evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
-    t0 = time.perf_counter()
-    evs[0].record()
-    for i in range(args.steps):
-        step()
-        evs[i + 1].record()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
+    ms_eager, eager_ms = timed(step, args.steps)
     prof = qmc.profile_report(reset=True)
     qmc.profile_enable(False)
-    ms_step = (t1 - t0) * 1e3 / args.steps
-    step_ms = [evs[i].elapsed_time(evs[i + 1]) for i in range(args.steps)]
+    P.copy_(P_init)
+    torch.cuda.synchronize()
 
-    # local energy alone: at least 50 repetitions or 1 s (at most 60), each between two HIP events
-    plan.local_energy(P, R, out=out)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    plan.local_energy(P, R, out=out)
-    torch.cuda.synchronize()
-    est = (time.perf_counter() - t0) * 1e3
-    reps = int(min(60, max(50 if est < 20 else 1, args.steps, math.ceil(1000.0 / max(est, 1e-3)))))
-    lev = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
-    t0 = time.perf_counter()
-    lev[0].record()
-    for i in range(reps):
+    # local energy alone (one graph per evaluation when it captures): at least 50 repetitions or 1 s
+    # (at most 60), each between two HIP events
+    def le_eager():
         plan.local_energy(P, R, out=out)
-        lev[i + 1].record()
-    torch.cuda.synchronize()
-    ms_le = (time.perf_counter() - t0) * 1e3 / reps
-    le_ms = [lev[i].elapsed_time(lev[i + 1]) for i in range(reps)]
+
+    le_run = le_eager
+    if graph is not None:
+        try:
+            gl = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(gl):
+                le_eager()
+            gl.replay()
+            torch.cuda.synchronize()
+            le_run = gl.replay
+        except Exception:  # noqa: BLE001 - eager local energies then
+            le_run = le_eager
+    est, _ = timed(le_run, 1)
+    reps = int(min(60, max(50 if est < 20 else 1, args.steps, math.ceil(1000.0 / max(est, 1e-3)))))
+    ms_le, le_ms = timed(le_run, reps)
     peaks = qmc.measure_peaks()
 
     eb = 8 if args.precision == "fp64" else 4
@@ -328,6 +363,9 @@ def main():
         "e_loc_per_s": W / (ms_le * 1e-3),
         "e_loc_ms": ms_le,
         "step_ms_events": dist(step_ms),
+        "step_launch": "one HIP graph per step" if graph is not None else f"eager (graph capture failed: {graph_err})",
+        "step_ms_eager_events": dist(eager_ms),
+        "kernel_timing": "HIP events around every launch, in an eager pass over the same steps",
         "e_loc_ms_events": dist(le_ms),
         "roofline": roof,
         "measured_peaks": {"fp32_mfma_tflops": peaks["fp32_mfma"], "bf16_mfma_tflops": peaks["bf16_mfma"],
