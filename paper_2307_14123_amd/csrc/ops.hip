@@ -722,10 +722,14 @@ hipError_t launch_aggregate(const SysDev& s, const S* h, const S* wsame, const S
                        wsame, wopp, wnuc, Y, stage, m);
     return hipGetLastError();
   }
-  // template on the larger spin block; above 8 electrons per spin the sender rows go through LDS
+  // template on the larger spin block
   const int ns = std::max(s.nup, s.ndn);
   if (ns <= 4) return agg_launch<S, 4>(s, h, wsame, wopp, ee, W, m, st);
   if (ns <= 8) return agg_launch<S, 8>(s, h, wsame, wopp, ee, W, m, st);
+  // float32 up to 16 electrons per spin: the streaming kernel (one receiver per thread above 8);
+  // larger spin blocks, and float64 above 8, stage the senders' rows in LDS (register budget)
+  if constexpr (sizeof(S) == 4)
+    if (ns <= 16) return agg_launch<S, 16>(s, h, wsame, wopp, ee, W, m, st);
   if (ns <= 16) return agg_lds_launch<S, 16>(s, h, wsame, wopp, ee, W, m, st);
   if (ns <= 24) return agg_lds_launch<S, 24>(s, h, wsame, wopp, ee, W, m, st);
   return hipErrorInvalidValue;
