@@ -2,7 +2,8 @@
 // functions): for every pair of one edge type,
 //   w(d) = tanh(rho(d) U1 + a1) U2 + a2,
 // from the pair distance to the filter row in one kernel, as a value row or
-// as a univariate jet in d (rows value, first and second derivative, zero).
+// as a univariate jet in d (rows value, first and second derivative; a 16-row
+// tile holds the jets of 5 pairs).
 //
 // The first layer is computed transposed, Z^T = U1^T rho^T (+ a1 through a
 // constant basis function on the value row), so that each lane's accumulator
@@ -10,8 +11,8 @@
 // 16*hb + 4*(l/16) + i of pair row l%16: exactly the A-operand slice the
 // second layer's MFMA wants from that lane (row l%16, k = 4*(l/16) + step).
 // The hidden layer never leaves the registers.  For jets the tanh is
-// propagated across the four rows of a pair (lanes 4p'..4p'+3 of a 16-lane
-// group) with quad shuffles: t = tanh(z0), t' z1, t' z2 + t'' z1^2.
+// propagated across the three rows of a pair (lanes 3p'..3p'+2 of a 16-lane
+// group) with shuffles: t = tanh(z0), t' z1, t' z2 + t'' z1^2.
 //
 // A persistent grid keeps U2 (transposed, 16-byte chunks XOR-swizzled by row
 // against LDS bank conflicts) and U1, a1, a2 in LDS, one copy per block of 12
@@ -55,16 +56,18 @@ __global__ __launch_bounds__(64 * NW) void edge_mlp_kernel(SysDev s, EdgeMlpArgs
   __syncthreads();
 
   const int P = a.type == 0 ? s.P0 : (a.type == 1 ? s.P1 : s.P2);
-  const int64_t rows = JET ? a.pairs * 4 : a.pairs;
-  const int64_t ntiles = (rows + 15) / 16;
+  // a tile holds 16 value rows, or the jets of 5 pairs (rows 3p .. 3p + 2; row 15 idle)
+  constexpr int PPT = JET ? 5 : 16;
+  const int64_t ntiles = (a.pairs + PPT - 1) / PPT;
+  const int pc = JET ? c / 3 : c;           // pair of this lane's row within the tile
+  const int e = JET ? c - 3 * pc : 0;       // its jet entry: value, first, second derivative
   for (int64_t tile = (int64_t)blockIdx.x * NW + wave; tile < ntiles; tile += (int64_t)gridDim.x * NW) {
-    const int64_t row0 = tile * 16;
+    const int64_t p0 = tile * PPT;
     // ---- this lane's pair row (column c of the first layer)
-    const int64_t row = row0 + c;
-    const int e = JET ? (int)(row & 3) : 0;
+    const int64_t pr = p0 + pc;
+    const bool rowok = (!JET || c < 15) && pr < a.pairs;
     float rb[4] = {0.f, 0.f, 0.f, 0.f};
-    if (row < rows && e < 3) {
-      const int64_t pr = JET ? row >> 2 : row;
+    if (rowok) {
       const int64_t w = pr / P;
       const int pi = (int)(pr - w * P);
       int i, j;
@@ -94,8 +97,8 @@ __global__ __launch_bounds__(64 * NW) void edge_mlp_kernel(SysDev s, EdgeMlpArgs
       acc = __builtin_amdgcn_mfma_f32_16x16x4f32(g == 0 ? a1s[16 * hb + c] : 0.f, bias_in, acc, 0, 0, 0);
       z[hb] = acc;
     }
-    // ---- tanh (through the jet of a pair's four rows)
-    const int qbase = (lane & ~3);  // lane of row 0 of this lane's pair (same 16-lane group)
+    // ---- tanh (through the jet of a pair's three rows); the idle row 15 borrows pair 4's lanes
+    const int qbase = (lane & 48) + 3 * (pc < 4 ? pc : 4);  // lane of row 0 of this lane's pair
 #pragma unroll
     for (int hb = 0; hb < ED / 16; ++hb)
 #pragma unroll
@@ -104,14 +107,14 @@ __global__ __launch_bounds__(64 * NW) void edge_mlp_kernel(SysDev s, EdgeMlpArgs
         if constexpr (JET) {
           const float z0 = __shfl(zi, qbase), z1 = __shfl(zi, qbase + 1), z2 = __shfl(zi, qbase + 2);
           const float t = tanh_f32(z0), t1 = 1.f - t * t, t2 = -2.f * t * t1;
-          z[hb][i] = e == 0 ? t : (e == 1 ? t1 * z1 : (e == 2 ? t1 * z2 + t2 * z1 * z1 : 0.f));
+          z[hb][i] = e == 0 ? t : (e == 1 ? t1 * z1 : t1 * z2 + t2 * z1 * z1);
         } else {
           z[hb][i] = tanh_f32(zi);
         }
       }
-    if (!JET && a.zout && row < rows) {
+    if (!JET && a.zout && rowok) {
 #pragma unroll
-      for (int hb = 0; hb < ED / 16; ++hb) *(f4*)&a.zout[row * ED + 16 * hb + 4 * g] = z[hb];
+      for (int hb = 0; hb < ED / 16; ++hb) *(f4*)&a.zout[pr * ED + 16 * hb + 4 * g] = z[hb];
     }
     // ---- second layer, two 16-column blocks at a time
 #pragma unroll 1
@@ -132,14 +135,17 @@ __global__ __launch_bounds__(64 * NW) void edge_mlp_kernel(SysDev s, EdgeMlpArgs
         acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(z[hb][3], b0.w, acc0, 0, 0, 0);
         acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(z[hb][3], b1.w, acc1, 0, 0, 0);
       }
-      // lane holds output rows row0 + 4g + i, columns n0 / n1; a2 goes to value rows only
+      // lane holds tile rows 4g + i, columns n0 / n1; a2 goes to value rows only.  Jets are stored
+      // as [pair][4][D] (rows value, first, second derivative; the fourth row is not written)
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const int64_t orow = row0 + 4 * g + i;
-        if (orow >= rows) continue;
-        const bool vrow = !JET || i == 0;  // row0 is a multiple of 4: row 4g + i of a jet is entry i
-        a.out[orow * ED + n0] = acc0[i] + (vrow ? a2s[n0] : 0.f);
-        a.out[orow * ED + n1] = acc1[i] + (vrow ? a2s[n1] : 0.f);
+        const int r = 4 * g + i;
+        const int rp = JET ? r / 3 : r, re = JET ? r - 3 * rp : 0;
+        const int64_t op = p0 + rp;
+        if ((JET && r == 15) || op >= a.pairs) continue;
+        const int64_t orow = JET ? op * 4 + re : op;
+        a.out[orow * ED + n0] = acc0[i] + (re == 0 ? a2s[n0] : 0.f);
+        a.out[orow * ED + n1] = acc1[i] + (re == 0 ? a2s[n1] : 0.f);
       }
     }
   }
@@ -163,8 +169,7 @@ hipError_t launch_edge_mlp(const SysDev& s, const EdgeMlpArgs& a, hipStream_t st
     const char* e = std::getenv("QMC_EDGE_WAVES");
     nw = e && std::atoi(e) == 4 ? 4 : 12;
   }
-  const int64_t rows = a.jet ? a.pairs * 4 : a.pairs;
-  const int64_t tiles = (rows + 15) / 16;
+  const int64_t tiles = a.jet ? (a.pairs + 4) / 5 : (a.pairs + 15) / 16;
   // blocks of nw waves share one copy of the weights in LDS (73 KB); as many blocks as fit per
   // compute unit, each walking tiles with a grid stride
   auto go = [&](auto kern, int w) {

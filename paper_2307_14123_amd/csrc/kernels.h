@@ -75,7 +75,7 @@ struct SysDev {
 struct EdgeMlpArgs {
   const float *U1, *a1, *U2, *a2;
   const double *ee, *en;  // geometry of the walker chunk (layouts as launch_geometry writes them)
-  float* out;             // [pairs][D] value rows, or [pairs][4][D] univariate jets
+  float* out;             // [pairs][D] value rows, or [pairs][4][D] univariate jets (rows 0-2 written)
   float* zout;            // optional, value rows only: the hidden layer tanh(rho U1 + a1), [pairs][D]
   int64_t pairs;          // walkers x pairs of this type
   int type;               // 0 same-spin, 1 up-down, 2 electron-nucleus
