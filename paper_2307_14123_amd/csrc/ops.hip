@@ -980,10 +980,12 @@ __global__ __launch_bounds__(256) void det_kernel(const S* __restrict__ src, int
       if (c < n) dst[c] = singular ? 0.0 : v[c];
   }
   if (!jet) return;
-  // LDS per problem slot: dA tile [n][n+1] (type S), X tile [n][n+1] (double)
-  const int ld1 = n + 1;
-  S* dsl = (S*)dsm + (size_t)slot * n * ld1;
-  double* xsl = (double*)(dsm + (((size_t)(blockDim.x / G) * n * ld1 * sizeof(S) + 15) / 16) * 16) +
+  // LDS per problem slot: dA tile [n][G] (type S), X tile [n][n+1] (double)
+  // dA tile: rows of G columns (zero beyond n, so the row reads are whole aligned vectors), slots
+  // 4 elements apart beyond that (the groups of a wave read different slots)
+  const int ld1 = n + 1, slot_stride = n * G + 4;
+  S* dsl = (S*)dsm + (size_t)slot * slot_stride;
+  double* xsl = (double*)(dsm + (((size_t)(blockDim.x / G) * slot_stride * sizeof(S) + 15) / 16) * 16) +
                 (size_t)slot * n * ld1;
   double qacc = 0.0;
   S nxt[G];
@@ -992,8 +994,7 @@ __global__ __launch_bounds__(256) void det_kernel(const S* __restrict__ src, int
   for (int t = 0; t < ntan; ++t) {
     if (row) {
 #pragma unroll
-      for (int c = 0; c < G; ++c)
-        if (c < n) dsl[r * ld1 + c] = nxt[c];
+      for (int c = 0; c < G; ++c) dsl[r * G + c] = nxt[c];
     }
     if (t + 1 < ntan) {
       const S* q = A + (int64_t)(2 + t) * nn + r * n;
@@ -1011,8 +1012,7 @@ __global__ __launch_bounds__(256) void det_kernel(const S* __restrict__ src, int
         if (k >= n) break;
         const double vk = v[k];
 #pragma unroll
-        for (int b = 0; b < G; ++b)
-          if (b < n) x[b] += vk * (double)dsl[k * ld1 + b];
+        for (int b = 0; b < G; ++b) x[b] += vk * (double)dsl[k * G + b];
       }
 #pragma unroll
       for (int b = 0; b < G; ++b)
@@ -1058,7 +1058,7 @@ static hipError_t det_dispatch(const S* src, int64_t stride_outer, int n_inner, 
   const int64_t blocks = (nprob + slots - 1) / slots;
   if (blocks > INT32_MAX) return hipErrorInvalidValue;
   const bool inv = jet || ainv;
-  const size_t lds = jet ? ((size_t)slots * n * (n + 1) * sizeof(S) + 15) / 16 * 16 + (size_t)slots * n * (n + 1) * 8
+  const size_t lds = jet ? ((size_t)slots * (n * G + 4) * sizeof(S) + 15) / 16 * 16 + (size_t)slots * n * (n + 1) * 8
                          : 0;
 #define QMC_DET(GG, II)                                                                                       \
   hipLaunchKernelGGL((det_kernel<S, GG, II>), dim3((unsigned)blocks), dim3(threads), lds, st, src, stride_outer, \
