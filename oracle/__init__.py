@@ -13,7 +13,7 @@ layout     -- unpack the flat parameter blob into named tensors
 ansatz     -- log|psi| and sign (torch, differentiable)
 npforward  -- log|psi| and sign (numpy only, for finite differences)
 energy     -- potential, local energy (serial autograd Laplacian)
-sampling   -- one random-walk Metropolis step
+sampling   -- one random-walk Metropolis step and one Langevin (MALA) step
 lossgrad   -- the VMC loss-gradient estimator
 slater     -- local energy of a Slater determinant of given analytic orbitals
 """
@@ -21,10 +21,10 @@ from .layout import unpack, param_shapes, param_count
 from .ansatz import logpsi
 from .npforward import logpsi_np
 from .energy import potential, local_energy
-from .sampling import metropolis_step
+from .sampling import logpsi_and_grad, mala_log_accept, mala_step, metropolis_step
 from .lossgrad import loss_grad, surrogate
 
 __all__ = [
     "unpack", "param_shapes", "param_count", "logpsi", "logpsi_np", "potential",
-    "local_energy", "metropolis_step", "loss_grad", "surrogate",
+    "local_energy", "metropolis_step", "mala_step", "mala_log_accept", "logpsi_and_grad", "loss_grad", "surrogate",
 ]

@@ -1,4 +1,5 @@
-"""One random-walk Metropolis step (Sec. V, Metropolis sampler), oracle side.
+"""One random-walk Metropolis step (Sec. V, Metropolis sampler) and one
+Metropolis-adjusted Langevin step (Sec. V, Langevin sampler), oracle side.
 
 All electrons move at once: r' = r + tau * xi with xi ~ N(0, 1) per
 coordinate.  The proposal is accepted when log(u) < 2 (log|psi(r')| -
@@ -31,3 +32,60 @@ def metropolis_step(r, logpsi_cur, noise, u, step, params, system, ans, chunk=25
     r_new = np.where(acc[:, None, None], prop, r)
     lp_out = np.where(acc, lp_prop, logpsi_cur)
     return r_new, lp_out, acc.astype(np.uint8), lp_prop
+
+
+def logpsi_and_grad(r, params, system, ans, chunk=256):
+    """log|psi| and its gradient over the electron coordinates by one reverse pass (numpy float64,
+    [W], [W, N, 3]); the gradient is NaN where log|psi| is not finite."""
+    r = np.asarray(r, dtype=np.float64)
+    theta = torch.as_tensor(np.asarray(params, dtype=np.float64))
+    lps, grads = [], []
+    for s in range(0, r.shape[0], chunk):
+        x = torch.as_tensor(r[s:s + chunk]).clone().requires_grad_(True)
+        lp = logpsi(x, theta, system, ans)[1]
+        g = torch.autograd.grad(lp.sum(), x, allow_unused=True)[0]
+        g = torch.zeros_like(x) if g is None else g
+        bad = ~torch.isfinite(lp)
+        g = torch.where(bad[:, None, None], torch.full_like(g, float("nan")), g)
+        lps.append(lp.detach().numpy())
+        grads.append(g.detach().numpy())
+    return np.concatenate(lps), np.concatenate(grads)
+
+
+def mala_log_accept(lp_cur, grad_cur, lp_prop, grad_prop, noise, step):
+    """log of the Metropolis-Hastings acceptance ratio of a Langevin proposal.
+
+    Target |psi|^2 = exp(2 l); proposal r' = r + eps^2 grad l(r) + eps xi (overdamped Langevin
+    with time step eps^2, eps = step), so q(x | y) = N(x; y + eps^2 grad l(y), eps^2).  With
+    r' - r - eps^2 g = eps xi and r - r' - eps^2 g' = -eps (xi + eps (g + g')):
+        log a = 2 (l' - l) + |xi|^2 / 2 - |xi + eps (g + g')|^2 / 2."""
+    xi = np.asarray(noise, dtype=np.float64)
+    W = xi.shape[0]
+    xi = xi.reshape(W, -1)
+    g = np.asarray(grad_cur, dtype=np.float64).reshape(W, -1)
+    gp = np.asarray(grad_prop, dtype=np.float64).reshape(W, -1)
+    back = xi + np.float64(step) * (g + gp)
+    return 2.0 * (np.asarray(lp_prop) - np.asarray(lp_cur)) + 0.5 * (xi * xi).sum(1) - 0.5 * (back * back).sum(1)
+
+
+def mala_step(r, logpsi_cur, grad_cur, noise, u, step, params, system, ans, chunk=256):
+    """One Metropolis-adjusted Langevin step (Sec. V, Langevin sampler), oracle side.
+
+    All electrons move at once: r' = (r + eps^2 grad l(r)) + eps xi with eps = step and
+    xi ~ N(0, 1) per coordinate; the proposal is accepted when log(u) < log a (mala_log_accept),
+    strictly and in float64, so a non-finite log|psi(r')| or gradient rejects.  The gradient at
+    the current state is an input (cached by the caller with log|psi|).  The step-size damping
+    near nuclei that the paper mentions is not part of this step (its form is not given there).
+    Returns (r_new, logpsi_new, grad_new, accepted, r_proposed)."""
+    r = np.asarray(r, dtype=np.float64)
+    g = np.asarray(grad_cur, dtype=np.float64)
+    eps = np.float64(step)
+    prop = (r + (eps * eps) * g) + eps * np.asarray(noise, dtype=np.float64)
+    lp_prop, g_prop = logpsi_and_grad(prop, params, system, ans, chunk)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        la = mala_log_accept(logpsi_cur, g, lp_prop, g_prop, noise, step)
+        acc = np.log(np.asarray(u, dtype=np.float64)) < la
+    r_new = np.where(acc[:, None, None], prop, r)
+    lp_out = np.where(acc, lp_prop, logpsi_cur)
+    g_out = np.where(acc[:, None, None], g_prop, g)
+    return r_new, lp_out, g_out, acc.astype(np.uint8), prop

@@ -387,3 +387,72 @@ def test_metropolis_hydrogen_mean_radius():
     mean = per_walker.mean()
     err = per_walker.std(ddof=1) / math.sqrt(W)
     assert abs(mean - 1.5) < 4 * err
+
+
+def _gauss_logq(x, y, gy, eps):
+    """log N(x; y + eps^2 gy, eps^2 I) up to the common constant, written out from the definition."""
+    d = (x - y - eps * eps * gy).reshape(x.shape[0], -1)
+    return -(d * d).sum(1) / (2.0 * eps * eps)
+
+
+def test_mala_acceptance_is_the_hastings_ratio():
+    """The closed form of the Langevin acceptance equals log pi(r') - log pi(r) + log q(r | r') -
+    log q(r' | r) with pi = |psi|^2 and Gaussian drift proposals, evaluated from the positions."""
+    s, a, p, r = qi.workload_inputs(0, 16)
+    lp, g = oracle.logpsi_and_grad(r, p, s, a)
+    xi = qi.make_noise(1, 16, s.n_elec, 7)[0]
+    for eps in (0.05, 0.3):
+        prop = (r + eps * eps * g) + eps * xi
+        lpp, gp = oracle.logpsi_and_grad(prop, p, s, a)
+        ref = 2.0 * (lpp - lp) + _gauss_logq(r, prop, gp, eps) - _gauss_logq(prop, r, g, eps)
+        got = oracle.mala_log_accept(lp, g, lpp, gp, xi, eps)
+        np.testing.assert_allclose(got, ref, rtol=1e-9, atol=1e-9)
+
+
+def test_mala_gradient_matches_finite_differences():
+    """The reverse-pass gradient the Langevin drift uses agrees with central differences of log|psi|."""
+    s, a, p, r = qi.workload_inputs(0, 4)
+    _, g = oracle.logpsi_and_grad(r, p, s, a)
+    h = 1e-5
+    for c in range(3):
+        rp, rm = r.copy(), r.copy()
+        rp[:, 1, c] += h
+        rm[:, 1, c] -= h
+        fd = (oracle.logpsi_np(rp, p, s, a)[1] - oracle.logpsi_np(rm, p, s, a)[1]) / (2 * h)
+        np.testing.assert_allclose(g[:, 1, c], fd, rtol=1e-6, atol=1e-7)
+
+
+def test_mala_zero_step_accepts_everything_and_rejects_nan():
+    s, a, p, r = qi.workload_inputs(0, 8)
+    lp, g = oracle.logpsi_and_grad(r, p, s, a)
+    xi = qi.make_noise(1, 8, s.n_elec, 2)[0]
+    u = qi.make_uniforms(1, 8, 3)[0]
+    r2, lp2, g2, acc, _ = oracle.mala_step(r, lp, g, xi, u, 0.0, p, s, a)
+    assert np.all(acc == 1) and np.all(r2 == r)
+    np.testing.assert_allclose(lp2, lp, rtol=1e-13)
+    gbad = g.copy()
+    gbad[2] = np.nan
+    _, _, _, acc2, _ = oracle.mala_step(r, lp, gbad, xi, np.zeros(8), 0.1, p, s, a)
+    assert acc2[2] == 0 and np.all(np.delete(acc2, 2) == 1)
+
+
+@pytest.mark.slow
+def test_mala_hydrogen_mean_radius():
+    """Sampling |exp(-r)|^2 with the Langevin step gives <r> = 3/2."""
+    H = qi.System((1.0,), ((0.0, 0.0, 0.0),), 1, 0)
+    a = qi.Ansatz(n_rbf=4, rbf_dmax=6.0, init_layers=1, width=4, mp_layers=0, n_det=1, n_env=1)
+    p = _one_center_params(H, a, 1.0)
+    W = 1000
+    r = _random_points(W, 1, 41, scale=1.0)
+    lp, g = oracle.logpsi_and_grad(r, p, H, a, chunk=W)
+    rng = np.random.default_rng(42)
+    rs = []
+    for t in range(300):
+        r, lp, g, acc, _ = oracle.mala_step(r, lp, g, rng.standard_normal((W, 1, 3)), rng.random(W), 0.5, p, H, a,
+                                            chunk=W)
+        if t >= 100:
+            rs.append(np.linalg.norm(r[:, 0], axis=-1))
+    per_walker = np.array(rs).mean(0)
+    mean = per_walker.mean()
+    err = per_walker.std(ddof=1) / math.sqrt(W)
+    assert abs(mean - 1.5) < 4 * err
