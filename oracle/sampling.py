@@ -52,38 +52,75 @@ def logpsi_and_grad(r, params, system, ans, chunk=256):
     return np.concatenate(lps), np.concatenate(grads)
 
 
-def mala_log_accept(lp_cur, grad_cur, lp_prop, grad_prop, noise, step):
+def drift_damping_a(zd):
+    """Damping strength a(Z d) of the drift limit of Umrigar, Nightingale and Runge (J. Chem. Phys.
+    99, 2865 (1993)) with its angular term at its mean: a = 1/2 + (Z d)^2 / (10 (4 + (Z d)^2)), so
+    a = 1/2 on a nucleus and a -> 3/5 far from it."""
+    zd2 = np.asarray(zd, dtype=np.float64) ** 2
+    return 0.5 + zd2 / (10.0 * (4.0 + zd2))
+
+
+def langevin_drift(r, grad, tau, system, damp=True):
+    """Drift velocity D(r) of the Langevin proposal r' = r + tau D(r) + sqrt(tau) xi, [W, N, 3].
+
+    Without damping D = grad log|psi|.  With damping (the step-size correction near nuclei that the
+    paper takes from Hermann et al.; its form is not printed there, this is the reading used here),
+    each electron's v = grad_i log|psi| is shortened as
+        v_bar = v * 2 / (1 + sqrt(1 + 2 a |v|^2 tau))      (the same as (sqrt(1 + 2x) - 1) / x, x = a|v|^2 tau)
+    with a = drift_damping_a(Z d) for its nearest nucleus (charge Z, distance d, lowest index on
+    ties), and then capped so that the drift step tau |v_bar| does not exceed d."""
+    r = np.asarray(r, dtype=np.float64)
+    g = np.asarray(grad, dtype=np.float64)
+    if not damp:
+        return g.copy()
+    R, Z = system.R(), system.Z()
+    dist = np.linalg.norm(r[:, :, None, :] - R[None, None], axis=-1)  # [W, N, M]
+    idx = np.argmin(dist, axis=-1)
+    d = np.take_along_axis(dist, idx[..., None], -1)[..., 0]
+    a = drift_damping_a(Z[idx] * d)
+    v2 = (g * g).sum(-1)
+    vb = g * (2.0 / (1.0 + np.sqrt(1.0 + 2.0 * a * v2 * tau)))[..., None]
+    step_len = tau * np.linalg.norm(vb, axis=-1)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        cap = np.where(step_len > d, d / step_len, 1.0)
+    return vb * cap[..., None]
+
+
+def mala_log_accept(lp_cur, drift_cur, lp_prop, drift_prop, noise, step):
     """log of the Metropolis-Hastings acceptance ratio of a Langevin proposal.
 
-    Target |psi|^2 = exp(2 l); proposal r' = r + eps^2 grad l(r) + eps xi (overdamped Langevin
-    with time step eps^2, eps = step), so q(x | y) = N(x; y + eps^2 grad l(y), eps^2).  With
-    r' - r - eps^2 g = eps xi and r - r' - eps^2 g' = -eps (xi + eps (g + g')):
-        log a = 2 (l' - l) + |xi|^2 / 2 - |xi + eps (g + g')|^2 / 2."""
+    Target |psi|^2 = exp(2 l); proposal r' = r + eps^2 D(r) + eps xi (overdamped Langevin with time
+    step tau = eps^2, eps = step), so q(x | y) = N(x; y + eps^2 D(y), eps^2).  With
+    r' - r - eps^2 D = eps xi and r - r' - eps^2 D' = -eps (xi + eps (D + D')):
+        log a = 2 (l' - l) + |xi|^2 / 2 - |xi + eps (D + D')|^2 / 2."""
     xi = np.asarray(noise, dtype=np.float64)
     W = xi.shape[0]
     xi = xi.reshape(W, -1)
-    g = np.asarray(grad_cur, dtype=np.float64).reshape(W, -1)
-    gp = np.asarray(grad_prop, dtype=np.float64).reshape(W, -1)
+    g = np.asarray(drift_cur, dtype=np.float64).reshape(W, -1)
+    gp = np.asarray(drift_prop, dtype=np.float64).reshape(W, -1)
     back = xi + np.float64(step) * (g + gp)
     return 2.0 * (np.asarray(lp_prop) - np.asarray(lp_cur)) + 0.5 * (xi * xi).sum(1) - 0.5 * (back * back).sum(1)
 
 
-def mala_step(r, logpsi_cur, grad_cur, noise, u, step, params, system, ans, chunk=256):
+def mala_step(r, logpsi_cur, grad_cur, noise, u, step, params, system, ans, damp=True, chunk=256):
     """One Metropolis-adjusted Langevin step (Sec. V, Langevin sampler), oracle side.
 
-    All electrons move at once: r' = (r + eps^2 grad l(r)) + eps xi with eps = step and
-    xi ~ N(0, 1) per coordinate; the proposal is accepted when log(u) < log a (mala_log_accept),
-    strictly and in float64, so a non-finite log|psi(r')| or gradient rejects.  The gradient at
-    the current state is an input (cached by the caller with log|psi|).  The step-size damping
-    near nuclei that the paper mentions is not part of this step (its form is not given there).
-    Returns (r_new, logpsi_new, grad_new, accepted, r_proposed)."""
+    All electrons move at once: r' = (r + eps^2 D(r)) + eps xi with eps = step, tau = eps^2,
+    xi ~ N(0, 1) per coordinate and D the (damped) drift of langevin_drift; the proposal is
+    accepted when log(u) < log a (mala_log_accept), strictly and in float64, so a non-finite
+    log|psi(r')| or gradient rejects.  The gradient at the current state is an input (cached by
+    the caller with log|psi|).  Returns (r_new, logpsi_new, grad_new, accepted, r_proposed)."""
     r = np.asarray(r, dtype=np.float64)
     g = np.asarray(grad_cur, dtype=np.float64)
     eps = np.float64(step)
-    prop = (r + (eps * eps) * g) + eps * np.asarray(noise, dtype=np.float64)
+    tau = eps * eps
+    with np.errstate(divide="ignore", invalid="ignore"):
+        drift = langevin_drift(r, g, tau, system, damp)
+        prop = (r + tau * drift) + eps * np.asarray(noise, dtype=np.float64)
     lp_prop, g_prop = logpsi_and_grad(prop, params, system, ans, chunk)
     with np.errstate(divide="ignore", invalid="ignore"):
-        la = mala_log_accept(logpsi_cur, g, lp_prop, g_prop, noise, step)
+        drift_prop = langevin_drift(prop, g_prop, tau, system, damp)
+        la = mala_log_accept(logpsi_cur, drift, lp_prop, drift_prop, noise, step)
         acc = np.log(np.asarray(u, dtype=np.float64)) < la
     r_new = np.where(acc[:, None, None], prop, r)
     lp_out = np.where(acc, lp_prop, logpsi_cur)

@@ -395,18 +395,57 @@ def _gauss_logq(x, y, gy, eps):
     return -(d * d).sum(1) / (2.0 * eps * eps)
 
 
-def test_mala_acceptance_is_the_hastings_ratio():
+@pytest.mark.parametrize("damp", [False, True])
+def test_mala_acceptance_is_the_hastings_ratio(damp):
     """The closed form of the Langevin acceptance equals log pi(r') - log pi(r) + log q(r | r') -
     log q(r' | r) with pi = |psi|^2 and Gaussian drift proposals, evaluated from the positions."""
     s, a, p, r = qi.workload_inputs(0, 16)
     lp, g = oracle.logpsi_and_grad(r, p, s, a)
     xi = qi.make_noise(1, 16, s.n_elec, 7)[0]
     for eps in (0.05, 0.3):
-        prop = (r + eps * eps * g) + eps * xi
+        D = oracle.langevin_drift(r, g, eps * eps, s, damp)
+        prop = (r + eps * eps * D) + eps * xi
         lpp, gp = oracle.logpsi_and_grad(prop, p, s, a)
-        ref = 2.0 * (lpp - lp) + _gauss_logq(r, prop, gp, eps) - _gauss_logq(prop, r, g, eps)
-        got = oracle.mala_log_accept(lp, g, lpp, gp, xi, eps)
+        Dp = oracle.langevin_drift(prop, gp, eps * eps, s, damp)
+        ref = 2.0 * (lpp - lp) + _gauss_logq(r, prop, Dp, eps) - _gauss_logq(prop, r, D, eps)
+        got = oracle.mala_log_accept(lp, D, lpp, Dp, xi, eps)
         np.testing.assert_allclose(got, ref, rtol=1e-9, atol=1e-9)
+        r2, _, _, _, prop2 = oracle.mala_step(r, lp, g, xi, np.full(16, 0.5), eps, p, s, a, damp=damp)
+        np.testing.assert_array_equal(prop2, prop)
+
+
+def test_drift_damping_limits():
+    """The damping keeps small drifts, bounds large ones by sqrt(2 tau / a) and by the distance to
+    the nearest nucleus, and a takes its published end values (1/2 on the nucleus, 3/5 far away)."""
+    assert oracle.drift_damping_a(0.0) == 0.5
+    assert abs(oracle.drift_damping_a(1e8) - 0.6) < 1e-12
+    H2 = qi.System((1.0, 1.0), ((0.0, 0.0, -0.7), (0.0, 0.0, 0.7)), 1, 1)
+    rng = np.random.default_rng(5)
+    r = rng.normal(size=(64, 2, 3)) * 2.0
+    tau = 0.04
+    tiny = rng.normal(size=r.shape) * 1e-4
+    r_far = r + np.array([0.0, 0.0, 50.0])
+    np.testing.assert_allclose(oracle.langevin_drift(r_far, tiny, tau, H2), tiny, rtol=1e-8)
+    big = rng.normal(size=r.shape) * 1e3
+    D = oracle.langevin_drift(r, big, tau, H2)
+    d = np.linalg.norm(r[:, :, None] - H2.R()[None, None], axis=-1).min(-1)
+    step = tau * np.linalg.norm(D, axis=-1)
+    assert np.all(step <= d * (1 + 1e-14))
+    assert np.all(step <= np.sqrt(2 * tau / 0.5) * (1 + 1e-14))
+    cos = (D * big).sum(-1) / (np.linalg.norm(D, axis=-1) * np.linalg.norm(big, axis=-1))
+    np.testing.assert_allclose(cos, 1.0, rtol=1e-12)
+    # an electron on a nucleus does not drift; far from the cap, the shortening factor is the
+    # (sqrt(1 + 2x) - 1) / x of the published limit
+    r0 = np.zeros((1, 2, 3))
+    r0[0, 0] = H2.R()[0]
+    r0[0, 1] = (0.0, 3.0, 0.0)
+    v = np.array([[[1.0, 2.0, 0.0], [0.3, 0.0, 0.0]]])
+    D0 = oracle.langevin_drift(r0, v, tau, H2)
+    assert np.all(D0[0, 0] == 0.0)
+    dn = math.sqrt(9 + 0.49)
+    a1 = 0.5 + dn ** 2 / (10 * (4 + dn ** 2))
+    x = a1 * 0.09 * tau
+    np.testing.assert_allclose(D0[0, 1], v[0, 1] * (math.sqrt(1 + 2 * x) - 1) / x, rtol=1e-12)
 
 
 def test_mala_gradient_matches_finite_differences():
@@ -437,8 +476,9 @@ def test_mala_zero_step_accepts_everything_and_rejects_nan():
 
 
 @pytest.mark.slow
-def test_mala_hydrogen_mean_radius():
-    """Sampling |exp(-r)|^2 with the Langevin step gives <r> = 3/2."""
+@pytest.mark.parametrize("damp", [False, True])
+def test_mala_hydrogen_mean_radius(damp):
+    """Sampling |exp(-r)|^2 with the Langevin step gives <r> = 3/2, with and without damping."""
     H = qi.System((1.0,), ((0.0, 0.0, 0.0),), 1, 0)
     a = qi.Ansatz(n_rbf=4, rbf_dmax=6.0, init_layers=1, width=4, mp_layers=0, n_det=1, n_env=1)
     p = _one_center_params(H, a, 1.0)
@@ -449,7 +489,7 @@ def test_mala_hydrogen_mean_radius():
     rs = []
     for t in range(300):
         r, lp, g, acc, _ = oracle.mala_step(r, lp, g, rng.standard_normal((W, 1, 3)), rng.random(W), 0.5, p, H, a,
-                                            chunk=W)
+                                            damp=damp, chunk=W)
         if t >= 100:
             rs.append(np.linalg.norm(r[:, 0], axis=-1))
     per_walker = np.array(rs).mean(0)
