@@ -109,7 +109,8 @@ enum {
   QMC_OP_LOCAL_ENERGY = 1,
   QMC_OP_METROPOLIS = 2,
   QMC_OP_LOGPSI_VJP = 3,
-  QMC_OP_LOSS_GRAD = 4
+  QMC_OP_LOSS_GRAD = 4,
+  QMC_OP_MALA = 5
 };
 
 typedef struct qmc_plan qmc_plan;
@@ -186,6 +187,27 @@ qmc_status qmc_local_energy(const qmc_plan* plan, const void* params, const doub
 qmc_status qmc_metropolis_step(const qmc_plan* plan, const void* params, double* r,
                                double* logpsi, const double* noise, const double* u, double step,
                                uint8_t* accepted, void* ws, size_t ws_bytes, void* stream);
+
+/* One Metropolis-adjusted Langevin step (Sec. V, Langevin sampler).  With
+ * tau = step^2 the proposal is r' = (r + tau D(r)) + step * noise, where the
+ * drift D is grad log|psi| (damp = 0) or, with damp = 1, each electron's
+ * gradient v shortened near its nearest nucleus I (charge Z, distance d):
+ *   a = 1/2 + (Z d)^2 / (10 (4 + (Z d)^2)),
+ *   v_bar = v * 2 / (1 + sqrt(1 + 2 a |v|^2 tau)),
+ * then scaled down so that tau |v_bar| <= d (the step-size correction near
+ * nuclei of Sec. V, taken in the drift-limit form of Umrigar, Nightingale and
+ * Runge, J. Chem. Phys. 99, 2865 (1993), angular term at its mean).  The
+ * proposal is accepted iff, in float64,
+ *   log(u) < 2 (l' - l) + |noise|^2 / 2 - |noise + step (D(r) + D(r'))|^2 / 2
+ * (the Metropolis-Hastings ratio of the two Gaussian proposal densities);
+ * a non-finite l' or gradient rejects.  r[W][N][3], logpsi[W] (log|psi(r)|)
+ * and grad[W][N][3] (grad log|psi(r)|, as returned by qmc_local_energy) are
+ * in/out and change only for accepted walkers.  noise[W][N][3] ~ N(0,1),
+ * u[W] in [0,1), accepted[W] in {0,1} (may be NULL).  step must be finite
+ * and >= 0; damp must be 0 or 1. */
+qmc_status qmc_mala_step(const qmc_plan* plan, const void* params, double* r, double* logpsi,
+                         double* grad, const double* noise, const double* u, double step,
+                         int32_t damp, uint8_t* accepted, void* ws, size_t ws_bytes, void* stream);
 
 /* Vector-Jacobian product of log|psi| with respect to the parameters:
  *   grad_params[P] = sum_w cotangent[w] * d log|psi_w| / d params. */

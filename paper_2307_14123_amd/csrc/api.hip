@@ -304,6 +304,37 @@ static qmc_status run_metropolis(const Plan& P, const void* params, double* r, d
 }
 
 
+template <typename S>
+static qmc_status run_mala(const Plan& P, const void* params, double* r, double* logpsi, double* grad,
+                           const double* noise, const double* u, double step, int damp, uint8_t* accepted, char* ws,
+                           hipStream_t st) {
+  return for_systems(P, QMC_OP_MALA, ws, st, [&](size_t si, hipStream_t ss, char* wsb) -> qmc_status {
+    const SysPlan& s = P.sys[si];
+    const SysDev dv = make_dev(P, s);
+    const S* prm = (const S*)params + s.param_offset;
+    const int64_t pos = pos_offset(P, s);
+    for (int64_t w0 = 0; w0 < s.W; w0 += s.Wc) {
+      const int64_t wc = std::min<int64_t>(s.Wc, s.W - w0);
+      const int64_t wg = s.walker_offset + w0;
+      const Workspace L = workspace_layout(P, s, QMC_OP_MALA, wc);
+      double* rp = (double*)(wsb + L.lp_prop);
+      double* gp = rp + wc * s.N * 3;
+      double* lpp = gp + wc * s.N * 3;
+      const int64_t off = pos + w0 * s.N * 3;
+      CK(launch_propose_mala(dv, r + off, grad + off, noise + off, step, damp, wc, rp, ss));
+      Outs oc;
+      std::memset(&oc, 0, sizeof(oc));
+      oc.logpsi = lpp;
+      oc.grad = gp;
+      const qmc_status e = forward_chunk<S>(P, s, prm, rp, wc, 1, L, wsb, oc, ss);
+      if (e != QMC_OK) return e;
+      CK(launch_accept_mala(dv, wc, rp, gp, lpp, noise + off, u + wg, step, damp, r + off, grad + off, logpsi + wg,
+                            accepted ? accepted + wg : nullptr, ss));
+    }
+    return QMC_OK;
+  });
+}
+
 // ---------------------------------------------------------------- parameter backward
 
 static WgradArgs wg(const void* X, int64_t ldx, const void* G, int64_t ldg, int64_t rows, int Kin, int Nout,
@@ -690,6 +721,21 @@ qmc_status qmc_metropolis_step(const qmc_plan* plan, const void* params, double*
   if (plan->p.prec == QMC_FP64)
     return run_metropolis<double>(plan->p, params, r, logpsi, noise, u, step, accepted, (char*)ws, st);
   return run_metropolis<float>(plan->p, params, r, logpsi, noise, u, step, accepted, (char*)ws, st);
+}
+
+qmc_status qmc_mala_step(const qmc_plan* plan, const void* params, double* r, double* logpsi, double* grad,
+                         const double* noise, const double* u, double step, int32_t damp, uint8_t* accepted, void* ws,
+                         size_t ws_bytes, void* stream) {
+  if (!plan || !params || !r || !logpsi || !grad || !noise || !u) return QMC_ERR_INVALID_ARGUMENT;
+  if (!std::isfinite(step) || step < 0 || (damp != 0 && damp != 1)) return QMC_ERR_INVALID_ARGUMENT;
+  if (!ws_ok(plan->p, QMC_OP_MALA, ws, ws_bytes)) {
+    if (ws && ws_bytes < workspace_bytes(plan->p, QMC_OP_MALA)) return QMC_ERR_WORKSPACE_TOO_SMALL;
+    return QMC_ERR_INVALID_ARGUMENT;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  if (plan->p.prec == QMC_FP64)
+    return run_mala<double>(plan->p, params, r, logpsi, grad, noise, u, step, damp, accepted, (char*)ws, st);
+  return run_mala<float>(plan->p, params, r, logpsi, grad, noise, u, step, damp, accepted, (char*)ws, st);
 }
 
 qmc_status qmc_logpsi_vjp(const qmc_plan* plan, const void* params, const double* r, const double* cotangent,

@@ -71,7 +71,7 @@ Workspace workspace_layout(const Plan& p, const SysPlan& s, int op, int64_t wc) 
     cur = align256(cur + bytes);
     return o;
   };
-  const bool jet = (op == QMC_OP_LOCAL_ENERGY);
+  const bool jet = (op == QMC_OP_LOCAL_ENERGY || op == QMC_OP_MALA);
   const size_t E = act_bytes(p.prec);
   const int64_t N = s.N, M = s.M, D = p.ans.width, K = p.ans.n_rbf, ND = p.ans.n_det;
   const int64_t Rp = jet ? s.Rp : 1, Rpe = jet ? 4 : 1;
@@ -100,7 +100,10 @@ Workspace workspace_layout(const Plan& p, const SysPlan& s, int op, int64_t wc) 
   w.dg = alloc(size_t(wc) * 2 * ND * (jet ? s.T : 1) * 8);
   w.dlap = alloc(size_t(wc) * 2 * ND * 8);
   if (op == QMC_OP_METROPOLIS) {
-    w.lp_prop = alloc(size_t(wc) * (N * 3 + 1) * 8);
+    w.lp_prop = alloc(size_t(wc) * (N * 3 + 1) * 8);  // proposal [wc][N][3], then its log|psi| [wc]
+  }
+  if (op == QMC_OP_MALA) {
+    w.lp_prop = alloc(size_t(wc) * (2 * N * 3 + 1) * 8);  // proposal, its gradient (both [wc][N][3]), log|psi|
   }
   w.total = cur;
   return w;
@@ -331,7 +334,7 @@ qmc_status qmc_plan_tiles(const qmc_plan* plan, int32_t s, int32_t tiles[4]) {
 }
 
 qmc_status qmc_workspace_size(const qmc_plan* plan, int32_t op, size_t* bytes) {
-  if (!plan || !bytes || op < QMC_OP_LOGPSI || op > QMC_OP_LOSS_GRAD) return QMC_ERR_INVALID_ARGUMENT;
+  if (!plan || !bytes || op < QMC_OP_LOGPSI || op > QMC_OP_MALA) return QMC_ERR_INVALID_ARGUMENT;
   *bytes = workspace_bytes(plan->p, op);
   return QMC_OK;
 }

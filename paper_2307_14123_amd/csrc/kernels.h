@@ -134,6 +134,13 @@ hipError_t launch_propose(const double* r, const double* noise, double step, int
                           hipStream_t st);
 hipError_t launch_accept(int64_t W, int N3, const double* rp, const double* lp_prop, const double* u,
                          double* r, double* logpsi, uint8_t* accepted, hipStream_t st);
+// Langevin step: drift proposal (one thread per electron) and Hastings acceptance (one per walker);
+// rp, gp [W][N][3] and lpp [W] are the proposal, its gradient and its log|psi|.
+hipError_t launch_propose_mala(const SysDev& s, const double* r, const double* g, const double* noise, double step,
+                               int damp, int64_t W, double* rp, hipStream_t st);
+hipError_t launch_accept_mala(const SysDev& s, int64_t W, const double* rp, const double* gp, const double* lpp,
+                              const double* noise, const double* u, double step, int damp, double* r, double* g,
+                              double* logpsi, uint8_t* accepted, hipStream_t st);
 
 // ---------------------------------------------------------------- backward
 

@@ -1218,6 +1218,111 @@ __global__ void accept_kernel(int64_t W, int N3, const double* __restrict__ rp, 
   if (accepted) accepted[w] = acc ? 1 : 0;
 }
 
+// ---------------------------------------------------------------- Langevin (MALA)
+
+// Drift of one electron at x with gradient v = grad_i log|psi| and time step tau: v itself, or
+// with damping v * 2 / (1 + sqrt(1 + 2 a |v|^2 tau)), a = 1/2 + (Z d)^2 / (10 (4 + (Z d)^2)) for
+// the nearest nucleus (lowest index on ties), scaled so that the drift step tau |v| stays <= d.
+__device__ inline void langevin_drift(const SysDev& s, const double* x, const double* v, double tau, int damp,
+                                      double D[3]) {
+#pragma clang fp contract(off)
+  D[0] = v[0];
+  D[1] = v[1];
+  D[2] = v[2];
+  if (!damp) return;
+  double d = INFINITY, Z = 0.0;
+  for (int I = 0; I < s.M; ++I) {
+    const double a0 = x[0] - s.R[3 * I], a1 = x[1] - s.R[3 * I + 1], a2 = x[2] - s.R[3 * I + 2];
+    const double dI = sqrt(a0 * a0 + a1 * a1 + a2 * a2);
+    if (dI < d) {
+      d = dI;
+      Z = s.Z[I];
+    }
+  }
+  const double zd = Z * d, zd2 = zd * zd;
+  const double a = 0.5 + zd2 / (10.0 * (4.0 + zd2));
+  const double v2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+  const double f = 2.0 / (1.0 + sqrt(1.0 + 2.0 * a * v2 * tau));
+  for (int c = 0; c < 3; ++c) D[c] = v[c] * f;
+  const double len = tau * sqrt(D[0] * D[0] + D[1] * D[1] + D[2] * D[2]);
+  if (len > d) {
+    const double cap = d / len;
+    for (int c = 0; c < 3; ++c) D[c] = D[c] * cap;
+  }
+}
+
+// r' = (r + tau D(r)) + step * xi, tau = step^2, one thread per electron.
+__global__ void propose_mala_kernel(SysDev s, const double* __restrict__ r, const double* __restrict__ g,
+                                    const double* __restrict__ noise, double step, int damp, int64_t n,
+                                    double* __restrict__ rp) {
+#pragma clang fp contract(off)
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  const double tau = step * step;
+  double x[3], v[3], D[3];
+  for (int c = 0; c < 3; ++c) {
+    x[c] = r[3 * t + c];
+    v[c] = g[3 * t + c];
+  }
+  langevin_drift(s, x, v, tau, damp, D);
+  for (int c = 0; c < 3; ++c) rp[3 * t + c] = (x[c] + tau * D[c]) + step * noise[3 * t + c];
+}
+
+// Hastings acceptance, one thread per walker:
+//   log a = 2 (l' - l) + |xi|^2 / 2 - |xi + step (D(r) + D(r'))|^2 / 2, accepted iff log u < log a.
+__global__ void accept_mala_kernel(SysDev s, int64_t W, const double* __restrict__ rp, const double* __restrict__ gp,
+                                   const double* __restrict__ lpp, const double* __restrict__ noise,
+                                   const double* __restrict__ u, double step, int damp, double* __restrict__ r,
+                                   double* __restrict__ g, double* __restrict__ logpsi,
+                                   uint8_t* __restrict__ accepted) {
+#pragma clang fp contract(off)
+  const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (w >= W) return;
+  const double tau = step * step;
+  const int64_t base = w * s.N * 3;
+  double fwd = 0.0, back = 0.0;
+  for (int i = 0; i < s.N; ++i) {
+    const int64_t o = base + 3 * i;
+    double D0[3], D1[3];
+    langevin_drift(s, r + o, g + o, tau, damp, D0);
+    langevin_drift(s, rp + o, gp + o, tau, damp, D1);
+    for (int c = 0; c < 3; ++c) {
+      const double xi = noise[o + c];
+      const double b = xi + step * (D0[c] + D1[c]);
+      fwd += xi * xi;
+      back += b * b;
+    }
+  }
+  const double la = 2.0 * (lpp[w] - logpsi[w]) + 0.5 * fwd - 0.5 * back;
+  const bool acc = log(u[w]) < la;
+  if (acc) {
+    for (int x = 0; x < 3 * s.N; ++x) {
+      r[base + x] = rp[base + x];
+      g[base + x] = gp[base + x];
+    }
+    logpsi[w] = lpp[w];
+  }
+  if (accepted) accepted[w] = acc ? 1 : 0;
+}
+
+hipError_t launch_propose_mala(const SysDev& s, const double* r, const double* g, const double* noise, double step,
+                               int damp, int64_t W, double* rp, hipStream_t st) {
+  ProfScope ps("propose_mala_kernel", st);
+  const int64_t n = W * s.N;
+  hipLaunchKernelGGL(propose_mala_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, s, r, g, noise, step,
+                     damp, n, rp);
+  return hipGetLastError();
+}
+
+hipError_t launch_accept_mala(const SysDev& s, int64_t W, const double* rp, const double* gp, const double* lpp,
+                              const double* noise, const double* u, double step, int damp, double* r, double* g,
+                              double* logpsi, uint8_t* accepted, hipStream_t st) {
+  ProfScope ps("accept_mala_kernel", st);
+  hipLaunchKernelGGL(accept_mala_kernel, dim3((unsigned)((W + 127) / 128)), dim3(128), 0, st, s, W, rp, gp, lpp,
+                     noise, u, step, damp, r, g, logpsi, accepted);
+  return hipGetLastError();
+}
+
 hipError_t launch_propose(const double* r, const double* noise, double step, int64_t n, double* rp, hipStream_t st) {
   ProfScope ps("propose_kernel", st);
   hipLaunchKernelGGL(propose_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, r, noise, step, n, rp);

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libqmc.so")
 
 QMC_FP64, QMC_FP32, QMC_BF16_MIXED = 0, 1, 2
 PRECISIONS = {"fp64": QMC_FP64, "fp32": QMC_FP32, "bf16": QMC_BF16_MIXED}
-OP_LOGPSI, OP_LOCAL_ENERGY, OP_METROPOLIS, OP_LOGPSI_VJP, OP_LOSS_GRAD = range(5)
+OP_LOGPSI, OP_LOCAL_ENERGY, OP_METROPOLIS, OP_LOGPSI_VJP, OP_LOSS_GRAD, OP_MALA = range(6)
 PLAN_CONCURRENT_SYSTEMS, PLAN_AUTOTUNE = 1, 2
 
 
@@ -62,6 +62,8 @@ def lib():
     L.qmc_local_energy.argtypes = [vp, vp, dp, dp, dp, dp, dp, dp, vp, sz, vp]
     L.qmc_metropolis_step.restype = i32
     L.qmc_metropolis_step.argtypes = [vp, vp, dp, dp, dp, dp, ctypes.c_double, vp, vp, sz, vp]
+    L.qmc_mala_step.restype = i32
+    L.qmc_mala_step.argtypes = [vp, vp, dp, dp, dp, dp, dp, ctypes.c_double, i32, vp, vp, sz, vp]
     L.qmc_logpsi_vjp.restype = i32
     L.qmc_logpsi_vjp.argtypes = [vp, vp, dp, dp, vp, vp, sz, vp]
     L.qmc_loss_grad.restype = i32
@@ -231,6 +233,24 @@ class Plan:
         _check(lib().qmc_metropolis_step(self.handle, _ptr(params), _ptr(r), _ptr(logpsi), _ptr(noise), _ptr(u),
                                          float(step), _ptr(accepted), _ptr(ws), ws.numel(), _stream()),
                "qmc_metropolis_step")
+        return accepted
+
+    def mala_step(self, params, r, logpsi, grad, noise, u, step, damp=True, accepted=None):
+        """One Langevin step, in place on r, logpsi and grad (grad log|psi| of the current state, e.g.
+        local_energy(...)["grad"]); returns the uint8 acceptance flags."""
+        self._check_inputs(params, r)
+        W = self.total_walkers
+        for name, t in (("noise", noise), ("grad", grad)):
+            if t.dtype != torch.float64 or t.numel() != self.total_positions or not t.is_contiguous():
+                raise ValueError(f"{name}: expected contiguous float64 like r")
+        if u.dtype != torch.float64 or u.numel() != W or logpsi.dtype != torch.float64 or logpsi.numel() != W:
+            raise ValueError("u/logpsi: expected float64 [W]")
+        if accepted is None:
+            accepted = torch.empty(W, dtype=torch.uint8, device=r.device)
+        ws = self.workspace(OP_MALA)
+        _check(lib().qmc_mala_step(self.handle, _ptr(params), _ptr(r), _ptr(logpsi), _ptr(grad), _ptr(noise),
+                                   _ptr(u), float(step), int(bool(damp)), _ptr(accepted), _ptr(ws), ws.numel(),
+                                   _stream()), "qmc_mala_step")
         return accepted
 
     def logpsi_vjp(self, params, r, cotangent):

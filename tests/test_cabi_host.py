@@ -79,6 +79,18 @@ def test_invalid_arguments_rejected():
         assert L.qmc_metropolis_step(handle, fake, fake, fake, fake, fake, float("nan"), None, vp(0x10000),
                                      sz.value, None) == 1
         assert L.qmc_loss_grad(handle, fake, fake, None, fake, None, vp(0x10000), 1 << 40, None) == 1
+        # Langevin: step and damping flag, missing gradient, small workspace
+        assert L.qmc_workspace_size(handle, 5, ctypes.byref(sz)) == 0
+        assert L.qmc_mala_step(handle, fake, fake, fake, fake, fake, fake, -0.1, 1, None, vp(0x10000), sz.value,
+                               None) == 1
+        assert L.qmc_mala_step(handle, fake, fake, fake, fake, fake, fake, float("inf"), 1, None, vp(0x10000),
+                               sz.value, None) == 1
+        assert L.qmc_mala_step(handle, fake, fake, fake, fake, fake, fake, 0.1, 2, None, vp(0x10000), sz.value,
+                               None) == 1
+        assert L.qmc_mala_step(handle, fake, fake, fake, None, fake, fake, 0.1, 1, None, vp(0x10000), sz.value,
+                               None) == 1
+        assert L.qmc_mala_step(handle, fake, fake, fake, fake, fake, fake, 0.1, 1, None, vp(0x10000), 16,
+                               None) == 3
         # determinant entry: bad sizes
         assert L.qmc_det_jets(4, 0, 3, fake, fake, fake, fake, fake, None) == 1
         assert L.qmc_det_jets(4, 33, 3, fake, fake, fake, fake, fake, None) == 1
