@@ -75,7 +75,7 @@ def algorithmic_model(s, a, elem_bytes, n_mc, with_grad, fused_edges):
         "wgrad_kernel": ("mfma", wgrad if with_grad else 0),
         # HBM-bound kernels: bytes of jets read and written
         "aggregate_kernel": ("hbm", L * eb * (N * R1 * D + N * R1 * 2 * D + (P[0] + P[1]) * 3 * D)),
-        "det_kernel": ("hbm", eb * nd * R1 * nsq + 8 * 2 * nd * (T + 3)),
+        "det_kernel<jet>": ("hbm", eb * nd * R1 * nsq + 8 * 2 * nd * (T + 3)),
         "envelope_kernel<jet>": ("hbm", 2 * eb * nd * R1 * nsq),
     }
     if eb == 4:
@@ -159,9 +159,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="n2", choices=["n2", "c4h4", "h2", "batched"],
+    ap.add_argument("--workload", default="n2", choices=["n2", "c4h4", "h2", "batched", "scaling"],
                     help="n2: the headline workload; c4h4 / h2: the precision and small FP64 systems; "
-                         "batched: 16 molecules (4-42 electrons) in one graph vs per-molecule launches")
+                         "batched: 16 molecules (4-42 electrons) in one graph vs per-molecule launches; "
+                         "scaling: train-step time of atoms and hydrogen chains up to 45 electrons")
     ap.add_argument("--walkers", type=int, default=None)
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64", "bf16"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -180,6 +181,8 @@ def main():
 
     if args.workload == "batched":
         return bench_batched(args)
+    if args.workload == "scaling":
+        return bench_scaling(args)
     k = {"n2": 1, "c4h4": 3, "h2": 0}[args.workload]
     wl = qi.workload(k)
     s, a = wl.systems[0], wl.ansatz
@@ -203,8 +206,8 @@ def main():
            "lap": torch.empty(W, dtype=torch.float64, device=dev),
            "e_loc": torch.empty(W, dtype=torch.float64, device=dev)}
     acc = torch.empty(W, dtype=torch.uint8, device=dev)
-    for op in range(3):
-        plan.workspace(op)
+    for op in (qmc.OP_LOGPSI, qmc.OP_LOCAL_ENERGY, qmc.OP_METROPOLIS, qmc.OP_MALA):
+        plan.workspace(op)  # the shared workspace reaches its size before any capture
     has_grad = True
     try:
         plan.loss_grad(P, R, out["e_loc"])
@@ -292,6 +295,33 @@ def main():
     est, _ = timed(le_run, 1)
     reps = int(min(60, max(50 if est < 20 else 1, args.steps, math.ceil(1000.0 / max(est, 1e-3)))))
     ms_le, le_ms = timed(le_run, reps)
+
+    # Langevin steps alone (the gradient-informed sampler), from the state the local energy left:
+    # drift proposal, jet forward at the proposal (log|psi| and its gradient), Hastings acceptance;
+    # n_mc steps per repetition with the step's noise streams
+    mala_eps = 0.1
+    Rm, LPm, Gm = R.clone(), out["logpsi"].clone(), out["grad"].clone()
+    ACCm = torch.empty((n_mc, W), dtype=torch.uint8, device=dev)
+
+    def mala_eager():
+        for t in range(n_mc):
+            plan.mala_step(P, Rm, LPm, Gm, NOISE[t], U[t], mala_eps, accepted=ACCm[t])
+
+    mala_eager()
+    torch.cuda.synchronize()
+    mala_run, mala_launch = mala_eager, "eager"
+    if graph is not None:
+        try:
+            gm = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(gm):
+                mala_eager()
+            gm.replay()
+            torch.cuda.synchronize()
+            mala_run, mala_launch = gm.replay, f"one HIP graph per {n_mc} steps"
+        except Exception:  # noqa: BLE001 - eager steps then
+            pass
+    ms_mala, mala_ms = timed(mala_run, 3)
+    mala_acc = float(ACCm.double().mean().item())
     peaks = qmc.measure_peaks()
 
     eb = 8 if args.precision == "fp64" else 4
@@ -367,6 +397,10 @@ def main():
         "step_ms_eager_events": dist(eager_ms),
         "kernel_timing": "HIP events around every launch, in an eager pass over the same steps",
         "e_loc_ms_events": dist(le_ms),
+        "mala_step": {"ms": ms_mala / n_mc, "walkers_per_s": W * n_mc / (ms_mala * 1e-3),
+                      "events_ms_per_repetition": dist(mala_ms), "steps_per_repetition": n_mc,
+                      "launch": mala_launch, "step_size": mala_eps, "damped_drift": True,
+                      "acceptance_last_repetition": mala_acc},
         "roofline": roof,
         "measured_peaks": {"fp32_mfma_tflops": peaks["fp32_mfma"], "bf16_mfma_tflops": peaks["bf16_mfma"],
                            "fp64_mfma_tflops": peaks["fp64_mfma"], "copy_gbs": peaks["copy"]},
@@ -502,6 +536,109 @@ def bench_batched(args):
     }
     print(json.dumps(res))
 
+
+def bench_scaling(args):
+    """Train-step time against system size (Sec. VI, scaling): atoms and hydrogen chains up to 45 electrons,
+    2000 walkers each, the N2-sized ansatz at random init; one step = the train step of the headline
+    workload (10 Metropolis steps + local energy + loss gradient + gradient-descent update), captured into
+    one HIP graph per system.  A power law t = c N^b is fitted per system class."""
+    import torch
+    import qmc_inputs as qi
+    from paper_2307_14123_amd import qmc
+
+    a = qi.SCALING_ANSATZ
+    W = args.walkers or qi.SCALING_WALKERS
+    prec = args.precision
+    n_mc, tau, lr = 10, 0.2, 1e-8
+    dev = torch.device("cuda", 0)
+    steps = max(2, args.steps)
+    rows = []
+    for cls, sizes, make in (("atoms", qi.SCALING_ATOMS, qi.atom), ("chains", qi.SCALING_CHAINS, qi.hydrogen_chain)):
+        for n in sizes:
+            s = make(n)
+            plan = qmc.Plan([s], [W], a, prec)
+            P = torch.as_tensor(qi.make_params(s, a, 9000 + n), dtype=plan.param_dtype, device=dev).contiguous()
+            R = torch.as_tensor(qi.make_walkers(s, W, 9100 + n), device=dev).contiguous()
+            NOISE = torch.as_tensor(qi.make_noise(n_mc, W, s.n_elec, 9200 + n), device=dev).contiguous()
+            U = torch.as_tensor(qi.make_uniforms(n_mc, W, 9300 + n), device=dev).contiguous()
+            for op in (qmc.OP_LOGPSI, qmc.OP_LOCAL_ENERGY, qmc.OP_METROPOLIS):
+                plan.workspace(op)
+            lp, _ = plan.logpsi(P, R)
+            out = plan.local_energy(P, R)
+            G, EM = plan.loss_grad(P, R, out["e_loc"])
+            acc = torch.empty(W, dtype=torch.uint8, device=dev)
+
+            def step():
+                for t in range(n_mc):
+                    plan.metropolis_step(P, R, lp, NOISE[t], U[t], tau, accepted=acc)
+                plan.local_energy(P, R, out=out)
+                plan.loss_grad(P, R, out["e_loc"], grad=G, e_mean=EM)
+                plan.sgd_update(P, G, lr)
+
+            for _ in range(max(1, args.warmup)):
+                step()
+            torch.cuda.synchronize()
+            run, launch = step, "eager"
+            try:
+                side = torch.cuda.Stream()
+                side.wait_stream(torch.cuda.current_stream())
+                with torch.cuda.stream(side):
+                    step()
+                torch.cuda.current_stream().wait_stream(side)
+                g = torch.cuda.CUDAGraph()
+                with torch.cuda.graph(g):
+                    step()
+                g.replay()
+                torch.cuda.synchronize()
+                run, launch = g.replay, "graph"
+            except Exception:  # noqa: BLE001 - eager steps then
+                g = None
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(steps):
+                run()
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / steps
+            e0.record()
+            plan.local_energy(P, R, out=out)
+            e1.record()
+            torch.cuda.synchronize()
+            ms_le = e0.elapsed_time(e1)
+            finite = float(torch.isfinite(out["e_loc"]).double().mean().item())
+            rows.append({"class": cls, "n": n, "electrons": s.n_elec, "nuclei": s.n_nuc, "step_ms": ms,
+                         "e_loc_ms": ms_le, "launch": launch, "finite_e_loc_fraction": finite})
+            print(f"[scaling] {cls} n={n}: step {ms:.2f} ms, local energy {ms_le:.2f} ms ({launch})", file=sys.stderr,
+                  flush=True)
+            del g, plan, P, R, NOISE, U, lp, out, G, EM, acc
+            torch.cuda.empty_cache()
+
+    def fit(cls, key, nmin):
+        pts = [(r["electrons"], r[key]) for r in rows if r["class"] == cls and r["electrons"] >= nmin]
+        b, c = np.polyfit(np.log([x for x, _ in pts]), np.log([y for _, y in pts]), 1)
+        return float(b)
+
+    fits = {cls: {"step_exponent_all": fit(cls, "step_ms", 1), "step_exponent_n_ge_10": fit(cls, "step_ms", 10),
+                  "e_loc_exponent_all": fit(cls, "e_loc_ms", 1), "e_loc_exponent_n_ge_10": fit(cls, "e_loc_ms", 10)}
+            for cls in ("atoms", "chains")}
+    largest = max(rows, key=lambda r: r["step_ms"])
+    res = {
+        "metric": "train step time vs electron count (power-law exponent)",
+        "value": fits["chains"]["step_exponent_all"],
+        "unit": "exponent",
+        "n_gpus": 1, "steps": steps, "warmup": args.warmup, "ms_per_step": largest["step_ms"],
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": {"fp32": "f32+f64", "fp64": "f64", "bf16": "bf16+f32+f64"}[prec],
+        "data": "synthetic",
+        "config": {"workload": f"atoms Z in {list(qi.SCALING_ATOMS)} and hydrogen chains n in "
+                               f"{list(qi.SCALING_CHAINS)} (1.8 bohr spacing), {W} walkers, width {a.width}, "
+                               f"{a.mp_layers} message-passing layers, {a.n_det} dets; step = {n_mc} Metropolis "
+                               f"steps + local energy + loss gradient + update",
+                   "walkers": W, "precision": prec},
+        "fits": fits,
+        "rows": rows,
+    }
+    print(json.dumps(res))
 
 if __name__ == "__main__":
     main()

@@ -268,6 +268,11 @@ qmc_status qmc_profile_report(char* buf, size_t len, int32_t reset);
 
 const char* qmc_status_str(qmc_status status);
 
+/* Text of the calling thread's last QMC_ERR_HIP: the HIP error name and the
+ * failing launch or call ("" before the first failure).  Static storage owned
+ * by the library, valid until the thread's next failing call. */
+const char* qmc_last_error(void);
+
 #ifdef __cplusplus
 }
 #endif

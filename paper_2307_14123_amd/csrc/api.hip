@@ -2,6 +2,7 @@
 // of each system and walker chunk on the caller's stream.
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 
 #include <mutex>
@@ -54,10 +55,18 @@ static SysDev make_dev(const Plan& P, const SysPlan& s) {
   return d;
 }
 
-#define CK(x)                                  \
-  do {                                         \
-    hipError_t e_ = (x);                       \
-    if (e_ != hipSuccess) return QMC_ERR_HIP;  \
+// The last HIP failure of this thread: error name, the failing call and its line.
+static thread_local char g_last_error[512];
+
+static qmc_status hip_failed(hipError_t e, const char* call, int line) {
+  snprintf(g_last_error, sizeof(g_last_error), "%s at api.hip:%d in %s", hipGetErrorName(e), line, call);
+  return QMC_ERR_HIP;
+}
+
+#define CK(x)                                                   \
+  do {                                                          \
+    hipError_t e_ = (x);                                        \
+    if (e_ != hipSuccess) return hip_failed(e_, #x, __LINE__);  \
   } while (0)
 
 static GemmKind embed_kind(qmc_precision p) {
@@ -772,6 +781,8 @@ qmc_status qmc_det_jets(int64_t n_mat, int32_t n, int32_t n_tan, const double* j
   CK(launch_det_generic(n_mat, n, n_tan, jets, logdet, sign, grad, lap, (hipStream_t)stream));
   return QMC_OK;
 }
+
+const char* qmc_last_error(void) { return g_last_error; }
 
 qmc_status qmc_sgd_update(int32_t precision, void* params, const void* grad, int64_t n, double lr, void* stream) {
   if (n < 0 || (n > 0 && (!params || !grad)) || !std::isfinite(lr)) return QMC_ERR_INVALID_ARGUMENT;

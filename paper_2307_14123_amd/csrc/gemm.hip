@@ -575,13 +575,20 @@ static hipError_t launch_kind_bk(const GemmArgs& a, int bits, hipStream_t st) {
     return half ? launch_mb<KIND, 4, 0, BKT>(a, persist, st) : launch_mb<KIND, 8, 0, BKT>(a, persist, st);
   if (a.Rp == 4)
     return half ? launch_mb<KIND, 4, 1, BKT>(a, persist, st) : launch_mb<KIND, 8, 1, BKT>(a, persist, st);
-  if (a.Rp % 16 != 0 || a.Rp > 128) return hipErrorInvalidValue;
+  // a tile holds whole jet groups: as many as fit in 128 rows, or one group of up to 208 rows
+  // (3N + 2 rows for up to 64 electrons)
+  if (a.Rp % 16 != 0 || a.Rp > 208) return hipErrorInvalidValue;
   const int bpg = a.Rp / 16;
-  switch (bpg * (8 / bpg)) {
+  switch (bpg <= 8 ? bpg * (8 / bpg) : bpg) {
     case 5: return launch_mb<KIND, 5, 2, BKT>(a, persist, st);
     case 6: return launch_mb<KIND, 6, 2, BKT>(a, persist, st);
     case 7: return launch_mb<KIND, 7, 2, BKT>(a, persist, st);
     case 8: return launch_mb<KIND, 8, 2, BKT>(a, persist, st);
+    case 9: return launch_mb<KIND, 9, 2, BKT>(a, persist, st);
+    case 10: return launch_mb<KIND, 10, 2, BKT>(a, persist, st);
+    case 11: return launch_mb<KIND, 11, 2, BKT>(a, persist, st);
+    case 12: return launch_mb<KIND, 12, 2, BKT>(a, persist, st);
+    case 13: return launch_mb<KIND, 13, 2, BKT>(a, persist, st);
   }
   return hipErrorInvalidValue;
 }

@@ -82,6 +82,8 @@ def lib():
     L.qmc_plan_tiles.argtypes = [vp, i32, ctypes.POINTER(i32)]
     L.qmc_status_str.restype = ctypes.c_char_p
     L.qmc_status_str.argtypes = [i32]
+    L.qmc_last_error.restype = ctypes.c_char_p
+    L.qmc_last_error.argtypes = []
     _lib = L
     return L
 
@@ -92,7 +94,10 @@ class QmcError(RuntimeError):
 
 def _check(status: int, what: str):
     if status != 0:
-        raise QmcError(f"{what}: {lib().qmc_status_str(status).decode()}")
+        msg = f"{what}: {lib().qmc_status_str(status).decode()}"
+        if status == 4:  # QMC_ERR_HIP: name the failing launch
+            msg += f" ({lib().qmc_last_error().decode()})"
+        raise QmcError(msg)
 
 
 def _ptr(t):

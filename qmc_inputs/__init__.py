@@ -225,6 +225,29 @@ def workload(k: int) -> Workload:
     raise ValueError(k)
 
 
+# --------------------------------------------------------------------------
+# System-size sweep (Sec. VI, scaling): atoms and hydrogen chains up to 45 electrons
+# --------------------------------------------------------------------------
+
+SCALING_ATOMS = (2, 4, 6, 10, 14, 18, 24, 30, 36, 45)
+SCALING_CHAINS = (2, 4, 6, 10, 14, 18, 24, 30, 36, 44)
+SCALING_WALKERS = 2000
+SCALING_ANSATZ = N2_ANSATZ
+
+
+def atom(Z: int) -> System:
+    """A neutral atom of charge Z at the origin with the smallest spin polarisation
+    (n_up = ceil(Z / 2))."""
+    return System((float(Z),), ((0.0, 0.0, 0.0),), (Z + 1) // 2, Z // 2)
+
+
+def hydrogen_chain(n: int, spacing: float = 1.8) -> System:
+    """n hydrogen atoms equally spaced (bohr) on the z axis, centred on the origin, neutral,
+    n_up = ceil(n / 2)."""
+    z0 = -0.5 * spacing * (n - 1)
+    return System((1.0,) * n, tuple((0.0, 0.0, z0 + spacing * i) for i in range(n)), (n + 1) // 2, n // 2)
+
+
 def seed(k: int, j: int) -> int:
     return 1000 * k + j
 
