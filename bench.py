@@ -322,6 +322,28 @@ def main():
             pass
     ms_mala, mala_ms = timed(mala_run, 3)
     mala_acc = float(ACCm.double().mean().item())
+
+    # Metropolis steps alone, for the comparison with the Langevin step (same walkers, same count)
+    Rq, LPq = R.clone(), out["logpsi"].clone()
+
+    def metro_eager():
+        for t in range(n_mc):
+            plan.metropolis_step(P, Rq, LPq, NOISE[t], U[t], tau, accepted=ACCm[t])
+
+    metro_eager()
+    torch.cuda.synchronize()
+    metro_run = metro_eager
+    if graph is not None:
+        try:
+            gq = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(gq):
+                metro_eager()
+            gq.replay()
+            torch.cuda.synchronize()
+            metro_run = gq.replay
+        except Exception:  # noqa: BLE001 - eager steps then
+            pass
+    ms_metro, _ = timed(metro_run, 3)
     peaks = qmc.measure_peaks()
 
     eb = 8 if args.precision == "fp64" else 4
@@ -400,7 +422,8 @@ def main():
         "mala_step": {"ms": ms_mala / n_mc, "walkers_per_s": W * n_mc / (ms_mala * 1e-3),
                       "events_ms_per_repetition": dist(mala_ms), "steps_per_repetition": n_mc,
                       "launch": mala_launch, "step_size": mala_eps, "damped_drift": True,
-                      "acceptance_last_repetition": mala_acc},
+                      "acceptance_last_repetition": mala_acc,
+                      "metropolis_step_ms": ms_metro / n_mc},
         "roofline": roof,
         "measured_peaks": {"fp32_mfma_tflops": peaks["fp32_mfma"], "bf16_mfma_tflops": peaks["bf16_mfma"],
                            "fp64_mfma_tflops": peaks["fp64_mfma"], "copy_gbs": peaks["copy"]},
@@ -606,8 +629,21 @@ def bench_scaling(args):
             torch.cuda.synchronize()
             ms_le = e0.elapsed_time(e1)
             finite = float(torch.isfinite(out["e_loc"]).double().mean().item())
+            # one eager step with HIP events around every launch: the largest kernel families
+            qmc.profile_enable(True)
+            qmc.profile_report(reset=True)
+            step()
+            torch.cuda.synchronize()
+            prof = qmc.profile_report(reset=True)
+            qmc.profile_enable(False)
+            fam = {}
+            for kname, (_, kms) in prof.items():
+                f = kernel_family(kname)
+                fam[f] = fam.get(f, 0.0) + kms
+            top = {k: round(v, 2) for k, v in sorted(fam.items(), key=lambda kv: -kv[1])[:6]}
             rows.append({"class": cls, "n": n, "electrons": s.n_elec, "nuclei": s.n_nuc, "step_ms": ms,
-                         "e_loc_ms": ms_le, "launch": launch, "finite_e_loc_fraction": finite})
+                         "e_loc_ms": ms_le, "launch": launch, "finite_e_loc_fraction": finite,
+                         "eager_step_kernels_ms": top})
             print(f"[scaling] {cls} n={n}: step {ms:.2f} ms, local energy {ms_le:.2f} ms ({launch})", file=sys.stderr,
                   flush=True)
             del g, plan, P, R, NOISE, U, lp, out, G, EM, acc
