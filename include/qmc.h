@@ -73,7 +73,14 @@ typedef struct qmc_system {
  *   mp_layers       : message-passing interaction layers
  *   n_det           : determinants
  *   n_env           : envelope exponents per (orbital, nucleus)
- *   include_vnn     : add sum_{I<J} Z_I Z_J / R_IJ to the potential */
+ *   include_vnn     : add sum_{I<J} Z_I Z_J / R_IJ to the potential
+ *   ee_cusp         : alpha > 0 multiplies psi by the fixed electron-electron
+ *                     cusp factor exp(gamma) of Sec. III.D, taken as
+ *                     gamma = sum_{i<j} -c_ij alpha^2 / (alpha + r_ij) with
+ *                     c_ij = 1/4 (same spin) or 1/2 (opposite spin), whose
+ *                     slope at r_ij = 0 is c_ij for every alpha; 0 = none.
+ *                     It has no parameters: gradients of log|psi| with respect
+ *                     to the blob do not change. */
 typedef struct qmc_ansatz {
   int32_t version;
   int32_t n_rbf;
@@ -84,6 +91,7 @@ typedef struct qmc_ansatz {
   int32_t n_det;
   int32_t n_env;
   int32_t include_vnn;
+  double ee_cusp;
 } qmc_ansatz;
 
 typedef enum qmc_precision {

@@ -123,8 +123,25 @@ def combine(logdets, signs, c):
     return torch.sign(S), mx[:, 0] + torch.log(torch.abs(S))
 
 
+def ee_cusp(r, system, alpha):
+    """Fixed electron-electron cusp factor exp(gamma) (Sec. III.D, electron-cusp equation).
+
+    Read as gamma = sum_{i<j} -c_ij alpha^2 / (alpha + r_ij), c_ij = 1/4 for same-spin and 1/2 for
+    opposite-spin pairs: its slope at r_ij = 0 is c_ij for every alpha (Kato's electron-electron
+    cusps), and alpha is the length over which it acts.  As printed, -alpha c / (1 + alpha r) has
+    slope alpha^2 c at coalescence, which meets the cusp condition only at alpha = 1; the two forms
+    agree there."""
+    N = r.shape[1]
+    i, j = torch.triu_indices(N, N, 1)
+    d = torch.linalg.vector_norm(r[:, i] - r[:, j], dim=-1)                     # [B, pairs]
+    same = (i < system.n_up) == (j < system.n_up)
+    c = torch.where(same, torch.tensor(0.25, dtype=r.dtype), torch.tensor(0.5, dtype=r.dtype))
+    return (-c * alpha * alpha / (alpha + d)).sum(-1)
+
+
 def logpsi(r, params, system, ans):
-    """(sign, log|psi|) for walkers r [B, N, 3] (torch float64)."""
+    """(sign, log|psi|) for walkers r [B, N, 3] (torch float64); with ans.ee_cusp = alpha > 0 the
+    fixed electron-electron cusp factor (ee_cusp) multiplies psi."""
     P = unpack(params, system, ans)
     mats = orbital_matrices(r, P, system, ans)
     B = r.shape[0]
@@ -136,4 +153,8 @@ def logpsi(r, params, system, ans):
         s, l = torch.linalg.slogdet(A)
         logdet = logdet + l
         sign = sign * s
-    return combine(logdet, sign, P["c"])
+    sg, lp = combine(logdet, sign, P["c"])
+    alpha = float(getattr(ans, "ee_cusp", 0.0))
+    if alpha > 0 and r.shape[1] > 1:
+        lp = lp + ee_cusp(r, system, alpha)
+    return sg, lp

@@ -6,7 +6,8 @@ finite-difference tests of the gradient and Laplacian.  Same passages as the
 torch forward: radial basis and node initialisation (Sec. III.A), graph
 convolution with mean normalisation and concatenation update (Sec. III.A),
 orbitals times isotropic envelopes (Sec. III.B), spin-factorised determinants
-(Sec. III.C), log-sum-exp over determinants (Sec. III.E).
+(Sec. III.C), log-sum-exp over determinants (Sec. III.E), optional fixed
+electron-electron cusp factor (Sec. III.D).
 """
 from __future__ import annotations
 
@@ -108,5 +109,13 @@ def logpsi_np(r, params, system, ans):
     mx = np.max(logdet, axis=1)
     mx = np.where(np.isfinite(mx), mx, 0.0)
     S = np.sum(c[None, :] * sign * np.exp(logdet - mx[:, None]), axis=1)
+    alpha = float(getattr(ans, "ee_cusp", 0.0))
+    gamma = np.zeros(W)
+    if alpha > 0:
+        # fixed electron-electron cusp factor exp(gamma) (Sec. III.D), pair by pair
+        for i in range(N):
+            for j in range(i + 1, N):
+                c_ij = 0.25 if spin[i] == spin[j] else 0.5
+                gamma += -c_ij * alpha * alpha / (alpha + dee[i][j])
     with np.errstate(divide="ignore"):
-        return np.sign(S), mx + np.log(np.abs(S))
+        return np.sign(S), mx + np.log(np.abs(S)) + gamma

@@ -48,6 +48,7 @@ static SysDev make_dev(const Plan& P, const SysPlan& s) {
   d.P2 = s.P[2];
   d.dmax = P.ans.rbf_dmax;
   d.vnn = P.ans.include_vnn ? s.vnn : 0.0;
+  d.ee_cusp = P.ans.ee_cusp;
   for (int I = 0; I < s.M; ++I) {
     d.Z[I] = s.Z[I];
     for (int x = 0; x < 3; ++x) d.R[3 * I + x] = s.R[3 * I + x];
@@ -215,7 +216,7 @@ static qmc_status forward_chunk(const Plan& P, const SysPlan& s, const S* prm, c
     off_e += n;
   }
   CK(launch_det<S>(dv, ajet, wc, jet, dld, dsg, dg, dlap, nullptr, st));
-  CK(launch_combine<S>(dv, prm + O.c, dld, dsg, dg, dlap, vpot, wc, jet, out.logpsi, out.sign, out.grad, out.lap,
+  CK(launch_combine<S>(dv, prm + O.c, dld, dsg, dg, dlap, vpot, ee, wc, jet, out.logpsi, out.sign, out.grad, out.lap,
                        out.eloc, st));
   return QMC_OK;
 }

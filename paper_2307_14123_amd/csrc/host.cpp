@@ -224,6 +224,7 @@ static bool valid_ansatz(const qmc_ansatz* a) {
   if (a->mp_layers < 0 || a->mp_layers > 16) return false;
   if (a->n_det < 1 || a->n_det > 64 || a->n_env < 1 || a->n_env > 32) return false;
   if (a->include_vnn != 0 && a->include_vnn != 1) return false;
+  if (!std::isfinite(a->ee_cusp) || a->ee_cusp < 0) return false;
   return true;
 }
 

@@ -66,6 +66,7 @@ hipError_t launch_gemm(GemmKind kind, const GemmArgs& a, hipStream_t st);
 struct SysDev {
   int N, M, nup, ndn, T, Rp, K, D, ndet, nenv, P0, P1, P2;
   double dmax, vnn;
+  double ee_cusp;  // alpha of the electron-electron cusp factor (0: none)
   double Z[64];
   double R[64 * 3];
 };
@@ -126,8 +127,8 @@ hipError_t launch_det_generic(int64_t nmat, int n, int ntan, const double* jets,
 
 template <typename S>
 hipError_t launch_combine(const SysDev& s, const S* c, const double* ld, const double* sg,
-                          const double* g, const double* dlap, const double* vpot, int64_t W, int jet,
-                          double* logpsi, double* sign, double* grad, double* lap, double* eloc,
+                          const double* g, const double* dlap, const double* vpot, const double* ee, int64_t W,
+                          int jet, double* logpsi, double* sign, double* grad, double* lap, double* eloc,
                           hipStream_t st);
 
 hipError_t launch_propose(const double* r, const double* noise, double step, int64_t n, double* rp,

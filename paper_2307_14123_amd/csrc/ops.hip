@@ -1107,11 +1107,17 @@ hipError_t launch_det_generic(int64_t nmat, int n, int ntan, const double* jets,
 // w_p = c_p D_p / psi: grad log|psi| = sum_p w_p grad l_p,
 // Delta psi / psi = sum_p w_p (Delta l_p + |grad l_p|^2),
 // E_loc = -1/2 Delta psi / psi + V.  One wavefront per walker.
+// With the electron-electron cusp factor exp(gamma), gamma = sum_{i<j} -c_ij a^2 / (a + r_ij),
+// log|psi| gains gamma, grad gains grad gamma, and Delta psi / psi gains
+// Delta gamma + 2 grad l . grad gamma + |grad gamma|^2 (l the determinant part), with
+// gamma' = c a^2 / (a + r)^2, gamma'' = -2 c a^2 / (a + r)^3, grad_i gamma = sum_j gamma'(r_ij) u_ij
+// and Delta gamma = sum_{i<j} 2 (gamma'' + 2 gamma' / r_ij).
 template <typename S>
 __global__ __launch_bounds__(64) void combine_kernel(SysDev s, const S* __restrict__ c, const double* __restrict__ ld,
                                                      const double* __restrict__ sg, const double* __restrict__ g,
                                                      const double* __restrict__ dlap, const double* __restrict__ vpot,
-                                                     int jet, double* __restrict__ logpsi, double* __restrict__ sign,
+                                                     const double* __restrict__ ee, int jet,
+                                                     double* __restrict__ logpsi, double* __restrict__ sign,
                                                      double* __restrict__ grad, double* __restrict__ lap,
                                                      double* __restrict__ eloc) {
   const int64_t w = blockIdx.x;
@@ -1136,15 +1142,35 @@ __global__ __launch_bounds__(64) void combine_kernel(SysDev s, const S* __restri
       }
     if (sgn != 0.0) S_ += sgn * exp(l - mx);
   }
-  const double lp = mx + log(fabs(S_));
   const double sgnpsi = S_ > 0 ? 1.0 : (S_ < 0 ? -1.0 : 0.0);
+  // electron-electron cusp factor: its value and Laplacian over the pairs i < j
+  const int N = s.N;
+  const bool cusp = s.ee_cusp > 0.0 && N > 1;
+  const double ca2 = s.ee_cusp * s.ee_cusp;
+  const double* eew = ee + w * (int64_t)N * N * 4;  // [N][N][4]: r_ij, unit vector of r_i - r_j
+  double gam = 0.0, glap = 0.0;
+  if (cusp) {
+    for (int e = lane; e < N * N; e += 64) {
+      const int i = e / N, j = e - (e / N) * N;
+      if (j <= i) continue;
+      const double d = eew[4 * e];
+      const double cij = ((i < s.nup) == (j < s.nup)) ? 0.25 : 0.5;
+      const double q = 1.0 / (s.ee_cusp + d);
+      gam -= cij * ca2 * q;
+      const double g1 = cij * ca2 * q * q, g2 = -2.0 * g1 * q;
+      glap += 2.0 * (g2 + 2.0 * g1 / d);
+    }
+    gam = wave_sum(gam);
+    glap = wave_sum(glap);
+  }
+  const double lp = mx + log(fabs(S_)) + gam;
   if (lane == 0) {
     if (logpsi) logpsi[w] = lp;
     if (sign) sign[w] = sgnpsi;
   }
   if (!jet) return;
   const double invS = 1.0 / S_;
-  double Apart = 0.0, Bpart = 0.0;
+  double Apart = 0.0, Bpart = 0.0, Cpart = 0.0;
   for (int cc = lane; cc < s.T; cc += 64) {
     double gc = 0.0, a2 = 0.0;
     for (int p = 0; p < nd; ++p) {
@@ -1162,9 +1188,23 @@ __global__ __launch_bounds__(64) void combine_kernel(SysDev s, const S* __restri
     }
     Apart += a2;
     Bpart += gc * gc;
+    if (cusp) {
+      // d gamma / d x_cc: the pairs of electron i = cc / 3, coordinate cc % 3
+      const int i = cc / 3, a = cc - 3 * (cc / 3);
+      double dg = 0.0;
+      for (int j = 0; j < N; ++j) {
+        if (j == i) continue;
+        const double* pij = eew + 4 * (i * N + j);
+        const double cij = ((i < s.nup) == (j < s.nup)) ? 0.25 : 0.5;
+        const double q = 1.0 / (s.ee_cusp + pij[0]);
+        dg += cij * ca2 * q * q * pij[1 + a];
+      }
+      Cpart += 2.0 * gc * dg + dg * dg;
+      gc += dg;
+    }
     if (grad) grad[w * s.T + cc] = sgnpsi != 0.0 ? gc : NAN;
   }
-  const double A = wave_sum(Apart), B = wave_sum(Bpart);
+  const double A = wave_sum(Apart), B = wave_sum(Bpart), C = wave_sum(Cpart);
   if (lane == 0) {
     double lsum = 0.0;
     for (int p = 0; p < nd; ++p) {
@@ -1179,18 +1219,18 @@ __global__ __launch_bounds__(64) void combine_kernel(SysDev s, const S* __restri
       if (sgn != 0.0) lsum += sgn * exp(l - mx) * invS * dl;
     }
     const double ok = sgnpsi != 0.0 ? 1.0 : NAN;
-    if (lap) lap[w] = ok * (lsum + A - B);
-    if (eloc) eloc[w] = ok * (-0.5 * (lsum + A) + vpot[w]);
+    if (lap) lap[w] = ok * (lsum + A - B + glap);
+    if (eloc) eloc[w] = ok * (-0.5 * (lsum + A + glap + C) + vpot[w]);
   }
 }
 
 template <typename S>
 hipError_t launch_combine(const SysDev& s, const S* c, const double* ld, const double* sg, const double* g,
-                          const double* dlap, const double* vpot, int64_t W, int jet, double* logpsi, double* sign,
-                          double* grad, double* lap, double* eloc, hipStream_t st) {
+                          const double* dlap, const double* vpot, const double* ee, int64_t W, int jet,
+                          double* logpsi, double* sign, double* grad, double* lap, double* eloc, hipStream_t st) {
   ProfScope ps("combine_kernel", st);
-  hipLaunchKernelGGL(combine_kernel<S>, dim3((unsigned)W), dim3(64), 0, st, s, c, ld, sg, g, dlap, vpot, jet, logpsi,
-                     sign, grad, lap, eloc);
+  hipLaunchKernelGGL(combine_kernel<S>, dim3((unsigned)W), dim3(64), 0, st, s, c, ld, sg, g, dlap, vpot, ee, jet,
+                     logpsi, sign, grad, lap, eloc);
   return hipGetLastError();
 }
 
@@ -1352,8 +1392,8 @@ hipError_t launch_accept(int64_t W, int N3, const double* rp, const double* lp_p
   template hipError_t launch_det<S>(const SysDev&, const S*, int64_t, int, double*, double*, double*, double*, \
                                     double*, hipStream_t);                                                             \
   template hipError_t launch_combine<S>(const SysDev&, const S*, const double*, const double*, const double*,    \
-                                        const double*, const double*, int64_t, int, double*, double*, double*,  \
-                                        double*, double*, hipStream_t);
+                                        const double*, const double*, const double*, int64_t, int, double*,     \
+                                        double*, double*, double*, double*, hipStream_t);
 QMC_INST(double)
 QMC_INST(float)
 

@@ -57,6 +57,7 @@ class Ansatz:
     n_det: int = 16          # determinants
     n_env: int = 8           # envelope exponents per nucleus and orbital
     include_vnn: int = 1     # add the constant nuclear repulsion to V
+    ee_cusp: float = 0.0     # length alpha of the fixed electron-electron cusp factor (0: none)
 
 
 @dataclasses.dataclass(frozen=True)

@@ -1,0 +1,91 @@
+"""Electron-electron cusp factor exp(gamma) (Sec. III.D) on the GPU against the FP64 oracle: H2 (all
+256 walkers), the N2 ansatz on a walker subset, a ragged molecule with same-spin pairs in both spin
+blocks; the helium-like closed form; value-mode log|psi| against the jet path; the loss gradient is
+unchanged (the factor has no parameters)."""
+import dataclasses
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import qmc_inputs as qi
+from tests.gpu_common import dev, host, rel_err
+from tests.test_gpu_parity import _compare_fp64, _run_le
+from tests.test_oracle_pins import SMALL, _one_center_params, _random_points
+
+pytestmark = pytest.mark.gpu
+
+
+def _q():
+    from paper_2307_14123_amd import qmc
+    return qmc
+
+
+def test_h2_fp64_with_cusp():
+    s, a, p, r = qi.workload_inputs(0)
+    _compare_fp64("h2 cusp fp64 256", s, dataclasses.replace(a, ee_cusp=1.0), p, r)
+
+
+def test_n2_subset_fp64_with_cusp():
+    s, a, p, r = qi.workload_inputs(1, 24)
+    _compare_fp64("n2 cusp fp64 24", s, dataclasses.replace(a, ee_cusp=0.5), p, r)
+
+
+def test_ragged_molecule_fp64_with_cusp():
+    s = qi.System((3.0, 1.0, 2.0), ((0.0, 0.0, 0.0), (1.6, 0.2, -0.3), (-0.5, 1.4, 0.9)), 4, 2)
+    a = qi.Ansatz(n_rbf=8, rbf_dmax=7.0, init_layers=2, width=40, mp_layers=2, n_det=3, n_env=3, ee_cusp=2.0)
+    p = qi.make_params(s, a, 41)
+    r = qi.make_walkers(s, 37, 42)
+    _compare_fp64("ragged cusp fp64 37", s, a, p, r)
+
+
+def test_n2_subset_fp32_with_cusp():
+    s, a, p, r = qi.workload_inputs(1, 24)
+    a = dataclasses.replace(a, ee_cusp=0.5)
+    ref = oracle.local_energy(r, p, s, a)
+    got = _run_le(s, a, p, r, "fp32")
+    scale = np.maximum.reduce([np.abs(ref["e_loc"]), 0.5 * np.abs(ref["lap"]),
+                               0.5 * (ref["grad"] ** 2).sum((1, 2)), np.ones_like(ref["e_loc"])])
+    e = np.abs(got["e_loc"] - ref["e_loc"]) / scale
+    print(f"[n2 cusp fp32] max rel E_L err {e.max():.3e}", flush=True)
+    assert e.max() < 2e-5
+    assert rel_err(got["logpsi"], ref["logpsi"]).max() < 2e-4
+
+
+@pytest.mark.parametrize("Z,alpha", [(2.0, 1.0), (3.0, 2.5)])
+def test_helium_like_closed_form_gpu(Z, alpha):
+    He = qi.System((Z,), ((0.0, 0.0, 0.0),), 1, 1)
+    a = dataclasses.replace(SMALL, ee_cusp=alpha)
+    p = _one_center_params(He, a, Z, np.random.default_rng(5))
+    r = _random_points(10, 2, 6)
+    got = _run_le(He, a, p, r, "fp64")
+    d = r[:, 0] - r[:, 1]
+    r12 = np.linalg.norm(d, axis=-1)
+    e12 = d / r12[:, None]
+    u1 = r[:, 0] / np.linalg.norm(r[:, 0], axis=-1)[:, None]
+    u2 = r[:, 1] / np.linalg.norm(r[:, 1], axis=-1)[:, None]
+    g1 = 0.5 * alpha ** 2 / (alpha + r12) ** 2
+    g2 = -alpha ** 2 / (alpha + r12) ** 3
+    exact = -Z ** 2 + 1 / r12 - g2 - 2 * g1 / r12 - g1 ** 2 + Z * g1 * ((u1 - u2) * e12).sum(-1)
+    np.testing.assert_allclose(got["e_loc"], exact, rtol=1e-10, atol=1e-10)
+
+
+def test_value_mode_and_loss_gradient_with_cusp():
+    s, a0, p, r = qi.workload_inputs(1, 32)
+    a = dataclasses.replace(a0, ee_cusp=0.5)
+    q = _q()
+    plan, plan0 = q.Plan([s], [32], a, "fp64"), q.Plan([s], [32], a0, "fp64")
+    P, R = dev(p), dev(r)
+    out = plan.local_energy(P, R)
+    lp, _ = plan.logpsi(P, R)
+    lp0, _ = plan0.logpsi(P, R)
+    torch.cuda.synchronize()
+    assert rel_err(host(lp), host(out["logpsi"])).max() < 1e-12
+    gam = oracle.ee_cusp(torch.as_tensor(r), s, 0.5).numpy()
+    assert np.abs(host(lp) - host(lp0) - gam).max() < 1e-10
+    g, em = plan.loss_grad(P, R, out["e_loc"])
+    g0, em0 = plan0.loss_grad(P, R, out["e_loc"])
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(host(g), host(g0))
+    np.testing.assert_array_equal(host(em), host(em0))

@@ -6,6 +6,7 @@ envelopes, the antisymmetry and equivariance requirements (Sec. II.A, II.C),
 invariances of a distance-only embedding, an independent numpy forward, and
 central finite differences of that numpy forward.
 """
+import dataclasses
 import math
 import os
 
@@ -117,6 +118,54 @@ def test_helium_like_product_state(Z):
     np.testing.assert_allclose(res["e_loc"], -Z ** 2 + 1 / r12, rtol=1e-12)
 
 
+@pytest.mark.parametrize("Z,alpha", [(2.0, 1.0), (2.0, 0.4), (3.0, 2.5)])
+def test_helium_like_product_state_with_ee_cusp(Z, alpha):
+    """1s^2 times exp(gamma(r12)), gamma = -alpha^2 / (2 (alpha + r12)): by hand,
+    E_L = -Z^2 + 1/r12 - gamma'' - 2 gamma'/r12 - gamma'^2 + Z gamma' (u1 - u2) . e12, with u the unit
+    vectors of the electrons and e12 that of r1 - r2."""
+    He = qi.System((Z,), ((0.0, 0.0, 0.0),), 1, 1)
+    a = dataclasses.replace(SMALL, ee_cusp=alpha)
+    p = _one_center_params(He, a, Z, np.random.default_rng(5))
+    r = _random_points(10, 2, 6)
+    res = oracle.local_energy(r, p, He, a)
+    d = r[:, 0] - r[:, 1]
+    r12 = np.linalg.norm(d, axis=-1)
+    e12 = d / r12[:, None]
+    u1 = r[:, 0] / np.linalg.norm(r[:, 0], axis=-1)[:, None]
+    u2 = r[:, 1] / np.linalg.norm(r[:, 1], axis=-1)[:, None]
+    g1 = 0.5 * alpha ** 2 / (alpha + r12) ** 2
+    g2 = -alpha ** 2 / (alpha + r12) ** 3
+    exact = -Z ** 2 + 1 / r12 - g2 - 2 * g1 / r12 - g1 ** 2 + Z * g1 * ((u1 - u2) * e12).sum(-1)
+    np.testing.assert_allclose(res["e_loc"], exact, rtol=1e-11, atol=1e-11)
+
+
+def test_ee_cusp_removes_the_coalescence_divergence():
+    """Kato: with the cusp factor the local energy of two opposite-spin electrons stays finite as
+    they meet (the kinetic -2 gamma'(0) / r12 cancels +1/r12); without it E_L grows as 1/r12.  The
+    slopes at coalescence are 1/4 (same spin) and 1/2 (opposite spin) for any alpha."""
+    He = qi.System((2.0,), ((0.0, 0.0, 0.0),), 1, 1)
+    mid = np.array([0.4, -0.3, 0.5])
+    axis = np.array([0.6, 0.0, 0.8])
+    for alpha in (0.5, 1.0, 3.0):
+        a = dataclasses.replace(SMALL, ee_cusp=alpha)
+        p = _one_center_params(He, a, 2.0, np.random.default_rng(8))
+        e = []
+        for eps in (1e-3, 1e-5, 1e-7):
+            r = np.stack([mid + 0.5 * eps * axis, mid - 0.5 * eps * axis])[None]
+            e.append(oracle.local_energy(r, p, He, a)["e_loc"][0])
+        assert abs(e[2] - e[1]) < 1e-3 and abs(e[1] - e[0]) < 1e-1
+        e_plain = oracle.local_energy(r, _one_center_params(He, SMALL, 2.0, np.random.default_rng(8)), He,
+                                      SMALL)["e_loc"][0]
+        assert e_plain > 1e6
+        for n_up, c in ((2, 0.25), (1, 0.5)):
+            s2 = qi.System((1.0,), ((0.0, 0.0, 0.0),), n_up, 2 - n_up)
+            for eps in (1e-6,):
+                x = torch.as_tensor(np.array([[mid, mid + eps * axis]]))
+                x0 = torch.as_tensor(np.array([[mid, mid]]))
+                slope = (oracle.ee_cusp(x, s2, alpha) - oracle.ee_cusp(x0, s2, alpha)).item() / eps
+                assert abs(slope - c) < 1e-5
+
+
 def _golden_hydrogenic():
     rows = []
     with open(os.path.join(GOLDEN, "hydrogenic_energies.txt")) as fh:
@@ -168,7 +217,16 @@ def _small_system():
     return qi.System((3.0, 1.0, 2.0), ((0.0, 0.0, 0.0), (1.6, 0.2, -0.3), (-0.5, 1.4, 0.9)), 3, 2)
 
 
+SMALL_CUSP = dataclasses.replace(SMALL, ee_cusp=0.7)
+
+
 def test_torch_and_numpy_forwards_agree():
+    s = _small_system()
+    p = qi.make_params(s, SMALL_CUSP, 13)
+    r = qi.make_walkers(s, 5, 14)
+    st, lt = oracle.logpsi(torch.as_tensor(r), torch.as_tensor(p), s, SMALL_CUSP)
+    sn, ln = oracle.logpsi_np(r, p, s, SMALL_CUSP)
+    np.testing.assert_allclose(lt.numpy(), ln, rtol=1e-12, atol=1e-12)
     for k in (0, 1):
         s, a, p, r = qi.workload_inputs(k, 6)
         st, lt = oracle.logpsi(torch.as_tensor(r), torch.as_tensor(p), s, a)
@@ -268,14 +326,15 @@ def _fd_grad_lap(r, p, s, a, h):
     return g, lap
 
 
-def test_gradient_and_laplacian_vs_finite_differences():
+@pytest.mark.parametrize("ans", [SMALL, SMALL_CUSP], ids=["plain", "ee_cusp"])
+def test_gradient_and_laplacian_vs_finite_differences(ans):
     s = _small_system()
-    p = qi.make_params(s, SMALL, 23)
+    p = qi.make_params(s, ans, 23)
     r = qi.make_walkers(s, 4, 24)
-    res = oracle.local_energy(r, p, s, SMALL)
+    res = oracle.local_energy(r, p, s, ans)
     h = 2e-3
-    g1, l1 = _fd_grad_lap(r, p, s, SMALL, h)
-    g2, l2 = _fd_grad_lap(r, p, s, SMALL, h / 2)
+    g1, l1 = _fd_grad_lap(r, p, s, ans, h)
+    g2, l2 = _fd_grad_lap(r, p, s, ans, h / 2)
     g = (4 * g2 - g1) / 3          # Richardson extrapolation of O(h^2) schemes
     lap = (4 * l2 - l1) / 3
     scale = np.abs(res["grad"]).max()
