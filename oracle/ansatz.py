@@ -88,9 +88,10 @@ def embedding(r, P, system, ans):
     return f, d_en
 
 
-def orbital_matrices(r, P, system, ans):
-    """A^{sigma,p} per spin: list of [B, n_det, n_sigma, n_sigma] tensors."""
-    f, d_en = embedding(r, P, system, ans)
+def orbital_matrices(r, P, system, ans, emb=None):
+    """A^{sigma,p} per spin: list of [B, n_det, n_sigma, n_sigma] tensors (emb: the embedding's
+    output when already computed)."""
+    f, d_en = embedding(r, P, system, ans) if emb is None else emb
     B = r.shape[0]
     out = []
     start = 0
@@ -139,11 +140,21 @@ def ee_cusp(r, system, alpha):
     return (-c * alpha * alpha / (alpha + d)).sum(-1)
 
 
+def jastrow(f, P):
+    """Learnable Jastrow exponent (Sec. III.D, learnable-Jastrow equation): J = eta(sum_i f_i) with
+    eta read as a two-layer MLP, tanh(x W1 + b1) W2 + b2 (one hidden layer of the embedding width,
+    scalar output).  Summing over electrons makes J symmetric under every permutation."""
+    x = f.sum(1)                                                     # [B, D]
+    return (torch.tanh(x @ P["jas.W1"] + P["jas.b1"]) @ P["jas.W2"] + P["jas.b2"])[:, 0]
+
+
 def logpsi(r, params, system, ans):
     """(sign, log|psi|) for walkers r [B, N, 3] (torch float64); with ans.ee_cusp = alpha > 0 the
-    fixed electron-electron cusp factor (ee_cusp) multiplies psi."""
+    fixed electron-electron cusp factor (ee_cusp) multiplies psi, and with ans.jastrow = 1 the
+    learnable factor exp(J) (jastrow)."""
     P = unpack(params, system, ans)
-    mats = orbital_matrices(r, P, system, ans)
+    emb = embedding(r, P, system, ans)
+    mats = orbital_matrices(r, P, system, ans, emb)
     B = r.shape[0]
     logdet = torch.zeros(B, ans.n_det, dtype=torch.float64)
     sign = torch.ones(B, ans.n_det, dtype=torch.float64)
@@ -157,4 +168,6 @@ def logpsi(r, params, system, ans):
     alpha = float(getattr(ans, "ee_cusp", 0.0))
     if alpha > 0 and r.shape[1] > 1:
         lp = lp + ee_cusp(r, system, alpha)
+    if getattr(ans, "jastrow", 0):
+        lp = lp + jastrow(emb[0], P)
     return sg, lp

@@ -43,6 +43,12 @@ def param_shapes(system, ans):
             shapes[f"orb.{s}.pi"] = (ans.n_det, n, M, ans.n_env)
             shapes[f"orb.{s}.sigma"] = (ans.n_det, n, M, ans.n_env)
     shapes["c"] = (ans.n_det,)
+    if getattr(ans, "jastrow", 0):
+        D = ans.width
+        shapes["jas.W1"] = (D, D)
+        shapes["jas.b1"] = (D,)
+        shapes["jas.W2"] = (D, 1)
+        shapes["jas.b2"] = (1,)
     return shapes
 
 

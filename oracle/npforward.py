@@ -7,7 +7,7 @@ torch forward: radial basis and node initialisation (Sec. III.A), graph
 convolution with mean normalisation and concatenation update (Sec. III.A),
 orbitals times isotropic envelopes (Sec. III.B), spin-factorised determinants
 (Sec. III.C), log-sum-exp over determinants (Sec. III.E), optional fixed
-electron-electron cusp factor (Sec. III.D).
+electron-electron cusp factor and learnable Jastrow factor (Sec. III.D).
 """
 from __future__ import annotations
 
@@ -111,6 +111,10 @@ def logpsi_np(r, params, system, ans):
     S = np.sum(c[None, :] * sign * np.exp(logdet - mx[:, None]), axis=1)
     alpha = float(getattr(ans, "ee_cusp", 0.0))
     gamma = np.zeros(W)
+    if getattr(ans, "jastrow", 0):
+        # learnable Jastrow exponent eta(sum_i f_i) (Sec. III.D)
+        fsum = sum(f)
+        gamma += (np.tanh(fsum @ P["jas.W1"] + P["jas.b1"]) @ P["jas.W2"])[:, 0] + P["jas.b2"][0]
     if alpha > 0:
         # fixed electron-electron cusp factor exp(gamma) (Sec. III.D), pair by pair
         for i in range(N):

@@ -58,6 +58,7 @@ class Ansatz:
     n_env: int = 8           # envelope exponents per nucleus and orbital
     include_vnn: int = 1     # add the constant nuclear repulsion to V
     ee_cusp: float = 0.0     # length alpha of the fixed electron-electron cusp factor (0: none)
+    jastrow: int = 0         # 1: learnable Jastrow factor exp(J), J an MLP of the summed embeddings
 
 
 @dataclasses.dataclass(frozen=True)
@@ -106,6 +107,11 @@ def param_table(system: System, ans: Ansatz) -> List[Tuple[str, Tuple[int, ...],
         out.append((f"orb.{s}.pi", (P, n, M, ans.n_env), "one", 0))
         out.append((f"orb.{s}.sigma", (P, n, M, ans.n_env), "sigma", 0))
     out.append(("c", (ans.n_det,), "one", 0))
+    if ans.jastrow:
+        out.append(("jas.W1", (D, D), "w", D))
+        out.append(("jas.b1", (D,), "zero", 0))
+        out.append(("jas.W2", (D, 1), "w", D))
+        out.append(("jas.b2", (1,), "zero", 0))
     return out
 
 

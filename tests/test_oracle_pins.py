@@ -166,6 +166,25 @@ def test_ee_cusp_removes_the_coalescence_divergence():
                 assert abs(slope - c) < 1e-5
 
 
+def test_constant_jastrow_shifts_log_psi_only():
+    """With W1 = 0 the Jastrow exponent is the constant tanh(b1) W2 + b2: log|psi| shifts by it and
+    the local energy, gradient and Laplacian do not change."""
+    s = _small_system()
+    p = qi.make_params(s, SMALL_JAS, 31)
+    P = unpack(p, s, SMALL_JAS)
+    P["jas.W1"][:] = 0.0
+    P["jas.b1"][:] = np.linspace(-1, 1, SMALL_JAS.width)
+    P["jas.b2"][:] = 0.3
+    shift = float(np.tanh(P["jas.b1"]) @ P["jas.W2"][:, 0] + 0.3)
+    p0 = p[:oracle.param_count(s, SMALL_CUSP)]
+    r = qi.make_walkers(s, 4, 32)
+    a = oracle.local_energy(r, p, s, SMALL_JAS)
+    b = oracle.local_energy(r, p0, s, SMALL_CUSP)
+    np.testing.assert_allclose(a["logpsi"] - b["logpsi"], shift, rtol=0, atol=1e-12)
+    np.testing.assert_allclose(a["e_loc"], b["e_loc"], rtol=1e-12, atol=1e-10)
+    np.testing.assert_allclose(a["grad"], b["grad"], rtol=1e-12, atol=1e-12)
+
+
 def _golden_hydrogenic():
     rows = []
     with open(os.path.join(GOLDEN, "hydrogenic_energies.txt")) as fh:
@@ -218,15 +237,18 @@ def _small_system():
 
 
 SMALL_CUSP = dataclasses.replace(SMALL, ee_cusp=0.7)
+SMALL_JAS = dataclasses.replace(SMALL, ee_cusp=0.7, jastrow=1)
 
 
 def test_torch_and_numpy_forwards_agree():
     s = _small_system()
-    p = qi.make_params(s, SMALL_CUSP, 13)
-    r = qi.make_walkers(s, 5, 14)
-    st, lt = oracle.logpsi(torch.as_tensor(r), torch.as_tensor(p), s, SMALL_CUSP)
-    sn, ln = oracle.logpsi_np(r, p, s, SMALL_CUSP)
-    np.testing.assert_allclose(lt.numpy(), ln, rtol=1e-12, atol=1e-12)
+    for ans in (SMALL_CUSP, SMALL_JAS):
+        p = qi.make_params(s, ans, 13)
+        r = qi.make_walkers(s, 5, 14)
+        st, lt = oracle.logpsi(torch.as_tensor(r), torch.as_tensor(p), s, ans)
+        sn, ln = oracle.logpsi_np(r, p, s, ans)
+        np.testing.assert_allclose(lt.numpy(), ln, rtol=1e-12, atol=1e-12)
+        assert np.all(st.numpy() == sn)
     for k in (0, 1):
         s, a, p, r = qi.workload_inputs(k, 6)
         st, lt = oracle.logpsi(torch.as_tensor(r), torch.as_tensor(p), s, a)
@@ -276,15 +298,16 @@ def test_cancelling_determinants_give_zero_psi():
     assert np.all(np.isnan(res["e_loc"]))
 
 
-def test_same_spin_exchange_antisymmetry():
+@pytest.mark.parametrize("ans", [SMALL, SMALL_JAS], ids=["plain", "cusp_jastrow"])
+def test_same_spin_exchange_antisymmetry(ans):
     s = _small_system()
-    p = qi.make_params(s, SMALL, 17)
+    p = qi.make_params(s, ans, 17)
     r = qi.make_walkers(s, 5, 18)
-    base = oracle.local_energy(r, p, s, SMALL)
+    base = oracle.local_energy(r, p, s, ans)
     for (i, j) in ((0, 2), (3, 4)):
         rs = r.copy()
         rs[:, [i, j]] = rs[:, [j, i]]
-        sw = oracle.local_energy(rs, p, s, SMALL)
+        sw = oracle.local_energy(rs, p, s, ans)
         assert np.all(sw["sign"] == -base["sign"])
         np.testing.assert_allclose(sw["logpsi"], base["logpsi"], rtol=1e-13, atol=1e-13)
         np.testing.assert_allclose(sw["e_loc"], base["e_loc"], rtol=1e-11, atol=1e-11)
@@ -326,7 +349,7 @@ def _fd_grad_lap(r, p, s, a, h):
     return g, lap
 
 
-@pytest.mark.parametrize("ans", [SMALL, SMALL_CUSP], ids=["plain", "ee_cusp"])
+@pytest.mark.parametrize("ans", [SMALL, SMALL_CUSP, SMALL_JAS], ids=["plain", "ee_cusp", "jastrow"])
 def test_gradient_and_laplacian_vs_finite_differences(ans):
     s = _small_system()
     p = qi.make_params(s, ans, 23)
@@ -342,23 +365,27 @@ def test_gradient_and_laplacian_vs_finite_differences(ans):
     np.testing.assert_allclose(lap, res["lap"], rtol=2e-6, atol=2e-6 * np.abs(res["lap"]).max())
 
 
-def test_loss_gradient_vs_finite_differences_of_surrogate():
+@pytest.mark.parametrize("ans", [SMALL, SMALL_JAS], ids=["plain", "jastrow"])
+def test_loss_gradient_vs_finite_differences_of_surrogate(ans):
     """FD (h = 1e-5, float64) of S(theta) = sum_w g_w log|psi_w(theta)| with the
-    weights frozen, on sampled parameters, against the autograd estimator."""
+    weights frozen, on sampled parameters (with the Jastrow: the last 64 too), against the autograd
+    estimator."""
     s = _small_system()
-    p = qi.make_params(s, SMALL, 25)
+    p = qi.make_params(s, ans, 25)
     r = qi.make_walkers(s, 6, 26)
-    e = oracle.local_energy(r, p, s, SMALL)["e_loc"]
-    G, e_mean, nf = oracle.loss_grad(r, e, p, s, SMALL)
+    e = oracle.local_energy(r, p, s, ans)["e_loc"]
+    G, e_mean, nf = oracle.loss_grad(r, e, p, s, ans)
     assert nf == 6 and abs(e_mean - e.mean()) < 1e-14 * abs(e_mean) + 1e-14
     wts = 2 * (e - e.mean()) / len(e)
     idx = np.random.default_rng(27).choice(len(p), 64, replace=False)
+    if ans.jastrow:
+        idx = np.concatenate([idx, np.arange(len(p) - 64, len(p))])
     h = 1e-5
     for k in idx:
         pp = p.copy(); pp[k] += h
         pm = p.copy(); pm[k] -= h
-        fd = (np.sum(wts * oracle.logpsi_np(r, pp, s, SMALL)[1]) -
-              np.sum(wts * oracle.logpsi_np(r, pm, s, SMALL)[1])) / (2 * h)
+        fd = (np.sum(wts * oracle.logpsi_np(r, pp, s, ans)[1]) -
+              np.sum(wts * oracle.logpsi_np(r, pm, s, ans)[1])) / (2 * h)
         assert abs(fd - G[k]) < 1e-7 * max(1.0, np.abs(G).max())
 
 
