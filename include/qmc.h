@@ -80,7 +80,11 @@ typedef struct qmc_system {
  *                     c_ij = 1/4 (same spin) or 1/2 (opposite spin), whose
  *                     slope at r_ij = 0 is c_ij for every alpha; 0 = none.
  *                     It has no parameters: gradients of log|psi| with respect
- *                     to the blob do not change. */
+ *                     to the blob do not change.
+ *   jastrow         : 1 multiplies psi by the learnable Jastrow factor exp(J)
+ *                     of Sec. III.D, J = tanh(s W1 + b1) W2 + b2 with
+ *                     s = sum_i f_i the sum of the final electron embeddings
+ *                     (an MLP of one hidden layer of width D); 0 = none. */
 typedef struct qmc_ansatz {
   int32_t version;
   int32_t n_rbf;
@@ -92,6 +96,7 @@ typedef struct qmc_ansatz {
   int32_t n_env;
   int32_t include_vnn;
   double ee_cusp;
+  int32_t jastrow;
 } qmc_ansatz;
 
 typedef enum qmc_precision {
@@ -131,7 +136,8 @@ typedef struct qmc_plan qmc_plan;
  *     U2[D][D] a2[D]; then Wh[D][D] bh[D] Y[M][D] Wg[3D][D] bg[D];
  *   per spin with n_sigma > 0: Worb[D][n_det*n_sigma] borb[n_det*n_sigma]
  *     pi[n_det][n_sigma][M][n_env] sigma[n_det][n_sigma][M][n_env];
- *   c[n_det]. */
+ *   c[n_det]; then, with jastrow = 1: jas.W1[D][D] jas.b1[D] jas.W2[D][1]
+ *   jas.b2[1]. */
 int64_t qmc_param_count(const qmc_system* system, const qmc_ansatz* ansatz);
 
 /* Plan flags.

@@ -203,6 +203,15 @@ static qmc_status forward_chunk(const Plan& P, const SysPlan& s, const S* prm, c
       CK(gemm(s, gk, g, st));
     }
   }
+  // learnable Jastrow exponent J = tanh(s W1 + b1) W2 + b2 of the summed embeddings s = sum_i f_i,
+  // with jets (the sum of the electrons' jet rows is the jet of s); h and m are free here
+  S* jas = nullptr;
+  if (P.ans.jastrow) {
+    jas = (S*)(ws + L.jas);
+    CK(launch_sum_electrons<S>(wc, (int)N, Rp, (int)D, f, h, st));
+    CK(gemm(s, gk, dense(h, D, prm + O.jW1, D, prm + O.jb1, m, D, wc * Rp, (int)D, (int)D, Rp, s.T, 1, vm), st));
+    CK(launch_jastrow_out<S>(wc * Rp, Rp, (int)D, m, prm + O.jW2, prm + O.jb2, jas, st));
+  }
   int64_t off_e = 0;
   for (int sp = 0; sp < 2; ++sp) {
     const int64_t n = s.nsig(sp);
@@ -216,7 +225,7 @@ static qmc_status forward_chunk(const Plan& P, const SysPlan& s, const S* prm, c
     off_e += n;
   }
   CK(launch_det<S>(dv, ajet, wc, jet, dld, dsg, dg, dlap, nullptr, st));
-  CK(launch_combine<S>(dv, prm + O.c, dld, dsg, dg, dlap, vpot, ee, wc, jet, out.logpsi, out.sign, out.grad, out.lap,
+  CK(launch_combine<S>(dv, prm + O.c, dld, dsg, dg, dlap, vpot, ee, jas, wc, jet, out.logpsi, out.sign, out.grad, out.lap,
                        out.eloc, st));
   return QMC_OK;
 }
@@ -423,6 +432,11 @@ static qmc_status forward_stash(const Plan& P, const SysPlan& s, const S* prm, c
     CK(launch_add<S>(rows * D, fprev, t, fo, st));
     fprev = fo;
   }
+  if (P.ans.jastrow) {
+    CK(launch_sum_electrons<S>(wc, (int)N, 1, (int)D, fprev, (S*)(ws + B.jsum), st));
+    CK(gemm(s, gk, dense((S*)(ws + B.jsum), D, prm + O.jW1, D, prm + O.jb1, (S*)(ws + B.jhid), D, wc, (int)D, (int)D,
+                         1, 0, 1, 1), st));
+  }
   int64_t off_e = 0;
   for (int sp = 0; sp < 2; ++sp) {
     const int64_t n = s.nsig(sp);
@@ -458,6 +472,21 @@ static qmc_status backward_chunk(const Plan& P, const SysPlan& s, const S* prm, 
   double* cpart = (double*)(ws + B.cpart);
   CK(launch_combine_bwd<S>(dv, prm + O.c, (double*)(ws + B.dld), (double*)(ws + B.dsg), gbar, wc, lbar, cpart, st));
   CK(launch_rowsum(cpart, wc, ND, ND, gacc + O.c, (double*)(ws + B.wpart), B.wpart_elems, st));
+  // Jastrow exponent: its cotangent is gbar itself (log|psi| = determinant part + J)
+  S* jfs = nullptr;
+  if (P.ans.jastrow) {
+    S* jhid = (S*)(ws + B.jhid);
+    S* jzb = (S*)(ws + B.jzb);
+    S* jgo = (S*)(ws + B.jgo);
+    jfs = (S*)(ws + B.jfs);
+    CK(launch_jastrow_bwd<S>(wc, (int)D, gbar, prm + O.jW2, jhid, jzb, jgo, st));
+    CK(launch_wgrad(bk, wg(jhid, D, jgo, 1, wc, (int)D, 1, B, ws), gacc + O.jW2, 1, gacc + O.jb2, st));
+    CK(launch_wgrad(bk, wg((S*)(ws + B.jsum), D, jzb, D, wc, (int)D, (int)D, B, ws), gacc + O.jW1, D, gacc + O.jb1,
+                    st));
+    GemmArgs gj = dense(jzb, D, prm + O.jW1, D, nullptr, jfs, D, wc, (int)D, (int)D, 1, 0, 0, 1);
+    gj.transw = 1;
+    CK(gemm(s, bk, gj, st));
+  }
   S* fL = L > 0 ? F_(B.fst, B.blk_f, L - 1) : F_(B.finit, B.blk_f, L0 - 1);
   S* fbar = (S*)(ws + B.fbar);
   S* fbar2 = (S*)(ws + B.fbar2);
@@ -488,6 +517,8 @@ static qmc_status backward_chunk(const Plan& P, const SysPlan& s, const S* prm, 
     CK(gemm(s, bk, g, st));
     off_e += n;
   }
+  // the summed embedding's cotangent reaches every electron
+  if (jfs) CK(launch_add_bcast<S>(wc, (int)N, (int)D, jfs, fbar, st));
   S* zbar = (S*)(ws + B.zbar);
   S* hbar = (S*)(ws + B.hbar);
   S* mbar = (S*)(ws + B.mbar);

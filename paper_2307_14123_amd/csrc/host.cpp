@@ -54,6 +54,13 @@ bool compute_offsets(const qmc_system& s, const qmc_ansatz& a, ParamOffsets* off
     off->sigma[sp] = take(cur, a.n_det * n * M * a.n_env);
   }
   off->c = take(cur, a.n_det);
+  off->jW1 = off->jb1 = off->jW2 = off->jb2 = -1;
+  if (a.jastrow) {
+    off->jW1 = take(cur, D * D);
+    off->jb1 = take(cur, D);
+    off->jW2 = take(cur, D);
+    off->jb2 = take(cur, 1);
+  }
   off->total = cur;
   return true;
 }
@@ -102,6 +109,7 @@ Workspace workspace_layout(const Plan& p, const SysPlan& s, int op, int64_t wc) 
   if (op == QMC_OP_METROPOLIS) {
     w.lp_prop = alloc(size_t(wc) * (N * 3 + 1) * 8);  // proposal [wc][N][3], then its log|psi| [wc]
   }
+  w.jas = alloc(p.ans.jastrow ? size_t(wc) * Rp * E : 0);
   if (op == QMC_OP_MALA) {
     w.lp_prop = alloc(size_t(wc) * (2 * N * 3 + 1) * 8);  // proposal, its gradient (both [wc][N][3]), log|psi|
   }
@@ -178,6 +186,12 @@ BwdWorkspace bwd_layout(const Plan& p, const SysPlan& s, int64_t wc) {
   }
   b.wpart = alloc(size_t(b.wpart_elems) * 8);
   b.gacc = alloc(size_t(s.off.total) * 8);
+  const size_t jb = p.ans.jastrow ? size_t(wc) * D * E : 0;
+  b.jsum = alloc(jb);
+  b.jhid = alloc(jb);
+  b.jzb = alloc(jb);
+  b.jfs = alloc(jb);
+  b.jgo = alloc(p.ans.jastrow ? size_t(wc) * E : 0);
   b.total = cur;
   return b;
 }
@@ -225,6 +239,7 @@ static bool valid_ansatz(const qmc_ansatz* a) {
   if (a->n_det < 1 || a->n_det > 64 || a->n_env < 1 || a->n_env > 32) return false;
   if (a->include_vnn != 0 && a->include_vnn != 1) return false;
   if (!std::isfinite(a->ee_cusp) || a->ee_cusp < 0) return false;
+  if (a->jastrow != 0 && a->jastrow != 1) return false;
   return true;
 }
 

@@ -127,9 +127,22 @@ hipError_t launch_det_generic(int64_t nmat, int n, int ntan, const double* jets,
 
 template <typename S>
 hipError_t launch_combine(const SysDev& s, const S* c, const double* ld, const double* sg,
-                          const double* g, const double* dlap, const double* vpot, const double* ee, int64_t W,
-                          int jet, double* logpsi, double* sign, double* grad, double* lap, double* eloc,
+                          const double* g, const double* dlap, const double* vpot, const double* ee, const S* jas,
+                          int64_t W, int jet, double* logpsi, double* sign, double* grad, double* lap, double* eloc,
                           hipStream_t st);
+// Learnable Jastrow factor: out[w][q][d] = sum_i f[w][i][q][d] (R rows per electron); the scalar
+// output layer out[row] = x[row] . W2 (+ b2 on value rows, every R-th row); in the backward
+// go[w] = gbar[w], zb[w][d] = gbar[w] W2[d] (1 - h[w][d]^2); and fbar[w][i][d] += fs[w][d].
+template <typename S>
+hipError_t launch_sum_electrons(int64_t W, int N, int R, int D, const S* f, S* out, hipStream_t st);
+template <typename S>
+hipError_t launch_jastrow_out(int64_t rows, int R, int D, const S* x, const S* W2, const S* b2, S* out,
+                              hipStream_t st);
+template <typename S>
+hipError_t launch_jastrow_bwd(int64_t W, int D, const double* gbar, const S* W2, const S* h, S* zb, S* go,
+                              hipStream_t st);
+template <typename S>
+hipError_t launch_add_bcast(int64_t W, int N, int D, const S* fs, S* fbar, hipStream_t st);
 
 hipError_t launch_propose(const double* r, const double* noise, double step, int64_t n, double* rp,
                           hipStream_t st);

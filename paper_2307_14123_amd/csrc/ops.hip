@@ -1116,8 +1116,9 @@ template <typename S>
 __global__ __launch_bounds__(64) void combine_kernel(SysDev s, const S* __restrict__ c, const double* __restrict__ ld,
                                                      const double* __restrict__ sg, const double* __restrict__ g,
                                                      const double* __restrict__ dlap, const double* __restrict__ vpot,
-                                                     const double* __restrict__ ee, int jet,
-                                                     double* __restrict__ logpsi, double* __restrict__ sign,
+                                                     const double* __restrict__ ee, const S* __restrict__ jas,
+                                                     int jet, double* __restrict__ logpsi,
+                                                     double* __restrict__ sign,
                                                      double* __restrict__ grad, double* __restrict__ lap,
                                                      double* __restrict__ eloc) {
   const int64_t w = blockIdx.x;
@@ -1163,6 +1164,12 @@ __global__ __launch_bounds__(64) void combine_kernel(SysDev s, const S* __restri
     gam = wave_sum(gam);
     glap = wave_sum(glap);
   }
+  // learnable Jastrow exponent: jet rows [Rp] per walker (value rows: one)
+  const S* jw = jas ? jas + w * (int64_t)(jet ? s.Rp : 1) : nullptr;
+  if (jw) {
+    gam += (double)jw[0];
+    if (jet) glap += (double)jw[s.T + 1];
+  }
   const double lp = mx + log(fabs(S_)) + gam;
   if (lane == 0) {
     if (logpsi) logpsi[w] = lp;
@@ -1188,16 +1195,18 @@ __global__ __launch_bounds__(64) void combine_kernel(SysDev s, const S* __restri
     }
     Apart += a2;
     Bpart += gc * gc;
-    if (cusp) {
-      // d gamma / d x_cc: the pairs of electron i = cc / 3, coordinate cc % 3
-      const int i = cc / 3, a = cc - 3 * (cc / 3);
-      double dg = 0.0;
-      for (int j = 0; j < N; ++j) {
-        if (j == i) continue;
-        const double* pij = eew + 4 * (i * N + j);
-        const double cij = ((i < s.nup) == (j < s.nup)) ? 0.25 : 0.5;
-        const double q = 1.0 / (s.ee_cusp + pij[0]);
-        dg += cij * ca2 * q * q * pij[1 + a];
+    if (cusp || jw) {
+      // d gamma / d x_cc: the pairs of electron i = cc / 3, coordinate cc % 3, and the Jastrow row
+      double dg = jw ? (double)jw[1 + cc] : 0.0;
+      if (cusp) {
+        const int i = cc / 3, a = cc - 3 * (cc / 3);
+        for (int j = 0; j < N; ++j) {
+          if (j == i) continue;
+          const double* pij = eew + 4 * (i * N + j);
+          const double cij = ((i < s.nup) == (j < s.nup)) ? 0.25 : 0.5;
+          const double q = 1.0 / (s.ee_cusp + pij[0]);
+          dg += cij * ca2 * q * q * pij[1 + a];
+        }
       }
       Cpart += 2.0 * gc * dg + dg * dg;
       gc += dg;
@@ -1226,11 +1235,109 @@ __global__ __launch_bounds__(64) void combine_kernel(SysDev s, const S* __restri
 
 template <typename S>
 hipError_t launch_combine(const SysDev& s, const S* c, const double* ld, const double* sg, const double* g,
-                          const double* dlap, const double* vpot, const double* ee, int64_t W, int jet,
+                          const double* dlap, const double* vpot, const double* ee, const S* jas, int64_t W, int jet,
                           double* logpsi, double* sign, double* grad, double* lap, double* eloc, hipStream_t st) {
   ProfScope ps("combine_kernel", st);
-  hipLaunchKernelGGL(combine_kernel<S>, dim3((unsigned)W), dim3(64), 0, st, s, c, ld, sg, g, dlap, vpot, ee, jet,
-                     logpsi, sign, grad, lap, eloc);
+  hipLaunchKernelGGL(combine_kernel<S>, dim3((unsigned)W), dim3(64), 0, st, s, c, ld, sg, g, dlap, vpot, ee, jas,
+                     jet, logpsi, sign, grad, lap, eloc);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- learnable Jastrow factor
+
+template <typename S>
+__global__ void sum_electrons_kernel(int64_t W, int N, int R, int D, const S* __restrict__ f, S* __restrict__ out) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t per = (int64_t)R * D;
+  if (t >= W * per) return;
+  const int64_t w = t / per, qd = t - w * per;
+  const S* src = f + w * N * per + qd;
+  S acc = 0;
+  for (int i = 0; i < N; ++i) acc += src[i * per];
+  out[t] = acc;
+}
+
+// one wavefront per row: lanes stride the D columns, then a butterfly sum
+template <typename S>
+__global__ __launch_bounds__(256) void jastrow_out_kernel(int64_t rows, int R, int D, const S* __restrict__ x,
+                                                          const S* __restrict__ W2, const S* __restrict__ b2,
+                                                          S* __restrict__ out) {
+  const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (row >= rows) return;
+  const S* xr = x + row * D;
+  float acc32 = 0.0f;
+  double acc64 = 0.0;
+  for (int d = lane; d < D; d += 64) {
+    if constexpr (sizeof(S) == 8)
+      acc64 += (double)xr[d] * (double)W2[d];
+    else
+      acc32 += (float)xr[d] * (float)W2[d];
+  }
+  double v = sizeof(S) == 8 ? acc64 : (double)acc32;
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  if (lane == 0) out[row] = (S)(v + (row % R == 0 ? (double)b2[0] : 0.0));
+}
+
+template <typename S>
+__global__ void jastrow_bwd_kernel(int64_t W, int D, const double* __restrict__ gbar, const S* __restrict__ W2,
+                                   const S* __restrict__ h, S* __restrict__ zb, S* __restrict__ go) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= W * D) return;
+  const int64_t w = t / D;
+  const int d = (int)(t - w * D);
+  const double g = gbar[w];
+  const double hv = (double)h[t];
+  zb[t] = (S)(g * (double)W2[d] * (1.0 - hv * hv));
+  if (d == 0) go[w] = (S)g;
+}
+
+template <typename S>
+__global__ void add_bcast_kernel(int64_t W, int N, int D, const S* __restrict__ fs, S* __restrict__ fbar) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= W * N * D) return;
+  const int64_t w = t / ((int64_t)N * D);
+  const int d = (int)(t % D);
+  fbar[t] += fs[w * D + d];
+}
+
+template <typename S>
+hipError_t launch_sum_electrons(int64_t W, int N, int R, int D, const S* f, S* out, hipStream_t st) {
+  const int64_t n = W * R * D;
+  if (n == 0) return hipSuccess;
+  ProfScope ps("jastrow_sum_kernel", st);
+  hipLaunchKernelGGL(sum_electrons_kernel<S>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, W, N, R, D, f,
+                     out);
+  return hipGetLastError();
+}
+
+template <typename S>
+hipError_t launch_jastrow_out(int64_t rows, int R, int D, const S* x, const S* W2, const S* b2, S* out,
+                              hipStream_t st) {
+  if (rows == 0) return hipSuccess;
+  ProfScope ps("jastrow_out_kernel", st);
+  hipLaunchKernelGGL(jastrow_out_kernel<S>, dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, st, rows, R, D, x, W2,
+                     b2, out);
+  return hipGetLastError();
+}
+
+template <typename S>
+hipError_t launch_jastrow_bwd(int64_t W, int D, const double* gbar, const S* W2, const S* h, S* zb, S* go,
+                              hipStream_t st) {
+  const int64_t n = W * D;
+  if (n == 0) return hipSuccess;
+  ProfScope ps("jastrow_bwd_kernel", st);
+  hipLaunchKernelGGL(jastrow_bwd_kernel<S>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, W, D, gbar, W2, h,
+                     zb, go);
+  return hipGetLastError();
+}
+
+template <typename S>
+hipError_t launch_add_bcast(int64_t W, int N, int D, const S* fs, S* fbar, hipStream_t st) {
+  const int64_t n = W * N * D;
+  if (n == 0) return hipSuccess;
+  ProfScope ps("jastrow_bcast_kernel", st);
+  hipLaunchKernelGGL(add_bcast_kernel<S>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, W, N, D, fs, fbar);
   return hipGetLastError();
 }
 
@@ -1392,8 +1499,13 @@ hipError_t launch_accept(int64_t W, int N3, const double* rp, const double* lp_p
   template hipError_t launch_det<S>(const SysDev&, const S*, int64_t, int, double*, double*, double*, double*, \
                                     double*, hipStream_t);                                                             \
   template hipError_t launch_combine<S>(const SysDev&, const S*, const double*, const double*, const double*,    \
-                                        const double*, const double*, const double*, int64_t, int, double*,     \
-                                        double*, double*, double*, double*, hipStream_t);
+                                        const double*, const double*, const double*, const S*, int64_t, int,    \
+                                        double*, double*, double*, double*, double*, hipStream_t);              \
+  template hipError_t launch_sum_electrons<S>(int64_t, int, int, int, const S*, S*, hipStream_t);               \
+  template hipError_t launch_jastrow_out<S>(int64_t, int, int, const S*, const S*, const S*, S*, hipStream_t);  \
+  template hipError_t launch_jastrow_bwd<S>(int64_t, int, const double*, const S*, const S*, S*, S*,            \
+                                            hipStream_t);                                                        \
+  template hipError_t launch_add_bcast<S>(int64_t, int, int, const S*, S*, hipStream_t);
 QMC_INST(double)
 QMC_INST(float)
 

@@ -19,6 +19,7 @@ struct ParamOffsets {
   std::vector<Layer> mp;
   int64_t orbW[2], orbb[2], pi[2], sigma[2];  // -1 when that spin block is empty
   int64_t c;
+  int64_t jW1, jb1, jW2, jb2;  // learnable Jastrow MLP, -1 without it
   int64_t total;
 };
 
@@ -66,6 +67,7 @@ struct Workspace {
   size_t phi[2], ajet;
   size_t dld, dsg, dg, dlap;
   size_t lp_prop;
+  size_t jas;  // Jastrow exponent jets [wc][Rp] (value rows: [wc])
   size_t total;
 };
 
@@ -79,6 +81,7 @@ struct BwdWorkspace {
   // cotangents
   size_t gbar, stats, lbar, cpart, phibar[2], pipart, sgpart, fbar, fbar2, zbar, hbar, mbar, wbar[3], ebar, ypart;
   size_t wpart, gacc;
+  size_t jsum, jhid, jzb, jfs, jgo;  // Jastrow: summed embeddings, hidden layer, their cotangents, J cotangent
   int64_t wpart_elems;
   int64_t rows_per_split;
   int max_split;
