@@ -167,6 +167,8 @@ def main():
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64", "bf16"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-walkers", type=int, default=96)
+    ap.add_argument("--jastrow", action="store_true", help="add the learnable Jastrow factor to the ansatz")
+    ap.add_argument("--ee-cusp", type=float, default=0.0, help="alpha of the electron-electron cusp factor (0: none)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="end with a plain 256 MiB device copy, the reference for traffic counters")
     args = ap.parse_args()
@@ -186,6 +188,9 @@ def main():
     k = {"n2": 1, "c4h4": 3, "h2": 0}[args.workload]
     wl = qi.workload(k)
     s, a = wl.systems[0], wl.ansatz
+    if args.jastrow or args.ee_cusp > 0:
+        import dataclasses
+        a = dataclasses.replace(a, jastrow=int(args.jastrow), ee_cusp=float(args.ee_cusp))
     W = args.walkers or wl.walkers
     n_mc, tau = 10, 0.2
     params = qi.make_params(s, a, qi.seed(k, 0))
@@ -407,7 +412,10 @@ def main():
                                 "c4h4": "C4H4-sized: 4 C + 4 H, 14 up + 14 down",
                                 "h2": "H2: 2 x Z=1 at 1.4 bohr, 1 up + 1 down"}[args.workload] + f", {W} walkers, "
                                f"{a.mp_layers} message-passing layers width {a.width}, {a.n_det} dets, "
-                               f"{a.n_env} envelope exponents; step = {n_mc} Metropolis steps (tau {tau}) + "
+                               f"{a.n_env} envelope exponents"
+                               + (", learnable Jastrow" if a.jastrow else "")
+                               + (f", e-e cusp factor alpha {a.ee_cusp}" if a.ee_cusp > 0 else "")
+                               + f"; step = {n_mc} Metropolis steps (tau {tau}) + "
                                f"local energy" + (" + loss gradient + gradient-descent update (lr 1e-8)"
                                                   if has_grad else ""),
                    "walkers": W, "electrons": s.n_elec, "precision": args.precision,
