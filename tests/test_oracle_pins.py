@@ -582,3 +582,62 @@ def test_mala_hydrogen_mean_radius(damp):
     mean = per_walker.mean()
     err = per_walker.std(ddof=1) / math.sqrt(W)
     assert abs(mean - 1.5) < 4 * err
+
+
+def _golden_clipping():
+    rows = []
+    with open(os.path.join(GOLDEN, "clipping_example.txt")) as fh:
+        for line in fh:
+            if line.strip() and not line.startswith("#"):
+                w, x, y = line.split("|")
+                rows.append((float(w), np.array(x.split(), dtype=float), np.array(y.split(), dtype=float)))
+    return rows
+
+
+@pytest.mark.parametrize("width,x,y", _golden_clipping())
+def test_hard_clipping_hand_example(width, x, y):
+    got = oracle.clip_local_energy(x, width, "hard")
+    np.testing.assert_allclose(got, y, rtol=1e-14, atol=1e-14)
+
+
+def test_clipping_window_statistics_by_brute_force():
+    """Median by sorting in plain Python (odd and even counts, non-finite values excluded), the
+    window, and the soft shape's continuity, unit slope at the edge, odd symmetry and logarithmic
+    growth."""
+    rng = np.random.default_rng(77)
+    for n in (1, 2, 7, 8, 101, 256):
+        x = rng.standard_cauchy(n) * 3 - 40
+        x_in = np.concatenate([x, [np.nan, np.inf, -np.inf]])
+        srt = sorted(float(v) for v in x)
+        med = srt[n // 2] if n % 2 else 0.5 * (srt[n // 2 - 1] + srt[n // 2])
+        mad = sum(abs(float(v) - med) for v in x) / n
+        for width in (0.5, 5.0):
+            sig = width * mad
+            hard = oracle.clip_local_energy(x_in, width, "hard")
+            soft = oracle.clip_local_energy(x_in, width, "soft")
+            assert np.isnan(hard[n]) and hard[n + 1] == np.inf and hard[n + 2] == -np.inf
+            inside = np.abs(x - med) <= sig
+            np.testing.assert_array_equal(hard[:n][inside], x[inside])
+            np.testing.assert_array_equal(soft[:n][inside], x[inside])
+            np.testing.assert_allclose(hard[:n][~inside], med + np.sign(x[~inside] - med) * sig, rtol=1e-13)
+            assert np.all(np.abs(soft[:n] - med) >= np.abs(hard[:n] - med) - 1e-12)
+            assert np.all(np.diff(soft[:n][np.argsort(x)]) >= 0)
+    # soft shape around mu = 0, sigma = 1 (values 0 and +-1 fix the median and deviation)
+    base = np.array([-1.0, 0.0, 1.0] * 50)
+    for t in (1.0 + 1e-9, 2.0, 4.0, 8.0):
+        v = oracle.clip_local_energy(np.concatenate([base, [t, -t]]), 1.0, "soft")[-2:]
+        mad = (100 + 2 * t) / 152
+        assert abs(v[0] + v[1]) < 1e-12
+        if t > 1.5:
+            assert abs(v[0] - mad * (1 + math.log(t / mad))) < 1e-12
+    # just outside the edge: t = sigma (1 + e) with sigma = (100 + 2 t) / 152 solved for t
+    e = 1e-7
+    t = (100 / 152) * (1 + e) / (1 - 2 * (1 + e) / 152)
+    a = oracle.clip_local_energy(np.concatenate([base, [t, -t]]), 1.0, "soft")[-2]
+    assert abs(a - t) < 1e-12  # continuous, unit slope at the edge
+
+
+def test_clipping_degenerate_cases():
+    assert np.all(np.isnan(oracle.clip_local_energy(np.array([np.nan, np.nan]), 5.0)))
+    x = np.full(6, -1.25)
+    np.testing.assert_array_equal(oracle.clip_local_energy(x, 5.0, "soft"), x)
