@@ -222,6 +222,8 @@ def main():
 
     G = torch.empty_like(P)
     EM = torch.empty(1, dtype=torch.float64, device=dev)
+    EC = torch.empty(W, dtype=torch.float64, device=dev)  # clipped local energies for the gradient
+    clip_width = 5.0
     P_init = P.clone()  # the seeded network, restored after the timed steps have updated it
     # plain gradient descent; its cost does not depend on lr, kept small so that the network stays near its
     # seeded initialisation over the warm-up and timed steps
@@ -232,7 +234,8 @@ def main():
             plan.metropolis_step(P, R, lp, NOISE[t], U[t], tau, accepted=acc)
         plan.local_energy(P, R, out=out)
         if has_grad:
-            plan.loss_grad(P, R, out["e_loc"], grad=G, e_mean=EM)
+            plan.clip_local_energy(out["e_loc"], clip_width, "hard", out=EC)
+            plan.loss_grad(P, R, EC, grad=G, e_mean=EM)
             plan.sgd_update(P, G, lr)
 
     for _ in range(args.warmup):
@@ -416,7 +419,8 @@ def main():
                                + (", learnable Jastrow" if a.jastrow else "")
                                + (f", e-e cusp factor alpha {a.ee_cusp}" if a.ee_cusp > 0 else "")
                                + f"; step = {n_mc} Metropolis steps (tau {tau}) + "
-                               f"local energy" + (" + loss gradient + gradient-descent update (lr 1e-8)"
+                               f"local energy" + (" + clipping (median +- 5 mean absolute deviations) + loss "
+                                                  "gradient + gradient-descent update (lr 1e-8)"
                                                   if has_grad else ""),
                    "walkers": W, "electrons": s.n_elec, "precision": args.precision,
                    "loss_gradient_in_step": has_grad},
@@ -452,7 +456,7 @@ def main():
             rs, lp_c, _, _ = oracle.metropolis_step(rs, lp_c, noise[t, :nw], uni[t, :nw], tau, pc, s, a)
         ref = oracle.local_energy(rs, pc, s, a, chunk=16)
         if has_grad:
-            gc = oracle.loss_grad(rs, ref["e_loc"], pc, s, a)[0]
+            gc = oracle.loss_grad(rs, oracle.clip_local_energy(ref["e_loc"], clip_width, "hard"), pc, s, a)[0]
             pc_next = pc - lr * gc  # the gradient-descent update of the step
         tc = time.perf_counter() - t0
         res["cpu_baseline"] = {"value": nw / tc, "unit": "walkers/s", "cores": torch.get_num_threads(),
@@ -571,7 +575,7 @@ def bench_batched(args):
 def bench_scaling(args):
     """Train-step time against system size (Sec. VI, scaling): atoms and hydrogen chains up to 45 electrons,
     2000 walkers each, the N2-sized ansatz at random init; one step = the train step of the headline
-    workload (10 Metropolis steps + local energy + loss gradient + gradient-descent update), captured into
+    workload (10 Metropolis steps + local energy + clipping + loss gradient + update), captured into
     one HIP graph per system.  A power law t = c N^b is fitted per system class."""
     import torch
     import qmc_inputs as qi
@@ -597,13 +601,15 @@ def bench_scaling(args):
             lp, _ = plan.logpsi(P, R)
             out = plan.local_energy(P, R)
             G, EM = plan.loss_grad(P, R, out["e_loc"])
+            EC = torch.empty_like(out["e_loc"])
             acc = torch.empty(W, dtype=torch.uint8, device=dev)
 
             def step():
                 for t in range(n_mc):
                     plan.metropolis_step(P, R, lp, NOISE[t], U[t], tau, accepted=acc)
                 plan.local_energy(P, R, out=out)
-                plan.loss_grad(P, R, out["e_loc"], grad=G, e_mean=EM)
+                plan.clip_local_energy(out["e_loc"], 5.0, "hard", out=EC)
+                plan.loss_grad(P, R, EC, grad=G, e_mean=EM)
                 plan.sgd_update(P, G, lr)
 
             for _ in range(max(1, args.warmup)):
@@ -654,7 +660,7 @@ def bench_scaling(args):
                          "eager_step_kernels_ms": top})
             print(f"[scaling] {cls} n={n}: step {ms:.2f} ms, local energy {ms_le:.2f} ms ({launch})", file=sys.stderr,
                   flush=True)
-            del g, plan, P, R, NOISE, U, lp, out, G, EM, acc
+            del g, plan, P, R, NOISE, U, lp, out, G, EM, EC, acc
             torch.cuda.empty_cache()
 
     def fit(cls, key, nmin):
@@ -677,7 +683,7 @@ def bench_scaling(args):
         "config": {"workload": f"atoms Z in {list(qi.SCALING_ATOMS)} and hydrogen chains n in "
                                f"{list(qi.SCALING_CHAINS)} (1.8 bohr spacing), {W} walkers, width {a.width}, "
                                f"{a.mp_layers} message-passing layers, {a.n_det} dets; step = {n_mc} Metropolis "
-                               f"steps + local energy + loss gradient + update",
+                               f"steps + local energy + clipping + loss gradient + update",
                    "walkers": W, "precision": prec},
         "fits": fits,
         "rows": rows,

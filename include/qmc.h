@@ -223,6 +223,18 @@ qmc_status qmc_mala_step(const qmc_plan* plan, const void* params, double* r, do
                          double* grad, const double* noise, const double* u, double step,
                          int32_t damp, uint8_t* accepted, void* ws, size_t ws_bytes, void* stream);
 
+/* Clipped local energies for the loss gradient (Sec. IV.D): per system, over
+ * its finite e_loc, mu = median (the mean of the two middle values for an
+ * even count) and sigma = width * mean |e_loc - mu|; mode 0 (hard) clamps to
+ * [mu - sigma, mu + sigma]; mode 1 (soft) leaves the window unchanged and maps
+ * a value outside it to mu +- sigma (1 + log(|e - mu| / sigma)).  Non-finite
+ * values pass through, and so does everything when sigma is not positive.
+ * e_loc[W] and e_out[W] are device arrays (e_out may equal e_loc); width
+ * must be finite and > 0.  Pass e_out to qmc_loss_grad; energy estimates use
+ * the unclipped values. */
+qmc_status qmc_clip_local_energy(const qmc_plan* plan, const double* e_loc, double* e_out, double width,
+                                 int32_t mode, void* stream);
+
 /* Vector-Jacobian product of log|psi| with respect to the parameters:
  *   grad_params[P] = sum_w cotangent[w] * d log|psi_w| / d params. */
 qmc_status qmc_logpsi_vjp(const qmc_plan* plan, const void* params, const double* r,

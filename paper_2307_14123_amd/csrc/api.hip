@@ -816,6 +816,15 @@ qmc_status qmc_det_jets(int64_t n_mat, int32_t n, int32_t n_tan, const double* j
 
 const char* qmc_last_error(void) { return g_last_error; }
 
+qmc_status qmc_clip_local_energy(const qmc_plan* plan, const double* e_loc, double* e_out, double width, int32_t mode,
+                                 void* stream) {
+  if (!plan || !e_loc || !e_out || !std::isfinite(width) || width <= 0 || (mode != 0 && mode != 1))
+    return QMC_ERR_INVALID_ARGUMENT;
+  for (const auto& s : plan->p.sys)
+    CK(launch_clip(e_loc + s.walker_offset, e_out + s.walker_offset, s.W, width, mode, (hipStream_t)stream));
+  return QMC_OK;
+}
+
 qmc_status qmc_sgd_update(int32_t precision, void* params, const void* grad, int64_t n, double lr, void* stream) {
   if (n < 0 || (n > 0 && (!params || !grad)) || !std::isfinite(lr)) return QMC_ERR_INVALID_ARGUMENT;
   if (precision != QMC_FP64 && precision != QMC_FP32 && precision != QMC_BF16_MIXED) return QMC_ERR_INVALID_ARGUMENT;

@@ -454,6 +454,110 @@ __global__ __launch_bounds__(1024) void emean_kernel(const double* __restrict__ 
   }
 }
 
+// ---------------------------------------------------------------- clipped local energies
+
+// Order-preserving map of a finite double onto uint64 keys, and back.
+__device__ inline uint64_t order_key(double x) {
+  const uint64_t u = (uint64_t)__double_as_longlong(x);
+  return (u >> 63) ? ~u : (u | 0x8000000000000000ull);
+}
+__device__ inline double key_value(uint64_t k) {
+  const uint64_t u = (k >> 63) ? (k & 0x7fffffffffffffffull) : ~k;
+  return __longlong_as_double((long long)u);
+}
+
+// Fixed-order block sum over 1024 threads (deterministic).
+__device__ inline double block_sum_1024(double v, double* red) {
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int o = 512; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  const double r = red[0];
+  __syncthreads();
+  return r;
+}
+
+// One block per system: the median of the finite values by an 8-pass radix select on order keys
+// (256-bin LDS histograms), the mean absolute deviation from it (fixed-order sums), then
+// hard: clamp to [mu - sigma, mu + sigma]; soft: outside the window mu +- sigma (1 + log(|E - mu| / sigma)).
+// Non-finite values pass through; so does everything when sigma is not positive.
+__global__ __launch_bounds__(1024) void clip_kernel(const double* __restrict__ e, double* __restrict__ out, int64_t n,
+                                                    double width, int mode) {
+  __shared__ unsigned hist[256];
+  __shared__ double red[1024];
+  __shared__ int sh_digit;
+  __shared__ unsigned long long sh_rank;
+  const int tid = threadIdx.x;
+  double c = 0.0;
+  for (int64_t i = tid; i < n; i += 1024) c += isfinite(e[i]) ? 1.0 : 0.0;
+  const double cnt = block_sum_1024(c, red);
+  double mu = 0.0, sigma = 0.0;
+  if (cnt > 0) {
+    const unsigned long long m = (unsigned long long)cnt;
+    auto select = [&](unsigned long long k) -> double {
+      uint64_t prefix = 0, mask = 0;
+      for (int shift = 56; shift >= 0; shift -= 8) {
+        if (tid < 256) hist[tid] = 0u;
+        __syncthreads();
+        for (int64_t i = tid; i < n; i += 1024) {
+          const double x = e[i];
+          if (!isfinite(x)) continue;
+          const uint64_t key = order_key(x);
+          if ((key & mask) == prefix) atomicAdd(&hist[(key >> shift) & 255], 1u);
+        }
+        __syncthreads();
+        if (tid == 0) {
+          unsigned long long acc = 0;
+          int d = 0;
+          for (; d < 255; ++d) {
+            if (acc + hist[d] > k) break;
+            acc += hist[d];
+          }
+          sh_digit = d;
+          sh_rank = k - acc;
+        }
+        __syncthreads();
+        prefix |= (uint64_t)sh_digit << shift;
+        mask |= (uint64_t)0xFF << shift;
+        k = sh_rank;
+        __syncthreads();
+      }
+      return key_value(prefix);
+    };
+    const double lo = select((m - 1) / 2);
+    mu = (m & 1) ? lo : (lo + select(m / 2)) * 0.5;
+    double a = 0.0;
+    for (int64_t i = tid; i < n; i += 1024) {
+      const double x = e[i];
+      if (isfinite(x)) a += fabs(x - mu);
+    }
+    sigma = width * (block_sum_1024(a, red) / cnt);
+  }
+  const bool clip = cnt > 0 && sigma > 0.0;
+  for (int64_t i = tid; i < n; i += 1024) {
+    const double x = e[i];
+    double y = x;
+    if (clip && isfinite(x)) {
+      if (mode == 0) {
+        y = fmin(fmax(x, mu - sigma), mu + sigma);
+      } else {
+        const double dv = fabs(x - mu);
+        if (dv > sigma) y = mu + copysign(sigma * (1.0 + log(dv / sigma)), x - mu);
+      }
+    }
+    out[i] = y;
+  }
+}
+
+hipError_t launch_clip(const double* e, double* out, int64_t n, double width, int mode, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  ProfScope ps("clip_kernel", st);
+  hipLaunchKernelGGL(clip_kernel, dim3(1), dim3(1024), 0, st, e, out, n, width, mode);
+  return hipGetLastError();
+}
+
 // g_w = 2 (e_w - mean) / count for finite e_w, else 0
 __global__ void gbar_kernel(const double* __restrict__ e, const double* __restrict__ stats, int64_t W,
                             double* __restrict__ g) {

@@ -148,6 +148,9 @@ hipError_t launch_propose(const double* r, const double* noise, double step, int
                           hipStream_t st);
 hipError_t launch_accept(int64_t W, int N3, const double* rp, const double* lp_prop, const double* u,
                          double* r, double* logpsi, uint8_t* accepted, hipStream_t st);
+// Clipped local energies of one system's n walkers (median-centred window of half-width
+// width x mean absolute deviation; mode 0 hard, 1 logarithmic soft); out may equal e.
+hipError_t launch_clip(const double* e, double* out, int64_t n, double width, int mode, hipStream_t st);
 // Langevin step: drift proposal (one thread per electron) and Hastings acceptance (one per walker);
 // rp, gp [W][N][3] and lpp [W] are the proposal, its gradient and its log|psi|.
 hipError_t launch_propose_mala(const SysDev& s, const double* r, const double* g, const double* noise, double step,

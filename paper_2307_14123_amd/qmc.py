@@ -83,6 +83,8 @@ def lib():
     L.qmc_plan_tiles.argtypes = [vp, i32, ctypes.POINTER(i32)]
     L.qmc_status_str.restype = ctypes.c_char_p
     L.qmc_status_str.argtypes = [i32]
+    L.qmc_clip_local_energy.restype = i32
+    L.qmc_clip_local_energy.argtypes = [vp, dp, dp, ctypes.c_double, i32, vp]
     L.qmc_last_error.restype = ctypes.c_char_p
     L.qmc_last_error.argtypes = []
     _lib = L
@@ -259,6 +261,18 @@ class Plan:
                                    _ptr(u), float(step), int(bool(damp)), _ptr(accepted), _ptr(ws), ws.numel(),
                                    _stream()), "qmc_mala_step")
         return accepted
+
+    def clip_local_energy(self, e_loc, width=5.0, mode="hard", out=None):
+        """Clipped local energies for the loss gradient (per system: median-centred window of half-width
+        width x mean absolute deviation); mode "hard" or "soft" (logarithmic)."""
+        if e_loc.dtype != torch.float64 or e_loc.numel() != self.total_walkers or not e_loc.is_contiguous():
+            raise ValueError("e_loc: expected contiguous float64 [W]")
+        out = torch.empty_like(e_loc) if out is None else out
+        if out.dtype != torch.float64 or out.numel() != self.total_walkers or not out.is_contiguous():
+            raise ValueError("out: expected contiguous float64 [W]")
+        _check(lib().qmc_clip_local_energy(self.handle, _ptr(e_loc), _ptr(out), float(width),
+                                           {"hard": 0, "soft": 1}[mode], _stream()), "qmc_clip_local_energy")
+        return out
 
     def logpsi_vjp(self, params, r, cotangent):
         self._check_inputs(params, r)

@@ -91,6 +91,11 @@ def test_invalid_arguments_rejected():
                                None) == 1
         assert L.qmc_mala_step(handle, fake, fake, fake, fake, fake, fake, 0.1, 1, None, vp(0x10000), 16,
                                None) == 3
+        # clipping: width and mode
+        assert L.qmc_clip_local_energy(handle, fake, fake, 0.0, 0, None) == 1
+        assert L.qmc_clip_local_energy(handle, fake, fake, float("nan"), 0, None) == 1
+        assert L.qmc_clip_local_energy(handle, fake, fake, 5.0, 2, None) == 1
+        assert L.qmc_clip_local_energy(handle, None, fake, 5.0, 0, None) == 1
         # determinant entry: bad sizes
         assert L.qmc_det_jets(4, 0, 3, fake, fake, fake, fake, fake, None) == 1
         assert L.qmc_det_jets(4, 33, 3, fake, fake, fake, fake, fake, None) == 1
