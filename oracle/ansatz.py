@@ -90,18 +90,23 @@ def embedding(r, P, system, ans):
 
 def orbital_matrices(r, P, system, ans, emb=None):
     """A^{sigma,p} per spin: list of [B, n_det, n_sigma, n_sigma] tensors (emb: the embedding's
-    output when already computed)."""
+    output when already computed).  With ans.full_det (Sec. III.C, full-determinant equation) every
+    spin's orbital map gives N orbitals, the rows of both spins form one N x N matrix per p, and the
+    list is [A (B, n_det, N, N), None]."""
     f, d_en = embedding(r, P, system, ans) if emb is None else emb
     B = r.shape[0]
+    full = bool(getattr(ans, "full_det", 0))
+    N = system.n_up + system.n_down
     out = []
     start = 0
     for s, n in (("up", system.n_up), ("down", system.n_down)):
         if n == 0:
             out.append(None)
             continue
+        no = N if full else n                                    # orbitals per determinant
         fs = f[:, start:start + n]                               # [B, n(a), D]
-        phi = (fs @ P[f"orb.{s}.W"] + P[f"orb.{s}.b"])           # [B, a, p*n + k]
-        phi = phi.reshape(B, n, ans.n_det, n).permute(0, 2, 1, 3)  # [B, p, a, k]
+        phi = (fs @ P[f"orb.{s}.W"] + P[f"orb.{s}.b"])           # [B, a, p*no + k]
+        phi = phi.reshape(B, n, ans.n_det, no).permute(0, 2, 1, 3)  # [B, p, a, k]
         pi = P[f"orb.{s}.pi"]                                    # [p, k, I, beta]
         sg = P[f"orb.{s}.sigma"]
         d = d_en[:, start:start + n]                             # [B, a, I]
@@ -109,6 +114,8 @@ def orbital_matrices(r, P, system, ans, emb=None):
                torch.exp(-sg[None, :, None, :, :, :] * d[:, None, :, None, :, None])).sum((-1, -2))
         out.append(phi * env)                                    # [B, p, a, k]
         start += n
+    if full:
+        return [torch.cat([A for A in out if A is not None], dim=2), None]
     return out
 
 

@@ -38,10 +38,12 @@ def param_shapes(system, ans):
         shapes[f"mp{l}.bg"] = (D,)
     for s, n in (("up", system.n_up), ("down", system.n_down)):
         if n > 0:
-            shapes[f"orb.{s}.W"] = (D, ans.n_det * n)
-            shapes[f"orb.{s}.b"] = (ans.n_det * n,)
-            shapes[f"orb.{s}.pi"] = (ans.n_det, n, M, ans.n_env)
-            shapes[f"orb.{s}.sigma"] = (ans.n_det, n, M, ans.n_env)
+            # full determinant: every spin's orbital map gives all N orbitals of each determinant
+            no = system.n_up + system.n_down if getattr(ans, "full_det", 0) else n
+            shapes[f"orb.{s}.W"] = (D, ans.n_det * no)
+            shapes[f"orb.{s}.b"] = (ans.n_det * no,)
+            shapes[f"orb.{s}.pi"] = (ans.n_det, no, M, ans.n_env)
+            shapes[f"orb.{s}.sigma"] = (ans.n_det, no, M, ans.n_env)
     shapes["c"] = (ans.n_det,)
     if getattr(ans, "jastrow", 0):
         D = ans.width

@@ -86,25 +86,33 @@ def logpsi_np(r, params, system, ans):
     logdet = np.zeros((W, ndet))
     sign = np.ones((W, ndet))
     blocks = (("up", list(range(system.n_up))), ("down", list(range(system.n_up, N))))
+    full = bool(getattr(ans, "full_det", 0))
+    Afull = np.zeros((W, ndet, N, N)) if full else None
     for s, idx in blocks:
         n = len(idx)
         if n == 0:
             continue
+        no = N if full else n                                      # orbitals per determinant
         Wo, bo = P[f"orb.{s}.W"], P[f"orb.{s}.b"]
         pi, sg = P[f"orb.{s}.pi"], P[f"orb.{s}.sigma"]
-        A = np.zeros((W, ndet, n, n))
+        A = np.zeros((W, ndet, n, no))
         for a, i in enumerate(idx):
-            phi = f[i] @ Wo + bo                                   # [W, ndet*n]
+            phi = f[i] @ Wo + bo                                   # [W, ndet*no]
             for p in range(ndet):
-                for k in range(n):
+                for k in range(no):
                     env = np.zeros(W)
                     for I in range(M):
                         for b in range(ans.n_env):
                             env += pi[p, k, I, b] * np.exp(-sg[p, k, I, b] * den[i][I])
-                    A[:, p, a, k] = phi[:, p * n + k] * env
+                    A[:, p, a, k] = phi[:, p * no + k] * env
+        if full:
+            Afull[:, :, idx[0]:idx[0] + n, :] = A                 # rows of this spin block
+            continue
         sg_, ld = np.linalg.slogdet(A)
         logdet += ld
         sign *= sg_
+    if full:
+        sign, logdet = np.linalg.slogdet(Afull)
     c = P["c"]
     mx = np.max(logdet, axis=1)
     mx = np.where(np.isfinite(mx), mx, 0.0)

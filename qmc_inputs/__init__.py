@@ -59,6 +59,7 @@ class Ansatz:
     include_vnn: int = 1     # add the constant nuclear repulsion to V
     ee_cusp: float = 0.0     # length alpha of the fixed electron-electron cusp factor (0: none)
     jastrow: int = 0         # 1: learnable Jastrow factor exp(J), J an MLP of the summed embeddings
+    full_det: int = 0        # 1: one N x N determinant per p over both spins (N orbitals per spin map)
 
 
 @dataclasses.dataclass(frozen=True)
@@ -102,10 +103,11 @@ def param_table(system: System, ans: Ansatz) -> List[Tuple[str, Tuple[int, ...],
         if n == 0:
             continue
         P = ans.n_det
-        out.append((f"orb.{s}.W", (D, P * n), "w", D))
-        out.append((f"orb.{s}.b", (P * n,), "zero", 0))
-        out.append((f"orb.{s}.pi", (P, n, M, ans.n_env), "one", 0))
-        out.append((f"orb.{s}.sigma", (P, n, M, ans.n_env), "sigma", 0))
+        no = system.n_up + system.n_down if ans.full_det else n  # orbitals per determinant
+        out.append((f"orb.{s}.W", (D, P * no), "w", D))
+        out.append((f"orb.{s}.b", (P * no,), "zero", 0))
+        out.append((f"orb.{s}.pi", (P, no, M, ans.n_env), "one", 0))
+        out.append((f"orb.{s}.sigma", (P, no, M, ans.n_env), "sigma", 0))
     out.append(("c", (ans.n_det,), "one", 0))
     if ans.jastrow:
         out.append(("jas.W1", (D, D), "w", D))

@@ -185,6 +185,67 @@ def test_constant_jastrow_shifts_log_psi_only():
     np.testing.assert_allclose(a["grad"], b["grad"], rtol=1e-12, atol=1e-12)
 
 
+def _full_from_factorized(pf, s, af, afull):
+    """Full-determinant parameters whose N x N matrices are block diagonal with the factorized
+    ansatz's spin blocks: the up map fills orbitals 0..n_up-1, the down map orbitals n_up..N-1, every
+    other orbital has zero weights, bias and envelope."""
+    N = s.n_up + s.n_down
+    Pf = unpack(pf, s, af)
+    pfull = np.zeros(oracle.param_count(s, afull))
+    Pn = unpack(pfull, s, afull)
+    for name, v in Pf.items():
+        if not name.startswith("orb."):
+            Pn[name][...] = v
+    Pn["orb.up.sigma"][...] = 1.0
+    Pn["orb.down.sigma"][...] = 1.0
+    for sp, n, k0 in (("up", s.n_up, 0), ("down", s.n_down, s.n_up)):
+        for p in range(af.n_det):
+            Pn[f"orb.{sp}.W"][:, p * N + k0:p * N + k0 + n] = Pf[f"orb.{sp}.W"][:, p * n:(p + 1) * n]
+            Pn[f"orb.{sp}.b"][p * N + k0:p * N + k0 + n] = Pf[f"orb.{sp}.b"][p * n:(p + 1) * n]
+            Pn[f"orb.{sp}.pi"][p, k0:k0 + n] = Pf[f"orb.{sp}.pi"][p]
+            Pn[f"orb.{sp}.sigma"][p, k0:k0 + n] = Pf[f"orb.{sp}.sigma"][p]
+    return pfull
+
+
+def test_full_determinant_reduces_to_factorized_for_block_diagonal_matrices():
+    """Block-diagonal full matrices give det A = det A_up det A_down (Sec. III.C), so the full-
+    determinant ansatz reproduces the spin-factorized one: log|psi|, sign and E_L."""
+    s = _small_system()
+    pf = qi.make_params(s, SMALL, 51)
+    pf[-SMALL.n_det:] = [1.0, -0.7, 0.4]
+    pfull = _full_from_factorized(pf, s, SMALL, SMALL_FULL)
+    r = qi.make_walkers(s, 5, 52)
+    a = oracle.local_energy(r, pf, s, SMALL)
+    b = oracle.local_energy(r, pfull, s, SMALL_FULL)
+    np.testing.assert_array_equal(a["sign"], b["sign"])
+    np.testing.assert_allclose(b["logpsi"], a["logpsi"], rtol=1e-12, atol=1e-12)
+    np.testing.assert_allclose(b["e_loc"], a["e_loc"], rtol=1e-9, atol=1e-9)
+
+
+def test_full_determinant_generalized_laplace_expansion():
+    """det of the full matrix = sum over n_up-subsets S of the orbitals of eps_S det A[up, S]
+    det A[down, complement], eps_S the sign of the permutation (S, complement), by brute force."""
+    import itertools
+    from oracle.ansatz import orbital_matrices
+    s = qi.System((3.0, 1.0), ((0.0, 0.0, 0.0), (1.6, 0.2, -0.3)), 2, 2)
+    a = dataclasses.replace(SMALL, n_det=1, full_det=1)
+    p = qi.make_params(s, a, 53)
+    P = unpack(p, s, a)
+    P["c"][:] = 1.0
+    r = qi.make_walkers(s, 6, 54)
+    A = orbital_matrices(torch.as_tensor(r), unpack(torch.as_tensor(p), s, a), s, a)[0][:, 0].numpy()
+    N, nu = 4, 2
+    det = np.zeros(len(r))
+    for S in itertools.combinations(range(N), nu):
+        Sb = [k for k in range(N) if k not in S]
+        perm = list(S) + Sb
+        inv = sum(1 for x in range(N) for y in range(x + 1, N) if perm[x] > perm[y])
+        det += (-1) ** inv * np.linalg.det(A[:, :nu][:, :, list(S)]) * np.linalg.det(A[:, nu:][:, :, Sb])
+    sg, lp = oracle.logpsi(torch.as_tensor(r), torch.as_tensor(p), s, a)
+    np.testing.assert_allclose(np.log(np.abs(det)), lp.numpy(), rtol=1e-12, atol=1e-12)
+    np.testing.assert_array_equal(np.sign(det), sg.numpy())
+
+
 def _golden_hydrogenic():
     rows = []
     with open(os.path.join(GOLDEN, "hydrogenic_energies.txt")) as fh:
@@ -238,11 +299,12 @@ def _small_system():
 
 SMALL_CUSP = dataclasses.replace(SMALL, ee_cusp=0.7)
 SMALL_JAS = dataclasses.replace(SMALL, ee_cusp=0.7, jastrow=1)
+SMALL_FULL = dataclasses.replace(SMALL, full_det=1)
 
 
 def test_torch_and_numpy_forwards_agree():
     s = _small_system()
-    for ans in (SMALL_CUSP, SMALL_JAS):
+    for ans in (SMALL_CUSP, SMALL_JAS, SMALL_FULL):
         p = qi.make_params(s, ans, 13)
         r = qi.make_walkers(s, 5, 14)
         st, lt = oracle.logpsi(torch.as_tensor(r), torch.as_tensor(p), s, ans)
@@ -298,7 +360,7 @@ def test_cancelling_determinants_give_zero_psi():
     assert np.all(np.isnan(res["e_loc"]))
 
 
-@pytest.mark.parametrize("ans", [SMALL, SMALL_JAS], ids=["plain", "cusp_jastrow"])
+@pytest.mark.parametrize("ans", [SMALL, SMALL_JAS, SMALL_FULL], ids=["plain", "cusp_jastrow", "full_det"])
 def test_same_spin_exchange_antisymmetry(ans):
     s = _small_system()
     p = qi.make_params(s, ans, 17)
@@ -349,7 +411,7 @@ def _fd_grad_lap(r, p, s, a, h):
     return g, lap
 
 
-@pytest.mark.parametrize("ans", [SMALL, SMALL_CUSP, SMALL_JAS], ids=["plain", "ee_cusp", "jastrow"])
+@pytest.mark.parametrize("ans", [SMALL, SMALL_CUSP, SMALL_JAS, SMALL_FULL], ids=["plain", "ee_cusp", "jastrow", "full_det"])
 def test_gradient_and_laplacian_vs_finite_differences(ans):
     s = _small_system()
     p = qi.make_params(s, ans, 23)
