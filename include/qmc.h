@@ -84,7 +84,12 @@ typedef struct qmc_system {
  *   jastrow         : 1 multiplies psi by the learnable Jastrow factor exp(J)
  *                     of Sec. III.D, J = tanh(s W1 + b1) W2 + b2 with
  *                     s = sum_i f_i the sum of the final electron embeddings
- *                     (an MLP of one hidden layer of width D); 0 = none. */
+ *                     (an MLP of one hidden layer of width D); 0 = none.
+ *   full_det        : 1 takes one N x N determinant per p over both spins
+ *                     (Sec. III.C, full-determinant equation): each spin's
+ *                     orbital map gives N orbitals, row i of A^p is electron i
+ *                     (up electrons first); needs N <= 32.  0 = spin-factorized
+ *                     determinants. */
 typedef struct qmc_ansatz {
   int32_t version;
   int32_t n_rbf;
@@ -97,6 +102,7 @@ typedef struct qmc_ansatz {
   int32_t include_vnn;
   double ee_cusp;
   int32_t jastrow;
+  int32_t full_det;
 } qmc_ansatz;
 
 typedef enum qmc_precision {
@@ -134,8 +140,9 @@ typedef struct qmc_plan qmc_plan;
  *   init.W1[(M+2)K][D] init.b1[D], then init.Wl[D][D] init.bl[D] for l>=2;
  *   per interaction layer: for t in (same, opp, nuc): U1[K][D] a1[D]
  *     U2[D][D] a2[D]; then Wh[D][D] bh[D] Y[M][D] Wg[3D][D] bg[D];
- *   per spin with n_sigma > 0: Worb[D][n_det*n_sigma] borb[n_det*n_sigma]
- *     pi[n_det][n_sigma][M][n_env] sigma[n_det][n_sigma][M][n_env];
+ *   per spin with n_sigma > 0, with n_o = n_sigma (or N with full_det):
+ *     Worb[D][n_det*n_o] borb[n_det*n_o] pi[n_det][n_o][M][n_env]
+ *     sigma[n_det][n_o][M][n_env];
  *   c[n_det]; then, with jastrow = 1: jas.W1[D][D] jas.b1[D] jas.W2[D][1]
  *   jas.b2[1]. */
 int64_t qmc_param_count(const qmc_system* system, const qmc_ansatz* ansatz);

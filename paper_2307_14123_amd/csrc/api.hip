@@ -49,6 +49,7 @@ static SysDev make_dev(const Plan& P, const SysPlan& s) {
   d.dmax = P.ans.rbf_dmax;
   d.vnn = P.ans.include_vnn ? s.vnn : 0.0;
   d.ee_cusp = P.ans.ee_cusp;
+  d.full_det = P.ans.full_det;
   for (int I = 0; I < s.M; ++I) {
     d.Z[I] = s.Z[I];
     for (int x = 0; x < 3; ++x) d.R[3 * I + x] = s.R[3 * I + x];
@@ -214,10 +215,10 @@ static qmc_status forward_chunk(const Plan& P, const SysPlan& s, const S* prm, c
   }
   int64_t off_e = 0;
   for (int sp = 0; sp < 2; ++sp) {
-    const int64_t n = s.nsig(sp);
+    const int64_t n = s.nsig(sp), no = s.norb(sp);  // electrons of this spin, orbitals per determinant
     if (n == 0) continue;
-    GemmArgs a = dense(f + off_e * Rp * D, D, prm + O.orbW[sp], ND * n, prm + O.orbb[sp], (S*)(ws + L.phi[sp]),
-                       ND * n, wc * n * Rp, (int)D, (int)(ND * n), Rp, s.T, 0, vm);
+    GemmArgs a = dense(f + off_e * Rp * D, D, prm + O.orbW[sp], ND * no, prm + O.orbb[sp], (S*)(ws + L.phi[sp]),
+                       ND * no, wc * n * Rp, (int)D, (int)(ND * no), Rp, s.T, 0, vm);
     a.xrpw = n * Rp;
     a.xws = N * Rp * D;
     CK(gemm(s, ok, a, st));
@@ -439,10 +440,10 @@ static qmc_status forward_stash(const Plan& P, const SysPlan& s, const S* prm, c
   }
   int64_t off_e = 0;
   for (int sp = 0; sp < 2; ++sp) {
-    const int64_t n = s.nsig(sp);
+    const int64_t n = s.nsig(sp), no = s.norb(sp);
     if (n == 0) continue;
-    GemmArgs a = dense(fprev + off_e * D, D, prm + O.orbW[sp], ND * n, prm + O.orbb[sp], (S*)(ws + B.phi[sp]), ND * n,
-                       wc * n, (int)D, (int)(ND * n), 1, 0, 0, 1);
+    GemmArgs a = dense(fprev + off_e * D, D, prm + O.orbW[sp], ND * no, prm + O.orbb[sp], (S*)(ws + B.phi[sp]),
+                       ND * no, wc * n, (int)D, (int)(ND * no), 1, 0, 0, 1);
     a.xrpw = n;
     a.xws = N * D;
     CK(gemm(s, ok, a, st));
@@ -495,11 +496,12 @@ static qmc_status backward_chunk(const Plan& P, const SysPlan& s, const S* prm, 
   for (int sp = 0; sp < 2; ++sp) {
     const int64_t n = s.nsig(sp);
     if (n == 0) continue;
-    const int64_t ncol = ND * n;
+    const int64_t ncol = ND * s.norb(sp);
     S* phib = (S*)(ws + B.phibar[sp]);
     double* pip = (double*)(ws + B.pipart);
     double* sgp = (double*)(ws + B.sgpart);
-    const double* ai = ainv + (sp ? wc * ND * s.nup * s.nup : 0);
+    // inverses of this spin's matrices (with the full determinant both spins share the N x N ones)
+    const double* ai = ainv + (sp && !s.full_det ? wc * ND * s.nup * s.nup : 0);
     CK(launch_orb_bwd<S>(dv, sp, lbar, ai, (S*)(ws + B.phi[sp]), prm + O.pi[sp], prm + O.sigma[sp], en, wc, phib, pip,
                          sgp, st));
     const int64_t ne = ncol * M * P.ans.n_env;

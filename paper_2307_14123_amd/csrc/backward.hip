@@ -593,7 +593,7 @@ __global__ void combine_bwd_kernel(SysDev s, const S* __restrict__ c, const doub
   const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (w >= W) return;
   const int nd = s.ndet;
-  const bool has[2] = {s.nup > 0, s.ndn > 0};
+  const bool has[2] = {det_dim(s, 0) > 0, det_dim(s, 1) > 0};
   double mx = -INFINITY;
   for (int p = 0; p < nd; ++p) {
     double l = 0.0;
@@ -648,20 +648,23 @@ __global__ void orb_bwd_kernel(SysDev s, int spin, const double* __restrict__ lb
                                double* __restrict__ pipart, double* __restrict__ sgpart) {
   // envelope values in the plan's activation type (as in the forward); sums in float64
   using T = S;
+  // n electrons of this spin, no orbitals per determinant, matrices of order dim with this spin's
+  // rows from row0 (spin-factorized: no = dim = n, row0 = 0)
   const int n = spin ? s.ndn : s.nup;
+  const int no = orb_count(s, spin), dim = s.full_det ? s.N : n, row0 = det_row0(s, spin);
   const int i0 = spin ? s.nup : 0;
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= W * s.ndet * n) return;
-  const int k = (int)(t % n);
-  const int p = (int)((t / n) % s.ndet);
-  const int64_t w = t / ((int64_t)n * s.ndet);
-  const int ncol = s.ndet * n;
+  if (t >= W * s.ndet * no) return;
+  const int k = (int)(t % no);
+  const int p = (int)((t / no) % s.ndet);
+  const int64_t w = t / ((int64_t)no * s.ndet);
+  const int ncol = s.ndet * no;
   const double lb = lbar[w * s.ndet + p];
-  const double* Ai = ainv + ((w * s.ndet + p) * n) * (int64_t)n;  // [n][n]
-  const double* gw = en + (w * s.N + i0) * s.M * 4;                // electron a of this spin: gw + a * M * 4
-  const S* phw = phi + (w * n) * (int64_t)ncol + p * n + k;        // row a: phw[a * ncol]
-  const S* pik = pi + ((int64_t)p * n + k) * s.M * s.nenv;
-  const S* sgk = sg + ((int64_t)p * n + k) * s.M * s.nenv;
+  const double* Ai = ainv + ((w * s.ndet + p) * dim) * (int64_t)dim;  // [dim][dim]
+  const double* gw = en + (w * s.N + i0) * s.M * 4;                    // electron a of this spin: gw + a * M * 4
+  const S* phw = phi + (w * n) * (int64_t)ncol + p * no + k;           // row a: phw[a * ncol]
+  const S* pik = pi + ((int64_t)p * no + k) * s.M * s.nenv;
+  const S* sgk = sg + ((int64_t)p * no + k) * s.M * s.nenv;
   // phi_bar = Abar * env, with Abar = lbar A^-T
   for (int a = 0; a < n; ++a) {
     const double* g = gw + a * s.M * 4;
@@ -670,7 +673,7 @@ __global__ void orb_bwd_kernel(SysDev s, int spin, const double* __restrict__ lb
       const T d = (T)g[I * 4];
       for (int b = 0; b < s.nenv; ++b) env += pik[I * s.nenv + b] * exp(-sgk[I * s.nenv + b] * d);
     }
-    phibar[(w * n + a) * (int64_t)ncol + p * n + k] = (S)(lb * Ai[k * n + a] * (double)env);
+    phibar[(w * n + a) * (int64_t)ncol + p * no + k] = (S)(lb * Ai[k * dim + row0 + a] * (double)env);
   }
   // pi_bar and sigma_bar of every (nucleus, exponent): sums over the electrons of the spin block
   double* pp = pipart + t * (int64_t)(s.M * s.nenv);
@@ -681,7 +684,7 @@ __global__ void orb_bwd_kernel(SysDev s, int spin, const double* __restrict__ lb
       double ap = 0.0, as = 0.0;
       for (int a = 0; a < n; ++a) {
         const T d = (T)gw[a * s.M * 4 + I * 4];
-        const double eb = lb * Ai[k * n + a] * (double)phw[(int64_t)a * ncol];
+        const double eb = lb * Ai[k * dim + row0 + a] * (double)phw[(int64_t)a * ncol];
         const double ex = (double)exp(-sgm * d);
         ap += eb * ex;
         as -= eb * (double)pw * (double)d * ex;
@@ -695,8 +698,7 @@ template <typename S>
 hipError_t launch_orb_bwd(const SysDev& s, int spin, const double* lbar, const double* ainv, const S* phi,
                           const S* pi, const S* sg, const double* en, int64_t W, S* phibar, double* pipart,
                           double* sgpart, hipStream_t st) {
-  const int n = spin ? s.ndn : s.nup;
-  const int64_t cnt = W * s.ndet * n;
+  const int64_t cnt = (spin ? s.ndn : s.nup) > 0 ? W * s.ndet * orb_count(s, spin) : 0;
   if (cnt == 0) return hipSuccess;
   ProfScope ps("orb_bwd_kernel", st);
   hipLaunchKernelGGL(orb_bwd_kernel<S>, dim3((unsigned)((cnt + 127) / 128)), dim3(128), 0, st, s, spin, lbar, ainv,

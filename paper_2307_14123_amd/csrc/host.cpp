@@ -43,11 +43,11 @@ bool compute_offsets(const qmc_system& s, const qmc_ansatz& a, ParamOffsets* off
   }
   const int ns[2] = {s.n_up, s.n_down};
   for (int sp = 0; sp < 2; ++sp) {
-    const int64_t n = ns[sp];
-    if (n == 0) {
+    if (ns[sp] == 0) {
       off->orbW[sp] = off->orbb[sp] = off->pi[sp] = off->sigma[sp] = -1;
       continue;
     }
+    const int64_t n = a.full_det ? int64_t(s.n_up) + s.n_down : ns[sp];  // orbitals per determinant
     off->orbW[sp] = take(cur, D * a.n_det * n);
     off->orbb[sp] = take(cur, a.n_det * n);
     off->pi[sp] = take(cur, a.n_det * n * M * a.n_env);
@@ -95,12 +95,8 @@ Workspace workspace_layout(const Plan& p, const SysPlan& s, int op, int64_t wc) 
   w.m = alloc(size_t(wc) * N * Rp * (jet ? 2 : 3) * D * E);
   w.mn5 = alloc(jet ? size_t(wc) * N * 5 * D * E : 0);
   w.zn5 = alloc(jet ? size_t(wc) * N * 5 * D * E : 0);
-  int64_t nsq = 0;
-  for (int sp = 0; sp < 2; ++sp) {
-    const int64_t n = s.nsig(sp);
-    w.phi[sp] = alloc(size_t(wc) * n * Rp * ND * n * E);
-    nsq += n * n;
-  }
+  const int64_t nsq = s.det_sq();
+  for (int sp = 0; sp < 2; ++sp) w.phi[sp] = alloc(size_t(wc) * s.nsig(sp) * Rp * ND * s.norb(sp) * E);
   w.ajet = alloc(size_t(wc) * ND * Rp * nsq * E);
   w.dld = alloc(size_t(wc) * 2 * ND * 8);
   w.dsg = alloc(size_t(wc) * 2 * ND * 8);
@@ -129,11 +125,10 @@ BwdWorkspace bwd_layout(const Plan& p, const SysPlan& s, int64_t wc) {
   const size_t E = act_bytes(p.prec);
   const int64_t N = s.N, M = s.M, D = p.ans.width, K = p.ans.n_rbf, ND = p.ans.n_det;
   const int64_t L = p.ans.mp_layers, L0 = p.ans.init_layers, F = (M + 2) * K;
-  int64_t nsq = 0, nmax = 0, pmax = 0;
-  for (int sp = 0; sp < 2; ++sp) {
-    nsq += int64_t(s.nsig(sp)) * s.nsig(sp);
-    if (s.nsig(sp) > nmax) nmax = s.nsig(sp);
-  }
+  const int64_t nsq = s.det_sq();
+  int64_t nmax = 0, pmax = 0;  // nmax: most orbitals per determinant of a spin map
+  for (int sp = 0; sp < 2; ++sp)
+    if (s.nsig(sp) > 0 && s.norb(sp) > nmax) nmax = s.norb(sp);
   for (int t = 0; t < 3; ++t)
     if (s.P[t] > pmax) pmax = s.P[t];
   b.geom = alloc(size_t(wc) * (N * N + N * M) * 4 * 8);
@@ -151,7 +146,7 @@ BwdWorkspace bwd_layout(const Plan& p, const SysPlan& s, int64_t wc) {
   b.hst = alloc(size_t(b.blk_f) * (L > 0 ? L : 1));
   b.mst = alloc(size_t(b.blk_m) * (L > 0 ? L : 1));
   b.tst = alloc(size_t(b.blk_f) * (L > 0 ? L : 1));
-  for (int sp = 0; sp < 2; ++sp) b.phi[sp] = alloc(size_t(wc) * s.nsig(sp) * ND * s.nsig(sp) * E);
+  for (int sp = 0; sp < 2; ++sp) b.phi[sp] = alloc(size_t(wc) * s.nsig(sp) * ND * s.norb(sp) * E);
   b.aval = alloc(size_t(wc) * ND * nsq * E);
   b.dld = alloc(size_t(wc) * 2 * ND * 8);
   b.dsg = alloc(size_t(wc) * 2 * ND * 8);
@@ -160,7 +155,7 @@ BwdWorkspace bwd_layout(const Plan& p, const SysPlan& s, int64_t wc) {
   b.stats = alloc(2 * 8);
   b.lbar = alloc(size_t(wc) * ND * 8);
   b.cpart = alloc(size_t(wc) * ND * 8);
-  for (int sp = 0; sp < 2; ++sp) b.phibar[sp] = alloc(size_t(wc) * s.nsig(sp) * ND * s.nsig(sp) * E);
+  for (int sp = 0; sp < 2; ++sp) b.phibar[sp] = alloc(size_t(wc) * s.nsig(sp) * ND * s.norb(sp) * E);
   b.pipart = alloc(size_t(wc) * ND * nmax * M * p.ans.n_env * 8);
   b.sgpart = alloc(size_t(wc) * ND * nmax * M * p.ans.n_env * 8);
   b.fbar = alloc(size_t(b.blk_f));
@@ -240,6 +235,7 @@ static bool valid_ansatz(const qmc_ansatz* a) {
   if (a->include_vnn != 0 && a->include_vnn != 1) return false;
   if (!std::isfinite(a->ee_cusp) || a->ee_cusp < 0) return false;
   if (a->jastrow != 0 && a->jastrow != 1) return false;
+  if (a->full_det != 0 && a->full_det != 1) return false;
   return true;
 }
 
@@ -288,6 +284,11 @@ qmc_status qmc_plan_create(qmc_plan** out, const qmc_system* systems, int32_t n_
     sp.nup = s->n_up;
     sp.ndn = s->n_down;
     sp.N = s->n_up + s->n_down;
+    sp.full_det = ansatz->full_det;
+    if (sp.full_det && sp.N > 32) {  // the determinant kernels hold a matrix row per lane of a 32-lane group
+      delete plan;
+      return QMC_ERR_UNSUPPORTED;
+    }
     sp.Z.assign(s->charges, s->charges + sp.M);
     sp.R.assign(s->coords, s->coords + 3 * sp.M);
     sp.vnn = 0;

@@ -67,9 +67,19 @@ struct SysDev {
   int N, M, nup, ndn, T, Rp, K, D, ndet, nenv, P0, P1, P2;
   double dmax, vnn;
   double ee_cusp;  // alpha of the electron-electron cusp factor (0: none)
+  int full_det;    // one N x N determinant per p instead of one per spin
   double Z[64];
   double R[64 * 3];
 };
+
+// Determinant matrices of spin s's stage (order; 0 when the stage has none), orbitals per
+// determinant of spin s's orbital map, and the first matrix row of spin s's electrons.  With the
+// full determinant, stage 0 holds the N x N matrices of both spins and stage 1 is empty.
+__host__ __device__ inline int det_dim(const SysDev& s, int sp) {
+  return s.full_det ? (sp ? 0 : s.N) : (sp ? s.ndn : s.nup);
+}
+__host__ __device__ inline int orb_count(const SysDev& s, int sp) { return s.full_det ? s.N : (sp ? s.ndn : s.nup); }
+__host__ __device__ inline int det_row0(const SysDev& s, int sp) { return s.full_det && sp ? s.nup : 0; }
 
 // Fused edge filters w(d) = tanh(rho(d) U1 + a1) U2 + a2 on MFMA (float32, width 128, at most 16
 // basis functions) for every pair of one edge type, from the geometry to the filter rows.

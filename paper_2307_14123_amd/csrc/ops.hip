@@ -759,7 +759,11 @@ __global__ __launch_bounds__(256) void envelope_kernel(SysDev s, int spin, const
   const int n = spin ? s.ndn : s.nup;
   const int i0 = spin ? s.nup : 0;
   const int Rp = jet ? s.Rp : 1;
-  const int nn = n * n, nb = s.nenv, M = s.M;
+  // n electrons (rows) of this spin, no orbitals (columns) per determinant, matrices of order dim
+  // starting at row row0 (dim = no = n and row0 = 0 for spin-factorized determinants)
+  const int no = orb_count(s, spin), dim = s.full_det ? s.N : n;
+  const int row0 = det_row0(s, spin);
+  const int nn = n * no, nb = s.nenv, M = s.M;
   // block b runs on XCD b % 8 (round-robin dispatch): the determinants of one chunk of
   // (walker, electron, orbital) triples are consecutive blocks of one XCD, so the orbital rows they
   // share (every determinant's columns side by side) are read from HBM once and then from that XCD's L2
@@ -772,17 +776,17 @@ __global__ __launch_bounds__(256) void envelope_kernel(SysDev s, int spin, const
   const bool live = t < W * nn;
   const int64_t w = live ? t / nn : 0;
   const int r = live ? (int)(t - w * nn) : 0;
-  const int a = r / n, k = r - a * n;
+  const int a = r / no, k = r - a * no;
   const int i = i0 + a;
   const double* g = en + (w * s.N + i) * M * 4;
   T e0 = 0, eg[3] = {0, 0, 0}, el = 0;
   for (int I0 = 0; I0 < M; I0 += ic) {
     const int ni = min(ic, M - I0);
     __syncthreads();  // the previous chunk has been read
-    for (int e = threadIdx.x; e < n * ni * nb; e += 256) {
+    for (int e = threadIdx.x; e < no * ni * nb; e += 256) {
       const int kk = e / (ni * nb), j = e - kk * (ni * nb);
-      const int64_t src = ((int64_t)(p * n + kk) * M + I0) * nb + j;
-      tab[j * n + kk] = S2{pi[src], sg[src]};
+      const int64_t src = ((int64_t)(p * no + kk) * M + I0) * nb + j;
+      tab[j * no + kk] = S2{pi[src], sg[src]};
     }
     __syncthreads();
     if (!live) continue;
@@ -790,7 +794,7 @@ __global__ __launch_bounds__(256) void envelope_kernel(SysDev s, int spin, const
       const T d = (T)g[(I0 + I) * 4];
       T s1 = 0, s2 = 0;
       for (int b = 0; b < nb; ++b) {
-        const S2 ps = tab[(I * nb + b) * n + k];
+        const S2 ps = tab[(I * nb + b) * no + k];
         const T e = ps.x * exp(-ps.y * d);
         e0 += e;
         s1 += ps.y * e;
@@ -803,15 +807,16 @@ __global__ __launch_bounds__(256) void envelope_kernel(SysDev s, int spin, const
     }
   }
   if (!live) return;
-  const int ncol = s.ndet * n;
-  const S* ph = phi + ((w * n + a) * Rp) * (int64_t)ncol + p * n + k;
-  const int64_t wstride = (int64_t)s.ndet * Rp * (s.nup * s.nup + s.ndn * s.ndn);
-  const int64_t soff = spin ? (int64_t)s.ndet * Rp * s.nup * s.nup : 0;
-  S* out = ajet + w * wstride + soff + ((int64_t)p * Rp * n + a) * n + k;
+  const int ncol = s.ndet * no;
+  const S* ph = phi + ((w * n + a) * Rp) * (int64_t)ncol + p * no + k;
+  const int d0 = det_dim(s, 0), d1 = det_dim(s, 1);
+  const int64_t wstride = (int64_t)s.ndet * Rp * (d0 * d0 + d1 * d1);
+  const int64_t soff = spin && !s.full_det ? (int64_t)s.ndet * Rp * d0 * d0 : 0;
+  S* out = ajet + w * wstride + soff + ((int64_t)p * Rp * dim + row0 + a) * dim + k;
   const T p0 = ph[0];
   out[0] = (S)(p0 * e0);
   if (!jet) return;
-  const int64_t rs = (int64_t)nn;
+  const int64_t rs = (int64_t)dim * dim;
   const int own = 1 + 3 * i;  // tangent rows of this electron's own coordinates
   for (int q = 1; q < Rp; ++q) {
     T v = 0;
@@ -830,10 +835,11 @@ template <typename S>
 hipError_t launch_envelope(const SysDev& s, int spin, const S* phi, const S* pi, const S* sigma, const double* en,
                            int64_t W, int jet, S* ajet, hipStream_t st) {
   const int n = spin ? s.ndn : s.nup;
-  const int64_t cnt = W * n * n;
+  const int no = orb_count(s, spin);
+  const int64_t cnt = W * n * no;
   if (cnt == 0) return hipSuccess;
   // nuclei per LDS chunk: at most 32 KB of (pi, sigma) pairs
-  const size_t per = (size_t)n * s.nenv * 2 * sizeof(S);
+  const size_t per = (size_t)no * s.nenv * 2 * sizeof(S);
   const int ic = (int)std::max<size_t>(1, std::min<size_t>(s.M, 32768 / per));
   const size_t lds = per * ic;
   const int64_t nx8 = ((cnt + 255) / 256 + 7) / 8 * 8;  // row chunks, rounded up to whole XCD rounds
@@ -1078,17 +1084,18 @@ template <typename S>
 hipError_t launch_det(const SysDev& s, const S* ajet, int64_t W, int jet, double* ld, double* sg, double* g,
                       double* lap, double* ainv, hipStream_t st) {
   const int Rp = jet ? s.Rp : 1;
-  const int64_t wstride = (int64_t)s.ndet * Rp * (s.nup * s.nup + s.ndn * s.ndn);
+  const int d0 = det_dim(s, 0);
+  const int64_t wstride = (int64_t)s.ndet * Rp * (d0 * d0 + det_dim(s, 1) * det_dim(s, 1));
   for (int spin = 0; spin < 2; ++spin) {
-    const int n = spin ? s.ndn : s.nup;
+    const int n = det_dim(s, spin);
     if (n == 0) continue;
     if (n > DMAX) return hipErrorInvalidValue;
-    const int64_t soff = spin ? (int64_t)s.ndet * Rp * s.nup * s.nup : 0;
+    const int64_t soff = spin ? (int64_t)s.ndet * Rp * d0 * d0 : 0;
     ProfScope ps(jet ? "det_kernel<jet>" : "det_kernel<val>", st);
     const hipError_t e =
         det_dispatch<S>(ajet + soff, wstride, s.ndet, (int64_t)Rp * n * n, W * s.ndet, n, s.T, jet,
                         (int64_t)2 * s.ndet, (int64_t)spin * s.ndet, ld, sg, g, lap,
-                        ainv ? ainv + (spin ? (int64_t)W * s.ndet * s.nup * s.nup : 0) : nullptr, st);
+                        ainv ? ainv + (spin ? (int64_t)W * s.ndet * d0 * d0 : 0) : nullptr, st);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -1124,7 +1131,7 @@ __global__ __launch_bounds__(64) void combine_kernel(SysDev s, const S* __restri
   const int64_t w = blockIdx.x;
   const int lane = threadIdx.x;
   const int nd = s.ndet;
-  const bool has[2] = {s.nup > 0, s.ndn > 0};
+  const bool has[2] = {det_dim(s, 0) > 0, det_dim(s, 1) > 0};
   double mx = -INFINITY;
   for (int p = 0; p < nd; ++p) {
     double l = 0.0;

@@ -39,7 +39,11 @@ struct SysPlan {
   int P[3];               // pairs per edge type: same-spin (unordered), up-down, electron-nucleus
   int64_t Wc;             // walkers per launch sequence (chunk)
   int tile[4];            // GEMM tile choice per class (TILE_*): 0 default, else 1 + tile bits
+  int full_det;
   int nsig(int s) const { return s == 0 ? nup : ndn; }
+  // orbitals per determinant of spin s's orbital map, and the order of the determinants' matrices
+  int norb(int s) const { return full_det ? N : nsig(s); }
+  int64_t det_sq() const { return full_det ? int64_t(N) * N : int64_t(nup) * nup + int64_t(ndn) * ndn; }
 };
 
 enum { TILE_JET = 0, TILE_VAL = 1, TILE_EDGE = 2, TILE_BWD = 3 };
