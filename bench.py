@@ -136,6 +136,11 @@ def environment():
                 env[key] = f.read().strip()
         except OSError:
             pass
+    # rocm-smi is a script started through env: skip it under a profiler, whose preloaded library would
+    # make that hop an exec of a process holding the GPU
+    if "rocprof" in os.environ.get("LD_PRELOAD", "") or any(k.startswith("ROCPROF") for k in os.environ):
+        env["rocm_smi"] = "skipped under a profiler"
+        return env
     try:
         res = subprocess.run(["rocm-smi", "--showclocks", "--showpower"], capture_output=True, text=True, timeout=30)
         keep = [ln.strip() for ln in res.stdout.splitlines()
