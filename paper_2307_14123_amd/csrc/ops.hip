@@ -665,7 +665,7 @@ __global__ __launch_bounds__(256) void aggregate_value_kernel(SysDev s, const S*
 template <typename S, int NS>
 static hipError_t agg_launch(const SysDev& s, const S* h, const S* ws, const S* wo, const double* ee, int64_t W, S* m,
                              hipStream_t st) {
-  constexpr int RG = (NS <= 8 && sizeof(S) == 4) ? 2 : 1;  // receivers per thread (register budget)
+  constexpr int RG = (NS <= 16 && sizeof(S) == 4) ? 2 : 1;  // receivers per thread (register budget)
   const int ngroups = (s.nup + RG - 1) / RG + (s.ndn + RG - 1) / RG;
   // columns per block: the largest power of two up to 64 with all groups in at most 512 threads
   int DC = 64;
