@@ -205,7 +205,8 @@ def main():
     uni = qi.make_uniforms(n_mc, W, qi.seed(k, 3))
 
     dev = torch.device("cuda", 0)
-    plan = qmc.Plan([s], [W], a, args.precision)
+    # GEMM tiles chosen by timing the candidates on the device at plan creation (outside the timed region)
+    plan = qmc.Plan([s], [W], a, args.precision, autotune=True)
     P = torch.as_tensor(params, dtype=plan.param_dtype, device=dev).contiguous()
     R = torch.as_tensor(r0, device=dev).contiguous()
     NOISE = torch.as_tensor(noise, device=dev).contiguous()
@@ -429,7 +430,7 @@ def main():
                                f"local energy" + (" + clipping (median +- 5 mean absolute deviations) + loss "
                                                   "gradient + gradient-descent update (lr 1e-8)"
                                                   if has_grad else ""),
-                   "walkers": W, "electrons": s.n_elec, "precision": args.precision,
+                   "walkers": W, "electrons": s.n_elec, "precision": args.precision, "tiles": plan.tiles()[0],
                    "loss_gradient_in_step": has_grad},
         "e_loc_per_s": W / (ms_le * 1e-3),
         "e_loc_ms": ms_le,
@@ -598,7 +599,7 @@ def bench_scaling(args):
     for cls, sizes, make in (("atoms", qi.SCALING_ATOMS, qi.atom), ("chains", qi.SCALING_CHAINS, qi.hydrogen_chain)):
         for n in sizes:
             s = make(n)
-            plan = qmc.Plan([s], [W], a, prec)
+            plan = qmc.Plan([s], [W], a, prec, autotune=True)
             P = torch.as_tensor(qi.make_params(s, a, 9000 + n), dtype=plan.param_dtype, device=dev).contiguous()
             R = torch.as_tensor(qi.make_walkers(s, W, 9100 + n), device=dev).contiguous()
             NOISE = torch.as_tensor(qi.make_noise(n_mc, W, s.n_elec, 9200 + n), device=dev).contiguous()

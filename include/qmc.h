@@ -129,7 +129,8 @@ enum {
   QMC_OP_METROPOLIS = 2,
   QMC_OP_LOGPSI_VJP = 3,
   QMC_OP_LOSS_GRAD = 4,
-  QMC_OP_MALA = 5
+  QMC_OP_MALA = 5,
+  QMC_OP_LOGPSI_GRAD = 6
 };
 
 typedef struct qmc_plan qmc_plan;
@@ -208,6 +209,13 @@ qmc_status qmc_local_energy(const qmc_plan* plan, const void* params, const doub
 qmc_status qmc_metropolis_step(const qmc_plan* plan, const void* params, double* r,
                                double* logpsi, const double* noise, const double* u, double step,
                                uint8_t* accepted, void* ws, size_t ws_bytes, void* stream);
+
+/* log|psi| and its gradient over the electron coordinates by the value
+ * forward and one reverse pass (no Laplacian): logpsi[W], grad[W][N][3]
+ * (NaN where log|psi| is not finite).  Equal to the logpsi and grad outputs
+ * of qmc_local_energy up to rounding. */
+qmc_status qmc_logpsi_grad(const qmc_plan* plan, const void* params, const double* r, double* logpsi,
+                           double* grad, void* ws, size_t ws_bytes, void* stream);
 
 /* One Metropolis-adjusted Langevin step (Sec. V, Langevin sampler).  With
  * tau = step^2 the proposal is r' = (r + tau D(r)) + step * noise, where the

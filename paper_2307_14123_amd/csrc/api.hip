@@ -324,37 +324,6 @@ static qmc_status run_metropolis(const Plan& P, const void* params, double* r, d
 }
 
 
-template <typename S>
-static qmc_status run_mala(const Plan& P, const void* params, double* r, double* logpsi, double* grad,
-                           const double* noise, const double* u, double step, int damp, uint8_t* accepted, char* ws,
-                           hipStream_t st) {
-  return for_systems(P, QMC_OP_MALA, ws, st, [&](size_t si, hipStream_t ss, char* wsb) -> qmc_status {
-    const SysPlan& s = P.sys[si];
-    const SysDev dv = make_dev(P, s);
-    const S* prm = (const S*)params + s.param_offset;
-    const int64_t pos = pos_offset(P, s);
-    for (int64_t w0 = 0; w0 < s.W; w0 += s.Wc) {
-      const int64_t wc = std::min<int64_t>(s.Wc, s.W - w0);
-      const int64_t wg = s.walker_offset + w0;
-      const Workspace L = workspace_layout(P, s, QMC_OP_MALA, wc);
-      double* rp = (double*)(wsb + L.lp_prop);
-      double* gp = rp + wc * s.N * 3;
-      double* lpp = gp + wc * s.N * 3;
-      const int64_t off = pos + w0 * s.N * 3;
-      CK(launch_propose_mala(dv, r + off, grad + off, noise + off, step, damp, wc, rp, ss));
-      Outs oc;
-      std::memset(&oc, 0, sizeof(oc));
-      oc.logpsi = lpp;
-      oc.grad = gp;
-      const qmc_status e = forward_chunk<S>(P, s, prm, rp, wc, 1, L, wsb, oc, ss);
-      if (e != QMC_OK) return e;
-      CK(launch_accept_mala(dv, wc, rp, gp, lpp, noise + off, u + wg, step, damp, r + off, grad + off, logpsi + wg,
-                            accepted ? accepted + wg : nullptr, ss));
-    }
-    return QMC_OK;
-  });
-}
-
 // ---------------------------------------------------------------- parameter backward
 
 static WgradArgs wg(const void* X, int64_t ldx, const void* G, int64_t ldg, int64_t rows, int Kin, int Nout,
@@ -457,22 +426,33 @@ static qmc_status forward_stash(const Plan& P, const SysPlan& s, const S* prm, c
 }
 
 // Cotangent gbar[wc] on log|psi| of the chunk -> accumulate parameter gradients into gacc (float64).
+// With rbar given, the pass computes the position gradient [wc][N][3] instead of the parameter
+// gradients (lp: log|psi| of the chunk, for the non-finite flag).
 template <typename S>
 static qmc_status backward_chunk(const Plan& P, const SysPlan& s, const S* prm, const double* gbar, int64_t wc,
-                                 const BwdWorkspace& B, char* ws, hipStream_t st) {
+                                 const BwdWorkspace& B, char* ws, hipStream_t st, double* rbar = nullptr,
+                                 const double* lp = nullptr) {
+  const bool pg = rbar == nullptr;  // parameter gradients
   const SysDev dv = make_dev(P, s);
   const int64_t N = s.N, M = s.M, D = P.ans.width, K = P.ans.n_rbf, ND = P.ans.n_det;
   const int L = P.ans.mp_layers, L0 = P.ans.init_layers;
   const GemmKind bk = P.prec == QMC_FP64 ? GK_F64 : GK_F32;
   const ParamOffsets& O = s.off;
   double* gacc = (double*)(ws + B.gacc);
-  double* en = (double*)(ws + B.geom) + wc * N * N * 4;
+  double* ee = (double*)(ws + B.geom);
+  double* en = ee + wc * N * N * 4;
+  double* dee = (double*)(ws + B.dee);
+  double* den = (double*)(ws + B.den);
+  if (!pg) {
+    CK(launch_fill(wc * N * N, 0.0, dee, st));
+    CK(launch_fill(wc * N * M, 0.0, den, st));
+  }
   auto F_ = [&](size_t base, int64_t blk, int l) { return (S*)(ws + base + size_t(blk) * l); };
   const int64_t rows = wc * N;
   double* lbar = (double*)(ws + B.lbar);
   double* cpart = (double*)(ws + B.cpart);
   CK(launch_combine_bwd<S>(dv, prm + O.c, (double*)(ws + B.dld), (double*)(ws + B.dsg), gbar, wc, lbar, cpart, st));
-  CK(launch_rowsum(cpart, wc, ND, ND, gacc + O.c, (double*)(ws + B.wpart), B.wpart_elems, st));
+  if (pg) CK(launch_rowsum(cpart, wc, ND, ND, gacc + O.c, (double*)(ws + B.wpart), B.wpart_elems, st));
   // Jastrow exponent: its cotangent is gbar itself (log|psi| = determinant part + J)
   S* jfs = nullptr;
   if (P.ans.jastrow) {
@@ -481,9 +461,11 @@ static qmc_status backward_chunk(const Plan& P, const SysPlan& s, const S* prm, 
     S* jgo = (S*)(ws + B.jgo);
     jfs = (S*)(ws + B.jfs);
     CK(launch_jastrow_bwd<S>(wc, (int)D, gbar, prm + O.jW2, jhid, jzb, jgo, st));
-    CK(launch_wgrad(bk, wg(jhid, D, jgo, 1, wc, (int)D, 1, B, ws), gacc + O.jW2, 1, gacc + O.jb2, st));
-    CK(launch_wgrad(bk, wg((S*)(ws + B.jsum), D, jzb, D, wc, (int)D, (int)D, B, ws), gacc + O.jW1, D, gacc + O.jb1,
-                    st));
+    if (pg) {
+      CK(launch_wgrad(bk, wg(jhid, D, jgo, 1, wc, (int)D, 1, B, ws), gacc + O.jW2, 1, gacc + O.jb2, st));
+      CK(launch_wgrad(bk, wg((S*)(ws + B.jsum), D, jzb, D, wc, (int)D, (int)D, B, ws), gacc + O.jW1, D,
+                      gacc + O.jb1, st));
+    }
     GemmArgs gj = dense(jzb, D, prm + O.jW1, D, nullptr, jfs, D, wc, (int)D, (int)D, 1, 0, 0, 1);
     gj.transw = 1;
     CK(gemm(s, bk, gj, st));
@@ -504,13 +486,18 @@ static qmc_status backward_chunk(const Plan& P, const SysPlan& s, const S* prm, 
     const double* ai = ainv + (sp && !s.full_det ? wc * ND * s.nup * s.nup : 0);
     CK(launch_orb_bwd<S>(dv, sp, lbar, ai, (S*)(ws + B.phi[sp]), prm + O.pi[sp], prm + O.sigma[sp], en, wc, phib, pip,
                          sgp, st));
-    const int64_t ne = ncol * M * P.ans.n_env;
-    CK(launch_rowsum(pip, wc, ne, ne, gacc + O.pi[sp], (double*)(ws + B.wpart), B.wpart_elems, st));
-    CK(launch_rowsum(sgp, wc, ne, ne, gacc + O.sigma[sp], (double*)(ws + B.wpart), B.wpart_elems, st));
-    WgradArgs a = wg(fL + off_e * D, D, phib, ncol, wc * n, (int)D, (int)ncol, B, ws);
-    a.xrpw = n;
-    a.xws = N * D;
-    CK(launch_wgrad(bk, a, gacc + O.orbW[sp], ncol, gacc + O.orbb[sp], st));
+    if (pg) {
+      const int64_t ne = ncol * M * P.ans.n_env;
+      CK(launch_rowsum(pip, wc, ne, ne, gacc + O.pi[sp], (double*)(ws + B.wpart), B.wpart_elems, st));
+      CK(launch_rowsum(sgp, wc, ne, ne, gacc + O.sigma[sp], (double*)(ws + B.wpart), B.wpart_elems, st));
+      WgradArgs a = wg(fL + off_e * D, D, phib, ncol, wc * n, (int)D, (int)ncol, B, ws);
+      a.xrpw = n;
+      a.xws = N * D;
+      CK(launch_wgrad(bk, a, gacc + O.orbW[sp], ncol, gacc + O.orbb[sp], st));
+    } else {
+      CK(launch_env_dbar<S>(dv, (int)sp, lbar, ai, (S*)(ws + B.phi[sp]), prm + O.pi[sp], prm + O.sigma[sp], en, wc,
+                            den, st));
+    }
     GemmArgs g = dense(phib, ncol, prm + O.orbW[sp], ncol, nullptr, fbar + off_e * D, D, wc * n, (int)ncol, (int)D, 1, 0,
                        0, 1);
     g.transw = 1;
@@ -529,8 +516,9 @@ static qmc_status backward_chunk(const Plan& P, const SysPlan& s, const S* prm, 
     const auto& Ly = O.mp[l];
     S* fin = l == 0 ? F_(B.finit, B.blk_f, L0 - 1) : F_(B.fst, B.blk_f, l - 1);
     CK(launch_tanh_bwd<S>(rows * D, fbar, F_(B.tst, B.blk_f, l), zbar, st));
-    CK(launch_wgrad(bk, wg(F_(B.mst, B.blk_m, l), 3 * D, zbar, D, rows, (int)(3 * D), (int)D, B, ws), gacc + Ly.Wg, D,
-                    gacc + Ly.bg, st));
+    if (pg)
+      CK(launch_wgrad(bk, wg(F_(B.mst, B.blk_m, l), 3 * D, zbar, D, rows, (int)(3 * D), (int)D, B, ws), gacc + Ly.Wg,
+                      D, gacc + Ly.bg, st));
     GemmArgs gm = dense(zbar, D, prm + Ly.Wg, D, nullptr, mbar, 3 * D, rows, (int)D, (int)(3 * D), 1, 0, 0, 1);
     gm.transw = 1;
     CK(gemm(s, bk, gm, st));
@@ -538,8 +526,10 @@ static qmc_status backward_chunk(const Plan& P, const SysPlan& s, const S* prm, 
     double* yp = (double*)(ws + B.ypart);
     CK(launch_agg_bwd<S>(dv, mbar, F_(B.hst, B.blk_f, l), F_(B.wv[0], B.blk_e[0], l), F_(B.wv[1], B.blk_e[1], l),
                          F_(B.wv[2], B.blk_e[2], l), prm + Ly.Y, wc, hbar, wb[0], wb[1], wb[2], yp, st));
-    CK(launch_rowsum(yp, wc, M * D, M * D, gacc + Ly.Y, (double*)(ws + B.wpart), B.wpart_elems, st));
-    CK(launch_wgrad(bk, wg(fin, D, hbar, D, rows, (int)D, (int)D, B, ws), gacc + Ly.Wh, D, gacc + Ly.bh, st));
+    if (pg) {
+      CK(launch_rowsum(yp, wc, M * D, M * D, gacc + Ly.Y, (double*)(ws + B.wpart), B.wpart_elems, st));
+      CK(launch_wgrad(bk, wg(fin, D, hbar, D, rows, (int)D, (int)D, B, ws), gacc + Ly.Wh, D, gacc + Ly.bh, st));
+    }
     GemmArgs gh = dense(hbar, D, prm + Ly.Wh, D, nullptr, fbar2, D, rows, (int)D, (int)D, 1, 0, 0, 1);
     gh.transw = 1;
     gh.Res = fbar;
@@ -549,13 +539,24 @@ static qmc_status backward_chunk(const Plan& P, const SysPlan& s, const S* prm, 
       const int64_t re = wc * s.P[t];
       if (re == 0) continue;
       S* eh = F_(B.ehid[t], B.blk_e[t], l);
-      CK(launch_wgrad(bk, wg(eh, D, wb[t], D, re, (int)D, (int)D, B, ws), gacc + Ly.U2[t], D, gacc + Ly.a2[t], st));
+      if (pg)
+        CK(launch_wgrad(bk, wg(eh, D, wb[t], D, re, (int)D, (int)D, B, ws), gacc + Ly.U2[t], D, gacc + Ly.a2[t],
+                        st));
       GemmArgs ge = dense(wb[t], D, prm + Ly.U2[t], D, nullptr, ebar, D, re, (int)D, (int)D, 1, 0, 2, 1);
       ge.transw = 1;
       ge.aux = eh;
       CK(gemm(s, bk, ge, st));
-      CK(launch_wgrad(bk, wg((S*)(ws + B.rho[t]), K, ebar, D, re, (int)K, (int)D, B, ws), gacc + Ly.U1[t], D,
-                      gacc + Ly.a1[t], st));
+      if (pg) {
+        CK(launch_wgrad(bk, wg((S*)(ws + B.rho[t]), K, ebar, D, re, (int)K, (int)D, B, ws), gacc + Ly.U1[t], D,
+                        gacc + Ly.a1[t], st));
+      } else {
+        // radial-basis cotangents rhobar = ebar U1^T, then the pair distances
+        S* rb = (S*)(ws + B.rhobar);
+        GemmArgs gr = dense(ebar, D, prm + Ly.U1[t], D, nullptr, rb, K, re, (int)D, (int)K, 1, 0, 0, 1);
+        gr.transw = 1;
+        CK(gemm(s, bk, gr, st));
+        CK(launch_pair_dbar<S>(dv, t, rb, ee, en, wc, dee, den, st));
+      }
     }
   }
   for (int l = L0 - 1; l >= 0; --l) {
@@ -563,18 +564,97 @@ static qmc_status backward_chunk(const Plan& P, const SysPlan& s, const S* prm, 
     CK(launch_tanh_bwd<S>(rows * D, fbar, out, zbar, st));
     const int Fd = (int)((M + 2) * K);
     if (l == 0) {
-      CK(launch_wgrad(bk, wg((S*)(ws + B.x0), Fd, zbar, D, rows, Fd, (int)D, B, ws), gacc + O.initW[0], D,
-                      gacc + O.initb[0], st));
+      if (pg) {
+        CK(launch_wgrad(bk, wg((S*)(ws + B.x0), Fd, zbar, D, rows, Fd, (int)D, B, ws), gacc + O.initW[0], D,
+                        gacc + O.initb[0], st));
+      } else {
+        // initial-feature cotangents x0bar = zbar W1^T, then the distances
+        S* xb = (S*)(ws + B.x0bar);
+        GemmArgs gx = dense(zbar, D, prm + O.initW[0], D, nullptr, xb, Fd, rows, (int)D, Fd, 1, 0, 0, 1);
+        gx.transw = 1;
+        CK(gemm(s, bk, gx, st));
+        CK(launch_init_dbar<S>(dv, xb, ee, en, wc, dee, den, st));
+      }
     } else {
-      CK(launch_wgrad(bk, wg(F_(B.finit, B.blk_f, l - 1), D, zbar, D, rows, (int)D, (int)D, B, ws), gacc + O.initW[l],
-                      D, gacc + O.initb[l], st));
+      if (pg)
+        CK(launch_wgrad(bk, wg(F_(B.finit, B.blk_f, l - 1), D, zbar, D, rows, (int)D, (int)D, B, ws),
+                        gacc + O.initW[l], D, gacc + O.initb[l], st));
       GemmArgs gi = dense(zbar, D, prm + O.initW[l], D, nullptr, fbar2, D, rows, (int)D, (int)D, 1, 0, 0, 1);
       gi.transw = 1;
       CK(gemm(s, bk, gi, st));
       std::swap(fbar, fbar2);
     }
   }
+  if (!pg) CK(launch_positions_bar(dv, ee, en, dee, den, lp, wc, rbar, st));
   return QMC_OK;
+}
+
+// log|psi| and its position gradient of one chunk by the value forward and one reverse pass
+// (r: the chunk's positions; lp [wc] and grad [wc][N][3] outputs).
+template <typename S>
+static qmc_status grad_chunk(const Plan& P, const SysPlan& s, const S* prm, const double* r, int64_t wc,
+                             const BwdWorkspace& B, char* ws, double* lp, double* grad, hipStream_t st) {
+  const qmc_status e = forward_stash<S>(P, s, prm, r, wc, B, ws, st);
+  if (e != QMC_OK) return e;
+  const SysDev dv = make_dev(P, s);
+  const ParamOffsets& O = s.off;
+  S* jv = nullptr;
+  if (P.ans.jastrow) {
+    jv = (S*)(ws + B.jval);
+    CK(launch_jastrow_out<S>(wc, 1, P.ans.width, (const S*)(ws + B.jhid), prm + O.jW2, prm + O.jb2, jv, st));
+  }
+  CK(launch_combine<S>(dv, prm + O.c, (double*)(ws + B.dld), (double*)(ws + B.dsg), nullptr, nullptr, nullptr,
+                       (double*)(ws + B.geom), jv, wc, 0, lp, nullptr, nullptr, nullptr, nullptr, st));
+  double* ones = (double*)(ws + B.ones);
+  CK(launch_fill(wc, 1.0, ones, st));
+  return backward_chunk<S>(P, s, prm, ones, wc, B, ws, st, grad, lp);
+}
+
+template <typename S>
+static qmc_status run_logpsi_grad(const Plan& P, const void* params, const double* r, double* logpsi, double* grad,
+                                  char* ws, hipStream_t st) {
+  return for_systems(P, QMC_OP_LOGPSI_GRAD, ws, st, [&](size_t si, hipStream_t ss, char* wsb) -> qmc_status {
+    const SysPlan& s = P.sys[si];
+    const S* prm = (const S*)params + s.param_offset;
+    const BwdWorkspace B0 = bwd_layout(P, s, s.Wc);
+    const int64_t pos = pos_offset(P, s);
+    for (int64_t w0 = 0; w0 < s.W; w0 += s.Wc) {
+      const int64_t wc = std::min<int64_t>(s.Wc, s.W - w0);
+      const qmc_status e = grad_chunk<S>(P, s, prm, r + pos + w0 * s.N * 3, wc, B0, wsb,
+                                         logpsi + s.walker_offset + w0, grad + pos + w0 * s.N * 3, ss);
+      if (e != QMC_OK) return e;
+    }
+    return QMC_OK;
+  });
+}
+
+// One Langevin step: drift proposal, log|psi| and its gradient at the proposal by the reverse pass,
+// Hastings acceptance.
+template <typename S>
+static qmc_status run_mala(const Plan& P, const void* params, double* r, double* logpsi, double* grad,
+                           const double* noise, const double* u, double step, int damp, uint8_t* accepted, char* ws,
+                           hipStream_t st) {
+  return for_systems(P, QMC_OP_MALA, ws, st, [&](size_t si, hipStream_t ss, char* wsb) -> qmc_status {
+    const SysPlan& s = P.sys[si];
+    const SysDev dv = make_dev(P, s);
+    const S* prm = (const S*)params + s.param_offset;
+    const BwdWorkspace B0 = bwd_layout(P, s, s.Wc);
+    const int64_t pos = pos_offset(P, s);
+    for (int64_t w0 = 0; w0 < s.W; w0 += s.Wc) {
+      const int64_t wc = std::min<int64_t>(s.Wc, s.W - w0);
+      const int64_t wg = s.walker_offset + w0;
+      double* rp = (double*)(wsb + B0.prop);
+      double* gp = rp + wc * s.N * 3;
+      double* lpp = gp + wc * s.N * 3;
+      const int64_t off = pos + w0 * s.N * 3;
+      CK(launch_propose_mala(dv, r + off, grad + off, noise + off, step, damp, wc, rp, ss));
+      const qmc_status e = grad_chunk<S>(P, s, prm, rp, wc, B0, wsb, lpp, gp, ss);
+      if (e != QMC_OK) return e;
+      CK(launch_accept_mala(dv, wc, rp, gp, lpp, noise + off, u + wg, step, damp, r + off, grad + off, logpsi + wg,
+                            accepted ? accepted + wg : nullptr, ss));
+    }
+    return QMC_OK;
+  });
 }
 
 // cot: per-walker cotangent (VJP) or nullptr with e_loc given (loss gradient).
@@ -764,6 +844,18 @@ qmc_status qmc_metropolis_step(const qmc_plan* plan, const void* params, double*
   if (plan->p.prec == QMC_FP64)
     return run_metropolis<double>(plan->p, params, r, logpsi, noise, u, step, accepted, (char*)ws, st);
   return run_metropolis<float>(plan->p, params, r, logpsi, noise, u, step, accepted, (char*)ws, st);
+}
+
+qmc_status qmc_logpsi_grad(const qmc_plan* plan, const void* params, const double* r, double* logpsi, double* grad,
+                           void* ws, size_t ws_bytes, void* stream) {
+  if (!plan || !params || !r || !logpsi || !grad) return QMC_ERR_INVALID_ARGUMENT;
+  if (!ws_ok(plan->p, QMC_OP_LOGPSI_GRAD, ws, ws_bytes)) {
+    if (ws && ws_bytes < workspace_bytes(plan->p, QMC_OP_LOGPSI_GRAD)) return QMC_ERR_WORKSPACE_TOO_SMALL;
+    return QMC_ERR_INVALID_ARGUMENT;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  if (plan->p.prec == QMC_FP64) return run_logpsi_grad<double>(plan->p, params, r, logpsi, grad, (char*)ws, st);
+  return run_logpsi_grad<float>(plan->p, params, r, logpsi, grad, (char*)ws, st);
 }
 
 qmc_status qmc_mala_step(const qmc_plan* plan, const void* params, double* r, double* logpsi, double* grad,

@@ -17,6 +17,7 @@
 #include <type_traits>
 
 #include "kernels.h"
+#include "pairs.h"
 
 namespace qmc {
 
@@ -793,9 +794,203 @@ hipError_t launch_agg_bwd(const SysDev& s, const S* mbar, const S* h, const S* w
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------- position gradient (reverse pass)
+//
+// d log|psi| / d r through the distances: every feature depends on the positions only through
+// d_ij and d_iI, so the cotangents of the radial bases, of the envelopes and of the cusp factor are
+// gathered per distance (dee[w][i][j] for i < j, den[w][i][I]) and then mapped to the positions
+// with the unit vectors: rbar_i = sum_j dbar_ij u_ij + sum_I dbar_iI u_iI.
+
+// edge filters of one type: dbar += sum_k rhobar[pair][k] drho_k / dd
+template <typename S>
+__global__ void pair_dbar_kernel(SysDev s, int type, const S* __restrict__ rhobar, const double* __restrict__ ee,
+                                 const double* __restrict__ en, int64_t W, double* __restrict__ dee,
+                                 double* __restrict__ den) {
+  const int P = type == 0 ? s.P0 : (type == 1 ? s.P1 : s.P2);
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= W * P) return;
+  const int64_t w = t / P;
+  const int p = (int)(t - w * P);
+  int i, j;
+  decode_pair(s, type, p, i, j);
+  const double d = type == 2 ? en[((w * s.N + i) * s.M + j) * 4] : ee[((w * s.N + i) * s.N + j) * 4];
+  const double sp = rbf_spacing(s.dmax, s.K), inv = (s.K - 1) / s.dmax;
+  double acc = 0.0;
+  for (int k = 0; k < s.K; ++k) {
+    double r0, r1, r2;
+    rbf3(d, k, sp, inv, r0, r1, r2);
+    acc += (double)rhobar[t * s.K + k] * r1;
+  }
+  if (type == 2)
+    den[(w * s.N + i) * s.M + j] += acc;
+  else
+    dee[(w * s.N + i) * s.N + j] += acc;  // i < j
+}
+
+// initial features x0 = [rho(d_iI) per nucleus, mean same-spin rho(d_ij), mean opposite-spin rho(d_ij)]:
+// threads over (w, i, I) for the e-n block and (w, i < j) for the two means (both ends of a pair)
+template <typename S>
+__global__ void init_dbar_kernel(SysDev s, const S* __restrict__ x0bar, const double* __restrict__ ee,
+                                 const double* __restrict__ en, int64_t W, double* __restrict__ dee,
+                                 double* __restrict__ den) {
+  const int N = s.N, M = s.M, K = s.K, F = (M + 2) * K;
+  const int per = N * M + N * N;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= W * per) return;
+  const int64_t w = t / per;
+  const int e = (int)(t - w * per);
+  const double sp = rbf_spacing(s.dmax, K), inv = (K - 1) / s.dmax;
+  if (e < N * M) {
+    const int i = e / M, I = e - (e / M) * M;
+    const double d = en[((w * N + i) * M + I) * 4];
+    const S* xb = x0bar + (w * N + i) * (int64_t)F + I * K;
+    double acc = 0.0;
+    for (int k = 0; k < K; ++k) {
+      double r0, r1, r2;
+      rbf3(d, k, sp, inv, r0, r1, r2);
+      acc += (double)xb[k] * r1;
+    }
+    den[(w * N + i) * M + I] += acc;
+    return;
+  }
+  const int q = e - N * M, i = q / N, j = q - (q / N) * N;
+  if (j <= i) return;
+  const bool ui = i < s.nup, uj = j < s.nup, same = ui == uj;
+  const int blk = same ? 0 : 1;
+  // members of each end's set: same spin without itself, or the other spin
+  const int ci = same ? (ui ? s.nup : s.ndn) - 1 : (ui ? s.ndn : s.nup);
+  const int cj = same ? (uj ? s.nup : s.ndn) - 1 : (uj ? s.ndn : s.nup);
+  const double d = ee[((w * N + i) * N + j) * 4];
+  const S* xi = x0bar + (w * N + i) * (int64_t)F + (M + blk) * K;
+  const S* xj = x0bar + (w * N + j) * (int64_t)F + (M + blk) * K;
+  double acc = 0.0;
+  for (int k = 0; k < K; ++k) {
+    double r0, r1, r2;
+    rbf3(d, k, sp, inv, r0, r1, r2);
+    acc += ((double)xi[k] / ci + (double)xj[k] / cj) * r1;
+  }
+  dee[(w * N + i) * N + j] += acc;
+}
+
+// envelopes: dA[a][k] / dd_aI = phi_k(a) sum_b (-sigma pi exp(-sigma d)), weighted by
+// Abar = lbar_p (A_p^-1)^T; thread per (w, electron a of this spin, nucleus I)
+template <typename S>
+__global__ void env_dbar_kernel(SysDev s, int spin, const double* __restrict__ lbar, const double* __restrict__ ainv,
+                                const S* __restrict__ phi, const S* __restrict__ pi, const S* __restrict__ sg,
+                                const double* __restrict__ en, int64_t W, double* __restrict__ den) {
+  const int n = spin ? s.ndn : s.nup;
+  const int no = orb_count(s, spin), dim = s.full_det ? s.N : n, row0 = det_row0(s, spin);
+  const int i0 = spin ? s.nup : 0;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= W * n * s.M) return;
+  const int I = (int)(t % s.M);
+  const int64_t wa = t / s.M;
+  const int a = (int)(wa % n);
+  const int64_t w = wa / n;
+  const int ncol = s.ndet * no;
+  const double d = en[((w * s.N + i0 + a) * s.M + I) * 4];
+  double acc = 0.0;
+  for (int p = 0; p < s.ndet; ++p) {
+    const double lb = lbar[w * s.ndet + p];
+    const double* Ai = ainv + ((w * s.ndet + p) * dim) * (int64_t)dim;
+    for (int k = 0; k < no; ++k) {
+      const int64_t o = (((int64_t)p * no + k) * s.M + I) * s.nenv;
+      double de = 0.0;
+      for (int b = 0; b < s.nenv; ++b) {
+        const double sgm = (double)sg[o + b];
+        de -= sgm * (double)pi[o + b] * exp(-sgm * d);
+      }
+      acc += lb * Ai[k * dim + row0 + a] * (double)phi[(w * n + a) * (int64_t)ncol + p * no + k] * de;
+    }
+  }
+  den[(w * s.N + i0 + a) * s.M + I] += acc;
+}
+
+// positions: rbar_i = sum_j dbar_ij u_ij + sum_I dbar_iI u_iI (+ the cusp factor's gradient); NaN
+// where log|psi| is not finite
+__global__ void positions_bar_kernel(SysDev s, const double* __restrict__ ee, const double* __restrict__ en,
+                                     const double* __restrict__ dee, const double* __restrict__ den,
+                                     const double* __restrict__ lp, int64_t W, double* __restrict__ out) {
+  const int N = s.N, M = s.M;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= W * N) return;
+  const int64_t w = t / N;
+  const int i = (int)(t - w * N);
+  double g[3] = {0.0, 0.0, 0.0};
+  const double a = s.ee_cusp, a2 = a * a;
+  for (int j = 0; j < N; ++j) {
+    if (j == i) continue;
+    const double* e = ee + ((w * N + i) * N + j) * 4;
+    double db = i < j ? dee[(w * N + i) * N + j] : dee[(w * N + j) * N + i];
+    if (a > 0.0) {
+      const double c = ((i < s.nup) == (j < s.nup)) ? 0.25 : 0.5;
+      const double q = 1.0 / (a + e[0]);
+      db += c * a2 * q * q;
+    }
+    for (int x = 0; x < 3; ++x) g[x] += db * e[1 + x];
+  }
+  for (int I = 0; I < M; ++I) {
+    const double* e = en + ((w * N + i) * M + I) * 4;
+    const double db = den[(w * N + i) * M + I];
+    for (int x = 0; x < 3; ++x) g[x] += db * e[1 + x];
+  }
+  const bool ok = isfinite(lp[w]);
+  for (int x = 0; x < 3; ++x) out[t * 3 + x] = ok ? g[x] : NAN;
+}
+
+template <typename S>
+hipError_t launch_pair_dbar(const SysDev& s, int type, const S* rhobar, const double* ee, const double* en, int64_t W,
+                            double* dee, double* den, hipStream_t st) {
+  const int P = type == 0 ? s.P0 : (type == 1 ? s.P1 : s.P2);
+  const int64_t n = W * P;
+  if (n == 0) return hipSuccess;
+  ProfScope ps("pair_dbar_kernel", st);
+  hipLaunchKernelGGL(pair_dbar_kernel<S>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, s, type, rhobar, ee, en,
+                     W, dee, den);
+  return hipGetLastError();
+}
+
+template <typename S>
+hipError_t launch_init_dbar(const SysDev& s, const S* x0bar, const double* ee, const double* en, int64_t W,
+                            double* dee, double* den, hipStream_t st) {
+  const int64_t n = W * (s.N * s.M + s.N * s.N);
+  if (n == 0) return hipSuccess;
+  ProfScope ps("init_dbar_kernel", st);
+  hipLaunchKernelGGL(init_dbar_kernel<S>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, s, x0bar, ee, en, W,
+                     dee, den);
+  return hipGetLastError();
+}
+
+template <typename S>
+hipError_t launch_env_dbar(const SysDev& s, int spin, const double* lbar, const double* ainv, const S* phi,
+                           const S* pi, const S* sg, const double* en, int64_t W, double* den, hipStream_t st) {
+  const int64_t n = W * (spin ? s.ndn : s.nup) * s.M;
+  if (n == 0) return hipSuccess;
+  ProfScope ps("env_dbar_kernel", st);
+  hipLaunchKernelGGL(env_dbar_kernel<S>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, s, spin, lbar, ainv, phi,
+                     pi, sg, en, W, den);
+  return hipGetLastError();
+}
+
+hipError_t launch_positions_bar(const SysDev& s, const double* ee, const double* en, const double* dee,
+                                const double* den, const double* lp, int64_t W, double* out, hipStream_t st) {
+  const int64_t n = W * s.N;
+  if (n == 0) return hipSuccess;
+  ProfScope ps("positions_bar_kernel", st);
+  hipLaunchKernelGGL(positions_bar_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, s, ee, en, dee, den,
+                     lp, W, out);
+  return hipGetLastError();
+}
+
 #define QMC_BWD_INST(S)                                                                                           \
   template hipError_t launch_tanh_bwd<S>(int64_t, const S*, const S*, S*, hipStream_t);                          \
   template hipError_t launch_add<S>(int64_t, const S*, const S*, S*, hipStream_t);                               \
+  template hipError_t launch_pair_dbar<S>(const SysDev&, int, const S*, const double*, const double*, int64_t,    \
+                                          double*, double*, hipStream_t);                                          \
+  template hipError_t launch_init_dbar<S>(const SysDev&, const S*, const double*, const double*, int64_t, double*, \
+                                          double*, hipStream_t);                                                   \
+  template hipError_t launch_env_dbar<S>(const SysDev&, int, const double*, const double*, const S*, const S*,     \
+                                         const S*, const double*, int64_t, double*, hipStream_t);                               \
   template hipError_t launch_cast<S>(int64_t, const double*, S*, hipStream_t);                                   \
   template hipError_t launch_combine_bwd<S>(const SysDev&, const S*, const double*, const double*, const double*, \
                                             int64_t, double*, double*, hipStream_t);                              \

@@ -78,7 +78,7 @@ Workspace workspace_layout(const Plan& p, const SysPlan& s, int op, int64_t wc) 
     cur = align256(cur + bytes);
     return o;
   };
-  const bool jet = (op == QMC_OP_LOCAL_ENERGY || op == QMC_OP_MALA);
+  const bool jet = (op == QMC_OP_LOCAL_ENERGY);
   const size_t E = act_bytes(p.prec);
   const int64_t N = s.N, M = s.M, D = p.ans.width, K = p.ans.n_rbf, ND = p.ans.n_det;
   const int64_t Rp = jet ? s.Rp : 1, Rpe = jet ? 4 : 1;
@@ -106,9 +106,7 @@ Workspace workspace_layout(const Plan& p, const SysPlan& s, int op, int64_t wc) 
     w.lp_prop = alloc(size_t(wc) * (N * 3 + 1) * 8);  // proposal [wc][N][3], then its log|psi| [wc]
   }
   w.jas = alloc(p.ans.jastrow ? size_t(wc) * Rp * E : 0);
-  if (op == QMC_OP_MALA) {
-    w.lp_prop = alloc(size_t(wc) * (2 * N * 3 + 1) * 8);  // proposal, its gradient (both [wc][N][3]), log|psi|
-  }
+
   w.total = cur;
   return w;
 }
@@ -187,12 +185,21 @@ BwdWorkspace bwd_layout(const Plan& p, const SysPlan& s, int64_t wc) {
   b.jzb = alloc(jb);
   b.jfs = alloc(jb);
   b.jgo = alloc(p.ans.jastrow ? size_t(wc) * E : 0);
+  b.dee = alloc(size_t(wc) * N * N * 8);
+  b.den = alloc(size_t(wc) * N * M * 8);
+  b.rhobar = alloc(size_t(wc) * pmax * K * E);
+  b.x0bar = alloc(size_t(wc) * N * F * E);
+  b.ones = alloc(size_t(wc) * 8);
+  b.lpv = alloc(size_t(wc) * 8);
+  b.jval = alloc(size_t(wc) * E);
+  b.prop = alloc(size_t(wc) * (2 * N * 3 + 1) * 8);
   b.total = cur;
   return b;
 }
 
 static size_t sys_bytes(const Plan& p, int op, const SysPlan& s) {
-  return (op == QMC_OP_LOGPSI_VJP || op == QMC_OP_LOSS_GRAD) ? bwd_layout(p, s, s.Wc).total
+  return (op == QMC_OP_LOGPSI_VJP || op == QMC_OP_LOSS_GRAD || op == QMC_OP_LOGPSI_GRAD || op == QMC_OP_MALA)
+             ? bwd_layout(p, s, s.Wc).total
                                                               : workspace_layout(p, s, op, s.Wc).total;
 }
 
@@ -351,7 +358,7 @@ qmc_status qmc_plan_tiles(const qmc_plan* plan, int32_t s, int32_t tiles[4]) {
 }
 
 qmc_status qmc_workspace_size(const qmc_plan* plan, int32_t op, size_t* bytes) {
-  if (!plan || !bytes || op < QMC_OP_LOGPSI || op > QMC_OP_MALA) return QMC_ERR_INVALID_ARGUMENT;
+  if (!plan || !bytes || op < QMC_OP_LOGPSI || op > QMC_OP_LOGPSI_GRAD) return QMC_ERR_INVALID_ARGUMENT;
   *bytes = workspace_bytes(plan->p, op);
   return QMC_OK;
 }

@@ -191,6 +191,20 @@ hipError_t launch_tanh_bwd(int64_t n, const S* ybar, const S* t, S* z, hipStream
 template <typename S>
 hipError_t launch_add(int64_t n, const S* a, const S* b, S* o, hipStream_t st);
 hipError_t launch_fill(int64_t n, double v, double* p, hipStream_t st);
+// Position gradient by the reverse pass: distance cotangents of the edge filters (rhobar [pairs][K]),
+// of the initial features (x0bar [N][(M+2)K] per walker) and of the envelopes, accumulated into
+// dee [W][N][N] (i < j) and den [W][N][M]; then rbar [W][N][3] (with the cusp factor's gradient).
+template <typename S>
+hipError_t launch_pair_dbar(const SysDev& s, int type, const S* rhobar, const double* ee, const double* en, int64_t W,
+                            double* dee, double* den, hipStream_t st);
+template <typename S>
+hipError_t launch_init_dbar(const SysDev& s, const S* x0bar, const double* ee, const double* en, int64_t W,
+                            double* dee, double* den, hipStream_t st);
+template <typename S>
+hipError_t launch_env_dbar(const SysDev& s, int spin, const double* lbar, const double* ainv, const S* phi,
+                           const S* pi, const S* sg, const double* en, int64_t W, double* den, hipStream_t st);
+hipError_t launch_positions_bar(const SysDev& s, const double* ee, const double* en, const double* dee,
+                                const double* den, const double* lp, int64_t W, double* out, hipStream_t st);
 template <typename S>
 hipError_t launch_sgd(int64_t n, double lr, const S* grad, S* params, hipStream_t st);
 template <typename S>

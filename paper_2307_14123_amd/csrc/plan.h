@@ -86,6 +86,10 @@ struct BwdWorkspace {
   size_t gbar, stats, lbar, cpart, phibar[2], pipart, sgpart, fbar, fbar2, zbar, hbar, mbar, wbar[3], ebar, ypart;
   size_t wpart, gacc;
   size_t jsum, jhid, jzb, jfs, jgo;  // Jastrow: summed embeddings, hidden layer, their cotangents, J cotangent
+  // position gradient: distance cotangents (e-e [N][N], e-n [N][M]), radial-basis and initial-feature
+  // cotangents, the unit cotangent, log|psi|, the Jastrow value; Langevin proposals (positions,
+  // their gradient, log|psi|)
+  size_t dee, den, rhobar, x0bar, ones, lpv, jval, prop;
   int64_t wpart_elems;
   int64_t rows_per_split;
   int max_split;

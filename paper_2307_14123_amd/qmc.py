@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libqmc.so")
 
 QMC_FP64, QMC_FP32, QMC_BF16_MIXED = 0, 1, 2
 PRECISIONS = {"fp64": QMC_FP64, "fp32": QMC_FP32, "bf16": QMC_BF16_MIXED}
-OP_LOGPSI, OP_LOCAL_ENERGY, OP_METROPOLIS, OP_LOGPSI_VJP, OP_LOSS_GRAD, OP_MALA = range(6)
+OP_LOGPSI, OP_LOCAL_ENERGY, OP_METROPOLIS, OP_LOGPSI_VJP, OP_LOSS_GRAD, OP_MALA, OP_LOGPSI_GRAD = range(7)
 PLAN_CONCURRENT_SYSTEMS, PLAN_AUTOTUNE = 1, 2
 
 
@@ -63,6 +63,8 @@ def lib():
     L.qmc_local_energy.argtypes = [vp, vp, dp, dp, dp, dp, dp, dp, vp, sz, vp]
     L.qmc_metropolis_step.restype = i32
     L.qmc_metropolis_step.argtypes = [vp, vp, dp, dp, dp, dp, ctypes.c_double, vp, vp, sz, vp]
+    L.qmc_logpsi_grad.restype = i32
+    L.qmc_logpsi_grad.argtypes = [vp, vp, dp, dp, dp, vp, sz, vp]
     L.qmc_mala_step.restype = i32
     L.qmc_mala_step.argtypes = [vp, vp, dp, dp, dp, dp, dp, ctypes.c_double, i32, vp, vp, sz, vp]
     L.qmc_logpsi_vjp.restype = i32
@@ -243,6 +245,16 @@ class Plan:
                                          float(step), _ptr(accepted), _ptr(ws), ws.numel(), _stream()),
                "qmc_metropolis_step")
         return accepted
+
+    def logpsi_grad(self, params, r):
+        """log|psi| [W] and its gradient over the positions [W*N*3] by one reverse pass (no Laplacian)."""
+        self._check_inputs(params, r)
+        lp = torch.empty(self.total_walkers, dtype=torch.float64, device=r.device)
+        g = torch.empty(self.total_positions, dtype=torch.float64, device=r.device)
+        ws = self.workspace(OP_LOGPSI_GRAD)
+        _check(lib().qmc_logpsi_grad(self.handle, _ptr(params), _ptr(r), _ptr(lp), _ptr(g), _ptr(ws), ws.numel(),
+                                     _stream()), "qmc_logpsi_grad")
+        return lp, g
 
     def mala_step(self, params, r, logpsi, grad, noise, u, step, damp=True, accepted=None):
         """One Langevin step, in place on r, logpsi and grad (grad log|psi| of the current state, e.g.

@@ -2,7 +2,8 @@
 
 Replay parity: both sides start each step from the GPU's state; acceptance decisions must agree
 except where |log u - log a| is below a margin set by the precision; for agreeing walkers the
-positions, log|psi| and gradients must match.  H2 (256 walkers of the small workload) and the
+positions, log|psi| and gradients must match.  The gradient at the proposal comes from the reverse
+pass (qmc_logpsi_grad's path).  H2 (256 walkers of the small workload) and the
 N2-sized ansatz on a walker subset, with and without the drift damping near nuclei.
 """
 import numpy as np
@@ -83,6 +84,9 @@ def test_mala_replay_n2_subset_fp32():
 
 
 def test_mala_zero_step_keeps_state():
+    """step = 0 proposes the current positions: every walker accepts, the positions keep every bit,
+    and log|psi| and the gradient become those of the reverse pass at the same positions (equal to
+    the jet forward's to rounding)."""
     s, a, p, r = qi.workload_inputs(0, 16)
     q = _q()
     plan = q.Plan([s], [16], a, "fp64")
@@ -91,8 +95,11 @@ def test_mala_zero_step_keeps_state():
     lp, G = out["logpsi"].clone(), out["grad"].clone()
     g_before, lp_before = host(G).copy(), host(lp).copy()
     acc = plan.mala_step(P, R, lp, G, dev(np.ones((16, 2, 3))), dev(np.full(16, 0.5)), 0.0)
+    lp_rev, g_rev = plan.logpsi_grad(P, R)
     torch.cuda.synchronize()
     assert np.all(host(acc) == 1)
     np.testing.assert_array_equal(host(R).reshape(r.shape), r)
-    np.testing.assert_array_equal(host(G), g_before)
-    np.testing.assert_array_equal(host(lp), lp_before)
+    np.testing.assert_array_equal(host(G), host(g_rev))
+    np.testing.assert_array_equal(host(lp), host(lp_rev))
+    np.testing.assert_allclose(host(G), g_before, rtol=1e-10, atol=1e-10)
+    np.testing.assert_allclose(host(lp), lp_before, rtol=1e-12, atol=1e-12)
