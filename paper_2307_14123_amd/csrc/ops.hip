@@ -916,11 +916,16 @@ __global__ __launch_bounds__(256) void det_kernel(const S* __restrict__ src, int
   int cp = r;        // column this lane was pivot for
   double logdet = 0.0, sgn = 1.0;
   bool singular = false;
+  // one elimination step for column col; every array index is a compile-time constant once the
+  // loops over c are unrolled, so the rows stay in registers even where the loop over col is not
+  // unrolled (32-lane groups)
+  auto eliminate = [&](int col) {
+    double acol = 0.0;
 #pragma unroll
-  for (int col = 0; col < G; ++col) {
-    if (col >= n) break;
+    for (int c = 0; c < G; ++c)
+      if (c == col) acol = a[c];
     // pivot: largest |a[col]| over the unused rows (NaN counts as largest; smallest row on ties)
-    double key = used ? -1.0 : (a[col] != a[col] ? INFINITY : fabs(a[col]));
+    double key = used ? -1.0 : (acol != acol ? INFINITY : fabs(acol));
     int idx = r;
 #pragma unroll
     for (int off = 1; off < G; off <<= 1) {
@@ -932,38 +937,91 @@ __global__ __launch_bounds__(256) void det_kernel(const S* __restrict__ src, int
       }
     }
     if (!(key > 0.0)) singular = true;
-    const double pv = __shfl(a[col], base + idx);
+    const double pv = __shfl(acol, base + idx);
     const double pvs = key > 0.0 ? pv : 1.0;
     logdet += log(fabs(pv));
     if (pv < 0) sgn = -sgn;
     const double rinv = 1.0 / pvs;
     const bool me = r == idx;
-    double prow[G], pvrow[G];
+    // Gauss-Jordan eliminates every other row, LU only the rows below (the unused ones); the pivot
+    // row's entries arrive one column at a time, so no copy of the row is held
+    const bool upd = !me && (INV || !used);
+    const double f = acol * rinv;
 #pragma unroll
-    for (int c = col + 1; c < G; ++c) prow[c] = __shfl(a[c], base + idx);
+    for (int c = 0; c < G; ++c) {
+      const double pc = __shfl(a[c], base + idx);
+      if (c > col) {
+        if (me) {
+          if (INV) a[c] *= rinv;
+        } else if (upd) {
+          a[c] -= f * pc;
+        }
+      }
+    }
     if (INV) {
 #pragma unroll
-      for (int c = 0; c < G; ++c) pvrow[c] = __shfl(v[c], base + idx);
+      for (int c = 0; c < G; ++c) {
+        const double pc = __shfl(v[c], base + idx);
+        v[c] = me ? v[c] * rinv : v[c] - f * pc;
+      }
     }
     if (me) {
       used = true;
       cp = col;
-      if (INV) {
+    }
+  };
+  if constexpr (G <= 16) {
 #pragma unroll
-        for (int c = col + 1; c < G; ++c) a[c] *= rinv;
+    for (int col = 0; col < G; ++col) {
+      if (col >= n) break;
+      // pivot: largest |a[col]| over the unused rows (NaN counts as largest; smallest row on ties)
+      double key = used ? -1.0 : (a[col] != a[col] ? INFINITY : fabs(a[col]));
+      int idx = r;
 #pragma unroll
-        for (int c = 0; c < G; ++c) v[c] *= rinv;
+      for (int off = 1; off < G; off <<= 1) {
+        const double ok = __shfl_xor(key, off);
+        const int oid = __shfl_xor(idx, off);
+        if (ok > key || (ok == key && oid < idx)) {
+          key = ok;
+          idx = oid;
+        }
       }
-    } else if (INV || !used) {
-      // Gauss-Jordan eliminates every other row, LU only the rows below (the unused ones)
-      const double f = a[col] * rinv;
+      if (!(key > 0.0)) singular = true;
+      const double pv = __shfl(a[col], base + idx);
+      const double pvs = key > 0.0 ? pv : 1.0;
+      logdet += log(fabs(pv));
+      if (pv < 0) sgn = -sgn;
+      const double rinv = 1.0 / pvs;
+      const bool me = r == idx;
+      double prow[G], pvrow[G];
 #pragma unroll
-      for (int c = col + 1; c < G; ++c) a[c] -= f * prow[c];
+      for (int c = col + 1; c < G; ++c) prow[c] = __shfl(a[c], base + idx);
       if (INV) {
 #pragma unroll
-        for (int c = 0; c < G; ++c) v[c] -= f * pvrow[c];
+        for (int c = 0; c < G; ++c) pvrow[c] = __shfl(v[c], base + idx);
+      }
+      if (me) {
+        used = true;
+        cp = col;
+        if (INV) {
+#pragma unroll
+          for (int c = col + 1; c < G; ++c) a[c] *= rinv;
+#pragma unroll
+          for (int c = 0; c < G; ++c) v[c] *= rinv;
+        }
+      } else if (INV || !used) {
+        // Gauss-Jordan eliminates every other row, LU only the rows below (the unused ones)
+        const double f = a[col] * rinv;
+#pragma unroll
+        for (int c = col + 1; c < G; ++c) a[c] -= f * prow[c];
+        if (INV) {
+#pragma unroll
+          for (int c = 0; c < G; ++c) v[c] -= f * pvrow[c];
+        }
       }
     }
+  } else {
+    for (int col = 0; col < n; ++col) eliminate(col);
   }
   // sign of the permutation row -> column: parity of its inversions
   int inv_cnt = 0;
