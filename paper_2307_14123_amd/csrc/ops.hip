@@ -732,6 +732,7 @@ hipError_t launch_aggregate(const SysDev& s, const S* h, const S* wsame, const S
     if (ns <= 16) return agg_launch<S, 16>(s, h, wsame, wopp, ee, W, m, st);
   if (ns <= 16) return agg_lds_launch<S, 16>(s, h, wsame, wopp, ee, W, m, st);
   if (ns <= 24) return agg_lds_launch<S, 24>(s, h, wsame, wopp, ee, W, m, st);
+  if (ns <= 32) return agg_lds_launch<S, 32>(s, h, wsame, wopp, ee, W, m, st);
   return hipErrorInvalidValue;
 }
 

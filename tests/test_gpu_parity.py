@@ -99,7 +99,7 @@ def test_small_molecule_ragged_fp64():
     _compare_fp64("ragged fp64 37", s, a, p, r)
 
 
-@pytest.mark.parametrize("n_up,n_down", [(10, 9), (9, 2), (17, 3)])
+@pytest.mark.parametrize("n_up,n_down", [(10, 9), (9, 2), (17, 3), (26, 3)])
 def test_large_spin_blocks_fp64(n_up, n_down):
     """More than 8 electrons in a spin block (balanced and strongly polarised): the message
     aggregation stages the senders' rows in LDS instead of holding one receiver group per thread,
