@@ -164,3 +164,35 @@ def test_sgd_update_rejects_bad_arguments():
     assert L.qmc_sgd_update(1, p, p, 10, float("nan"), None) == 1
     assert L.qmc_sgd_update(7, p, p, 10, 1e-3, None) == 1
     assert L.qmc_sgd_update(1, None, None, 0, 1e-3, None) == 0
+
+
+def test_ansatz_options_count_and_limits():
+    """Parameter counts with the Jastrow and full-determinant options match the blob layout; invalid
+    option values and a full determinant above 32 electrons are rejected."""
+    import dataclasses
+    qmc, L = _lib()
+    for s in (qi.N2, qi.C4H4, qi.System((3.0, 1.0), ((0.0, 0.0, 0.0), (1.6, 0.2, -0.3)), 3, 1)):
+        for opts in ({"jastrow": 1}, {"full_det": 1}, {"jastrow": 1, "full_det": 1, "ee_cusp": 0.5}):
+            a = dataclasses.replace(qi.N2_ANSATZ, **opts)
+            assert qmc.param_count(s, a) == qi.param_count(s, a)
+    h = qmc._SysHolder(qi.N2)
+    for opts in ({"jastrow": 2}, {"full_det": -1}, {"ee_cusp": -1.0}, {"ee_cusp": float("inf")}):
+        a = qmc.make_ansatz(dataclasses.replace(qi.N2_ANSATZ, **opts))
+        assert L.qmc_param_count(ctypes.byref(h.s), ctypes.byref(a)) < 0
+    big = qi.atom(33)
+    hb = qmc._SysHolder(big)
+    arr = (qmc.QmcSystem * 1)(hb.s)
+    W = (ctypes.c_int64 * 1)(4)
+    handle = ctypes.c_void_p()
+    a = qmc.make_ansatz(dataclasses.replace(qi.N2_ANSATZ, full_det=1))
+    assert L.qmc_plan_create(ctypes.byref(handle), arr, 1, W, ctypes.byref(a), 1, 0) == 2
+    a = qmc.make_ansatz(qi.N2_ANSATZ)
+    assert L.qmc_plan_create(ctypes.byref(handle), arr, 1, W, ctypes.byref(a), 1, 0) == 0
+    try:
+        sz = ctypes.c_size_t()
+        assert L.qmc_workspace_size(handle, 6, ctypes.byref(sz)) == 0 and sz.value > 0
+        fake = ctypes.c_void_p(0x1000)
+        assert L.qmc_logpsi_grad(handle, fake, fake, None, fake, ctypes.c_void_p(0x10000), sz.value, None) == 1
+        assert L.qmc_logpsi_grad(handle, fake, fake, fake, fake, ctypes.c_void_p(0x10000), 16, None) == 3
+    finally:
+        assert L.qmc_plan_destroy(handle) == 0
