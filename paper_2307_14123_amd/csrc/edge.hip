@@ -1,4 +1,4 @@
-// Fused edge filters on MFMA (float32, width 128, at most 16 radial basis
+// Fused edge filters on MFMA (float32, width 128 or 256, at most 16 radial basis
 // functions): for every pair of one edge type,
 //   w(d) = tanh(rho(d) U1 + a1) U2 + a2,
 // from the pair distance to the filter row in one kernel, as a value row or
@@ -16,7 +16,9 @@
 //
 // A persistent grid keeps U2 (transposed, 16-byte chunks XOR-swizzled by row
 // against LDS bank conflicts) and U1, a1, a2 in LDS, one copy per block of 12
-// waves (three per SIMD); each wave takes 16 pair rows at a time.  The radial
+// waves (three per SIMD); each wave takes 16 pair rows at a time.  A launch
+// writes 128 output columns from c0 on: width 256 takes two launches, each
+// recomputing the 256 hidden units (the half of U2 it needs fills 128 KB of LDS).  The radial
 // basis is evaluated in float64 and rounded, as in the separate basis kernel;
 // tanh is the float32 form of act.h.
 #include <algorithm>
@@ -30,29 +32,28 @@ namespace qmc {
 
 typedef float f4 __attribute__((ext_vector_type(4)));
 
-constexpr int ED = 128;  // filter width handled here
+constexpr int ED = 128;  // output columns per launch
 
-template <int JET, int NW>
-__global__ __launch_bounds__(64 * NW) void edge_mlp_kernel(SysDev s, EdgeMlpArgs a) {
-  __shared__ __attribute__((aligned(16))) float u2t[ED * ED];  // U2^T (n, k), chunk (k/4) ^ (n & 7)
-  __shared__ __attribute__((aligned(16))) float u1t[ED * 16];  // U1^T (k, r), r < 16
-  __shared__ float a1s[ED], a2s[ED];
+// EH: hidden (and full output) width, 128 or 256; c0: first output column of this launch
+template <int JET, int NW, int EH>
+__global__ __launch_bounds__(64 * NW) void edge_mlp_kernel(SysDev s, EdgeMlpArgs a, int c0) {
+  __shared__ __attribute__((aligned(16))) float u2t[ED * EH];  // U2^T (n, k), chunk (k/4) ^ (n & 7)
+  __shared__ __attribute__((aligned(16))) float u1t[EH * 16];  // U1^T (k, r), r < 16
+  __shared__ float a1s[EH], a2s[ED];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int g = lane >> 4, c = lane & 15;
   const int K = s.K;
   const double rs = rbf_spacing(s.dmax, K), ris = (K - 1) / s.dmax;
-  for (int e = tid; e < ED * ED; e += 64 * NW) {
+  for (int e = tid; e < ED * EH; e += 64 * NW) {
     const int k = e / ED, n = e - k * ED;
-    u2t[n * ED + (((k >> 2) ^ (n & 7)) << 2) + (k & 3)] = a.U2[e];
+    u2t[n * EH + (((k >> 2) ^ (n & 7)) << 2) + (k & 3)] = a.U2[(int64_t)k * EH + c0 + n];
   }
-  for (int e = tid; e < ED * 16; e += 64 * NW) {
+  for (int e = tid; e < EH * 16; e += 64 * NW) {
     const int k = e >> 4, r = e & 15;
-    u1t[e] = r < K ? a.U1[r * ED + k] : 0.f;
+    u1t[e] = r < K ? a.U1[r * EH + k] : 0.f;
   }
-  for (int e = tid; e < ED; e += 64 * NW) {
-    a1s[e] = a.a1[e];
-    a2s[e] = a.a2[e];
-  }
+  for (int e = tid; e < EH; e += 64 * NW) a1s[e] = a.a1[e];
+  for (int e = tid; e < ED; e += 64 * NW) a2s[e] = a.a2[c0 + e];
   __syncthreads();
 
   const int P = a.type == 0 ? s.P0 : (a.type == 1 ? s.P1 : s.P2);
@@ -85,9 +86,9 @@ __global__ __launch_bounds__(64 * NW) void edge_mlp_kernel(SysDev s, EdgeMlpArgs
     }
     const float bias_in = (g == 0 && e == 0) ? 1.f : 0.f;  // constant basis function of the value row
     // ---- first layer: z^T blocks of 16 hidden units
-    f4 z[ED / 16];
+    f4 z[EH / 16];
 #pragma unroll
-    for (int hb = 0; hb < ED / 16; ++hb) {
+    for (int hb = 0; hb < EH / 16; ++hb) {
       f4 acc = {0.f, 0.f, 0.f, 0.f};
       const f4 ua = *(const f4*)&u1t[(16 * hb + c) * 16 + 4 * g];
       acc = __builtin_amdgcn_mfma_f32_16x16x4f32(ua.x, rb[0], acc, 0, 0, 0);
@@ -100,7 +101,7 @@ __global__ __launch_bounds__(64 * NW) void edge_mlp_kernel(SysDev s, EdgeMlpArgs
     // ---- tanh (through the jet of a pair's three rows); the idle row 15 borrows pair 4's lanes
     const int qbase = (lane & 48) + 3 * (pc < 4 ? pc : 4);  // lane of row 0 of this lane's pair
 #pragma unroll
-    for (int hb = 0; hb < ED / 16; ++hb)
+    for (int hb = 0; hb < EH / 16; ++hb)
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const float zi = z[hb][i];
@@ -112,9 +113,9 @@ __global__ __launch_bounds__(64 * NW) void edge_mlp_kernel(SysDev s, EdgeMlpArgs
           z[hb][i] = tanh_f32(zi);
         }
       }
-    if (!JET && a.zout && rowok) {
+    if (!JET && a.zout && rowok && c0 == 0) {
 #pragma unroll
-      for (int hb = 0; hb < ED / 16; ++hb) *(f4*)&a.zout[pr * ED + 16 * hb + 4 * g] = z[hb];
+      for (int hb = 0; hb < EH / 16; ++hb) *(f4*)&a.zout[pr * EH + 16 * hb + 4 * g] = z[hb];
     }
     // ---- second layer, two 16-column blocks at a time
 #pragma unroll 1
@@ -122,10 +123,10 @@ __global__ __launch_bounds__(64 * NW) void edge_mlp_kernel(SysDev s, EdgeMlpArgs
       f4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
       const int n0 = 16 * nb + c, n1 = n0 + 16;
 #pragma unroll
-      for (int hb = 0; hb < ED / 16; ++hb) {
+      for (int hb = 0; hb < EH / 16; ++hb) {
         const int ch = 4 * hb + g;
-        const f4 b0 = *(const f4*)&u2t[n0 * ED + ((ch ^ (n0 & 7)) << 2)];
-        const f4 b1 = *(const f4*)&u2t[n1 * ED + ((ch ^ (n1 & 7)) << 2)];
+        const f4 b0 = *(const f4*)&u2t[n0 * EH + ((ch ^ (n0 & 7)) << 2)];
+        const f4 b1 = *(const f4*)&u2t[n1 * EH + ((ch ^ (n1 & 7)) << 2)];
         acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(z[hb][0], b0.x, acc0, 0, 0, 0);
         acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(z[hb][0], b1.x, acc1, 0, 0, 0);
         acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(z[hb][1], b0.y, acc0, 0, 0, 0);
@@ -144,14 +145,14 @@ __global__ __launch_bounds__(64 * NW) void edge_mlp_kernel(SysDev s, EdgeMlpArgs
         const int64_t op = p0 + rp;
         if ((JET && r == 15) || op >= a.pairs) continue;
         const int64_t orow = JET ? op * 4 + re : op;
-        a.out[orow * ED + n0] = acc0[i] + (re == 0 ? a2s[n0] : 0.f);
-        a.out[orow * ED + n1] = acc1[i] + (re == 0 ? a2s[n1] : 0.f);
+        a.out[orow * EH + c0 + n0] = acc0[i] + (re == 0 ? a2s[n0] : 0.f);
+        a.out[orow * EH + c0 + n1] = acc1[i] + (re == 0 ? a2s[n1] : 0.f);
       }
     }
   }
 }
 
-bool edge_mlp_supported(const SysDev& s) { return s.D == ED && s.K >= 2 && s.K <= 16; }
+bool edge_mlp_supported(const SysDev& s) { return (s.D == 128 || s.D == 256) && s.K >= 2 && s.K <= 16; }
 
 hipError_t launch_edge_mlp(const SysDev& s, const EdgeMlpArgs& a, hipStream_t st) {
   if (!edge_mlp_supported(s) || a.pairs < 0 || a.type < 0 || a.type > 2) return hipErrorInvalidValue;
@@ -172,23 +173,31 @@ hipError_t launch_edge_mlp(const SysDev& s, const EdgeMlpArgs& a, hipStream_t st
   const int64_t tiles = a.jet ? (a.pairs + 4) / 5 : (a.pairs + 15) / 16;
   // blocks of nw waves share one copy of the weights in LDS (73 KB); as many blocks as fit per
   // compute unit, each walking tiles with a grid stride
-  auto go = [&](auto kern, int w) {
+  auto go = [&](auto kern, int w, int c0) {
     int occ = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, 64 * w, 0) != hipSuccess || occ < 1) occ = 1;
     const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>((tiles + w - 1) / w, (int64_t)occ * cus));
-    hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(64 * w), 0, st, s, a);
+    hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(64 * w), 0, st, s, a, c0);
   };
   ProfScope ps(a.jet ? "edge_mlp_kernel<jet>" : "edge_mlp_kernel<val>", st);
-  if (a.jet) {
+  if (s.D == 256) {
+    // the 256 hidden units take 64 more registers: two waves per SIMD
+    for (int c0 = 0; c0 < 256; c0 += ED) {
+      if (a.jet)
+        go(edge_mlp_kernel<1, 8, 256>, 8, c0);
+      else
+        go(edge_mlp_kernel<0, 8, 256>, 8, c0);
+    }
+  } else if (a.jet) {
     if (nw == 4)
-      go(edge_mlp_kernel<1, 4>, 4);
+      go(edge_mlp_kernel<1, 4, 128>, 4, 0);
     else
-      go(edge_mlp_kernel<1, 12>, 12);
+      go(edge_mlp_kernel<1, 12, 128>, 12, 0);
   } else {
     if (nw == 4)
-      go(edge_mlp_kernel<0, 4>, 4);
+      go(edge_mlp_kernel<0, 4, 128>, 4, 0);
     else
-      go(edge_mlp_kernel<0, 12>, 12);
+      go(edge_mlp_kernel<0, 12, 128>, 12, 0);
   }
   return hipGetLastError();
 }

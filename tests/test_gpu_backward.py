@@ -114,6 +114,27 @@ def test_loss_grad_fp32_n2():
     assert worst[0] < 2e-2
 
 
+def test_loss_grad_fp32_width256():
+    """Width 256 (the C4H4-sized ansatz): the fused edge filters run in two column halves, and the
+    backward reads their stashed 256-unit hidden layer; same bounds as the width-128 case."""
+    s, a, p, r = qi.workload_inputs(3, 8)
+    q = _q()
+    plan = q.Plan([s], [8], a, "fp32")
+    P, R = dev(p, torch.float32), dev(r)
+    e = plan.local_energy(P, R)["e_loc"]
+    g, _ = plan.loss_grad(P, R, e)
+    torch.cuda.synchronize()
+    p32 = p.astype(np.float32).astype(np.float64)
+    Gref, _, _ = oracle.loss_grad(r, host(e), p32, s, a)
+    got = host(g).astype(np.float64)
+    err = _normwise(got, Gref)
+    gb, rb = unpack(got, s, a), unpack(Gref, s, a)
+    floor = 1e-3 * np.linalg.norm(Gref)
+    worst = max((np.linalg.norm(gb[k] - rb[k]) / max(np.linalg.norm(rb[k]), floor), k) for k in rb)
+    print(f"[loss grad c4h4 fp32] normwise {err:.3e}, worst tensor {worst[1]}: {worst[0]:.3e}", flush=True)
+    assert err < 2e-3 and worst[0] < 2e-2
+
+
 def test_loss_grad_zero_variance_hydrogen():
     H = qi.System((1.0,), ((0.0, 0.0, 0.0),), 1, 0)
     a = qi.Ansatz(n_rbf=6, rbf_dmax=6.0, init_layers=1, width=12, mp_layers=1, n_det=2, n_env=2)
