@@ -171,7 +171,7 @@ def main():
     ap.add_argument("--walkers", type=int, default=None)
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64", "bf16"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-walkers", type=int, default=96)
+    ap.add_argument("--cpu-walkers", type=int, default=160)
     ap.add_argument("--jastrow", action="store_true", help="add the learnable Jastrow factor to the ansatz")
     ap.add_argument("--ee-cusp", type=float, default=0.0, help="alpha of the electron-electron cusp factor (0: none)")
     ap.add_argument("--full-det", action="store_true", help="one N x N determinant per p over both spins")
@@ -456,21 +456,46 @@ def main():
         import oracle
         torch.set_num_threads(os.cpu_count() or 1)
         nw = min(args.cpu_walkers, W) if args.workload == "n2" else min(8, W)
-        rs = r0[:nw].copy()
-        t0 = time.perf_counter()
-        lp_c = oracle.logpsi_np(rs, P.double().cpu().numpy(), s, a)[1]
-        pc = P.double().cpu().numpy()
-        for t in range(n_mc):
-            rs, lp_c, _, _ = oracle.metropolis_step(rs, lp_c, noise[t, :nw], uni[t, :nw], tau, pc, s, a)
-        ref = oracle.local_energy(rs, pc, s, a, chunk=16)
-        if has_grad:
-            gc = oracle.loss_grad(rs, oracle.clip_local_energy(ref["e_loc"], clip_width, "hard"), pc, s, a)[0]
-            pc_next = pc - lr * gc  # the gradient-descent update of the step
-        tc = time.perf_counter() - t0
+        pc = P_init.double().cpu().numpy()
+
+        def cpu_step(nw_):
+            """the step on the first nw_ walkers with the float64 oracle; (positions, E_L dict, part times)"""
+            rs_ = r0[:nw_].copy()
+            t = [time.perf_counter()]
+            lp_c = oracle.logpsi_np(rs_, pc, s, a)[1]
+            for tt in range(n_mc):
+                rs_, lp_c, _, _ = oracle.metropolis_step(rs_, lp_c, noise[tt, :nw_], uni[tt, :nw_], tau, pc, s, a)
+            t.append(time.perf_counter())
+            ref_ = oracle.local_energy(rs_, pc, s, a, chunk=16)
+            t.append(time.perf_counter())
+            if has_grad:
+                gc = oracle.loss_grad(rs_, oracle.clip_local_energy(ref_["e_loc"], clip_width, "hard"), pc, s, a)[0]
+                _ = pc - lr * gc  # the gradient-descent update of the step
+            t.append(time.perf_counter())
+            return rs_, ref_, [t[1] - t[0], t[2] - t[1], t[3] - t[2]]
+
+        rs, ref, parts = cpu_step(nw)
+        tc = sum(parts)
+        try:
+            with open("/proc/cpuinfo") as f:
+                cpu_model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), None)
+        except OSError:
+            cpu_model = None
         res["cpu_baseline"] = {"value": nw / tc, "unit": "walkers/s", "cores": torch.get_num_threads(),
                                "kind": "oracle",
                                "sample": f"{nw} of the {W} walkers through the same step (float64 CPU oracle: "
-                                         f"serial autograd Laplacian), {tc:.1f} s"}
+                                         f"serial autograd Laplacian), {tc:.1f} s",
+                               "cpu_model": cpu_model, "os_cpu_count": os.cpu_count(),
+                               "e_loc_per_s": nw / parts[1], "metropolis_10_steps_s": parts[0],
+                               "loss_grad_s": parts[2]}
+        # the same oracle on one thread, on a smaller sample
+        torch.set_num_threads(1)
+        n1 = min(8, nw)
+        _, _, parts1 = cpu_step(n1)
+        torch.set_num_threads(os.cpu_count() or 1)
+        res["cpu_baseline_1thread"] = {"value": n1 / sum(parts1), "unit": "walkers/s", "cores": 1,
+                                       "e_loc_per_s": n1 / parts1[1],
+                                       "sample": f"{n1} walkers, {sum(parts1):.1f} s"}
         # error of the GPU local energy on the same sample positions
         Rs = torch.as_tensor(rs, device=dev).contiguous()
         sub = qmc.Plan([s], [nw], a, args.precision)
