@@ -150,7 +150,7 @@ static qmc_status forward_chunk(const Plan& P, const SysPlan& s, const S* prm, c
   const ParamOffsets& O = s.off;
 
   CK(launch_geometry(dv, r, wc, ee, en, jet ? vpot : nullptr, st));
-  // float32 plans of width 128 evaluate each edge filter in one fused kernel from the distances
+  // float32 plans of width 128 or 256 evaluate each edge filter in one fused kernel from the distances
   const bool fused = std::is_same<S, float>::value && P.prec == QMC_FP32 && edge_mlp_supported(dv);
   if (P.ans.mp_layers > 0 && !fused)
     for (int t = 0; t < 3; ++t) CK(launch_rbf<S>(dv, t, ee, en, wc, jet, rho[t], st));
