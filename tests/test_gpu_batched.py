@@ -71,6 +71,37 @@ def test_concurrent_matches_sequential_bitwise():
     print(f"[concurrent vs sequential] {len(mols)} molecules, {W} walkers: bitwise equal", flush=True)
 
 
+def test_concurrent_langevin_and_gradient_bitwise():
+    """The reverse-pass gradient and a Langevin step over a concurrent plan equal the same calls on
+    one plan per molecule (each molecule's walkers and outputs at its offsets)."""
+    targets, walkers = [4, 9, 14], [12, 20, 8]
+    mols, a, params, pos = _batch(targets, walkers)
+    q = _q()
+    con = q.Plan(mols, walkers, a, "fp32", concurrent=True)
+    P, R = dev(_cat(params), torch.float32), dev(_cat(pos))
+    lp, g = con.logpsi_grad(P, R)
+    W = sum(walkers)
+    noise = np.random.default_rng(903).standard_normal(R.numel())
+    u = np.random.default_rng(904).random(W)
+    R2, lp2, g2 = R.clone(), lp.clone(), g.clone()
+    acc = con.mala_step(P, R2, lp2, g2, dev(noise), dev(u), 0.1)
+    torch.cuda.synchronize()
+    w0, x0 = 0, 0
+    for m, p, r, w in zip(mols, params, pos, walkers):
+        one = q.Plan([m], [w], a, "fp32")
+        Pm, Rm = dev(p, torch.float32), dev(r)
+        lpm, gm = one.logpsi_grad(Pm, Rm)
+        n3 = w * m.n_elec * 3
+        accm = one.mala_step(Pm, Rm, lpm, gm, dev(noise[x0:x0 + n3]), dev(u[w0:w0 + w]), 0.1)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(host(acc)[w0:w0 + w], host(accm))
+        np.testing.assert_array_equal(host(R2)[x0:x0 + n3], host(Rm).ravel())
+        np.testing.assert_array_equal(host(lp2)[w0:w0 + w], host(lpm))
+        np.testing.assert_array_equal(host(g2)[x0:x0 + n3], host(gm))
+        w0 += w
+        x0 += n3
+
+
 def test_concurrent_fp64_matches_oracle():
     targets, walkers = [4, 9], [6, 5]
     mols, a, params, pos = _batch(targets, walkers)
