@@ -643,10 +643,12 @@ hipError_t launch_combine_bwd(const SysDev& s, const S* c, const double* ld, con
 // phi_bar = A_bar * env (written per electron row), and the envelope weights
 // and exponents collect env_bar * exp(-sigma d) and -env_bar * pi * d * exp(-sigma d).
 template <typename S>
-__global__ void orb_bwd_kernel(SysDev s, int spin, const double* __restrict__ lbar, const double* __restrict__ ainv,
-                               const S* __restrict__ phi, const S* __restrict__ pi, const S* __restrict__ sg,
-                               const double* __restrict__ en, int64_t W, S* __restrict__ phibar,
-                               double* __restrict__ pipart, double* __restrict__ sgpart) {
+__global__ __launch_bounds__(128) void orb_bwd_kernel(SysDev s, int spin, const double* __restrict__ lbar,
+                                                     const double* __restrict__ ainv, const S* __restrict__ phi,
+                                                     const S* __restrict__ pi, const S* __restrict__ sg,
+                                                     const double* __restrict__ en, int64_t W,
+                                                     S* __restrict__ phibar, double* __restrict__ pipart,
+                                                     double* __restrict__ sgpart) {
   // envelope values in the plan's activation type (as in the forward); sums in float64
   using T = S;
   // n electrons of this spin, no orbitals per determinant, matrices of order dim with this spin's
@@ -666,33 +668,41 @@ __global__ void orb_bwd_kernel(SysDev s, int spin, const double* __restrict__ lb
   const S* phw = phi + (w * n) * (int64_t)ncol + p * no + k;           // row a: phw[a * ncol]
   const S* pik = pi + ((int64_t)p * no + k) * s.M * s.nenv;
   const S* sgk = sg + ((int64_t)p * no + k) * s.M * s.nenv;
-  // phi_bar = Abar * env, with Abar = lbar A^-T
-  for (int a = 0; a < n; ++a) {
-    const double* g = gw + a * s.M * 4;
-    T env = 0;
-    for (int I = 0; I < s.M; ++I) {
-      const T d = (T)g[I * 4];
-      for (int b = 0; b < s.nenv; ++b) env += pik[I * s.nenv + b] * exp(-sgk[I * s.nenv + b] * d);
-    }
-    phibar[(w * n + a) * (int64_t)ncol + p * no + k] = (S)(lb * Ai[k * dim + row0 + a] * (double)env);
+  // One pass over (nucleus, exponent), each exponential evaluated once per electron: it feeds the
+  // envelope of electron a (for phi_bar = Abar * env, Abar = lbar A^-T) and the pi_bar, sigma_bar
+  // sums over the electrons of the spin block.  The spin block has at most 32 electrons (the
+  // determinant limit), so its per-electron values stay in registers.
+  constexpr int AMAX = 32;
+  double eba[AMAX];
+  T enva[AMAX];
+#pragma unroll
+  for (int a = 0; a < AMAX; ++a) {
+    enva[a] = 0;
+    eba[a] = a < n ? lb * Ai[k * dim + row0 + a] * (double)phw[(int64_t)a * ncol] : 0.0;
   }
-  // pi_bar and sigma_bar of every (nucleus, exponent): sums over the electrons of the spin block
   double* pp = pipart + t * (int64_t)(s.M * s.nenv);
   double* sp = sgpart + t * (int64_t)(s.M * s.nenv);
   for (int I = 0; I < s.M; ++I)
     for (int b = 0; b < s.nenv; ++b) {
       const T pw = pik[I * s.nenv + b], sgm = sgk[I * s.nenv + b];
       double ap = 0.0, as = 0.0;
-      for (int a = 0; a < n; ++a) {
-        const T d = (T)gw[a * s.M * 4 + I * 4];
-        const double eb = lb * Ai[k * dim + row0 + a] * (double)phw[(int64_t)a * ncol];
-        const double ex = (double)exp(-sgm * d);
-        ap += eb * ex;
-        as -= eb * (double)pw * (double)d * ex;
+#pragma unroll
+      for (int a = 0; a < AMAX; ++a) {
+        if (a < n) {
+          const T d = (T)gw[a * s.M * 4 + I * 4];
+          const T e = exp(-sgm * d);
+          enva[a] += pw * e;
+          const double ex = (double)e;
+          ap += eba[a] * ex;
+          as -= eba[a] * (double)pw * (double)d * ex;
+        }
       }
       pp[I * s.nenv + b] = ap;
       sp[I * s.nenv + b] = as;
     }
+#pragma unroll
+  for (int a = 0; a < AMAX; ++a)
+    if (a < n) phibar[(w * n + a) * (int64_t)ncol + p * no + k] = (S)(lb * Ai[k * dim + row0 + a] * (double)enva[a]);
 }
 
 template <typename S>
