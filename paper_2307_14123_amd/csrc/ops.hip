@@ -603,20 +603,22 @@ hipError_t launch_nuc_message(const SysDev& s, const S* wnuc, const S* Y, const 
   return hipGetLastError();
 }
 
-// Value rows only (log|psi| without derivatives).  Block: one walker.  The
-// senders' features are staged in LDS (when they fit) with a table of pair
-// indices and types; each thread produces (receiver, column) outputs, so the
-// filter values are read once per ordered pair with consecutive columns.
+// Value rows only (log|psi| without derivatives).  Block: one walker, or for walkers of more than
+// 2048 (receiver, column) outputs a chunk of 1024 of them, so that large walkers spread over several
+// blocks (more loads in flight).  The senders' features are staged in LDS (when they fit) with a table of pair
+// indices and types; each thread produces (receiver, column) outputs, so the filter values are
+// read once per ordered pair with consecutive columns.
 template <typename S>
 __global__ __launch_bounds__(256) void aggregate_value_kernel(SysDev s, const S* __restrict__ h,
                                                               const S* __restrict__ wsame,
                                                               const S* __restrict__ wopp,
                                                               const S* __restrict__ wnuc,
-                                                              const S* __restrict__ Y, int stage,
-                                                              S* __restrict__ m) {
+                                                              const S* __restrict__ Y, int stage, int nck,
+                                                              int cs, S* __restrict__ m) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int N = s.N, D = s.D, M = s.M;
-  const int64_t w = blockIdx.x;
+  const int64_t w = blockIdx.x / nck;
+  const int ck = (int)(blockIdx.x - w * nck);
   constexpr int OPP = 1 << 30;
   int* po = (int*)smem;               // [N][N]: pair index, | OPP for an up-down pair
   S* hs = (S*)(smem + ((N * N * sizeof(int) + 15) / 16) * 16);  // [N][D] when staged
@@ -638,7 +640,8 @@ __global__ __launch_bounds__(256) void aggregate_value_kernel(SysDev s, const S*
   const S* wsw = wsame + w * s.P0 * (int64_t)D;
   const S* wow = wopp + w * s.P1 * (int64_t)D;
   const S* wnw = wnuc + w * s.P2 * (int64_t)D;
-  for (int o = threadIdx.x; o < N * D; o += blockDim.x) {
+  const int o_end = min(N * D, (ck + 1) * cs);
+  for (int o = ck * cs + threadIdx.x; o < o_end; o += blockDim.x) {
     const int i = o / D, d = o - (o / D) * D;
     const bool up = i < s.nup;
     const int nsame = (up ? s.nup : s.ndn) - 1;
@@ -717,9 +720,11 @@ hipError_t launch_aggregate(const SysDev& s, const S* h, const S* wsame, const S
     const size_t tab = ((size_t)s.N * s.N * sizeof(int) + 15) / 16 * 16;
     const size_t hb = (size_t)s.N * s.D * sizeof(S);
     const int stage = tab + hb <= 64 * 1024;
+    const int cs = s.N * s.D > 2048 ? 1024 : s.N * s.D;  // outputs per block
+    const int nck = (s.N * s.D + cs - 1) / cs;
     ProfScope ps("aggregate_value_kernel", st);
-    hipLaunchKernelGGL(aggregate_value_kernel<S>, dim3((unsigned)W), dim3(256), tab + (stage ? hb : 0), st, s, h,
-                       wsame, wopp, wnuc, Y, stage, m);
+    hipLaunchKernelGGL(aggregate_value_kernel<S>, dim3((unsigned)(W * nck)), dim3(256), tab + (stage ? hb : 0), st, s,
+                       h, wsame, wopp, wnuc, Y, stage, nck, cs, m);
     return hipGetLastError();
   }
   // template on the larger spin block
