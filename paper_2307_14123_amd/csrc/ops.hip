@@ -714,7 +714,8 @@ static hipError_t agg_lds_launch(const SysDev& s, const S* h, const S* ws, const
 
 template <typename S>
 hipError_t launch_aggregate(const SysDev& s, const S* h, const S* wsame, const S* wopp, const S* wnuc, const S* Y,
-                            const double* ee, const double* en, int64_t W, int jet, S* m, hipStream_t st) {
+                            const double* ee, const double* /*en: the nuclear messages need no geometry here*/,
+                            int64_t W, int jet, S* m, hipStream_t st) {
   if (W <= 0) return hipSuccess;
   if (!jet) {
     const size_t tab = ((size_t)s.N * s.N * sizeof(int) + 15) / 16 * 16;

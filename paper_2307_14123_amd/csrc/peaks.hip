@@ -86,8 +86,8 @@ static float time_best(hipStream_t st, F f) {
     if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) break;
     if (rep > 0 && (best < 0.f || ms < best)) best = ms;
   }
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   return best;
 }
 
