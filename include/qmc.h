@@ -229,9 +229,11 @@ qmc_status qmc_logpsi_grad(const qmc_plan* plan, const void* params, const doubl
  * proposal is accepted iff, in float64,
  *   log(u) < 2 (l' - l) + |noise|^2 / 2 - |noise + step (D(r) + D(r'))|^2 / 2
  * (the Metropolis-Hastings ratio of the two Gaussian proposal densities);
- * a non-finite l' or gradient rejects.  r[W][N][3], logpsi[W] (log|psi(r)|)
- * and grad[W][N][3] (grad log|psi(r)|, as returned by qmc_local_energy) are
- * in/out and change only for accepted walkers.  noise[W][N][3] ~ N(0,1),
+ * a non-finite l' or gradient rejects.  l' and its gradient come from the
+ * value forward and one reverse pass (as qmc_logpsi_grad computes them).
+ * r[W][N][3], logpsi[W] (log|psi(r)|) and grad[W][N][3] (grad log|psi(r)|,
+ * as returned by qmc_logpsi_grad or qmc_local_energy) are in/out and change
+ * only for accepted walkers.  noise[W][N][3] ~ N(0,1),
  * u[W] in [0,1), accepted[W] in {0,1} (may be NULL).  step must be finite
  * and >= 0; damp must be 0 or 1. */
 qmc_status qmc_mala_step(const qmc_plan* plan, const void* params, double* r, double* logpsi,
