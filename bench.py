@@ -169,7 +169,8 @@ def main():
                          "batched: 16 molecules (4-42 electrons) in one graph vs per-molecule launches; "
                          "scaling: train-step time of atoms and hydrogen chains up to 45 electrons")
     ap.add_argument("--walkers", type=int, default=None)
-    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64", "bf16"])
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64", "bf16", "bf16v"],
+                    help="bf16v: bf16 operands in the value-row forwards only (local-energy jets in float32)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-walkers", type=int, default=160)
     ap.add_argument("--jastrow", action="store_true", help="add the learnable Jastrow factor to the ansatz")
@@ -362,7 +363,7 @@ def main():
     peaks = qmc.measure_peaks()
 
     eb = 8 if args.precision == "fp64" else 4
-    fused = args.precision == "fp32" and a.width == 128 and a.n_rbf <= 16
+    fused = args.precision == "fp32" and a.width in (128, 256) and a.n_rbf <= 16
     model = algorithmic_model(s, a, eb, n_mc, has_grad, fused)
     fam = {}
     for k, (nl, ms) in prof.items():
@@ -371,7 +372,7 @@ def main():
         fam[f] = (n0 + nl, m0 + ms)
     # dominant kernel family by total time in the timed region
     name, (nl, tot_ms) = max(fam.items(), key=lambda kv: kv[1][1])
-    gemm_dtype = {"fp32": "fp32_mfma", "fp64": "fp64_mfma", "bf16": "bf16_mfma"}[args.precision]
+    gemm_dtype = {"fp32": "fp32_mfma", "fp64": "fp64_mfma", "bf16": "bf16_mfma", "bf16v": "fp32_mfma"}[args.precision]
     roof = None
     if name in model:
         bound, work_per_walker = model[name]
@@ -416,7 +417,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"fp32": "f32+f64", "fp64": "f64", "bf16": "bf16+f32+f64"}[args.precision],
+        "dtype": {"fp32": "f32+f64", "fp64": "f64", "bf16": "bf16+f32+f64", "bf16v": "bf16+f32+f64"}[args.precision],
         "data": "synthetic",
         "config": {"workload": {"n2": "N2-sized: 2 x Z=7 at 2.068 bohr, 7 up + 7 down",
                                 "c4h4": "C4H4-sized: 4 C + 4 H, 14 up + 14 down",
@@ -587,7 +588,7 @@ def bench_batched(args):
         "unit": "walkers/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_graph,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": {"fp32": "f32+f64", "fp64": "f64", "bf16": "bf16+f32+f64"}[prec],
+        "dtype": {"fp32": "f32+f64", "fp64": "f64", "bf16": "bf16+f32+f64", "bf16v": "bf16+f32+f64"}[prec],
         "data": "synthetic",
         "config": {"workload": f"16 molecules ({', '.join(str(m.n_up + m.n_down) for m in mols)} electrons), "
                                f"{W} walkers each, width {a.width}, {a.n_det} dets; step = local energy + loss "
@@ -711,7 +712,7 @@ def bench_scaling(args):
         "unit": "exponent",
         "n_gpus": 1, "steps": steps, "warmup": args.warmup, "ms_per_step": largest["step_ms"],
         "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
-        "dtype": {"fp32": "f32+f64", "fp64": "f64", "bf16": "bf16+f32+f64"}[prec],
+        "dtype": {"fp32": "f32+f64", "fp64": "f64", "bf16": "bf16+f32+f64", "bf16v": "bf16+f32+f64"}[prec],
         "data": "synthetic",
         "config": {"workload": f"atoms Z in {list(qi.SCALING_ATOMS)} and hydrogen chains n in "
                                f"{list(qi.SCALING_CHAINS)} (1.8 bohr spacing), {W} walkers, width {a.width}, "

@@ -109,8 +109,12 @@ typedef enum qmc_precision {
   QMC_FP64 = 0,        /* every stage in float64 */
   QMC_FP32 = 1,        /* embedding/orbital jets in float32, determinants,
                           geometry and combination in float64 */
-  QMC_BF16_MIXED = 2   /* as QMC_FP32, but the embedding GEMMs take bf16
+  QMC_BF16_MIXED = 2,  /* as QMC_FP32, but the embedding GEMMs take bf16
                           operands with float32 accumulation */
+  QMC_BF16_VALUE = 3   /* bf16 operands only in the forwards of value rows
+                          (log|psi| for Metropolis, the loss gradient and
+                          qmc_logpsi_grad); the jets of the local energy stay
+                          float32 */
 } qmc_precision;
 
 typedef enum qmc_status {

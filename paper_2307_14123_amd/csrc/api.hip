@@ -71,8 +71,15 @@ static qmc_status hip_failed(hipError_t e, const char* call, int line) {
     if (e_ != hipSuccess) return hip_failed(e_, #x, __LINE__);  \
   } while (0)
 
-static GemmKind embed_kind(qmc_precision p) {
-  return p == QMC_FP64 ? GK_F64 : (p == QMC_BF16_MIXED ? GK_BF16 : GK_F32);
+// Kind of the embedding GEMMs: value_rows for the log|psi| forwards (value rows only).
+static GemmKind embed_kind(qmc_precision p, bool value_rows) {
+  if (p == QMC_FP64) return GK_F64;
+  if (p == QMC_BF16_MIXED || (p == QMC_BF16_VALUE && value_rows)) return GK_BF16;
+  return GK_F32;
+}
+// float32 plans whose edge filters of this pass run in the fused float32 kernel
+static bool fused_edges(const Plan& P, bool value_rows) {
+  return P.prec == QMC_FP32 || (P.prec == QMC_BF16_VALUE && !value_rows);
 }
 static GemmKind orbital_kind(qmc_precision p) { return p == QMC_FP64 ? GK_F64 : GK_F32; }
 
@@ -126,7 +133,7 @@ static qmc_status forward_chunk(const Plan& P, const SysPlan& s, const S* prm, c
   const SysDev dv = make_dev(P, s);
   const int64_t N = s.N, M = s.M, D = P.ans.width, K = P.ans.n_rbf, ND = P.ans.n_det;
   const int Rp = jet ? s.Rp : 1, Re = jet ? 4 : 1, vm = jet ? 0 : 1;
-  const GemmKind gk = embed_kind(P.prec), ok = orbital_kind(P.prec);
+  const GemmKind gk = embed_kind(P.prec, !jet), ok = orbital_kind(P.prec);
   double* ee = (double*)(ws + L.geom);
   double* en = ee + wc * N * N * 4;
   double* vpot = (double*)(ws + L.vpot);
@@ -151,7 +158,7 @@ static qmc_status forward_chunk(const Plan& P, const SysPlan& s, const S* prm, c
 
   CK(launch_geometry(dv, r, wc, ee, en, jet ? vpot : nullptr, st));
   // float32 plans of width 128 or 256 evaluate each edge filter in one fused kernel from the distances
-  const bool fused = std::is_same<S, float>::value && P.prec == QMC_FP32 && edge_mlp_supported(dv);
+  const bool fused = std::is_same<S, float>::value && fused_edges(P, !jet) && edge_mlp_supported(dv);
   if (P.ans.mp_layers > 0 && !fused)
     for (int t = 0; t < 3; ++t) CK(launch_rbf<S>(dv, t, ee, en, wc, jet, rho[t], st));
   CK(launch_init_features<S>(dv, ee, en, wc, jet, x0, st));
@@ -354,7 +361,7 @@ static qmc_status forward_stash(const Plan& P, const SysPlan& s, const S* prm, c
   const SysDev dv = make_dev(P, s);
   const int64_t N = s.N, M = s.M, D = P.ans.width, K = P.ans.n_rbf, ND = P.ans.n_det;
   const int L = P.ans.mp_layers, L0 = P.ans.init_layers;
-  const GemmKind gk = embed_kind(P.prec), ok = orbital_kind(P.prec);
+  const GemmKind gk = embed_kind(P.prec, true), ok = orbital_kind(P.prec);
   const ParamOffsets& O = s.off;
   double* ee = (double*)(ws + B.geom);
   double* en = ee + wc * N * N * 4;
@@ -380,7 +387,7 @@ static qmc_status forward_stash(const Plan& P, const SysPlan& s, const S* prm, c
       S* eh = F_(B.ehid[t], B.blk_e[t], l);
       S* wv = F_(B.wv[t], B.blk_e[t], l);
       if constexpr (std::is_same<S, float>::value) {
-        if (P.prec == QMC_FP32 && edge_mlp_supported(dv)) {
+        if (fused_edges(P, true) && edge_mlp_supported(dv)) {
           // the hidden layer is kept for the backward
           EdgeMlpArgs ea{prm + Ly.U1[t], prm + Ly.a1[t], prm + Ly.U2[t], prm + Ly.a2[t], ee, en, wv, eh, re, t, 0};
           CK(launch_edge_mlp(dv, ea, st));
@@ -709,7 +716,6 @@ static float time_gemm(GemmKind kind, const GemmArgs& a, hipStream_t st, hipEven
 // Times the tile candidates of every system's four GEMM classes on representative shapes (at most
 // 2^20 rows each, zero operands) and keeps the fastest in SysPlan::tile.
 static qmc_status autotune(Plan& P) {
-  const GemmKind gk = embed_kind(P.prec);
   const size_t E = act_bytes(P.prec);
   const int64_t D = P.ans.width, cap = int64_t(1) << 20;
   const size_t xb = size_t(cap) * 2 * D * E, wb = size_t(2 * D) * D * E, yb = size_t(cap) * D * E;
@@ -722,7 +728,7 @@ static qmc_status autotune(Plan& P) {
       hipMemset(B, 0, D * E) != hipSuccess || hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
     err = QMC_ERR_HIP;
-  const bool f32 = P.prec == QMC_FP32;
+  const bool f32 = P.prec == QMC_FP32 || P.prec == QMC_BF16_VALUE;
   // K-step (bit 0) and persistent grids (bit 2) are float32 options
   const std::vector<int> jet_bits = f32 ? std::vector<int>{0, 1, 4, 5} : std::vector<int>{0};
   const std::vector<int> row_bits = f32 ? std::vector<int>{0, 1, 2, 3, 4, 6} : std::vector<int>{0, 2};
@@ -741,6 +747,10 @@ static qmc_status autotune(Plan& P) {
         a.transw = cls == TILE_BWD;
       }
       if (a.rows <= 0) continue;
+      // the kind these shapes run in: jets and edge jets as the local energy, value rows as the
+      // log|psi| forwards, the backward's data products in the backward kind
+      const GemmKind gk = cls == TILE_BWD ? (P.prec == QMC_FP64 ? GK_F64 : GK_F32)
+                                          : embed_kind(P.prec, cls == TILE_VAL);
       float best = 1e30f;
       int pick = 0;
       for (int bits : (cls == TILE_JET ? jet_bits : row_bits)) {
@@ -921,7 +931,8 @@ qmc_status qmc_clip_local_energy(const qmc_plan* plan, const double* e_loc, doub
 
 qmc_status qmc_sgd_update(int32_t precision, void* params, const void* grad, int64_t n, double lr, void* stream) {
   if (n < 0 || (n > 0 && (!params || !grad)) || !std::isfinite(lr)) return QMC_ERR_INVALID_ARGUMENT;
-  if (precision != QMC_FP64 && precision != QMC_FP32 && precision != QMC_BF16_MIXED) return QMC_ERR_INVALID_ARGUMENT;
+  if (precision != QMC_FP64 && precision != QMC_FP32 && precision != QMC_BF16_MIXED && precision != QMC_BF16_VALUE)
+    return QMC_ERR_INVALID_ARGUMENT;
   if (n == 0) return QMC_OK;
   if (precision == QMC_FP64)
     CK(launch_sgd<double>(n, lr, (const double*)grad, (double*)params, (hipStream_t)stream));

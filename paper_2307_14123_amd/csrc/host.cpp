@@ -266,7 +266,7 @@ qmc_status qmc_plan_create(qmc_plan** out, const qmc_system* systems, int32_t n_
   *out = nullptr;
   if (!systems || n_systems < 1 || n_systems > 4096 || !walkers_per_system) return QMC_ERR_INVALID_ARGUMENT;
   if (!valid_ansatz(ansatz)) return QMC_ERR_INVALID_ARGUMENT;
-  if (precision != QMC_FP64 && precision != QMC_FP32 && precision != QMC_BF16_MIXED)
+  if (precision != QMC_FP64 && precision != QMC_FP32 && precision != QMC_BF16_MIXED && precision != QMC_BF16_VALUE)
     return QMC_ERR_INVALID_ARGUMENT;
   if (flags & ~uint32_t(QMC_PLAN_CONCURRENT_SYSTEMS | QMC_PLAN_AUTOTUNE)) return QMC_ERR_INVALID_ARGUMENT;
   // the bf16 MFMA path works on K in steps of 32 and the jet GEMM tiles on 16-wide

@@ -15,8 +15,8 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libqmc.so")
 
-QMC_FP64, QMC_FP32, QMC_BF16_MIXED = 0, 1, 2
-PRECISIONS = {"fp64": QMC_FP64, "fp32": QMC_FP32, "bf16": QMC_BF16_MIXED}
+QMC_FP64, QMC_FP32, QMC_BF16_MIXED, QMC_BF16_VALUE = 0, 1, 2, 3
+PRECISIONS = {"fp64": QMC_FP64, "fp32": QMC_FP32, "bf16": QMC_BF16_MIXED, "bf16v": QMC_BF16_VALUE}
 OP_LOGPSI, OP_LOCAL_ENERGY, OP_METROPOLIS, OP_LOGPSI_VJP, OP_LOSS_GRAD, OP_MALA, OP_LOGPSI_GRAD = range(7)
 PLAN_CONCURRENT_SYSTEMS, PLAN_AUTOTUNE = 1, 2
 

@@ -1,7 +1,7 @@
 """Mixed precision on the cyclobutadiene-sized system (4 C + 4 H, 14 up + 14
 down electrons, width 256, 32 determinants): embedding GEMMs with bf16
-operands and float32 accumulation, determinants and the energy combination in
-float64.  E_L is compared with the FP64 oracle on a walker subset and the
+operands and float32 accumulation (everywhere, or only in the value-row
+forwards: bf16v), determinants and the energy combination in float64.  E_L is compared with the FP64 oracle on a walker subset and the
 error is reported in mHa, beside the float32 plan on the same walkers."""
 import numpy as np
 import pytest
@@ -37,7 +37,7 @@ def c4h4_case():
     return s, a, p, r, ref, ok, scale
 
 
-@pytest.mark.parametrize("precision,rel_bound", [("fp32", 2e-5), ("bf16", 5e-2)])
+@pytest.mark.parametrize("precision,rel_bound", [("fp32", 2e-5), ("bf16", 5e-2), ("bf16v", 2e-5)])
 def test_c4h4_precision_vs_oracle(c4h4_case, precision, rel_bound):
     s, a, p, r, ref, ok, scale = c4h4_case
     got = _run(s, a, p, r, precision)
@@ -48,3 +48,24 @@ def test_c4h4_precision_vs_oracle(c4h4_case, precision, rel_bound):
           f"log|psi| max abs err {np.abs(got['logpsi'] - ref['logpsi'])[ok].max():.2e}", flush=True)
     assert np.all(got["sign"][ok] == ref["sign"][ok])
     assert rel.max() < rel_bound
+
+
+def test_c4h4_bf16_value_rows_logpsi(c4h4_case):
+    """bf16v: the value-row forward (log|psi| for Metropolis and the loss gradient) takes bf16
+    operands, so its log|psi| carries bf16 rounding (bounded like the bf16 plan's), while the local
+    energy above keeps the float32 bound; the loss gradient stays within 5e-2 normwise."""
+    from paper_2307_14123_amd import qmc
+    s, a, p, r, ref, ok, scale = c4h4_case
+    plan = qmc.Plan([s], [r.shape[0]], a, "bf16v")
+    P, R = dev(p, plan.param_dtype), dev(r)
+    lp, sg = plan.logpsi(P, R)
+    g, _ = plan.loss_grad(P, R, dev(ref["e_loc"]))
+    torch.cuda.synchronize()
+    err = np.abs(host(lp) - ref["logpsi"])[ok]
+    p32 = p.astype(np.float32).astype(np.float64)
+    Gref = oracle.loss_grad(r, ref["e_loc"], p32, s, a)[0]
+    gerr = np.linalg.norm(host(g).astype(np.float64) - Gref) / np.linalg.norm(Gref)
+    print(f"[c4h4 bf16v] value-row log|psi| max abs err {err.max():.2e}; loss gradient normwise {gerr:.2e}",
+          flush=True)
+    assert np.all(host(sg)[ok] == ref["sign"][ok])
+    assert err.max() < 5e-2 * max(1.0, np.abs(ref["logpsi"]).max()) and gerr < 5e-2
