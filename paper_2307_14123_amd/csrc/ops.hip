@@ -665,6 +665,19 @@ __global__ __launch_bounds__(256) void aggregate_value_kernel(SysDev s, const S*
   }
 }
 
+// Raises a kernel's dynamic-LDS limit above 64 KB, once per device (the attribute is a per-device
+// setting; done[dev] keeps the largest size set so far).
+static hipError_t allow_lds(const void* fn, size_t lds, size_t* done) {
+  if (lds <= 64 * 1024) return hipSuccess;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return hipErrorInvalidValue;
+  if (lds <= done[dev]) return hipSuccess;
+  if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+    return hipErrorInvalidValue;
+  done[dev] = lds;
+  return hipSuccess;
+}
+
 template <typename S, int NS>
 static hipError_t agg_launch(const SysDev& s, const S* h, const S* ws, const S* wo, const double* ee, int64_t W, S* m,
                              hipStream_t st) {
@@ -675,13 +688,9 @@ static hipError_t agg_launch(const SysDev& s, const S* h, const S* ws, const S* 
   while (DC > 1 && (DC >= 2 * s.D || DC * ngroups > 512)) DC >>= 1;
   const int nch = (s.D + DC - 1) / DC;
   const size_t lds = (size_t)s.N * s.N * 4 * sizeof(S) + (size_t)s.N * s.N * sizeof(int);
-  static size_t lds_set = 0;
-  if (lds > 64 * 1024 && lds > lds_set) {
-    if (hipFuncSetAttribute((const void*)aggregate_kernel<S, NS, RG>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)lds) != hipSuccess)
-      return hipErrorInvalidValue;
-    lds_set = lds;
-  }
+  static size_t lds_set[64] = {};
+  const hipError_t le = allow_lds((const void*)aggregate_kernel<S, NS, RG>, lds, lds_set);
+  if (le != hipSuccess) return le;
   ProfScope ps("aggregate_kernel", st);
   // blocks of one walker are adjacent, so they run together and share its rows in L2
   hipLaunchKernelGGL((aggregate_kernel<S, NS, RG>), dim3((unsigned)(W * nch)), dim3(DC * ngroups), lds, st, s, h, ws,
@@ -699,13 +708,9 @@ static hipError_t agg_lds_launch(const SysDev& s, const S* h, const S* ws, const
   const int nch = (s.D + DC - 1) / DC;
   const size_t lds = ((size_t)s.N * s.N * 4 + (size_t)RC * 2 * NS * DC + (size_t)2 * NS * DC) * sizeof(S) +
                      (size_t)s.N * s.N * sizeof(int);
-  static size_t lds_set = 0;
-  if (lds > 64 * 1024 && lds > lds_set) {
-    if (hipFuncSetAttribute((const void*)aggregate_lds_kernel<S, NS, RC>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
-      return hipErrorInvalidValue;
-    lds_set = lds;
-  }
+  static size_t lds_set[64] = {};
+  const hipError_t le = allow_lds((const void*)aggregate_lds_kernel<S, NS, RC>, lds, lds_set);
+  if (le != hipSuccess) return le;
   ProfScope ps("aggregate_kernel", st);
   hipLaunchKernelGGL((aggregate_lds_kernel<S, NS, RC>), dim3((unsigned)(W * nch)), dim3(DC * s.N), lds, st, s, h,
                      ws, wo, ee, DC, nch, m);
