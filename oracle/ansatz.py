@@ -74,10 +74,15 @@ def embedding(r, P, system, ans):
     f = torch.tanh(x @ P["init.W1"] + P["init.b1"])
     for l in range(2, ans.init_layers + 1):
         f = torch.tanh(f @ P[f"init.W{l}"] + P[f"init.b{l}"])
+    # edge features per edge type: the radial basis, or with ans.edge_update its update
+    # f_e^l = tanh(f_e^(l-1) Ve^l + ce^l) in every layer after the first (Sec. III.A, edge update)
+    fe = {"same": rho_ee, "opp": rho_ee, "nuc": rho_en}
     for l in range(ans.mp_layers):
         w = {}
-        for t, rho in (("same", rho_ee), ("opp", rho_ee), ("nuc", rho_en)):
-            w[t] = _mlp_filter(rho, P[f"mp{l}.{t}.U1"], P[f"mp{l}.{t}.a1"],
+        for t in ("same", "opp", "nuc"):
+            if getattr(ans, "edge_update", 0) and l >= 1:
+                fe[t] = torch.tanh(fe[t] @ P[f"mp{l}.{t}.Ve"] + P[f"mp{l}.{t}.ce"])
+            w[t] = _mlp_filter(fe[t], P[f"mp{l}.{t}.U1"], P[f"mp{l}.{t}.a1"],
                                P[f"mp{l}.{t}.U2"], P[f"mp{l}.{t}.a2"])
         h = f @ P[f"mp{l}.Wh"] + P[f"mp{l}.bh"]         # [B, N, D] sender features
         m_same = (mask_same[None, :, :, None] * w["same"] * h[:, None, :, :]).sum(2) / n_same[None, :, None]

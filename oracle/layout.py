@@ -31,6 +31,9 @@ def param_shapes(system, ans):
             shapes[f"mp{l}.{t}.a1"] = (D,)
             shapes[f"mp{l}.{t}.U2"] = (D, D)
             shapes[f"mp{l}.{t}.a2"] = (D,)
+            if getattr(ans, "edge_update", 0) and l >= 1:
+                shapes[f"mp{l}.{t}.Ve"] = (K, K)
+                shapes[f"mp{l}.{t}.ce"] = (K,)
         shapes[f"mp{l}.Wh"] = (D, D)
         shapes[f"mp{l}.bh"] = (D,)
         shapes[f"mp{l}.Y"] = (M, D)

@@ -55,7 +55,11 @@ def logpsi_np(r, params, system, ans):
         f = [np.tanh(fi @ P[f"init.W{l}"] + P[f"init.b{l}"]) for fi in f]
 
     def filt(l, t, d):
-        hid = np.tanh(_rho(d, K, dmax) @ P[f"mp{l}.{t}.U1"] + P[f"mp{l}.{t}.a1"])
+        x = _rho(d, K, dmax)
+        if getattr(ans, "edge_update", 0):
+            for lu in range(1, l + 1):  # the edge features' updates up to layer l
+                x = np.tanh(x @ P[f"mp{lu}.{t}.Ve"] + P[f"mp{lu}.{t}.ce"])
+        hid = np.tanh(x @ P[f"mp{l}.{t}.U1"] + P[f"mp{l}.{t}.a1"])
         return hid @ P[f"mp{l}.{t}.U2"] + P[f"mp{l}.{t}.a2"]
 
     for l in range(ans.mp_layers):

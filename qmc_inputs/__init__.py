@@ -60,6 +60,7 @@ class Ansatz:
     ee_cusp: float = 0.0     # length alpha of the fixed electron-electron cusp factor (0: none)
     jastrow: int = 0         # 1: learnable Jastrow factor exp(J), J an MLP of the summed embeddings
     full_det: int = 0        # 1: one N x N determinant per p over both spins (N orbitals per spin map)
+    edge_update: int = 0     # 1: edge features updated in every interaction layer after the first
 
 
 @dataclasses.dataclass(frozen=True)
@@ -94,6 +95,9 @@ def param_table(system: System, ans: Ansatz) -> List[Tuple[str, Tuple[int, ...],
             out.append((f"mp{l}.{t}.a1", (D,), "zero", 0))
             out.append((f"mp{l}.{t}.U2", (D, D), "w", D))
             out.append((f"mp{l}.{t}.a2", (D,), "zero", 0))
+            if ans.edge_update and l >= 1:
+                out.append((f"mp{l}.{t}.Ve", (K, K), "w", K))
+                out.append((f"mp{l}.{t}.ce", (K,), "zero", 0))
         out.append((f"mp{l}.Wh", (D, D), "w", D))
         out.append((f"mp{l}.bh", (D,), "zero", 0))
         out.append((f"mp{l}.Y", (M, D), "normal", 0))

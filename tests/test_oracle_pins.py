@@ -300,11 +300,12 @@ def _small_system():
 SMALL_CUSP = dataclasses.replace(SMALL, ee_cusp=0.7)
 SMALL_JAS = dataclasses.replace(SMALL, ee_cusp=0.7, jastrow=1)
 SMALL_FULL = dataclasses.replace(SMALL, full_det=1)
+SMALL_EDGE = dataclasses.replace(SMALL, edge_update=1)
 
 
 def test_torch_and_numpy_forwards_agree():
     s = _small_system()
-    for ans in (SMALL_CUSP, SMALL_JAS, SMALL_FULL):
+    for ans in (SMALL_CUSP, SMALL_JAS, SMALL_FULL, SMALL_EDGE):
         p = qi.make_params(s, ans, 13)
         r = qi.make_walkers(s, 5, 14)
         st, lt = oracle.logpsi(torch.as_tensor(r), torch.as_tensor(p), s, ans)
@@ -360,7 +361,8 @@ def test_cancelling_determinants_give_zero_psi():
     assert np.all(np.isnan(res["e_loc"]))
 
 
-@pytest.mark.parametrize("ans", [SMALL, SMALL_JAS, SMALL_FULL], ids=["plain", "cusp_jastrow", "full_det"])
+@pytest.mark.parametrize("ans", [SMALL, SMALL_JAS, SMALL_FULL, SMALL_EDGE],
+                         ids=["plain", "cusp_jastrow", "full_det", "edge_update"])
 def test_same_spin_exchange_antisymmetry(ans):
     s = _small_system()
     p = qi.make_params(s, ans, 17)
@@ -411,7 +413,8 @@ def _fd_grad_lap(r, p, s, a, h):
     return g, lap
 
 
-@pytest.mark.parametrize("ans", [SMALL, SMALL_CUSP, SMALL_JAS, SMALL_FULL], ids=["plain", "ee_cusp", "jastrow", "full_det"])
+@pytest.mark.parametrize("ans", [SMALL, SMALL_CUSP, SMALL_JAS, SMALL_FULL, SMALL_EDGE],
+                         ids=["plain", "ee_cusp", "jastrow", "full_det", "edge_update"])
 def test_gradient_and_laplacian_vs_finite_differences(ans):
     s = _small_system()
     p = qi.make_params(s, ans, 23)
@@ -427,7 +430,7 @@ def test_gradient_and_laplacian_vs_finite_differences(ans):
     np.testing.assert_allclose(lap, res["lap"], rtol=2e-6, atol=2e-6 * np.abs(res["lap"]).max())
 
 
-@pytest.mark.parametrize("ans", [SMALL, SMALL_JAS], ids=["plain", "jastrow"])
+@pytest.mark.parametrize("ans", [SMALL, SMALL_JAS, SMALL_EDGE], ids=["plain", "jastrow", "edge_update"])
 def test_loss_gradient_vs_finite_differences_of_surrogate(ans):
     """FD (h = 1e-5, float64) of S(theta) = sum_w g_w log|psi_w(theta)| with the
     weights frozen, on sampled parameters (with the Jastrow: the last 64 too), against the autograd
@@ -442,6 +445,12 @@ def test_loss_gradient_vs_finite_differences_of_surrogate(ans):
     idx = np.random.default_rng(27).choice(len(p), 64, replace=False)
     if ans.jastrow:
         idx = np.concatenate([idx, np.arange(len(p) - 64, len(p))])
+    if ans.edge_update:  # every parameter of one edge update
+        off = 0
+        for name, v in unpack(p, s, ans).items():
+            if name == "mp1.opp.Ve":
+                idx = np.concatenate([idx, off + np.arange(v.size)])
+            off += v.size
     h = 1e-5
     for k in idx:
         pp = p.copy(); pp[k] += h
@@ -703,3 +712,25 @@ def test_clipping_degenerate_cases():
     assert np.all(np.isnan(oracle.clip_local_energy(np.array([np.nan, np.nan]), 5.0)))
     x = np.full(6, -1.25)
     np.testing.assert_array_equal(oracle.clip_local_energy(x, 5.0, "soft"), x)
+
+
+def test_zero_edge_updates_match_zeroed_filter_inputs():
+    """Edge updates with Ve = 0 and ce = 0 map every later edge feature to tanh(0) = 0, so the
+    ansatz equals the plain one whose later layers have U1 = 0 (their filters see only the bias)."""
+    s = _small_system()
+    pe = qi.make_params(s, SMALL_EDGE, 33)
+    Pe = unpack(pe, s, SMALL_EDGE)
+    for l in range(1, SMALL.mp_layers):
+        for t in ("same", "opp", "nuc"):
+            Pe[f"mp{l}.{t}.Ve"][:] = 0.0
+            Pe[f"mp{l}.{t}.ce"][:] = 0.0
+    r = qi.make_walkers(s, 4, 34)
+    a = oracle.logpsi_np(r, pe, s, SMALL_EDGE)[1]
+    # the same parameters without the updates, U1 = 0 in the later layers
+    p0 = np.concatenate([Pe[k].ravel() for k in Pe if not k.endswith((".Ve", ".ce"))])
+    P0 = unpack(p0, s, SMALL)
+    for l in range(1, SMALL.mp_layers):
+        for t in ("same", "opp", "nuc"):
+            P0[f"mp{l}.{t}.U1"][:] = 0.0
+    b = oracle.logpsi_np(r, p0, s, SMALL)[1]
+    np.testing.assert_allclose(a, b, rtol=1e-13, atol=1e-13)
