@@ -176,6 +176,8 @@ def main():
     ap.add_argument("--jastrow", action="store_true", help="add the learnable Jastrow factor to the ansatz")
     ap.add_argument("--ee-cusp", type=float, default=0.0, help="alpha of the electron-electron cusp factor (0: none)")
     ap.add_argument("--full-det", action="store_true", help="one N x N determinant per p over both spins")
+    ap.add_argument("--edge-update", action="store_true",
+                    help="update the edge features in every interaction layer after the first")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="end with a plain 256 MiB device copy, the reference for traffic counters")
     args = ap.parse_args()
@@ -195,9 +197,10 @@ def main():
     k = {"n2": 1, "c4h4": 3, "h2": 0}[args.workload]
     wl = qi.workload(k)
     s, a = wl.systems[0], wl.ansatz
-    if args.jastrow or args.ee_cusp > 0 or args.full_det:
+    if args.jastrow or args.ee_cusp > 0 or args.full_det or args.edge_update:
         import dataclasses
-        a = dataclasses.replace(a, jastrow=int(args.jastrow), ee_cusp=float(args.ee_cusp), full_det=int(args.full_det))
+        a = dataclasses.replace(a, jastrow=int(args.jastrow), ee_cusp=float(args.ee_cusp), full_det=int(args.full_det),
+                                edge_update=int(args.edge_update))
     W = args.walkers or wl.walkers
     n_mc, tau = 10, 0.2
     params = qi.make_params(s, a, qi.seed(k, 0))
@@ -427,6 +430,7 @@ def main():
                                + (", learnable Jastrow" if a.jastrow else "")
                                + (f", e-e cusp factor alpha {a.ee_cusp}" if a.ee_cusp > 0 else "")
                                + (", full determinants" if a.full_det else "")
+                               + (", edge-feature updates" if a.edge_update else "")
                                + f"; step = {n_mc} Metropolis steps (tau {tau}) + "
                                f"local energy" + (" + clipping (median +- 5 mean absolute deviations) + loss "
                                                   "gradient + gradient-descent update (lr 1e-8)"

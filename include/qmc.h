@@ -89,7 +89,12 @@ typedef struct qmc_system {
  *                     (Sec. III.C, full-determinant equation): each spin's
  *                     orbital map gives N orbitals, row i of A^p is electron i
  *                     (up electrons first); needs N <= 32.  0 = spin-factorized
- *                     determinants. */
+ *                     determinants.
+ *   edge_update     : 1 updates the edge features in every interaction layer
+ *                     after the first (Sec. III.A, edge update), per edge
+ *                     type: f_e^l = tanh(f_e^(l-1) Ve^l + ce^l), f_e^0 the
+ *                     radial basis; the filters of layer l read f_e^l.  0 =
+ *                     the basis is reused in every layer. */
 typedef struct qmc_ansatz {
   int32_t version;
   int32_t n_rbf;
@@ -103,6 +108,7 @@ typedef struct qmc_ansatz {
   double ee_cusp;
   int32_t jastrow;
   int32_t full_det;
+  int32_t edge_update;
 } qmc_ansatz;
 
 typedef enum qmc_precision {
@@ -144,7 +150,8 @@ typedef struct qmc_plan qmc_plan;
  * Blob order (matrices stored [in][out] so that a layer is y = x W + b):
  *   init.W1[(M+2)K][D] init.b1[D], then init.Wl[D][D] init.bl[D] for l>=2;
  *   per interaction layer: for t in (same, opp, nuc): U1[K][D] a1[D]
- *     U2[D][D] a2[D]; then Wh[D][D] bh[D] Y[M][D] Wg[3D][D] bg[D];
+ *     U2[D][D] a2[D] (then, with edge_update, in layers after the first:
+ *     Ve[K][K] ce[K]); then Wh[D][D] bh[D] Y[M][D] Wg[3D][D] bg[D];
  *   per spin with n_sigma > 0, with n_o = n_sigma (or N with full_det):
  *     Worb[D][n_det*n_o] borb[n_det*n_o] pi[n_det][n_o][M][n_env]
  *     sigma[n_det][n_o][M][n_env];

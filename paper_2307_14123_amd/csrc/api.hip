@@ -158,8 +158,9 @@ static qmc_status forward_chunk(const Plan& P, const SysPlan& s, const S* prm, c
 
   CK(launch_geometry(dv, r, wc, ee, en, jet ? vpot : nullptr, st));
   // float32 plans of width 128 or 256 evaluate each edge filter in one fused kernel from the distances
+  // (with edge updates, the updated features of later layers are read from memory instead)
   const bool fused = std::is_same<S, float>::value && fused_edges(P, !jet) && edge_mlp_supported(dv);
-  if (P.ans.mp_layers > 0 && !fused)
+  if (P.ans.mp_layers > 0 && (!fused || P.ans.edge_update))
     for (int t = 0; t < 3; ++t) CK(launch_rbf<S>(dv, t, ee, en, wc, jet, rho[t], st));
   CK(launch_init_features<S>(dv, ee, en, wc, jet, x0, st));
   const int64_t rows = wc * N * Rp;
@@ -172,20 +173,28 @@ static qmc_status forward_chunk(const Plan& P, const SysPlan& s, const S* prm, c
     f = h;
     h = tmp;
   }
+  S* fe[3] = {rho[0], rho[1], rho[2]};  // the edge features the filters read
   for (int l = 0; l < P.ans.mp_layers; ++l) {
     const auto& Ly = O.mp[l];
     for (int t = 0; t < 3; ++t) {
       const int64_t re = wc * s.P[t] * Re;
       if (re == 0) continue;
+      if (Ly.Ve[t] >= 0) {
+        // edge-feature update f_e <- tanh(f_e Ve + ce), univariate jets (4 rows an edge) or values
+        S* nx = fe[t] == rho[t] ? (S*)(ws + L.rho2[t]) : rho[t];
+        CK(gemm(s, gk, dense(fe[t], K, prm + Ly.Ve[t], K, prm + Ly.ce[t], nx, K, re, (int)K, (int)K, Re, 1, 1, vm),
+                st));
+        fe[t] = nx;
+      }
       if constexpr (std::is_same<S, float>::value) {
         if (fused) {
           EdgeMlpArgs ea{prm + Ly.U1[t], prm + Ly.a1[t], prm + Ly.U2[t], prm + Ly.a2[t], ee, en, wj[t], nullptr,
-                         wc * s.P[t], t, jet};
+                         wc * s.P[t], t, jet, Ly.Ve[t] >= 0 ? (const float*)fe[t] : nullptr};
           CK(launch_edge_mlp(dv, ea, st));
           continue;
         }
       }
-      CK(gemm(s, gk, dense(rho[t], K, prm + Ly.U1[t], D, prm + Ly.a1[t], ehid[t], D, re, (int)K, (int)D, Re, 1, 1, vm),
+      CK(gemm(s, gk, dense(fe[t], K, prm + Ly.U1[t], D, prm + Ly.a1[t], ehid[t], D, re, (int)K, (int)D, Re, 1, 1, vm),
                      st));
       CK(gemm(s, gk, dense(ehid[t], D, prm + Ly.U2[t], D, prm + Ly.a2[t], wj[t], D, re, (int)D, (int)D, Re, 1, 0, vm),
                      st));
@@ -386,16 +395,21 @@ static qmc_status forward_stash(const Plan& P, const SysPlan& s, const S* prm, c
       if (re == 0) continue;
       S* eh = F_(B.ehid[t], B.blk_e[t], l);
       S* wv = F_(B.wv[t], B.blk_e[t], l);
+      // edge features of this layer: the radial basis, or its update (every layer's is kept)
+      S* fe = F_(B.rho[t], B.blk_r[t], Ly.Ve[t] >= 0 ? l : 0);
+      if (Ly.Ve[t] >= 0)
+        CK(gemm(s, gk, dense(F_(B.rho[t], B.blk_r[t], l - 1), K, prm + Ly.Ve[t], K, prm + Ly.ce[t], fe, K, re, (int)K,
+                             (int)K, 1, 0, 1, 1), st));
       if constexpr (std::is_same<S, float>::value) {
         if (fused_edges(P, true) && edge_mlp_supported(dv)) {
           // the hidden layer is kept for the backward
-          EdgeMlpArgs ea{prm + Ly.U1[t], prm + Ly.a1[t], prm + Ly.U2[t], prm + Ly.a2[t], ee, en, wv, eh, re, t, 0};
+          EdgeMlpArgs ea{prm + Ly.U1[t], prm + Ly.a1[t], prm + Ly.U2[t], prm + Ly.a2[t], ee, en, wv, eh, re, t, 0,
+                         Ly.Ve[t] >= 0 ? (const float*)fe : nullptr};
           CK(launch_edge_mlp(dv, ea, st));
           continue;
         }
       }
-      CK(gemm(s, gk, dense((S*)(ws + B.rho[t]), K, prm + Ly.U1[t], D, prm + Ly.a1[t], eh, D, re, (int)K, (int)D, 1,
-                               0, 1, 1), st));
+      CK(gemm(s, gk, dense(fe, K, prm + Ly.U1[t], D, prm + Ly.a1[t], eh, D, re, (int)K, (int)D, 1, 0, 1, 1), st));
       CK(gemm(s, gk, dense(eh, D, prm + Ly.U2[t], D, prm + Ly.a2[t], wv, D, re, (int)D, (int)D, 1, 0, 0, 1), st));
     }
     S* h = F_(B.hst, B.blk_f, l);
@@ -553,16 +567,34 @@ static qmc_status backward_chunk(const Plan& P, const SysPlan& s, const S* prm, 
       ge.transw = 1;
       ge.aux = eh;
       CK(gemm(s, bk, ge, st));
-      if (pg) {
-        CK(launch_wgrad(bk, wg((S*)(ws + B.rho[t]), K, ebar, D, re, (int)K, (int)D, B, ws), gacc + Ly.U1[t], D,
-                        gacc + Ly.a1[t], st));
-      } else {
-        // radial-basis cotangents rhobar = ebar U1^T, then the pair distances
+      const bool upd = Ly.Ve[t] >= 0;  // this layer's edge features are an update of the previous layer's
+      S* fe = F_(B.rho[t], B.blk_r[t], upd ? l : 0);
+      if (pg)
+        CK(launch_wgrad(bk, wg(fe, K, ebar, D, re, (int)K, (int)D, B, ws), gacc + Ly.U1[t], D, gacc + Ly.a1[t], st));
+      if (!pg || upd) {
+        // edge-feature cotangents rhobar = ebar U1^T, plus what the next layer's update carried back
         S* rb = (S*)(ws + B.rhobar);
+        S* carry = (S*)(ws + B.ecarry[t]);
         GemmArgs gr = dense(ebar, D, prm + Ly.U1[t], D, nullptr, rb, K, re, (int)D, (int)K, 1, 0, 0, 1);
         gr.transw = 1;
+        if (l + 1 < L && O.mp[l + 1].Ve[t] >= 0 && (!pg || l >= 1)) gr.Res = carry;
         CK(gemm(s, bk, gr, st));
-        CK(launch_pair_dbar<S>(dv, t, rb, ee, en, wc, dee, den, st));
+        if (upd) {
+          // through f_e^l = tanh(f_e^(l-1) Ve + ce): pre-activation cotangent (in ebar's space), the
+          // update's weights, and the cotangent of f_e^(l-1) when a lower layer still needs it
+          S* zb = ebar;
+          CK(launch_tanh_bwd<S>(re * K, rb, fe, zb, st));
+          if (pg)
+            CK(launch_wgrad(bk, wg(F_(B.rho[t], B.blk_r[t], l - 1), K, zb, K, re, (int)K, (int)K, B, ws),
+                            gacc + Ly.Ve[t], K, gacc + Ly.ce[t], st));
+          if (!pg || l >= 2) {
+            GemmArgs gc = dense(zb, K, prm + Ly.Ve[t], K, nullptr, carry, K, re, (int)K, (int)K, 1, 0, 0, 1);
+            gc.transw = 1;
+            CK(gemm(s, bk, gc, st));
+          }
+        } else if (!pg) {
+          CK(launch_pair_dbar<S>(dv, t, rb, ee, en, wc, dee, den, st));
+        }
       }
     }
   }

@@ -69,18 +69,26 @@ __global__ __launch_bounds__(64 * NW) void edge_mlp_kernel(SysDev s, EdgeMlpArgs
     const bool rowok = (!JET || c < 15) && pr < a.pairs;
     float rb[4] = {0.f, 0.f, 0.f, 0.f};
     if (rowok) {
-      const int64_t w = pr / P;
-      const int pi = (int)(pr - w * P);
-      int i, j;
-      decode_pair(s, a.type, pi, i, j);
-      const double d = a.type == 2 ? a.en[((w * s.N + i) * s.M + j) * 4] : a.ee[((w * s.N + i) * s.N + j) * 4];
+      if (a.feat) {
+        // precomputed edge features (an updated edge feature, Sec. III.A)
+        const float* fr = a.feat + (JET ? pr * 4 + e : pr) * K;
 #pragma unroll
-      for (int kq = 0; kq < 4; ++kq) {
-        const int r = 4 * g + kq;
-        if (r < K) {
-          double r0, r1, r2;
-          rbf3(d, r, rs, ris, r0, r1, r2);
-          rb[kq] = (float)(e == 0 ? r0 : (e == 1 ? r1 : r2));
+        for (int kq = 0; kq < 4; ++kq)
+          if (4 * g + kq < K) rb[kq] = fr[4 * g + kq];
+      } else {
+        const int64_t w = pr / P;
+        const int pi = (int)(pr - w * P);
+        int i, j;
+        decode_pair(s, a.type, pi, i, j);
+        const double d = a.type == 2 ? a.en[((w * s.N + i) * s.M + j) * 4] : a.ee[((w * s.N + i) * s.N + j) * 4];
+#pragma unroll
+        for (int kq = 0; kq < 4; ++kq) {
+          const int r = 4 * g + kq;
+          if (r < K) {
+            double r0, r1, r2;
+            rbf3(d, r, rs, ris, r0, r1, r2);
+            rb[kq] = (float)(e == 0 ? r0 : (e == 1 ? r1 : r2));
+          }
         }
       }
     }

@@ -34,6 +34,11 @@ bool compute_offsets(const qmc_system& s, const qmc_ansatz& a, ParamOffsets* off
       L.a1[t] = take(cur, D);
       L.U2[t] = take(cur, D * D);
       L.a2[t] = take(cur, D);
+      L.Ve[t] = L.ce[t] = -1;
+      if (a.edge_update && l >= 1) {
+        L.Ve[t] = take(cur, K * K);
+        L.ce[t] = take(cur, K);
+      }
     }
     L.Wh = take(cur, D * D);
     L.bh = take(cur, D);
@@ -86,6 +91,7 @@ Workspace workspace_layout(const Plan& p, const SysPlan& s, int op, int64_t wc) 
   w.vpot = alloc(size_t(wc) * 8);
   for (int t = 0; t < 3; ++t) {
     w.rho[t] = alloc(size_t(wc) * s.P[t] * Rpe * K * E);
+    w.rho2[t] = alloc(p.ans.edge_update ? size_t(wc) * s.P[t] * Rpe * K * E : 0);
     w.ehid[t] = alloc(size_t(wc) * s.P[t] * Rpe * D * E);
     w.wjet[t] = alloc(size_t(wc) * s.P[t] * Rpe * D * E);
   }
@@ -132,7 +138,9 @@ BwdWorkspace bwd_layout(const Plan& p, const SysPlan& s, int64_t wc) {
   b.geom = alloc(size_t(wc) * (N * N + N * M) * 4 * 8);
   for (int t = 0; t < 3; ++t) {
     b.blk_e[t] = int64_t(align256(size_t(wc) * s.P[t] * D * E));
-    b.rho[t] = alloc(size_t(wc) * s.P[t] * K * E);
+    b.blk_r[t] = int64_t(align256(size_t(wc) * s.P[t] * K * E));
+    b.rho[t] = alloc(size_t(b.blk_r[t]) * (p.ans.edge_update && L > 1 ? L : 1));
+    b.ecarry[t] = alloc(p.ans.edge_update ? size_t(wc) * s.P[t] * K * E : 0);
     b.ehid[t] = alloc(size_t(b.blk_e[t]) * (L > 0 ? L : 1));
     b.wv[t] = alloc(size_t(b.blk_e[t]) * (L > 0 ? L : 1));
   }
@@ -243,6 +251,7 @@ static bool valid_ansatz(const qmc_ansatz* a) {
   if (!std::isfinite(a->ee_cusp) || a->ee_cusp < 0) return false;
   if (a->jastrow != 0 && a->jastrow != 1) return false;
   if (a->full_det != 0 && a->full_det != 1) return false;
+  if (a->edge_update != 0 && a->edge_update != 1) return false;
   return true;
 }
 

@@ -91,6 +91,8 @@ struct EdgeMlpArgs {
   int64_t pairs;          // walkers x pairs of this type
   int type;               // 0 same-spin, 1 up-down, 2 electron-nucleus
   int jet;
+  const float* feat;      // optional edge features in place of the radial basis of the distance:
+                          // [pairs][K] values, or [pairs][4][K] univariate jets (rows 0-2 read)
 };
 bool edge_mlp_supported(const SysDev& s);
 hipError_t launch_edge_mlp(const SysDev& s, const EdgeMlpArgs& a, hipStream_t st);

@@ -14,6 +14,7 @@ struct ParamOffsets {
   int64_t initW[8], initb[8];  // init layers 1..L0 (index l-1)
   struct Layer {
     int64_t U1[3], a1[3], U2[3], a2[3];  // edge filters: 0 same, 1 opp, 2 nuc
+    int64_t Ve[3], ce[3];                // edge-feature update (layers after the first), -1 without
     int64_t Wh, bh, Y, Wg, bg;
   };
   std::vector<Layer> mp;
@@ -67,6 +68,7 @@ struct Plan {
 struct Workspace {
   size_t geom, vpot;
   size_t rho[3], ehid[3], wjet[3];
+  size_t rho2[3];  // the updated edge features (with edge updates: ping-pong with rho)
   size_t x0, f, h, m, mn5, zn5;
   size_t phi[2], ajet;
   size_t dld, dsg, dg, dlap;
@@ -90,6 +92,8 @@ struct BwdWorkspace {
   // cotangents, the unit cotangent, log|psi|, the Jastrow value; Langevin proposals (positions,
   // their gradient, log|psi|)
   size_t dee, den, rhobar, x0bar, ones, lpv, jval, prop;
+  size_t ecarry[3];      // with edge updates: cotangent of a layer's edge features from the next layer
+  int64_t blk_r[3];      // bytes of one layer's edge features (rho holds every layer's with edge updates)
   int64_t wpart_elems;
   int64_t rows_per_split;
   int max_split;

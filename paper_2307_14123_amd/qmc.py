@@ -31,7 +31,8 @@ class QmcAnsatz(ctypes.Structure):
     _fields_ = [("version", ctypes.c_int32), ("n_rbf", ctypes.c_int32), ("rbf_dmax", ctypes.c_double),
                 ("init_layers", ctypes.c_int32), ("width", ctypes.c_int32), ("mp_layers", ctypes.c_int32),
                 ("n_det", ctypes.c_int32), ("n_env", ctypes.c_int32), ("include_vnn", ctypes.c_int32),
-                ("ee_cusp", ctypes.c_double), ("jastrow", ctypes.c_int32), ("full_det", ctypes.c_int32)]
+                ("ee_cusp", ctypes.c_double), ("jastrow", ctypes.c_int32), ("full_det", ctypes.c_int32),
+                ("edge_update", ctypes.c_int32)]
 
 
 _lib = None
@@ -116,7 +117,8 @@ def _stream():
 def make_ansatz(ans) -> QmcAnsatz:
     return QmcAnsatz(1, ans.n_rbf, float(ans.rbf_dmax), ans.init_layers, ans.width, ans.mp_layers, ans.n_det,
                      ans.n_env, ans.include_vnn, float(getattr(ans, "ee_cusp", 0.0)),
-                     int(getattr(ans, "jastrow", 0)), int(getattr(ans, "full_det", 0)))
+                     int(getattr(ans, "jastrow", 0)), int(getattr(ans, "full_det", 0)),
+                     int(getattr(ans, "edge_update", 0)))
 
 
 class _SysHolder:

@@ -167,16 +167,17 @@ def test_sgd_update_rejects_bad_arguments():
 
 
 def test_ansatz_options_count_and_limits():
-    """Parameter counts with the Jastrow and full-determinant options match the blob layout; invalid
+    """Parameter counts with the Jastrow, full-determinant and edge-update options match the blob layout; invalid
     option values and a full determinant above 32 electrons are rejected."""
     import dataclasses
     qmc, L = _lib()
     for s in (qi.N2, qi.C4H4, qi.System((3.0, 1.0), ((0.0, 0.0, 0.0), (1.6, 0.2, -0.3)), 3, 1)):
-        for opts in ({"jastrow": 1}, {"full_det": 1}, {"jastrow": 1, "full_det": 1, "ee_cusp": 0.5}):
+        for opts in ({"jastrow": 1}, {"full_det": 1}, {"jastrow": 1, "full_det": 1, "ee_cusp": 0.5},
+                     {"edge_update": 1}, {"edge_update": 1, "mp_layers": 1}, {"edge_update": 1, "jastrow": 1}):
             a = dataclasses.replace(qi.N2_ANSATZ, **opts)
             assert qmc.param_count(s, a) == qi.param_count(s, a)
     h = qmc._SysHolder(qi.N2)
-    for opts in ({"jastrow": 2}, {"full_det": -1}, {"ee_cusp": -1.0}, {"ee_cusp": float("inf")}):
+    for opts in ({"jastrow": 2}, {"full_det": -1}, {"ee_cusp": -1.0}, {"ee_cusp": float("inf")}, {"edge_update": 3}):
         a = qmc.make_ansatz(dataclasses.replace(qi.N2_ANSATZ, **opts))
         assert L.qmc_param_count(ctypes.byref(h.s), ctypes.byref(a)) < 0
     big = qi.atom(33)
