@@ -19,8 +19,8 @@
 // waves (three per SIMD); each wave takes 16 pair rows at a time.  A launch
 // writes 128 output columns from c0 on: width 256 takes two launches, each
 // recomputing the 256 hidden units (the half of U2 it needs fills 128 KB of LDS).  The radial
-// basis is evaluated in float64 and rounded, as in the separate basis kernel;
-// tanh is the float32 form of act.h.
+// basis takes its exponent in float64 and the exponential of its fractional part
+// in float32 (rbf3_f32); tanh is the float32 form of act.h.
 #include <algorithm>
 #include <cstdlib>
 
@@ -33,6 +33,24 @@ namespace qmc {
 typedef float f4 __attribute__((ext_vector_type(4)));
 
 constexpr int ED = 128;  // output columns per launch
+
+// Gaussian basis function k of the distance d and its first two derivatives in d.  The offset, its
+// square and the base-2 exponent y = -x^2 log2(e) are formed in float64 (d up to tens of bohr loses
+// no digits to the centre's cancellation), y is split into an integer n and a fraction f in [0, 1),
+// and only 2^f is evaluated in float32 (the hardware exp2), then scaled by 2^n: the value carries
+// about one float32 rounding at any argument.  The float64 exponential it replaces was the largest
+// VALU cost per pair.  A NaN distance gives NaN; exponents below -200 give 0.
+__device__ inline void rbf3_f32(double d, int k, double s, double inv_s, float& r0, float& r1, float& r2) {
+  const double x = (d - k * s) * inv_s;
+  double y = -(x * x) * 1.4426950408889634;  // log2(e)
+  if (y < -200.0) y = -200.0;
+  const double fl = floor(y);
+  const float xf = (float)x, is = (float)inv_s;
+  const float e = ldexpf(__builtin_amdgcn_exp2f((float)(y - fl)), (int)fl);
+  r0 = e;
+  r1 = -2.f * xf * is * e;
+  r2 = (4.f * xf * xf - 2.f) * (is * is) * e;
+}
 
 // EH: hidden (and full output) width, 128 or 256; c0: first output column of this launch
 template <int JET, int NW, int EH>
@@ -85,9 +103,9 @@ __global__ __launch_bounds__(64 * NW) void edge_mlp_kernel(SysDev s, EdgeMlpArgs
         for (int kq = 0; kq < 4; ++kq) {
           const int r = 4 * g + kq;
           if (r < K) {
-            double r0, r1, r2;
-            rbf3(d, r, rs, ris, r0, r1, r2);
-            rb[kq] = (float)(e == 0 ? r0 : (e == 1 ? r1 : r2));
+            float r0, r1, r2;
+            rbf3_f32(d, r, rs, ris, r0, r1, r2);
+            rb[kq] = e == 0 ? r0 : (e == 1 ? r1 : r2);
           }
         }
       }
