@@ -80,8 +80,24 @@ __global__ __launch_bounds__(64 * NW) void edge_mlp_kernel(SysDev s, EdgeMlpArgs
   const int64_t ntiles = (a.pairs + PPT - 1) / PPT;
   const int pc = JET ? c / 3 : c;           // pair of this lane's row within the tile
   const int e = JET ? c - 3 * pc : 0;       // its jet entry: value, first, second derivative
-  for (int64_t tile = (int64_t)blockIdx.x * NW + wave; tile < ntiles; tile += (int64_t)gridDim.x * NW) {
+  // distance of this lane's pair row in a tile (0 for idle rows and with precomputed features)
+  auto pair_distance = [&](int64_t tl) -> double {
+    const int64_t pr = tl * PPT + pc;
+    if ((JET && c >= 15) || pr >= a.pairs || a.feat) return 0.0;
+    const int64_t w = pr / P;
+    const int pi = (int)(pr - w * P);
+    int i, j;
+    decode_pair(s, a.type, pi, i, j);
+    return a.type == 2 ? a.en[((w * s.N + i) * s.M + j) * 4] : a.ee[((w * s.N + i) * s.N + j) * 4];
+  };
+  const int64_t tstride = (int64_t)gridDim.x * NW;
+  int64_t tile = (int64_t)blockIdx.x * NW + wave;
+  // the next tile's distance is loaded one tile ahead, so its gather latency hides behind the MFMAs
+  double dnext = tile < ntiles ? pair_distance(tile) : 0.0;
+  for (; tile < ntiles; tile += tstride) {
     const int64_t p0 = tile * PPT;
+    const double d = dnext;
+    if (tile + tstride < ntiles) dnext = pair_distance(tile + tstride);
     // ---- this lane's pair row (column c of the first layer)
     const int64_t pr = p0 + pc;
     const bool rowok = (!JET || c < 15) && pr < a.pairs;
@@ -94,11 +110,6 @@ __global__ __launch_bounds__(64 * NW) void edge_mlp_kernel(SysDev s, EdgeMlpArgs
         for (int kq = 0; kq < 4; ++kq)
           if (4 * g + kq < K) rb[kq] = fr[4 * g + kq];
       } else {
-        const int64_t w = pr / P;
-        const int pi = (int)(pr - w * P);
-        int i, j;
-        decode_pair(s, a.type, pi, i, j);
-        const double d = a.type == 2 ? a.en[((w * s.N + i) * s.M + j) * 4] : a.ee[((w * s.N + i) * s.N + j) * 4];
 #pragma unroll
         for (int kq = 0; kq < 4; ++kq) {
           const int r = 4 * g + kq;
