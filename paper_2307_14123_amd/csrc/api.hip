@@ -176,6 +176,8 @@ static qmc_status forward_chunk(const Plan& P, const SysPlan& s, const S* prm, c
   S* fe[3] = {rho[0], rho[1], rho[2]};  // the edge features the filters read
   for (int l = 0; l < P.ans.mp_layers; ++l) {
     const auto& Ly = O.mp[l];
+    EdgeMlpArgs eb[3];  // the fused filters of this layer, one launch for all types
+    int ne = 0;
     for (int t = 0; t < 3; ++t) {
       const int64_t re = wc * s.P[t] * Re;
       if (re == 0) continue;
@@ -188,9 +190,8 @@ static qmc_status forward_chunk(const Plan& P, const SysPlan& s, const S* prm, c
       }
       if constexpr (std::is_same<S, float>::value) {
         if (fused) {
-          EdgeMlpArgs ea{prm + Ly.U1[t], prm + Ly.a1[t], prm + Ly.U2[t], prm + Ly.a2[t], ee, en, wj[t], nullptr,
-                         wc * s.P[t], t, jet, Ly.Ve[t] >= 0 ? (const float*)fe[t] : nullptr};
-          CK(launch_edge_mlp(dv, ea, st));
+          eb[ne++] = EdgeMlpArgs{prm + Ly.U1[t], prm + Ly.a1[t], prm + Ly.U2[t], prm + Ly.a2[t], ee, en, wj[t],
+                                 nullptr, wc * s.P[t], t, jet, Ly.Ve[t] >= 0 ? (const float*)fe[t] : nullptr};
           continue;
         }
       }
@@ -199,6 +200,7 @@ static qmc_status forward_chunk(const Plan& P, const SysPlan& s, const S* prm, c
       CK(gemm(s, gk, dense(ehid[t], D, prm + Ly.U2[t], D, prm + Ly.a2[t], wj[t], D, re, (int)D, (int)D, Re, 1, 0, vm),
                      st));
     }
+    if (ne > 0) CK(launch_edge_mlp_types(dv, eb, ne, st));
     CK(gemm(s, gk, dense(f, D, prm + Ly.Wh, D, prm + Ly.bh, h, D, rows, (int)D, (int)D, Rp, s.T, 0, vm), st));
     CK(launch_aggregate<S>(dv, h, wj[0], wj[1], wj[2], prm + Ly.Y, ee, en, wc, jet, m, st));
     if (jet) {
@@ -390,6 +392,8 @@ static qmc_status forward_stash(const Plan& P, const SysPlan& s, const S* prm, c
   S* fprev = F_(B.finit, B.blk_f, L0 - 1);
   for (int l = 0; l < L; ++l) {
     const auto& Ly = O.mp[l];
+    EdgeMlpArgs eb[3];  // the fused filters of this layer, one launch for all types
+    int ne = 0;
     for (int t = 0; t < 3; ++t) {
       const int64_t re = wc * s.P[t];
       if (re == 0) continue;
@@ -403,15 +407,15 @@ static qmc_status forward_stash(const Plan& P, const SysPlan& s, const S* prm, c
       if constexpr (std::is_same<S, float>::value) {
         if (fused_edges(P, true) && edge_mlp_supported(dv)) {
           // the hidden layer is kept for the backward
-          EdgeMlpArgs ea{prm + Ly.U1[t], prm + Ly.a1[t], prm + Ly.U2[t], prm + Ly.a2[t], ee, en, wv, eh, re, t, 0,
-                         Ly.Ve[t] >= 0 ? (const float*)fe : nullptr};
-          CK(launch_edge_mlp(dv, ea, st));
+          eb[ne++] = EdgeMlpArgs{prm + Ly.U1[t], prm + Ly.a1[t], prm + Ly.U2[t], prm + Ly.a2[t], ee, en, wv, eh, re, t,
+                                 0, Ly.Ve[t] >= 0 ? (const float*)fe : nullptr};
           continue;
         }
       }
       CK(gemm(s, gk, dense(fe, K, prm + Ly.U1[t], D, prm + Ly.a1[t], eh, D, re, (int)K, (int)D, 1, 0, 1, 1), st));
       CK(gemm(s, gk, dense(eh, D, prm + Ly.U2[t], D, prm + Ly.a2[t], wv, D, re, (int)D, (int)D, 1, 0, 0, 1), st));
     }
+    if (ne > 0) CK(launch_edge_mlp_types(dv, eb, ne, st));
     S* h = F_(B.hst, B.blk_f, l);
     S* m = F_(B.mst, B.blk_m, l);
     S* t = F_(B.tst, B.blk_f, l);

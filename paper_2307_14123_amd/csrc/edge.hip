@@ -23,6 +23,7 @@
 // in float32 (rbf3_f32); tanh is the float32 form of act.h.
 #include <algorithm>
 #include <cstdlib>
+#include <cstring>
 
 #include "act.h"
 #include "kernels.h"
@@ -53,8 +54,20 @@ __device__ inline void rbf3_f32(double d, int k, double s, double inv_s, float& 
 }
 
 // EH: hidden (and full output) width, 128 or 256; c0: first output column of this launch
+// Up to three edge types in one launch: blocks [0, b1) take type slot 0, [b1, b2) slot 1, [b2, grid)
+// slot 2, each walking its type's tiles with a stride of its own block count.
+struct EdgeMlpBatch {
+  EdgeMlpArgs t[3];
+  int b1, b2;
+};
+
 template <int JET, int NW, int EH>
-__global__ __launch_bounds__(64 * NW) void edge_mlp_kernel(SysDev s, EdgeMlpArgs a, int c0) {
+__global__ __launch_bounds__(64 * NW) void edge_mlp_kernel(SysDev s, EdgeMlpBatch B, int c0) {
+  const int slot = (int)blockIdx.x < B.b1 ? 0 : ((int)blockIdx.x < B.b2 ? 1 : 2);
+  const int bstart = slot == 0 ? 0 : (slot == 1 ? B.b1 : B.b2);
+  const int bcount = (slot == 0 ? B.b1 : (slot == 1 ? B.b2 : (int)gridDim.x)) - bstart;
+  // (selected field by field: the slot is uniform, and no copy of the batch goes to scratch)
+  const EdgeMlpArgs a = slot == 0 ? B.t[0] : (slot == 1 ? B.t[1] : B.t[2]);
   __shared__ __attribute__((aligned(16))) float u2t[ED * EH];  // U2^T (n, k), chunk (k/4) ^ (n & 7)
   __shared__ __attribute__((aligned(16))) float u1t[EH * 16];  // U1^T (k, r), r < 16
   __shared__ float a1s[EH], a2s[ED];
@@ -90,8 +103,8 @@ __global__ __launch_bounds__(64 * NW) void edge_mlp_kernel(SysDev s, EdgeMlpArgs
     decode_pair(s, a.type, pi, i, j);
     return a.type == 2 ? a.en[((w * s.N + i) * s.M + j) * 4] : a.ee[((w * s.N + i) * s.N + j) * 4];
   };
-  const int64_t tstride = (int64_t)gridDim.x * NW;
-  int64_t tile = (int64_t)blockIdx.x * NW + wave;
+  const int64_t tstride = (int64_t)bcount * NW;
+  int64_t tile = (int64_t)((int)blockIdx.x - bstart) * NW + wave;
   // the next tile's distance is loaded one tile ahead, so its gather latency hides behind the MFMAs
   double dnext = tile < ntiles ? pair_distance(tile) : 0.0;
   for (; tile < ntiles; tile += tstride) {
@@ -192,40 +205,62 @@ __global__ __launch_bounds__(64 * NW) void edge_mlp_kernel(SysDev s, EdgeMlpArgs
 bool edge_mlp_supported(const SysDev& s) { return (s.D == 128 || s.D == 256) && s.K >= 2 && s.K <= 16; }
 
 hipError_t launch_edge_mlp(const SysDev& s, const EdgeMlpArgs& a, hipStream_t st) {
-  if (!edge_mlp_supported(s) || a.pairs < 0 || a.type < 0 || a.type > 2) return hipErrorInvalidValue;
-  if (a.pairs == 0) return hipSuccess;
-  if (a.jet && a.zout) return hipErrorInvalidValue;
-  static int cus = 0, nw = 0;
+  return launch_edge_mlp_types(s, &a, 1, st);
+}
+
+hipError_t launch_edge_mlp_types(const SysDev& s, const EdgeMlpArgs* a, int n, hipStream_t st) {
+  if (!edge_mlp_supported(s) || n < 1 || n > 3) return hipErrorInvalidValue;
+  EdgeMlpBatch B;
+  std::memset(&B, 0, sizeof(B));
+  int64_t tiles[3] = {0, 0, 0}, total = 0;
+  int m = 0;  // slots with pairs
+  for (int i = 0; i < n; ++i) {
+    if (a[i].pairs < 0 || a[i].type < 0 || a[i].type > 2 || a[i].jet != a[0].jet) return hipErrorInvalidValue;
+    if (a[i].pairs == 0) continue;
+    B.t[m] = a[i];
+    tiles[m] = a[i].jet ? (a[i].pairs + 4) / 5 : (a[i].pairs + 15) / 16;
+    total += tiles[m++];
+  }
+  if (m == 0) return hipSuccess;
+  const int jet = a[0].jet;
+  static int cus = 0, nw = 12;
   if (cus == 0) {
-    int dev = 0, n = 0;
+    int dev = 0, c = 0;
     cus = (hipGetDevice(&dev) == hipSuccess &&
-           hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && n > 0)
-              ? n
+           hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && c > 0)
+              ? c
               : 256;
     // waves per block: 12 (three per SIMD, one block per compute unit: the VGPR budget) by default;
     // QMC_EDGE_WAVES=4 for two blocks of 4 (a tuning knob)
     const char* e = std::getenv("QMC_EDGE_WAVES");
     nw = e && std::atoi(e) == 4 ? 4 : 12;
   }
-  const int64_t tiles = a.jet ? (a.pairs + 4) / 5 : (a.pairs + 15) / 16;
-  // blocks of nw waves share one copy of the weights in LDS (73 KB); as many blocks as fit per
-  // compute unit, each walking tiles with a grid stride
+  // blocks of w waves share one copy of their type's weights in LDS (73 KB); as many blocks as fit
+  // per compute unit, split among the types in proportion to their tiles (at least one each, at
+  // most one per w tiles), each type's blocks walking its tiles with a stride
   auto go = [&](auto kern, int w, int c0) {
     int occ = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, 64 * w, 0) != hipSuccess || occ < 1) occ = 1;
-    const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>((tiles + w - 1) / w, (int64_t)occ * cus));
-    hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(64 * w), 0, st, s, a, c0);
+    const int64_t cap = (int64_t)occ * cus;
+    int64_t nb[3] = {0, 0, 0}, sum = 0;
+    for (int i = 0; i < m; ++i) {
+      nb[i] = std::max<int64_t>(1, std::min<int64_t>((tiles[i] + w - 1) / w, cap * tiles[i] / total));
+      sum += nb[i];
+    }
+    B.b1 = (int)nb[0];
+    B.b2 = (int)(nb[0] + nb[1]);
+    hipLaunchKernelGGL(kern, dim3((unsigned)sum), dim3(64 * w), 0, st, s, B, c0);
   };
-  ProfScope ps(a.jet ? "edge_mlp_kernel<jet>" : "edge_mlp_kernel<val>", st);
+  ProfScope ps(jet ? "edge_mlp_kernel<jet>" : "edge_mlp_kernel<val>", st);
   if (s.D == 256) {
     // the 256 hidden units take 64 more registers: two waves per SIMD
     for (int c0 = 0; c0 < 256; c0 += ED) {
-      if (a.jet)
+      if (jet)
         go(edge_mlp_kernel<1, 8, 256>, 8, c0);
       else
         go(edge_mlp_kernel<0, 8, 256>, 8, c0);
     }
-  } else if (a.jet) {
+  } else if (jet) {
     if (nw == 4)
       go(edge_mlp_kernel<1, 4, 128>, 4, 0);
     else

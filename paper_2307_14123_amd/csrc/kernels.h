@@ -96,6 +96,9 @@ struct EdgeMlpArgs {
 };
 bool edge_mlp_supported(const SysDev& s);
 hipError_t launch_edge_mlp(const SysDev& s, const EdgeMlpArgs& a, hipStream_t st);
+// the filters of n (1..3) edge types in one launch (all value rows or all jets), the blocks split
+// among the types in proportion to their tiles
+hipError_t launch_edge_mlp_types(const SysDev& s, const EdgeMlpArgs* a, int n, hipStream_t st);
 
 hipError_t launch_geometry(const SysDev& s, const double* r, int64_t W, double* ee, double* en,
                            double* vpot, hipStream_t st);
