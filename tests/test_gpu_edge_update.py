@@ -12,10 +12,9 @@ import torch
 
 import oracle
 import qmc_inputs as qi
-from oracle.ansatz import orbital_matrices
-from oracle.layout import param_shapes, unpack
+from oracle.layout import param_shapes
 from tests.gpu_common import dev, host, rel_err
-from tests.test_gpu_parity import _compare_fp64, _run_le
+from tests.test_gpu_parity import _compare_fp64, _run_le, cancellation
 
 pytestmark = pytest.mark.gpu
 
@@ -44,17 +43,6 @@ def _update_slices(s, a):
             out.append(slice(off, off + n))
         off += n
     return out
-
-
-def _cancellation(r, p, s, a):
-    """Per walker, sum_p |c_p det_p| / |sum_p c_p det_p| (oracle-computed): the factor by which the
-    determinant combination magnifies the rounding of its terms in log|psi| and its derivatives."""
-    P = unpack(torch.as_tensor(p), s, a)
-    mats = orbital_matrices(torch.as_tensor(r), P, s, a)
-    ld = sum(torch.linalg.slogdet(A)[1] for A in mats if A is not None).numpy()
-    sg = np.prod([torch.linalg.slogdet(A)[0].numpy() for A in mats if A is not None], axis=0)
-    t = P["c"].numpy()[None] * sg * np.exp(ld - ld.max(1, keepdims=True))
-    return np.abs(t).sum(1) / np.abs(t.sum(1))
 
 
 def _normwise(g, ref):
@@ -91,7 +79,7 @@ def test_loss_grad_with_edge_update(prec, tol):
     parity covers every walker."""
     s, a, p, r = _n2(24 if prec == "fp32" else 16)
     if prec == "fp32":
-        keep = _cancellation(r, p, s, a) < 100.0
+        keep = cancellation(r, p, s, a) < 100.0
         assert keep.sum() >= 16
         r = np.ascontiguousarray(r[keep][:16])
     q = _q()

@@ -47,6 +47,19 @@ def flagged(r, p, s, a):
     return bad
 
 
+def cancellation(r, p, s, a):
+    """Per walker, sum_p |c_p det_p| / |sum_p c_p det_p| (oracle-computed, spin-factorised
+    determinants): the factor by which the determinant combination magnifies the rounding of its
+    terms in log|psi| and its derivatives.  float32 comparisons of log|psi| and the loss gradient
+    take walkers below 100."""
+    P = unpack(torch.as_tensor(p), s, a)
+    mats = orbital_matrices(torch.as_tensor(r), P, s, a)
+    ld = sum(torch.linalg.slogdet(A)[1] for A in mats if A is not None).numpy()
+    sg = np.prod([torch.linalg.slogdet(A)[0].numpy() for A in mats if A is not None], axis=0)
+    t = P["c"].numpy()[None] * sg * np.exp(ld - ld.max(1, keepdims=True))
+    return np.abs(t).sum(1) / np.abs(t.sum(1))
+
+
 def _run_le(s, a, p, r, precision):
     q = _q()
     plan = q.Plan([s], [r.shape[0]], a, precision)
@@ -329,3 +342,39 @@ def test_metropolis_zero_step_accepts_all():
     torch.cuda.synchronize()
     assert np.all(host(acc) == 1)
     np.testing.assert_array_equal(host(R).reshape(r.shape), r)
+
+
+@pytest.mark.parametrize("name,system", [("h_atom", qi.atom(1)), ("h2_chain", qi.hydrogen_chain(2)),
+                                         ("li_2up_1dn", qi.atom(3))])
+def test_fp32_fused_filters_with_missing_edge_types(name, system):
+    """The fused float32 edge filters of a layer run as one launch over the edge types that have
+    pairs: one type (a single electron: nuclear edges only), two (one electron per spin: no
+    same-spin pairs) or three.  Width-128 ansatz, float32 plan: E_L within 2e-5 of its largest
+    addend, value-mode and jet-mode log|psi| within the float32 value-mode bar (2e-4) of the
+    oracle, and the loss gradient within 2e-3 normwise, on walkers whose determinant terms cancel
+    by less than 100x (one of the first 40 Li walkers cancels by 454x)."""
+    a = qi.N2_ANSATZ
+    p = qi.make_params(system, a, 91)
+    r = qi.make_walkers(system, 48, 92)
+    r = np.ascontiguousarray(r[cancellation(r, p, system, a) < 100.0][:40])
+    assert r.shape[0] == 40
+    ref = oracle.local_energy(r, p, system, a)
+    q = _q()
+    plan = q.Plan([system], [40], a, "fp32")
+    P, R = dev(p, plan.param_dtype), dev(r)
+    out = plan.local_energy(P, R)
+    lp, _ = plan.logpsi(P, R)
+    g, _ = plan.loss_grad(P, R, out["e_loc"])
+    torch.cuda.synchronize()
+    got = {k: host(v) for k, v in out.items()}
+    scale = np.maximum.reduce([np.abs(ref["e_loc"]), 0.5 * np.abs(ref["lap"]),
+                               0.5 * (ref["grad"] ** 2).sum((1, 2)), np.ones_like(ref["e_loc"])])
+    e = np.abs(got["e_loc"] - ref["e_loc"]) / scale
+    Gref, _, _ = oracle.loss_grad(r, got["e_loc"], p, system, a)
+    gerr = float(np.linalg.norm(host(g) - Gref) / np.linalg.norm(Gref))
+    print(f"[{name} fp32 fused] E_L {e.max():.2e}, log|psi| jet {rel_err(got['logpsi'], ref['logpsi']).max():.2e} "
+          f"value {rel_err(host(lp), ref['logpsi']).max():.2e}, loss gradient {gerr:.2e}", flush=True)
+    assert e.max() < 2e-5
+    assert rel_err(got["logpsi"], ref["logpsi"]).max() < 2e-4
+    assert rel_err(host(lp), ref["logpsi"]).max() < 2e-4
+    assert gerr < 2e-3
