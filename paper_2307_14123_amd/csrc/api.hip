@@ -754,7 +754,7 @@ static float time_gemm(GemmKind kind, const GemmArgs& a, hipStream_t st, hipEven
 static qmc_status autotune(Plan& P) {
   const size_t E = act_bytes(P.prec);
   const int64_t D = P.ans.width, cap = int64_t(1) << 20;
-  const size_t xb = size_t(cap) * 2 * D * E, wb = size_t(2 * D) * D * E, yb = size_t(cap) * D * E;
+  const size_t xb = size_t(cap) * 2 * D * E, wb = size_t(3 * D) * D * E, yb = size_t(cap) * D * E;
   void *X = nullptr, *Wm = nullptr, *B = nullptr, *Y = nullptr;
   hipStream_t st = nullptr;
   hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -778,6 +778,11 @@ static qmc_status autotune(Plan& P) {
                   s.Rp, s.T, 1, 0);
       } else if (cls == TILE_EDGE) {
         a = dense(X, D, Wm, D, B, Y, D, std::min(cap, s.Wc * pmax * 4) / 4 * 4, (int)D, (int)D, 4, 1, 1, 0);
+      } else if (cls == TILE_VAL && fused_edges(P, true) && edge_mlp_supported(make_dev(P, s))) {
+        // the value-row edge filters run fused: the node products dominate, the message product
+        // (K = 3D) the most
+        // (rows x 3D inputs within the 2D x cap buffer)
+        a = dense(X, 3 * D, Wm, D, B, Y, D, std::min(cap * 2 / 3, s.Wc * s.N), (int)(3 * D), (int)D, 1, 0, 1, 1);
       } else {
         a = dense(X, D, Wm, D, B, Y, D, std::min(cap, s.Wc * pmax), (int)D, (int)D, 1, 0, 0, 1);
         a.transw = cls == TILE_BWD;
