@@ -4,6 +4,8 @@
 // electron-nucleus pairs).
 #pragma once
 
+#include <type_traits>
+
 #include "kernels.h"
 
 namespace qmc {
@@ -16,6 +18,26 @@ __device__ inline void rbf3(double d, int k, double s, double inv_s, double& r0,
   r0 = exp(-x * x);
   r1 = -2.0 * x * inv_s * r0;
   r2 = (4.0 * x * x - 2.0) * (inv_s * inv_s) * r0;
+}
+
+// The same basis for kernels whose outputs are rounded to S.  For float, the exponent
+// y = -x^2 log2(e) is formed in float64 and split into an integer n and a fraction f in [0, 1),
+// and only 2^f is taken in float32 (the hardware exp2), scaled by 2^n: about one float32 rounding
+// at any argument, against a float64 exponential's several dozen float64 instructions.  A NaN
+// distance gives NaN; exponents below -200 give 0.
+template <typename S>
+__device__ inline void rbf3_as(double d, int k, double s, double inv_s, double& r0, double& r1, double& r2) {
+  if constexpr (std::is_same<S, float>::value) {
+    const double x = (d - k * s) * inv_s;
+    double y = -(x * x) * 1.4426950408889634;  // log2(e)
+    if (y < -200.0) y = -200.0;
+    const double fl = floor(y);
+    r0 = (double)ldexpf(__builtin_amdgcn_exp2f((float)(y - fl)), (int)fl);
+    r1 = -2.0 * x * inv_s * r0;
+    r2 = (4.0 * x * x - 2.0) * (inv_s * inv_s) * r0;
+  } else {
+    rbf3(d, k, s, inv_s, r0, r1, r2);
+  }
 }
 
 // unordered pair index of electrons i != j inside their edge type (0 same-spin, 1 up-down)

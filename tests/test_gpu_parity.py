@@ -253,7 +253,7 @@ def test_fp32_value_mode_logpsi():
     le = plan.local_energy(P, dev(r))
     torch.cuda.synchronize()
     ref_s, ref_l = oracle.logpsi_np(r, p.astype(np.float32).astype(np.float64), s, a)
-    ok = ~flagged(r, p, s, a)
+    ok = ~flagged(r, p, s, a) & (cancellation(r, p, s, a) < 100.0)
     e_or = np.abs(host(lp) - ref_l)[ok]
     e_jet = np.abs(host(lp) - host(le["logpsi"]))[ok]
     print(f"[fp32 value logpsi] max |dlogpsi| vs oracle {e_or.max():.3e}, vs jet path {e_jet.max():.3e}", flush=True)
