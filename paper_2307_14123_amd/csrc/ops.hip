@@ -94,7 +94,11 @@ __global__ void rbf_kernel(SysDev s, int type, const double* __restrict__ ee, co
   decode_pair(s, type, p, i, j);
   const double d = (type == 2) ? en[((w * s.N + i) * s.M + j) * 4] : ee[((w * s.N + i) * s.N + j) * 4];
   double r0, r1, r2;
-  rbf3_as<S>(d, k, rbf_spacing(s.dmax, s.K), (s.K - 1) / s.dmax, r0, r1, r2);
+  // value rows take the float32 exponential; jets, which carry the local energy, the float64 one
+  if (jet)
+    rbf3(d, k, rbf_spacing(s.dmax, s.K), (s.K - 1) / s.dmax, r0, r1, r2);
+  else
+    rbf3_as<S>(d, k, rbf_spacing(s.dmax, s.K), (s.K - 1) / s.dmax, r0, r1, r2);
   if (jet) {
     S* o = rho + wp * 4 * s.K + k;
     o[0] = (S)r0;
@@ -138,7 +142,11 @@ __global__ void init_features_kernel(SysDev s, const double* __restrict__ ee, co
     const int I = f / K, k = f % K;
     const double* g = en + ((w * s.N + i) * s.M + I) * 4;
     double r0, r1, r2;
-    rbf3_as<S>(g[0], k, rbf_spacing(s.dmax, K), (K - 1) / s.dmax, r0, r1, r2);
+    // value rows take the float32 exponential; jets, which carry the local energy, the float64 one
+    if (jet)
+      rbf3(g[0], k, rbf_spacing(s.dmax, K), (K - 1) / s.dmax, r0, r1, r2);
+    else
+      rbf3_as<S>(g[0], k, rbf_spacing(s.dmax, K), (K - 1) / s.dmax, r0, r1, r2);
     out[0] = (S)r0;
     if (!jet) return;
     for (int q = 1; q < Rp; ++q) {
@@ -179,7 +187,7 @@ __global__ void init_features_kernel(SysDev s, const double* __restrict__ ee, co
     if (j == i) continue;
     double r0, r1, r2;
     const double* g = eei + j * 4;
-    rbf3_as<S>(g[0], k, sp, isp, r0, r1, r2);
+    rbf3(g[0], k, sp, isp, r0, r1, r2);
     val += r0;
     for (int a = 0; a < 3; ++a) gs[a] += r1 * g[1 + a];
     lap += 2.0 * r2 + 4.0 * r1 / g[0];
@@ -194,7 +202,7 @@ __global__ void init_features_kernel(SysDev s, const double* __restrict__ ee, co
       } else if (j >= lo && j < hi) {
         const double* g = eei + j * 4;
         double r0, r1, r2;
-        rbf3_as<S>(g[0], k, sp, isp, r0, r1, r2);
+        rbf3(g[0], k, sp, isp, r0, r1, r2);
         v = -r1 * g[1 + a] * inv;
       }
     } else if (q == s.T + 1) {
