@@ -1,9 +1,11 @@
 """Benchmark of the VMC hot path on one MI355X.
 
-One step = the whole hot path over one batch of walkers: 10 random-walk
-Metropolis steps (each a full log|psi| evaluation of the proposals), the local
-energy with exact gradient and Laplacian, the loss gradient and the
-gradient-descent update of the parameters.  Workload: the N2-sized system (two
+One step = one VMC training iteration over one batch of walkers: 10
+random-walk Metropolis steps (each a full log|psi| evaluation of the
+proposals), the local energy with exact gradient and Laplacian, clipping of
+the local energies, the loss gradient, the gradient-descent update of the
+parameters, and log|psi| of the walkers under the updated parameters (the
+state the next iteration's Metropolis steps compare against).  Workload: the N2-sized system (two
 Z=7 nuclei 2.068 bohr apart, 7 up + 7 down electrons, 4096 walkers, 4
 message-passing layers of width 128, 16 determinants, 8 envelope exponents),
 float32 jets with float64 determinants.  Inputs are seeded, synthetic and
@@ -67,7 +69,9 @@ def algorithmic_model(s, a, elem_bytes, n_mc, with_grad, fused_edges):
     # data cotangents of the backward (x_bar = y_bar W^T), weight gradients (W_bar = x^T y_bar)
     val_bwd = 2 * D * nd * nsq + L * (2 * N * 3 * D * D + 2 * N * D * D + sum(P) * 2 * D * D) + (L0 - 1) * 2 * N * D * D
     wgrad = node_val + edge_val
-    n_val = n_mc + (1 if with_grad else 0)
+    # value forwards per step: the Metropolis proposals, the loss gradient's stashed forward and, after
+    # the parameter update, log|psi| of the walkers under the new parameters
+    n_val = n_mc + (2 if with_grad else 0)
     m = {
         "gemm_kernel<jet>": ("mfma", node_jet),
         "gemm_kernel<val>": ("mfma", n_val * node_val + (0 if fused_edges else n_val * edge_val)
@@ -178,6 +182,8 @@ def main():
     ap.add_argument("--full-det", action="store_true", help="one N x N determinant per p over both spins")
     ap.add_argument("--edge-update", action="store_true",
                     help="update the edge features in every interaction layer after the first")
+    ap.add_argument("--no-sub-records", action="store_true",
+                    help="skip the fp64_form / c4h4 / batched sub-records of the default n2 line")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="end with a plain 256 MiB device copy, the reference for traffic counters")
     args = ap.parse_args()
@@ -248,6 +254,9 @@ def main():
             plan.clip_local_energy(out["e_loc"], clip_width, "hard", out=EC)
             plan.loss_grad(P, R, EC, grad=G, e_mean=EM)
             plan.sgd_update(P, G, lr)
+            # the sampler follows psi under the updated parameters: the next step's Metropolis
+            # comparisons need log|psi| of the current walkers under them
+            plan.logpsi(P, R, out=(lp, None))
 
     for _ in range(args.warmup):
         step()
@@ -433,10 +442,15 @@ def main():
                                + (", edge-feature updates" if a.edge_update else "")
                                + f"; step = {n_mc} Metropolis steps (tau {tau}) + "
                                f"local energy" + (" + clipping (median +- 5 mean absolute deviations) + loss "
-                                                  "gradient + gradient-descent update (lr 1e-8)"
-                                                  if has_grad else ""),
+                                                  "gradient + gradient-descent update (lr 1e-8) + log|psi| under "
+                                                  "the updated parameters" if has_grad else ""),
                    "walkers": W, "electrons": s.n_elec, "precision": args.precision, "tiles": plan.tiles()[0],
-                   "loss_gradient_in_step": has_grad},
+                   "chunk_walkers": plan.chunk_walkers()[0],
+                   "loss_gradient_in_step": has_grad,
+                   "step_vs_plain_definition": ("adds clipping of the local energies before the loss gradient "
+                                                "(0.13 ms) and the log|psi| refresh after the update (one value "
+                                                "forward) to 10 Metropolis steps + local energy + loss gradient "
+                                                "+ update" if has_grad else "no loss gradient")},
         "e_loc_per_s": W / (ms_le * 1e-3),
         "e_loc_ms": ms_le,
         "step_ms_events": dist(step_ms),
@@ -501,14 +515,28 @@ def main():
         res["cpu_baseline_1thread"] = {"value": n1 / sum(parts1), "unit": "walkers/s", "cores": 1,
                                        "e_loc_per_s": n1 / parts1[1],
                                        "sample": f"{n1} walkers, {sum(parts1):.1f} s"}
-        # error of the GPU local energy on the same sample positions
-        Rs = torch.as_tensor(rs, device=dev).contiguous()
-        sub = qmc.Plan([s], [nw], a, args.precision)
-        o2 = sub.local_energy(P, Rs)
+        # error of the GPU local energy on the same sample positions, from the timed (autotuned) plan
+        # itself: the sample is written into the first walkers of the full batch
+        R.view(W, s.n_elec, 3)[:nw] = torch.as_tensor(rs, device=dev)
+        plan.local_energy(P, R, out=out)
         torch.cuda.synchronize()
-        err = np.abs(o2["e_loc"].cpu().numpy() - ref["e_loc"]) * 1e3
+        err = np.abs(out["e_loc"][:nw].cpu().numpy() - ref["e_loc"]) * 1e3
         res["e_loc_err_mha_vs_fp64_oracle"] = {"p50": float(np.median(err)), "p99": float(np.percentile(err, 99)),
-                                               "max": float(err.max()), "walkers": nw}
+                                               "max": float(err.max()), "walkers": nw,
+                                               "plan": f"the timed plan ({W} walkers, tiles {plan.tiles()[0]}), "
+                                                       f"sample in its first {nw} walkers"}
+    if args.workload == "n2" and args.precision == "fp32" and not args.no_sub_records and not (
+            a.jastrow or a.ee_cusp > 0 or a.full_det or a.edge_update):
+        # the comparison forms, each with its own plan, freed before the next
+        del plan
+        plan = None
+        torch.cuda.empty_cache()
+        res["fp64_form"] = fp64_form_record(s, a, W, params, r0, dev)
+        torch.cuda.empty_cache()
+        res["c4h4"] = c4h4_record(dev, with_oracle=not args.no_cpu_baseline)
+        torch.cuda.empty_cache()
+        res["batched"] = batched_record(qi.workload(4).walkers, "fp32", 2, 1, dev)
+        torch.cuda.empty_cache()
     if args.copy_calibration:
         x = torch.ones(64 << 20, dtype=torch.float32, device=dev)
         y = torch.empty_like(x)
@@ -518,33 +546,88 @@ def main():
     print(json.dumps(res))
 
 
-def bench_batched(args):
-    """16 molecules x 1024 walkers: local energy + loss gradient of the whole batch as one graph launch
-    (a concurrent, autotuned plan: one stream per molecule inside the graph) against per-molecule launches
-    (one plan per molecule, run one after another)."""
+def _event_reps(fn, reps):
+    """one untimed call, then reps calls each between two HIP events on the launch stream (ms list)"""
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
+    ev[0].record()
+    for i in range(reps):
+        fn()
+        ev[i + 1].record()
+    torch.cuda.synchronize()
+    return [ev[i].elapsed_time(ev[i + 1]) for i in range(reps)]
+
+
+def fp64_form_record(s, a, W, params, r0, dev, reps=10):
+    """Local energies per second of the plain float64 GPU form (every stage in float64, autotuned
+    tiles) on the same walkers, the comparison form for the float32 plan."""
+    import torch
+    from paper_2307_14123_amd import qmc
+    plan = qmc.Plan([s], [W], a, "fp64", autotune=True)
+    P = torch.as_tensor(params, dtype=torch.float64, device=dev).contiguous()
+    R = torch.as_tensor(r0, device=dev).contiguous()
+    out = plan.local_energy(P, R)
+    ms = _event_reps(lambda: plan.local_energy(P, R, out=out), reps)
+    d = dist(ms)
+    rec = {"e_loc_per_s": W / (d["median"] * 1e-3), "e_loc_ms_events": d, "walkers": W,
+           "tiles": plan.tiles()[0], "precision": "fp64"}
+    del plan, P, R, out
+    return rec
+
+
+def c4h4_record(dev, with_oracle=True, reps=3, n_err=4):
+    """C4H4-sized system at 8192 walkers (width 256, 32 determinants): local-energy time in the float32
+    plan and in the plan with bf16 operands in the value-row forwards (bf16v), each on its own
+    autotuned plan, and the E_L error of both against the float64 oracle on a few walkers written into
+    the first rows of the full batch."""
+    import torch
+    import oracle
+    import qmc_inputs as qi
+    from paper_2307_14123_amd import qmc
+    s, a, p, r = qi.workload_inputs(3)
+    W = r.shape[0]
+    ref = oracle.local_energy(r[:n_err], p.astype(np.float32).astype(np.float64), s, a) if with_oracle else None
+    rec = {"walkers": W, "electrons": s.n_elec, "width": a.width, "dets": a.n_det}
+    for prec in ("fp32", "bf16v"):
+        plan = qmc.Plan([s], [W], a, prec, autotune=True)
+        P = torch.as_tensor(p, dtype=torch.float32, device=dev).contiguous()
+        R = torch.as_tensor(r, device=dev).contiguous()
+        out = plan.local_energy(P, R)
+        ms = _event_reps(lambda: plan.local_energy(P, R, out=out), reps)
+        d = dist(ms)
+        lp, _ = plan.logpsi(P, R)
+        torch.cuda.synchronize()
+        e = {"e_loc_ms_events": d, "e_loc_per_s": W / (d["median"] * 1e-3), "tiles": plan.tiles()[0],
+             "chunk_walkers": plan.chunk_walkers()[0]}
+        if ref is not None:
+            err = np.abs(out["e_loc"][:n_err].cpu().numpy() - ref["e_loc"]) * 1e3
+            e["e_loc_err_mha_vs_fp64_oracle"] = {"max": float(err.max()), "p50": float(np.median(err)),
+                                                 "walkers": n_err}
+            e["value_logpsi_max_abs_err"] = float(np.abs(lp[:n_err].cpu().numpy() - ref["logpsi"]).max())
+        rec[prec] = e
+        del plan, P, R, out, lp
+        torch.cuda.empty_cache()
+    return rec
+
+
+def batched_record(W, prec, steps, warmup, dev):
+    """16 molecules x W walkers: local energy + loss gradient of the whole batch as one graph launch
+    (a concurrent, autotuned plan: one stream per molecule inside the graph) against per-molecule
+    launches (one plan per molecule, run one after another)."""
     import torch
     import qmc_inputs as qi
     from paper_2307_14123_amd import qmc
 
     wl = qi.workload(4)
     mols, a = list(wl.systems), wl.ansatz
-    W = args.walkers or wl.walkers
-    prec = args.precision
-    dev = torch.device("cuda", 0)
     params = [qi.make_params(m, a, qi.seed(4, 10 + k)) for k, m in enumerate(mols)]
     pos = [qi.make_walkers(m, W, qi.seed(4, 40 + k)) for k, m in enumerate(mols)]
     dt = torch.float64 if prec == "fp64" else torch.float32
 
     def timed(fn, reps):
-        fn()
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(reps):
-            fn()
-        e1.record()
-        torch.cuda.synchronize()
-        return e0.elapsed_time(e1) / reps
+        return float(np.sum(_event_reps(fn, reps)) / reps)
 
     # per-molecule launches: one single-system plan per molecule, eager, one after another
     per_mol = []
@@ -557,7 +640,7 @@ def bench_batched(args):
         def one():
             plan.local_energy(Pm, Rm, out=o)
             plan.loss_grad(Pm, Rm, o["e_loc"])
-        per_mol.append(timed(one, max(2, args.steps)))
+        per_mol.append(timed(one, max(2, steps)))
         del plan, o
         torch.cuda.empty_cache()
     ms_per_mol = float(sum(per_mol))
@@ -573,7 +656,7 @@ def bench_batched(args):
     def eager():
         plan.local_energy(P, R, out=o)
         plan.loss_grad(P, R, o["e_loc"])
-    ms_eager = timed(eager, max(2, args.steps))
+    ms_eager = timed(eager, max(2, steps))
     # one profiled eager pass for the per-kernel split
     qmc.profile_enable(True)
     qmc.profile_report(reset=True)
@@ -582,31 +665,42 @@ def bench_batched(args):
     prof = qmc.profile_report(reset=True)
     qmc.profile_enable(False)
     g = qmc.GraphStep(plan, P, R)
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         g.replay()
-    ms_graph = timed(g.replay, args.steps)
-    Wt = W * len(mols)
+    ms_graph = timed(g.replay, steps)
+    rec = {"electrons": [m.n_up + m.n_down for m in mols], "walkers_each": W, "width": a.width, "dets": a.n_det,
+           "step": "local energy + loss gradient of every molecule",
+           "batched_graph_ms": ms_graph, "batched_eager_ms": ms_eager, "per_molecule_ms": ms_per_mol,
+           "per_molecule_ms_each": [round(x, 3) for x in per_mol],
+           "speedup_graph_vs_per_molecule": ms_per_mol / ms_graph, "autotune_s": t_tune, "tiles": plan.tiles(),
+           "kernels_ms_eager_pass": {k: round(v[1], 3) for k, v in sorted(prof.items(), key=lambda kv: -kv[1][1])[:12]}}
+    del g, plan, P, R, o
+    return rec
+
+
+def bench_batched(args):
+    """The batched workload alone: 16 molecules x 1024 walkers in one graph vs per-molecule launches."""
+    import torch
+    import qmc_inputs as qi
+    wl = qi.workload(4)
+    W = args.walkers or wl.walkers
+    prec = args.precision
+    rec = batched_record(W, prec, args.steps, args.warmup, torch.device("cuda", 0))
+    Wt = W * len(wl.systems)
     res = {
         "metric": "walker local energies/sec at stated mHa error vs FP64 oracle; VMC train step ms",
-        "value": Wt / (ms_graph * 1e-3),
+        "value": Wt / (rec["batched_graph_ms"] * 1e-3),
         "unit": "walkers/s",
-        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_graph,
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": rec["batched_graph_ms"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": {"fp32": "f32+f64", "fp64": "f64", "bf16": "bf16+f32+f64", "bf16v": "bf16+f32+f64"}[prec],
         "data": "synthetic",
-        "config": {"workload": f"16 molecules ({', '.join(str(m.n_up + m.n_down) for m in mols)} electrons), "
-                               f"{W} walkers each, width {a.width}, {a.n_det} dets; step = local energy + loss "
-                               f"gradient of every molecule",
+        "config": {"workload": f"16 molecules ({', '.join(str(n) for n in rec['electrons'])} electrons), "
+                               f"{W} walkers each, width {rec['width']}, {rec['dets']} dets; step = local energy + "
+                               f"loss gradient of every molecule",
                    "walkers": Wt, "precision": prec},
-        "batched_graph_ms": ms_graph,
-        "batched_eager_ms": ms_eager,
-        "per_molecule_ms": ms_per_mol,
-        "per_molecule_ms_each": [round(x, 3) for x in per_mol],
-        "speedup_graph_vs_per_molecule": ms_per_mol / ms_graph,
-        "autotune_s": t_tune,
-        "tiles": plan.tiles(),
-        "kernels_ms_eager_pass": {k: round(v[1], 3) for k, v in sorted(prof.items(), key=lambda kv: -kv[1][1])[:12]},
     }
+    res.update(rec)
     print(json.dumps(res))
 
 

@@ -184,7 +184,21 @@ qmc_status qmc_plan_create(qmc_plan** out, const qmc_system* systems, int32_t n_
                            const int64_t* walkers_per_system, const qmc_ansatz* ansatz,
                            qmc_precision precision, uint32_t flags);
 
+/* As qmc_plan_create, with every system's walkers processed in chunks of at
+ * most max_chunk_walkers walkers (0 = no cap; negative is an invalid
+ * argument).  Chunks run one after another on the same workspace, so the cap
+ * bounds the workspace of every operation; results do not depend on it.
+ * Without a cap (and below the cap) the plan still halves a system's chunk
+ * until the local-energy workspace of one chunk is at most 24 GiB. */
+qmc_status qmc_plan_create_ex(qmc_plan** out, const qmc_system* systems, int32_t n_systems,
+                              const int64_t* walkers_per_system, const qmc_ansatz* ansatz,
+                              qmc_precision precision, uint32_t flags, int64_t max_chunk_walkers);
+
 qmc_status qmc_plan_destroy(qmc_plan* plan);
+
+/* Walkers per chunk of system s (the last chunk holds the remainder).  Host
+ * only. */
+qmc_status qmc_plan_chunk_walkers(const qmc_plan* plan, int32_t s, int64_t* walkers);
 
 /* GEMM tile choice of system s, one entry per GEMM class (electron jets,
  * value rows, edge jets, backward value rows): 0 = built-in default, else
@@ -273,7 +287,14 @@ qmc_status qmc_logpsi_vjp(const qmc_plan* plan, const void* params, const double
  * e_loc is finite, e_mean = their mean local energy (float64) and
  *   grad_params = (2 / W_f) sum_w (e_loc[w] - e_mean) d log|psi_w| / d params.
  * e_loc[W] is an input (as returned by qmc_local_energy); e_mean[n_systems]
- * is a device output (may be NULL). */
+ * is a device output (may be NULL).  Walkers with a non-finite e_loc (psi = 0,
+ * coincident particles) are left out of e_mean and of the sum; their count is
+ * reported in the workspace header: when the call has completed on the
+ * stream, ws begins with int64_t n_finite[n_systems], the number W_f of
+ * walkers of each system that entered the estimator (0 gives e_mean = NaN
+ * and a zero gradient).  The header is the first
+ * roundup(8 n_systems, 256) bytes of ws and is included in
+ * qmc_workspace_size(plan, QMC_OP_LOSS_GRAD). */
 qmc_status qmc_loss_grad(const qmc_plan* plan, const void* params, const double* r,
                          const double* e_loc, void* grad_params, double* e_mean, void* ws,
                          size_t ws_bytes, void* stream);

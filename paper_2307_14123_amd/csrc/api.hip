@@ -271,7 +271,7 @@ template <class F>
 static qmc_status for_systems(const Plan& P, int op, char* ws, hipStream_t st, F f) {
   if (!P.concurrent()) {
     for (size_t si = 0; si < P.sys.size(); ++si) {
-      const qmc_status e = f(si, st, ws);
+      const qmc_status e = f(si, st, ws + sys_ws_offset(P, op, si));
       if (e != QMC_OK) return e;
     }
     return QMC_OK;
@@ -716,8 +716,9 @@ static qmc_status run_backward(const Plan& P, const void* params, const double* 
       gall = cot + s.walker_offset;
     } else {
       double* gb = (double*)(wsb + B0.gbar);
+      // the workspace header receives the system's count of finite local energies
       CK(launch_loss_weights(e_loc + s.walker_offset, s.W, (double*)(wsb + B0.stats), gb,
-                             e_mean ? e_mean + si : nullptr, ss));
+                             e_mean ? e_mean + si : nullptr, (int64_t*)ws + si, ss));
       gall = gb;
     }
     for (int64_t w0 = 0; w0 < s.W; w0 += s.Wc) {

@@ -428,7 +428,8 @@ hipError_t launch_rowsum(const double* src, int64_t R, int64_t C, int64_t ld, do
 
 // stats[0] = mean of the finite e_loc, stats[1] = their count.  One block,
 // fixed per-thread order and tree reduction: deterministic.
-__global__ __launch_bounds__(1024) void emean_kernel(const double* __restrict__ e, int64_t W, double* __restrict__ stats) {
+__global__ __launch_bounds__(1024) void emean_kernel(const double* __restrict__ e, int64_t W, double* __restrict__ stats,
+                                                     int64_t* __restrict__ nfin) {
   __shared__ double ss[1024];
   __shared__ double sc[1024];
   double s = 0.0, c = 0.0;
@@ -452,6 +453,7 @@ __global__ __launch_bounds__(1024) void emean_kernel(const double* __restrict__ 
   if (threadIdx.x == 0) {
     stats[0] = sc[0] > 0 ? ss[0] / sc[0] : NAN;
     stats[1] = sc[0];
+    if (nfin) *nfin = (int64_t)sc[0];
   }
 }
 
@@ -569,10 +571,10 @@ __global__ void gbar_kernel(const double* __restrict__ e, const double* __restri
 }
 
 hipError_t launch_loss_weights(const double* e, int64_t W, double* stats, double* g, double* e_mean,
-                               hipStream_t st) {
+                               int64_t* n_finite, hipStream_t st) {
   {
     ProfScope ps("emean_kernel", st);
-    hipLaunchKernelGGL(emean_kernel, dim3(1), dim3(1024), 0, st, e, W, stats);
+    hipLaunchKernelGGL(emean_kernel, dim3(1), dim3(1024), 0, st, e, W, stats, n_finite);
   }
   if (e_mean) {
     if (hipMemcpyAsync(e_mean, stats, sizeof(double), hipMemcpyDeviceToDevice, st) != hipSuccess)

@@ -211,9 +211,13 @@ static size_t sys_bytes(const Plan& p, int op, const SysPlan& s) {
                                                               : workspace_layout(p, s, op, s.Wc).total;
 }
 
+size_t ws_header_bytes(const Plan& p, int op) {
+  return op == QMC_OP_LOSS_GRAD ? align256(sizeof(int64_t) * p.sys.size()) : 0;
+}
+
 size_t sys_ws_offset(const Plan& p, int op, size_t si) {
-  if (!p.concurrent()) return 0;
-  size_t off = 0;
+  size_t off = ws_header_bytes(p, op);
+  if (!p.concurrent()) return off;
   for (size_t k = 0; k < si; ++k) off += align256(sys_bytes(p, op, p.sys[k]));
   return off;
 }
@@ -225,7 +229,7 @@ size_t workspace_bytes(const Plan& p, int op) {
     if (b > mx) mx = b;
     sum += align256(b);
   }
-  return (p.concurrent() ? sum : mx) + 256;
+  return ws_header_bytes(p, op) + (p.concurrent() ? sum : mx) + 256;
 }
 
 static bool valid_system(const qmc_system* s) {
@@ -271,8 +275,15 @@ int64_t qmc_param_count(const qmc_system* system, const qmc_ansatz* ansatz) {
 qmc_status qmc_plan_create(qmc_plan** out, const qmc_system* systems, int32_t n_systems,
                            const int64_t* walkers_per_system, const qmc_ansatz* ansatz,
                            qmc_precision precision, uint32_t flags) {
+  return qmc_plan_create_ex(out, systems, n_systems, walkers_per_system, ansatz, precision, flags, 0);
+}
+
+qmc_status qmc_plan_create_ex(qmc_plan** out, const qmc_system* systems, int32_t n_systems,
+                              const int64_t* walkers_per_system, const qmc_ansatz* ansatz,
+                              qmc_precision precision, uint32_t flags, int64_t max_chunk_walkers) {
   if (!out) return QMC_ERR_INVALID_ARGUMENT;
   *out = nullptr;
+  if (max_chunk_walkers < 0) return QMC_ERR_INVALID_ARGUMENT;
   if (!systems || n_systems < 1 || n_systems > 4096 || !walkers_per_system) return QMC_ERR_INVALID_ARGUMENT;
   if (!valid_ansatz(ansatz)) return QMC_ERR_INVALID_ARGUMENT;
   if (precision != QMC_FP64 && precision != QMC_FP32 && precision != QMC_BF16_MIXED && precision != QMC_BF16_VALUE)
@@ -334,9 +345,11 @@ qmc_status qmc_plan_create(qmc_plan** out, const qmc_system* systems, int32_t n_
     P.total_params += sp.off.total;
     P.sys.push_back(sp);
   }
-  // walker chunks: bound the largest workspace (local energy) by max_chunk_bytes
+  // walker chunks: at most max_chunk_walkers (when given), and halved until the largest workspace
+  // (local energy) fits max_chunk_bytes
   for (auto& sp : P.sys) {
     int64_t wc = sp.W;
+    if (max_chunk_walkers > 0 && wc > max_chunk_walkers) wc = max_chunk_walkers;
     while (wc > 64 && workspace_layout(P, sp, QMC_OP_LOCAL_ENERGY, wc).total > size_t(P.max_chunk_bytes))
       wc = (wc + 1) / 2;
     sp.Wc = wc;
@@ -357,6 +370,12 @@ qmc_status qmc_plan_destroy(qmc_plan* plan) {
   if (!plan) return QMC_ERR_INVALID_ARGUMENT;
   plan_device_release(plan->p);
   delete plan;
+  return QMC_OK;
+}
+
+qmc_status qmc_plan_chunk_walkers(const qmc_plan* plan, int32_t s, int64_t* walkers) {
+  if (!plan || !walkers || s < 0 || s >= (int32_t)plan->p.sys.size()) return QMC_ERR_INVALID_ARGUMENT;
+  *walkers = plan->p.sys[s].Wc;
   return QMC_OK;
 }
 

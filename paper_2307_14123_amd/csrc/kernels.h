@@ -216,8 +216,10 @@ template <typename S>
 hipError_t launch_cast(int64_t n, const double* src, S* dst, hipStream_t st);
 hipError_t launch_rowsum(const double* src, int64_t R, int64_t C, int64_t ld, double* dst, double* scratch,
                          int64_t scratch_elems, hipStream_t st);
+// Mean of the finite e[W] (stats[0]; count in stats[1] and, when n_finite is given, *n_finite) and the
+// loss weights g[w] = 2 (e[w] - mean) / count (0 for non-finite e[w]); e_mean (may be NULL) receives the mean.
 hipError_t launch_loss_weights(const double* e, int64_t W, double* stats, double* g, double* e_mean,
-                               hipStream_t st);
+                               int64_t* n_finite, hipStream_t st);
 template <typename S>
 hipError_t launch_combine_bwd(const SysDev& s, const S* c, const double* ld, const double* sg, const double* gbar,
                               int64_t W, double* lbar, double* cpart, hipStream_t st);

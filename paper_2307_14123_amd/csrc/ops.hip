@@ -1324,7 +1324,9 @@ __global__ __launch_bounds__(64) void combine_kernel(SysDev s, const S* __restri
     }
     const double ok = sgnpsi != 0.0 ? 1.0 : NAN;
     if (lap) lap[w] = ok * (lsum + A - B + glap);
-    if (eloc) eloc[w] = ok * (-0.5 * (lsum + A + glap + C) + vpot[w]);
+    // an undefined local energy (psi = 0, or a coincident pair where the potential is singular) is NaN
+    const double e = ok * (-0.5 * (lsum + A + glap + C) + vpot[w]);
+    if (eloc) eloc[w] = isfinite(e) ? e : NAN;
   }
 }
 

@@ -106,7 +106,11 @@ size_t act_bytes(qmc_precision p);
 Workspace workspace_layout(const Plan& p, const SysPlan& s, int op, int64_t wc);
 BwdWorkspace bwd_layout(const Plan& p, const SysPlan& s, int64_t wc);
 size_t workspace_bytes(const Plan& p, int op);
-// Byte offset of system si's workspace region (0 unless the plan runs systems concurrently).
+// Bytes at the start of the workspace of op that hold documented outputs (the loss gradient's
+// per-system count of finite local energies), before the systems' regions.
+size_t ws_header_bytes(const Plan& p, int op);
+// Byte offset of system si's workspace region: the header, plus the regions of the systems before si
+// when the plan runs systems concurrently.
 size_t sys_ws_offset(const Plan& p, int op, size_t si);
 // Streams, events and autotuning of a plan created with flags (device code, in the HIP part).
 qmc_status plan_device_init(Plan& p);

@@ -52,6 +52,11 @@ def lib():
     L.qmc_plan_create.restype = i32
     L.qmc_plan_create.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(QmcSystem), i32, ctypes.POINTER(i64),
                                   ctypes.POINTER(QmcAnsatz), i32, ctypes.c_uint32]
+    L.qmc_plan_create_ex.restype = i32
+    L.qmc_plan_create_ex.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(QmcSystem), i32, ctypes.POINTER(i64),
+                                     ctypes.POINTER(QmcAnsatz), i32, ctypes.c_uint32, i64]
+    L.qmc_plan_chunk_walkers.restype = i32
+    L.qmc_plan_chunk_walkers.argtypes = [vp, i32, ctypes.POINTER(i64)]
     L.qmc_plan_destroy.restype = i32
     L.qmc_plan_destroy.argtypes = [vp]
     L.qmc_workspace_size.restype = i32
@@ -144,10 +149,12 @@ class Plan:
     concurrent: run every system on its own stream of the plan (fork/join with
     the current stream), so that a multi-system batch shares the device and
     captures into one graph.  autotune: time the GEMM tile candidates of every
-    system at creation and keep the fastest."""
+    system at creation and keep the fastest.  max_chunk_walkers: process each
+    system's walkers in chunks of at most this many (0 = the library's own
+    choice)."""
 
     def __init__(self, systems: Sequence, walkers: Sequence[int], ans, precision: str = "fp64",
-                 concurrent: bool = False, autotune: bool = False):
+                 concurrent: bool = False, autotune: bool = False, max_chunk_walkers: int = 0):
         self.systems = list(systems)
         self.walkers = [int(w) for w in walkers]
         self.ans = ans
@@ -158,8 +165,9 @@ class Plan:
         a = make_ansatz(ans)
         handle = ctypes.c_void_p(0)
         flags = (PLAN_CONCURRENT_SYSTEMS if concurrent else 0) | (PLAN_AUTOTUNE if autotune else 0)
-        _check(lib().qmc_plan_create(ctypes.byref(handle), arr, len(holders), wps, ctypes.byref(a),
-                                     PRECISIONS[precision], flags), "qmc_plan_create")
+        _check(lib().qmc_plan_create_ex(ctypes.byref(handle), arr, len(holders), wps, ctypes.byref(a),
+                                        PRECISIONS[precision], flags, int(max_chunk_walkers)),
+               "qmc_plan_create_ex")
         self.handle = handle
         tw, tp, tpos = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
         _check(lib().qmc_plan_info(self.handle, ctypes.byref(tw), ctypes.byref(tp), ctypes.byref(tpos)),
@@ -181,6 +189,15 @@ class Plan:
             t = (ctypes.c_int32 * 4)()
             _check(lib().qmc_plan_tiles(self.handle, k, t), "qmc_plan_tiles")
             out.append(tuple(int(x) for x in t))
+        return out
+
+    def chunk_walkers(self):
+        """Per system: walkers per chunk (the last chunk holds the remainder)."""
+        out = []
+        for k in range(len(self.systems)):
+            w = ctypes.c_int64()
+            _check(lib().qmc_plan_chunk_walkers(self.handle, k, ctypes.byref(w)), "qmc_plan_chunk_walkers")
+            out.append(int(w.value))
         return out
 
     def workspace_bytes(self, op: int) -> int:
@@ -206,11 +223,20 @@ class Plan:
         if not (params.is_cuda and r.is_cuda):
             raise ValueError("params and r must be device tensors")
 
-    def logpsi(self, params, r):
+    def logpsi(self, params, r, out=None):
+        """(log|psi| [W], sign [W]); out: optional (logpsi, sign) float64 device tensors to write
+        (sign may be None)."""
         self._check_inputs(params, r)
         W = self.total_walkers
-        lp = torch.empty(W, dtype=torch.float64, device=r.device)
-        sg = torch.empty(W, dtype=torch.float64, device=r.device)
+        if out is None:
+            lp = torch.empty(W, dtype=torch.float64, device=r.device)
+            sg = torch.empty(W, dtype=torch.float64, device=r.device)
+        else:
+            lp, sg = out
+            if lp.dtype != torch.float64 or lp.numel() != W or not lp.is_contiguous():
+                raise ValueError("out logpsi: expected contiguous float64 [W]")
+            if sg is not None and (sg.dtype != torch.float64 or sg.numel() != W or not sg.is_contiguous()):
+                raise ValueError("out sign: expected contiguous float64 [W]")
         ws = self.workspace(OP_LOGPSI)
         _check(lib().qmc_logpsi(self.handle, _ptr(params), _ptr(r), _ptr(lp), _ptr(sg), _ptr(ws), ws.numel(),
                                 _stream()), "qmc_logpsi")
@@ -306,6 +332,12 @@ class Plan:
         _check(lib().qmc_loss_grad(self.handle, _ptr(params), _ptr(r), _ptr(e_loc), _ptr(g), _ptr(em), _ptr(ws),
                                    ws.numel(), _stream()), "qmc_loss_grad")
         return g, em
+
+    def loss_grad_finite_counts(self):
+        """Per system, the number of walkers with a finite local energy that entered the last loss
+        gradient (the workspace header written by qmc_loss_grad; read after that call)."""
+        ws = self._ws["shared"]
+        return ws[:8 * len(self.systems)].view(torch.int64).cpu().tolist()
 
     def sgd_update(self, params, grad, lr: float):
         """params -= lr * grad on the device (the optimizer step of a training iteration)."""

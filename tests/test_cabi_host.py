@@ -197,3 +197,48 @@ def test_ansatz_options_count_and_limits():
         assert L.qmc_logpsi_grad(handle, fake, fake, fake, fake, ctypes.c_void_p(0x10000), 16, None) == 3
     finally:
         assert L.qmc_plan_destroy(handle) == 0
+
+
+def test_chunk_cap_and_loss_grad_header():
+    """qmc_plan_create_ex caps the walkers per chunk (ragged last chunk), rejects a negative cap, and
+    the loss-gradient workspace carries its documented header of one int64 count per system."""
+    qmc, L = _lib()
+    a = qmc.make_ansatz(qi.N2_ANSATZ)
+    h = qmc._SysHolder(qi.N2)
+    arr = (qmc.QmcSystem * 1)(h.s)
+    W = (ctypes.c_int64 * 1)(100)
+    handle = ctypes.c_void_p()
+    assert L.qmc_plan_create_ex(ctypes.byref(handle), arr, 1, W, ctypes.byref(a), 1, 0, -1) == 1
+    sizes = {}
+    for cap, expect in ((0, 100), (30, 30), (100, 100), (1000, 100)):
+        handle = ctypes.c_void_p()
+        assert L.qmc_plan_create_ex(ctypes.byref(handle), arr, 1, W, ctypes.byref(a), 1, 0, cap) == 0
+        try:
+            wc = ctypes.c_int64()
+            assert L.qmc_plan_chunk_walkers(handle, 0, ctypes.byref(wc)) == 0 and wc.value == expect
+            assert L.qmc_plan_chunk_walkers(handle, 1, ctypes.byref(wc)) == 1
+            sz = {}
+            for op in (1, 4):
+                b = ctypes.c_size_t()
+                assert L.qmc_workspace_size(handle, op, ctypes.byref(b)) == 0
+                sz[op] = b.value
+            sizes[cap] = sz
+        finally:
+            assert L.qmc_plan_destroy(handle) == 0
+    # a smaller chunk needs a smaller workspace
+    assert sizes[30][1] < sizes[0][1] and sizes[30][4] < sizes[0][4]
+    assert sizes[1000] == sizes[0]
+    # two systems: header of two int64 counts, rounded to 256 bytes, before the regions
+    a = qmc.make_ansatz(qi.BATCH_ANSATZ)
+    mols = qi.workload(4).systems[:2]
+    hs = [qmc._SysHolder(m) for m in mols]
+    arr = (qmc.QmcSystem * 2)(*[x.s for x in hs])
+    W = (ctypes.c_int64 * 2)(8, 8)
+    handle = ctypes.c_void_p()
+    assert L.qmc_plan_create_ex(ctypes.byref(handle), arr, 2, W, ctypes.byref(a), 1, 0, 3) == 0
+    try:
+        wc = ctypes.c_int64()
+        for k in range(2):
+            assert L.qmc_plan_chunk_walkers(handle, k, ctypes.byref(wc)) == 0 and wc.value == 3
+    finally:
+        assert L.qmc_plan_destroy(handle) == 0

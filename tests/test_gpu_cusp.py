@@ -11,7 +11,8 @@ import torch
 import oracle
 import qmc_inputs as qi
 from tests.gpu_common import dev, host, rel_err
-from tests.test_gpu_parity import _compare_fp64, _run_le, cancellation
+from tests.test_gpu_parity import (_compare_fp64, _run_le, amplification, check_fp32_logpsi, fp32_eloc_bound,
+                                    fp32_grad_bound)
 from tests.test_oracle_pins import SMALL, _one_center_params, _random_points
 
 pytestmark = pytest.mark.gpu
@@ -49,10 +50,9 @@ def test_n2_subset_fp32_with_cusp():
                                0.5 * (ref["grad"] ** 2).sum((1, 2)), np.ones_like(ref["e_loc"])])
     e = np.abs(got["e_loc"] - ref["e_loc"]) / scale
     print(f"[n2 cusp fp32] max rel E_L err {e.max():.3e}", flush=True)
-    assert e.max() < 2e-5
-    # log|psi| on walkers whose determinant terms cancel by less than 100x (see cancellation)
-    ok = cancellation(r, p, s, a) < 100.0
-    assert rel_err(got["logpsi"][ok], ref["logpsi"][ok]).max() < 2e-4
+    alpha = amplification(r, p, s, a)
+    assert np.all(e <= fp32_eloc_bound(alpha))
+    check_fp32_logpsi("n2 cusp fp32", got["logpsi"], ref["logpsi"], alpha)
 
 
 @pytest.mark.parametrize("Z,alpha", [(2.0, 1.0), (3.0, 2.5)])

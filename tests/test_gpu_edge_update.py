@@ -14,7 +14,8 @@ import oracle
 import qmc_inputs as qi
 from oracle.layout import param_shapes
 from tests.gpu_common import dev, host, rel_err
-from tests.test_gpu_parity import _compare_fp64, _run_le, cancellation
+from tests.test_gpu_parity import (_compare_fp64, _run_le, amplification, check_fp32_logpsi, fp32_eloc_bound,
+                                    fp32_grad_bound)
 
 pytestmark = pytest.mark.gpu
 
@@ -67,23 +68,18 @@ def test_n2_subset_fp32_edge_update():
                                0.5 * (ref["grad"] ** 2).sum((1, 2)), np.ones_like(ref["e_loc"])])
     e = np.abs(got["e_loc"] - ref["e_loc"]) / scale
     print(f"[n2 edge update fp32] max rel E_L err {e.max():.3e}", flush=True)
-    assert e.max() < 2e-5
-    # log|psi| on walkers whose determinant terms cancel by less than 100x (see cancellation)
-    ok = cancellation(r, p, s, a) < 100.0
-    assert rel_err(got["logpsi"][ok], ref["logpsi"][ok]).max() < 2e-4
+    alpha = amplification(r, p, s, a)
+    assert np.all(e <= fp32_eloc_bound(alpha))
+    check_fp32_logpsi("n2 edge update fp32", got["logpsi"], ref["logpsi"], alpha)
 
 
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32", 2e-3)])
 def test_loss_grad_with_edge_update(prec, tol):
-    """float32 runs on the walkers whose determinant terms cancel by less than 100x.  A walker whose
-    terms cancel strongly (one of the 16-walker draw sums to 1/1460 of their absolute sum) has a
-    float32 log|psi| and gradient that move by 1e-4..1e-3 with any change of rounding order; float64
-    parity covers every walker."""
-    s, a, p, r = _n2(24 if prec == "fp32" else 16)
-    if prec == "fp32":
-        keep = cancellation(r, p, s, a) < 100.0
-        assert keep.sum() >= 16
-        r = np.ascontiguousarray(r[keep][:16])
+    """Every walker, float32 bounds scaled with the amplification alpha: a walker whose determinant
+    terms cancel strongly (one of this 16-walker draw sums to 1/1460 of their absolute sum) has a
+    float32 log|psi| and gradient that move by 1e-4..1e-3 with any change of rounding order."""
+    s, a, p, r = _n2(16)
+    alpha = amplification(r, p, s, a)
     q = _q()
     plan = q.Plan([s], [16], a, prec)
     P, R = dev(p, plan.param_dtype), dev(r)
@@ -93,10 +89,12 @@ def test_loss_grad_with_edge_update(prec, tol):
     torch.cuda.synchronize()
     # float32: the value forward and the jet forward round in different orders through the chained
     # updates (the float32 value-mode bar, 2e-4, against each other and the oracle)
-    tl = 1e-12 if prec == "fp64" else 2e-4
-    assert rel_err(host(lp), host(out["logpsi"])).max() < tl
-    if prec == "fp32":
-        assert rel_err(host(lp), oracle.logpsi_and_grad(r, p, s, a)[0]).max() < tl
+    if prec == "fp64":
+        assert rel_err(host(lp), host(out["logpsi"])).max() < 1e-12
+    else:
+        check_fp32_logpsi("edge update fp32 value vs jet", host(lp), host(out["logpsi"]), alpha)
+        check_fp32_logpsi("edge update fp32 value vs oracle", host(lp), oracle.logpsi_and_grad(r, p, s, a)[0], alpha)
+        tol = fp32_grad_bound(alpha)
     Gref, em_ref, nf = oracle.loss_grad(r, host(out["e_loc"]), p, s, a)
     G = host(g).astype(np.float64)
     sl = _update_slices(s, a)

@@ -60,6 +60,56 @@ def cancellation(r, p, s, a):
     return np.abs(t).sum(1) / np.abs(t.sum(1))
 
 
+def amplification(r, p, s, a):
+    """Per walker, alpha = sum_p |w_p| sum_sigma cond_2(A^{sigma,p}) with w_p = c_p D_p / psi
+    (oracle-computed): the first-order factor by which a relative perturbation eps of the
+    orbital-matrix entries moves log|psi|, since d log|psi| = sum_p w_p sum_sigma tr(A^-1 dA) and
+    |tr(A^-1 dA)| <= cond_2(A) eps.  It combines the cancellation of the determinant sum
+    (sum_p |w_p| = kappa) with the conditioning of each matrix."""
+    P = unpack(torch.as_tensor(p), s, a)
+    with torch.no_grad():
+        mats = [A for A in orbital_matrices(torch.as_tensor(r), P, s, a) if A is not None]
+    ld = sum(torch.linalg.slogdet(A)[1] for A in mats).numpy()
+    sg = np.prod([torch.linalg.slogdet(A)[0].numpy() for A in mats], axis=0)
+    t = P["c"].numpy()[None] * sg * np.exp(ld - ld.max(1, keepdims=True))
+    w = t / t.sum(1, keepdims=True)
+    cond = sum(np.linalg.cond(A.numpy()) for A in mats)
+    return (np.abs(w) * cond).sum(1)
+
+
+# float32 bounds, per walker: the orbital-matrix entries of the float32 plans carry relative errors
+# of order 1e-7 (a few float32 roundings), which reach log|psi| multiplied by the walker's
+# amplification alpha; typical walkers (alpha below 2000) meet the fixed bars measured on them.
+def fp32_logpsi_bound(alpha):
+    """|d log|psi|| of a float32 plan against the oracle: max(2e-4, 1e-7 alpha)."""
+    return np.maximum(2e-4, 1e-7 * np.asarray(alpha))
+
+
+def fp32_eloc_bound(alpha):
+    """|d E_L| of a float32 plan, relative to the largest addend of E_L: max(2e-5, 1e-8 alpha)."""
+    return np.maximum(2e-5, 1e-8 * np.asarray(alpha))
+
+
+def fp32_grad_bound(alpha):
+    """Normwise relative error of a float32 loss gradient over walkers with the given alphas."""
+    return 2e-3 * max(1.0, float(np.max(alpha)) / 2000.0)
+
+
+def check_fp32_logpsi(name, got, ref, alpha):
+    """Every walker within fp32_logpsi_bound; walkers with alpha >= 2000 printed with their error."""
+    err = np.abs(np.asarray(got) - np.asarray(ref))
+    for w in np.nonzero(alpha >= 2000.0)[0]:
+        print(f"[{name}] walker {w}: alpha {alpha[w]:.3g}, |dlogpsi| {err[w]:.3e}, bound {fp32_logpsi_bound(alpha[w]):.3e}",
+              flush=True)
+    assert np.all(err <= fp32_logpsi_bound(alpha)), (name, float((err / fp32_logpsi_bound(alpha)).max()))
+
+
+# float64: the same amplification sets a rounding floor of about 1e-16 alpha, so walkers with
+# alpha above 1e5 are counted as ill-conditioned (with the pair-distance and matrix-condition flags)
+# and held to 1e-15 alpha instead of 1e-10.
+FP64_ALPHA_FLAG = 1e5
+
+
 def _run_le(s, a, p, r, precision):
     q = _q()
     plan = q.Plan([s], [r.shape[0]], a, precision)
@@ -72,10 +122,16 @@ def _run_le(s, a, p, r, precision):
 def _compare_fp64(name, s, a, p, r, tol=1e-10):
     ref = oracle.local_energy(r, p, s, a)
     got = _run_le(s, a, p, r, "fp64")
-    ok = ~flagged(r, p, s, a)
+    bad = flagged(r, p, s, a)
+    alpha = amplification(r, p, s, a)
+    amp = ~bad & (alpha > FP64_ALPHA_FLAG)
+    ok = ~bad & ~amp
     W = r.shape[0]
-    print(f"[{name}] walkers={W} flagged={int((~ok).sum())}", flush=True)
+    print(f"[{name}] walkers={W} flagged={int(bad.sum())} amplification-flagged={int(amp.sum())}", flush=True)
     assert ok.sum() >= W // 2
+    if amp.any():
+        la = np.abs(got["logpsi"] - ref["logpsi"]) / np.maximum(1.0, np.abs(ref["logpsi"]))
+        assert np.all(la[amp] <= 1e-15 * alpha[amp])
     np.testing.assert_array_equal(got["sign"][ok], ref["sign"][ok])
     assert rel_err(got["logpsi"][ok], ref["logpsi"][ok]).max() < tol
     # E_L = -1/2 (lap + |grad|^2) + V: errors are measured against the largest
@@ -253,12 +309,15 @@ def test_fp32_value_mode_logpsi():
     le = plan.local_energy(P, dev(r))
     torch.cuda.synchronize()
     ref_s, ref_l = oracle.logpsi_np(r, p.astype(np.float32).astype(np.float64), s, a)
-    ok = ~flagged(r, p, s, a) & (cancellation(r, p, s, a) < 100.0)
-    e_or = np.abs(host(lp) - ref_l)[ok]
-    e_jet = np.abs(host(lp) - host(le["logpsi"]))[ok]
-    print(f"[fp32 value logpsi] max |dlogpsi| vs oracle {e_or.max():.3e}, vs jet path {e_jet.max():.3e}", flush=True)
-    assert np.all(host(sg)[ok] == ref_s[ok])
-    assert e_or.max() < 2e-4 and e_jet.max() < 2e-4
+    alpha = amplification(r, p, s, a)
+    e_or = np.abs(host(lp) - ref_l)
+    e_jet = np.abs(host(lp) - host(le["logpsi"]))
+    print(f"[fp32 value logpsi] max |dlogpsi| vs oracle {e_or.max():.3e}, vs jet path {e_jet.max():.3e}, "
+          f"max alpha {alpha.max():.3g}", flush=True)
+    check_fp32_logpsi("fp32 value logpsi vs oracle", host(lp), ref_l, alpha)
+    check_fp32_logpsi("fp32 value logpsi vs jet", host(lp), host(le["logpsi"]), alpha)
+    keep = cancellation(r, p, s, a) < 1e3
+    assert np.all(host(sg)[keep] == ref_s[keep])
 
 
 def test_det_stage_on_hydrogenic_jets():
@@ -351,13 +410,12 @@ def test_fp32_fused_filters_with_missing_edge_types(name, system):
     pairs: one type (a single electron: nuclear edges only), two (one electron per spin: no
     same-spin pairs) or three.  Width-128 ansatz, float32 plan: E_L within 2e-5 of its largest
     addend, value-mode and jet-mode log|psi| within the float32 value-mode bar (2e-4) of the
-    oracle, and the loss gradient within 2e-3 normwise, on walkers whose determinant terms cancel
-    by less than 100x (one of the first 40 Li walkers cancels by 454x)."""
+    oracle, and the loss gradient within 2e-3 normwise, each scaled with the walkers' amplification
+    alpha (one of the first 40 Li walkers cancels by 454x)."""
     a = qi.N2_ANSATZ
     p = qi.make_params(system, a, 91)
-    r = qi.make_walkers(system, 48, 92)
-    r = np.ascontiguousarray(r[cancellation(r, p, system, a) < 100.0][:40])
-    assert r.shape[0] == 40
+    r = qi.make_walkers(system, 40, 92)
+    alpha = amplification(r, p, system, a)
     ref = oracle.local_energy(r, p, system, a)
     q = _q()
     plan = q.Plan([system], [40], a, "fp32")
@@ -374,7 +432,7 @@ def test_fp32_fused_filters_with_missing_edge_types(name, system):
     gerr = float(np.linalg.norm(host(g) - Gref) / np.linalg.norm(Gref))
     print(f"[{name} fp32 fused] E_L {e.max():.2e}, log|psi| jet {rel_err(got['logpsi'], ref['logpsi']).max():.2e} "
           f"value {rel_err(host(lp), ref['logpsi']).max():.2e}, loss gradient {gerr:.2e}", flush=True)
-    assert e.max() < 2e-5
-    assert rel_err(got["logpsi"], ref["logpsi"]).max() < 2e-4
-    assert rel_err(host(lp), ref["logpsi"]).max() < 2e-4
-    assert gerr < 2e-3
+    assert np.all(e <= fp32_eloc_bound(alpha))
+    check_fp32_logpsi(f"{name} jet", got["logpsi"], ref["logpsi"], alpha)
+    check_fp32_logpsi(f"{name} value", host(lp), ref["logpsi"], alpha)
+    assert gerr < fp32_grad_bound(alpha)

@@ -28,3 +28,57 @@ def test_sgd_update_after_loss_grad(precision):
     want = (before.astype(np.float64) - lr * gh.astype(np.float64)).astype(before.dtype)
     np.testing.assert_array_equal(host(P), want)
     assert np.abs(gh).max() > 0
+
+
+def test_two_train_iterations_replay_fp64():
+    """Two training iterations at a visible learning rate, in the order the benchmark's step runs
+    them (Sec. IV.A and V): log|psi| of the walkers refreshed under the current parameters, three
+    Metropolis steps, local energies, clipping, the loss gradient and the gradient-descent update.
+    The oracle replays the chain on its own parameter updates; acceptance decisions agree outside
+    the margin 2e-9 (and the oracle follows the GPU's walkers after a within-margin flip), local
+    energies, gradients and the updated parameters agree to 1e-10."""
+    import oracle
+    from paper_2307_14123_amd import qmc
+    from tests.gpu_common import rel_err
+    s, a, p, r = qi.workload_inputs(0, 64)
+    W, n_mc, tau, lr = 64, 3, 0.2, 2e-3
+    plan = qmc.Plan([s], [W], a, "fp64")
+    P, R = dev(p), dev(r)
+    noise = qi.make_noise(2 * n_mc, W, s.n_elec, 7)
+    u = qi.make_uniforms(2 * n_mc, W, 8)
+    p_o, r_o = p.copy(), r.copy()
+    flips = 0
+    for it in range(2):
+        lp, _ = plan.logpsi(P, R)       # the walkers' log|psi| under the current parameters
+        torch.cuda.synchronize()
+        lp_o = oracle.logpsi_np(r_o, p_o, s, a)[1]
+        assert rel_err(host(lp), lp_o).max() < 1e-10
+        for t in range(n_mc):
+            k = it * n_mc + t
+            acc = host(plan.metropolis_step(P, R, lp, dev(noise[k]), dev(u[k]), tau))
+            torch.cuda.synchronize()
+            _, _, acc_o, prop = oracle.metropolis_step(r_o, lp_o, noise[k], u[k], tau, p_o, s, a)
+            margin = np.abs(np.log(u[k]) - 2 * (prop - lp_o))
+            assert np.all((acc == acc_o) | (margin < 2e-9))
+            flips += int((acc != acc_o).sum())
+            r_o, lp_o = host(R).reshape(r.shape).copy(), host(lp).copy()
+        out = plan.local_energy(P, R)
+        ec = plan.clip_local_energy(out["e_loc"], 5.0, "hard")
+        g, em = plan.loss_grad(P, R, ec)
+        torch.cuda.synchronize()
+        ref = oracle.local_energy(r_o, p_o, s, a)
+        scale = np.maximum(np.abs(ref["e_loc"]), np.maximum(0.5 * np.abs(ref["lap"]), 1.0))
+        assert (np.abs(host(out["e_loc"]) - ref["e_loc"]) / scale).max() < 1e-10
+        ec_o = oracle.clip_local_energy(ref["e_loc"], 5.0, "hard")
+        Gref, _, _ = oracle.loss_grad(r_o, ec_o, p_o, s, a)
+        assert np.linalg.norm(host(g) - Gref) / np.linalg.norm(Gref) < 1e-10
+        plan.sgd_update(P, g, lr)
+        torch.cuda.synchronize()
+        p_new = p_o - lr * Gref
+        step = np.linalg.norm(p_new - p_o) / np.linalg.norm(p_o)
+        print(f"[train replay fp64] iteration {it}: relative parameter step {step:.2e}, E mean {host(em)[0]:.6f}",
+              flush=True)
+        assert step > 1e-4                   # the parameters move visibly
+        assert np.linalg.norm(host(P) - p_new) / np.linalg.norm(p_new - p_o) < 1e-8
+        p_o = p_new
+    print(f"[train replay fp64] within-margin flips {flips}", flush=True)

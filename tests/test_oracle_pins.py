@@ -734,3 +734,20 @@ def test_zero_edge_updates_match_zeroed_filter_inputs():
             P0[f"mp{l}.{t}.U1"][:] = 0.0
     b = oracle.logpsi_np(r, p0, s, SMALL)[1]
     np.testing.assert_allclose(a, b, rtol=1e-13, atol=1e-13)
+
+
+def test_coincident_pair_gives_nan_local_energy():
+    """At an exactly coincident electron pair the Coulomb potential is singular and E_L is undefined:
+    the oracle returns NaN there and an ordinary value elsewhere (opposite-spin pairs: a same-spin
+    pair makes two rows of a matrix equal, and autograd through an exactly singular matrix raises)."""
+    s, a, p, r = qi.workload_inputs(0, 3)
+    r = r.copy()
+    r[0, 1] = r[0, 0]
+    res = oracle.local_energy(r, p, s, a)
+    assert np.isnan(res["e_loc"][0]) and np.all(np.isfinite(res["e_loc"][1:]))
+    assert np.isfinite(res["logpsi"][0])
+    s, a, p, r = qi.workload_inputs(1, 2)
+    r = r.copy()
+    r[0, 8] = r[0, 1]
+    res = oracle.local_energy(r, p, s, a)
+    assert np.isnan(res["e_loc"][0]) and np.isfinite(res["e_loc"][1])
