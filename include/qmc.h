@@ -226,6 +226,28 @@ qmc_status qmc_local_energy(const qmc_plan* plan, const void* params, const doub
                             double* logpsi, double* sign, double* grad, double* lap, double* e_loc,
                             void* ws, size_t ws_bytes, void* stream);
 
+/* Size of the device array that qmc_local_energy_noalloc uses as its
+ * workspace (64 MiB; one array per device, held from the library's load
+ * until the process ends). */
+#define QMC_NOALLOC_SCRATCH_BYTES (64u << 20)
+
+/* qmc_local_energy for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same outputs from the same kernels, with the workspace
+ * taken from the library's own scratch array instead of a caller buffer.  It
+ * calls no allocator.  The plan's local-energy workspace,
+ * qmc_workspace_size(plan, QMC_OP_LOCAL_ENERGY), must be at most
+ * QMC_NOALLOC_SCRATCH_BYTES (create the plan with qmc_plan_create_ex and a
+ * max_chunk_walkers small enough); otherwise QMC_ERR_WORKSPACE_TOO_SMALL is
+ * returned, nothing is launched, and qmc_last_error() states both sizes.
+ * Every call on a device shares that device's array: calls that overlap on
+ * one device (different streams, or host threads) race and must be
+ * serialised by the caller.  The array keeps the last call's contents; the
+ * local energy does not depend on what its workspace holds on entry (as for
+ * the caller's ws of qmc_local_energy), so nothing is cleared between calls. */
+qmc_status qmc_local_energy_noalloc(const qmc_plan* plan, const void* params, const double* r, double* logpsi,
+                                    double* sign, double* grad, double* lap, double* e_loc, void* stream);
+
 /* One random-walk Metropolis step (Sec. V): r' = r + step * noise, accepted
  * iff log(u) < 2 (log|psi(r')| - logpsi) in float64.  r and logpsi are
  * in/out and change only for accepted walkers; logpsi must hold log|psi(r)|

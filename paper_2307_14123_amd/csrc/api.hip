@@ -848,6 +848,31 @@ void plan_device_release(Plan& P) {
   P.fork = nullptr;
 }
 
+// ---------------------------------------------------------------- local energy without allocation
+//
+// The workspace of qmc_local_energy_noalloc: one array per device, held by the loaded code object
+// until the process ends.  In host code its name is only a stand-in for the symbol; the device
+// address comes from hipGetSymbolAddress, taken once per device with that device current.
+static __device__ __align__(256) char scratch[QMC_NOALLOC_SCRATCH_BYTES];
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[64];
+
+// Device address of this device's scratch array (resolved on the first call on the device).
+static qmc_status scratch_address(void** out) {
+  int dev = 0;
+  CK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) return QMC_ERR_UNSUPPORTED;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    CK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p || reinterpret_cast<uintptr_t>(p) % 256 != 0) return QMC_ERR_INTERNAL;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return QMC_OK;
+}
+
 }  // namespace qmc
 
 using namespace qmc;
@@ -877,6 +902,26 @@ qmc_status qmc_local_energy(const qmc_plan* plan, const void* params, const doub
     if (ws && ws_bytes < workspace_bytes(plan->p, QMC_OP_LOCAL_ENERGY)) return QMC_ERR_WORKSPACE_TOO_SMALL;
     return QMC_ERR_INVALID_ARGUMENT;
   }
+  Outs o = {logpsi, sign, grad, lap, e_loc};
+  hipStream_t st = (hipStream_t)stream;
+  if (plan->p.prec == QMC_FP64) return run_forward<double>(plan->p, params, r, o, 1, (char*)ws, st);
+  return run_forward<float>(plan->p, params, r, o, 1, (char*)ws, st);
+}
+
+qmc_status qmc_local_energy_noalloc(const qmc_plan* plan, const void* params, const double* r, double* logpsi,
+                                    double* sign, double* grad, double* lap, double* e_loc, void* stream) {
+  if (!plan || !params || !r || !e_loc) return QMC_ERR_INVALID_ARGUMENT;
+  const size_t need = workspace_bytes(plan->p, QMC_OP_LOCAL_ENERGY);
+  if (need > size_t(QMC_NOALLOC_SCRATCH_BYTES)) {
+    snprintf(g_last_error, sizeof(g_last_error),
+             "qmc_local_energy_noalloc: the plan's local-energy workspace (%zu bytes) exceeds the %zu-byte scratch "
+             "array; create the plan with a smaller max_chunk_walkers",
+             need, size_t(QMC_NOALLOC_SCRATCH_BYTES));
+    return QMC_ERR_WORKSPACE_TOO_SMALL;
+  }
+  void* ws = nullptr;
+  const qmc_status e = scratch_address(&ws);
+  if (e != QMC_OK) return e;
   Outs o = {logpsi, sign, grad, lap, e_loc};
   hipStream_t st = (hipStream_t)stream;
   if (plan->p.prec == QMC_FP64) return run_forward<double>(plan->p, params, r, o, 1, (char*)ws, st);
