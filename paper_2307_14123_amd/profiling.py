@@ -7,6 +7,11 @@
       achieved HBM bytes and GB/s of every kernel family of a program: bytes per launch from a FETCH_SIZE
       run and a WRITE_SIZE run (scaled by the device copy in the same runs), average duration from a
       --kernel-trace --stats run of the same program
+  python -m paper_2307_14123_amd.profiling mfma <pmc dir> <kernel_stats.csv> --command "<cmd>" --out <file.md>
+      matrix-core and VALU counters per kernel family from one --pmc run of SQ_VALU_MFMA_BUSY_CYCLES,
+      SQ_BUSY_CYCLES, SQ_BUSY_CU_CYCLES, SQ_INSTS_MFMA, SQ_INSTS_VALU, SQ_INSTS_VALU_MFMA_MOPS_F32,
+      SQ_LDS_BANK_CONFLICT, SQ_WAIT_INST_LDS and GRBM_GUI_ACTIVE, with durations from a --kernel-trace
+      --stats run of the same program
   python -m paper_2307_14123_amd.profiling traffic <fetch dir> <write dir> --family "gemm_kernel<jet>"
       --source <csrc file> --command "<cmd>" --out <file.txt>
       HBM bytes per launch of one kernel family from a FETCH_SIZE run and a WRITE_SIZE run,
@@ -158,6 +163,65 @@ def hbm(fetch_dir: str, write_dir: str, stats_csv: str, command: str, top: int =
     return "\n".join(out) + "\n"
 
 
+MFMA_COUNTERS = ("SQ_VALU_MFMA_BUSY_CYCLES", "SQ_BUSY_CYCLES", "SQ_BUSY_CU_CYCLES", "SQ_INSTS_MFMA", "SQ_INSTS_VALU",
+                 "SQ_INSTS_VALU_MFMA_MOPS_F32", "SQ_LDS_BANK_CONFLICT", "SQ_WAIT_INST_LDS", "GRBM_GUI_ACTIVE")
+SIMDS = 256 * 4  # MI355X: 256 compute units of 4 SIMDs
+CLOCK_HZ = 2.4e9  # MI355X peak engine clock
+
+
+def mfma(pmc_dir: str, stats_csv: str, command: str, top: int = 14) -> str:
+    per = {c: _counter(pmc_dir, c) for c in MFMA_COUNTERS}
+    fam = collections.defaultdict(lambda: collections.defaultdict(float))
+    for c, d in per.items():
+        for k, disp in d.items():
+            if not k.startswith(("qmc::", "void qmc::")) or "_peak_kernel" in k:
+                continue
+            f = family(k)
+            fam[f][c] += sum(disp.values())
+            if c == "SQ_INSTS_MFMA":
+                fam[f]["dispatches"] += len(disp)
+    dur = collections.defaultdict(lambda: [0, 0.0])
+    for r in csv.DictReader(open(stats_csv)):
+        f = family(r["Name"])
+        dur[f][0] += int(r["Calls"])
+        dur[f][1] += float(r["TotalDurationNs"])
+    out = ["# Matrix-core (MFMA) and VALU counters per kernel family", "", "Commands (run from the repository root):",
+           "", "    " + command, "",
+           "Columns, per dispatch of the family (sums over all dispatches of the counter run divided by their count; "
+           "durations from the trace run):",
+           f"- MFMA busy = SQ_VALU_MFMA_BUSY_CYCLES / (average duration x {CLOCK_HZ / 1e9:.1f} GHz x {SIMDS} SIMDs): "
+           "the share of SIMD-cycles in which the matrix core was busy (the counter is summed over the SIMDs);",
+           "- MFMA TFLOP/s = SQ_INSTS_VALU_MFMA_MOPS_F32 x 512 flops / average duration: executed float32 MFMA work "
+           "(padding rows included) per second;",
+           "- VALU / MFMA = SQ_INSTS_VALU / SQ_INSTS_MFMA (SQ_INSTS_VALU counts the MFMA instructions too);",
+           "- LDS bank-conflict cycles and LDS-issue waits (quad-cycles) per dispatch;",
+           f"- GRBM / clk and SQ busy / clk: GRBM_GUI_ACTIVE and SQ_BUSY_CYCLES over average duration x "
+           f"{CLOCK_HZ / 1e9:.1f} GHz, the number of counter instances summed (a check of the clock assumption).", "",
+           "| family | dispatches | average us | MFMA busy | MFMA TFLOP/s (f32) | MFMA insts / dispatch | "
+           "VALU / MFMA | LDS bank-conflict cycles / dispatch | LDS wait / dispatch | GRBM / clk | SQ busy / clk |",
+           "|---|---|---|---|---|---|---|---|---|---|---|"]
+    rows = []
+    for f, v in fam.items():
+        n = v.get("dispatches", 0)
+        if n == 0 or f not in dur or dur[f][0] == 0:
+            continue
+        rows.append((dur[f][1], f, n, v))
+    for _, f, n, v in sorted(rows, key=lambda t: t[0], reverse=True)[:top]:
+        avg_s = dur[f][1] / dur[f][0] * 1e-9
+        cyc = avg_s * CLOCK_HZ
+        util = v["SQ_VALU_MFMA_BUSY_CYCLES"] / n / (cyc * SIMDS)
+        tf = v["SQ_INSTS_VALU_MFMA_MOPS_F32"] * 512.0 / n / avg_s / 1e12
+        ratio = v["SQ_INSTS_VALU"] / v["SQ_INSTS_MFMA"] if v["SQ_INSTS_MFMA"] > 0 else float("nan")
+        out.append(f"| {f} | {n} | {avg_s * 1e6:.1f} | {100 * util:.1f}% | {tf:.1f} | {v['SQ_INSTS_MFMA'] / n:.3g} | "
+                   f"{ratio:.2f} | {v['SQ_LDS_BANK_CONFLICT'] / n:.3g} | {v['SQ_WAIT_INST_LDS'] / n:.3g} | "
+                   f"{v['GRBM_GUI_ACTIVE'] / n / cyc:.2f} | {v['SQ_BUSY_CYCLES'] / n / cyc:.2f} |")
+    out += ["", "Raw sums over the counter run:", "", "| family | " + " | ".join(MFMA_COUNTERS) + " |",
+            "|---|" + "---|" * len(MFMA_COUNTERS)]
+    for _, f, n, v in sorted(rows, key=lambda t: t[0], reverse=True)[:top]:
+        out.append(f"| {f} | " + " | ".join(f"{v[c]:.4g}" for c in MFMA_COUNTERS) + " |")
+    return "\n".join(out) + "\n"
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -178,8 +242,15 @@ def main():
     a3.add_argument("stats_csv")
     a3.add_argument("--command", required=True)
     a3.add_argument("--out", required=True)
+    a4 = sub.add_parser("mfma")
+    a4.add_argument("pmc_dir")
+    a4.add_argument("stats_csv")
+    a4.add_argument("--command", required=True)
+    a4.add_argument("--out", required=True)
     args = ap.parse_args()
-    if args.cmd == "hbm":
+    if args.cmd == "mfma":
+        text = mfma(args.pmc_dir, args.stats_csv, args.command)
+    elif args.cmd == "hbm":
         text = hbm(args.fetch_dir, args.write_dir, args.stats_csv, args.command)
     elif args.cmd == "stats":
         text = stats(args.csv, args.command)

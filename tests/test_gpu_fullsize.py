@@ -41,9 +41,11 @@ def _scale(ref):
 
 
 def _print_high_alpha(name, alpha, err, kappa):
+    """The count of walkers with alpha >= 2000 and the ten closest to their bound."""
     hi = np.nonzero(alpha >= 2000.0)[0]
     print(f"[{name}] walkers with alpha >= 2000: {len(hi)}", flush=True)
-    for w in hi:
+    ratio = err / fp32_logpsi_bound(alpha)
+    for w in hi[np.argsort(-ratio[hi])][:10]:
         print(f"[{name}]   walker {w}: alpha {alpha[w]:.3g} (kappa {kappa[w]:.1f}), error {err[w]:.3e}, "
               f"bound {fp32_logpsi_bound(alpha[w]):.3e}", flush=True)
 
@@ -93,9 +95,13 @@ def test_n2_full_size_parity(prec):
     gr = ref["grad"].reshape(48, -1)
     gn = np.linalg.norm(g - gr, axis=1) / np.maximum(np.linalg.norm(gr, axis=1), 1.0)
     le = rel_err(got["lap"][idx], ref["lap"], floor=1.0)
-    report(f"n2 full {prec} sample 48", (got["e_loc"][idx] - ref["e_loc"]) * 1e3)
-    print(f"[n2 full {prec}] sample: E_L/scale {e.max():.3e}, grad {gn.max():.3e}, lap {le.max():.3e}", flush=True)
     okw = ~bad[idx]
+    report(f"n2 full {prec} sample 48", (got["e_loc"][idx] - ref["e_loc"]) * 1e3)
+    report(f"n2 full {prec} sample 48 unflagged", ((got["e_loc"][idx] - ref["e_loc"]) * 1e3)[okw])
+    # the error on the scale max(|E_L|, 1 Ha) as well as on the largest addend of E_L
+    e_own = np.abs(got["e_loc"][idx] - ref["e_loc"]) / np.maximum(np.abs(ref["e_loc"]), 1.0)
+    print(f"[n2 full {prec}] sample: E_L/scale {e.max():.3e}, E_L/max(|E_L|,1) over unflagged {e_own[okw].max():.3e}, "
+          f"grad {gn.max():.3e}, lap {le.max():.3e}", flush=True)
     al = alpha[idx]
     print(f"[n2 full {prec}] sample: {int((~okw).sum())} flagged walkers (alpha {al[~okw]})", flush=True)
     if prec == "fp64":
