@@ -426,34 +426,26 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs a) {
           const int64_t gidx = rg / Rp;
           const int el = A5 ? (int)(gidx % a.nel) : -1;
           const S* Cg = Cc + grp * Rp;
-          // pre-activation of row q, including the bias and the five-row term
-          auto zrow = [&](int q) -> S {
-            S z = Cg[q];
-            if (q == 0) z += b;
+          // One pass over the group's rows: the value row gives t, t' and t''; a gradient row's
+          // output needs only t', so it is written as its pre-activation is read, while the
+          // squares are summed for the Laplacian row, which is written last.  The bias enters the
+          // value row only; the nuclear five-row term enters the value row, the electron's own
+          // three coordinate rows and the Laplacian row.
+          S ssq = 0, t = 0, t1 = 1, t2 = 0, a5c0 = 0, a5c1 = 0, a5c2 = 0, a5l = 0;
+          int q5 = -8;  // first own-coordinate row of the group's electron
+          int64_t base = 0;
+          if (gvalid) {
+            S z0 = Cg[0] + b;
             if (A5) {
-              int k5 = -1;
-              if (q == 0)
-                k5 = 0;
-              else if (q == T + 1)
-                k5 = 4;
-              else if (q >= 1 + 3 * el && q <= 3 + 3 * el)
-                k5 = q - 3 * el;
-              if (k5 >= 0) z += A5[(gidx * 5 + k5) * a.Ncols + col];
+              const S* a5 = A5 + gidx * 5 * a.Ncols + col;
+              z0 += a5[0];
+              a5c0 = a5[a.Ncols];
+              a5c1 = a5[2 * a.Ncols];
+              a5c2 = a5[3 * a.Ncols];
+              a5l = a5[4 * a.Ncols];
+              q5 = 1 + 3 * el;
             }
-            return z;
-          };
-          S ssq = 0, z0 = 0;
-          if (gvalid) {
-            z0 = zrow(0);
-            const int q1 = qlo < 1 ? 1 : qlo, q2 = qlo + rpp - 1 < T ? qlo + rpp - 1 : T;
-            for (int q = q1; q <= q2; ++q) {
-              const S z = zrow(q);
-              ssq += z * z;
-            }
-          }
-          for (int o = 1; o < PPG; o <<= 1) ssq += __shfl_xor(ssq, NCP * o);
-          if (gvalid) {
-            S t = z0, t1 = 1, t2 = 0;
+            t = z0;
             if (a.act) {
               t = dtanh(z0);
               t1 = S(1) - t * t;
@@ -461,21 +453,37 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs a) {
             }
             const uint32_t rpw = (uint32_t)a.yrpw;
             const uint32_t qb = (uint32_t)rg / rpw;
-            const int64_t base = (int64_t)qb * a.yws + (int64_t)((uint32_t)rg - qb * rpw) * a.ldy + col;
-            for (int q = qlo; q < qlo + rpp; ++q) {
-              S o;
-              if (q == 0)
-                o = t;
-              else if (q <= T)
-                o = t1 * zrow(q);
-              else if (q == T + 1)
-                o = t1 * zrow(q) + t2 * ssq;
-              else
-                o = 0;
-              const int64_t off = base + (int64_t)q * a.ldy;
-              if (Res) o += Res[off];
-              Y[off] = o;
+            base = (int64_t)qb * a.yws + (int64_t)((uint32_t)rg - qb * rpw) * a.ldy + col;
+            // runs of 4 rows: the residual loads of a run are issued before its outputs are formed
+            for (int q0 = qlo; q0 < qlo + rpp; q0 += 4) {
+              S rv[4] = {S(0), S(0), S(0), S(0)};
+              if (Res) {
+  #pragma unroll
+                for (int u = 0; u < 4; ++u) rv[u] = Res[base + (int64_t)(q0 + u) * a.ldy];
+              }
+  #pragma unroll
+              for (int u = 0; u < 4; ++u) {
+                const int q = q0 + u;
+                S z = Cg[q];
+                const int d5 = q - q5;
+                if (d5 >= 0 && d5 < 3) z += d5 == 0 ? a5c0 : (d5 == 1 ? a5c1 : a5c2);
+                S o = 0;
+                if (q == 0) {
+                  o = t;
+                } else if (q <= T) {
+                  ssq += z * z;
+                  o = t1 * z;
+                }
+                if (q != T + 1) Y[base + (int64_t)q * a.ldy] = o + rv[u];
+              }
             }
+          }
+          for (int o = 1; o < PPG; o <<= 1) ssq += __shfl_xor(ssq, NCP * o);
+          if (gvalid && T + 1 >= qlo && T + 1 < qlo + rpp) {
+            const int64_t off = base + (int64_t)(T + 1) * a.ldy;
+            S o = t1 * (Cg[T + 1] + a5l) + t2 * ssq;
+            if (Res) o += Res[off];
+            Y[off] = o;
           }
         }
       }
