@@ -168,15 +168,18 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="n2", choices=["n2", "c4h4", "h2", "batched", "scaling"],
+    ap.add_argument("--workload", default="n2", choices=["n2", "c4h4", "h2", "batched", "scaling", "precision"],
                     help="n2: the headline workload; c4h4 / h2: the precision and small FP64 systems; "
                          "batched: 16 molecules (4-42 electrons) in one graph vs per-molecule launches; "
-                         "scaling: train-step time of atoms and hydrogen chains up to 45 electrons")
+                         "scaling: train-step time of atoms and hydrogen chains up to 45 electrons; "
+                         "precision: C4H4-sized local energies in the fp32, bf16v and bf16 plans against the "
+                         "oracle on --cpu-walkers walkers (64 by default)")
     ap.add_argument("--walkers", type=int, default=None)
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64", "bf16", "bf16v"],
                     help="bf16v: bf16 operands in the value-row forwards only (local-energy jets in float32)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-walkers", type=int, default=160)
+    ap.add_argument("--cpu-walkers", type=int, default=None,
+                    help="oracle sample size (160 for n2, 64 for precision)")
     ap.add_argument("--jastrow", action="store_true", help="add the learnable Jastrow factor to the ansatz")
     ap.add_argument("--ee-cusp", type=float, default=0.0, help="alpha of the electron-electron cusp factor (0: none)")
     ap.add_argument("--full-det", action="store_true", help="one N x N determinant per p over both spins")
@@ -200,6 +203,8 @@ def main():
         return bench_batched(args)
     if args.workload == "scaling":
         return bench_scaling(args)
+    if args.workload == "precision":
+        return bench_precision(args)
     k = {"n2": 1, "c4h4": 3, "h2": 0}[args.workload]
     wl = qi.workload(k)
     s, a = wl.systems[0], wl.ansatz
@@ -474,7 +479,7 @@ def main():
     if not args.no_cpu_baseline:
         import oracle
         torch.set_num_threads(os.cpu_count() or 1)
-        nw = min(args.cpu_walkers, W) if args.workload == "n2" else min(8, W)
+        nw = min(args.cpu_walkers or 160, W) if args.workload == "n2" else min(8, W)
         pc = P_init.double().cpu().numpy()
 
         def cpu_step(nw_):
@@ -676,6 +681,71 @@ def batched_record(W, prec, steps, warmup, dev):
            "kernels_ms_eager_pass": {k: round(v[1], 3) for k, v in sorted(prof.items(), key=lambda kv: -kv[1][1])[:12]}}
     del g, plan, P, R, o
     return rec
+
+
+def bench_precision(args):
+    """C4H4-sized system (28 electrons, width 256, 32 determinants) at 8192 walkers: the local energy in
+    the float32 plan, the plan with bf16 operands in the value-row forwards (bf16v: the local-energy jets
+    stay float32) and the plan with bf16 operands in every embedding GEMM (bf16), each autotuned; E_L of
+    an oracle sample (written into the first walkers of the full batch) against the float64 oracle on
+    the float32-rounded parameters, and the value-row log|psi| that Metropolis uses."""
+    import torch
+    import oracle
+    import qmc_inputs as qi
+    from paper_2307_14123_amd import qmc
+    s, a, p, r = qi.workload_inputs(3)
+    W = r.shape[0]
+    nw = min(args.cpu_walkers or 64, W)
+    pr = p.astype(np.float32).astype(np.float64)
+    torch.set_num_threads(os.cpu_count() or 1)
+    t0 = time.perf_counter()
+    parts = []
+    for i in range(0, nw, 16):
+        parts.append(oracle.local_energy(r[i:min(i + 16, nw)], pr, s, a, chunk=16))
+        print(f"[precision] oracle walkers {i}..{min(i + 16, nw) - 1} done", file=sys.stderr, flush=True)
+    ref = {k: np.concatenate([q[k] for q in parts]) for k in parts[0]}
+    t_or = time.perf_counter() - t0
+    print(f"[precision] oracle on {nw} walkers: {t_or:.1f} s", file=sys.stderr, flush=True)
+    scale = np.maximum.reduce([np.abs(ref["e_loc"]), 0.5 * np.abs(ref["lap"]),
+                               0.5 * (ref["grad"] ** 2).sum((1, 2)), np.ones(nw)])
+    dev = torch.device("cuda", 0)
+    rows = {}
+    for prec in ("fp32", "bf16v", "bf16"):
+        plan = qmc.Plan([s], [W], a, prec, autotune=True)
+        P = torch.as_tensor(p, dtype=torch.float32, device=dev).contiguous()
+        R = torch.as_tensor(r, device=dev).contiguous()
+        out = plan.local_energy(P, R)
+        ms = _event_reps(lambda: plan.local_energy(P, R, out=out), max(2, args.steps))
+        lp, _ = plan.logpsi(P, R)
+        lpt = _event_reps(lambda: plan.logpsi(P, R, out=(lp, None)), max(2, args.steps))
+        torch.cuda.synchronize()
+        e = out["e_loc"][:nw].cpu().numpy()
+        err = np.abs(e - ref["e_loc"]) * 1e3
+        rel = np.abs(e - ref["e_loc"]) / scale
+        lerr = np.abs(lp[:nw].cpu().numpy() - ref["logpsi"])
+        rows[prec] = {"e_loc_ms_events": dist(ms), "e_loc_per_s": W / (np.median(ms) * 1e-3),
+                      "logpsi_ms_events": dist(lpt), "tiles": plan.tiles()[0],
+                      "e_loc_err_mha": {"p50": float(np.median(err)), "p99": float(np.percentile(err, 99)),
+                                        "max": float(err.max()), "mean_energy": float(abs(e.mean() - ref["e_loc"].mean()) * 1e3)},
+                      "e_loc_err_rel_largest_addend_max": float(rel.max()),
+                      "value_logpsi_abs_err": {"p50": float(np.median(lerr)), "max": float(lerr.max())}}
+        print(f"[precision] {prec}: E_L {np.median(ms):.1f} ms, p50 {np.median(err):.3g} mHa, max {err.max():.3g} mHa",
+              file=sys.stderr, flush=True)
+        del plan, P, R, out, lp
+        torch.cuda.empty_cache()
+    res = {
+        "metric": "walker local energies/sec at stated mHa error vs FP64 oracle; VMC train step ms",
+        "value": rows["fp32"]["e_loc_per_s"], "unit": "walkers/s", "n_gpus": 1, "steps": max(2, args.steps),
+        "warmup": 1, "ms_per_step": float(np.median(rows["fp32"]["e_loc_ms_events"]["median"])),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64 (bf16 variants below)",
+        "data": "synthetic",
+        "config": {"workload": f"C4H4-sized: 4 C + 4 H, 14 up + 14 down, {W} walkers, width {a.width}, "
+                               f"{a.n_det} dets; step = local energy", "walkers": W},
+        "oracle_sample": {"walkers": nw, "seconds": t_or, "cores": torch.get_num_threads(),
+                          "params": "float32-rounded"},
+        "variants": rows,
+    }
+    print(json.dumps(res))
 
 
 def bench_batched(args):

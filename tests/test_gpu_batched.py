@@ -167,3 +167,45 @@ def test_autotuned_tiles_bitwise(precision):
     got = _step(tuned, P, R, noise, u)
     for k in ref:
         np.testing.assert_array_equal(got[k], ref[k], err_msg=k)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_batch_workload_molecules_vs_oracle(precision):
+    """Four molecules of the 16-molecule batch (4, 17, 29 and 42 electrons: the smallest and the
+    largest, spin blocks of 2 to 21 electrons, both aggregation kernels), 2 walkers each, in one
+    concurrent plan: local energies and the loss gradient against the oracle (float64: 1e-10 of
+    the largest E_L addend and normwise; float32: the amplification-scaled bounds)."""
+    from tests.test_gpu_parity import amplification, fp32_eloc_bound, fp32_grad_bound
+    wl = qi.workload(4)
+    a = wl.ansatz
+    idx = [0, 5, 10, 15]
+    mols = [wl.systems[k] for k in idx]
+    assert [m.n_elec for m in mols] == [4, 17, 29, 42]
+    params = [qi.make_params(m, a, qi.seed(4, 10 + k)) for k, m in zip(idx, mols)]
+    pos = [qi.make_walkers(m, 2, qi.seed(4, 40 + k)) for k, m in zip(idx, mols)]
+    q = _q()
+    plan = q.Plan(mols, [2] * 4, a, precision, concurrent=True)
+    P, R = dev(_cat(params), plan.param_dtype), dev(_cat(pos))
+    out = plan.local_energy(P, R)
+    g, em = plan.loss_grad(P, R, out["e_loc"])
+    torch.cuda.synchronize()
+    e = host(out["e_loc"])
+    G = host(g).astype(np.float64)
+    p0 = 0
+    for k, (s, p, r) in enumerate(zip(mols, params, pos)):
+        pr = p.astype(np.float32).astype(np.float64) if precision == "fp32" else p
+        ref = oracle.local_energy(r, pr, s, a)
+        scale = np.maximum.reduce([np.abs(ref["e_loc"]), 0.5 * np.abs(ref["lap"]),
+                                   0.5 * (ref["grad"] ** 2).sum((1, 2)), np.ones(2)])
+        err = np.abs(e[2 * k:2 * k + 2] - ref["e_loc"]) / scale
+        Gref, em_ref, _ = oracle.loss_grad(r, e[2 * k:2 * k + 2], pr, s, a)
+        n = len(p)
+        gerr = np.linalg.norm(G[p0:p0 + n] - Gref) / np.linalg.norm(Gref)
+        alpha = amplification(r, p, s, a)
+        print(f"[batch {precision} N={s.n_elec}] E_L/scale {err.max():.3e} (alpha {alpha.max():.3g}), "
+              f"loss gradient {gerr:.3e}, E mean {host(em)[k]:.6f} vs {em_ref:.6f}", flush=True)
+        if precision == "fp64":
+            assert err.max() < 1e-10 and gerr < 1e-10
+        else:
+            assert np.all(err <= fp32_eloc_bound(alpha)) and gerr < fp32_grad_bound(alpha)
+        p0 += n
