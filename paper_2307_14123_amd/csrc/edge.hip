@@ -14,15 +14,26 @@
 // propagated across the three rows of a pair (lanes 3p'..3p'+2 of a 16-lane
 // group) with shuffles: t = tanh(z0), t' z1, t' z2 + t'' z1^2.
 //
+// At width 128 the second layer runs on bf16 matrix cores with float32 accuracy: each
+// operand x is split into three bf16 pieces x = x0 + x1 + x2 (x0 = bf16(x), x1 = bf16(x - x0),
+// x2 = bf16(x - x0 - x1), round to nearest; the differences are exact in float32, |x1| <= 2^-8 |x|,
+// |x2| <= 2^-16 |x| and |x - x0 - x1 - x2| <= 2^-24 |x|), and the product is the sum of the six
+// piece products whose orders add up to at most 2 (each exact in float32, accumulated in float32
+// by the MFMA; the three omitted ones add up to at most about 2^-23 |x y|): float32-level error.
+// The order-0 product goes to one accumulator, the five corrections to two others, added at the end.
+// Six v_mfma_f32_16x16x32_bf16 replace eight v_mfma_f32_16x16x4f32 per 32 hidden units, at
+// 16 instead of 32 cycles each.  The lane holding z for hidden units 16 hb + 4 g + i of
+// pair row c supplies k-slots 8 g + 4 (hb mod 2) + i of the MFMA covering hb = 2 m, 2 m + 1, and
+// U2's three pieces are stored in LDS in that k order (16-byte chunks XOR-swizzled by column).
+//
 // A persistent grid keeps U2 (transposed, 16-byte chunks XOR-swizzled by row
-// against LDS bank conflicts) and U1, a1, a2 in LDS, one copy per block of 12
-// waves (three per SIMD); each wave takes 16 pair rows at a time.  A launch
+// against LDS bank conflicts) and U1, a1, a2 in LDS, one copy per block of 8
+// waves (two per SIMD: the register budget); each wave takes 16 pair rows at a time.  A launch
 // writes 128 output columns from c0 on: width 256 takes two launches, each
 // recomputing the 256 hidden units (the half of U2 it needs fills 128 KB of LDS).  The radial
 // basis takes its exponent in float64 and the exponential of its fractional part
 // in float32 (rbf3_f32); tanh is the float32 form of act.h.
 #include <algorithm>
-#include <cstdlib>
 #include <cstring>
 
 #include "act.h"
@@ -32,6 +43,7 @@
 namespace qmc {
 
 typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 constexpr int ED = 128;  // output columns per launch
 
@@ -61,23 +73,49 @@ struct EdgeMlpBatch {
   int b1, b2;
 };
 
+// Splits x into three bf16 pieces (round to nearest each): x0 + x1 + x2 = x within 2^-27 |x|.
+__device__ inline void split3(float x, __bf16& x0, __bf16& x1, __bf16& x2) {
+  x0 = (__bf16)x;
+  const float r1 = x - (float)x0;
+  x1 = (__bf16)r1;
+  x2 = (__bf16)(r1 - (float)x1);
+}
+
 template <int JET, int NW, int EH>
 __global__ __launch_bounds__(64 * NW) void edge_mlp_kernel(SysDev s, EdgeMlpBatch B, int c0) {
+  constexpr bool SPLIT = EH == 128;  // second layer on bf16 matrix cores with three-piece operands
   const int slot = (int)blockIdx.x < B.b1 ? 0 : ((int)blockIdx.x < B.b2 ? 1 : 2);
   const int bstart = slot == 0 ? 0 : (slot == 1 ? B.b1 : B.b2);
   const int bcount = (slot == 0 ? B.b1 : (slot == 1 ? B.b2 : (int)gridDim.x)) - bstart;
   // (selected field by field: the slot is uniform, and no copy of the batch goes to scratch)
   const EdgeMlpArgs a = slot == 0 ? B.t[0] : (slot == 1 ? B.t[1] : B.t[2]);
-  __shared__ __attribute__((aligned(16))) float u2t[ED * EH];  // U2^T (n, k), chunk (k/4) ^ (n & 7)
+  // float32: U2^T (n, k), 4-float chunk (k/4) ^ (n & 7); split: three bf16 planes of U2^T (n, k'),
+  // k' the MFMA k order, 8-element chunk (k'/8) ^ (n & 15)
+  __shared__ __attribute__((aligned(16))) char u2raw[SPLIT ? 3 * ED * EH * 2 : ED * EH * 4];
   __shared__ __attribute__((aligned(16))) float u1t[EH * 16];  // U1^T (k, r), r < 16
   __shared__ float a1s[EH], a2s[ED];
+  float* u2t = (float*)u2raw;
+  __bf16* u2b = (__bf16*)u2raw;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int g = lane >> 4, c = lane & 15;
   const int K = s.K;
   const double rs = rbf_spacing(s.dmax, K), ris = (K - 1) / s.dmax;
   for (int e = tid; e < ED * EH; e += 64 * NW) {
     const int k = e / ED, n = e - k * ED;
-    u2t[n * EH + (((k >> 2) ^ (n & 7)) << 2) + (k & 3)] = a.U2[(int64_t)k * EH + c0 + n];
+    const float v = a.U2[(int64_t)k * EH + c0 + n];
+    if constexpr (SPLIT) {
+      // hidden unit k = 32 m + 16 h + 4 gg + i sits at k-slot 8 gg + 4 h + i of block m
+      const int m = k >> 5, h = (k >> 4) & 1, gg = (k >> 2) & 3, i = k & 3;
+      const int ch = (4 * m + gg) ^ (n & 15);
+      const int at = n * EH + ch * 8 + 4 * h + i;
+      __bf16 p0, p1, p2;
+      split3(v, p0, p1, p2);
+      u2b[at] = p0;
+      u2b[ED * EH + at] = p1;
+      u2b[2 * ED * EH + at] = p2;
+    } else {
+      u2t[n * EH + (((k >> 2) ^ (n & 7)) << 2) + (k & 3)] = v;
+    }
   }
   for (int e = tid; e < EH * 16; e += 64 * NW) {
     const int k = e >> 4, r = e & 15;
@@ -167,6 +205,59 @@ __global__ __launch_bounds__(64 * NW) void edge_mlp_kernel(SysDev s, EdgeMlpBatc
 #pragma unroll
       for (int hb = 0; hb < EH / 16; ++hb) *(f4*)&a.zout[pr * EH + 16 * hb + 4 * g] = z[hb];
     }
+    if constexpr (SPLIT) {
+      // ---- second layer on bf16 matrix cores: operand pieces of the 32 hidden units of block m
+      bf16x8 zp[3][EH / 32];
+#pragma unroll
+      for (int m = 0; m < EH / 32; ++m)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          __bf16 p0, p1, p2;
+          split3(z[2 * m + (j >> 2)][j & 3], p0, p1, p2);
+          zp[0][m][j] = p0;
+          zp[1][m][j] = p1;
+          zp[2][m][j] = p2;
+        }
+#pragma unroll 1
+      for (int nb = 0; nb < ED / 16; nb += 2) {
+        f4 h0 = {0.f, 0.f, 0.f, 0.f}, h1 = h0, la0 = h0, la1 = h0, lb0 = h0, lb1 = h0;
+        const int n0 = 16 * nb + c, n1 = n0 + 16;
+#pragma unroll
+        for (int m = 0; m < EH / 32; ++m) {
+          const int o0 = n0 * EH + (((4 * m + g) ^ (n0 & 15)) << 3);
+          const int o1 = n1 * EH + (((4 * m + g) ^ (n1 & 15)) << 3);
+          bf16x8 b0[3], b1[3];
+#pragma unroll
+          for (int p = 0; p < 3; ++p) {
+            b0[p] = *(const bf16x8*)&u2b[p * ED * EH + o0];
+            b1[p] = *(const bf16x8*)&u2b[p * ED * EH + o1];
+          }
+          lb0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(zp[2][m], b0[0], lb0, 0, 0, 0);
+          lb1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(zp[2][m], b1[0], lb1, 0, 0, 0);
+          la0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(zp[1][m], b0[0], la0, 0, 0, 0);
+          la1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(zp[1][m], b1[0], la1, 0, 0, 0);
+          lb0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(zp[1][m], b0[1], lb0, 0, 0, 0);
+          lb1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(zp[1][m], b1[1], lb1, 0, 0, 0);
+          la0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(zp[0][m], b0[1], la0, 0, 0, 0);
+          la1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(zp[0][m], b1[1], la1, 0, 0, 0);
+          lb0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(zp[0][m], b0[2], lb0, 0, 0, 0);
+          lb1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(zp[0][m], b1[2], lb1, 0, 0, 0);
+          h0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(zp[0][m], b0[0], h0, 0, 0, 0);
+          h1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(zp[0][m], b1[0], h1, 0, 0, 0);
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int r = 4 * g + i;
+          const int rp = JET ? r / 3 : r, re = JET ? r - 3 * rp : 0;
+          const int64_t op = p0 + rp;
+          if ((JET && r == 15) || op >= a.pairs) continue;
+          const int64_t orow = JET ? op * 4 + re : op;
+          a.out[orow * EH + c0 + n0] = (h0[i] + (la0[i] + lb0[i])) + (re == 0 ? a2s[n0] : 0.f);
+          a.out[orow * EH + c0 + n1] = (h1[i] + (la1[i] + lb1[i])) + (re == 0 ? a2s[n1] : 0.f);
+        }
+      }
+      continue;
+    }
     // ---- second layer, two 16-column blocks at a time
 #pragma unroll 1
     for (int nb = 0; nb < ED / 16; nb += 2) {
@@ -223,17 +314,13 @@ hipError_t launch_edge_mlp_types(const SysDev& s, const EdgeMlpArgs* a, int n, h
   }
   if (m == 0) return hipSuccess;
   const int jet = a[0].jet;
-  static int cus = 0, nw = 12;
+  static int cus = 0;
   if (cus == 0) {
     int dev = 0, c = 0;
     cus = (hipGetDevice(&dev) == hipSuccess &&
            hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && c > 0)
               ? c
               : 256;
-    // waves per block: 12 (three per SIMD, one block per compute unit: the VGPR budget) by default;
-    // QMC_EDGE_WAVES=4 for two blocks of 4 (a tuning knob)
-    const char* e = std::getenv("QMC_EDGE_WAVES");
-    nw = e && std::atoi(e) == 4 ? 4 : 12;
   }
   // blocks of w waves share one copy of their type's weights in LDS (73 KB); as many blocks as fit
   // per compute unit, split among the types in proportion to their tiles (at least one each, at
@@ -261,15 +348,10 @@ hipError_t launch_edge_mlp_types(const SysDev& s, const EdgeMlpArgs* a, int n, h
         go(edge_mlp_kernel<0, 8, 256>, 8, c0);
     }
   } else if (jet) {
-    if (nw == 4)
-      go(edge_mlp_kernel<1, 4, 128>, 4, 0);
-    else
-      go(edge_mlp_kernel<1, 12, 128>, 12, 0);
+    // the three-piece operands take 48 more registers than the float32 form: two waves per SIMD
+    go(edge_mlp_kernel<1, 8, 128>, 8, 0);
   } else {
-    if (nw == 4)
-      go(edge_mlp_kernel<0, 4, 128>, 4, 0);
-    else
-      go(edge_mlp_kernel<0, 12, 128>, 12, 0);
+    go(edge_mlp_kernel<0, 8, 128>, 8, 0);
   }
   return hipGetLastError();
 }
