@@ -617,10 +617,15 @@ def c4h4_record(dev, with_oracle=True, reps=3, n_err=4):
     return rec
 
 
-def batched_record(W, prec, steps, warmup, dev):
+def batched_record(W, prec, steps, warmup, dev, packing_bound=False):
     """16 molecules x W walkers: local energy + loss gradient of the whole batch as one graph launch
     (a concurrent, autotuned plan: one stream per molecule inside the graph) against per-molecule
-    launches (one plan per molecule, run one after another)."""
+    launches (one plan per molecule, run one after another).
+
+    packing_bound: also time every molecule alone at 8 W walkers, where its kernels fill the device.
+    No single launch that packs the molecules' tiles together can process a molecule's W walkers
+    faster than a full device does (per walker), so sum_m t_m(8 W) / 8 is a lower bound on the
+    batch's time in any grouped launch, and (per-molecule time) / that bound caps its speed-up."""
     import torch
     import qmc_inputs as qi
     from paper_2307_14123_amd import qmc
@@ -649,6 +654,23 @@ def batched_record(W, prec, steps, warmup, dev):
         del plan, o
         torch.cuda.empty_cache()
     ms_per_mol = float(sum(per_mol))
+    full = []
+    if packing_bound:
+        for m, p, r in zip(mols, params, pos):
+            W8 = 8 * W
+            plan = qmc.Plan([m], [W8], a, prec)
+            Pm = torch.as_tensor(p, dtype=dt, device=dev)
+            Rm = torch.as_tensor(np.concatenate([r] * 8).ravel(), device=dev).contiguous()
+            o = plan.local_energy(Pm, Rm)
+
+            def one8():
+                plan.local_energy(Pm, Rm, out=o)
+                plan.loss_grad(Pm, Rm, o["e_loc"])
+            full.append(timed(one8, 2) / 8)
+            print(f"[batched] {m.n_up + m.n_down} electrons: {per_mol[len(full) - 1]:.2f} ms at {W} walkers, "
+                  f"{full[-1]:.2f} ms per {W} at {W8}", file=sys.stderr, flush=True)
+            del plan, o, Rm
+            torch.cuda.empty_cache()
 
     # the batch: one plan, concurrent molecules, autotuned tiles
     t0 = time.perf_counter()
@@ -678,6 +700,9 @@ def batched_record(W, prec, steps, warmup, dev):
            "batched_graph_ms": ms_graph, "batched_eager_ms": ms_eager, "per_molecule_ms": ms_per_mol,
            "per_molecule_ms_each": [round(x, 3) for x in per_mol],
            "speedup_graph_vs_per_molecule": ms_per_mol / ms_graph, "autotune_s": t_tune, "tiles": plan.tiles(),
+           **({"full_device_ms_each_per_W": [round(x, 3) for x in full],
+               "packed_lower_bound_ms": float(sum(full)),
+               "grouped_launch_speedup_cap": ms_per_mol / float(sum(full))} if full else {}),
            "kernels_ms_eager_pass": {k: round(v[1], 3) for k, v in sorted(prof.items(), key=lambda kv: -kv[1][1])[:12]}}
     del g, plan, P, R, o
     return rec
@@ -755,7 +780,7 @@ def bench_batched(args):
     wl = qi.workload(4)
     W = args.walkers or wl.walkers
     prec = args.precision
-    rec = batched_record(W, prec, args.steps, args.warmup, torch.device("cuda", 0))
+    rec = batched_record(W, prec, args.steps, args.warmup, torch.device("cuda", 0), packing_bound=True)
     Wt = W * len(wl.systems)
     res = {
         "metric": "walker local energies/sec at stated mHa error vs FP64 oracle; VMC train step ms",

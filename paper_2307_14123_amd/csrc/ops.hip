@@ -228,8 +228,11 @@ hipError_t launch_init_features(const SysDev& s, const double* ee, const double*
 // propagated with the product rule, written as [W][N][Rp][2D].  (The nuclear
 // message is nonzero in 5 jet rows only and is handled by nuc_message_kernel.)
 //
-// Block: one walker and a chunk of DC columns.  Thread: one column d and one
-// group of up to RG receivers of the same spin.  The group's filter values
+// Block: one walker, a chunk of DC columns and a part of its receiver groups
+// (all of them unless DC columns x all groups exceed 512 threads: then the
+// groups are split over `parts` adjacent blocks of gpb groups each, which read
+// the same sender rows).  Thread: one column d and one group of up to RG
+// receivers of the same spin.  The group's filter values
 // w(d_ij) for every sender stay in registers in fixed sender slots (up
 // electrons, then down electrons, NS slots each; empty slots hold weight 0 and
 // read a valid row, so the sums have no branches), and same/opposite follows
@@ -247,13 +250,13 @@ hipError_t launch_init_features(const SysDev& s, const double* ee, const double*
 template <typename S, int NS, int RG>
 __global__ __launch_bounds__(512) void aggregate_kernel(SysDev s, const S* __restrict__ h,
                                                         const S* __restrict__ wsame, const S* __restrict__ wopp,
-                                                        const double* __restrict__ ee, int DC, int nch,
-                                                        S* __restrict__ m) {
+                                                        const double* __restrict__ ee, int DC, int nch, int parts,
+                                                        int gpb, S* __restrict__ m) {
   extern __shared__ __align__(16) unsigned char smem[];
   constexpr int OPP = 1 << 30;
   const int N = s.N, D = s.D, Rp = s.Rp, T = s.T, nup = s.nup, ndn = s.ndn;
-  const int64_t w = blockIdx.x / nch;
-  const int chunk = blockIdx.x - (int)(w * nch);
+  const int64_t w = blockIdx.x / ((int64_t)nch * parts);
+  const int cp = (int)(blockIdx.x - w * nch * parts), chunk = cp / parts, part = cp - chunk * parts;
   S* gu = (S*)smem;                  // [N][N][4]: d_ij, unit vector of r_i - r_j
   int* pt = (int*)(gu + N * N * 4);  // [N][N]: pair index within its type, | OPP for an up-down pair
   for (int e = threadIdx.x; e < N * N * 4; e += blockDim.x) gu[e] = (S)ee[w * N * N * 4 + e];
@@ -268,10 +271,10 @@ __global__ __launch_bounds__(512) void aggregate_kernel(SysDev s, const S* __res
     pt[e] = v;
   }
   __syncthreads();
-  const int dr = chunk * DC + (int)(threadIdx.x % DC), g = threadIdx.x / DC;
+  const int dr = chunk * DC + (int)(threadIdx.x % DC), gl = threadIdx.x / DC, g = part * gpb + gl;
   const int ngu = (nup + RG - 1) / RG, ngd = (ndn + RG - 1) / RG;
   // threads past the last column or group compute nothing (cnt = 0) but meet the barriers
-  const bool live = dr < D && g < ngu + ngd;
+  const bool live = dr < D && gl < gpb && g < ngu + ngd;
   const int d = min(dr, D - 1);
   const bool up = g < ngu;
   const int i0 = up ? g * RG : nup + (g - ngu) * RG;
@@ -699,20 +702,40 @@ static hipError_t allow_lds(const void* fn, size_t lds, size_t* done) {
 template <typename S, int NS>
 static hipError_t agg_launch(const SysDev& s, const S* h, const S* ws, const S* wo, const double* ee, int64_t W, S* m,
                              hipStream_t st) {
-  constexpr int RG = (NS <= 16 && sizeof(S) == 4) ? 2 : 1;  // receivers per thread (register budget)
+  constexpr int RG = (NS <= 24 && sizeof(S) == 4) ? 2 : 1;  // receivers per thread (register budget)
   const int ngroups = (s.nup + RG - 1) / RG + (s.ndn + RG - 1) / RG;
-  // columns per block: the largest power of two up to 64 with all groups in at most 512 threads
+  // columns per block: the largest power of two up to 64 with all groups in at most 512 threads, but
+  // not below 32 (128-byte row segments per load): more groups go to `parts` blocks of gpb each
   int DC = 64;
-  while (DC > 1 && (DC >= 2 * s.D || DC * ngroups > 512)) DC >>= 1;
+  while (DC > 1 && (DC >= 2 * s.D || (DC > 32 && DC * ngroups > 512))) DC >>= 1;
   const int nch = (s.D + DC - 1) / DC;
   const size_t lds = (size_t)s.N * s.N * 4 * sizeof(S) + (size_t)s.N * s.N * sizeof(int);
   static size_t lds_set[64] = {};
   const hipError_t le = allow_lds((const void*)aggregate_kernel<S, NS, RG>, lds, lds_set);
   if (le != hipSuccess) return le;
+  // receiver parts: the fewest that reach the most busy threads per compute unit (resident blocks x
+  // threads with a group), as the kernel's occupancy gives them for each block size
+  int parts = 1;
+  if (DC * ngroups > 512) {
+    long best = -1;
+    for (int p = 2; p <= 8; ++p) {
+      const int gp = (ngroups + p - 1) / p;
+      if (DC * gp > 512) continue;
+      int occ = 0;
+      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, aggregate_kernel<S, NS, RG>, DC * gp, lds) != hipSuccess)
+        occ = 1;
+      const long busy = (long)std::max(occ, 1) * DC * gp * 100 / (100 + 3 * (p - 2));  // 3 % per extra part
+      if (busy > best) {
+        best = busy;
+        parts = p;
+      }
+    }
+  }
+  const int gpb = (ngroups + parts - 1) / parts;
   ProfScope ps("aggregate_kernel", st);
   // blocks of one walker are adjacent, so they run together and share its rows in L2
-  hipLaunchKernelGGL((aggregate_kernel<S, NS, RG>), dim3((unsigned)(W * nch)), dim3(DC * ngroups), lds, st, s, h, ws,
-                     wo, ee, DC, nch, m);
+  hipLaunchKernelGGL((aggregate_kernel<S, NS, RG>), dim3((unsigned)(W * nch * parts)), dim3(DC * gpb), lds, st, s, h,
+                     ws, wo, ee, DC, nch, parts, gpb, m);
   return hipGetLastError();
 }
 
@@ -755,10 +778,15 @@ hipError_t launch_aggregate(const SysDev& s, const S* h, const S* wsame, const S
   const int ns = std::max(s.nup, s.ndn);
   if (ns <= 4) return agg_launch<S, 4>(s, h, wsame, wopp, ee, W, m, st);
   if (ns <= 8) return agg_launch<S, 8>(s, h, wsame, wopp, ee, W, m, st);
-  // float32 up to 16 electrons per spin: the streaming kernel (one receiver per thread above 8);
-  // larger spin blocks, and float64 above 8, stage the senders' rows in LDS (register budget)
+  // float32: the streaming kernel up to 32 electrons per spin (two receivers per thread up to 24,
+  // one above); float64 above 8 electrons per spin stages the senders' rows in LDS (register budget)
   if constexpr (sizeof(S) == 4)
     if (ns <= 16) return agg_launch<S, 16>(s, h, wsame, wopp, ee, W, m, st);
+  if constexpr (sizeof(S) == 4) {
+    if (ns <= 20) return agg_launch<S, 20>(s, h, wsame, wopp, ee, W, m, st);
+    if (ns <= 24) return agg_launch<S, 24>(s, h, wsame, wopp, ee, W, m, st);
+    if (ns <= 32) return agg_launch<S, 32>(s, h, wsame, wopp, ee, W, m, st);
+  }
   if (ns <= 16) return agg_lds_launch<S, 16>(s, h, wsame, wopp, ee, W, m, st);
   if (ns <= 24) return agg_lds_launch<S, 24>(s, h, wsame, wopp, ee, W, m, st);
   if (ns <= 32) return agg_lds_launch<S, 32>(s, h, wsame, wopp, ee, W, m, st);
