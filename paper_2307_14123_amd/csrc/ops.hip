@@ -714,17 +714,18 @@ static hipError_t agg_launch(const SysDev& s, const S* h, const S* ws, const S* 
   const hipError_t le = allow_lds((const void*)aggregate_kernel<S, NS, RG>, lds, lds_set);
   if (le != hipSuccess) return le;
   // receiver parts: the fewest that reach the most busy threads per compute unit (resident blocks x
-  // threads with a group), as the kernel's occupancy gives them for each block size
+  // threads with a group, on average over the parts), as the kernel's occupancy gives them for each
+  // block size; every extra part re-reads the walker's sender rows (3 % per part)
   int parts = 1;
-  if (DC * ngroups > 512) {
+  {
     long best = -1;
-    for (int p = 2; p <= 8; ++p) {
+    for (int p = 1; p <= 8 && p <= ngroups; ++p) {
       const int gp = (ngroups + p - 1) / p;
       if (DC * gp > 512) continue;
       int occ = 0;
       if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, aggregate_kernel<S, NS, RG>, DC * gp, lds) != hipSuccess)
         occ = 1;
-      const long busy = (long)std::max(occ, 1) * DC * gp * 100 / (100 + 3 * (p - 2));  // 3 % per extra part
+      const long busy = (long)std::max(occ, 1) * DC * ngroups * 100 / ((long)p * (100 + 3 * (p - 1)));
       if (busy > best) {
         best = busy;
         parts = p;
@@ -780,8 +781,10 @@ hipError_t launch_aggregate(const SysDev& s, const S* h, const S* wsame, const S
   if (ns <= 8) return agg_launch<S, 8>(s, h, wsame, wopp, ee, W, m, st);
   // float32: the streaming kernel up to 32 electrons per spin (two receivers per thread up to 24,
   // one above); float64 above 8 electrons per spin stages the senders' rows in LDS (register budget)
-  if constexpr (sizeof(S) == 4)
+  if constexpr (sizeof(S) == 4) {
+    if (ns <= 12) return agg_launch<S, 12>(s, h, wsame, wopp, ee, W, m, st);
     if (ns <= 16) return agg_launch<S, 16>(s, h, wsame, wopp, ee, W, m, st);
+  }
   if constexpr (sizeof(S) == 4) {
     if (ns <= 20) return agg_launch<S, 20>(s, h, wsame, wopp, ee, W, m, st);
     if (ns <= 24) return agg_launch<S, 24>(s, h, wsame, wopp, ee, W, m, st);
