@@ -9,7 +9,7 @@
       --kernel-trace --stats run of the same program
   python -m paper_2307_14123_amd.profiling mfma <pmc dir> <kernel_stats.csv> --command "<cmd>" --out <file.md>
       matrix-core and VALU counters per kernel family from one --pmc run of SQ_VALU_MFMA_BUSY_CYCLES,
-      SQ_BUSY_CYCLES, SQ_BUSY_CU_CYCLES, SQ_INSTS_MFMA, SQ_INSTS_VALU, SQ_INSTS_VALU_MFMA_MOPS_F32,
+      SQ_BUSY_CYCLES, SQ_INSTS_MFMA, SQ_INSTS_VALU, SQ_INSTS_VALU_MFMA_MOPS_F32, SQ_INSTS_VALU_MFMA_MOPS_BF16,
       SQ_LDS_BANK_CONFLICT, SQ_WAIT_INST_LDS and GRBM_GUI_ACTIVE, with durations from a --kernel-trace
       --stats run of the same program
   python -m paper_2307_14123_amd.profiling traffic <fetch dir> <write dir> --family "gemm_kernel<jet>"
@@ -163,8 +163,9 @@ def hbm(fetch_dir: str, write_dir: str, stats_csv: str, command: str, top: int =
     return "\n".join(out) + "\n"
 
 
-MFMA_COUNTERS = ("SQ_VALU_MFMA_BUSY_CYCLES", "SQ_BUSY_CYCLES", "SQ_BUSY_CU_CYCLES", "SQ_INSTS_MFMA", "SQ_INSTS_VALU",
-                 "SQ_INSTS_VALU_MFMA_MOPS_F32", "SQ_LDS_BANK_CONFLICT", "SQ_WAIT_INST_LDS", "GRBM_GUI_ACTIVE")
+MFMA_COUNTERS = ("SQ_VALU_MFMA_BUSY_CYCLES", "SQ_BUSY_CYCLES", "SQ_INSTS_MFMA", "SQ_INSTS_VALU",
+                 "SQ_INSTS_VALU_MFMA_MOPS_F32", "SQ_INSTS_VALU_MFMA_MOPS_BF16", "SQ_LDS_BANK_CONFLICT",
+                 "SQ_WAIT_INST_LDS", "GRBM_GUI_ACTIVE")
 SIMDS = 256 * 4  # MI355X: 256 compute units of 4 SIMDs
 CLOCK_HZ = 2.4e9  # MI355X peak engine clock
 
@@ -192,14 +193,16 @@ def mfma(pmc_dir: str, stats_csv: str, command: str, top: int = 14) -> str:
            f"- MFMA busy = SQ_VALU_MFMA_BUSY_CYCLES / (average duration x {CLOCK_HZ / 1e9:.1f} GHz x {SIMDS} SIMDs): "
            "the share of SIMD-cycles in which the matrix core was busy (the counter is summed over the SIMDs);",
            "- MFMA TFLOP/s = SQ_INSTS_VALU_MFMA_MOPS_F32 x 512 flops / average duration: executed float32 MFMA work "
-           "(padding rows included) per second;",
+           "(padding rows included) per second; bf16 TFLOP/s the same from SQ_INSTS_VALU_MFMA_MOPS_BF16 (the edge "
+           "filters' three-piece second layer: six bf16 products per float32 product);",
            "- VALU / MFMA = SQ_INSTS_VALU / SQ_INSTS_MFMA (SQ_INSTS_VALU counts the MFMA instructions too);",
            "- LDS bank-conflict cycles and LDS-issue waits (quad-cycles) per dispatch;",
            f"- GRBM / clk and SQ busy / clk: GRBM_GUI_ACTIVE and SQ_BUSY_CYCLES over average duration x "
            f"{CLOCK_HZ / 1e9:.1f} GHz, the number of counter instances summed (a check of the clock assumption).", "",
-           "| family | dispatches | average us | MFMA busy | MFMA TFLOP/s (f32) | MFMA insts / dispatch | "
-           "VALU / MFMA | LDS bank-conflict cycles / dispatch | LDS wait / dispatch | GRBM / clk | SQ busy / clk |",
-           "|---|---|---|---|---|---|---|---|---|---|---|"]
+           "| family | dispatches | average us | MFMA busy | MFMA TFLOP/s (f32) | MFMA TFLOP/s (bf16) | "
+           "MFMA insts / dispatch | VALU / MFMA | LDS bank-conflict cycles / dispatch | LDS wait / dispatch | "
+           "GRBM / clk | SQ busy / clk |",
+           "|---|---|---|---|---|---|---|---|---|---|---|---|"]
     rows = []
     for f, v in fam.items():
         n = v.get("dispatches", 0)
@@ -211,8 +214,9 @@ def mfma(pmc_dir: str, stats_csv: str, command: str, top: int = 14) -> str:
         cyc = avg_s * CLOCK_HZ
         util = v["SQ_VALU_MFMA_BUSY_CYCLES"] / n / (cyc * SIMDS)
         tf = v["SQ_INSTS_VALU_MFMA_MOPS_F32"] * 512.0 / n / avg_s / 1e12
+        tb = v["SQ_INSTS_VALU_MFMA_MOPS_BF16"] * 512.0 / n / avg_s / 1e12
         ratio = v["SQ_INSTS_VALU"] / v["SQ_INSTS_MFMA"] if v["SQ_INSTS_MFMA"] > 0 else float("nan")
-        out.append(f"| {f} | {n} | {avg_s * 1e6:.1f} | {100 * util:.1f}% | {tf:.1f} | {v['SQ_INSTS_MFMA'] / n:.3g} | "
+        out.append(f"| {f} | {n} | {avg_s * 1e6:.1f} | {100 * util:.1f}% | {tf:.1f} | {tb:.1f} | {v['SQ_INSTS_MFMA'] / n:.3g} | "
                    f"{ratio:.2f} | {v['SQ_LDS_BANK_CONFLICT'] / n:.3g} | {v['SQ_WAIT_INST_LDS'] / n:.3g} | "
                    f"{v['GRBM_GUI_ACTIVE'] / n / cyc:.2f} | {v['SQ_BUSY_CYCLES'] / n / cyc:.2f} |")
     out += ["", "Raw sums over the counter run:", "", "| family | " + " | ".join(MFMA_COUNTERS) + " |",
