@@ -209,3 +209,43 @@ def test_batch_workload_molecules_vs_oracle(precision):
         else:
             assert np.all(err <= fp32_eloc_bound(alpha)) and gerr < fp32_grad_bound(alpha)
         p0 += n
+
+
+def test_large_spin_blocks_fp32_vs_oracle():
+    """The float32 jet aggregation's register form for large spin blocks, against the oracle: 17 + 17
+    electrons (20 sender slots, two receivers per thread) and 26 + 26 electrons (32 slots, one receiver
+    per thread), each with its receiver groups split over several blocks, in one concurrent plan;
+    local energies within the amplification-scaled float32 bound and the loss gradient within its
+    bound (oracle at the float32-rounded parameters)."""
+    from tests.test_gpu_parity import amplification, fp32_eloc_bound, fp32_grad_bound
+    wl = qi.workload(4)
+    a = wl.ansatz
+    big = qi.System((20.0, 18.0, 14.0), ((0.0, 0.0, 0.0), (3.1, 0.4, -0.6), (-1.2, 2.9, 1.5)), 26, 26)
+    mols = [wl.systems[12], big]
+    assert [(m.n_up, m.n_down) for m in mols] == [(17, 17), (26, 26)]
+    nw = [2, 2]  # (one walker would give E_L - mean = 0: a zero loss gradient)
+    params = [qi.make_params(m, a, qi.seed(4, 90 + k)) for k, m in enumerate(mols)]
+    pos = [qi.make_walkers(m, n, qi.seed(4, 95 + k)) for k, (m, n) in enumerate(zip(mols, nw))]
+    q = _q()
+    plan = q.Plan(mols, nw, a, "fp32", concurrent=True)
+    P, R = dev(_cat(params), plan.param_dtype), dev(_cat(pos))
+    out = plan.local_energy(P, R)
+    g, _ = plan.loss_grad(P, R, out["e_loc"])
+    torch.cuda.synchronize()
+    e = host(out["e_loc"])
+    G = host(g).astype(np.float64)
+    w0 = p0 = 0
+    for s, p, r, n in zip(mols, params, pos, nw):
+        pr = p.astype(np.float32).astype(np.float64)
+        ref = oracle.local_energy(r, pr, s, a)
+        scale = np.maximum.reduce([np.abs(ref["e_loc"]), 0.5 * np.abs(ref["lap"]),
+                                   0.5 * (ref["grad"] ** 2).sum((1, 2)), np.ones(n)])
+        err = np.abs(e[w0:w0 + n] - ref["e_loc"]) / scale
+        Gref, _, _ = oracle.loss_grad(r, e[w0:w0 + n], pr, s, a)
+        gerr = np.linalg.norm(G[p0:p0 + len(p)] - Gref) / np.linalg.norm(Gref)
+        alpha = amplification(r, p, s, a)
+        print(f"[large spin {s.n_up}/{s.n_down} fp32] E_L/scale {err.max():.3e} (alpha {alpha.max():.3g}), "
+              f"loss gradient {gerr:.3e}", flush=True)
+        assert np.all(err <= fp32_eloc_bound(alpha)) and gerr < fp32_grad_bound(alpha)
+        w0 += n
+        p0 += len(p)
