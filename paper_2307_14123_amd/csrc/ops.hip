@@ -686,6 +686,88 @@ __global__ __launch_bounds__(256) void aggregate_value_kernel(SysDev s, const S*
   }
 }
 
+// Value messages for spin blocks of at most NS electrons: a thread per (walker, column) holds the
+// walker's sender features and every receiver's two sums in registers and reads each unordered pair's
+// filter once, adding it to both of its receivers (the pair order, a ascending and then b, gives each
+// receiver its senders in ascending order, as aggregate_value_kernel sums them).  Each filter row is
+// read from memory exactly once, with consecutive columns across the wavefront.
+template <typename S, int NS>
+__global__ __launch_bounds__(256) void aggregate_value_pairs_kernel(SysDev s, const S* __restrict__ h,
+                                                                    const S* __restrict__ wsame,
+                                                                    const S* __restrict__ wopp,
+                                                                    const S* __restrict__ wnuc,
+                                                                    const S* __restrict__ Y, int64_t W,
+                                                                    S* __restrict__ m) {
+  const int N = s.N, D = s.D, M = s.M, nup = s.nup, ndn = s.ndn;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t w = t / D;
+  const int d = (int)(t - w * D);
+  if (w >= W) return;
+  // sender slots: up electrons 0..NS-1, down electrons NS..2NS-1 (zero past the block)
+  S hv[2 * NS], ms[2 * NS], mo[2 * NS];
+  const S* hw = h + w * N * (int64_t)D + d;
+#pragma unroll
+  for (int sl = 0; sl < 2 * NS; ++sl) {
+    const bool ok = sl < NS ? sl < nup : sl - NS < ndn;
+    const S r = hw[ok ? (int64_t)(sl < NS ? sl : nup + sl - NS) * D : 0];
+    hv[sl] = ok ? r : S(0);
+    ms[sl] = mo[sl] = S(0);
+  }
+  const S* ws = wsame + w * s.P0 * (int64_t)D + d;
+  const S* wo = wopp + w * s.P1 * (int64_t)D + d;
+  // Every slot pair issues its load (slot pairs outside the spin blocks read the walker's first
+  // feature row instead and take a zero weight), so that the loads of a thread are independent of
+  // branches and all in flight together.
+  // same-spin pairs (a, b), a < b, of the up block, then of the down block (pair indices as ee_pair)
+#pragma unroll
+  for (int a = 0; a < NS; ++a)
+#pragma unroll
+    for (int b = a + 1; b < NS; ++b) {
+      const bool ok = b < nup;
+      const S r = *(ok ? ws + (int64_t)(a * (2 * nup - a - 1) / 2 + (b - a - 1)) * D : hw);
+      const S x = ok ? r : S(0);
+      ms[a] += x * hv[b];
+      ms[b] += x * hv[a];
+    }
+  const int dn0 = nup * (nup - 1) / 2;
+#pragma unroll
+  for (int a = 0; a < NS; ++a)
+#pragma unroll
+    for (int b = a + 1; b < NS; ++b) {
+      const bool ok = b < ndn;
+      const S r = *(ok ? ws + (int64_t)(dn0 + a * (2 * ndn - a - 1) / 2 + (b - a - 1)) * D : hw);
+      const S x = ok ? r : S(0);
+      ms[NS + a] += x * hv[NS + b];
+      ms[NS + b] += x * hv[NS + a];
+    }
+  // up-down pairs (a, b): index a * ndn + b
+#pragma unroll
+  for (int a = 0; a < NS; ++a)
+#pragma unroll
+    for (int b = 0; b < NS; ++b) {
+      const bool ok = a < nup && b < ndn;
+      const S r = *(ok ? wo + (int64_t)(a * ndn + b) * D : hw);
+      const S x = ok ? r : S(0);
+      mo[a] += x * hv[NS + b];
+      mo[NS + b] += x * hv[a];
+    }
+  const S* wn = wnuc + w * s.P2 * (int64_t)D + d;
+#pragma unroll
+  for (int sl = 0; sl < 2 * NS; ++sl) {
+    const bool up = sl < NS;
+    const int li = up ? sl : sl - NS;
+    if (li >= (up ? nup : ndn)) continue;
+    const int i = up ? li : nup + li;
+    const int nsame = (up ? nup : ndn) - 1, nopp = up ? ndn : nup;
+    S nuc = 0;
+    for (int I = 0; I < M; ++I) nuc += wn[(int64_t)(i * M + I) * D] * Y[I * D + d];
+    S* row = m + (w * N + i) * 3 * (int64_t)D + d;
+    row[0] = nsame > 0 ? ms[sl] / S(nsame) : S(0);
+    row[D] = nopp > 0 ? mo[sl] / S(nopp) : S(0);
+    row[2 * D] = nuc / S(M);
+  }
+}
+
 // Raises a kernel's dynamic-LDS limit above 64 KB, once per device (the attribute is a per-device
 // setting; done[dev] keeps the largest size set so far).
 static hipError_t allow_lds(const void* fn, size_t lds, size_t* done) {
@@ -765,6 +847,18 @@ hipError_t launch_aggregate(const SysDev& s, const S* h, const S* wsame, const S
                             int64_t W, int jet, S* m, hipStream_t st) {
   if (W <= 0) return hipSuccess;
   if (!jet) {
+    const int nsp = std::max(s.nup, s.ndn);
+    if (nsp <= 8) {
+      const int64_t n = W * s.D;
+      ProfScope ps("aggregate_value_kernel", st);
+      if (nsp <= 4)
+        hipLaunchKernelGGL((aggregate_value_pairs_kernel<S, 4>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, s,
+                           h, wsame, wopp, wnuc, Y, W, m);
+      else
+        hipLaunchKernelGGL((aggregate_value_pairs_kernel<S, 8>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, s,
+                           h, wsame, wopp, wnuc, Y, W, m);
+      return hipGetLastError();
+    }
     const size_t tab = ((size_t)s.N * s.N * sizeof(int) + 15) / 16 * 16;
     const size_t hb = (size_t)s.N * s.D * sizeof(S);
     const int stage = tab + hb <= 64 * 1024;
