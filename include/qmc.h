@@ -169,7 +169,9 @@ int64_t qmc_param_count(const qmc_system* system, const qmc_ansatz* ansatz);
  *   maximum).  Calls on such a plan must not overlap (one caller stream at a
  *   time, in host order).
  * QMC_PLAN_AUTOTUNE: qmc_plan_create times the candidate GEMM tiles (K-step,
- *   tile height, persistent grid) on the current device for every system's
+ *   tile height, persistent grid, and for float32 GEMMs the float32 form on
+ *   the bf16 matrix cores with three-piece operands, whose error is at the
+ *   float32 level) on the current device for every system's
  *   jet, value, edge and backward GEMM shapes and keeps the fastest.  This
  *   allocates device memory transiently and synchronises the device. */
 enum { QMC_PLAN_CONCURRENT_SYSTEMS = 1u, QMC_PLAN_AUTOTUNE = 2u };
@@ -203,7 +205,8 @@ qmc_status qmc_plan_chunk_walkers(const qmc_plan* plan, int32_t s, int64_t* walk
 /* GEMM tile choice of system s, one entry per GEMM class (electron jets,
  * value rows, edge jets, backward value rows): 0 = built-in default, else
  * 1 + bits (bit 0: 32-wide K steps, bit 1: 64-row tiles, bit 2: persistent
- * grid).  Host only. */
+ * grid, bit 3: float32 operands split into three bf16 pieces on the bf16
+ * matrix cores).  Host only. */
 qmc_status qmc_plan_tiles(const qmc_plan* plan, int32_t s, int32_t tiles[4]);
 
 /* Bytes of workspace that operation `op` (QMC_OP_*) needs. */

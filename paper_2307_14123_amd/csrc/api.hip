@@ -766,9 +766,16 @@ static qmc_status autotune(Plan& P) {
       hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
     err = QMC_ERR_HIP;
   const bool f32 = P.prec == QMC_FP32 || P.prec == QMC_BF16_VALUE;
-  // K-step (bit 0) and persistent grids (bit 2) are float32 options
-  const std::vector<int> jet_bits = f32 ? std::vector<int>{0, 1, 4, 5} : std::vector<int>{0};
-  const std::vector<int> row_bits = f32 ? std::vector<int>{0, 1, 2, 3, 4, 6} : std::vector<int>{0, 2};
+  // K-step (bit 0) and persistent grids (bit 2) are float32 options; the three-piece bf16 form (bit 3)
+  // is a candidate at width 256 and above, where the matrix cores bound the wide products (at width 128
+  // the products are bound elsewhere and the form gains nothing)
+  const bool x3 = f32 && D >= 256;
+  std::vector<int> jet_bits = f32 ? std::vector<int>{0, 1, 4, 5} : std::vector<int>{0};
+  std::vector<int> row_bits = f32 ? std::vector<int>{0, 1, 2, 3, 4, 6} : std::vector<int>{0, 2};
+  if (x3) {
+    jet_bits.insert(jet_bits.end(), {8, 12});
+    row_bits.insert(row_bits.end(), {8, 10, 12, 14});
+  }
   for (auto& s : P.sys) {
     if (err != QMC_OK) break;
     const int64_t pmax = std::max<int64_t>(1, std::max(s.P[0], std::max(s.P[1], s.P[2])));

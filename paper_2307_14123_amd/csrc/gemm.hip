@@ -28,7 +28,19 @@
 // as row segments shared by 32 (16 for f64) lanes.
 //
 // MFMA shapes: f64 v_mfma_f64_16x16x4, f32 v_mfma_f32_16x16x4, bf16
-// v_mfma_f32_16x16x32 (operands rounded to bf16, float accumulation).  The
+// v_mfma_f32_16x16x32 (operands rounded to bf16, float accumulation), and
+// float32 on the bf16 matrix cores (tile bit 3, "f32x3"): every operand x is
+// split into three round-to-nearest bf16 pieces x = x0 + x1 + x2 (x0 = bf16(x),
+// x1 = bf16(x - x0), x2 = bf16(x - x0 - x1); the differences are exact in
+// float32 and the pieces represent x within 2^-24 |x|), and each product is the
+// sum of the six piece products of order at most 2, exact in float32 and
+// accumulated in float32 by v_mfma_f32_16x16x32_bf16, smallest first; the
+// omitted products add up to at most about 2^-23 |x y|, so the result has
+// float32-level error.  Six 16-cycle MFMAs replace eight 32-cycle float32 ones
+// per 32 k.  A is split once per element when the tile is stored (three bf16
+// planes in LDS, k-contiguous), B's fragment once per K-step by the wave that
+// owns its columns (float32 in LDS, k-contiguous); one LDS stage (two barriers
+// per K-step) keeps the block at the float32 kernel's LDS size.  The
 // 16x16 accumulator layouts: f32/bf16: lane l, element i -> row 4*(l/16)+i,
 // column l%16; f64: row (l/16)+4*i, column l%16.  Operand layout: lane l
 // supplies row (A) / column (B) l%16 and the k-slice selected by l/16; A and
@@ -49,6 +61,16 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
+constexpr int GK_F32X3 = 3;  // float32 operands on bf16 matrix cores (three-piece split)
+
+// Splits x into three bf16 pieces (round to nearest each): x0 + x1 + x2 = x within 2^-24 |x|.
+__device__ inline void split3(float x, __bf16& x0, __bf16& x1, __bf16& x2) {
+  x0 = (__bf16)x;
+  const float r1 = x - (float)x0;
+  x1 = (__bf16)r1;
+  x2 = (__bf16)(r1 - (float)x1);
+}
+
 template <int KIND> struct GT;
 template <> struct GT<GK_F64> {
   using S = double;
@@ -64,6 +86,11 @@ template <> struct GT<GK_BF16> {
   using S = float;
   using Acc = f4;
   using L = __bf16;
+};
+template <> struct GT<GK_F32X3> {
+  using S = float;
+  using Acc = f4;
+  using L = __bf16;  // the A planes; B stays float32 in LDS
 };
 
 template <typename S> struct V4;
@@ -91,21 +118,24 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs a) {
   constexpr int BM = 16 * MB;
   constexpr int BN = 128;
   constexpr bool BF = (KIND == GK_BF16);
-  constexpr int APAD = BF ? 8 : 4;
+  constexpr bool X3 = (KIND == GK_F32X3);
+  constexpr bool KC = BF || X3;  // k-contiguous tiles ([rows][k], [columns][k])
+  constexpr int APAD = KC ? 8 : 4;
   constexpr int ALD = BK + APAD;
-  constexpr int BLD = BF ? BK + 8 : BN + 4;
-  constexpr int ASZ = BM * ALD;
-  constexpr int BSZ = BF ? BN * BLD : BK * BLD;
+  constexpr int BLD = BF ? BK + 8 : (X3 ? BK + 4 : BN + 4);
+  constexpr int ASZ = BM * ALD;  // one A stage (X3: one of the three planes)
+  constexpr int BSZ = KC ? BN * BLD : BK * BLD;
   // epilogue staging: per wave NCP columns x CLD rows per pass
   constexpr int NPASS = (KIND == GK_F64) ? 2 : 1;
   constexpr int NCP = 32 / NPASS;  // columns staged per pass
   constexpr int LPC = 64 / NCP;    // lanes sharing one column
   constexpr int CLD = BM + 4;
-  constexpr int STAGE_BYTES = 2 * (ASZ + BSZ) * (int)sizeof(L);
+  constexpr int STAGE_BYTES = X3 ? 3 * ASZ * 2 + BSZ * 4 : 2 * (ASZ + BSZ) * (int)sizeof(L);
   constexpr int C_BYTES = 4 * NCP * CLD * (int)sizeof(S);
   __shared__ __attribute__((aligned(16))) char smem[cmax(STAGE_BYTES, C_BYTES)];
   L* const As = (L*)smem;
   L* const Bs = As + 2 * ASZ;
+  float* const Bf = (float*)(smem + 3 * ASZ * 2);  // X3: B stage [BN][BLD]
 
   constexpr int AV = BM * BK / 4, BV = BK * BN / 4;
   constexpr int NA = (AV + 255) / 256, NB = (BV + 255) / 256;
@@ -150,7 +180,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs a) {
     // transposed W and bf16: 4 consecutive k of column n
     int bkk[NB], bnn[NB];
     {
-      const bool tr = BF || a.transw;
+      const bool tr = KC || a.transw;
   #pragma unroll
       for (int u = 0; u < NB; ++u) {
         const int v = tid + 256 * u;
@@ -184,7 +214,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs a) {
         const int kg = k0 + bkk[u];
         int ng = n0 + bnn[u];
         if (MODE == 1 || (MODE == 0 && !a.transw)) {
-          if constexpr (!BF) {
+          if constexpr (!KC) {
             // 4 consecutive columns of W row kg
             if (MODE == 1) ng = ng < a.Ncols ? ng : a.Ncols - 4;
             const S* src = Wt + (int64_t)kg * a.ldw + ng;
@@ -228,7 +258,10 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs a) {
       for (int u = 0; u < NA; ++u) {
         if (tid + 256 * u >= AV) continue;
         L* dst = &As[buf * ASZ + arr[u] * ALD + akk[u]];
-        if constexpr (BF) {
+        if constexpr (X3) {
+  #pragma unroll
+          for (int e = 0; e < 4; ++e) split3(ra[u][e], dst[e], dst[ASZ + e], dst[2 * ASZ + e]);
+        } else if constexpr (BF) {
   #pragma unroll
           for (int e = 0; e < 4; ++e) dst[e] = (L)ra[u][e];
         } else {
@@ -240,7 +273,9 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs a) {
         const int v = tid + 256 * u;
         if (v >= BV) continue;
         const int kk = bkk[u], nn = bnn[u];
-        if constexpr (BF) {
+        if constexpr (X3) {
+          *(Vec*)&Bf[nn * BLD + kk] = Vec{rb[u][0], rb[u][1], rb[u][2], rb[u][3]};
+        } else if constexpr (BF) {
           L* dst = &Bs[buf * BSZ + nn * BLD + kk];
   #pragma unroll
           for (int e = 0; e < 4; ++e) dst[e] = (L)rb[u][e];
@@ -270,6 +305,51 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs a) {
       load_tiles(0, mode_tag);
       store_tiles(0);
       __syncthreads();
+      if constexpr (X3) {
+        for (int kt = 0; kt < nk; ++kt) {
+          if (kt + 1 < nk) load_tiles((kt + 1) * BK, mode_tag);
+          // the wave's two B fragments (columns wave*32 + nb*16 + c, k = 8g .. 8g + 7), split once
+          bf16x8 bp[2][3];
+  #pragma unroll
+          for (int nb = 0; nb < 2; ++nb) {
+            const float* src = &Bf[(wave * 32 + nb * 16 + c) * BLD + 8 * g];
+            const f4 lo = *(const f4*)src, hi = *(const f4*)(src + 4);
+  #pragma unroll
+            for (int j = 0; j < 8; ++j) {
+              __bf16 p0, p1, p2;
+              split3(j < 4 ? lo[j] : hi[j - 4], p0, p1, p2);
+              bp[nb][0][j] = p0;
+              bp[nb][1][j] = p1;
+              bp[nb][2][j] = p2;
+            }
+          }
+  #pragma unroll
+          for (int mb = 0; mb < MB; ++mb) {
+            const int ao = (mb * 16 + c) * ALD + 8 * g;
+            const bf16x8 a0 = *(const bf16x8*)&As[ao], a1 = *(const bf16x8*)&As[ASZ + ao],
+                         a2 = *(const bf16x8*)&As[2 * ASZ + ao];
+            // smallest products first; two independent chains (nb) interleaved
+  #pragma unroll
+            for (int nb = 0; nb < 2; ++nb) acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a2, bp[nb][0], acc[mb][nb], 0, 0, 0);
+  #pragma unroll
+            for (int nb = 0; nb < 2; ++nb) acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, bp[nb][1], acc[mb][nb], 0, 0, 0);
+  #pragma unroll
+            for (int nb = 0; nb < 2; ++nb) acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, bp[nb][2], acc[mb][nb], 0, 0, 0);
+  #pragma unroll
+            for (int nb = 0; nb < 2; ++nb) acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, bp[nb][0], acc[mb][nb], 0, 0, 0);
+  #pragma unroll
+            for (int nb = 0; nb < 2; ++nb) acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, bp[nb][1], acc[mb][nb], 0, 0, 0);
+  #pragma unroll
+            for (int nb = 0; nb < 2; ++nb) acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, bp[nb][0], acc[mb][nb], 0, 0, 0);
+          }
+          if (kt + 1 < nk) {
+            __syncthreads();  // every wave is done with the stage
+            store_tiles(0);
+          }
+          __syncthreads();
+        }
+        return;
+      }
       for (int kt = 0; kt < nk; ++kt) {
         const int cur = kt & 1;
         if (kt + 1 < nk) load_tiles((kt + 1) * BK, mode_tag);
@@ -501,12 +581,12 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs a) {
 }
 
 static const char* gemm_name(int kind, int mb, int epi) {
-  static const char* kn[3] = {"f64", "f32", "bf16"};
+  static const char* kn[4] = {"f64", "f32", "bf16", "f32x3"};
   static const char* en[3] = {"val", "edge", "jet"};
-  static char names[3][17][3][40];
+  static char names[4][17][3][40];
   static bool init = false;
   if (!init) {
-    for (int k = 0; k < 3; ++k)
+    for (int k = 0; k < 4; ++k)
       for (int m = 0; m < 17; ++m)
         for (int e = 0; e < 3; ++e) snprintf(names[k][m][e], 40, "gemm_kernel<%s,%d,%s>", kn[k], m, en[e]);
     init = true;
@@ -555,23 +635,24 @@ static hipError_t launch_grid(const GemmArgs& a, hipStream_t st) {
 // Persistent variants are instantiated for float32 only (the other kinds ignore the bit).
 template <int KIND, int MB, int EPI, int BKT>
 static hipError_t launch_mb(const GemmArgs& a, bool persist, hipStream_t st) {
-  if constexpr (KIND == GK_F32)
+  if constexpr (KIND == GK_F32 || KIND == GK_F32X3)
     if (persist) return launch_grid<KIND, MB, EPI, BKT, true>(a, st);
   return launch_grid<KIND, MB, EPI, BKT, false>(a, st);
 }
 
 // Tile choice (GemmArgs::tile - 1 when nonzero, or QMC_GEMM_TILE=<bits> for tuning runs): bit 0
 // selects 32-wide K stages for float32, bit 1 half-height (64-row) value and edge tiles, bit 2 a
-// persistent grid (float32).  The default takes half-height tiles when full ones would give fewer than 4
+// persistent grid (float32), bit 3 float32 on the bf16 matrix cores (three-piece operands, 32-wide
+// K stages).  The default takes half-height tiles when full ones would give fewer than 4
 // blocks per compute unit.
 static int tile_bits(const GemmArgs& a) {
   static int env = -2;
   if (env == -2) {
     env = -1;
-    if (const char* e = getenv("QMC_GEMM_TILE")) env = atoi(e) & 7;
+    if (const char* e = getenv("QMC_GEMM_TILE")) env = atoi(e) & 15;
   }
   if (env >= 0) return env;
-  if (a.tile > 0) return (a.tile - 1) & 7;
+  if (a.tile > 0) return (a.tile - 1) & 15;
   const int64_t blocks = ((a.rows + 127) / 128) * ((a.Ncols + 127) / 128);
   return (a.vmode || a.Rp == 4) && blocks < 4 * 256 ? 2 : 0;
 }
@@ -617,6 +698,7 @@ hipError_t launch_gemm(GemmKind kind, const GemmArgs& a, hipStream_t st) {
   switch (kind) {
     case GK_F64: return launch_kind_bk<GK_F64, 16>(a, bits, st);
     case GK_F32:
+      if (bits & 8) return launch_kind_bk<GK_F32X3, 32>(a, bits, st);
       return (bits & 1) ? launch_kind_bk<GK_F32, 32>(a, bits, st) : launch_kind_bk<GK_F32, 16>(a, bits, st);
     case GK_BF16: return launch_kind_bk<GK_BF16, 32>(a, bits, st);
   }

@@ -54,7 +54,8 @@ struct GemmArgs {
   const void* add5;
   int nel;
   // tile choice: 0 = default, else 1 + bits (bit 0: 32-wide K stages for float32, bit 1: half-height
-  // value and edge tiles, bit 2: persistent grid)
+  // value and edge tiles, bit 2: persistent grid, bit 3: float32 on the bf16 matrix cores with
+  // three-piece operands)
   int tile;
 };
 

@@ -69,3 +69,34 @@ def test_c4h4_bf16_value_rows_logpsi(c4h4_case):
           flush=True)
     assert np.all(host(sg)[ok] == ref["sign"][ok])
     assert err.max() < 5e-2 * max(1.0, np.abs(ref["logpsi"]).max()) and gerr < 5e-2
+
+
+def test_c4h4_fp32_three_piece_gemms(c4h4_case):
+    """The float32 plan with autotuned tiles: at width 256 the tuner may choose the three-piece bf16
+    form of the float32 GEMMs (operands split into three bf16 pieces, six products accumulated in
+    float32 on the bf16 matrix cores).  When it does, the local energies keep the float32 bound against
+    the oracle (2e-5 of the largest addend, as the plain float32 plan above) and the loss gradient the
+    amplification-scaled float32 bound."""
+    from paper_2307_14123_amd import qmc
+    from tests.test_gpu_parity import amplification, fp32_grad_bound
+    s, a, p, r, ref, ok, scale = c4h4_case
+    plan = qmc.Plan([s], [r.shape[0]], a, "fp32", autotune=True)
+    tiles = plan.tiles()[0]
+    print(f"[c4h4 fp32 autotuned] tiles {tiles} (bit 3 = three-piece bf16 form)", flush=True)
+    if not any(t > 0 and ((t - 1) & 8) for t in tiles):
+        pytest.skip(f"the tuner kept the float32 MFMA form for every GEMM class on this device: {tiles}")
+    P, R = dev(p, plan.param_dtype), dev(r)
+    out = plan.local_energy(P, R)
+    g, _ = plan.loss_grad(P, R, dev(ref["e_loc"]))
+    torch.cuda.synchronize()
+    e = host(out["e_loc"])
+    rel = np.abs(e - ref["e_loc"])[ok] / scale[ok]
+    p32 = p.astype(np.float32).astype(np.float64)
+    Gref = oracle.loss_grad(r, ref["e_loc"], p32, s, a)[0]
+    gerr = np.linalg.norm(host(g).astype(np.float64) - Gref) / np.linalg.norm(Gref)
+    alpha = amplification(r, p, s, a)
+    print(f"[c4h4 fp32 autotuned] E_L max error relative to the largest addend {rel.max():.2e}; "
+          f"loss gradient normwise {gerr:.2e} (bound {fp32_grad_bound(alpha):.2e})", flush=True)
+    assert np.all(host(out["sign"])[ok] == ref["sign"][ok])
+    assert rel.max() < 2e-5
+    assert gerr < fp32_grad_bound(alpha)
