@@ -10,6 +10,9 @@
 #include <cmath>
 
 #include <algorithm>
+#include <map>
+#include <mutex>
+#include <tuple>
 
 #include "kernels.h"
 #include "pairs.h"
@@ -798,8 +801,21 @@ static hipError_t agg_launch(const SysDev& s, const S* h, const S* ws, const S* 
   // receiver parts: the fewest that reach the most busy threads per compute unit (resident blocks x
   // threads with a group, on average over the parts), as the kernel's occupancy gives them for each
   // block size; every extra part re-reads the walker's sender rows (3 % per part)
-  int parts = 1;
+  // (the choice depends only on the device and the shape: it is kept per (device, N, D, nup), so the
+  // occupancy queries run on the first launch of a shape only)
+  static std::mutex mu;
+  static std::map<std::tuple<int, int, int, int>, int> chosen;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return hipErrorInvalidValue;
+  const auto key = std::make_tuple(dev, s.N, s.D, s.nup);
+  int parts = 0;
   {
+    std::lock_guard<std::mutex> lk(mu);
+    const auto it = chosen.find(key);
+    if (it != chosen.end()) parts = it->second;
+  }
+  if (parts == 0) {
+    parts = 1;
     long best = -1;
     for (int p = 1; p <= 8 && p <= ngroups; ++p) {
       const int gp = (ngroups + p - 1) / p;
@@ -813,6 +829,8 @@ static hipError_t agg_launch(const SysDev& s, const S* h, const S* ws, const S* 
         parts = p;
       }
     }
+    std::lock_guard<std::mutex> lk(mu);
+    chosen[key] = parts;
   }
   const int gpb = (ngroups + parts - 1) / parts;
   ProfScope ps("aggregate_kernel", st);
