@@ -838,6 +838,8 @@ def bench_scaling(args):
                 plan.clip_local_energy(out["e_loc"], 5.0, "hard", out=EC)
                 plan.loss_grad(P, R, EC, grad=G, e_mean=EM)
                 plan.sgd_update(P, G, lr)
+                # the next step's Metropolis comparisons need log|psi| under the updated parameters
+                plan.logpsi(P, R, out=(lp, None))
 
             for _ in range(max(1, args.warmup)):
                 step()
