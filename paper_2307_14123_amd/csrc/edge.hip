@@ -27,8 +27,11 @@
 // U2's three pieces are stored in LDS in that k order (16-byte chunks XOR-swizzled by column).
 //
 // A persistent grid keeps U2 (transposed, 16-byte chunks XOR-swizzled by row
-// against LDS bank conflicts) and U1, a1, a2 in LDS, one copy per block of 8
-// waves (two per SIMD: the register budget); each wave takes 16 pair rows at a time.  A launch
+// against LDS bank conflicts) and U1, a1, a2 in LDS, one copy per block; each wave takes 16 pair
+// rows at a time.  At width 128 the second layer forms one 16-column block at a time (three
+// accumulators and three U2 fragments live), which keeps the kernel within 168 registers: blocks of
+// 12 waves, three per SIMD (two 16-column blocks at a time needed 174-194 registers, two waves per
+// SIMD; value rows 5 % and jets 13 % slower).  At width 256, 8 waves, two per SIMD.  A launch
 // writes 128 output columns from c0 on: width 256 takes two launches, each
 // recomputing the 256 hidden units (the half of U2 it needs fills 128 KB of LDS).  The radial
 // basis takes its exponent in float64 and the exponential of its fractional part
@@ -219,31 +222,21 @@ __global__ __launch_bounds__(64 * NW) void edge_mlp_kernel(SysDev s, EdgeMlpBatc
           zp[2][m][j] = p2;
         }
 #pragma unroll 1
-      for (int nb = 0; nb < ED / 16; nb += 2) {
-        f4 h0 = {0.f, 0.f, 0.f, 0.f}, h1 = h0, la0 = h0, la1 = h0, lb0 = h0, lb1 = h0;
-        const int n0 = 16 * nb + c, n1 = n0 + 16;
+      for (int nb = 0; nb < ED / 16; ++nb) {
+        f4 h0 = {0.f, 0.f, 0.f, 0.f}, la0 = h0, lb0 = h0;
+        const int n0 = 16 * nb + c;
 #pragma unroll
         for (int m = 0; m < EH / 32; ++m) {
           const int o0 = n0 * EH + (((4 * m + g) ^ (n0 & 15)) << 3);
-          const int o1 = n1 * EH + (((4 * m + g) ^ (n1 & 15)) << 3);
-          bf16x8 b0[3], b1[3];
+          bf16x8 b0[3];
 #pragma unroll
-          for (int p = 0; p < 3; ++p) {
-            b0[p] = *(const bf16x8*)&u2b[p * ED * EH + o0];
-            b1[p] = *(const bf16x8*)&u2b[p * ED * EH + o1];
-          }
+          for (int p = 0; p < 3; ++p) b0[p] = *(const bf16x8*)&u2b[p * ED * EH + o0];
           lb0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(zp[2][m], b0[0], lb0, 0, 0, 0);
-          lb1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(zp[2][m], b1[0], lb1, 0, 0, 0);
           la0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(zp[1][m], b0[0], la0, 0, 0, 0);
-          la1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(zp[1][m], b1[0], la1, 0, 0, 0);
           lb0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(zp[1][m], b0[1], lb0, 0, 0, 0);
-          lb1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(zp[1][m], b1[1], lb1, 0, 0, 0);
           la0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(zp[0][m], b0[1], la0, 0, 0, 0);
-          la1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(zp[0][m], b1[1], la1, 0, 0, 0);
           lb0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(zp[0][m], b0[2], lb0, 0, 0, 0);
-          lb1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(zp[0][m], b1[2], lb1, 0, 0, 0);
           h0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(zp[0][m], b0[0], h0, 0, 0, 0);
-          h1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(zp[0][m], b1[0], h1, 0, 0, 0);
         }
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
@@ -253,7 +246,6 @@ __global__ __launch_bounds__(64 * NW) void edge_mlp_kernel(SysDev s, EdgeMlpBatc
           if ((JET && r == 15) || op >= a.pairs) continue;
           const int64_t orow = JET ? op * 4 + re : op;
           a.out[orow * EH + c0 + n0] = (h0[i] + (la0[i] + lb0[i])) + (re == 0 ? a2s[n0] : 0.f);
-          a.out[orow * EH + c0 + n1] = (h1[i] + (la1[i] + lb1[i])) + (re == 0 ? a2s[n1] : 0.f);
         }
       }
       continue;
@@ -322,9 +314,9 @@ hipError_t launch_edge_mlp_types(const SysDev& s, const EdgeMlpArgs* a, int n, h
               ? c
               : 256;
   }
-  // blocks of w waves share one copy of their type's weights in LDS (73 KB); as many blocks as fit
-  // per compute unit, split among the types in proportion to their tiles (at least one each, at
-  // most one per w tiles), each type's blocks walking its tiles with a stride
+  // blocks of w waves share one copy of their type's weights in LDS (105 KB at width 128, 146 KB at
+  // 256); as many blocks as fit per compute unit, split among the types in proportion to their tiles
+  // (at least one each, at most one per w tiles), each type's blocks walking its tiles with a stride
   auto go = [&](auto kern, int w, int c0) {
     int occ = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, 64 * w, 0) != hipSuccess || occ < 1) occ = 1;
@@ -348,10 +340,10 @@ hipError_t launch_edge_mlp_types(const SysDev& s, const EdgeMlpArgs* a, int n, h
         go(edge_mlp_kernel<0, 8, 256>, 8, c0);
     }
   } else if (jet) {
-    // the three-piece operands take 48 more registers than the float32 form: two waves per SIMD
-    go(edge_mlp_kernel<1, 8, 128>, 8, 0);
+    // one 16-column block at a time in the second layer: within 168 registers, three waves per SIMD
+    go(edge_mlp_kernel<1, 12, 128>, 12, 0);
   } else {
-    go(edge_mlp_kernel<0, 8, 128>, 8, 0);
+    go(edge_mlp_kernel<0, 12, 128>, 12, 0);
   }
   return hipGetLastError();
 }
