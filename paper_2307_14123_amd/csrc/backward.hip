@@ -255,18 +255,6 @@ __global__ __launch_bounds__(256) void wgrad_reduce_kernel(const P* __restrict__
     gb[n] += s;
 }
 
-static int backward_cus() {
-  static int cus = 0;
-  if (cus == 0) {
-    int dev = 0, n = 0;
-    cus = (hipGetDevice(&dev) == hipSuccess &&
-           hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && n > 0)
-              ? n
-              : 256;
-  }
-  return cus;
-}
-
 static bool wgrad_f32_tiles_ok(const WgradArgs& a) {
   auto al = [](const void* p) { return ((uintptr_t)p & 15) == 0; };
   return a.Kin % 4 == 0 && a.Nout % 4 == 0 && a.ldx % 4 == 0 && a.ldg % 4 == 0 && a.xws % 4 == 0 &&
@@ -290,7 +278,7 @@ hipError_t launch_wgrad(GemmKind kind, const WgradArgs& a0, double* gW, int64_t 
     const int v = e ? std::atoi(e) : 2;
     return v >= 1 && v <= 8 ? v : 2;
   }();
-  int64_t nsplit = std::min<int64_t>((per_cu * backward_cus() + mt * nt - 1) / (mt * nt), (a.rows + 255) / 256);
+  int64_t nsplit = std::min<int64_t>((per_cu * device_cus() + mt * nt - 1) / (mt * nt), (a.rows + 255) / 256);
   nsplit = std::max<int64_t>(1, std::min<int64_t>(nsplit, cap));
   a.rows_per_split = ((a.rows + nsplit - 1) / nsplit + 31) / 32 * 32;
   nsplit = (a.rows + a.rows_per_split - 1) / a.rows_per_split;

@@ -306,14 +306,7 @@ hipError_t launch_edge_mlp_types(const SysDev& s, const EdgeMlpArgs* a, int n, h
   }
   if (m == 0) return hipSuccess;
   const int jet = a[0].jet;
-  static int cus = 0;
-  if (cus == 0) {
-    int dev = 0, c = 0;
-    cus = (hipGetDevice(&dev) == hipSuccess &&
-           hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && c > 0)
-              ? c
-              : 256;
-  }
+  const int cus = device_cus();
   // blocks of w waves share one copy of their type's weights in LDS (105 KB at width 128, 146 KB at
   // 256); as many blocks as fit per compute unit, split among the types in proportion to their tiles
   // (at least one each, at most one per w tiles), each type's blocks walking its tiles with a stride

@@ -49,6 +49,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <algorithm>
+#include <atomic>
 #include <cstring>
 #include <type_traits>
 
@@ -580,31 +581,32 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs a) {
   }
 }
 
+struct GemmNames {
+  char n[4][17][3][40];
+};
+
 static const char* gemm_name(int kind, int mb, int epi) {
-  static const char* kn[4] = {"f64", "f32", "bf16", "f32x3"};
-  static const char* en[3] = {"val", "edge", "jet"};
-  static char names[4][17][3][40];
-  static bool init = false;
-  if (!init) {
+  static const GemmNames names = [] {
+    const char* kn[4] = {"f64", "f32", "bf16", "f32x3"};
+    const char* en[3] = {"val", "edge", "jet"};
+    GemmNames g;
     for (int k = 0; k < 4; ++k)
       for (int m = 0; m < 17; ++m)
-        for (int e = 0; e < 3; ++e) snprintf(names[k][m][e], 40, "gemm_kernel<%s,%d,%s>", kn[k], m, en[e]);
-    init = true;
-  }
-  return names[kind][mb][epi];
+        for (int e = 0; e < 3; ++e) snprintf(g.n[k][m][e], 40, "gemm_kernel<%s,%d,%s>", kn[k], m, en[e]);
+    return g;
+  }();
+  return names.n[kind][mb][epi];
 }
 
-static int device_cus() {
-  static int cus = 0;
-  if (cus == 0) {
-    int dev = 0, n = 0;
-    if (hipGetDevice(&dev) == hipSuccess &&
-        hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && n > 0)
-      cus = n;
-    else
-      cus = 256;
-  }
-  return cus;
+int device_cus() {
+  static std::atomic<int> cache[64];
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  int n = cache[dev].load(std::memory_order_relaxed);
+  if (n > 0) return n;
+  if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) n = 256;
+  cache[dev].store(n, std::memory_order_relaxed);
+  return n;
 }
 
 template <int KIND, int MB, int EPI, int BKT, bool PERSIST>
@@ -615,15 +617,17 @@ static hipError_t launch_grid(const GemmArgs& a, hipStream_t st) {
   const unsigned gy = (unsigned)((a.Ncols + 127) / 128);
   int64_t gx = nbx;
   if constexpr (PERSIST) {
-    // as many blocks as fit on the device at once, each walking row tiles with a grid stride
-    static int occ = 0;
-    if (occ == 0) {
-      int o = 0;
-      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, gemm_kernel<KIND, MB, EPI, BKT, true>, 256, 0) !=
+    // as many blocks as fit on the device at once, each walking row tiles with a grid stride (the
+    // kernel's resident blocks per compute unit, queried once per device)
+    static std::atomic<int> occ_cache[64];
+    int dev = 0, occ = 0;
+    if (hipGetDevice(&dev) == hipSuccess && dev >= 0 && dev < 64) occ = occ_cache[dev].load(std::memory_order_relaxed);
+    if (occ < 1) {
+      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, gemm_kernel<KIND, MB, EPI, BKT, true>, 256, 0) !=
               hipSuccess ||
-          o < 1)
-        o = 1;
-      occ = o;
+          occ < 1)
+        occ = 1;
+      if (dev >= 0 && dev < 64) occ_cache[dev].store(occ, std::memory_order_relaxed);
     }
     const int64_t slots = (int64_t)occ * device_cus() / gy;
     gx = std::max<int64_t>(1, std::min<int64_t>(nbx, slots));
@@ -646,11 +650,10 @@ static hipError_t launch_mb(const GemmArgs& a, bool persist, hipStream_t st) {
 // K stages).  The default takes half-height tiles when full ones would give fewer than 4
 // blocks per compute unit.
 static int tile_bits(const GemmArgs& a) {
-  static int env = -2;
-  if (env == -2) {
-    env = -1;
-    if (const char* e = getenv("QMC_GEMM_TILE")) env = atoi(e) & 15;
-  }
+  static const int env = [] {
+    const char* e = getenv("QMC_GEMM_TILE");
+    return e ? atoi(e) & 15 : -1;
+  }();
   if (env >= 0) return env;
   if (a.tile > 0) return (a.tile - 1) & 15;
   const int64_t blocks = ((a.rows + 127) / 128) * ((a.Ncols + 127) / 128);

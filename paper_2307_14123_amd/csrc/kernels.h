@@ -82,6 +82,9 @@ __host__ __device__ inline int det_dim(const SysDev& s, int sp) {
 __host__ __device__ inline int orb_count(const SysDev& s, int sp) { return s.full_det ? s.N : (sp ? s.ndn : s.nup); }
 __host__ __device__ inline int det_row0(const SysDev& s, int sp) { return s.full_det && sp ? s.nup : 0; }
 
+// Compute units of the current device (queried once per device, thread-safe; 256 if the query fails).
+int device_cus();
+
 // Fused edge filters w(d) = tanh(rho(d) U1 + a1) U2 + a2 on MFMA (float32, width 128 or 256, at most 16
 // basis functions) for every pair of one edge type, from the geometry to the filter rows.
 struct EdgeMlpArgs {

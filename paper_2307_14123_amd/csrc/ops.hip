@@ -777,6 +777,9 @@ static hipError_t allow_lds(const void* fn, size_t lds, size_t* done) {
   if (lds <= 64 * 1024) return hipSuccess;
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return hipErrorInvalidValue;
+  // under one lock: callers on several host threads never lower a limit another has just raised
+  static std::mutex mu;
+  std::lock_guard<std::mutex> lk(mu);
   if (lds <= done[dev]) return hipSuccess;
   if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
     return hipErrorInvalidValue;
